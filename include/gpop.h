@@ -1,0 +1,249 @@
+/*
+ * gpop.h -- C ABI of the MI355X partition-centric scatter/gather engine.
+ *
+ * The engine runs the iteration of "GPOP: A scalable cache- and
+ * memory-efficient framework for Graph Processing Over Partitions"
+ * (Lakhotia, Pati, Kannan, Prasanna): vertices are split into index-range
+ * partitions of q vertices (Sec. 3.1.1); each iteration scatters the active
+ * partitions' messages into per-(source, destination)-partition bins, in
+ * source-centric or partition-centric mode chosen per partition (Sec. 3.1.2,
+ * Algorithms 2 and 3, Sec. 3.2), then gathers each destination partition's
+ * bins into its vertex state and builds the next frontier (Algorithm 2).
+ *
+ * Conventions for every call:
+ *   - Return value is a gpop_status; 0 (GPOP_OK) means success. On failure
+ *     gpop_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread). No C++ exception crosses this boundary.
+ *   - "device" pointers are HIP device allocations owned by the caller. The
+ *     library never allocates device memory: every device buffer it uses is
+ *     carved from the caller's workspace, whose size gpop_plan() reports.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Calls enqueue work on it and return without synchronising unless the
+ *     call says otherwise.
+ *   - A gpop_graph handle is not thread-safe; one handle serves one stream
+ *     at a time. It borrows the CSR, the workspace and the state array, which
+ *     must outlive it.
+ */
+#ifndef GPOP_H
+#define GPOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPOP_ABI_VERSION 1
+
+typedef enum gpop_status {
+    GPOP_OK = 0,
+    GPOP_EINVAL = 1,    /* malformed argument or graph                      */
+    GPOP_ENOMEM = 2,    /* workspace smaller than gpop_plan() asked for     */
+    GPOP_EDEVICE = 3,   /* a HIP runtime call failed                        */
+    GPOP_ESTATE = 4,    /* call out of order (e.g. iterate before init)     */
+    GPOP_ENOTSUP = 5    /* valid request this build does not support        */
+} gpop_status;
+
+/* Programs: the user functions of the programming-interface section
+ * (scatterFunc, initFunc, gatherFunc, filterFunc, applyWeight) compiled in.
+ * Gather combines messages with a commutative, associative reduce (min for
+ * the integer programs, sum for the PageRank family), which is what lets one
+ * workgroup combine a partition's messages in parallel. */
+typedef enum gpop_program {
+    GPOP_PROG_BFS_LEVEL = 0,     /* u32 hop level; unreached 0xFFFFFFFF (BFS app)     */
+    GPOP_PROG_CC_MINLABEL = 1,   /* u32 min vertex id of the component (CC app)       */
+    GPOP_PROG_SSSP_U32 = 2,      /* u32 distance, u8 weights, saturating (SSSP app)   */
+    GPOP_PROG_PAGERANK_F32 = 3,  /* f32 PageRank, dangling mass spread uniformly       */
+    GPOP_PROG_PPR_F32 = 4,       /* f32 personalised PageRank, restart to one seed     */
+    GPOP_PROG_CARRY_BFS = 5      /* BFS levels where initFunc keeps a reached vertex
+                                    active for `persist` iterations (selective
+                                    continuity of the active set)                      */
+} gpop_program;
+
+typedef enum gpop_selector {
+    GPOP_SEL_ANALYTICAL = 0,  /* Eq. 1 of the performance-modelling section      */
+    GPOP_SEL_FORCE_SC = 1,    /* every scattered partition source-centric        */
+    GPOP_SEL_FORCE_PC = 2,    /* every scattered partition partition-centric     */
+    GPOP_SEL_LEARNED = 3      /* MLP on per-partition features; falls back to    */
+                              /* the analytical model if no valid weights        */
+} gpop_selector;
+
+/* Per-partition mode of one iteration. */
+#define GPOP_MODE_NONE 0u  /* no active vertex: not scattered */
+#define GPOP_MODE_SC 1u
+#define GPOP_MODE_PC 2u
+
+/* CSR input (the graph format of the challenges section): offsets has V + 1
+ * non-decreasing entries with offsets[0] = 0 and offsets[V] = E; cols has E
+ * entries < V, each row sorted ascending (duplicates and self-loops allowed);
+ * weights is NULL or E bytes. All three are device pointers. */
+typedef struct gpop_graph_desc {
+    uint32_t num_vertices;        /* V >= 1                                   */
+    uint32_t reserved0;
+    uint64_t num_edges;           /* E < 2^32                                 */
+    const uint32_t* offsets;
+    const uint32_t* cols;
+    const uint8_t* weights;
+} gpop_graph_desc;
+
+typedef struct gpop_options {
+    uint32_t log2_part;   /* q = 2^log2_part vertices per partition, 8..15;
+                             0 picks 14 (16384 vertices)                        */
+    uint32_t reserved[7]; /* must be zero                                      */
+} gpop_options;
+
+typedef struct gpop_plan_info {
+    uint32_t q;                 /* vertices per partition                     */
+    uint32_t k;                 /* number of partitions, ceil(V / q)          */
+    uint64_t workspace_bytes;   /* device workspace gpop_graph_create needs   */
+    uint64_t reserved[6];
+} gpop_plan_info;
+
+typedef struct gpop_params {
+    uint32_t root;       /* BFS / SSSP / CARRY root, PPR seed                 */
+    uint32_t persist;    /* CARRY_BFS: iterations a vertex stays active (>=1) */
+    float damping;       /* PAGERANK damping d (0.85 in the paper's runs)    */
+    float alpha;         /* PPR restart probability                           */
+    uint32_t reserved[4];
+} gpop_params;
+
+/* Static per-graph statistics after preprocessing. */
+typedef struct gpop_graph_info {
+    uint32_t q, k;
+    uint64_t num_vertices, num_edges;
+    uint64_t num_messages;      /* M = sum_p r^p E^p: PNG messages (Sec. 3.1.2) */
+    uint64_t nonempty_bins;     /* (p, q) pairs with at least one edge          */
+    uint64_t reserved[6];
+} gpop_graph_info;
+
+/* One record per completed iteration (written on the device). */
+typedef struct gpop_iter_stats {
+    uint64_t active_vertices;   /* sum_p V_a^p at the start of the iteration  */
+    uint64_t active_edges;      /* sum_p E_a^p                                 */
+    uint32_t sc_parts, pc_parts;
+    uint64_t sc_msgs, sc_ids;   /* messages / ids written in SC mode           */
+    uint64_t pc_msgs, pc_ids;   /* messages / static ids of PC partitions      */
+    uint64_t gathered_ids;      /* ids read by gather                          */
+    uint32_t gather_parts;      /* partitions gathered                         */
+    uint32_t reserved;
+} gpop_iter_stats;
+
+/* ------------------------------------------------------------------ setup */
+
+/* Partition count and workspace size for a graph (host-side arithmetic from
+ * V, E and the options; the device pointers are not read). Partitioning is
+ * the paper's index-range scheme with q a power of two (Sec. 3.1.1).
+ * Errors: GPOP_EINVAL for V = 0, E >= 2^32, bad log2_part or nonzero
+ * reserved fields. */
+int gpop_plan(const gpop_graph_desc* desc, const gpop_options* opts, gpop_plan_info* out);
+
+/* Validates the CSR on the device and builds the partition-node bipartite
+ * layout (PNG, Sec. 3.1.2 and Algorithm 3): for every partition pair (p, q)
+ * the sources N_i^p(q) and their destination ids, written once and reused by
+ * every partition-centric scatter. Runs on `stream` and synchronises it.
+ * d_workspace must be 256-byte aligned with ws_bytes >= workspace_bytes.
+ * Errors: GPOP_EINVAL (malformed CSR: non-monotone offsets, col >= V, unsorted
+ * row), GPOP_ENOMEM (workspace too small), GPOP_EDEVICE. */
+int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts,
+                      void* d_workspace, size_t ws_bytes, void* stream, struct gpop_graph** out);
+
+/* Releases the host-side handle (device memory stays the caller's). NULL ok. */
+int gpop_graph_destroy(struct gpop_graph* g);
+
+int gpop_graph_get_info(const struct gpop_graph* g, gpop_graph_info* out);
+
+/* ---------------------------------------------------------------- program */
+
+/* Binds `prog` and the caller's state array (V x 4 bytes: u32 for the integer
+ * programs, f32 for the PageRank family) and writes its initial values
+ * (initial val[] of each application in the applications section; PageRank
+ * 1/V, PPR e_seed, CC v, BFS/SSSP/CARRY infinity except root = 0). Clears the
+ * frontier and the iteration counter. Errors: GPOP_EINVAL for a bad program,
+ * root >= V, persist = 0 or a weighted program on an unweighted graph. */
+int gpop_state_init(struct gpop_graph* g, gpop_program prog, const gpop_params* prm,
+                    void* d_state, void* stream);
+
+/* loadFrontier (applications section): makes the n device-resident vertex
+ * ids the active set. Order and duplicates do not matter. Ids >= V make the
+ * next gpop_check() report GPOP_EINVAL and are ignored. */
+int gpop_set_frontier(struct gpop_graph* g, const uint32_t* d_vertices, uint32_t n, void* stream);
+
+/* Makes every vertex active. */
+int gpop_set_frontier_all(struct gpop_graph* g, void* stream);
+
+/* Mode selection per partition (performance-modelling section). bw_ratio is
+ * BW_PC / BW_SC (the paper's default is 2). s_i / s_v are the index and value
+ * sizes in bytes used by the model (the paper uses 4 and 4). For
+ * GPOP_SEL_LEARNED, d_mlp is a device buffer of GPOP_MLP_PARAMS bf16 weights
+ * in the layout of gpop_mlp.h; NULL keeps the analytical model. */
+int gpop_set_selector(struct gpop_graph* g, gpop_selector kind, float bw_ratio,
+                      uint32_t s_i, uint32_t s_v, const void* d_mlp);
+
+/* -------------------------------------------------------------- iteration */
+
+/* Scatter half of one iteration (Algorithm 2, scatter phase, with
+ * Algorithm 3 for partition-centric partitions): picks the mode of each
+ * partition with active vertices and writes its bins. */
+int gpop_scatter(struct gpop_graph* g, void* stream);
+
+/* Gather half (Algorithm 2: reInit, gather, filter): each partition that
+ * received messages or has active vertices combines its bins into its
+ * state in on-chip memory, then builds the next frontier. */
+int gpop_gather(struct gpop_graph* g, void* stream);
+
+/* scatter_and_gather: one full iteration. */
+int gpop_iterate(struct gpop_graph* g, void* stream);
+
+/* Iterates while the frontier is non-empty and fewer than max_iter
+ * iterations have run (the driver loop of the applications section).
+ * Synchronises `stream` before returning and reports the iterations run in
+ * *h_iters (may be NULL). Reaching max_iter with a non-empty frontier is not
+ * an error: gpop_frontier_size() then reports the remaining frontier. */
+int gpop_run(struct gpop_graph* g, uint32_t max_iter, uint32_t* h_iters, void* stream);
+
+/* G.frontierSize: number of active vertices. Synchronises `stream`. */
+int gpop_frontier_size(struct gpop_graph* g, uint64_t* h_out, void* stream);
+
+/* Iterations completed since gpop_state_init (host-side counter). */
+int gpop_iterations(const struct gpop_graph* g, uint32_t* h_out);
+
+/* Copies up to max_records per-iteration records (oldest first) into h_out
+ * and reports how many were copied. Synchronises `stream`. */
+int gpop_iter_stats_read(struct gpop_graph* g, gpop_iter_stats* h_out, uint32_t max_records,
+                         uint32_t* h_count, void* stream);
+
+/* Copies the per-partition modes chosen in the most recent scatter (k bytes,
+ * GPOP_MODE_*) into h_modes. Synchronises `stream`. */
+int gpop_modes_read(struct gpop_graph* g, uint8_t* h_modes, void* stream);
+
+/* Reads the device error word (ids >= V passed to gpop_set_frontier).
+ * Synchronises `stream`. Returns GPOP_EINVAL if an error was recorded. */
+int gpop_check(struct gpop_graph* g, void* stream);
+
+/* ------------------------------------------------------------- profiling */
+
+/* Kernel identifiers for gpop_profile_read. */
+#define GPOP_KERNEL_PLAN 0
+#define GPOP_KERNEL_SCATTER_SC 1
+#define GPOP_KERNEL_SCATTER_PC 2
+#define GPOP_KERNEL_GATHER 3
+#define GPOP_KERNEL_COUNT 4
+
+/* When enabled, every kernel launch is bracketed by HIP events on its
+ * stream. gpop_profile_read synchronises the stream and returns, per kernel
+ * id, the summed milliseconds and the number of launches since profiling
+ * was enabled (arrays of GPOP_KERNEL_COUNT entries). */
+int gpop_profile_enable(struct gpop_graph* g, int enable);
+int gpop_profile_read(struct gpop_graph* g, double* h_ms, uint64_t* h_launches, void* stream);
+
+/* --------------------------------------------------------------- errors */
+
+const char* gpop_last_error(void);
+int gpop_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPOP_H */

@@ -1,0 +1,283 @@
+"""Python binding of libgpop.so: argument marshalling only.
+
+Every step of the scatter/gather iteration runs in the library's HIP kernels;
+PyTorch provides device memory (the workspace and the caller's arrays) and the
+stream. Names follow include/gpop.h. Importing this module does not touch the
+GPU; loading the library fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpop.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gpop.h")
+
+# status codes
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTSUP = range(6)
+# programs
+BFS_LEVEL, CC_MINLABEL, SSSP_U32, PAGERANK_F32, PPR_F32, CARRY_BFS = range(6)
+PROGRAMS = {"bfs": BFS_LEVEL, "cc": CC_MINLABEL, "sssp": SSSP_U32, "pagerank": PAGERANK_F32,
+            "ppr": PPR_F32, "carry_bfs": CARRY_BFS}
+# selectors
+SEL_ANALYTICAL, SEL_FORCE_SC, SEL_FORCE_PC, SEL_LEARNED = range(4)
+SELECTORS = {"analytical": SEL_ANALYTICAL, "sc": SEL_FORCE_SC, "pc": SEL_FORCE_PC,
+             "learned": SEL_LEARNED}
+MODE_NONE, MODE_SC, MODE_PC = 0, 1, 2
+KERNELS = ["plan", "scatter_sc", "scatter_pc", "gather"]
+
+
+class GpopError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("gpop error %d: %s" % (code, msg))
+        self.code = code
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("num_edges", ctypes.c_uint64), ("offsets", ctypes.c_void_p),
+                ("cols", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("log2_part", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("workspace_bytes", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 6)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("root", ctypes.c_uint32), ("persist", ctypes.c_uint32),
+                ("damping", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("num_vertices", ctypes.c_uint64), ("num_edges", ctypes.c_uint64),
+                ("num_messages", ctypes.c_uint64), ("nonempty_bins", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 6)]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [("active_vertices", ctypes.c_uint64), ("active_edges", ctypes.c_uint64),
+                ("sc_parts", ctypes.c_uint32), ("pc_parts", ctypes.c_uint32),
+                ("sc_msgs", ctypes.c_uint64), ("sc_ids", ctypes.c_uint64),
+                ("pc_msgs", ctypes.c_uint64), ("pc_ids", ctypes.c_uint64),
+                ("gathered_ids", ctypes.c_uint64), ("gather_parts", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
+_lib = None
+
+_SIGS = {
+    "gpop_abi_version": (ctypes.c_int, []),
+    "gpop_last_error": (ctypes.c_char_p, []),
+    "gpop_plan": (ctypes.c_int, [ctypes.POINTER(GraphDesc), ctypes.POINTER(Options),
+                                 ctypes.POINTER(PlanInfo)]),
+    "gpop_graph_create": (ctypes.c_int, [ctypes.POINTER(GraphDesc), ctypes.POINTER(Options),
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "gpop_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "gpop_graph_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GraphInfo)]),
+    "gpop_state_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Params),
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_set_frontier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                         ctypes.c_void_p]),
+    "gpop_set_frontier_all": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_set_selector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
+                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]),
+    "gpop_scatter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_iterate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.c_void_p]),
+    "gpop_frontier_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                          ctypes.c_void_p]),
+    "gpop_iterations": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
+    "gpop_iter_stats_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(IterStats),
+                                            ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                            ctypes.c_void_p]),
+    "gpop_modes_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "gpop_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Loads libgpop.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgpop.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> Sequence[str]:
+    """Function names declared in include/gpop.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(gpop_\w+)\s*\(", text, re.M)))
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise GpopError(rc, lib().gpop_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def plan(num_vertices: int, num_edges: int, log2_part: int = 14) -> PlanInfo:
+    d = GraphDesc(num_vertices, 0, num_edges, None, None, None)
+    o = Options(log2_part)
+    out = PlanInfo()
+    _check(lib().gpop_plan(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)))
+    return out
+
+
+class Graph:
+    """A preprocessed graph on the GPU. `offsets`, `cols` (int32/uint32) and
+    optional `weights` (uint8) are CUDA tensors the caller keeps alive; the
+    workspace is allocated here as a torch tensor and owned by this object."""
+
+    def __init__(self, offsets, cols, weights=None, log2_part: int = 14, stream=None):
+        import torch
+        self._keep = (offsets, cols, weights)
+        n = offsets.numel() - 1
+        m = cols.numel()
+        self.desc = GraphDesc(n, 0, m, offsets.data_ptr(), cols.data_ptr() if m else 0,
+                              None if weights is None else weights.data_ptr())
+        self.opts = Options(log2_part)
+        info = PlanInfo()
+        _check(lib().gpop_plan(ctypes.byref(self.desc), ctypes.byref(self.opts), ctypes.byref(info)))
+        self.q, self.k = info.q, info.k
+        self.workspace = torch.empty(info.workspace_bytes + 256, dtype=torch.uint8, device=offsets.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        h = ctypes.c_void_p()
+        _check(lib().gpop_graph_create(ctypes.byref(self.desc), ctypes.byref(self.opts),
+                                       ctypes.c_void_p(aligned), info.workspace_bytes,
+                                       _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.n, self.m = n, m
+        self.prog = None
+        self.state = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gpop_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> GraphInfo:
+        out = GraphInfo()
+        _check(lib().gpop_graph_get_info(self.h, ctypes.byref(out)))
+        return out
+
+    def state_init(self, prog, state, root: int = 0, persist: int = 1, damping: float = 0.85,
+                   alpha: float = 0.15, stream=None):
+        prog = PROGRAMS[prog] if isinstance(prog, str) else int(prog)
+        p = Params(root, persist, damping, alpha)
+        _check(lib().gpop_state_init(self.h, prog, ctypes.byref(p), _ptr(state), _stream(stream)))
+        self.prog, self.state = prog, state
+
+    def set_frontier(self, vertices, stream=None):
+        _check(lib().gpop_set_frontier(self.h, _ptr(vertices), vertices.numel(), _stream(stream)))
+
+    def set_frontier_all(self, stream=None):
+        _check(lib().gpop_set_frontier_all(self.h, _stream(stream)))
+
+    def set_selector(self, kind="analytical", bw_ratio: float = 2.0, s_i: int = 4, s_v: int = 4,
+                     mlp=None):
+        kind = SELECTORS[kind] if isinstance(kind, str) else int(kind)
+        _check(lib().gpop_set_selector(self.h, kind, bw_ratio, s_i, s_v, _ptr(mlp)))
+
+    def scatter(self, stream=None):
+        _check(lib().gpop_scatter(self.h, _stream(stream)))
+
+    def gather(self, stream=None):
+        _check(lib().gpop_gather(self.h, _stream(stream)))
+
+    def iterate(self, stream=None):
+        _check(lib().gpop_iterate(self.h, _stream(stream)))
+
+    def run(self, max_iter: int = 1 << 30, stream=None) -> int:
+        it = ctypes.c_uint32()
+        _check(lib().gpop_run(self.h, max_iter, ctypes.byref(it), _stream(stream)))
+        return it.value
+
+    def frontier_size(self, stream=None) -> int:
+        out = ctypes.c_uint64()
+        _check(lib().gpop_frontier_size(self.h, ctypes.byref(out), _stream(stream)))
+        return out.value
+
+    def iterations(self) -> int:
+        out = ctypes.c_uint32()
+        _check(lib().gpop_iterations(self.h, ctypes.byref(out)))
+        return out.value
+
+    def iter_stats(self, stream=None):
+        cap = 4096
+        buf = (IterStats * cap)()
+        n = ctypes.c_uint32()
+        _check(lib().gpop_iter_stats_read(self.h, buf, cap, ctypes.byref(n), _stream(stream)))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def modes(self, stream=None):
+        import numpy as np
+        out = np.zeros(self.k, dtype=np.uint8)
+        _check(lib().gpop_modes_read(self.h, ctypes.c_void_p(out.ctypes.data), _stream(stream)))
+        return out
+
+    def check(self, stream=None):
+        _check(lib().gpop_check(self.h, _stream(stream)))
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().gpop_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, stream=None):
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_uint64 * 4)()
+        _check(lib().gpop_profile_read(self.h, ms, n, _stream(stream)))
+        return {KERNELS[i]: (ms[i], int(n[i])) for i in range(4)}
+
+
+def upload_csr(g, device="cuda"):
+    """Copies a host CSR (numpy offsets/cols[/weights]) to device tensors."""
+    import numpy as np
+    import torch
+    off = torch.from_numpy(np.ascontiguousarray(g.offsets).view(np.int32)).to(device)
+    cols = torch.from_numpy(np.ascontiguousarray(g.cols).view(np.int32)).to(device)
+    w = None
+    if getattr(g, "weights", None) is not None:
+        w = torch.from_numpy(np.ascontiguousarray(g.weights)).to(device)
+    return off, cols, w

@@ -1,0 +1,522 @@
+// C ABI of the engine: argument checks, workspace carving, preprocessing and
+// the iteration driver. No device memory is allocated here; every buffer is
+// a slice of the caller's workspace.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+using namespace gpop;
+
+namespace {
+
+constexpr uint32_t kPcTask = 32768;  // message slots per partition-centric task
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(GPOP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_OR_RETURN(expr, what)                       \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+struct Pending {
+    int kid;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct gpop_graph {
+    Dev G{};
+    Params P{};
+    int prog = -1;
+    uint32_t* state = nullptr;
+    uint32_t it = 0;
+    uint64_t M = 0;
+    uint64_t nonempty_bins = 0;
+    bool prof = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[GPOP_KERNEL_COUNT] = {0, 0, 0, 0};
+    uint64_t prof_n[GPOP_KERNEL_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves every device buffer out of `base` (nullptr: just measure). Returns
+// the bytes needed.
+size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, uint32_t s) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + o : nullptr;
+        o += align256(bytes ? bytes : 1);
+        return p;
+    };
+    const uint64_t q = 1ull << s;
+    const uint64_t k = (V + q - 1) / q;
+    const uint64_t kk = k * k;
+    const uint64_t E_pad = align256(E ? E : 1);
+    const uint64_t nch = E_pad / kChunk;
+    const uint64_t ntask = E / kPcTask + k + 1;
+    G->part_E = (uint32_t*)take(k * 4);
+    G->part_M = (uint32_t*)take(k * 4);
+    G->bin_moff = (uint32_t*)take((kk + 1) * 4);
+    G->bin_ioff = (uint32_t*)take((kk + 1) * 4);
+    G->cm = (uint4*)take(kk * 16);
+    G->png_src = (uint16_t*)take(E_pad * 2);
+    G->png_ids = (uint16_t*)take(E_pad * 2);
+    G->png_w = (uint8_t*)take(E_pad);
+    G->png_chunk = (uint32_t*)take(nch * 4);
+    G->pctask = (uint4*)take(ntask * 16);
+    G->data = (uint32_t*)take(E_pad * 4);
+    G->sc_ids = (uint16_t*)take(E_pad * 2);
+    G->sc_w = (uint8_t*)take(E_pad);
+    G->sc_chunk = (uint32_t*)take(nch * 4);
+    G->sc_cnt = (uint2*)take(kk * 8);
+    G->sc_tot = (uint2*)take(k * 8);
+    G->gat_ids = (uint32_t*)take(k * 4);
+    G->mode = (uint8_t*)take(k);
+    for (int b = 0; b < 2; ++b) {
+        G->flist[b] = (uint16_t*)take(k * q * 2);
+        G->fbits[b] = (uint32_t*)take(k * q / 8);
+        G->fVa[b] = (uint32_t*)take(k * 4);
+        G->fEa[b] = (uint32_t*)take(k * 4);
+        G->dpart[b] = (double*)take(k * 8);
+    }
+    G->marks = (uint8_t*)take(k * q);
+    G->cnt_m = (uint32_t*)take(kk * 4);
+    G->cnt_i = (uint32_t*)take(kk * 4);
+    G->scan_tmp = (uint32_t*)take(scan_tmp_words(kk) * 4);
+    G->ctrl = (Ctrl*)take(sizeof(Ctrl));
+    G->log = (gpop_iter_stats*)take(kLogCap * sizeof(gpop_iter_stats));
+    return o;
+}
+
+int check_desc(const gpop_graph_desc* d, const gpop_options* o, uint32_t* s_out) {
+    if (!d) return fail(GPOP_EINVAL, "desc is NULL");
+    if (d->num_vertices == 0) return fail(GPOP_EINVAL, "graph has no vertex");
+    if (d->num_edges >= 0xFFFFFFFFull) return fail(GPOP_EINVAL, "E must be < 2^32 - 1");
+    if (d->reserved0) return fail(GPOP_EINVAL, "reserved0 must be zero");
+    uint32_t s = 14;
+    if (o) {
+        for (int i = 0; i < 7; ++i)
+            if (o->reserved[i]) return fail(GPOP_EINVAL, "options.reserved must be zero");
+        if (o->log2_part) s = o->log2_part;
+    }
+    if (s < 8 || s > 15) return fail(GPOP_EINVAL, "log2_part must be in [8, 15]");
+    const uint64_t q = 1ull << s;
+    const uint64_t k = (d->num_vertices + q - 1) / q;
+    if (k > 4096) return fail(GPOP_EINVAL, "too many partitions (k = %llu > 4096); raise log2_part",
+                              (unsigned long long)k);
+    *s_out = s;
+    return GPOP_OK;
+}
+
+hipEvent_t get_event(gpop_graph* g) {
+    if (!g->pool.empty()) {
+        hipEvent_t e = g->pool.back();
+        g->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <class F>
+int timed(gpop_graph* g, int kid, hipStream_t s, F&& f, const char* what) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (g->prof) {
+        a = get_event(g);
+        b = get_event(g);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    hipError_t e = f();
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (g->prof && a && b) {
+        (void)hipEventRecord(b, s);
+        g->pending.push_back({kid, a, b});
+    }
+    return GPOP_OK;
+}
+
+int collect_profile(gpop_graph* g) {
+    for (const Pending& p : g->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g->prof_ms[p.kid] += ms;
+            g->prof_n[p.kid] += 1;
+        }
+        g->pool.push_back(p.a);
+        g->pool.push_back(p.b);
+    }
+    g->pending.clear();
+    return GPOP_OK;
+}
+
+int max_lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gpop_abi_version(void) { return GPOP_ABI_VERSION; }
+
+const char* gpop_last_error(void) { return g_err.c_str(); }
+
+int gpop_plan(const gpop_graph_desc* desc, const gpop_options* opts, gpop_plan_info* out) {
+    uint32_t s;
+    int rc = check_desc(desc, opts, &s);
+    if (rc) return rc;
+    if (!out) return fail(GPOP_EINVAL, "out is NULL");
+    Dev G{};
+    memset(out, 0, sizeof *out);
+    out->q = 1u << s;
+    out->k = (desc->num_vertices + out->q - 1) / out->q;
+    out->workspace_bytes = carve(&G, nullptr, desc->num_vertices, desc->num_edges, s);
+    return GPOP_OK;
+}
+
+int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, void* d_ws,
+                      size_t ws_bytes, void* stream, gpop_graph** out) {
+    uint32_t s;
+    int rc = check_desc(desc, opts, &s);
+    if (rc) return rc;
+    if (!out) return fail(GPOP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!desc->offsets || (!desc->cols && desc->num_edges))
+        return fail(GPOP_EINVAL, "offsets/cols must be device pointers");
+    if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(GPOP_EINVAL, "workspace must be 256-byte aligned");
+    Dev G{};
+    const size_t need = carve(&G, nullptr, desc->num_vertices, desc->num_edges, s);
+    if (ws_bytes < need)
+        return fail(GPOP_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    carve(&G, (char*)d_ws, desc->num_vertices, desc->num_edges, s);
+    G.V = desc->num_vertices;
+    G.E = desc->num_edges;
+    G.s = s;
+    G.q = 1u << s;
+    G.k = (G.V + G.q - 1) / G.q;
+    G.nbits = 0;
+    while ((1u << G.nbits) < G.k) ++G.nbits;
+    G.off = desc->offsets;
+    G.cols = desc->cols;
+    G.w = desc->weights;
+    hipStream_t st = (hipStream_t)stream;
+
+    if (sc_lds_bytes(G.k, sc_waves_for(G.k)) > (size_t)max_lds_per_block() ||
+        gather_lds_bytes(P_BFS, G.q) + 2048 > (size_t)max_lds_per_block())
+        return fail(GPOP_ENOTSUP, "partition of %u vertices does not fit the LDS", G.q);
+
+    HIP_OR_RETURN(hipMemsetAsync(G.ctrl, 0, sizeof(Ctrl), st), "clear control block");
+    HIP_OR_RETURN(launch_validate(G, st), "validate CSR");
+    Ctrl hc;
+    HIP_OR_RETURN(hipMemcpyAsync(&hc, G.ctrl, sizeof hc, hipMemcpyDeviceToHost, st), "read control");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    if (hc.csr_err) {
+        static const char* why[] = {"", "offsets[0] != 0", "decreasing offsets or offset > E",
+                                    "offsets[V] != E", "column index >= V", "row not sorted ascending"};
+        return fail(GPOP_EINVAL, "malformed CSR: %s", why[hc.csr_err < 6 ? hc.csr_err : 0]);
+    }
+    const uint64_t kk = (uint64_t)G.k * G.k;
+    HIP_OR_RETURN(launch_part_E(G, st), "partition edges");
+    HIP_OR_RETURN(launch_sc_build(G, 0, st), "count bins");
+    HIP_OR_RETURN(launch_scan_excl(G.cnt_m, G.bin_moff, kk, G.scan_tmp, st), "scan messages");
+    HIP_OR_RETURN(launch_scan_excl(G.cnt_i, G.bin_ioff, kk, G.scan_tmp, st), "scan ids");
+    HIP_OR_RETURN(launch_part_M(G, st), "partition messages");
+    HIP_OR_RETURN(launch_colmajor(G, st), "column table");
+    HIP_OR_RETURN(launch_sc_build(G, 1, st), "fill PNG");
+
+    std::vector<uint32_t> partM(G.k), cnti(kk);
+    HIP_OR_RETURN(hipMemcpyAsync(partM.data(), G.part_M, G.k * 4, hipMemcpyDeviceToHost, st), "read M");
+    HIP_OR_RETURN(hipMemcpyAsync(cnti.data(), G.cnt_i, kk * 4, hipMemcpyDeviceToHost, st), "read counts");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    std::vector<uint4> tasks;
+    uint64_t slot = 0;
+    for (uint32_t p = 0; p < G.k; ++p) {
+        for (uint64_t a = 0; a < partM[p]; a += kPcTask) {
+            const uint64_t b = std::min<uint64_t>(partM[p], a + kPcTask);
+            tasks.push_back(make_uint4(p, (uint32_t)(slot + a), (uint32_t)(slot + b), 0));
+        }
+        slot += partM[p];
+    }
+    if (slot >= 0x80000000ull)
+        return fail(GPOP_ENOTSUP, "graph has %llu messages; at most 2^31 - 1 supported",
+                    (unsigned long long)slot);
+    uint64_t nz = 0;
+    for (uint64_t i = 0; i < kk; ++i) nz += cnti[i] != 0;
+    G.n_pctask = (uint32_t)tasks.size();
+    if (!tasks.empty())
+        HIP_OR_RETURN(hipMemcpyAsync(G.pctask, tasks.data(), tasks.size() * sizeof(uint4),
+                                     hipMemcpyHostToDevice, st), "write task table");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+
+    gpop_graph* g = new (std::nothrow) gpop_graph();
+    if (!g) return fail(GPOP_ENOMEM, "host allocation failed");
+    g->G = G;
+    g->M = slot;
+    g->nonempty_bins = nz;
+    g->P.selector = GPOP_SEL_ANALYTICAL;
+    g->P.s_i = 4;
+    g->P.s_v = 4;
+    g->P.ratio_num = 2048;
+    g->P.ratio_den = 1024;
+    *out = g;
+    return GPOP_OK;
+}
+
+int gpop_graph_destroy(gpop_graph* g) {
+    if (!g) return GPOP_OK;
+    for (const Pending& p : g->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
+    delete g;
+    return GPOP_OK;
+}
+
+int gpop_graph_get_info(const gpop_graph* g, gpop_graph_info* out) {
+    if (!g || !out) return fail(GPOP_EINVAL, "NULL argument");
+    memset(out, 0, sizeof *out);
+    out->q = g->G.q;
+    out->k = g->G.k;
+    out->num_vertices = g->G.V;
+    out->num_edges = g->G.E;
+    out->num_messages = g->M;
+    out->nonempty_bins = g->nonempty_bins;
+    return GPOP_OK;
+}
+
+int gpop_state_init(gpop_graph* g, gpop_program prog, const gpop_params* prm, void* d_state,
+                    void* stream) {
+    if (!g || !prm || !d_state) return fail(GPOP_EINVAL, "NULL argument");
+    if ((int)prog < 0 || (int)prog > GPOP_PROG_CARRY_BFS) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
+    const bool rooted = prog != GPOP_PROG_CC_MINLABEL && prog != GPOP_PROG_PAGERANK_F32;
+    if (rooted && prm->root >= g->G.V) return fail(GPOP_EINVAL, "root %u >= V", prm->root);
+    if (prog == GPOP_PROG_CARRY_BFS && prm->persist == 0) return fail(GPOP_EINVAL, "persist must be >= 1");
+    if (prog == GPOP_PROG_SSSP_U32 && !g->G.w) return fail(GPOP_EINVAL, "SSSP needs edge weights");
+    if (prog == GPOP_PROG_PAGERANK_F32 && !(prm->damping >= 0.f && prm->damping <= 1.f))
+        return fail(GPOP_EINVAL, "damping must be in [0, 1]");
+    if (prog == GPOP_PROG_PPR_F32 && !(prm->alpha >= 0.f && prm->alpha <= 1.f))
+        return fail(GPOP_EINVAL, "alpha must be in [0, 1]");
+    if (gather_lds_bytes(prog, g->G.q) + 2048 > (size_t)max_lds_per_block())
+        return fail(GPOP_ENOTSUP, "program %d needs %zu bytes of LDS at q = %u; use a smaller partition",
+                    (int)prog, gather_lds_bytes(prog, g->G.q), g->G.q);
+    g->prog = (int)prog;
+    g->state = (uint32_t*)d_state;
+    g->it = 0;
+    g->P.root = prm->root;
+    g->P.persist = prm->persist;
+    g->P.damping = prm->damping;
+    g->P.alpha = prm->alpha;
+    g->P.inv_n = 1.0 / (double)g->G.V;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OR_RETURN(launch_state_init(g->G, g->P, g->prog, g->state, st), "state init");
+    return GPOP_OK;
+}
+
+int gpop_set_frontier(gpop_graph* g, const uint32_t* d_vertices, uint32_t n, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    if (n && !d_vertices) return fail(GPOP_EINVAL, "NULL vertex array");
+    HIP_OR_RETURN(launch_set_frontier(g->G, d_vertices, n, 0, g->it & 1u, (hipStream_t)stream),
+                  "set frontier");
+    return GPOP_OK;
+}
+
+int gpop_set_frontier_all(gpop_graph* g, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    HIP_OR_RETURN(launch_set_frontier(g->G, nullptr, 0, 1, g->it & 1u, (hipStream_t)stream),
+                  "set frontier");
+    return GPOP_OK;
+}
+
+int gpop_set_selector(gpop_graph* g, gpop_selector kind, float bw_ratio, uint32_t s_i,
+                      uint32_t s_v, const void* d_mlp) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    if ((int)kind < 0 || (int)kind > GPOP_SEL_LEARNED) return fail(GPOP_EINVAL, "unknown selector");
+    if (!(bw_ratio > 0.f) || !std::isfinite(bw_ratio) || bw_ratio > 1e6f)
+        return fail(GPOP_EINVAL, "bw_ratio must be finite and > 0");
+    if (s_i < 1 || s_i > 16 || s_v < 1 || s_v > 16) return fail(GPOP_EINVAL, "s_i, s_v in [1, 16]");
+    g->P.selector = (uint32_t)kind;
+    g->P.ratio_num = (uint32_t)std::lround((double)bw_ratio * 1024.0);
+    if (g->P.ratio_num == 0) g->P.ratio_num = 1;
+    g->P.ratio_den = 1024;
+    g->P.s_i = s_i;
+    g->P.s_v = s_v;
+    g->P.mlp = (const uint16_t*)d_mlp;
+    if (kind == GPOP_SEL_LEARNED && !d_mlp) g->P.selector = GPOP_SEL_ANALYTICAL;
+    return GPOP_OK;
+}
+
+int gpop_scatter(gpop_graph* g, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if ((rc = timed(g, GPOP_KERNEL_PLAN, st, [&] { return launch_plan(g->G, g->P, g->it, st); }, "plan")))
+        return rc;
+    if ((rc = timed(g, GPOP_KERNEL_SCATTER_SC, st,
+                    [&] { return launch_scatter_sc(g->G, g->P, g->prog, g->state, g->it, st); },
+                    "scatter SC")))
+        return rc;
+    if ((rc = timed(g, GPOP_KERNEL_SCATTER_PC, st,
+                    [&] { return launch_scatter_pc(g->G, g->P, g->prog, g->state, g->it, st); },
+                    "scatter PC")))
+        return rc;
+    return GPOP_OK;
+}
+
+int gpop_gather(gpop_graph* g, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = timed(g, GPOP_KERNEL_GATHER, st,
+                   [&] { return launch_gather(g->G, g->P, g->prog, g->state, g->it, st); }, "gather");
+    if (rc) return rc;
+    g->it += 1;
+    return GPOP_OK;
+}
+
+int gpop_iterate(gpop_graph* g, void* stream) {
+    int rc = gpop_scatter(g, stream);
+    if (rc) return rc;
+    return gpop_gather(g, stream);
+}
+
+int gpop_run(gpop_graph* g, uint32_t max_iter, uint32_t* h_iters, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t start = g->it;
+    uint32_t batch = 4;
+    while (g->it - start < max_iter) {
+        const uint32_t n = std::min(batch, max_iter - (g->it - start));
+        for (uint32_t i = 0; i < n; ++i) {
+            int rc = gpop_iterate(g, stream);
+            if (rc) return rc;
+        }
+        Ctrl hc;
+        HIP_OR_RETURN(hipMemcpyAsync(&hc, g->G.ctrl, sizeof hc, hipMemcpyDeviceToHost, st), "read control");
+        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+        if (hc.done) {
+            g->it = hc.iters > start ? hc.iters : start;
+            break;
+        }
+        batch = std::min<uint32_t>(batch * 2, 16);
+    }
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    if (h_iters) *h_iters = g->it - start;
+    return GPOP_OK;
+}
+
+int gpop_frontier_size(gpop_graph* g, uint64_t* h_out, void* stream) {
+    if (!g || !h_out) return fail(GPOP_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<uint32_t> va(g->G.k);
+    HIP_OR_RETURN(hipMemcpyAsync(va.data(), g->G.fVa[g->it & 1u], g->G.k * 4, hipMemcpyDeviceToHost, st),
+                  "read frontier sizes");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    uint64_t t = 0;
+    for (uint32_t x : va) t += x;
+    *h_out = t;
+    return GPOP_OK;
+}
+
+int gpop_iterations(const gpop_graph* g, uint32_t* h_out) {
+    if (!g || !h_out) return fail(GPOP_EINVAL, "NULL argument");
+    *h_out = g->it;
+    return GPOP_OK;
+}
+
+int gpop_iter_stats_read(gpop_graph* g, gpop_iter_stats* h_out, uint32_t max_records,
+                         uint32_t* h_count, void* stream) {
+    if (!g || !h_count || (max_records && !h_out)) return fail(GPOP_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (g->it > 0) HIP_OR_RETURN(launch_finalize(g->G, g->it, st), "finalize stats");
+    const uint32_t avail = std::min<uint32_t>(g->it, kLogCap);
+    const uint32_t n = std::min(avail, max_records);
+    const uint32_t first = g->it - avail;
+    for (uint32_t i = 0; i < n; ++i) {
+        HIP_OR_RETURN(hipMemcpyAsync(h_out + i, g->G.log + ((first + i) % kLogCap), sizeof(gpop_iter_stats),
+                                     hipMemcpyDeviceToHost, st), "read stats");
+    }
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    *h_count = n;
+    return GPOP_OK;
+}
+
+int gpop_modes_read(gpop_graph* g, uint8_t* h_modes, void* stream) {
+    if (!g || !h_modes) return fail(GPOP_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OR_RETURN(hipMemcpyAsync(h_modes, g->G.mode, g->G.k, hipMemcpyDeviceToHost, st), "read modes");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    return GPOP_OK;
+}
+
+int gpop_check(gpop_graph* g, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t err = 0, bug = 0;
+    HIP_OR_RETURN(hipMemcpyAsync(&err, &g->G.ctrl->err, 4, hipMemcpyDeviceToHost, st), "read error word");
+    HIP_OR_RETURN(hipMemcpyAsync(&bug, &g->G.ctrl->bug, 4, hipMemcpyDeviceToHost, st), "read error word");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    if (bug) return fail(GPOP_EDEVICE, "internal error: inconsistent bin detected by gather");
+    if (err) {
+        HIP_OR_RETURN(hipMemsetAsync(&g->G.ctrl->err, 0, 4, st), "clear error word");
+        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+        return fail(GPOP_EINVAL, "a vertex id >= V was passed to gpop_set_frontier");
+    }
+    return GPOP_OK;
+}
+
+int gpop_profile_enable(gpop_graph* g, int enable) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    g->prof = enable != 0;
+    for (int i = 0; i < GPOP_KERNEL_COUNT; ++i) {
+        g->prof_ms[i] = 0;
+        g->prof_n[i] = 0;
+    }
+    return GPOP_OK;
+}
+
+int gpop_profile_read(gpop_graph* g, double* h_ms, uint64_t* h_launches, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    HIP_OR_RETURN(hipStreamSynchronize((hipStream_t)stream), "sync");
+    collect_profile(g);
+    for (int i = 0; i < GPOP_KERNEL_COUNT; ++i) {
+        if (h_ms) h_ms[i] = g->prof_ms[i];
+        if (h_launches) h_launches[i] = g->prof_n[i];
+    }
+    return GPOP_OK;
+}
+
+}  // extern "C"

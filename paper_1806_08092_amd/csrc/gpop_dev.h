@@ -1,0 +1,180 @@
+// Device-side layout and wavefront primitives of the gfx950 engine.
+//
+// Bins (message generation, Sec. 3.1.2): every partition pair (p, q) owns a
+// message range [bin_moff, +M(p,q)) of the value array `data` and an id range
+// [bin_ioff, +E(p,q)) of an id array, both in row-major (p, q) order so one
+// partition's partition-centric scatter writes one contiguous stretch
+// (Algorithm 3 writes bin[p][q] before bin[p][q+1]). Ids are 16-bit local
+// destination ids with bit 15 marking the first id of a message; the
+// partition-centric ids are static (png_ids, written once), the
+// source-centric ids are rewritten each iteration (sc_ids) at the same
+// positions. A chunk table holds, for every 256-id-aligned position, the
+// index of the message containing it, so any 256-id chunk of a bin can be
+// decoded on its own.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gpop.h"
+
+namespace gpop {
+
+constexpr uint32_t kChunk = 256;          // ids per decode chunk
+constexpr uint32_t kFlag = 0x8000u;       // message-start bit of an id
+constexpr uint32_t kLocalMask = 0x7FFFu;  // local destination id bits
+constexpr uint32_t kIdentMin = 0xFFFFFFFFu;  // min-combine identity ("no message")
+constexpr uint32_t kIdentSum = 0x80000000u;  // sum-combine identity: -0.0f bits
+constexpr uint32_t kLogCap = 4096;        // per-iteration stats records
+constexpr double kFix = 1152921504606846976.0;      // 2^60: fixed-point scale of sums
+constexpr double kInvFix = 8.673617379884035e-19;   // 2^-60
+
+enum Prog : int {
+    P_BFS = GPOP_PROG_BFS_LEVEL,
+    P_CC = GPOP_PROG_CC_MINLABEL,
+    P_SSSP = GPOP_PROG_SSSP_U32,
+    P_PR = GPOP_PROG_PAGERANK_F32,
+    P_PPR = GPOP_PROG_PPR_F32,
+    P_CARRY = GPOP_PROG_CARRY_BFS,
+};
+
+__host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || prog == P_PPR; }
+__host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP; }
+
+struct Ctrl {
+    uint32_t done;        // frontier became empty
+    uint32_t iters;       // iterations whose plan found active vertices
+    uint32_t err;         // bad vertex id passed to set_frontier
+    uint32_t csr_err;     // CSR validation failure code
+    uint32_t bug;         // a kernel found an inconsistent bin (internal error)
+    uint64_t frontier;    // sum of V_a at the last plan
+    double dangling;      // PageRank-family dangling mass of the current frontier
+    uint32_t pad[55];
+};
+
+// Everything the kernels read or write, by value in each launch.
+struct Dev {
+    uint32_t V, k, s, q;      // vertices, partitions, log2 q, q
+    uint32_t nbits;           // bits needed for a partition id
+    uint32_t n_pctask;
+    uint64_t E;
+    const uint32_t* off;
+    const uint32_t* cols;
+    const uint8_t* w;
+    // static (preprocessing)
+    uint32_t* part_E;         // [k] out-edges of partition p
+    uint32_t* part_M;         // [k] messages of p when all of it is active
+    uint32_t* bin_moff;       // [k*k+1] row-major message offsets
+    uint32_t* bin_ioff;       // [k*k+1] row-major id offsets
+    uint4* cm;                // [k*k] column-major {moff, ioff, mcnt, icnt}, index q*k+p
+    uint16_t* png_src;        // [M] local source id of each message
+    uint16_t* png_ids;        // [E_pad] static ids
+    uint8_t* png_w;           // [E_pad] static weights
+    uint32_t* png_chunk;      // [E_pad/256]
+    uint4* pctask;            // [n_pctask] {p, slot_begin, slot_end, 0}
+    // per iteration
+    uint32_t* data;           // [M] message values
+    uint16_t* sc_ids;         // [E_pad]
+    uint8_t* sc_w;            // [E_pad]
+    uint32_t* sc_chunk;       // [E_pad/256]
+    uint2* sc_cnt;            // [k*k] column-major {mcnt, icnt} of SC bins
+    uint2* sc_tot;            // [k] SC totals {msgs, ids} per partition
+    uint32_t* gat_ids;        // [k] ids gathered per column
+    uint8_t* mode;            // [k]
+    uint16_t* flist[2];       // [k*q] frontier lists (local ids, ascending)
+    uint32_t* fbits[2];       // [k*q/32] frontier bitmaps
+    uint32_t* fVa[2];         // [k]
+    uint32_t* fEa[2];         // [k]
+    double* dpart[2];         // [k] dangling partial sums
+    uint8_t* marks;           // [k*q] set_frontier scratch
+    uint32_t* cnt_m;          // [k*k] preprocessing counts, row-major
+    uint32_t* cnt_i;          // [k*k]
+    uint32_t* scan_tmp;       // scan scratch
+    Ctrl* ctrl;
+    gpop_iter_stats* log;     // [kLogCap]
+};
+
+// Program parameters and the mode model.
+struct Params {
+    uint32_t root, persist;
+    float damping, alpha;
+    double inv_n;             // 1 / V
+    uint32_t selector;        // gpop_selector
+    uint32_t s_i, s_v;        // model element sizes (bytes)
+    uint32_t ratio_num, ratio_den;  // BW_PC / BW_SC as a fraction
+    const uint16_t* mlp;      // bf16 weights or null
+};
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Number of set bits of m among lanes below the calling lane.
+__device__ __forceinline__ uint32_t popc_lt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (l >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Butterfly sum: the same fixed tree on every call, so results are
+// reproducible bit for bit.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ bool test_bit(const uint32_t* bits, uint32_t i) {
+    return (bits[i >> 5] >> (i & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+    uint32_t c = a + b;
+    return c < a ? 0xFFFFFFFFu : c;
+}
+
+// scatterFunc of each program for an active vertex v (global id).
+template <int PROG>
+__device__ __forceinline__ uint32_t scatter_value(const Dev& G, const uint32_t* st, uint32_t v) {
+    if constexpr (PROG == P_BFS || PROG == P_CARRY) {
+        return st[v] + 1u;
+    } else if constexpr (PROG == P_CC || PROG == P_SSSP) {
+        return st[v];
+    } else {
+        uint32_t deg = G.off[v + 1] - G.off[v];
+        float x = __uint_as_float(st[v]);
+        return __float_as_uint(deg ? x / (float)deg : 0.0f);
+    }
+}
+
+template <int PROG>
+__device__ __forceinline__ uint32_t ident_of() {
+    return is_sum(PROG) ? kIdentSum : kIdentMin;
+}
+
+}  // namespace gpop

@@ -1,0 +1,37 @@
+// Host-side launchers of the engine's kernels (one translation unit each).
+#pragma once
+
+#include "gpop_dev.h"
+
+namespace gpop {
+
+// preprocessing (png.hip)
+hipError_t launch_validate(const Dev& G, hipStream_t st);
+hipError_t launch_part_E(const Dev& G, hipStream_t st);
+hipError_t launch_scan_excl(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* tmp,
+                            hipStream_t st);
+size_t scan_tmp_words(uint64_t n);
+hipError_t launch_part_M(const Dev& G, hipStream_t st);
+hipError_t launch_colmajor(const Dev& G, hipStream_t st);
+
+// scatter side (scatter.hip)
+size_t sc_lds_bytes(uint32_t k, int waves);
+int sc_waves_for(uint32_t k);
+hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st);
+hipError_t launch_plan(const Dev& G, const Params& P, uint32_t it, hipStream_t st);
+hipError_t launch_finalize(const Dev& G, uint32_t it, hipStream_t st);
+hipError_t launch_scatter_sc(const Dev& G, const Params& P, int prog, const uint32_t* state,
+                             uint32_t it, hipStream_t st);
+hipError_t launch_scatter_pc(const Dev& G, const Params& P, int prog, const uint32_t* state,
+                             uint32_t it, hipStream_t st);
+
+// gather side (gather.hip)
+size_t gather_lds_bytes(int prog, uint32_t q);
+hipError_t launch_gather(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
+                         hipStream_t st);
+hipError_t launch_state_init(const Dev& G, const Params& P, int prog, uint32_t* state,
+                             hipStream_t st);
+hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all,
+                               uint32_t buf, hipStream_t st);
+
+}  // namespace gpop

@@ -1,0 +1,162 @@
+// Preprocessing: CSR validation, per-partition statistics, bin offsets and
+// the column-major bin table the gather reads (graph partitioning Sec. 3.1.1,
+// message generation Sec. 3.1.2, PNG layout of Algorithm 3).
+#include "launch.h"
+
+namespace gpop {
+
+// Error codes written to Ctrl::csr_err (plain stores: any writer sets it).
+// 1 offsets[0] != 0, 2 decreasing offsets or offsets beyond E,
+// 3 offsets[V] != E, 4 column >= V, 5 row not sorted ascending.
+__global__ void k_validate(Dev G) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= G.V) return;
+    const uint32_t a = G.off[v], b = G.off[v + 1];
+    if (v == 0 && a != 0) G.ctrl->csr_err = 1;
+    if (a > b || (uint64_t)b > G.E) {
+        G.ctrl->csr_err = 2;
+        return;
+    }
+    if (v == G.V - 1 && (uint64_t)b != G.E) G.ctrl->csr_err = 3;
+    uint32_t prev = 0;
+    for (uint32_t e = a; e < b; ++e) {
+        const uint32_t c = G.cols[e];
+        if (c >= G.V) {
+            G.ctrl->csr_err = 4;
+            return;
+        }
+        if (e > a && c < prev) {
+            G.ctrl->csr_err = 5;
+            return;
+        }
+        prev = c;
+    }
+}
+
+hipError_t launch_validate(const Dev& G, hipStream_t st) {
+    hipLaunchKernelGGL(k_validate, dim3((G.V + 255) / 256), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
+// E^p: out-edges of the index range of partition p.
+__global__ void k_part_E(Dev G) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= G.k) return;
+    const uint32_t lo = p << G.s;
+    const uint32_t hi = min(lo + G.q, G.V);
+    G.part_E[p] = G.off[hi] - G.off[lo];
+}
+
+hipError_t launch_part_E(const Dev& G, hipStream_t st) {
+    hipLaunchKernelGGL(k_part_E, dim3((G.k + 255) / 256), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------- exclusive scan (u32)
+constexpr uint32_t kScanT = 256, kScanPer = 16, kScanTile = kScanT * kScanPer;
+
+size_t scan_tmp_words(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+__device__ uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
+    __shared__ uint32_t s_w[kScanT / 64];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (uint32_t w = 0; w < kScanT / 64; ++w) {
+        if (w < wave) before += s_w[w];
+        tot += s_w[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - x;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan_tiles(const uint32_t* __restrict__ in, uint64_t n,
+                                                       uint32_t* __restrict__ tile_sums) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+    uint32_t s = 0;
+    for (uint32_t j = 0; j < kScanPer; ++j)
+        if (base + j < n) s += in[base + j];
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan_sums(uint32_t* __restrict__ sums, uint32_t nt,
+                                                      uint32_t* __restrict__ out_total) {
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nt; b0 += kScanT) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t x = i < nt ? sums[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(x, &tot);
+        if (i < nt) sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan_apply(const uint32_t* __restrict__ in, uint64_t n,
+                                                       const uint32_t* __restrict__ tile_off,
+                                                       uint32_t* __restrict__ out) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t s = 0;
+    for (uint32_t j = 0; j < kScanPer; ++j) {
+        v[j] = base + j < n ? in[base + j] : 0u;
+        s += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = tile_off[blockIdx.x] + block_excl_scan(s, &tot);
+    for (uint32_t j = 0; j < kScanPer; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+}
+
+// out[i] = sum of in[0..i) for i <= n (n + 1 entries). tmp holds
+// scan_tmp_words(n) words.
+hipError_t launch_scan_excl(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* tmp,
+                            hipStream_t st) {
+    const uint32_t nt = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    if (nt) hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kScanT), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanT), 0, st, tmp, nt, out + n);
+    if (nt) hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kScanT), 0, st, in, n, tmp, out);
+    return hipGetLastError();
+}
+
+// M^p from the row-major message offsets.
+__global__ void k_part_M(Dev G) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= G.k) return;
+    const size_t k = G.k;
+    G.part_M[p] = G.bin_moff[(p + 1) * k] - G.bin_moff[p * k];
+}
+
+hipError_t launch_part_M(const Dev& G, hipStream_t st) {
+    hipLaunchKernelGGL(k_part_M, dim3((G.k + 255) / 256), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
+// Column-major copy: cm[q*k + p] = {moff, ioff, mcnt, icnt} of bin[p][q].
+__global__ void k_colmajor(Dev G) {
+    const uint64_t kk = (uint64_t)G.k * G.k;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < kk;
+         o += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = o / G.k, p = o % G.k;
+        const uint64_t r = p * G.k + q;
+        G.cm[o] = make_uint4(G.bin_moff[r], G.bin_ioff[r], G.cnt_m[r], G.cnt_i[r]);
+    }
+}
+
+hipError_t launch_colmajor(const Dev& G, hipStream_t st) {
+    const uint64_t kk = (uint64_t)G.k * G.k;
+    const uint64_t want = (kk + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_colmajor, dim3(blocks), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
+}  // namespace gpop

@@ -1,0 +1,46 @@
+"""Helpers for GPU tests: run a program through the C-ABI on seeded inputs."""
+import numpy as np
+
+import graphgen as gg
+
+
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+def make_graph(g, log2_part):
+    import paper_1806_08092_amd as gp
+    off, cols, w = gp.upload_csr(g)
+    return gp.Graph(off, cols, w, log2_part=log2_part), (off, cols, w)
+
+
+def run_program(G, prog, n, root=0, persist=1, selector="analytical", max_iter=1 << 20,
+                damping=0.85, alpha=0.15, bw_ratio=2.0, frontier=None):
+    """Runs one program to completion (or max_iter) and returns the state as
+    a numpy array (uint32 or float32) plus the iterations run."""
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    G.set_selector(selector, bw_ratio)
+    G.state_init(prog, st, root=root, persist=persist, damping=damping, alpha=alpha)
+    if frontier is not None:
+        G.set_frontier(torch.as_tensor(np.asarray(frontier, np.int32), device="cuda"))
+    elif prog in ("cc", "pagerank"):
+        G.set_frontier_all()
+    else:
+        G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+    iters = G.run(max_iter)
+    G.check()
+    torch.cuda.synchronize()
+    out = st.cpu().numpy()
+    if prog in ("pagerank", "ppr"):
+        return out.view(np.float32), iters
+    return out.view(np.uint32), iters
+
+
+def pr_ok(x32, ref64, max_abs=1e-6, rel_l1=1e-5):
+    x = x32.astype(np.float64)
+    return (np.max(np.abs(x - ref64)) <= max_abs and
+            np.sum(np.abs(x - ref64)) <= rel_l1 * np.sum(np.abs(ref64)))

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path through the C-ABI against the oracle, element by
+element, on seeded inputs. Integer programs must be bit-exact; PageRank-family
+results within 1e-6 max-abs and 1e-5 relative L1 of the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle import gpop_ref
+
+from gpu_util import make_graph, pr_ok, run_program
+
+pytestmark = pytest.mark.gpu
+
+INF = 0xFFFFFFFF
+SELECTORS = ["analytical", "sc", "pc"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def edges_graph(n, edges, wseed=None):
+    src = np.array([e[0] for e in edges], np.uint32)
+    dst = np.array([e[1] for e in edges], np.uint32)
+    return gg.from_edges(n, src, dst, wseed)
+
+
+def zoo():
+    """(name, graph, log2_part): skewed, uniform, deep, degenerate."""
+    out = [
+        ("rmat10", gg.rmat_graph(10, 8, 11, weights_seed=12), 8),
+        ("rmat11sym", gg.rmat_graph(11, 8, 13, symmetric=True, weights_seed=14), 8),
+        ("er3000", gg.er_graph(3000, 24000, 15, weights_seed=16), 8),
+        ("path700", edges_graph(700, [(i, i + 1) for i in range(699)] +
+                                [(i + 1, i) for i in range(699)], 17), 8),
+        ("star", edges_graph(1500, [(0, i) for i in range(1, 1500)] +
+                             [(i, 0) for i in range(1, 1500)], 18), 8),
+        ("messy", edges_graph(777, [(0, 0), (0, 0), (5, 5), (3, 700), (3, 700), (700, 3),
+                                    (776, 0), (0, 776)] +
+                              [(i, (i * 37) % 777) for i in range(0, 777, 3)], 19), 8),
+        ("single", edges_graph(1, [(0, 0)], 20), 8),
+        ("noedges", edges_graph(300, [], 21), 8),
+        ("rmat12_q10", gg.rmat_graph(12, 16, 22, weights_seed=23), 10),
+    ]
+    return out
+
+
+ZOO = None
+
+
+def get_zoo():
+    global ZOO
+    if ZOO is None:
+        ZOO = [(name, g, lp, make_graph(g, lp)) for name, g, lp in zoo()]
+    return ZOO
+
+
+def roots_of(g, n=3):
+    r = gg.pick_sources(g.offsets, 99, n).tolist()
+    return r if r else [0]
+
+
+@pytest.mark.parametrize("zi", range(9))
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_bfs_levels(zi, sel):
+    name, g, lp, (G, _) = get_zoo()[zi]
+    for root in roots_of(g):
+        say("bfs", name, sel, "root", root)
+        got, iters = run_program(G, "bfs", g.n, root=root, selector=sel)
+        ref = oracle.bfs_levels(g, root)
+        assert np.array_equal(got, ref), (name, sel, root, np.flatnonzero(got != ref)[:10])
+
+
+@pytest.mark.parametrize("zi", range(9))
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_sssp(zi, sel):
+    name, g, lp, (G, _) = get_zoo()[zi]
+    for root in roots_of(g, 2):
+        say("sssp", name, sel, "root", root)
+        got, _ = run_program(G, "sssp", g.n, root=root, selector=sel)
+        ref = oracle.sssp(g, root)
+        assert np.array_equal(got, ref), (name, sel, root, np.flatnonzero(got != ref)[:10])
+
+
+@pytest.mark.parametrize("zi", range(9))
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_cc(zi, sel):
+    name, g, lp, _ = get_zoo()[zi]
+    sym = gg.from_edges(g.n, *gg.symmetrize(*edge_arrays(g)))
+    G, keep = make_graph(sym, lp)
+    say("cc", name, sel)
+    got, _ = run_program(G, "cc", sym.n, selector=sel)
+    ref = oracle.cc_minlabel(sym)
+    assert np.array_equal(got, ref), (name, sel, np.flatnonzero(got != ref)[:10])
+
+
+def edge_arrays(g):
+    rows = np.repeat(np.arange(g.n, dtype=np.uint32), np.diff(g.offsets.astype(np.int64)))
+    return rows, g.cols.copy()
+
+
+@pytest.mark.parametrize("zi", [0, 1, 2, 4, 5, 7, 8])
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_pagerank(zi, sel):
+    name, g, lp, (G, _) = get_zoo()[zi]
+    say("pagerank", name, sel)
+    got, iters = run_program(G, "pagerank", g.n, selector=sel, max_iter=10)
+    assert iters == 10
+    ref = oracle.pagerank(g, 0.85, 10)
+    assert pr_ok(got, ref), (name, sel, np.max(np.abs(got - ref)))
+    assert abs(float(got.astype(np.float64).sum()) - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("zi", [0, 1, 2, 5, 8])
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_ppr(zi, sel):
+    name, g, lp, (G, _) = get_zoo()[zi]
+    for seed in roots_of(g, 2):
+        say("ppr", name, sel, seed)
+        got, _ = run_program(G, "ppr", g.n, root=seed, selector=sel, max_iter=20)
+        ref = oracle.ppr(g, seed, 0.15, 20)
+        assert pr_ok(got, ref), (name, sel, seed, np.max(np.abs(got - ref)))
+
+
+@pytest.mark.parametrize("persist", [1, 2, 3])
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_carry_frontier_sizes(persist, sel):
+    # selective continuity: vertices stay active for `persist` iterations
+    name, g, lp, (G, _) = get_zoo()[1]
+    root = roots_of(g, 1)[0]
+    got, iters = run_program(G, "carry_bfs", g.n, root=root, persist=persist, selector=sel)
+    lv = oracle.bfs_levels(g, root)
+    assert np.array_equal(got, lv)
+    stats = G.iter_stats()
+    finite = lv[lv != INF].astype(np.int64)
+    for it, rec in enumerate(stats):
+        want = int(np.sum((finite <= it) & (finite > it - persist)))
+        assert rec["active_vertices"] == want, (it, rec, want)
+
+
+def test_iteration_stats_match_model():
+    """Per iteration: active vertices/edges and the SC/PC partition counts
+    equal what the oracle's mode model decides for the BFS frontiers."""
+    name, g, lp, (G, _) = get_zoo()[8]
+    root = roots_of(g, 1)[0]
+    got, iters = run_program(G, "bfs", g.n, root=root, selector="analytical")
+    lv = oracle.bfs_levels(g, root)
+    q = 1 << lp
+    png = gpop_ref.build_png(g, q)
+    deg = g.degrees()
+    stats = G.iter_stats()
+    assert len(stats) == iters
+    for it, rec in enumerate(stats):
+        act = np.flatnonzero(lv == it)
+        assert rec["active_vertices"] == len(act)
+        assert rec["active_edges"] == int(deg[act].sum())
+        nsc = npc = 0
+        for p in np.unique(act // q):
+            a = act[act // q == p]
+            m = gpop_ref.choose_mode(png.E[p], png.M[p], len(a), int(deg[a].sum()), png.k)
+            nsc += m == "SC"
+            npc += m == "PC"
+        assert (rec["sc_parts"], rec["pc_parts"]) == (nsc, npc), (it, rec)
+
+
+def test_pagerank_c1_workload():
+    """The PageRank workload itself: directed RMAT scale 16, edge factor 16,
+    10 iterations, d = 0.85, against the FP64 oracle."""
+    g = gg.workload_pagerank_rmat16()
+    G, _ = make_graph(g, 13)
+    for sel in SELECTORS:
+        got, _ = run_program(G, "pagerank", g.n, selector=sel, max_iter=10)
+        ref = oracle.pagerank(g, 0.85, 10)
+        err = np.abs(got.astype(np.float64) - ref)
+        say("C1 pagerank", sel, "max abs", err.max(), "rel l1", err.sum() / ref.sum())
+        assert pr_ok(got, ref)
+
+
+def test_mode_invariance_bitwise():
+    """The mode never changes the arithmetic: forced SC, forced PC and the
+    analytical choice give identical bits, also for PageRank."""
+    name, g, lp, (G, _) = get_zoo()[8]
+    outs = {}
+    for prog, kw in [("bfs", dict(root=roots_of(g, 1)[0])), ("pagerank", dict(max_iter=10)),
+                     ("ppr", dict(root=roots_of(g, 1)[0], max_iter=20))]:
+        res = [run_program(G, prog, g.n, selector=s, **kw)[0] for s in SELECTORS]
+        for r in res[1:]:
+            assert np.array_equal(r.view(np.uint32), res[0].view(np.uint32)), prog
+
+
+def test_determinism_repeat():
+    name, g, lp, (G, _) = get_zoo()[0]
+    a, _ = run_program(G, "pagerank", g.n, max_iter=10)
+    b, _ = run_program(G, "pagerank", g.n, max_iter=10)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_partition_sizes_agree():
+    g = gg.rmat_graph(13, 8, 31, symmetric=True)
+    root = roots_of(g, 1)[0]
+    ref = oracle.bfs_levels(g, root)
+    for lp in (8, 10, 12, 14):
+        G, _ = make_graph(g, lp)
+        got, _ = run_program(G, "bfs", g.n, root=root)
+        assert np.array_equal(got, ref), lp
+        got, _ = run_program(G, "cc", g.n)
+        assert np.array_equal(got, oracle.cc_minlabel(g)), lp
+
+
+def test_bad_frontier_vertex_reported():
+    import torch
+    import paper_1806_08092_amd as gp
+    name, g, lp, (G, _) = get_zoo()[0]
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    G.state_init("bfs", st, root=0)
+    G.set_frontier(torch.tensor([0, g.n + 5], dtype=torch.int32, device="cuda"))
+    with pytest.raises(gp.GpopError) as e:
+        G.check()
+    assert e.value.code == gp.EINVAL
+    G.check()  # cleared
+
+
+def test_max_iter_partial_state():
+    name, g, lp, (G, _) = get_zoo()[3]  # path: one level per iteration
+    got, iters = run_program(G, "bfs", g.n, root=0, max_iter=5)
+    assert iters == 5
+    assert G.frontier_size() == 1
+    ref = oracle.bfs_levels(g, 0)
+    assert np.array_equal(got[:6], ref[:6]) and np.all(got[6:] == INF)
+    # continuing finishes the traversal
+    G.run()
+    import torch
+    torch.cuda.synchronize()
+
+
+def test_malformed_csr_rejected():
+    import torch
+    import paper_1806_08092_amd as gp
+    off = torch.tensor([0, 2, 3], dtype=torch.int32, device="cuda")
+    for cols in ([1, 0, 1], [0, 5, 1]):  # unsorted row, column out of range
+        c = torch.tensor(cols, dtype=torch.int32, device="cuda")
+        with pytest.raises(gp.GpopError) as e:
+            gp.Graph(off, c, log2_part=8)
+        assert e.value.code == gp.EINVAL
+    bad_off = torch.tensor([0, 3, 2], dtype=torch.int32, device="cuda")
+    with pytest.raises(gp.GpopError):
+        gp.Graph(bad_off, torch.tensor([0, 1, 1], dtype=torch.int32, device="cuda"), log2_part=8)
