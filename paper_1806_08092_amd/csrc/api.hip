@@ -323,7 +323,7 @@ int gpop_state_init(gpop_graph* g, gpop_program prog, const gpop_params* prm, vo
     const bool rooted = prog != GPOP_PROG_CC_MINLABEL && prog != GPOP_PROG_PAGERANK_F32;
     if (rooted && prm->root >= g->G.V) return fail(GPOP_EINVAL, "root %u >= V", prm->root);
     if (prog == GPOP_PROG_CARRY_BFS && prm->persist == 0) return fail(GPOP_EINVAL, "persist must be >= 1");
-    if (prog == GPOP_PROG_SSSP_U32 && !g->G.w) return fail(GPOP_EINVAL, "SSSP needs edge weights");
+    if (prog == GPOP_PROG_SSSP_U32 && !g->G.w && g->G.E > 0) return fail(GPOP_EINVAL, "SSSP needs edge weights");
     if (prog == GPOP_PROG_PAGERANK_F32 && !(prm->damping >= 0.f && prm->damping <= 1.f))
         return fail(GPOP_EINVAL, "damping must be in [0, 1]");
     if (prog == GPOP_PROG_PPR_F32 && !(prm->alpha >= 0.f && prm->alpha <= 1.f))
