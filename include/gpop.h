@@ -90,7 +90,13 @@ typedef struct gpop_graph_desc {
 typedef struct gpop_options {
     uint32_t log2_part;   /* q = 2^log2_part vertices per partition, 8..15;
                              0 picks 14 (16384 vertices)                        */
-    uint32_t reserved[7]; /* must be zero                                      */
+    uint32_t sc_task_log2;     /* log2 of active edges per source-centric task,
+                                  6..24; 0 picks max(2048, 8k)                  */
+    uint32_t gather_task_ids;  /* ids per gather task (>= 256); 0 picks
+                                  max(2^18, E / 512). A partition whose bins
+                                  hold more ids is gathered by several tasks
+                                  (at most 64) and merged                      */
+    uint32_t reserved[5];      /* must be zero                                  */
 } gpop_options;
 
 typedef struct gpop_plan_info {
@@ -124,9 +130,13 @@ typedef struct gpop_iter_stats {
     uint32_t sc_parts, pc_parts;
     uint64_t sc_msgs, sc_ids;   /* messages / ids written in SC mode           */
     uint64_t pc_msgs, pc_ids;   /* messages / static ids of PC partitions      */
-    uint64_t gathered_ids;      /* ids read by gather                          */
-    uint32_t gather_parts;      /* partitions gathered                         */
-    uint32_t reserved;
+    uint64_t gathered_ids;      /* non-identity ids combined by gather         */
+    uint32_t gather_parts;      /* whole-partition gather tasks that ran       */
+    uint32_t split_tasks;       /* partial gather tasks that wrote a result    */
+    uint64_t sc_active_vertices; /* V_a summed over SC partitions              */
+    uint64_t sc_active_edges;    /* E_a summed over SC partitions              */
+    uint64_t pc_vertices;        /* vertices of PC partitions                  */
+    uint64_t merged_parts;       /* split partitions merged                    */
 } gpop_iter_stats;
 
 /* ------------------------------------------------------------------ setup */
@@ -228,7 +238,8 @@ int gpop_check(struct gpop_graph* g, void* stream);
 #define GPOP_KERNEL_SCATTER_SC 1
 #define GPOP_KERNEL_SCATTER_PC 2
 #define GPOP_KERNEL_GATHER 3
-#define GPOP_KERNEL_COUNT 4
+#define GPOP_KERNEL_MERGE 4  /* combine of partitions gathered by several tasks */
+#define GPOP_KERNEL_COUNT 5
 
 /* When enabled, every kernel launch is bracketed by HIP events on its
  * stream. gpop_profile_read synchronises the stream and returns, per kernel

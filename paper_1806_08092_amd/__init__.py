@@ -27,7 +27,7 @@ SEL_ANALYTICAL, SEL_FORCE_SC, SEL_FORCE_PC, SEL_LEARNED = range(4)
 SELECTORS = {"analytical": SEL_ANALYTICAL, "sc": SEL_FORCE_SC, "pc": SEL_FORCE_PC,
              "learned": SEL_LEARNED}
 MODE_NONE, MODE_SC, MODE_PC = 0, 1, 2
-KERNELS = ["plan", "scatter_sc", "scatter_pc", "gather"]
+KERNELS = ["plan", "scatter_sc", "scatter_pc", "gather", "merge"]
 
 
 class GpopError(RuntimeError):
@@ -43,7 +43,8 @@ class GraphDesc(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("log2_part", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+    _fields_ = [("log2_part", ctypes.c_uint32), ("sc_task_log2", ctypes.c_uint32),
+                ("gather_task_ids", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -70,7 +71,9 @@ class IterStats(ctypes.Structure):
                 ("sc_msgs", ctypes.c_uint64), ("sc_ids", ctypes.c_uint64),
                 ("pc_msgs", ctypes.c_uint64), ("pc_ids", ctypes.c_uint64),
                 ("gathered_ids", ctypes.c_uint64), ("gather_parts", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("split_tasks", ctypes.c_uint32), ("sc_active_vertices", ctypes.c_uint64),
+                ("sc_active_edges", ctypes.c_uint64), ("pc_vertices", ctypes.c_uint64),
+                ("merged_parts", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
@@ -151,9 +154,10 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
-def plan(num_vertices: int, num_edges: int, log2_part: int = 14) -> PlanInfo:
+def plan(num_vertices: int, num_edges: int, log2_part: int = 14, sc_task_log2: int = 0,
+         gather_task_ids: int = 0) -> PlanInfo:
     d = GraphDesc(num_vertices, 0, num_edges, None, None, None)
-    o = Options(log2_part)
+    o = Options(log2_part, sc_task_log2, gather_task_ids)
     out = PlanInfo()
     _check(lib().gpop_plan(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)))
     return out
@@ -164,14 +168,15 @@ class Graph:
     optional `weights` (uint8) are CUDA tensors the caller keeps alive; the
     workspace is allocated here as a torch tensor and owned by this object."""
 
-    def __init__(self, offsets, cols, weights=None, log2_part: int = 14, stream=None):
+    def __init__(self, offsets, cols, weights=None, log2_part: int = 14, stream=None,
+                 sc_task_log2: int = 0, gather_task_ids: int = 0):
         import torch
         self._keep = (offsets, cols, weights)
         n = offsets.numel() - 1
         m = cols.numel()
         self.desc = GraphDesc(n, 0, m, offsets.data_ptr(), cols.data_ptr() if m else 0,
                               None if weights is None else weights.data_ptr())
-        self.opts = Options(log2_part)
+        self.opts = Options(log2_part, sc_task_log2, gather_task_ids)
         info = PlanInfo()
         _check(lib().gpop_plan(ctypes.byref(self.desc), ctypes.byref(self.opts), ctypes.byref(info)))
         self.q, self.k = info.q, info.k
@@ -265,10 +270,11 @@ class Graph:
         _check(lib().gpop_profile_enable(self.h, 1 if on else 0))
 
     def profile_read(self, stream=None):
-        ms = (ctypes.c_double * 4)()
-        n = (ctypes.c_uint64 * 4)()
+        nk = len(KERNELS)
+        ms = (ctypes.c_double * nk)()
+        n = (ctypes.c_uint64 * nk)()
         _check(lib().gpop_profile_read(self.h, ms, n, _stream(stream)))
-        return {KERNELS[i]: (ms[i], int(n[i])) for i in range(4)}
+        return {KERNELS[i]: (ms[i], int(n[i])) for i in range(nk)}
 
 
 def upload_csr(g, device="cuda"):

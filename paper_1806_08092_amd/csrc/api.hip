@@ -57,29 +57,57 @@ struct gpop_graph {
     bool prof = false;
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
-    double prof_ms[GPOP_KERNEL_COUNT] = {0, 0, 0, 0};
-    uint64_t prof_n[GPOP_KERNEL_COUNT] = {0, 0, 0, 0};
+    double prof_ms[GPOP_KERNEL_COUNT] = {};
+    uint64_t prof_n[GPOP_KERNEL_COUNT] = {};
 };
 
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Carves every device buffer out of `base` (nullptr: just measure). Returns
-// the bytes needed.
-size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, uint32_t s) {
+// Task sizes of a graph: active out-edges per source-centric task (at least
+// 2048 and at least 8k, so the per-task count row stays small next to the
+// task's edges) and ids per gather task (enough tasks to spread hub
+// partitions over the chip).
+struct Sizes {
+    uint32_t s, sc_shift;
+    uint64_t q, k, T;
+};
+
+Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
+    Sizes z{};
+    z.s = s;
+    z.q = 1ull << s;
+    z.k = (V + z.q - 1) / z.q;
+    z.sc_shift = 11;
+    while ((1ull << z.sc_shift) < 8 * z.k) ++z.sc_shift;
+    if (o && o->sc_task_log2) z.sc_shift = o->sc_task_log2;
+    z.T = std::max<uint64_t>(1ull << 18, E / 512);
+    if (o && o->gather_task_ids) z.T = o->gather_task_ids;
+    return z;
+}
+
+uint64_t max_sctask_for(uint64_t E, const Sizes& z) { return (E >> z.sc_shift) + z.k + 1; }
+
+uint64_t max_gtask_for(uint64_t E, const Sizes& z) {
+    return (E + 512ull * z.k * z.k) / z.T + z.k + 1;
+}
+
+size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z) {
     size_t o = 0;
     auto take = [&](size_t bytes) -> char* {
         char* p = base ? base + o : nullptr;
         o += align256(bytes ? bytes : 1);
         return p;
     };
-    const uint64_t q = 1ull << s;
-    const uint64_t k = (V + q - 1) / q;
+    const uint64_t q = z.q;
+    const uint64_t k = z.k;
     const uint64_t kk = k * k;
     const uint64_t E_pad = align256(E ? E : 1);
     const uint64_t nch = E_pad / kChunk;
     const uint64_t ntask = E / kPcTask + k + 1;
+    const uint64_t nsct = max_sctask_for(E, z);
+    const uint64_t ngt = max_gtask_for(E, z);
     G->part_E = (uint32_t*)take(k * 4);
     G->part_M = (uint32_t*)take(k * 4);
     G->bin_moff = (uint32_t*)take((kk + 1) * 4);
@@ -90,19 +118,28 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, uint32_t s) {
     G->png_w = (uint8_t*)take(E_pad);
     G->png_chunk = (uint32_t*)take(nch * 4);
     G->pctask = (uint4*)take(ntask * 16);
+    G->bld_t0 = (uint32_t*)take((k + 1) * 4);
+    G->gtask = (uint4*)take(ngt * 32);
+    G->gsplit = (uint4*)take(k * 16);
+    G->gpart = (uint32_t*)take(ngt * q * 8);
+    G->gflag = (uint32_t*)take(ngt * 4);
     G->data = (uint32_t*)take(E_pad * 4);
     G->sc_ids = (uint16_t*)take(E_pad * 2);
     G->sc_w = (uint8_t*)take(E_pad);
     G->sc_chunk = (uint32_t*)take(nch * 4);
     G->sc_cnt = (uint2*)take(kk * 8);
     G->sc_tot = (uint2*)take(k * 8);
-    G->gat_ids = (uint32_t*)take(k * 4);
+    G->sc_t0 = (uint32_t*)take((k + 1) * 4);
+    G->sc_tc = (uint2*)take(nsct * k * 8);
+    G->gat_ids = (uint32_t*)take(ngt * 4);
+    G->gat_ran = (uint32_t*)take((ngt + k) * 4);
     G->mode = (uint8_t*)take(k);
     for (int b = 0; b < 2; ++b) {
         G->flist[b] = (uint16_t*)take(k * q * 2);
         G->fbits[b] = (uint32_t*)take(k * q / 8);
         G->fVa[b] = (uint32_t*)take(k * 4);
         G->fEa[b] = (uint32_t*)take(k * 4);
+        G->fpre[b] = (uint32_t*)take(k * q * 4);
         G->dpart[b] = (double*)take(k * 8);
     }
     G->marks = (uint8_t*)take(k * q);
@@ -121,9 +158,13 @@ int check_desc(const gpop_graph_desc* d, const gpop_options* o, uint32_t* s_out)
     if (d->reserved0) return fail(GPOP_EINVAL, "reserved0 must be zero");
     uint32_t s = 14;
     if (o) {
-        for (int i = 0; i < 7; ++i)
+        for (int i = 0; i < 5; ++i)
             if (o->reserved[i]) return fail(GPOP_EINVAL, "options.reserved must be zero");
         if (o->log2_part) s = o->log2_part;
+        if (o->sc_task_log2 && (o->sc_task_log2 < 6 || o->sc_task_log2 > 24))
+            return fail(GPOP_EINVAL, "sc_task_log2 must be 0 or in [6, 24]");
+        if (o->gather_task_ids && o->gather_task_ids < 256)
+            return fail(GPOP_EINVAL, "gather_task_ids must be 0 or >= 256");
     }
     if (s < 8 || s > 15) return fail(GPOP_EINVAL, "log2_part must be in [8, 15]");
     const uint64_t q = 1ull << s;
@@ -201,7 +242,8 @@ int gpop_plan(const gpop_graph_desc* desc, const gpop_options* opts, gpop_plan_i
     memset(out, 0, sizeof *out);
     out->q = 1u << s;
     out->k = (desc->num_vertices + out->q - 1) / out->q;
-    out->workspace_bytes = carve(&G, nullptr, desc->num_vertices, desc->num_edges, s);
+    out->workspace_bytes = carve(&G, nullptr, desc->num_vertices, desc->num_edges,
+                                 sizes_for(desc->num_vertices, desc->num_edges, s, opts));
     return GPOP_OK;
 }
 
@@ -216,10 +258,11 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
         return fail(GPOP_EINVAL, "offsets/cols must be device pointers");
     if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(GPOP_EINVAL, "workspace must be 256-byte aligned");
     Dev G{};
-    const size_t need = carve(&G, nullptr, desc->num_vertices, desc->num_edges, s);
+    const Sizes z = sizes_for(desc->num_vertices, desc->num_edges, s, opts);
+    const size_t need = carve(&G, nullptr, desc->num_vertices, desc->num_edges, z);
     if (ws_bytes < need)
         return fail(GPOP_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
-    carve(&G, (char*)d_ws, desc->num_vertices, desc->num_edges, s);
+    carve(&G, (char*)d_ws, desc->num_vertices, desc->num_edges, z);
     G.V = desc->num_vertices;
     G.E = desc->num_edges;
     G.s = s;
@@ -232,7 +275,9 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     G.w = desc->weights;
     hipStream_t st = (hipStream_t)stream;
 
-    if (sc_lds_bytes(G.k, sc_waves_for(G.k)) > (size_t)max_lds_per_block() ||
+    G.sc_shift = z.sc_shift;
+    G.max_sctask = (uint32_t)max_sctask_for(G.E, z);
+    if (sc_lds_bytes(G.k) > (size_t)max_lds_per_block() ||
         gather_lds_bytes(P_BFS, G.q) + 2048 > (size_t)max_lds_per_block())
         return fail(GPOP_ENOTSUP, "partition of %u vertices does not fit the LDS", G.q);
 
@@ -248,6 +293,20 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     }
     const uint64_t kk = (uint64_t)G.k * G.k;
     HIP_OR_RETURN(launch_part_E(G, st), "partition edges");
+    std::vector<uint32_t> partE(G.k), bld(G.k + 1);
+    HIP_OR_RETURN(hipMemcpyAsync(partE.data(), G.part_E, G.k * 4, hipMemcpyDeviceToHost, st), "read E^p");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    {
+        uint64_t t = 0;
+        for (uint32_t p = 0; p < G.k; ++p) {
+            bld[p] = (uint32_t)t;
+            t += ((uint64_t)partE[p] + (1ull << G.sc_shift) - 1) >> G.sc_shift;
+        }
+        bld[G.k] = (uint32_t)t;
+        G.n_bldtask = (uint32_t)t;
+    }
+    HIP_OR_RETURN(hipMemcpyAsync(G.bld_t0, bld.data(), (G.k + 1) * 4, hipMemcpyHostToDevice, st),
+                  "write build tasks");
     HIP_OR_RETURN(launch_sc_build(G, 0, st), "count bins");
     HIP_OR_RETURN(launch_scan_excl(G.cnt_m, G.bin_moff, kk, G.scan_tmp, st), "scan messages");
     HIP_OR_RETURN(launch_scan_excl(G.cnt_i, G.bin_ioff, kk, G.scan_tmp, st), "scan ids");
@@ -255,10 +314,13 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     HIP_OR_RETURN(launch_colmajor(G, st), "column table");
     HIP_OR_RETURN(launch_sc_build(G, 1, st), "fill PNG");
 
-    std::vector<uint32_t> partM(G.k), cnti(kk);
+    std::vector<uint32_t> partM(G.k), cnti(kk), ioff(kk + 1);
     HIP_OR_RETURN(hipMemcpyAsync(partM.data(), G.part_M, G.k * 4, hipMemcpyDeviceToHost, st), "read M");
     HIP_OR_RETURN(hipMemcpyAsync(cnti.data(), G.cnt_i, kk * 4, hipMemcpyDeviceToHost, st), "read counts");
+    HIP_OR_RETURN(hipMemcpyAsync(ioff.data(), G.bin_ioff, (kk + 1) * 4, hipMemcpyDeviceToHost, st),
+                  "read offsets");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    // partition-centric scatter tasks: slices of each partition's message range
     std::vector<uint4> tasks;
     uint64_t slot = 0;
     for (uint32_t p = 0; p < G.k; ++p) {
@@ -277,7 +339,56 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     if (!tasks.empty())
         HIP_OR_RETURN(hipMemcpyAsync(G.pctask, tasks.data(), tasks.size() * sizeof(uint4),
                                      hipMemcpyHostToDevice, st), "write task table");
+    // gather tasks: each destination partition's static 256-id pieces, in
+    // source-partition order, cut into ranges of about gather_task_ids ids
+    const uint64_t T = z.T;
+    const uint64_t max_gt = max_gtask_for(G.E, z);
+    std::vector<uint4> gt, gs;
+    std::vector<uint64_t> sp(G.k);
+    uint32_t nslot = 0;
+    for (uint32_t q = 0; q < G.k; ++q) {
+        uint64_t tot = 0;
+        for (uint32_t p = 0; p < G.k; ++p) {
+            const uint64_t r = (uint64_t)p * G.k + q;
+            const uint64_t c = cnti[r], o = ioff[r];
+            sp[p] = c ? (o + c - 1) / kChunk - o / kChunk + 1 : 0;
+            tot += sp[p];
+        }
+        uint64_t nt = (tot * kChunk + T - 1) / T;
+        nt = std::max<uint64_t>(1, std::min<uint64_t>(nt, 64));
+        const uint32_t first_task = (uint32_t)(gt.size() / 2);
+        uint32_t p = 0;
+        uint64_t before = 0;  // static pieces of bins p' < p
+        for (uint64_t j = 0; j < nt; ++j) {
+            const uint64_t a = tot * j / nt, b = tot * (j + 1) / nt;
+            while (p + 1 < G.k && before + sp[p] <= a) before += sp[p++];
+            uint32_t plo = nt == 1 ? 0 : p;
+            uint64_t blo = nt == 1 ? 0 : before;
+            uint32_t phi = plo;
+            uint64_t acc = blo;
+            if (nt == 1) phi = G.k - 1;
+            else {
+                while (phi + 1 < G.k && acc + sp[phi] < b) acc += sp[phi++];
+            }
+            const uint32_t s0 = (uint32_t)(a - blo), s1 = (uint32_t)(b - blo);
+            const uint32_t sl = nt > 1 ? nslot++ : 0u;
+            gt.push_back(make_uint4(q, plo, phi, (uint32_t)(nt << 16) | (uint32_t)j));
+            gt.push_back(make_uint4(s0, s1, sl, 0));
+        }
+        if (nt > 1) gs.push_back(make_uint4(q, first_task, (uint32_t)nt, nslot - (uint32_t)nt));
+    }
+    if (gt.size() / 2 > max_gt) return fail(GPOP_EDEVICE, "internal: gather task bound exceeded");
+    G.n_gtask = (uint32_t)(gt.size() / 2);
+    G.n_gsplit = (uint32_t)gs.size();
+    HIP_OR_RETURN(hipMemcpyAsync(G.gtask, gt.data(), gt.size() * sizeof(uint4), hipMemcpyHostToDevice, st),
+                  "write gather tasks");
+    if (!gs.empty())
+        HIP_OR_RETURN(hipMemcpyAsync(G.gsplit, gs.data(), gs.size() * sizeof(uint4), hipMemcpyHostToDevice,
+                                     st), "write split list");
+    Ctrl hc2;
+    HIP_OR_RETURN(hipMemcpyAsync(&hc2, G.ctrl, sizeof hc2, hipMemcpyDeviceToHost, st), "read control");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    if (hc2.bug) return fail(GPOP_EDEVICE, "internal error while building the partition layout");
 
     gpop_graph* g = new (std::nothrow) gpop_graph();
     if (!g) return fail(GPOP_ENOMEM, "host allocation failed");
@@ -401,6 +512,9 @@ int gpop_gather(gpop_graph* g, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     int rc = timed(g, GPOP_KERNEL_GATHER, st,
                    [&] { return launch_gather(g->G, g->P, g->prog, g->state, g->it, st); }, "gather");
+    if (rc) return rc;
+    rc = timed(g, GPOP_KERNEL_MERGE, st,
+               [&] { return launch_merge(g->G, g->P, g->prog, g->state, g->it, st); }, "merge");
     if (rc) return rc;
     g->it += 1;
     return GPOP_OK;

@@ -9,7 +9,7 @@ constexpr uint32_t kGW = kGT / 64;
 
 // LDS layout of the gather workgroup (bytes, all offsets 16-aligned).
 struct GatherLds {
-    size_t state, flag_a, flag_b, tag, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_scan, total;
+    size_t state, flag_a, flag_b, tag, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
 };
 
 __host__ __device__ inline GatherLds gather_layout(bool sum, uint32_t q) {
@@ -23,6 +23,7 @@ __host__ __device__ inline GatherLds gather_layout(bool sum, uint32_t q) {
     L.bl_icnt = o; o += kGT * 4;
     L.bl_moff = o; o += kGT * 4;
     L.bl_mcnt = o; o += kGT * 4;
+    L.bl_jlo = o;  o += kGT * 4;
     L.bl_scan = o; o += (kGT + 4) * 4;
     L.total = o;
     return L;
@@ -36,38 +37,178 @@ __device__ __forceinline__ uint32_t wave_excl_small(uint32_t c) {
     return popc_lt(ballot(c & 1u)) + 2u * popc_lt(ballot(c & 2u)) + 4u * popc_lt(ballot(c & 4u));
 }
 
-// One workgroup per destination partition cq. The partition's vertex state
-// lives in LDS for the whole phase (the cached vertex data of Sec. 3: each
-// message updates on-chip state, each bin is read once, sequentially).
+__device__ __forceinline__ uint32_t pieces_of(uint32_t ioff, uint32_t icnt) {
+    return icnt ? (ioff + icnt - 1u) / kChunk - ioff / kChunk + 1u : 0u;
+}
+
+struct GatherShared {
+    uint32_t wc[kGW], wp[kGW], ws[kGW];
+    uint64_t r64[3][kGW];
+    double rd[kGW];
+};
+
+// reInit frontier: initFunc on the vertices that were active before scatter.
+template <int PROG>
+__device__ void reinit(const Dev& G, const Params& P, uint32_t it, uint32_t cq, const uint32_t* st32,
+                       uint8_t* carry) {
+    const uint32_t cur = it & 1u;
+    const uint32_t vbase = cq << G.s;
+    const uint32_t prevVa = G.fVa[cur][cq];
+    const uint16_t* __restrict__ prev = G.flist[cur] + vbase;
+    for (uint32_t i = threadIdx.x; i < prevVa; i += kGT) {
+        const uint32_t u = prev[i];
+        if constexpr (PROG == P_CARRY) {
+            carry[u] = (it + 1u - st32[u]) < P.persist;
+        } else if constexpr (is_sum(PROG)) {
+            carry[u] = 1;  // PageRank family: value restarts at 0, vertex stays active
+        }
+    }
+}
+
+// filterFunc on carried and newly activated vertices, state write-back, and
+// ballot compaction of the next frontier (list, bitmap, active-edge prefix,
+// V_a, E_a, dangling partial sum). For the min programs a vertex is newly
+// activated when its value decreased (hit); for the sum programs when it
+// received a non-zero amount.
+template <int PROG>
+__device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __restrict__ state,
+                                 uint32_t it, uint32_t cq, const uint32_t* st32,
+                                 const unsigned long long* acc, const uint8_t* hit,
+                                 const uint8_t* carry, GatherShared& sh, uint32_t ids_done,
+                                 uint32_t task) {
+    constexpr bool SUM = is_sum(PROG);
+    const uint32_t nxt = (it & 1u) ^ 1u;
+    const uint32_t vbase = cq << G.s, Q = G.q;
+    const uint32_t nv = min(Q, G.V - vbase);
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    const double dang = SUM ? G.ctrl->dangling : 0.0;
+    uint32_t running = 0, erun = 0;
+    double my_d = 0.0;
+    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
+    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
+    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
+    for (uint32_t u0 = 0; u0 < nv; u0 += kGT) {
+        const uint32_t u = u0 + tid;
+        const bool in = u < nv;
+        bool keep = false;
+        uint32_t deg = 0;
+        if (in) {
+            const uint32_t v = vbase + u;
+            deg = G.off[v + 1] - G.off[v];
+            if constexpr (!SUM) {
+                keep = hit[u] || carry[u];  // filterFunc returns true for the min programs
+                if (hit[u]) state[v] = st32[u];
+            } else {
+                const bool prelim = acc[u] != 0ull || carry[u];
+                if (prelim) {
+                    const double y = (double)acc[u] * kInvFix;
+                    float x;
+                    if constexpr (PROG == P_PR) {
+                        const double d = (double)P.damping;
+                        x = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
+                        keep = true;
+                    } else {
+                        const double a = (double)P.alpha;
+                        double xd = (1.0 - a) * y;
+                        if (v == P.root) xd += a + (1.0 - a) * dang;
+                        x = (float)xd;
+                        keep = x > 0.0f;
+                    }
+                    state[v] = __float_as_uint(x);
+                    if (deg == 0) my_d += (double)x;
+                }
+            }
+        }
+        const uint64_t bm = ballot(keep);
+        const uint32_t kdeg = keep ? deg : 0u;
+        const uint32_t dincl = wave_incl_scan(kdeg);
+        if (lane == 0 && u0 + wave * 64u < Q) {
+            const uint32_t wi = (u0 + wave * 64u) >> 5;
+            nbits[wi] = (uint32_t)bm;
+            nbits[wi + 1] = (uint32_t)(bm >> 32);
+        }
+        if (lane == 63) {
+            sh.wc[wave] = popc64(bm);
+            sh.ws[wave] = dincl;
+        }
+        __syncthreads();
+        uint32_t before = 0, tot = 0, ebefore = 0, etot = 0;
+        for (uint32_t w = 0; w < kGW; ++w) {
+            if (w < wave) {
+                before += sh.wc[w];
+                ebefore += sh.ws[w];
+            }
+            tot += sh.wc[w];
+            etot += sh.ws[w];
+        }
+        if (keep) {
+            const uint32_t pos = running + before + popc_lt(bm);
+            nlist[pos] = (uint16_t)u;
+            npre[pos] = erun + ebefore + dincl - kdeg;
+        }
+        running += tot;
+        erun += etot;
+        __syncthreads();
+    }
+    my_d = wave_sum_f64(my_d);
+    const uint64_t ids64 = wave_sum_u64((uint64_t)ids_done);
+    if (lane == 0) {
+        sh.r64[1][wave] = ids64;
+        sh.rd[wave] = my_d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t ni = 0;
+        double d = 0.0;
+        for (uint32_t w = 0; w < kGW; ++w) {
+            ni += sh.r64[1][w];
+            d += sh.rd[w];
+        }
+        G.fVa[nxt][cq] = running;
+        G.fEa[nxt][cq] = erun;
+        G.dpart[nxt][cq] = d;
+        if (task != 0xFFFFFFFFu) G.gat_ids[task] = (uint32_t)ni;
+    }
+}
+
+// Gather task: a contiguous range [s0, s1) of the static 256-id pieces of the
+// bins bin[p][cq], p in [p_lo, p_hi], taken in p order. The destination
+// partition's state lives in LDS (the cached vertex data of Sec. 3): every
+// message updates on-chip state, every bin piece is read once, sequentially.
+// Partitions whose bins hold few ids get one task that also runs reInit and
+// the filter; heavy partitions (RMAT hubs) get several tasks that each leave
+// a partial result for k_merge.
 //
-// Bins bin[p][cq] are enumerated from the per-partition modes and counts (the
-// two-level active list: a partition is gathered only if some bin of its
-// column is non-empty or it has active vertices; inside it only non-empty
-// bins are read). Each bin is cut into 256-id-aligned pieces that one wave
-// decodes on its own: message index of an id = chunk-table base + number of
-// message-start flags after the piece start.
+// Bins are enumerated from the per-partition modes and counts (the two-level
+// active list: only non-empty bins of the scattered partitions are read).
+// Each piece is decoded by one wave: message index of an id = chunk-table
+// base + number of message-start flags after the piece start.
 //
-// Combining is atomic-free. For min programs each round every pending lane
-// reads the state word and writes its value if smaller; after a barrier each
-// lane re-reads, and only lanes whose value is still smaller stay pending.
-// Every round lowers each contested word strictly, so the loop ends with the
-// exact minimum whatever the write order. For sum programs a round lets every
-// pending lane write its slot number into a per-vertex tag; after a barrier
-// the lane that finds its own number adds its value (one writer per word),
-// the rest retry. Sums are accumulated as 64-bit integers in units of 2^-60,
-// so the result is exact and independent of the order of additions.
+// Combining is atomic-free. Min programs: every pending lane reads the state
+// word and writes its value if smaller; after a barrier each lane re-reads,
+// and only lanes whose value is still smaller stay pending. Each round lowers
+// every contested word strictly, so the loop ends with the exact minimum
+// whatever the write order. Sum programs: every pending lane writes its slot
+// number into a per-vertex tag; after a barrier the lane that finds its own
+// number adds its value (one writer per word) and the rest retry. Sums are
+// 64-bit integers in units of 2^-60, so the result is exact and independent
+// of the order of additions.
 template <int PROG>
 __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __restrict__ state,
                                                 uint32_t it) {
     if (G.ctrl->done) return;
     constexpr bool SUM = is_sum(PROG);
     constexpr uint32_t IDENT = is_sum(PROG) ? kIdentSum : kIdentMin;
-    const uint32_t cq = blockIdx.x, cur = it & 1u, nxt = cur ^ 1u;
-    const uint32_t k = G.k, s = G.s, Q = G.q;
-    const uint32_t vbase = cq << s;
+    const uint32_t task = blockIdx.x;
+    const uint4 TA = G.gtask[2 * task], TB = G.gtask[2 * task + 1];
+    const uint32_t cq = TA.x, p_lo = TA.y, p_hi = TA.z, nt = TA.w >> 16;
+    const uint32_t s0 = TB.x, s1 = TB.y, slot = TB.z;
+    const bool split = nt > 1;
+    const uint32_t cur = it & 1u, nxt = cur ^ 1u;
+    const uint32_t k = G.k, Q = G.q;
+    const uint32_t vbase = cq << G.s;
     const uint32_t nv = min(Q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    const uint32_t prevVa = G.fVa[cur][cq];
     const uint4* __restrict__ cmcol = G.cm + (size_t)cq * k;
     const uint2* __restrict__ sccol = G.sc_cnt + (size_t)cq * k;
 
@@ -76,21 +217,19 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
     uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
     uint16_t* tag = reinterpret_cast<uint16_t*>(smem + L.tag);
-    uint8_t* hit = smem + L.flag_a;     // improved (min) / received (sum)
+    uint8_t* hit = smem + L.flag_a;     // min programs: value decreased
     uint8_t* carry = smem + L.flag_b;   // kept active by initFunc
     uint32_t* bl_ioff = reinterpret_cast<uint32_t*>(smem + L.bl_ioff);
     uint32_t* bl_icnt = reinterpret_cast<uint32_t*>(smem + L.bl_icnt);
     uint32_t* bl_moff = reinterpret_cast<uint32_t*>(smem + L.bl_moff);  // bit 31: SC bin
     uint32_t* bl_mcnt = reinterpret_cast<uint32_t*>(smem + L.bl_mcnt);
+    uint32_t* bl_jlo = reinterpret_cast<uint32_t*>(smem + L.bl_jlo);
     uint32_t* bl_scan = reinterpret_cast<uint32_t*>(smem + L.bl_scan);
-    __shared__ uint32_t s_wc[kGW];
-    __shared__ uint32_t s_wp[kGW];
-    __shared__ uint64_t s_r64[3][kGW];
-    __shared__ double s_rd[kGW];
+    __shared__ GatherShared sh;
 
-    // ---- is there anything to do for this partition?
-    int any = prevVa > 0;
-    for (uint32_t p = tid; p < k && !any; p += kGT) {
+    // ---- anything to do for this task?
+    int any = (!split && G.fVa[cur][cq] > 0) ? 1 : 0;
+    for (uint32_t p = p_lo + tid; p <= p_hi && !any; p += kGT) {
         const uint32_t md = G.mode[p];
         const uint32_t ic = md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
         any |= ic > 0;
@@ -98,67 +237,83 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
     any = __syncthreads_or(any);
     if (!any) {
         if (tid == 0) {
-            G.fVa[nxt][cq] = 0;
-            G.fEa[nxt][cq] = 0;
-            G.dpart[nxt][cq] = 0.0;
-            G.gat_ids[cq] = 0;
+            if (split) {
+                G.gflag[slot] = 0;
+            } else {
+                G.fVa[nxt][cq] = 0;
+                G.fEa[nxt][cq] = 0;
+                G.dpart[nxt][cq] = 0.0;
+            }
+            G.gat_ids[task] = 0;
+            G.gat_ran[task] = 0;
         }
         return;
     }
+    if (tid == 0) G.gat_ran[task] = split ? 2u : 1u;
 
-    // ---- load the partition's state into LDS
+    // ---- state into LDS: the partition's values (single task) or the
+    //      combine identity (partial of a split task)
     for (uint32_t u = tid; u < Q; u += kGT) {
         if constexpr (SUM) acc[u] = 0ull;
-        else st32[u] = u < nv ? state[vbase + u] : 0xFFFFFFFFu;
+        else st32[u] = (!split && u < nv) ? state[vbase + u] : 0xFFFFFFFFu;
         hit[u] = 0;
         carry[u] = 0;
     }
     __syncthreads();
-
-    // ---- reInit frontier: initFunc on the vertices active before scatter
-    const uint16_t* __restrict__ prev = G.flist[cur] + vbase;
-    for (uint32_t i = tid; i < prevVa; i += kGT) {
-        const uint32_t u = prev[i];
-        if constexpr (PROG == P_CARRY) {
-            carry[u] = (it + 1u - st32[u]) < P.persist;
-        } else if constexpr (SUM) {
-            carry[u] = 1;  // PageRank family: value restarts at 0, vertex stays active
-        }
+    if (!split) {
+        reinit<PROG>(G, P, it, cq, st32, carry);
+        __syncthreads();
     }
-    __syncthreads();
 
-    // ---- gather all non-empty bins bin[p][cq]
+    // ---- gather the task's pieces
     uint32_t my_ids = 0;
-    for (uint32_t p0 = 0; p0 < k; p0 += kGT) {
+    uint32_t sp_run = 0;  // static pieces of the bins before the current window
+    for (uint32_t p0 = p_lo; p0 <= p_hi; p0 += kGT) {
         const uint32_t p = p0 + tid;
-        uint32_t md = p < k ? G.mode[p] : GPOP_MODE_NONE;
-        uint32_t ioff = 0, icnt = 0, moff = 0, mcnt = 0;
-        if (md != GPOP_MODE_NONE) {
+        const bool inr = p <= p_hi;
+        const uint32_t md = inr ? G.mode[p] : GPOP_MODE_NONE;
+        uint32_t sp = 0, ioff = 0, icnt = 0, moff = 0, mcnt = 0;
+        if (inr) {
             const uint4 c = cmcol[p];
+            sp = pieces_of(c.y, c.w);
             ioff = c.y;
             moff = c.x;
             if (md == GPOP_MODE_PC) {
                 icnt = c.w;
                 mcnt = c.z;
-            } else {
+            } else if (md == GPOP_MODE_SC) {
                 const uint2 d = sccol[p];
                 icnt = d.y;
                 mcnt = d.x;
             }
         }
-        const bool nz = icnt > 0;
-        const uint32_t npieces = nz ? (ioff + icnt - 1u) / kChunk - ioff / kChunk + 1u : 0u;
-        // compact non-empty bins in p order and scan their piece counts
+        const uint32_t dp = pieces_of(ioff, icnt);
+        // static piece prefix of this bin inside the task's enumeration
+        const uint32_t sincl = wave_incl_scan(sp);
+        if (lane == 63) sh.ws[wave] = sincl;
+        __syncthreads();
+        uint32_t sbefore = 0, stot = 0;
+        for (uint32_t w = 0; w < kGW; ++w) {
+            if (w < wave) sbefore += sh.ws[w];
+            stot += sh.ws[w];
+        }
+        const uint32_t SP = sp_run + sbefore + sincl - sp;
+        sp_run += stot;
+        // pieces of this bin that fall in [s0, s1)
+        const uint32_t jlo = s0 > SP ? s0 - SP : 0u;
+        const uint32_t jhi = min(dp, s1 > SP ? s1 - SP : 0u);
+        const uint32_t npieces = jhi > jlo ? jhi - jlo : 0u;
+        const bool nz = npieces > 0;
         const uint64_t bm = ballot(nz);
         const uint32_t pincl = wave_incl_scan(npieces);
         if (lane == 63) {
-            s_wc[wave] = popc64(bm);
-            s_wp[wave] = pincl;
+            sh.wc[wave] = popc64(bm);
+            sh.wp[wave] = pincl;
         }
         __syncthreads();
         uint32_t boff = 0, poff = 0, nb = 0, npt = 0;
         for (uint32_t w = 0; w < kGW; ++w) {
-            const uint32_t c = s_wc[w], pc = s_wp[w];
+            const uint32_t c = sh.wc[w], pc = sh.wp[w];
             if (w < wave) {
                 boff += c;
                 poff += pc;
@@ -172,6 +327,7 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
             bl_icnt[b] = icnt;
             bl_moff[b] = moff | (md == GPOP_MODE_SC ? 0x80000000u : 0u);
             bl_mcnt[b] = mcnt;
+            bl_jlo[b] = jlo;
             bl_scan[b] = poff + pincl - npieces;
         }
         __syncthreads();
@@ -193,7 +349,7 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
                 const uint32_t bmcnt = bl_mcnt[b];
                 const bool sc = bmo & 0x80000000u;
                 const uint32_t bmoff = bmo & 0x7FFFFFFFu;
-                const uint32_t c = bioff / kChunk + (pid - bl_scan[b]);
+                const uint32_t c = bioff / kChunk + bl_jlo[b] + (pid - bl_scan[b]);
                 const uint32_t lo_x = max(bioff, c * kChunk);
                 const uint32_t hi_x = min(bioff + bicnt, c * kChunk + kChunk);
                 const uint16_t* __restrict__ ids = sc ? G.sc_ids : G.png_ids;
@@ -269,7 +425,6 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
                     for (int j = 0; j < 4; ++j) {
                         if (((pend >> j) & 1u) && tag[dst[j]] == (uint16_t)(tid * 4u + j)) {
                             acc[dst[j]] += fx[j];
-                            hit[dst[j]] = 1;
                             pend &= ~(1u << j);
                         }
                     }
@@ -280,90 +435,96 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
         __syncthreads();
     }
 
-    // ---- filter frontier, write state back, compact the next frontier
-    const double dang = SUM ? G.ctrl->dangling : 0.0;
-    uint32_t running = 0;
-    uint64_t my_ea = 0;
-    double my_d = 0.0;
-    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
-    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
-    for (uint32_t u0 = 0; u0 < nv; u0 += kGT) {
-        const uint32_t u = u0 + tid;
-        const bool in = u < nv;
-        bool keep = false;
-        uint32_t deg = 0;
-        if (in) {
-            const uint32_t v = vbase + u;
-            deg = G.off[v + 1] - G.off[v];
-            const bool prelim = hit[u] || carry[u];
-            if constexpr (!SUM) {
-                keep = prelim;  // filterFunc returns true for the min programs
-                if (hit[u]) state[v] = st32[u];
-            } else if constexpr (PROG == P_PR) {
-                if (prelim) {
-                    const double y = (double)acc[u] * kInvFix;
-                    const double d = (double)P.damping;
-                    const float x = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
-                    state[v] = __float_as_uint(x);
-                    keep = true;
-                    if (deg == 0) my_d += (double)x;
-                }
-            } else {  // P_PPR
-                if (prelim) {
-                    const double y = (double)acc[u] * kInvFix;
-                    const double a = (double)P.alpha;
-                    double xd = (1.0 - a) * y;
-                    if (v == P.root) xd += a + (1.0 - a) * dang;
-                    const float x = (float)xd;
-                    state[v] = __float_as_uint(x);
-                    keep = x > 0.0f;
-                    if (deg == 0) my_d += (double)x;
-                }
-            }
+    if (split) {
+        // partial result of this task for the merge
+        if constexpr (SUM) {
+            unsigned long long* out = reinterpret_cast<unsigned long long*>(G.gpart) + (size_t)slot * Q;
+            for (uint32_t u = tid; u < nv; u += kGT) out[u] = acc[u];
+        } else {
+            uint32_t* out = G.gpart + (size_t)slot * 2 * Q;
+            for (uint32_t u = tid; u < nv; u += kGT) out[u] = st32[u];
         }
-        const uint64_t bm = ballot(keep);
-        if (lane == 0 && u0 + wave * 64u < Q) {
-            const uint32_t wi = (u0 + wave * 64u) >> 5;
-            nbits[wi] = (uint32_t)bm;
-            nbits[wi + 1] = (uint32_t)(bm >> 32);
-        }
-        if (lane == 0) s_wc[wave] = popc64(bm);
+        const uint64_t ids64 = wave_sum_u64((uint64_t)my_ids);
+        if (lane == 0) sh.r64[1][wave] = ids64;
         __syncthreads();
-        uint32_t before = 0, tot = 0;
-        for (uint32_t w = 0; w < kGW; ++w) {
-            if (w < wave) before += s_wc[w];
-            tot += s_wc[w];
+        if (tid == 0) {
+            uint64_t ni = 0;
+            for (uint32_t w = 0; w < kGW; ++w) ni += sh.r64[1][w];
+            G.gflag[slot] = 1;
+            G.gat_ids[task] = (uint32_t)ni;
         }
-        if (keep) {
-            nlist[running + before + popc_lt(bm)] = (uint16_t)u;
-            my_ea += deg;
-        }
-        running += tot;
-        __syncthreads();
+        return;
     }
-    // deterministic reductions: per-thread partials, butterfly per wave, waves in order
-    my_ea = wave_sum_u64(my_ea);
-    uint64_t ids64 = wave_sum_u64((uint64_t)my_ids);
-    my_d = wave_sum_f64(my_d);
-    if (lane == 0) {
-        s_r64[0][wave] = my_ea;
-        s_r64[1][wave] = ids64;
-        s_rd[wave] = my_d;
+    finish_partition<PROG>(G, P, state, it, cq, st32, acc, hit, carry, sh, my_ids, task);
+}
+
+// Merge of a partition whose gather was split over several tasks: combines
+// the partial results (min, or exact fixed-point sum) with the state, then
+// runs reInit and the filter like a single-task gather.
+template <int PROG>
+__global__ __launch_bounds__(kGT) void k_merge(Dev G, Params P, uint32_t* __restrict__ state,
+                                               uint32_t it) {
+    if (G.ctrl->done) return;
+    constexpr bool SUM = is_sum(PROG);
+    const uint4 S = G.gsplit[blockIdx.x];
+    const uint32_t cq = S.x, nt = S.z, slot0 = S.w;
+    const uint32_t Q = G.q;
+    const uint32_t vbase = cq << G.s;
+    const uint32_t nv = min(Q, G.V - vbase);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const GatherLds L = gather_layout(SUM, Q);
+    uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
+    uint8_t* hit = smem + L.flag_a;
+    uint8_t* carry = smem + L.flag_b;
+    __shared__ GatherShared sh;
+    __shared__ uint32_t s_flag[64];
+    for (uint32_t j = threadIdx.x; j < 64; j += kGT) s_flag[j] = j < nt ? G.gflag[slot0 + j] : 0u;
+    __syncthreads();
+    {
+        const uint32_t cur = it & 1u, nxt = cur ^ 1u;
+        int any = threadIdx.x < 64 && s_flag[threadIdx.x];
+        any = __syncthreads_or(any || G.fVa[cur][cq] > 0);
+        if (!any) {
+            if (threadIdx.x == 0) {
+                G.fVa[nxt][cq] = 0;
+                G.fEa[nxt][cq] = 0;
+                G.dpart[nxt][cq] = 0.0;
+                G.gat_ran[G.n_gtask + blockIdx.x] = 0;
+            }
+            return;
+        }
+        if (threadIdx.x == 0) G.gat_ran[G.n_gtask + blockIdx.x] = 3;
+    }
+    for (uint32_t u = threadIdx.x; u < Q; u += kGT) {
+        carry[u] = 0;
+        hit[u] = 0;
+        if constexpr (SUM) acc[u] = 0ull;
+        else st32[u] = u < nv ? state[vbase + u] : 0xFFFFFFFFu;
     }
     __syncthreads();
-    if (tid == 0) {
-        uint64_t ea = 0, ni = 0;
-        double d = 0.0;
-        for (uint32_t w = 0; w < kGW; ++w) {
-            ea += s_r64[0][w];
-            ni += s_r64[1][w];
-            d += s_rd[w];
+    uint64_t written = 0;  // partials that were written (at most 64 tasks per partition)
+    for (uint32_t j = 0; j < nt; ++j) written |= (s_flag[j] ? 1ull : 0ull) << j;
+    reinit<PROG>(G, P, it, cq, st32, carry);  // initFunc sees the values from before gather
+    __syncthreads();
+    for (uint32_t u = threadIdx.x; u < nv; u += kGT) {
+        if constexpr (SUM) {
+            unsigned long long a = 0;
+            const unsigned long long* part = reinterpret_cast<const unsigned long long*>(G.gpart);
+            for (uint32_t j = 0; j < nt; ++j)
+                if ((written >> j) & 1u) a += part[(size_t)(slot0 + j) * Q + u];
+            acc[u] = a;
+        } else {
+            const uint32_t orig = st32[u];
+            uint32_t m = orig;
+            for (uint32_t j = 0; j < nt; ++j)
+                if ((written >> j) & 1u) m = min(m, G.gpart[(size_t)(slot0 + j) * 2 * Q + u]);
+            st32[u] = m;
+            hit[u] = m < orig;
         }
-        G.fVa[nxt][cq] = running;
-        G.fEa[nxt][cq] = (uint32_t)ea;
-        G.dpart[nxt][cq] = d;
-        G.gat_ids[cq] = (uint32_t)ni;
     }
+    __syncthreads();
+    finish_partition<PROG>(G, P, state, it, cq, st32, acc, hit, carry, sh, 0, 0xFFFFFFFFu);
 }
 
 template <int PROG>
@@ -374,21 +535,42 @@ static hipError_t launch_gather_p(const Dev& G, const Params& P, uint32_t* state
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(G.k), dim3(kGT), lds, st, G, P, state, it);
+    hipLaunchKernelGGL(fn, dim3(G.n_gtask), dim3(kGT), lds, st, G, P, state, it);
     return hipGetLastError();
 }
 
+template <int PROG>
+static hipError_t launch_merge_p(const Dev& G, const Params& P, uint32_t* state, uint32_t it,
+                                 hipStream_t st) {
+    if (G.n_gsplit == 0) return hipSuccess;
+    const size_t lds = gather_lds_bytes(PROG, G.q);
+    auto fn = k_merge<PROG>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(G.n_gsplit), dim3(kGT), lds, st, G, P, state, it);
+    return hipGetLastError();
+}
+
+#define GPOP_DISPATCH(fn)                                             \
+    switch (prog) {                                                   \
+        case P_BFS: return fn<P_BFS>(G, P, state, it, st);           \
+        case P_CC: return fn<P_CC>(G, P, state, it, st);             \
+        case P_SSSP: return fn<P_SSSP>(G, P, state, it, st);         \
+        case P_PR: return fn<P_PR>(G, P, state, it, st);             \
+        case P_PPR: return fn<P_PPR>(G, P, state, it, st);           \
+        case P_CARRY: return fn<P_CARRY>(G, P, state, it, st);       \
+    }                                                                 \
+    return hipErrorInvalidValue;
+
 hipError_t launch_gather(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
                          hipStream_t st) {
-    switch (prog) {
-        case P_BFS: return launch_gather_p<P_BFS>(G, P, state, it, st);
-        case P_CC: return launch_gather_p<P_CC>(G, P, state, it, st);
-        case P_SSSP: return launch_gather_p<P_SSSP>(G, P, state, it, st);
-        case P_PR: return launch_gather_p<P_PR>(G, P, state, it, st);
-        case P_PPR: return launch_gather_p<P_PPR>(G, P, state, it, st);
-        case P_CARRY: return launch_gather_p<P_CARRY>(G, P, state, it, st);
-    }
-    return hipErrorInvalidValue;
+    GPOP_DISPATCH(launch_gather_p)
+}
+
+hipError_t launch_merge(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
+                        hipStream_t st) {
+    GPOP_DISPATCH(launch_merge_p)
 }
 
 // ---------------------------------------------------------------------------
@@ -425,7 +607,6 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
         G.fEa[0][p] = 0;
         G.fVa[1][p] = 0;
         G.fEa[1][p] = 0;
-        G.gat_ids[p] = 0;
         G.mode[p] = GPOP_MODE_NONE;
     }
     if (p == 0 && threadIdx.x == 0) {
@@ -466,43 +647,48 @@ __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all, uint
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    __shared__ uint32_t s_wc[16];
-    __shared__ uint64_t s_e[16];
+    __shared__ uint32_t s_wc[16], s_ws[16];
     uint16_t* list = G.flist[buf] + vbase;
+    uint32_t* pre = G.fpre[buf] + vbase;
     uint32_t* bits = G.fbits[buf] + (vbase >> 5);
-    uint32_t running = 0;
-    uint64_t my_ea = 0;
+    uint32_t running = 0, erun = 0;
     for (uint32_t u0 = 0; u0 < nv; u0 += 1024) {
         const uint32_t u = u0 + tid;
         const bool keep = u < nv && (all || G.marks[vbase + u]);
+        const uint32_t deg = keep ? G.off[vbase + u + 1] - G.off[vbase + u] : 0u;
         const uint64_t bm = ballot(keep);
+        const uint32_t dincl = wave_incl_scan(deg);
         if (lane == 0 && u0 + wave * 64u < G.q) {
             const uint32_t wi = (u0 + wave * 64u) >> 5;
             bits[wi] = (uint32_t)bm;
             bits[wi + 1] = (uint32_t)(bm >> 32);
         }
-        if (lane == 0) s_wc[wave] = popc64(bm);
+        if (lane == 63) {
+            s_wc[wave] = popc64(bm);
+            s_ws[wave] = dincl;
+        }
         __syncthreads();
-        uint32_t before = 0, tot = 0;
+        uint32_t before = 0, tot = 0, eb = 0, et = 0;
         for (uint32_t w = 0; w < 16; ++w) {
-            if (w < wave) before += s_wc[w];
+            if (w < wave) {
+                before += s_wc[w];
+                eb += s_ws[w];
+            }
             tot += s_wc[w];
+            et += s_ws[w];
         }
         if (keep) {
-            list[running + before + popc_lt(bm)] = (uint16_t)u;
-            my_ea += G.off[vbase + u + 1] - G.off[vbase + u];
+            const uint32_t pos = running + before + popc_lt(bm);
+            list[pos] = (uint16_t)u;
+            pre[pos] = erun + eb + dincl - deg;
         }
         running += tot;
+        erun += et;
         __syncthreads();
     }
-    my_ea = wave_sum_u64(my_ea);
-    if (lane == 0) s_e[wave] = my_ea;
-    __syncthreads();
     if (tid == 0) {
-        uint64_t e = 0;
-        for (int w = 0; w < 16; ++w) e += s_e[w];
         G.fVa[buf][p] = running;
-        G.fEa[buf][p] = (uint32_t)e;
+        G.fEa[buf][p] = erun;
     }
     if (p == 0 && tid == 0) {
         G.ctrl->done = 0;

@@ -47,16 +47,22 @@ struct Ctrl {
     uint32_t err;         // bad vertex id passed to set_frontier
     uint32_t csr_err;     // CSR validation failure code
     uint32_t bug;         // a kernel found an inconsistent bin (internal error)
+    uint32_t n_sctask;    // source-centric tasks of the current iteration
     uint64_t frontier;    // sum of V_a at the last plan
     double dangling;      // PageRank-family dangling mass of the current frontier
-    uint32_t pad[55];
+    uint32_t pad[54];
 };
 
 // Everything the kernels read or write, by value in each launch.
 struct Dev {
     uint32_t V, k, s, q;      // vertices, partitions, log2 q, q
     uint32_t nbits;           // bits needed for a partition id
-    uint32_t n_pctask;
+    uint32_t n_pctask;        // partition-centric scatter tasks (static)
+    uint32_t sc_shift;        // log2 of the active edges per source-centric task
+    uint32_t max_sctask;      // bound on source-centric tasks per iteration
+    uint32_t n_bldtask;       // tasks of the preprocessing build
+    uint32_t n_gtask;         // gather tasks (static)
+    uint32_t n_gsplit;        // partitions whose gather is split over tasks
     uint64_t E;
     const uint32_t* off;
     const uint32_t* cols;
@@ -72,6 +78,11 @@ struct Dev {
     uint8_t* png_w;           // [E_pad] static weights
     uint32_t* png_chunk;      // [E_pad/256]
     uint4* pctask;            // [n_pctask] {p, slot_begin, slot_end, 0}
+    uint32_t* bld_t0;         // [k+1] task prefix of the build (all vertices active)
+    uint4* gtask;             // [2*n_gtask] {q, p_lo, p_hi, nt<<16|j}, {s0, s1, slot, 0}
+    uint4* gsplit;            // [n_gsplit] {q, first task, nt, first slot}
+    uint32_t* gpart;          // partial results of split gathers, q (u32) or 2q (u64) words per slot
+    uint32_t* gflag;          // [slots] a split task wrote its partial
     // per iteration
     uint32_t* data;           // [M] message values
     uint16_t* sc_ids;         // [E_pad]
@@ -79,12 +90,16 @@ struct Dev {
     uint32_t* sc_chunk;       // [E_pad/256]
     uint2* sc_cnt;            // [k*k] column-major {mcnt, icnt} of SC bins
     uint2* sc_tot;            // [k] SC totals {msgs, ids} per partition
-    uint32_t* gat_ids;        // [k] ids gathered per column
+    uint32_t* sc_t0;          // [k+1] exclusive prefix of SC tasks per partition
+    uint2* sc_tc;             // [max_sctask*k] per-(task, q) counts, then bases
+    uint32_t* gat_ids;        // [n_gtask] ids combined per gather task
+    uint32_t* gat_ran;        // [n_gtask + n_gsplit] 1 whole partition, 2 partial, 3 merge, 0 idle
     uint8_t* mode;            // [k]
     uint16_t* flist[2];       // [k*q] frontier lists (local ids, ascending)
     uint32_t* fbits[2];       // [k*q/32] frontier bitmaps
     uint32_t* fVa[2];         // [k]
     uint32_t* fEa[2];         // [k]
+    uint32_t* fpre[2];        // [k*q] active-edge prefix of each frontier entry
     double* dpart[2];         // [k] dangling partial sums
     uint8_t* marks;           // [k*q] set_frontier scratch
     uint32_t* cnt_m;          // [k*k] preprocessing counts, row-major

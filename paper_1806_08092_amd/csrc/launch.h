@@ -15,8 +15,7 @@ hipError_t launch_part_M(const Dev& G, hipStream_t st);
 hipError_t launch_colmajor(const Dev& G, hipStream_t st);
 
 // scatter side (scatter.hip)
-size_t sc_lds_bytes(uint32_t k, int waves);
-int sc_waves_for(uint32_t k);
+size_t sc_lds_bytes(uint32_t k);
 hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st);
 hipError_t launch_plan(const Dev& G, const Params& P, uint32_t it, hipStream_t st);
 hipError_t launch_finalize(const Dev& G, uint32_t it, hipStream_t st);
@@ -27,6 +26,8 @@ hipError_t launch_scatter_pc(const Dev& G, const Params& P, int prog, const uint
 
 // gather side (gather.hip)
 size_t gather_lds_bytes(int prog, uint32_t q);
+hipError_t launch_merge(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
+                        hipStream_t st);
 hipError_t launch_gather(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
                          hipStream_t st);
 hipError_t launch_state_init(const Dev& G, const Params& P, int prog, uint32_t* state,

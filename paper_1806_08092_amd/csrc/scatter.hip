@@ -1,250 +1,330 @@
 // Scatter phase: mode selection, source-centric scatter and partition-centric
 // scatter (Algorithm 2 scatter phase; Algorithm 3; Sec. 3.2).
+#include <algorithm>
+
 #include "launch.h"
 
 namespace gpop {
 
 // ---------------------------------------------------------------------------
-// Ordered multi-split of one partition's edges by destination partition.
-//
 // Source-centric scatter (Algorithm 2, scatter loop): for active v in
 // ascending order, for each neighbouring partition q in ascending order,
-// insert {val[v], ids of v's out-neighbours in q} into bin[p][q]. Successive
-// messages to q land at consecutive insertion points of bin[p][q]
-// (Sec. 3.1.2, source-centric mode). On the GPU the insertion points are
-// exclusive prefix sums: a workgroup of W waves takes the active list in
-// rounds of W*R vertices (wave w owns a contiguous block of R), flattens the
-// edges of 64 vertices at a time across the lanes, groups lanes by
-// destination partition with a ballot match on the partition id bits, counts
-// per (wave, q) in LDS (pass 0), scans the counts across waves (so wave w
-// starts where wave w-1 ends), and writes (pass 1). Only the lowest lane of
-// each match group touches a counter, so no two lanes of a wave update the
-// same word and no atomics are needed; waves own disjoint counter rows.
+// insert {val[v], ids of v's out-neighbours in q} into bin[p][q]; successive
+// messages to q land at consecutive insertion points (Sec. 3.1.2,
+// source-centric mode).
 //
-// The same routine builds the static partition-node layout once with every
-// vertex active: MODE 1 counts messages and ids per (p, q), MODE 2 writes
-// N_i^p(q) (png_src) and the static ids (Algorithm 3 reuses them).
-// MODE 0 is the per-iteration source-centric scatter.
+// GPU form: the active out-edges of partition p, taken in (vertex, edge)
+// order, are cut into tasks of C consecutive edges (a task may start or end
+// inside a vertex's row, so hubs spread over many tasks). One wave owns one
+// task. The insertion points are exclusive prefix sums over that order:
+//   count pass  - each task counts ids and message starts per destination q;
+//   scan pass   - per (p, q), an exclusive scan over the tasks of p gives each
+//                 task its base in bin[p][q] (and the bin's totals);
+//   write pass  - each task replays its edges and writes at base + rank.
+// Inside a task, lanes that hold edges to the same q are grouped with a
+// ballot match on the bits of q; only the lowest lane of a group updates the
+// wave's LDS counter row, so no two lanes touch the same word and no atomics
+// are used. A message is a maximal run of a vertex's edges into one q; its
+// first edge carries the message-start flag and writes the value.
+//
+// The same kernels build the static partition-node layout once, with every
+// vertex active (BUILD): N_i^p(q) (png_src) and the static ids that
+// partition-centric scatter reuses every iteration (Algorithm 3).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kR = 256;  // vertices per wave per round
 
-template <int PROG, int MODE, int W>
-__global__ __launch_bounds__(W * 64) void k_sc(Dev G, Params P, const uint32_t* __restrict__ state,
-                                               uint32_t it) {
-    const uint32_t p = blockIdx.x;
+// Largest p with t0[p] <= t (t0 is a non-decreasing task prefix over k
+// partitions, t < t0[k]); lands on a partition that owns task t.
+__device__ __forceinline__ uint32_t task_owner(const uint32_t* t0, uint32_t k, uint32_t t) {
+    uint32_t lo = 0, hi = k;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (t0[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Processes active-edge range [f0, f1) of partition p with one wave.
+// WRITE = false: adds per-destination counts to (ci, cm).
+// WRITE = true : (ci, cm) hold the task's bases; writes the bins.
+template <int PROG, bool BUILD, bool WRITE>
+__device__ void sc_wave_task(const Dev& G, const uint32_t* __restrict__ state, uint32_t p,
+                             uint32_t f0, uint32_t f1, uint32_t nact,
+                             const uint16_t* __restrict__ alist, const uint32_t* __restrict__ fpre,
+                             uint32_t* ci, uint32_t* cm) {
+    const uint32_t lane = lane_id();
+    const uint32_t k = G.k, s = G.s, qmask = G.q - 1u;
+    const uint32_t vbase = p << s;
+    const uint32_t* __restrict__ off = G.off;
+    const uint32_t* __restrict__ cols = G.cols;
+    const uint32_t* __restrict__ rmoff = G.bin_moff + (size_t)p * k;
+    const uint32_t* __restrict__ rioff = G.bin_ioff + (size_t)p * k;
+    const uint32_t base_off = off[vbase];
+    auto pre = [&](uint32_t i) -> uint32_t {
+        return BUILD ? off[vbase + i] - base_off : fpre[i];
+    };
+    // first active vertex whose edges reach f0
+    uint32_t lo = 0, hi = nact;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre(mid) <= f0) lo = mid; else hi = mid;
+    }
+    for (uint32_t i0 = lo; i0 < nact; i0 += 64) {
+        const uint32_t ii = i0 + lane;
+        const bool vv = ii < nact;
+        const uint32_t vl = vv ? (BUILD ? ii : (uint32_t)alist[ii]) : 0u;
+        const uint32_t v = vbase + vl;
+        const uint32_t rs = vv ? off[v] : 0u;
+        const uint32_t deg = vv ? off[v + 1] - rs : 0u;
+        const uint32_t pr = vv ? pre(ii) : 0u;
+        const uint32_t clo = max(pr, f0);
+        const uint32_t chi = min(pr + deg, f1);
+        const uint32_t cdeg = (vv && chi > clo) ? chi - clo : 0u;
+        const uint32_t cst = rs + (clo - pr);
+        uint32_t val = vl;
+        if constexpr (WRITE && !BUILD) {
+            if (cdeg) val = scatter_value<PROG>(G, state, v);
+        }
+        const uint32_t incl = wave_incl_scan(cdeg);
+        const uint32_t total = __shfl(incl, 63, 64);
+        for (uint32_t g0 = 0; g0 < total; g0 += 64) {
+            const uint32_t f = g0 + lane;
+            const bool valid = f < total;
+            uint32_t o = 0;
+#pragma unroll
+            for (uint32_t step = 32; step >= 1; step >>= 1) {
+                const uint32_t c = __shfl(incl, (int)(o + step - 1), 64);
+                if (c <= f) o += step;
+            }
+            const uint32_t o_rs = __shfl(rs, (int)o, 64);
+            const uint32_t o_cst = __shfl(cst, (int)o, 64);
+            const uint32_t o_incl = __shfl(incl, (int)o, 64);
+            const uint32_t o_cdeg = __shfl(cdeg, (int)o, 64);
+            const uint32_t o_val = __shfl(val, (int)o, 64);
+            const uint32_t e = o_cst + (f - (o_incl - o_cdeg));
+            const uint32_t col = valid ? cols[e] : 0u;
+            const uint32_t key = col >> s;
+            const bool flag = valid && (e == o_rs || (cols[e - 1] >> s) != key);
+            uint64_t peers = ballot(valid);
+            for (uint32_t b = 0; b < G.nbits; ++b) {
+                const bool bit = (key >> b) & 1u;
+                const uint64_t m = ballot(valid && bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint64_t fpeers = ballot(flag) & peers;
+            const uint32_t rank_i = popc_lt(peers);
+            const uint32_t m_le = popc_lt(fpeers) + (flag ? 1u : 0u);
+            uint32_t bi = 0, bm = 0;
+            if (valid) {
+                bi = ci[key];
+                bm = cm[key];
+            }
+            if (valid && rank_i == 0) {
+                ci[key] = bi + popc64(peers);
+                cm[key] = bm + popc64(fpeers);
+            }
+            if (WRITE && valid) {
+                const uint32_t pos = rioff[key] + bi + rank_i;
+                const uint32_t midx = bm + m_le - 1u;
+                // positions must stay inside the static capacity of bin[p][key]
+                if (pos >= rioff[key + 1] || midx >= rmoff[key + 1] - rmoff[key]) {
+                    G.ctrl->bug = 1;
+                    continue;
+                }
+                const uint16_t idw = (uint16_t)((col & qmask) | (flag ? kFlag : 0u));
+                if constexpr (!BUILD) {
+                    if (flag) G.data[rmoff[key] + midx] = o_val;
+                    G.sc_ids[pos] = idw;
+                    if constexpr (is_weighted(PROG)) G.sc_w[pos] = G.w[e];
+                    if ((pos & (kChunk - 1)) == 0) G.sc_chunk[pos / kChunk] = midx;
+                } else {
+                    if (flag) G.png_src[rmoff[key] + midx] = (uint16_t)o_val;
+                    G.png_ids[pos] = idw;
+                    if (G.w) G.png_w[pos] = G.w[e];
+                    if ((pos & (kChunk - 1)) == 0) G.png_chunk[pos / kChunk] = midx;
+                }
+            }
+        }
+        if (i0 + 64 >= nact || pre(i0 + 64) >= f1) break;
+    }
+}
+
+constexpr uint32_t kScWaves = 4;  // independent task waves per workgroup
+
+// Count pass (WRITE = false) and write pass (WRITE = true) of the task waves.
+template <int PROG, bool BUILD, bool WRITE>
+__global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
+                                                           const uint32_t* __restrict__ state,
+                                                           uint32_t it) {
+    if (!BUILD && G.ctrl->done) return;
     const uint32_t cur = it & 1u;
-    if constexpr (MODE == 0) {
+    const uint32_t k = G.k;
+    const uint32_t ntask = BUILD ? G.n_bldtask : G.ctrl->n_sctask;
+    const uint32_t* __restrict__ t0 = BUILD ? G.bld_t0 : G.sc_t0;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    extern __shared__ uint32_t lds[];
+    uint32_t* ci = lds + wave * 2 * k;
+    uint32_t* cm = ci + k;
+    for (uint32_t t = blockIdx.x * kScWaves + wave; t < ntask; t += gridDim.x * kScWaves) {
+        uint2* __restrict__ tc = G.sc_tc + (size_t)t * k;
+        for (uint32_t j = lane; j < k; j += 64) {
+            if constexpr (WRITE) {
+                const uint2 b = tc[j];
+                cm[j] = b.x;
+                ci[j] = b.y;
+            } else {
+                cm[j] = 0;
+                ci[j] = 0;
+            }
+        }
+        const uint32_t p = task_owner(t0, k, t);
+        const uint32_t jt = t - t0[p];
+        const uint32_t vbase = p << G.s;
+        const uint32_t nv = min(G.q, G.V - vbase);
+        const uint32_t Ea = BUILD ? G.part_E[p] : G.fEa[cur][p];
+        const uint32_t nact = BUILD ? nv : G.fVa[cur][p];
+        const uint32_t f0 = jt << G.sc_shift;
+        const uint32_t f1 = min(f0 + (1u << G.sc_shift), Ea);
+        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, G.flist[cur] + vbase,
+                                         G.fpre[cur] + vbase, ci, cm);
+        if constexpr (!WRITE) {
+            for (uint32_t j = lane; j < k; j += 64) tc[j] = make_uint2(cm[j], ci[j]);
+        }
+    }
+}
+
+// Scan pass: per source partition p and destination q, exclusive scan of the
+// task counts over the tasks of p (in place), giving each task its base in
+// bin[p][q]; the totals are the bin's message and id counts this iteration.
+// 16 strips of tasks x 64 destinations per round; strip sums are scanned in
+// LDS, then each strip rewrites its counts as bases.
+template <bool BUILD>
+__global__ __launch_bounds__(1024) void k_sc_scan(Dev G) {
+    const uint32_t p = blockIdx.x;
+    if constexpr (!BUILD) {
         if (G.ctrl->done) return;
         if (G.mode[p] != GPOP_MODE_SC) return;
     }
-    const uint32_t k = G.k, s = G.s, qmask = G.q - 1u;
-    const uint32_t vbase = p << s;
-    const uint32_t nv = min(G.q, G.V - vbase);
-    const uint32_t nact = (MODE == 0) ? G.fVa[cur][p] : nv;
-    const uint16_t* __restrict__ alist = G.flist[cur] + vbase;
-    const uint32_t* __restrict__ rmoff = G.bin_moff + (size_t)p * k;
-    const uint32_t* __restrict__ rioff = G.bin_ioff + (size_t)p * k;
-    const uint32_t* __restrict__ off = G.off;
-    const uint32_t* __restrict__ cols = G.cols;
-
-    extern __shared__ uint32_t lds[];
-    uint32_t* cnt_i = lds;              // [W][k] ids per (wave, q)
-    uint32_t* cnt_m = lds + W * k;      // [W][k] messages per (wave, q)
-    uint32_t* gi = lds + 2 * W * k;     // [k] running ids of bin[p][q]
-    uint32_t* gm = gi + k;              // [k] running messages of bin[p][q]
-
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    for (uint32_t j = tid; j < k; j += W * 64) {
-        gi[j] = 0;
-        gm[j] = 0;
-    }
-
-    for (uint32_t rbase = 0; rbase < nact; rbase += W * kR) {
-        for (uint32_t j = tid; j < W * k; j += W * 64) {
-            cnt_i[j] = 0;
-            cnt_m[j] = 0;
+    const uint32_t k = G.k;
+    const uint32_t* __restrict__ t0 = BUILD ? G.bld_t0 : G.sc_t0;
+    const uint32_t tb = t0[p], n = t0[p + 1] - tb;
+    const uint32_t tid = threadIdx.x, ql = tid & 63u, strip = tid >> 6;
+    __shared__ uint32_t s_m[16][64], s_i[16][64];
+    __shared__ uint64_t s_tot[2][16];
+    const uint32_t per = (n + 15u) / 16u;
+    const uint32_t a = min(strip * per, n), b = min(a + per, n);
+    uint64_t my_tm = 0, my_ti = 0;
+    for (uint32_t q0 = 0; q0 < k; q0 += 64) {
+        const uint32_t q = q0 + ql;
+        uint32_t sm = 0, si = 0;
+        if (q < k)
+            for (uint32_t t = a; t < b; ++t) {
+                const uint2 c = G.sc_tc[(size_t)(tb + t) * k + q];
+                sm += c.x;
+                si += c.y;
+            }
+        s_m[strip][ql] = sm;
+        s_i[strip][ql] = si;
+        __syncthreads();
+        uint32_t rm = 0, ri = 0, tm = 0, ti = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            if (w < strip) {
+                rm += s_m[w][ql];
+                ri += s_i[w][ql];
+            }
+            tm += s_m[w][ql];
+            ti += s_i[w][ql];
         }
         __syncthreads();
-        const uint32_t wbeg = rbase + wave * kR;
-        const uint32_t wend = min(wbeg + kR, nact);
-        uint32_t* my_i = cnt_i + wave * k;
-        uint32_t* my_m = cnt_m + wave * k;
-
-        for (int pass = 0; pass < 2; ++pass) {
-            if (pass == 1) {
-                __syncthreads();
-                // exclusive scan of the counts over waves, per destination q
-                for (uint32_t j = tid; j < k; j += W * 64) {
-                    uint32_t ri = gi[j], rm = gm[j];
-#pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        uint32_t ti = cnt_i[w * k + j], tm = cnt_m[w * k + j];
-                        cnt_i[w * k + j] = ri;
-                        cnt_m[w * k + j] = rm;
-                        ri += ti;
-                        rm += tm;
-                    }
-                    gi[j] = ri;
-                    gm[j] = rm;
-                }
-                __syncthreads();
-                if constexpr (MODE == 1) break;
+        if (q < k) {
+            for (uint32_t t = a; t < b; ++t) {
+                uint2* c = G.sc_tc + (size_t)(tb + t) * k + q;
+                const uint2 x = *c;
+                *c = make_uint2(rm, ri);
+                rm += x.x;
+                ri += x.y;
             }
-            for (uint32_t x0 = wbeg; x0 < wend; x0 += 64) {
-                const uint32_t i = x0 + lane;
-                const bool vv = i < wend;
-                const uint32_t vl = vv ? ((MODE == 0) ? (uint32_t)alist[i] : i) : 0u;
-                const uint32_t v = vbase + vl;
-                const uint32_t rs = vv ? off[v] : 0u;
-                const uint32_t deg = vv ? off[v + 1] - rs : 0u;
-                uint32_t val = vl;
-                if constexpr (MODE == 0) {
-                    if (vv && pass == 1) val = scatter_value<PROG>(G, state, v);
-                }
-                const uint32_t incl = wave_incl_scan(deg);
-                const uint32_t total = __shfl(incl, 63, 64);
-                for (uint32_t f0 = 0; f0 < total; f0 += 64) {
-                    const uint32_t f = f0 + lane;
-                    const bool valid = f < total;
-                    // owner lane: number of window vertices whose edges end at or before f
-                    uint32_t o = 0;
-#pragma unroll
-                    for (uint32_t step = 32; step >= 1; step >>= 1) {
-                        uint32_t c = __shfl(incl, (int)(o + step - 1), 64);
-                        if (c <= f) o += step;
-                    }
-                    const uint32_t o_rs = __shfl(rs, (int)o, 64);
-                    const uint32_t o_incl = __shfl(incl, (int)o, 64);
-                    const uint32_t o_deg = __shfl(deg, (int)o, 64);
-                    const uint32_t o_val = __shfl(val, (int)o, 64);
-                    const uint32_t e = o_rs + (f - (o_incl - o_deg));
-                    const uint32_t col = valid ? cols[e] : 0u;
-                    const uint32_t key = col >> s;
-                    const bool flag = valid && (e == o_rs || (cols[e - 1] >> s) != key);
-                    // lanes with the same destination partition
-                    uint64_t peers = ballot(valid);
-                    for (uint32_t b = 0; b < G.nbits; ++b) {
-                        const bool bit = (key >> b) & 1u;
-                        const uint64_t m = ballot(valid && bit);
-                        peers &= bit ? m : ~m;
-                    }
-                    const uint64_t fpeers = ballot(flag) & peers;
-                    const uint32_t rank_i = popc_lt(peers);
-                    const uint32_t m_le = popc_lt(fpeers) + (flag ? 1u : 0u);
-                    uint32_t bi = 0, bm = 0;
-                    if (valid) {
-                        bi = my_i[key];
-                        bm = my_m[key];
-                    }
-                    if (valid && rank_i == 0) {
-                        my_i[key] = bi + popc64(peers);
-                        my_m[key] = bm + popc64(fpeers);
-                    }
-                    if (pass == 1 && valid) {
-                        const uint32_t pos = rioff[key] + bi + rank_i;
-                        const uint32_t midx = bm + m_le - 1u;
-                        // positions must stay inside the static capacity of bin[p][key]
-                        if (pos >= rioff[key + 1] || midx >= rmoff[key + 1] - rmoff[key]) {
-                            G.ctrl->bug = 1;
-                            continue;
-                        }
-                        const uint16_t idw = (uint16_t)((col & qmask) | (flag ? kFlag : 0u));
-                        if constexpr (MODE == 0) {
-                            if (flag) G.data[rmoff[key] + midx] = o_val;
-                            G.sc_ids[pos] = idw;
-                            if constexpr (is_weighted(PROG)) G.sc_w[pos] = G.w[e];
-                            if ((pos & (kChunk - 1)) == 0) G.sc_chunk[pos / kChunk] = midx;
-                        } else {
-                            if (flag) G.png_src[rmoff[key] + midx] = (uint16_t)o_val;
-                            G.png_ids[pos] = idw;
-                            if (G.w) G.png_w[pos] = G.w[e];
-                            if ((pos & (kChunk - 1)) == 0) G.png_chunk[pos / kChunk] = midx;
-                        }
-                    }
+            if (strip == 0) {
+                if constexpr (BUILD) {
+                    G.cnt_m[(size_t)p * k + q] = tm;
+                    G.cnt_i[(size_t)p * k + q] = ti;
+                } else {
+                    G.sc_cnt[(size_t)q * k + p] = make_uint2(tm, ti);
+                    my_tm += tm;
+                    my_ti += ti;
                 }
             }
         }
-        __syncthreads();
     }
-
-    // epilogue: per-bin totals of this source partition
-    if constexpr (MODE == 0) {
-        uint32_t tm = 0, ti = 0;
-        for (uint32_t j = tid; j < k; j += W * 64) {
-            G.sc_cnt[(size_t)j * k + p] = make_uint2(gm[j], gi[j]);
-            tm += gm[j];
-            ti += gi[j];
-        }
-        tm = wave_sum_u32(tm);
-        ti = wave_sum_u32(ti);
-        __syncthreads();
-        if (lane == 0) {
-            cnt_i[wave] = ti;
-            cnt_m[wave] = tm;
+    if constexpr (!BUILD) {
+        my_tm = wave_sum_u64(my_tm);
+        my_ti = wave_sum_u64(my_ti);
+        if (ql == 0) {
+            s_tot[0][strip] = my_tm;
+            s_tot[1][strip] = my_ti;
         }
         __syncthreads();
         if (tid == 0) {
-            uint32_t a = 0, b = 0;
-            for (int w = 0; w < W; ++w) {
-                a += cnt_m[w];
-                b += cnt_i[w];
+            uint64_t x = 0, y = 0;
+            for (int w = 0; w < 16; ++w) {
+                x += s_tot[0][w];
+                y += s_tot[1][w];
             }
-            G.sc_tot[p] = make_uint2(a, b);
-        }
-    } else if constexpr (MODE == 1) {
-        for (uint32_t j = tid; j < k; j += W * 64) {
-            G.cnt_m[(size_t)p * k + j] = gm[j];
-            G.cnt_i[(size_t)p * k + j] = gi[j];
+            G.sc_tot[p] = make_uint2((uint32_t)x, (uint32_t)y);
         }
     }
 }
 
-int sc_waves_for(uint32_t k) {
-    // (2W + 2) * k words of LDS must fit in 80 KB
-    if ((2 * 4 + 2) * (size_t)k * 4 <= 81920) return 4;
-    if ((2 * 2 + 2) * (size_t)k * 4 <= 81920) return 2;
-    return 1;
-}
+size_t sc_lds_bytes(uint32_t k) { return (size_t)kScWaves * 2 * k * 4; }
 
-size_t sc_lds_bytes(uint32_t k, int waves) { return (size_t)(2 * waves + 2) * k * 4; }
-
-template <int PROG, int MODE, int W>
-static hipError_t launch_sc_w(const Dev& G, const Params& P, const uint32_t* state, uint32_t it,
-                              hipStream_t st) {
-    const size_t lds = sc_lds_bytes(G.k, W);
-    auto fn = k_sc<PROG, MODE, W>;
+template <int PROG, bool BUILD, bool WRITE>
+static hipError_t launch_pass(const Dev& G, const Params& P, const uint32_t* state, uint32_t it,
+                              uint32_t max_tasks, hipStream_t st) {
+    if (max_tasks == 0) return hipSuccess;
+    const size_t lds = sc_lds_bytes(G.k);
+    auto fn = k_sc_pass<PROG, BUILD, WRITE>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(G.k), dim3(W * 64), lds, st, G, P, state, it);
+    const uint32_t blocks = std::min<uint32_t>((max_tasks + kScWaves - 1) / kScWaves, 2048u);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kScWaves * 64), lds, st, G, P, state, it);
     return hipGetLastError();
 }
 
-template <int PROG, int MODE>
-static hipError_t launch_sc_any(const Dev& G, const Params& P, const uint32_t* state, uint32_t it,
-                                hipStream_t st) {
-    switch (sc_waves_for(G.k)) {
-        case 4: return launch_sc_w<PROG, MODE, 4>(G, P, state, it, st);
-        case 2: return launch_sc_w<PROG, MODE, 2>(G, P, state, it, st);
-        default: return launch_sc_w<PROG, MODE, 1>(G, P, state, it, st);
-    }
+template <bool BUILD>
+static hipError_t launch_scan_pass(const Dev& G, hipStream_t st) {
+    hipLaunchKernelGGL(k_sc_scan<BUILD>, dim3(G.k), dim3(1024), 0, st, G);
+    return hipGetLastError();
 }
 
 hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st) {
     Params P{};
-    return fill ? launch_sc_any<P_BFS, 2>(G, P, nullptr, 0, st)
-                : launch_sc_any<P_BFS, 1>(G, P, nullptr, 0, st);
+    if (!fill) {
+        hipError_t e = launch_pass<P_BFS, true, false>(G, P, nullptr, 0, G.n_bldtask, st);
+        if (e != hipSuccess) return e;
+        return launch_scan_pass<true>(G, st);
+    }
+    return launch_pass<P_BFS, true, true>(G, P, nullptr, 0, G.n_bldtask, st);
+}
+
+template <int PROG>
+static hipError_t launch_sc_prog(const Dev& G, const Params& P, const uint32_t* state, uint32_t it,
+                                 hipStream_t st) {
+    hipError_t e = launch_pass<PROG, false, false>(G, P, state, it, G.max_sctask, st);
+    if (e != hipSuccess) return e;
+    e = launch_scan_pass<false>(G, st);
+    if (e != hipSuccess) return e;
+    return launch_pass<PROG, false, true>(G, P, state, it, G.max_sctask, st);
 }
 
 hipError_t launch_scatter_sc(const Dev& G, const Params& P, int prog, const uint32_t* state,
                              uint32_t it, hipStream_t st) {
     switch (prog) {
-        case P_BFS: return launch_sc_any<P_BFS, 0>(G, P, state, it, st);
-        case P_CC: return launch_sc_any<P_CC, 0>(G, P, state, it, st);
-        case P_SSSP: return launch_sc_any<P_SSSP, 0>(G, P, state, it, st);
-        case P_PR: return launch_sc_any<P_PR, 0>(G, P, state, it, st);
-        case P_PPR: return launch_sc_any<P_PPR, 0>(G, P, state, it, st);
-        case P_CARRY: return launch_sc_any<P_CARRY, 0>(G, P, state, it, st);
+        case P_BFS: return launch_sc_prog<P_BFS>(G, P, state, it, st);
+        case P_CC: return launch_sc_prog<P_CC>(G, P, state, it, st);
+        case P_SSSP: return launch_sc_prog<P_SSSP>(G, P, state, it, st);
+        case P_PR: return launch_sc_prog<P_PR>(G, P, state, it, st);
+        case P_PPR: return launch_sc_prog<P_PPR>(G, P, state, it, st);
+        case P_CARRY: return launch_sc_prog<P_CARRY>(G, P, state, it, st);
     }
     return hipErrorInvalidValue;
 }
@@ -342,43 +422,38 @@ __device__ __forceinline__ uint8_t analytical_mode(const Dev& G, const Params& P
 // gathered) from per-partition values the previous iteration wrote. Reads
 // mode[], so it must run before the next plan overwrites it.
 __device__ void finalize_prev(const Dev& G, uint32_t it) {
-    __shared__ uint64_t red[4][16];
+    __shared__ uint64_t red[6][16];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    uint64_t scm = 0, sci = 0, gid = 0, gpt = 0;
+    uint64_t v[6] = {0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged
     for (uint32_t p = tid; p < G.k; p += blockDim.x) {
         if (G.mode[p] == GPOP_MODE_SC) {
             const uint2 t = G.sc_tot[p];
-            scm += t.x;
-            sci += t.y;
+            v[0] += t.x;
+            v[1] += t.y;
         }
-        const uint32_t g = G.gat_ids[p];
-        gid += g;
-        gpt += g ? 1u : 0u;
     }
-    scm = wave_sum_u64(scm);
-    sci = wave_sum_u64(sci);
-    gid = wave_sum_u64(gid);
-    gpt = wave_sum_u64(gpt);
-    if (lane == 0) {
-        red[0][wave] = scm;
-        red[1][wave] = sci;
-        red[2][wave] = gid;
-        red[3][wave] = gpt;
+    for (uint32_t t = tid; t < G.n_gtask + G.n_gsplit; t += blockDim.x) {
+        if (t < G.n_gtask) v[2] += G.gat_ids[t];
+        const uint32_t r = G.gat_ran[t];
+        v[3] += r == 1;
+        v[4] += r == 2;
+        v[5] += r == 3;
     }
+    for (int j = 0; j < 6; ++j) v[j] = wave_sum_u64(v[j]);
+    if (lane == 0)
+        for (int j = 0; j < 6; ++j) red[j][wave] = v[j];
     __syncthreads();
     if (tid == 0) {
-        uint64_t a = 0, b = 0, c = 0, d = 0;
-        for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
-            a += red[0][w];
-            b += red[1][w];
-            c += red[2][w];
-            d += red[3][w];
-        }
+        uint64_t t[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t w = 0; w < blockDim.x / 64; ++w)
+            for (int j = 0; j < 6; ++j) t[j] += red[j][w];
         gpop_iter_stats* r = G.log + ((it - 1) % kLogCap);
-        r->sc_msgs = a;
-        r->sc_ids = b;
-        r->gathered_ids = c;
-        r->gather_parts = (uint32_t)d;
+        r->sc_msgs = t[0];
+        r->sc_ids = t[1];
+        r->gathered_ids = t[2];
+        r->gather_parts = (uint32_t)t[3];
+        r->split_tasks = (uint32_t)t[4];
+        r->merged_parts = t[5];
     }
     __syncthreads();
 }
@@ -392,29 +467,52 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
     if (C->done) return;
     const uint32_t cur = it & 1u;
     if (it > 0) finalize_prev(G, it);
-    __shared__ uint64_t red[6][16];
+    __shared__ uint64_t red[9][16];
     __shared__ double dred[16];
+    __shared__ uint32_t s_w[16];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0;
+    uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0, sva = 0, sea = 0, pcv = 0;
     double dang = 0.0;
-    for (uint32_t p = tid; p < G.k; p += 1024) {
-        const uint32_t Va = G.fVa[cur][p], Ea = G.fEa[cur][p];
-        uint8_t md = GPOP_MODE_NONE;
-        if (Va) {
-            if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
-            else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
-            else md = analytical_mode(G, P, p, Va, Ea);
+    uint32_t tcarry = 0;  // source-centric tasks of the partitions before this block
+    for (uint32_t p0 = 0; p0 < G.k; p0 += 1024) {
+        const uint32_t p = p0 + tid;
+        uint32_t ntask = 0;
+        if (p < G.k) {
+            const uint32_t Va = G.fVa[cur][p], Ea = G.fEa[cur][p];
+            uint8_t md = GPOP_MODE_NONE;
+            if (Va) {
+                if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
+                else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
+                else md = analytical_mode(G, P, p, Va, Ea);
+            }
+            G.mode[p] = md;
+            va += Va;
+            ea += Ea;
+            if (md == GPOP_MODE_PC) {
+                ++npc;
+                pcm += G.part_M[p];
+                pci += G.part_E[p];
+                pcv += min(G.q, G.V - (p << G.s));
+            } else if (md == GPOP_MODE_SC) {
+                ++nsc;
+                sva += Va;
+                sea += Ea;
+                ntask = (Ea + (1u << G.sc_shift) - 1u) >> G.sc_shift;
+            }
+            dang += G.dpart[cur][p];
         }
-        G.mode[p] = md;
-        va += Va;
-        ea += Ea;
-        nsc += md == GPOP_MODE_SC;
-        npc += md == GPOP_MODE_PC;
-        if (md == GPOP_MODE_PC) {
-            pcm += G.part_M[p];
-            pci += G.part_E[p];
+        // exclusive scan of the task counts in partition order
+        const uint32_t incl = wave_incl_scan(ntask);
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            if (w < wave) before += s_w[w];
+            tot += s_w[w];
         }
-        dang += G.dpart[cur][p];
+        if (p < G.k) G.sc_t0[p] = tcarry + before + incl - ntask;
+        tcarry += tot;
+        __syncthreads();
     }
     va = wave_sum_u64(va);
     ea = wave_sum_u64(ea);
@@ -422,6 +520,9 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
     npc = wave_sum_u64(npc);
     pcm = wave_sum_u64(pcm);
     pci = wave_sum_u64(pci);
+    sva = wave_sum_u64(sva);
+    sea = wave_sum_u64(sea);
+    pcv = wave_sum_u64(pcv);
     dang = wave_sum_f64(dang);
     if (lane == 0) {
         red[0][wave] = va;
@@ -430,16 +531,21 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
         red[3][wave] = npc;
         red[4][wave] = pcm;
         red[5][wave] = pci;
+        red[6][wave] = sva;
+        red[7][wave] = sea;
+        red[8][wave] = pcv;
         dred[wave] = dang;
     }
     __syncthreads();
     if (tid == 0) {
-        uint64_t t[6] = {0, 0, 0, 0, 0, 0};
+        uint64_t t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         double d = 0.0;
         for (int w = 0; w < 16; ++w) {
-            for (int j = 0; j < 6; ++j) t[j] += red[j][w];
+            for (int j = 0; j < 9; ++j) t[j] += red[j][w];
             d += dred[w];
         }
+        G.sc_t0[G.k] = tcarry;
+        C->n_sctask = tcarry;
         C->frontier = t[0];
         C->dangling = d;
         if (t[0] == 0) {
@@ -453,10 +559,15 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
             r->pc_parts = (uint32_t)t[3];
             r->pc_msgs = t[4];
             r->pc_ids = t[5];
+            r->sc_active_vertices = t[6];
+            r->sc_active_edges = t[7];
+            r->pc_vertices = t[8];
             r->sc_msgs = 0;
             r->sc_ids = 0;
             r->gathered_ids = 0;
             r->gather_parts = 0;
+            r->split_tasks = 0;
+            r->merged_parts = 0;
         }
     }
 }

@@ -10,10 +10,12 @@ def torch_cuda():
     return torch
 
 
-def make_graph(g, log2_part):
+def make_graph(g, log2_part, sc_task_log2=0, gather_task_ids=0):
     import paper_1806_08092_amd as gp
     off, cols, w = gp.upload_csr(g)
-    return gp.Graph(off, cols, w, log2_part=log2_part), (off, cols, w)
+    G = gp.Graph(off, cols, w, log2_part=log2_part, sc_task_log2=sc_task_log2,
+                 gather_task_ids=gather_task_ids)
+    return G, (off, cols, w)
 
 
 def run_program(G, prog, n, root=0, persist=1, selector="analytical", max_iter=1 << 20,

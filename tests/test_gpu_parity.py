@@ -249,3 +249,37 @@ def test_malformed_csr_rejected():
     bad_off = torch.tensor([0, 3, 2], dtype=torch.int32, device="cuda")
     with pytest.raises(gp.GpopError):
         gp.Graph(bad_off, torch.tensor([0, 1, 1], dtype=torch.int32, device="cuda"), log2_part=8)
+
+
+@pytest.mark.parametrize("sc_log2,gids", [(6, 256), (8, 1024), (6, 4096)])
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_task_splits(sc_log2, gids, sel):
+    """Source-centric scatter cut into many small edge tasks (tasks start and
+    end inside rows) and gathers split over many tasks plus the merge: results
+    must not change."""
+    g = gg.rmat_graph(12, 16, 41, weights_seed=42)
+    sym = gg.rmat_graph(12, 16, 43, symmetric=True)
+    G, _ = make_graph(g, 10, sc_task_log2=sc_log2, gather_task_ids=gids)
+    Gs, _ = make_graph(sym, 10, sc_task_log2=sc_log2, gather_task_ids=gids)
+    for root in roots_of(g, 2):
+        got, _ = run_program(G, "bfs", g.n, root=root, selector=sel)
+        assert np.array_equal(got, oracle.bfs_levels(g, root))
+        got, _ = run_program(G, "sssp", g.n, root=root, selector=sel)
+        assert np.array_equal(got, oracle.sssp(g, root))
+        got, _ = run_program(G, "ppr", g.n, root=root, selector=sel, max_iter=20)
+        assert pr_ok(got, oracle.ppr(g, root, 0.15, 20))
+        got, _ = run_program(Gs, "carry_bfs", sym.n, root=root, persist=2, selector=sel)
+        assert np.array_equal(got, oracle.bfs_levels(sym, root))
+    got, _ = run_program(Gs, "cc", sym.n, selector=sel)
+    assert np.array_equal(got, oracle.cc_minlabel(sym))
+    got, _ = run_program(G, "pagerank", g.n, selector=sel, max_iter=10)
+    assert pr_ok(got, oracle.pagerank(g, 0.85, 10))
+
+
+def test_split_results_bitwise_equal_unsplit():
+    g = gg.rmat_graph(12, 16, 44)
+    G1, _ = make_graph(g, 10)
+    G2, _ = make_graph(g, 10, sc_task_log2=6, gather_task_ids=256)
+    a, _ = run_program(G1, "pagerank", g.n, max_iter=10)
+    b, _ = run_program(G2, "pagerank", g.n, max_iter=10)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
