@@ -121,8 +121,14 @@ def main():
     ap.add_argument("--selector", default="analytical")
     ap.add_argument("--bw-ratio", type=float, default=2.0)
     ap.add_argument("--log2-part", type=int, default=0)
+    ap.add_argument("--gather-task-ids", type=int, default=0,
+                    help="ids per gather task (0: library default)")
+    ap.add_argument("--sc-task-log2", type=int, default=0,
+                    help="log2 of active edges per source-centric task (0: library default)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the device copy used as the practical bandwidth ceiling")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -141,7 +147,8 @@ def main():
     off, cols, w = gp.upload_csr(g)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    G = gp.Graph(off, cols, w, log2_part=lp)
+    G = gp.Graph(off, cols, w, log2_part=lp, sc_task_log2=args.sc_task_log2,
+                 gather_task_ids=args.gather_task_ids)
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - t) * 1e3
     info = G.info()
@@ -232,12 +239,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "vertices": g.n, "edges": g.m, "q": info.q, "k": info.k,
                    "selector": args.selector, "bw_ratio": args.bw_ratio,
+                   "gather_task_ids": args.gather_task_ids, "sc_task_log2": args.sc_task_log2,
                    "runs_per_step": len(runs), "iterations_per_run": iters_per_run,
                    "edges_traversed_per_step": edges_per_step, "preprocess_ms": prep_ms},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS, "traffic": None},
         "per_kernel": per_kernel,
     }
+    if args.copy_mib:
+        # a plain device-to-device copy of known size: the measured ceiling,
+        # and the reference that scales rocprofv3 FETCH_SIZE / WRITE_SIZE
+        n = args.copy_mib << 18
+        a = torch.empty(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        out["copy_ceiling"] = {"bytes": 2 * 4 * n, "GBps": 2 * 4 * n / (ms * 1e-3) / 1e9}
+        out["roofline"]["frac_of_copy"] = ach / out["copy_ceiling"]["GBps"]
+        del a, b
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         v, sample = cpu_baseline(g, runs, args.cpu_budget)

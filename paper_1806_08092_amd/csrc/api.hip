@@ -286,6 +286,11 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     Ctrl hc;
     HIP_OR_RETURN(hipMemcpyAsync(&hc, G.ctrl, sizeof hc, hipMemcpyDeviceToHost, st), "read control");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    if (!hc.csr_err) {
+        HIP_OR_RETURN(launch_validate_edges(G, st), "validate CSR");
+        HIP_OR_RETURN(hipMemcpyAsync(&hc, G.ctrl, sizeof hc, hipMemcpyDeviceToHost, st), "read control");
+        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    }
     if (hc.csr_err) {
         static const char* why[] = {"", "offsets[0] != 0", "decreasing offsets or offset > E",
                                     "offsets[V] != E", "column index >= V", "row not sorted ascending"};

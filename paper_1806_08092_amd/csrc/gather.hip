@@ -4,21 +4,27 @@
 
 namespace gpop {
 
-constexpr uint32_t kGT = 1024;    // gather threads per workgroup
+// Gather workgroups are 8 waves; with a 16K-vertex partition of 4-byte state
+// two of them fit the 160 KB LDS of a CU, so one can wait on a barrier while
+// the other streams bins.
+constexpr uint32_t kGT = 512;
 constexpr uint32_t kGW = kGT / 64;
 
-// LDS layout of the gather workgroup (bytes, all offsets 16-aligned).
+// Programs whose initFunc keeps vertices active need a per-vertex carry flag.
+__host__ __device__ constexpr bool has_carry(int prog) { return prog == P_CARRY || is_sum(prog); }
+
+// LDS layout of the gather workgroup (bytes, all offsets 16-aligned). The
+// bin-list arrays double as scratch for the frontier masks in the filter.
 struct GatherLds {
-    size_t state, flag_a, flag_b, tag, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
+    size_t state, tag, carry, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
 };
 
-__host__ __device__ inline GatherLds gather_layout(bool sum, uint32_t q) {
+__host__ __device__ inline GatherLds gather_layout(int prog, uint32_t q) {
     GatherLds L{};
     size_t o = 0;
-    L.state = o;  o += (size_t)q * (sum ? 8 : 4);
-    L.tag = o;    o += sum ? ((size_t)q * 2 + 15) / 16 * 16 : 0;
-    L.flag_a = o; o += ((size_t)q + 15) / 16 * 16;
-    L.flag_b = o; o += ((size_t)q + 15) / 16 * 16;
+    L.state = o;  o += (size_t)q * (is_sum(prog) ? 8 : 4);
+    L.tag = o;    o += is_sum(prog) ? ((size_t)q * 2 + 15) / 16 * 16 : 0;
+    L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
     L.bl_ioff = o; o += kGT * 4;
     L.bl_icnt = o; o += kGT * 4;
     L.bl_moff = o; o += kGT * 4;
@@ -29,7 +35,7 @@ __host__ __device__ inline GatherLds gather_layout(bool sum, uint32_t q) {
     return L;
 }
 
-size_t gather_lds_bytes(int prog, uint32_t q) { return gather_layout(is_sum(prog), q).total; }
+size_t gather_lds_bytes(int prog, uint32_t q) { return gather_layout(prog, q).total; }
 
 // Exclusive prefix of a 0..7 per-lane count across the wave, from bit-plane
 // ballots.
@@ -43,7 +49,7 @@ __device__ __forceinline__ uint32_t pieces_of(uint32_t ioff, uint32_t icnt) {
 
 struct GatherShared {
     uint32_t wc[kGW], wp[kGW], ws[kGW];
-    uint64_t r64[3][kGW];
+    uint64_t r64[kGW];
     double rd[kGW];
 };
 
@@ -51,30 +57,33 @@ struct GatherShared {
 template <int PROG>
 __device__ void reinit(const Dev& G, const Params& P, uint32_t it, uint32_t cq, const uint32_t* st32,
                        uint8_t* carry) {
-    const uint32_t cur = it & 1u;
-    const uint32_t vbase = cq << G.s;
-    const uint32_t prevVa = G.fVa[cur][cq];
-    const uint16_t* __restrict__ prev = G.flist[cur] + vbase;
-    for (uint32_t i = threadIdx.x; i < prevVa; i += kGT) {
-        const uint32_t u = prev[i];
-        if constexpr (PROG == P_CARRY) {
-            carry[u] = (it + 1u - st32[u]) < P.persist;
-        } else if constexpr (is_sum(PROG)) {
-            carry[u] = 1;  // PageRank family: value restarts at 0, vertex stays active
+    if constexpr (has_carry(PROG)) {
+        const uint32_t cur = it & 1u;
+        const uint32_t vbase = cq << G.s;
+        const uint32_t prevVa = G.fVa[cur][cq];
+        const uint16_t* __restrict__ prev = G.flist[cur] + vbase;
+        for (uint32_t i = threadIdx.x; i < prevVa; i += kGT) {
+            const uint32_t u = prev[i];
+            if constexpr (PROG == P_CARRY) carry[u] = (it + 1u - st32[u]) < P.persist;
+            else carry[u] = 1;  // PageRank family: value restarts at 0, vertex stays active
         }
     }
 }
 
-// filterFunc on carried and newly activated vertices, state write-back, and
-// ballot compaction of the next frontier (list, bitmap, active-edge prefix,
-// V_a, E_a, dangling partial sum). For the min programs a vertex is newly
-// activated when its value decreased (hit); for the sum programs when it
-// received a non-zero amount.
+// filterFunc on carried and newly activated vertices, state write-back and
+// compaction of the next frontier (ascending list, bitmap, active-edge
+// prefix, V_a, E_a, dangling partial sum). A min-program vertex is newly
+// activated when its combined value is below the value still in memory; a
+// sum-program vertex when it received a non-zero amount. Wave w owns a
+// contiguous vertex range: pass 1 applies the filter, writes the state and
+// counts kept vertices and their out-edges (keep masks go to LDS scratch),
+// one scan across waves gives every wave its offsets, pass 2 writes the
+// frontier.
 template <int PROG>
 __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __restrict__ state,
                                  uint32_t it, uint32_t cq, const uint32_t* st32,
-                                 const unsigned long long* acc, const uint8_t* hit,
-                                 const uint8_t* carry, GatherShared& sh, uint32_t ids_done,
+                                 const unsigned long long* acc, const uint8_t* carry,
+                                 uint64_t* kscratch, GatherShared& sh, uint32_t ids_done,
                                  uint32_t task) {
     constexpr bool SUM = is_sum(PROG);
     const uint32_t nxt = (it & 1u) ^ 1u;
@@ -82,25 +91,24 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
     const uint32_t nv = min(Q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     const double dang = SUM ? G.ctrl->dangling : 0.0;
-    uint32_t running = 0, erun = 0;
+    const uint32_t* __restrict__ off = G.off;
+    const uint32_t per = ((Q / kGW) + 63u) & ~63u;  // vertices per wave, multiple of 64
+    const uint32_t wb = wave * per;
+    uint32_t cnt = 0, edges = 0;
     double my_d = 0.0;
-    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
-    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
-    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
-    for (uint32_t u0 = 0; u0 < nv; u0 += kGT) {
-        const uint32_t u = u0 + tid;
-        const bool in = u < nv;
+    for (uint32_t u0 = wb; u0 < wb + per && u0 < Q; u0 += 64) {
+        const uint32_t u = u0 + lane;
         bool keep = false;
         uint32_t deg = 0;
-        if (in) {
+        if (u < nv) {
             const uint32_t v = vbase + u;
-            deg = G.off[v + 1] - G.off[v];
             if constexpr (!SUM) {
-                keep = hit[u] || carry[u];  // filterFunc returns true for the min programs
-                if (hit[u]) state[v] = st32[u];
+                const bool hit = st32[u] < state[v];
+                keep = hit;
+                if constexpr (has_carry(PROG)) keep = keep || carry[u];
+                if (hit) state[v] = st32[u];
             } else {
-                const bool prelim = acc[u] != 0ull || carry[u];
-                if (prelim) {
+                if (acc[u] != 0ull || carry[u]) {
                     const double y = (double)acc[u] * kInvFix;
                     float x;
                     if constexpr (PROG == P_PR) {
@@ -115,45 +123,56 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
                         keep = x > 0.0f;
                     }
                     state[v] = __float_as_uint(x);
-                    if (deg == 0) my_d += (double)x;
+                    if (off[v + 1] == off[v]) my_d += (double)x;
                 }
             }
+            if (keep) deg = off[v + 1] - off[v];
         }
-        const uint64_t bm = ballot(keep);
-        const uint32_t kdeg = keep ? deg : 0u;
-        const uint32_t dincl = wave_incl_scan(kdeg);
-        if (lane == 0 && u0 + wave * 64u < Q) {
-            const uint32_t wi = (u0 + wave * 64u) >> 5;
-            nbits[wi] = (uint32_t)bm;
-            nbits[wi + 1] = (uint32_t)(bm >> 32);
+        const uint64_t km = ballot(keep);
+        if (lane == 0) kscratch[u0 >> 6] = km;
+        cnt += popc64(km);
+        edges += deg;
+    }
+    edges = wave_sum_u32(edges);
+    if (lane == 0) {
+        sh.wc[wave] = cnt;
+        sh.ws[wave] = edges;
+    }
+    __syncthreads();
+    uint32_t pos = 0, epos = 0, tot = 0, etot = 0;
+    for (uint32_t w = 0; w < kGW; ++w) {
+        if (w < wave) {
+            pos += sh.wc[w];
+            epos += sh.ws[w];
         }
-        if (lane == 63) {
-            sh.wc[wave] = popc64(bm);
-            sh.ws[wave] = dincl;
-        }
-        __syncthreads();
-        uint32_t before = 0, tot = 0, ebefore = 0, etot = 0;
-        for (uint32_t w = 0; w < kGW; ++w) {
-            if (w < wave) {
-                before += sh.wc[w];
-                ebefore += sh.ws[w];
-            }
-            tot += sh.wc[w];
-            etot += sh.ws[w];
+        tot += sh.wc[w];
+        etot += sh.ws[w];
+    }
+    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
+    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
+    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
+    for (uint32_t u0 = wb; u0 < wb + per && u0 < Q; u0 += 64) {
+        const uint32_t u = u0 + lane;
+        const uint64_t km = kscratch[u0 >> 6];
+        const bool keep = (km >> lane) & 1u;
+        const uint32_t deg = keep ? off[vbase + u + 1] - off[vbase + u] : 0u;
+        const uint32_t dincl = wave_incl_scan(deg);
+        if (lane == 0) {
+            nbits[u0 >> 5] = (uint32_t)km;
+            nbits[(u0 >> 5) + 1] = (uint32_t)(km >> 32);
         }
         if (keep) {
-            const uint32_t pos = running + before + popc_lt(bm);
-            nlist[pos] = (uint16_t)u;
-            npre[pos] = erun + ebefore + dincl - kdeg;
+            const uint32_t at = pos + popc_lt(km);
+            nlist[at] = (uint16_t)u;
+            npre[at] = epos + dincl - deg;
         }
-        running += tot;
-        erun += etot;
-        __syncthreads();
+        pos += popc64(km);
+        epos += __shfl(dincl, 63, 64);
     }
     my_d = wave_sum_f64(my_d);
     const uint64_t ids64 = wave_sum_u64((uint64_t)ids_done);
     if (lane == 0) {
-        sh.r64[1][wave] = ids64;
+        sh.r64[wave] = ids64;
         sh.rd[wave] = my_d;
     }
     __syncthreads();
@@ -161,11 +180,11 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
         uint64_t ni = 0;
         double d = 0.0;
         for (uint32_t w = 0; w < kGW; ++w) {
-            ni += sh.r64[1][w];
+            ni += sh.r64[w];
             d += sh.rd[w];
         }
-        G.fVa[nxt][cq] = running;
-        G.fEa[nxt][cq] = erun;
+        G.fVa[nxt][cq] = tot;
+        G.fEa[nxt][cq] = etot;
         G.dpart[nxt][cq] = d;
         if (task != 0xFFFFFFFFu) G.gat_ids[task] = (uint32_t)ni;
     }
@@ -181,8 +200,8 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
 //
 // Bins are enumerated from the per-partition modes and counts (the two-level
 // active list: only non-empty bins of the scattered partitions are read).
-// Each piece is decoded by one wave: message index of an id = chunk-table
-// base + number of message-start flags after the piece start.
+// Each wave decodes a contiguous run of pieces: message index of an id =
+// chunk-table base + number of message-start flags after the piece start.
 //
 // Combining is atomic-free. Min programs: every pending lane reads the state
 // word and writes its value if smaller; after a barrier each lane re-reads,
@@ -194,11 +213,13 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
 // 64-bit integers in units of 2^-60, so the result is exact and independent
 // of the order of additions.
 template <int PROG>
-__global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __restrict__ state,
-                                                uint32_t it) {
+__global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __restrict__ state,
+                                                   uint32_t it) {
     if (G.ctrl->done) return;
     constexpr bool SUM = is_sum(PROG);
     constexpr uint32_t IDENT = is_sum(PROG) ? kIdentSum : kIdentMin;
+    // pieces per wave per combine round (sum tags are 16-bit: kGT * 4 * PPW < 65536)
+    constexpr uint32_t PPW = SUM ? 2 : 4;
     const uint32_t task = blockIdx.x;
     const uint4 TA = G.gtask[2 * task], TB = G.gtask[2 * task + 1];
     const uint32_t cq = TA.x, p_lo = TA.y, p_hi = TA.z, nt = TA.w >> 16;
@@ -213,12 +234,11 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
     const uint2* __restrict__ sccol = G.sc_cnt + (size_t)cq * k;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const GatherLds L = gather_layout(SUM, Q);
+    const GatherLds L = gather_layout(PROG, Q);
     uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
     uint16_t* tag = reinterpret_cast<uint16_t*>(smem + L.tag);
-    uint8_t* hit = smem + L.flag_a;     // min programs: value decreased
-    uint8_t* carry = smem + L.flag_b;   // kept active by initFunc
+    uint8_t* carry = smem + L.carry;   // kept active by initFunc
     uint32_t* bl_ioff = reinterpret_cast<uint32_t*>(smem + L.bl_ioff);
     uint32_t* bl_icnt = reinterpret_cast<uint32_t*>(smem + L.bl_icnt);
     uint32_t* bl_moff = reinterpret_cast<uint32_t*>(smem + L.bl_moff);  // bit 31: SC bin
@@ -256,8 +276,7 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
     for (uint32_t u = tid; u < Q; u += kGT) {
         if constexpr (SUM) acc[u] = 0ull;
         else st32[u] = (!split && u < nv) ? state[vbase + u] : 0xFFFFFFFFu;
-        hit[u] = 0;
-        carry[u] = 0;
+        if constexpr (has_carry(PROG)) carry[u] = 0;
     }
     __syncthreads();
     if (!split) {
@@ -265,7 +284,7 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
         __syncthreads();
     }
 
-    // ---- gather the task's pieces
+    // ---- gather the task's pieces, bins in windows of kGT source partitions
     uint32_t my_ids = 0;
     uint32_t sp_run = 0;  // static pieces of the bins before the current window
     for (uint32_t p0 = p_lo; p0 <= p_hi; p0 += kGT) {
@@ -330,87 +349,109 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
             bl_jlo[b] = jlo;
             bl_scan[b] = poff + pincl - npieces;
         }
+        if (tid == 0) bl_scan[nb] = npt;  // sentinel
         __syncthreads();
 
-        for (uint32_t r0 = 0; r0 < npt; r0 += kGW) {
-            const uint32_t pid = r0 + wave;
-            uint32_t dst[4], val[4];
-            unsigned long long fx[4];
+        // every wave takes a contiguous run of pieces; rounds of PPW pieces
+        // per wave, then all waves combine
+        const uint32_t per_w = (npt + kGW - 1) / kGW;
+        const uint32_t pw0 = min(wave * per_w, npt), pw1 = min(pw0 + per_w, npt);
+        uint32_t bcur = 0;
+        {
+            uint32_t lo = 0, hi = nb ? nb : 1u;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (bl_scan[mid] <= pw0) lo = mid; else hi = mid;
+            }
+            bcur = lo;
+        }
+        const uint32_t nrounds = (per_w + PPW - 1) / PPW;
+        for (uint32_t r = 0; r < nrounds; ++r) {
+            uint32_t dst[4 * PPW], val[4 * PPW];
+            unsigned long long fx[SUM ? 4 * PPW : 1];
             uint32_t pend = 0;
-            if (pid < npt) {
-                // bin holding piece pid: last b with bl_scan[b] <= pid
-                uint32_t lo = 0, hi = nb;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (bl_scan[mid] <= pid) lo = mid; else hi = mid;
-                }
-                const uint32_t b = lo;
+            uint64_t raw[PPW];
+            uint32_t wts[PPW], lo_x[PPW], hi_x[PPW], x0[PPW], mb[PPW], bmoff[PPW], bmcnt[PPW];
+            // phase 1: piece metadata, id / weight / chunk-base loads
+#pragma unroll
+            for (uint32_t pi = 0; pi < PPW; ++pi) {
+                const uint32_t pid = pw0 + r * PPW + pi;
+                const bool live = pid < pw1;
+                if (live)
+                    while (pid >= bl_scan[bcur + 1]) ++bcur;
+                const uint32_t b = bcur;
                 const uint32_t bioff = bl_ioff[b], bicnt = bl_icnt[b], bmo = bl_moff[b];
-                const uint32_t bmcnt = bl_mcnt[b];
+                bmcnt[pi] = bl_mcnt[b];
                 const bool sc = bmo & 0x80000000u;
-                const uint32_t bmoff = bmo & 0x7FFFFFFFu;
+                bmoff[pi] = bmo & 0x7FFFFFFFu;
                 const uint32_t c = bioff / kChunk + bl_jlo[b] + (pid - bl_scan[b]);
-                const uint32_t lo_x = max(bioff, c * kChunk);
-                const uint32_t hi_x = min(bioff + bicnt, c * kChunk + kChunk);
-                const uint16_t* __restrict__ ids = sc ? G.sc_ids : G.png_ids;
-                const uint32_t mbase = (lo_x == bioff) ? 0u : (sc ? G.sc_chunk[c] : G.png_chunk[c]);
-                const uint32_t x0 = c * kChunk + lane * 4u;
-                uint64_t raw = 0;
-                if (x0 + 3u >= lo_x && x0 < hi_x)
-                    raw = *reinterpret_cast<const uint64_t*>(ids + x0);
-                uint32_t wts = 0;
-                if constexpr (is_weighted(PROG)) {
-                    if (x0 + 3u >= lo_x && x0 < hi_x)
-                        wts = *reinterpret_cast<const uint32_t*>((sc ? G.sc_w : G.png_w) + x0);
-                }
+                lo_x[pi] = max(bioff, c * kChunk);
+                hi_x[pi] = live ? min(bioff + bicnt, c * kChunk + kChunk) : 0u;
+                x0[pi] = c * kChunk + lane * 4u;
+                const bool any4 = x0[pi] + 3u >= lo_x[pi] && x0[pi] < hi_x[pi];
+                raw[pi] = any4 ? *reinterpret_cast<const uint64_t*>((sc ? G.sc_ids : G.png_ids) + x0[pi]) : 0ull;
+                wts[pi] = 0;
+                if constexpr (is_weighted(PROG))
+                    wts[pi] = any4 ? *reinterpret_cast<const uint32_t*>((sc ? G.sc_w : G.png_w) + x0[pi]) : 0u;
+                mb[pi] = (live && lo_x[pi] != bioff) ? (sc ? G.sc_chunk[c] : G.png_chunk[c]) : 0u;
+            }
+            // phase 2: message indices and value loads
+            uint32_t vmaskall = 0;
+#pragma unroll
+            for (uint32_t pi = 0; pi < PPW; ++pi) {
                 uint32_t vmask = 0, fmask = 0, fc = 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const uint32_t x = x0 + j;
-                    const uint32_t id = (uint32_t)(raw >> (16 * j)) & 0xFFFFu;
-                    const bool v = x >= lo_x && x < hi_x;
-                    const bool f = v && x > lo_x && (id & kFlag);
+                    const uint32_t x = x0[pi] + j;
+                    const uint32_t id = (uint32_t)(raw[pi] >> (16 * j)) & 0xFFFFu;
+                    const bool v = x >= lo_x[pi] && x < hi_x[pi];
+                    const bool f = v && x > lo_x[pi] && (id & kFlag);
                     vmask |= (uint32_t)v << j;
                     fmask |= (uint32_t)f << j;
                     fc += f;
-                    dst[j] = id & kLocalMask;
+                    dst[4 * pi + j] = id & kLocalMask;
                 }
-                uint32_t midx = mbase + wave_excl_small(fc);
+                uint32_t midx = mb[pi] + wave_excl_small(fc);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     midx += (fmask >> j) & 1u;
-                    if (((vmask >> j) & 1u) && (midx >= bmcnt || dst[j] >= nv)) {
+                    const bool ok = (vmask >> j) & 1u;
+                    if (ok && (midx >= bmcnt[pi] || dst[4 * pi + j] >= nv)) {
                         G.ctrl->bug = 1;  // inconsistent bin: never read or write out of range
                         vmask &= ~(1u << j);
                     }
-                    if ((vmask >> j) & 1u) {
-                        uint32_t x = G.data[bmoff + midx];
-                        if (x != IDENT) {
-                            if constexpr (is_weighted(PROG)) x = sat_add(x, (wts >> (8 * j)) & 0xFFu);
-                            val[j] = x;
-                            if constexpr (SUM)
-                                fx[j] = __double2ull_rn((double)__uint_as_float(x) * kFix);
-                            pend |= 1u << j;
-                            ++my_ids;
-                        }
-                    }
+                    val[4 * pi + j] = ((vmask >> j) & 1u) ? G.data[bmoff[pi] + midx] : IDENT;
+                }
+                vmaskall |= vmask << (4 * pi);
+            }
+            // phase 3: drop identity messages, apply weights, convert sums
+#pragma unroll
+            for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                uint32_t x = val[j];
+                if (((vmaskall >> j) & 1u) && x != IDENT) {
+                    if constexpr (is_weighted(PROG)) x = sat_add(x, (wts[j / 4] >> (8 * (j % 4))) & 0xFFu);
+                    val[j] = x;
+                    if constexpr (SUM) fx[j] = __double2ull_rn((double)__uint_as_float(x) * kFix);
+                    pend |= 1u << j;
+                    ++my_ids;
                 }
             }
             if constexpr (!SUM) {
                 // write-verify rounds for the min combine
+                // A lane whose value is not below the word it reads is done
+                // for good (words only decrease); only lanes that wrote must
+                // check, after the barrier, that their write survived.
                 for (;;) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (uint32_t j = 0; j < 4 * PPW; ++j) {
                         if ((pend >> j) & 1u) {
-                            if (val[j] < st32[dst[j]]) {
-                                st32[dst[j]] = val[j];
-                                hit[dst[j]] = 1;
-                            }
+                            if (val[j] < st32[dst[j]]) st32[dst[j]] = val[j];
+                            else pend &= ~(1u << j);
                         }
                     }
                     __syncthreads();
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (uint32_t j = 0; j < 4 * PPW; ++j)
                         if (((pend >> j) & 1u) && !(val[j] < st32[dst[j]])) pend &= ~(1u << j);
                     if (!__syncthreads_or(pend != 0)) break;
                 }
@@ -418,12 +459,12 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
                 // tagged rounds for the exact fixed-point sum
                 for (;;) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if ((pend >> j) & 1u) tag[dst[j]] = (uint16_t)(tid * 4u + j);
+                    for (uint32_t j = 0; j < 4 * PPW; ++j)
+                        if ((pend >> j) & 1u) tag[dst[j]] = (uint16_t)(tid * 4u * PPW + j);
                     __syncthreads();
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if (((pend >> j) & 1u) && tag[dst[j]] == (uint16_t)(tid * 4u + j)) {
+                    for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                        if (((pend >> j) & 1u) && tag[dst[j]] == (uint16_t)(tid * 4u * PPW + j)) {
                             acc[dst[j]] += fx[j];
                             pend &= ~(1u << j);
                         }
@@ -445,25 +486,26 @@ __global__ __launch_bounds__(kGT) void k_gather(Dev G, Params P, uint32_t* __res
             for (uint32_t u = tid; u < nv; u += kGT) out[u] = st32[u];
         }
         const uint64_t ids64 = wave_sum_u64((uint64_t)my_ids);
-        if (lane == 0) sh.r64[1][wave] = ids64;
+        if (lane == 0) sh.r64[wave] = ids64;
         __syncthreads();
         if (tid == 0) {
             uint64_t ni = 0;
-            for (uint32_t w = 0; w < kGW; ++w) ni += sh.r64[1][w];
+            for (uint32_t w = 0; w < kGW; ++w) ni += sh.r64[w];
             G.gflag[slot] = 1;
             G.gat_ids[task] = (uint32_t)ni;
         }
         return;
     }
-    finish_partition<PROG>(G, P, state, it, cq, st32, acc, hit, carry, sh, my_ids, task);
+    finish_partition<PROG>(G, P, state, it, cq, st32, acc, carry,
+                           reinterpret_cast<uint64_t*>(bl_ioff), sh, my_ids, task);
 }
 
 // Merge of a partition whose gather was split over several tasks: combines
 // the partial results (min, or exact fixed-point sum) with the state, then
 // runs reInit and the filter like a single-task gather.
 template <int PROG>
-__global__ __launch_bounds__(kGT) void k_merge(Dev G, Params P, uint32_t* __restrict__ state,
-                                               uint32_t it) {
+__global__ __launch_bounds__(kGT, 2) void k_merge(Dev G, Params P, uint32_t* __restrict__ state,
+                                                  uint32_t it) {
     if (G.ctrl->done) return;
     constexpr bool SUM = is_sum(PROG);
     const uint4 S = G.gsplit[blockIdx.x];
@@ -472,11 +514,10 @@ __global__ __launch_bounds__(kGT) void k_merge(Dev G, Params P, uint32_t* __rest
     const uint32_t vbase = cq << G.s;
     const uint32_t nv = min(Q, G.V - vbase);
     extern __shared__ __align__(16) unsigned char smem[];
-    const GatherLds L = gather_layout(SUM, Q);
+    const GatherLds L = gather_layout(PROG, Q);
     uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
-    uint8_t* hit = smem + L.flag_a;
-    uint8_t* carry = smem + L.flag_b;
+    uint8_t* carry = smem + L.carry;
     __shared__ GatherShared sh;
     __shared__ uint32_t s_flag[64];
     for (uint32_t j = threadIdx.x; j < 64; j += kGT) s_flag[j] = j < nt ? G.gflag[slot0 + j] : 0u;
@@ -497,8 +538,7 @@ __global__ __launch_bounds__(kGT) void k_merge(Dev G, Params P, uint32_t* __rest
         if (threadIdx.x == 0) G.gat_ran[G.n_gtask + blockIdx.x] = 3;
     }
     for (uint32_t u = threadIdx.x; u < Q; u += kGT) {
-        carry[u] = 0;
-        hit[u] = 0;
+        if constexpr (has_carry(PROG)) carry[u] = 0;
         if constexpr (SUM) acc[u] = 0ull;
         else st32[u] = u < nv ? state[vbase + u] : 0xFFFFFFFFu;
     }
@@ -507,24 +547,58 @@ __global__ __launch_bounds__(kGT) void k_merge(Dev G, Params P, uint32_t* __rest
     for (uint32_t j = 0; j < nt; ++j) written |= (s_flag[j] ? 1ull : 0ull) << j;
     reinit<PROG>(G, P, it, cq, st32, carry);  // initFunc sees the values from before gather
     __syncthreads();
-    for (uint32_t u = threadIdx.x; u < nv; u += kGT) {
+    // every thread owns up to kMU vertices (u = tid + kGT * i); for each
+    // written partial it loads all of them at once
+    constexpr uint32_t kMU = 16;
+    for (uint32_t ub = 0; ub < nv; ub += kGT * kMU) {
         if constexpr (SUM) {
-            unsigned long long a = 0;
+            unsigned long long a[kMU];
+#pragma unroll
+            for (uint32_t i = 0; i < kMU; ++i) a[i] = 0ull;
             const unsigned long long* part = reinterpret_cast<const unsigned long long*>(G.gpart);
-            for (uint32_t j = 0; j < nt; ++j)
-                if ((written >> j) & 1u) a += part[(size_t)(slot0 + j) * Q + u];
-            acc[u] = a;
+            for (uint32_t j = 0; j < nt; ++j) {
+                if (!((written >> j) & 1u)) continue;
+                const unsigned long long* pj = part + (size_t)(slot0 + j) * Q;
+#pragma unroll
+                for (uint32_t i = 0; i < kMU; ++i) {
+                    const uint32_t u = ub + threadIdx.x + kGT * i;
+                    if (u < nv) a[i] += pj[u];
+                }
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < kMU; ++i) {
+                const uint32_t u = ub + threadIdx.x + kGT * i;
+                if (u < nv) acc[u] = a[i];
+            }
         } else {
-            const uint32_t orig = st32[u];
-            uint32_t m = orig;
-            for (uint32_t j = 0; j < nt; ++j)
-                if ((written >> j) & 1u) m = min(m, G.gpart[(size_t)(slot0 + j) * 2 * Q + u]);
-            st32[u] = m;
-            hit[u] = m < orig;
+            uint32_t m[kMU];
+#pragma unroll
+            for (uint32_t i = 0; i < kMU; ++i) {
+                const uint32_t u = ub + threadIdx.x + kGT * i;
+                m[i] = u < nv ? st32[u] : 0u;
+            }
+            for (uint32_t j = 0; j < nt; ++j) {
+                if (!((written >> j) & 1u)) continue;
+                const uint32_t* pj = G.gpart + (size_t)(slot0 + j) * 2 * Q;
+                uint32_t x[kMU];
+#pragma unroll
+                for (uint32_t i = 0; i < kMU; ++i) {
+                    const uint32_t u = ub + threadIdx.x + kGT * i;
+                    x[i] = u < nv ? pj[u] : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (uint32_t i = 0; i < kMU; ++i) m[i] = min(m[i], x[i]);
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < kMU; ++i) {
+                const uint32_t u = ub + threadIdx.x + kGT * i;
+                if (u < nv) st32[u] = m[i];
+            }
         }
     }
     __syncthreads();
-    finish_partition<PROG>(G, P, state, it, cq, st32, acc, hit, carry, sh, 0, 0xFFFFFFFFu);
+    finish_partition<PROG>(G, P, state, it, cq, st32, acc, carry,
+                           reinterpret_cast<uint64_t*>(smem + L.bl_ioff), sh, 0, 0xFFFFFFFFu);
 }
 
 template <int PROG>

@@ -7,6 +7,7 @@ namespace gpop {
 
 // preprocessing (png.hip)
 hipError_t launch_validate(const Dev& G, hipStream_t st);
+hipError_t launch_validate_edges(const Dev& G, hipStream_t st);
 hipError_t launch_part_E(const Dev& G, hipStream_t st);
 hipError_t launch_scan_excl(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* tmp,
                             hipStream_t st);

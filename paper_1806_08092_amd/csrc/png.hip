@@ -8,7 +8,9 @@ namespace gpop {
 // Error codes written to Ctrl::csr_err (plain stores: any writer sets it).
 // 1 offsets[0] != 0, 2 decreasing offsets or offsets beyond E,
 // 3 offsets[V] != E, 4 column >= V, 5 row not sorted ascending.
-__global__ void k_validate(Dev G) {
+// Vertex pass: offsets, and a row-start mark for every non-empty row in a
+// byte array over the edges (marks start at zero).
+__global__ void k_validate_rows(Dev G, uint8_t* __restrict__ rowstart) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= G.V) return;
     const uint32_t a = G.off[v], b = G.off[v + 1];
@@ -18,23 +20,37 @@ __global__ void k_validate(Dev G) {
         return;
     }
     if (v == G.V - 1 && (uint64_t)b != G.E) G.ctrl->csr_err = 3;
-    uint32_t prev = 0;
-    for (uint32_t e = a; e < b; ++e) {
+    if (b > a) rowstart[a] = 1;
+}
+
+// Edge pass: every column < V, and non-decreasing inside each row.
+__global__ void k_validate_edges(Dev G, const uint8_t* __restrict__ rowstart) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < G.E;
+         e += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t c = G.cols[e];
-        if (c >= G.V) {
-            G.ctrl->csr_err = 4;
-            return;
-        }
-        if (e > a && c < prev) {
-            G.ctrl->csr_err = 5;
-            return;
-        }
-        prev = c;
+        if (c >= G.V) G.ctrl->csr_err = 4;
+        else if (e > 0 && !rowstart[e] && G.cols[e - 1] > c) G.ctrl->csr_err = 5;
     }
 }
 
+__global__ void k_zero_u8(uint8_t* __restrict__ p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// The edge pass runs only when the offsets are valid (checked by the caller
+// between the two launches), so every row index it reads is in range.
 hipError_t launch_validate(const Dev& G, hipStream_t st) {
-    hipLaunchKernelGGL(k_validate, dim3((G.V + 255) / 256), dim3(256), 0, st, G);
+    uint8_t* marks = G.sc_w;  // E_pad bytes, unused until the first iteration
+    hipLaunchKernelGGL(k_zero_u8, dim3(2048), dim3(256), 0, st, marks, G.E);
+    hipLaunchKernelGGL(k_validate_rows, dim3((G.V + 255) / 256), dim3(256), 0, st, G, marks);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_edges(const Dev& G, hipStream_t st) {
+    if (G.E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate_edges, dim3(4096), dim3(256), 0, st, G, G.sc_w);
     return hipGetLastError();
 }
 
