@@ -63,6 +63,42 @@ def run_bytes(stats, q, k, weighted, sum_prog):
 
 
 # ----------------------------------------------------------------- workloads
+KERNEL_SOURCES = {
+    "plan": ["scatter.hip", "gpop_dev.h"],
+    "scatter_sc": ["scatter.hip", "gpop_dev.h"],
+    "scatter_pc": ["scatter.hip", "gpop_dev.h"],
+    "gather": ["gather.hip", "gpop_dev.h"],
+    "merge": ["gather.hip", "gpop_dev.h"],
+}
+
+
+def kernel_source_hash(kname):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kname]:
+        with open(os.path.join(ROOT, "paper_1806_08092_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kname, workload):
+    """HBM bytes per launch of one kernel family from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration.
+    None when there is no summary or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kname, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash(kname):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def load_workload(name):
     import graphgen as gg
     if name == "bfs_cc_rmat22":
@@ -223,6 +259,7 @@ def main():
         }
     dom = max(per_kernel, key=lambda kn: per_kernel[kn]["ms_per_step"])
     ach = per_kernel[dom]["achieved_GBps"]
+    traffic = measured_traffic(dom, args.workload)
     gteps = edges_per_step / (ms_per_step * 1e-3) / 1e9
     out = {
         "metric": "GTEPS (traversed directed CSR edges per second) and % of HBM peak per kernel",
@@ -243,22 +280,24 @@ def main():
                    "runs_per_step": len(runs), "iterations_per_run": iters_per_run,
                    "edges_traversed_per_step": edges_per_step, "preprocess_ms": prep_ms},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS, "traffic": None},
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS, "traffic": traffic,
+                     "alg_bytes_per_launch": bytes_step[dom] / per_kernel[dom]["launches_per_step"]},
         "per_kernel": per_kernel,
     }
     if args.copy_mib:
-        # a plain device-to-device copy of known size: the measured ceiling,
-        # and the reference that scales rocprofv3 FETCH_SIZE / WRITE_SIZE
+        # a plain elementwise copy kernel of known size (reads and writes
+        # 4n bytes): the measured ceiling, and the reference that scales
+        # rocprofv3 FETCH_SIZE / WRITE_SIZE
         n = args.copy_mib << 18
         a = torch.empty(n, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1)
-        b.copy_(a)
+        torch.bitwise_not(a, out=b)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(5):
-            b.copy_(a)
+            torch.bitwise_not(a, out=b)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
