@@ -180,3 +180,15 @@ def workload_sssp_er24() -> Graph:
 
 
 SOURCE_SEED = BASE_SEED + 6
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Seeded He-normal initial weights of the selector network (12 -> 64 ->
+    64 -> 1), biases zero, in the parameter order W1[64][12], b1[64],
+    W2[64][64], b2[64], w3[64], b3. float32 [5057]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w1 = rng.standard_normal(64 * 12) * np.sqrt(2.0 / 12)
+    w2 = rng.standard_normal(64 * 64) * np.sqrt(2.0 / 64)
+    w3 = rng.standard_normal(64) * np.sqrt(2.0 / 64)
+    z = np.zeros(64)
+    return np.concatenate([w1, z, w2, z, w3, [0.0]]).astype(np.float32)
