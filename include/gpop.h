@@ -30,6 +30,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "gpop_mlp.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -185,10 +187,34 @@ int gpop_set_frontier_all(struct gpop_graph* g, void* stream);
 /* Mode selection per partition (performance-modelling section). bw_ratio is
  * BW_PC / BW_SC (the paper's default is 2). s_i / s_v are the index and value
  * sizes in bytes used by the model (the paper uses 4 and 4). For
- * GPOP_SEL_LEARNED, d_mlp is a device buffer of GPOP_MLP_PARAMS bf16 weights
- * in the layout of gpop_mlp.h; NULL keeps the analytical model. */
+ * GPOP_SEL_LEARNED, d_mlp is a device gpop_mlp_model (gpop_mlp.h); the call
+ * copies it into the graph's workspace (synchronously), so the caller may
+ * free or retrain it afterwards. A model whose header is wrong or whose
+ * values are not finite is rejected with GPOP_EINVAL and the previous
+ * selector stays active; NULL with GPOP_SEL_LEARNED selects the analytical
+ * model. bw_ratio, s_i and s_v also feed the learned model's last feature
+ * and its analytical fallback. */
 int gpop_set_selector(struct gpop_graph* g, gpop_selector kind, float bw_ratio,
                       uint32_t s_i, uint32_t s_v, const void* d_mlp);
+
+/* Per-partition features of the learned selector (gpop_mlp.h) for the
+ * current frontier and iteration: writes k x GPOP_MLP_IN floats (row p =
+ * partition p) to d_out. Partitions without active vertices get their
+ * features too (V_a = E_a = 0). */
+int gpop_features(struct gpop_graph* g, float* d_out, void* stream);
+
+/* Measures what scattering the current frontier costs in one mode, without
+ * changing the run: plans every active partition in mode `kind`
+ * (GPOP_SEL_FORCE_SC or GPOP_SEL_FORCE_PC), runs that mode's scatter kernels
+ * with per-task timers, and splits the measured kernel time over the
+ * partitions in proportion to the wave time their tasks took. Writes k
+ * floats (microseconds; 0 for partitions without active vertices) to h_us
+ * and the whole scatter time to *h_total_us (either may be NULL).
+ * Synchronises `stream`. The bins it writes are overwritten by the next
+ * gpop_scatter, and the iteration records are unaffected. Errors:
+ * GPOP_EINVAL for another kind, GPOP_ESTATE before gpop_state_init. */
+int gpop_probe_scatter(struct gpop_graph* g, gpop_selector kind, float* h_us, float* h_total_us,
+                       void* stream);
 
 /* -------------------------------------------------------------- iteration */
 

@@ -14,7 +14,8 @@ from typing import Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgpop.so")
-HEADER = os.path.join(os.path.dirname(HERE), "include", "gpop.h")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+HEADERS = [os.path.join(INCLUDE, "gpop.h"), os.path.join(INCLUDE, "gpop_mlp.h")]
 
 # status codes
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTSUP = range(6)
@@ -28,6 +29,9 @@ SELECTORS = {"analytical": SEL_ANALYTICAL, "sc": SEL_FORCE_SC, "pc": SEL_FORCE_P
              "learned": SEL_LEARNED}
 MODE_NONE, MODE_SC, MODE_PC = 0, 1, 2
 KERNELS = ["plan", "scatter_sc", "scatter_pc", "gather", "merge"]
+# learned selector (include/gpop_mlp.h)
+MLP_IN, MLP_HIDDEN, MLP_PARAMS, MLP_MODEL_BYTES = 12, 64, 5057, 10240
+MLP_MAGIC = 0x504C4D47
 
 
 class GpopError(RuntimeError):
@@ -114,6 +118,20 @@ _SIGS = {
     "gpop_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "gpop_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
+    "gpop_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_probe_scatter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
+    "gpop_mlp_init": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_uint32, ctypes.c_void_p]),
+    "gpop_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_mlp_grad_workspace": (ctypes.c_size_t, [ctypes.c_uint32]),
+    "gpop_mlp_grad": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_uint32] + [ctypes.c_void_p] * 3
+                      + [ctypes.c_size_t, ctypes.c_void_p]),
+    "gpop_mlp_adam": (ctypes.c_int, [ctypes.c_void_p] * 5 + [ctypes.c_uint32, ctypes.c_float,
+                                                             ctypes.c_void_p]),
+    "gpop_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_uint32, ctypes.c_uint32,
+                                                                   ctypes.c_float]
+                            + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 
@@ -133,9 +151,9 @@ def lib():
 
 
 def header_symbols() -> Sequence[str]:
-    """Function names declared in include/gpop.h."""
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(gpop_\w+)\s*\(", text, re.M)))
+    """Function names declared in include/*.h."""
+    text = "".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(gpop_\w+)\s*\(", text, re.M)))
 
 
 def _check(rc: int):
@@ -226,6 +244,24 @@ class Graph:
         kind = SELECTORS[kind] if isinstance(kind, str) else int(kind)
         _check(lib().gpop_set_selector(self.h, kind, bw_ratio, s_i, s_v, _ptr(mlp)))
 
+    def features(self, stream=None):
+        """k x 12 float32 CUDA tensor of the learned selector's features."""
+        import torch
+        out = torch.empty((self.k, MLP_IN), dtype=torch.float32, device="cuda")
+        _check(lib().gpop_features(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def probe_scatter(self, kind, stream=None):
+        """Per-partition scatter time (us, numpy float32 [k]) of the current
+        frontier in mode `kind` ("sc" or "pc"), and the whole scatter time."""
+        import numpy as np
+        kind = SELECTORS[kind] if isinstance(kind, str) else int(kind)
+        out = np.zeros(self.k, dtype=np.float32)
+        tot = ctypes.c_float()
+        _check(lib().gpop_probe_scatter(self.h, kind, ctypes.c_void_p(out.ctypes.data),
+                                        ctypes.byref(tot), _stream(stream)))
+        return out, tot.value
+
     def scatter(self, stream=None):
         _check(lib().gpop_scatter(self.h, _stream(stream)))
 
@@ -275,6 +311,62 @@ class Graph:
         n = (ctypes.c_uint64 * nk)()
         _check(lib().gpop_profile_read(self.h, ms, n, _stream(stream)))
         return {KERNELS[i]: (ms[i], int(n[i])) for i in range(nk)}
+
+
+class Mlp:
+    """Device buffers of one learned-selector model (include/gpop_mlp.h):
+    the model the selector reads, f32 masters, Adam moments, the last
+    gradient and loss. Every computation runs in the library's kernels."""
+
+    def __init__(self):
+        import torch
+        self.model = torch.zeros(MLP_MODEL_BYTES // 4, dtype=torch.int32, device="cuda")
+        self.master = torch.zeros(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.grad = torch.zeros_like(self.master)
+        self.loss = torch.zeros(2, dtype=torch.float32, device="cuda")
+        self.ws = None
+        self.step = 0
+
+    def init(self, init_params, x, stream=None):
+        """init_params: f32 [5057] CUDA tensor; x: n x 12 training features."""
+        _check(lib().gpop_mlp_init(_ptr(self.model), _ptr(self.master), _ptr(self.m), _ptr(self.v),
+                                   _ptr(init_params), _ptr(x), x.shape[0], _stream(stream)))
+        self.step = 0
+
+    def forward(self, x, stream=None):
+        import torch
+        out = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().gpop_mlp_forward(_ptr(self.model), _ptr(x), x.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def _workspace(self, n):
+        import torch
+        need = lib().gpop_mlp_grad_workspace(n)
+        if self.ws is None or self.ws.numel() * 4 < need:
+            self.ws = torch.empty((need + 3) // 4, dtype=torch.float32, device="cuda")
+        return self.ws
+
+    def compute_grad(self, x, t_sc, t_pc, stream=None):
+        ws = self._workspace(x.shape[0])
+        _check(lib().gpop_mlp_grad(_ptr(self.model), _ptr(x), _ptr(t_sc), _ptr(t_pc), x.shape[0],
+                                   _ptr(self.grad), _ptr(self.loss), _ptr(ws), ws.numel() * 4,
+                                   _stream(stream)))
+        return self.grad
+
+    def adam(self, lr=1e-3, stream=None):
+        self.step += 1
+        _check(lib().gpop_mlp_adam(_ptr(self.model), _ptr(self.master), _ptr(self.m), _ptr(self.v),
+                                   _ptr(self.grad), self.step, lr, _stream(stream)))
+
+    def train_step(self, x, t_sc, t_pc, lr=1e-3, stream=None):
+        ws = self._workspace(x.shape[0])
+        self.step += 1
+        _check(lib().gpop_mlp_train_step(_ptr(self.model), _ptr(self.master), _ptr(self.m), _ptr(self.v),
+                                         _ptr(x), _ptr(t_sc), _ptr(t_pc), x.shape[0], self.step, lr,
+                                         _ptr(self.grad), _ptr(self.loss), _ptr(ws), ws.numel() * 4,
+                                         _stream(stream)))
 
 
 def upload_csr(g, device="cuda"):

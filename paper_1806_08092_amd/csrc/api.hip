@@ -19,6 +19,10 @@ constexpr uint32_t kPcTask = 32768;  // message slots per partition-centric task
 
 thread_local std::string g_err;
 
+}  // namespace
+
+namespace gpop {
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -33,11 +37,10 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(GPOP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_OR_RETURN(expr, what)                       \
-    do {                                                \
-        hipError_t e_ = (expr);                         \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
+}  // namespace gpop
+
+namespace {
+
 
 struct Pending {
     int kid;
@@ -148,6 +151,11 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z) {
     G->scan_tmp = (uint32_t*)take(scan_tmp_words(kk) * 4);
     G->ctrl = (Ctrl*)take(sizeof(Ctrl));
     G->log = (gpop_iter_stats*)take(kLogCap * sizeof(gpop_iter_stats));
+    G->pfill = (float*)take(k * 4);
+    G->pskew = (float*)take(k * 4);
+    G->mode_l = (uint8_t*)take(k);
+    G->mlp = (gpop_mlp_model*)take(sizeof(gpop_mlp_model));
+    G->probe = (unsigned long long*)take(3 * k * 8);
     return o;
 }
 
@@ -390,6 +398,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     if (!gs.empty())
         HIP_OR_RETURN(hipMemcpyAsync(G.gsplit, gs.data(), gs.size() * sizeof(uint4), hipMemcpyHostToDevice,
                                      st), "write split list");
+    HIP_OR_RETURN(launch_part_static(G, st), "partition features");
     Ctrl hc2;
     HIP_OR_RETURN(hipMemcpyAsync(&hc2, G.ctrl, sizeof hc2, hipMemcpyDeviceToHost, st), "read control");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
@@ -482,14 +491,82 @@ int gpop_set_selector(gpop_graph* g, gpop_selector kind, float bw_ratio, uint32_
     if (!(bw_ratio > 0.f) || !std::isfinite(bw_ratio) || bw_ratio > 1e6f)
         return fail(GPOP_EINVAL, "bw_ratio must be finite and > 0");
     if (s_i < 1 || s_i > 16 || s_v < 1 || s_v > 16) return fail(GPOP_EINVAL, "s_i, s_v in [1, 16]");
+    if (kind == GPOP_SEL_LEARNED && d_mlp) {
+        // validate on the host, then keep a private copy in the workspace
+        gpop_mlp_model h;
+        HIP_OR_RETURN(hipMemcpy(&h, d_mlp, sizeof h, hipMemcpyDeviceToHost), "read model");
+        if (h.magic != GPOP_MLP_MAGIC || h.n_params != GPOP_MLP_PARAMS)
+            return fail(GPOP_EINVAL, "not a gpop_mlp_model (bad magic or parameter count)");
+        for (int i = 0; i < GPOP_MLP_IN; ++i)
+            if (!std::isfinite(h.mean[i]) || !std::isfinite(h.inv_std[i]) || !(h.inv_std[i] > 0.f))
+                return fail(GPOP_EINVAL, "model standardisation %d is not finite and positive", i);
+        for (int j = 0; j < GPOP_MLP_PARAMS; ++j)
+            if ((h.w[j] & 0x7F80u) == 0x7F80u) return fail(GPOP_EINVAL, "model weight %d is not finite", j);
+        HIP_OR_RETURN(hipMemcpy(g->G.mlp, &h, sizeof h, hipMemcpyHostToDevice), "write model");
+    }
     g->P.selector = (uint32_t)kind;
     g->P.ratio_num = (uint32_t)std::lround((double)bw_ratio * 1024.0);
     if (g->P.ratio_num == 0) g->P.ratio_num = 1;
     g->P.ratio_den = 1024;
     g->P.s_i = s_i;
     g->P.s_v = s_v;
-    g->P.mlp = (const uint16_t*)d_mlp;
     if (kind == GPOP_SEL_LEARNED && !d_mlp) g->P.selector = GPOP_SEL_ANALYTICAL;
+    return GPOP_OK;
+}
+
+int gpop_features(gpop_graph* g, float* d_out, void* stream) {
+    if (!g || !d_out) return fail(GPOP_EINVAL, "NULL argument");
+    HIP_OR_RETURN(launch_features(g->G, g->P, g->it, d_out, (hipStream_t)stream), "features");
+    return GPOP_OK;
+}
+
+int gpop_probe_scatter(gpop_graph* g, gpop_selector kind, float* h_us, float* h_total_us, void* stream) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
+    if (kind != GPOP_SEL_FORCE_SC && kind != GPOP_SEL_FORCE_PC)
+        return fail(GPOP_EINVAL, "probe kind must be GPOP_SEL_FORCE_SC or GPOP_SEL_FORCE_PC");
+    hipStream_t st = (hipStream_t)stream;
+    const Dev& G = g->G;
+    const uint32_t k = G.k;
+    Params P = g->P;
+    P.selector = (uint32_t)kind;
+    P.probe = 1;
+    hipEvent_t ev[4];
+    for (int i = 0; i < 4; ++i) HIP_OR_RETURN(hipEventCreate(&ev[i]), "event");
+    struct Guard {
+        hipEvent_t* e;
+        ~Guard() {
+            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+    HIP_OR_RETURN(launch_fill_u8((uint8_t*)G.probe, 3ull * k * 8, 0, st), "clear probe");
+    HIP_OR_RETURN(launch_plan(G, P, g->it, st), "probe plan");
+    HIP_OR_RETURN(hipEventRecord(ev[0], st), "event");
+    HIP_OR_RETURN(launch_scatter_sc(G, P, g->prog, g->state, g->it, st), "probe scatter SC");
+    HIP_OR_RETURN(hipEventRecord(ev[1], st), "event");
+    HIP_OR_RETURN(hipEventRecord(ev[2], st), "event");
+    HIP_OR_RETURN(launch_scatter_pc(G, P, g->prog, g->state, g->it, st), "probe scatter PC");
+    HIP_OR_RETURN(hipEventRecord(ev[3], st), "event");
+    std::vector<unsigned long long> acc(3ull * k);
+    std::vector<uint32_t> va(k);
+    HIP_OR_RETURN(hipMemcpyAsync(acc.data(), G.probe, acc.size() * 8, hipMemcpyDeviceToHost, st), "read probe");
+    HIP_OR_RETURN(hipMemcpyAsync(va.data(), G.fVa[g->it & 1u], k * 4, hipMemcpyDeviceToHost, st),
+                  "read frontier sizes");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    float ms = 0.f;
+    if (kind == GPOP_SEL_FORCE_SC) HIP_OR_RETURN(hipEventElapsedTime(&ms, ev[0], ev[1]), "elapsed");
+    else HIP_OR_RETURN(hipEventElapsedTime(&ms, ev[2], ev[3]), "elapsed");
+    const double total_us = (double)ms * 1e3;
+    double sum = 0.0;
+    std::vector<double> wt(k, 0.0);
+    for (uint32_t p = 0; p < k; ++p) {
+        if (!va[p]) continue;
+        wt[p] = kind == GPOP_SEL_FORCE_SC ? (double)acc[p] + (double)acc[k + p] : (double)acc[2 * k + p];
+        sum += wt[p];
+    }
+    if (h_us)
+        for (uint32_t p = 0; p < k; ++p) h_us[p] = sum > 0.0 ? (float)(total_us * wt[p] / sum) : 0.f;
+    if (h_total_us) *h_total_us = (float)total_us;
     return GPOP_OK;
 }
 
@@ -498,7 +575,15 @@ int gpop_scatter(gpop_graph* g, void* stream) {
     if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
     hipStream_t st = (hipStream_t)stream;
     int rc;
-    if ((rc = timed(g, GPOP_KERNEL_PLAN, st, [&] { return launch_plan(g->G, g->P, g->it, st); }, "plan")))
+    if ((rc = timed(g, GPOP_KERNEL_PLAN, st,
+                    [&] {
+                        if (g->P.selector == GPOP_SEL_LEARNED) {
+                            hipError_t e = launch_select(g->G, g->P, g->it, st);
+                            if (e != hipSuccess) return e;
+                        }
+                        return launch_plan(g->G, g->P, g->it, st);
+                    },
+                    "plan")))
         return rc;
     if ((rc = timed(g, GPOP_KERNEL_SCATTER_SC, st,
                     [&] { return launch_scatter_sc(g->G, g->P, g->prog, g->state, g->it, st); },

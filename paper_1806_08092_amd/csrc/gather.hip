@@ -688,6 +688,8 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
         G.ctrl->iters = 0;
         G.ctrl->frontier = 0;
         G.ctrl->dangling = 0.0;
+        G.ctrl->fin_it = 0;
+        G.ctrl->mlp_fallback = 0;
     }
 }
 
@@ -706,6 +708,13 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, uint64_t n, uint8_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
 }
 
 __global__ void k_mark(Dev G, const uint32_t* __restrict__ verts, uint32_t n) {

@@ -50,7 +50,9 @@ struct Ctrl {
     uint32_t n_sctask;    // source-centric tasks of the current iteration
     uint64_t frontier;    // sum of V_a at the last plan
     double dangling;      // PageRank-family dangling mass of the current frontier
-    uint32_t pad[54];
+    uint32_t fin_it;      // records below this iteration are final
+    uint32_t mlp_fallback;  // partitions the learned selector left to Eq. 1
+    uint32_t pad[52];
 };
 
 // Everything the kernels read or write, by value in each launch.
@@ -107,6 +109,12 @@ struct Dev {
     uint32_t* scan_tmp;       // scan scratch
     Ctrl* ctrl;
     gpop_iter_stats* log;     // [kLogCap]
+    // learned selector
+    float* pfill;             // [k] non-empty PNG bins of row p / k
+    float* pskew;             // [k] log(max / mean out-degree) of partition p
+    uint8_t* mode_l;          // [k] modes the learned selector picked for the next plan
+    gpop_mlp_model* mlp;      // the selector's copy of the model
+    unsigned long long* probe;  // [3k] wave time of probe tasks: SC count, SC write, PC
 };
 
 // Program parameters and the mode model.
@@ -117,7 +125,7 @@ struct Params {
     uint32_t selector;        // gpop_selector
     uint32_t s_i, s_v;        // model element sizes (bytes)
     uint32_t ratio_num, ratio_den;  // BW_PC / BW_SC as a fraction
-    const uint16_t* mlp;      // bf16 weights or null
+    uint32_t probe;           // scatter kernels time their tasks into Dev::probe
 };
 
 // ------------------------------------------------------------ wave helpers

@@ -5,6 +5,16 @@
 
 namespace gpop {
 
+// error reporting of the C ABI (api.hip): sets gpop_last_error, returns code
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define HIP_OR_RETURN(expr, what)                              \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return ::gpop::hip_fail(e_, what); \
+    } while (0)
+
 // preprocessing (png.hip)
 hipError_t launch_validate(const Dev& G, hipStream_t st);
 hipError_t launch_validate_edges(const Dev& G, hipStream_t st);
@@ -33,6 +43,12 @@ hipError_t launch_gather(const Dev& G, const Params& P, int prog, uint32_t* stat
                          hipStream_t st);
 hipError_t launch_state_init(const Dev& G, const Params& P, int prog, uint32_t* state,
                              hipStream_t st);
+// learned selector (select.hip)
+hipError_t launch_part_static(const Dev& G, hipStream_t st);
+hipError_t launch_select(const Dev& G, const Params& P, uint32_t it, hipStream_t st);
+hipError_t launch_features(const Dev& G, const Params& P, uint32_t it, float* out, hipStream_t st);
+
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st);
 hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all,
                                uint32_t buf, hipStream_t st);
 

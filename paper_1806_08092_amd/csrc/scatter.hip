@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "launch.h"
+#include "select_dev.h"
 
 namespace gpop {
 
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
     uint32_t* ci = lds + wave * 2 * k;
     uint32_t* cm = ci + k;
     for (uint32_t t = blockIdx.x * kScWaves + wave; t < ntask; t += gridDim.x * kScWaves) {
+        const uint64_t t_beg = (!BUILD && P.probe) ? wall_clock64() : 0;
         uint2* __restrict__ tc = G.sc_tc + (size_t)t * k;
         for (uint32_t j = lane; j < k; j += 64) {
             if constexpr (WRITE) {
@@ -189,6 +191,8 @@ __global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
         if constexpr (!WRITE) {
             for (uint32_t j = lane; j < k; j += 64) tc[j] = make_uint2(cm[j], ci[j]);
         }
+        if (!BUILD && P.probe && lane == 0)  // one wave's time, charged to its partition
+            atomicAdd(G.probe + (WRITE ? k : 0) + p, (unsigned long long)(wall_clock64() - t_beg));
     }
 }
 
@@ -345,6 +349,11 @@ __global__ __launch_bounds__(256) void k_pc(Dev G, Params P, const uint32_t* __r
     const uint4 t = G.pctask[blockIdx.x];
     const uint32_t p = t.x;
     if (G.mode[p] != GPOP_MODE_PC) return;
+    uint64_t t_beg = 0;
+    if (P.probe) {
+        __syncthreads();
+        t_beg = wall_clock64();
+    }
     const uint32_t cur = it & 1u;
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
@@ -370,6 +379,11 @@ __global__ __launch_bounds__(256) void k_pc(Dev G, Params P, const uint32_t* __r
         *reinterpret_cast<uint4*>(data + i) = o;
     }
     for (uint32_t i = b4 + threadIdx.x; i < b; i += 256) data[i] = mv[src[i]];
+    if (P.probe) {  // four waves' time, charged to the partition
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicAdd(G.probe + 2 * G.k + p, 4ull * (unsigned long long)(wall_clock64() - t_beg));
+    }
 }
 
 template <int PROG>
@@ -396,26 +410,6 @@ hipError_t launch_scatter_pc(const Dev& G, const Params& P, int prog, const uint
         case P_CARRY: return launch_pc_p<P_CARRY>(G, P, state, it, st);
     }
     return hipErrorInvalidValue;
-}
-
-// ---------------------------------------------------------------------------
-// Mode selection (Sec. 3.2, Eq. 1). With r^p = M^p / E^p the
-// partition-centric volume E^p((r^p+1)s_i + 2 r^p s_v) + k s_i is the integer
-// (M^p + E^p) s_i + 2 M^p s_v + k s_i, and E^p times the source-centric volume
-// 2 r^p E_a s_v + 3 E_a s_i + V_a s_i is 2 M^p E_a s_v + (3 E_a + V_a) s_i E^p.
-// PC is chosen iff cost_PC / BW_PC <= cost_SC / BW_SC, evaluated exactly in
-// 128-bit integers with BW_PC / BW_SC = ratio_num / ratio_den; ties pick PC.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint8_t analytical_mode(const Dev& G, const Params& P, uint32_t p,
-                                                   uint32_t Va, uint32_t Ea) {
-    typedef unsigned __int128 u128;
-    const uint64_t Ep = G.part_E[p], Mp = G.part_M[p];
-    const uint64_t si = P.s_i, sv = P.s_v;
-    const uint64_t cost_pc = (Mp + Ep) * si + 2ull * Mp * sv + (uint64_t)G.k * si;
-    const u128 lhs = (u128)cost_pc * Ep * P.ratio_den;
-    const u128 sc_scaled = (u128)(2ull * sv) * Mp * Ea + (u128)((3ull * Ea + Va) * si) * Ep;
-    const u128 rhs = sc_scaled * P.ratio_num;
-    return lhs <= rhs ? (uint8_t)GPOP_MODE_PC : (uint8_t)GPOP_MODE_SC;
 }
 
 // Fills the stats record of iteration it - 1 (source-centric totals and ids
@@ -458,15 +452,25 @@ __device__ void finalize_prev(const Dev& G, uint32_t it) {
     __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(Dev G, uint32_t it) {
-    if (it > 0) finalize_prev(G, it);
+// Runs finalize_prev once per iteration: a probe scatter or a stats read may
+// come before the plan of the same iteration, and both rewrite what it reads.
+__device__ void finalize_once(const Dev& G, uint32_t it) {
+    __shared__ uint32_t s_need;
+    if (threadIdx.x == 0) s_need = it > 0 && G.ctrl->fin_it < it;
+    __syncthreads();
+    if (s_need) {
+        finalize_prev(G, it);
+        if (threadIdx.x == 0) G.ctrl->fin_it = it;
+    }
 }
+
+__global__ __launch_bounds__(1024) void k_finalize(Dev G, uint32_t it) { finalize_once(G, it); }
 
 __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
     Ctrl* C = G.ctrl;
     if (C->done) return;
     const uint32_t cur = it & 1u;
-    if (it > 0) finalize_prev(G, it);
+    finalize_once(G, it);
     __shared__ uint64_t red[9][16];
     __shared__ double dred[16];
     __shared__ uint32_t s_w[16];
@@ -483,6 +487,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
                 else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
+                else if (P.selector == GPOP_SEL_LEARNED) md = G.mode_l[p];
                 else md = analytical_mode(G, P, p, Va, Ea);
             }
             G.mode[p] = md;
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
         C->dangling = d;
         if (t[0] == 0) {
             C->done = 1;
-        } else {
+        } else if (!P.probe) {
             C->iters = it + 1;
             gpop_iter_stats* r = G.log + (it % kLogCap);
             r->active_vertices = t[0];

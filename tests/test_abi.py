@@ -53,3 +53,26 @@ def test_create_rejects_unaligned_workspace_without_touching_device():
     rc = gp.lib().gpop_graph_create(ctypes.byref(d), ctypes.byref(o), ctypes.c_void_p(0x1000),
                                     16, None, ctypes.byref(h))
     assert rc == gp.ENOMEM
+
+
+def test_selector_entry_points_reject_bad_arguments_on_host():
+    L = gp.lib()
+    fake = ctypes.c_void_p(256)  # never dereferenced: each call fails before any device work
+    assert L.gpop_features(None, fake, None) == gp.EINVAL
+    assert L.gpop_probe_scatter(None, gp.SEL_FORCE_SC, None, None, None) == gp.EINVAL
+    assert L.gpop_mlp_init(None, fake, fake, fake, fake, fake, 10, None) == gp.EINVAL
+    assert L.gpop_mlp_init(fake, fake, fake, fake, fake, fake, 0, None) == gp.EINVAL
+    assert L.gpop_mlp_forward(None, fake, 1, fake, None) == gp.EINVAL
+    assert L.gpop_mlp_grad(fake, fake, fake, fake, 0, fake, None, fake, 1 << 20, None) == gp.EINVAL
+    assert L.gpop_mlp_grad(fake, fake, fake, fake, 100, fake, None, fake, 16, None) == gp.ENOMEM
+    assert L.gpop_mlp_adam(fake, fake, fake, fake, fake, 0, 1e-3, None) == gp.EINVAL
+    assert L.gpop_mlp_adam(fake, fake, fake, fake, fake, 1, -1.0, None) == gp.EINVAL
+    assert b"Adam" in L.gpop_last_error() or b"lr" in L.gpop_last_error()
+
+
+def test_mlp_workspace_size():
+    L = gp.lib()
+    # one partial row (5057 gradients + loss + weight sum) per 64 samples
+    assert L.gpop_mlp_grad_workspace(1) == 5059 * 4
+    assert L.gpop_mlp_grad_workspace(64) == 5059 * 4
+    assert L.gpop_mlp_grad_workspace(65) == 2 * 5059 * 4

@@ -1,0 +1,299 @@
+"""GPU tests of the learned scatter-mode selector through the C-ABI: features,
+the network's forward pass, gradient and Adam against the FP64 oracle
+(oracle/mlp_ref.py), per-partition probe timings, learned mode choices, and
+that the selector never changes results."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle import gpop_ref
+from oracle import mlp_ref as mr
+from gpu_util import make_graph, run_program, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _graphs():
+    return {
+        "rmat10": gg.rmat_graph(10, 8, seed=gg.BASE_SEED + 40),
+        "rmat12_sym": gg.rmat_graph(12, 8, seed=gg.BASE_SEED + 41, symmetric=True),
+        "er": gg.er_graph(3000, 20000, seed=gg.BASE_SEED + 42),
+    }
+
+
+def _model_from_device(mlp):
+    raw = mlp.model.cpu().numpy().view(np.uint8)
+    magic, npar = raw[:8].view(np.uint32)
+    mean = raw[8:56].view(np.float32).astype(np.float64)
+    inv = raw[56:104].view(np.float32).astype(np.float64)
+    wbits = raw[104:104 + 2 * 5057].view(np.uint16).astype(np.uint32) << 16
+    w = wbits.view(np.float32).astype(np.float64)
+    return int(magic), int(npar), mean, inv, w
+
+
+@pytest.mark.parametrize("name", ["rmat10", "rmat12_sym", "er"])
+@pytest.mark.parametrize("lp", [8, 9])
+def test_features_match_oracle_at_start(name, lp):
+    torch = torch_cuda()
+    g = _graphs()[name]
+    G, _ = make_graph(g, lp)
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    G.state_init("bfs", st, root=0)
+    rng = np.random.default_rng(lp)
+    front = np.unique(rng.choice(g.n, g.n // 7, replace=False)).astype(np.int32)
+    G.set_frontier(torch.from_numpy(front).cuda())
+    got = G.features().cpu().numpy().astype(np.float64)
+    want = mr.features(g.offsets, g.cols, 1 << lp, front, 0)
+    assert got.shape == want.shape
+    assert np.allclose(got, want, rtol=2e-6, atol=2e-6), np.max(np.abs(got - want))
+
+
+def test_features_match_oracle_during_bfs():
+    torch = torch_cuda()
+    g = _graphs()["rmat12_sym"]
+    lp = 8
+    G, _ = make_graph(g, lp)
+    root = int(gg.pick_sources(g.offsets, gg.SOURCE_SEED, 1)[0])
+    lv = oracle.bfs_levels(g, root)
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    G.state_init("bfs", st, root=root)
+    G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+    for t in range(int(lv[lv != 0xFFFFFFFF].max()) + 1):
+        got = G.features().cpu().numpy().astype(np.float64)
+        want = mr.features(g.offsets, g.cols, 1 << lp, np.nonzero(lv == t)[0], t)
+        assert np.allclose(got, want, rtol=2e-6, atol=2e-6), (t, np.max(np.abs(got - want)))
+        G.iterate()
+
+
+def test_mlp_init_and_forward_match_oracle():
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    rng = np.random.default_rng(3)
+    X = (rng.standard_normal((1000, 12)) * rng.random(12) * 10 + rng.standard_normal(12)).astype(np.float32)
+    X[:, 4] = 2.5  # a constant column: inv_std = 1e6
+    init = gg.mlp_init_params(17)
+    mlp = gp.Mlp()
+    xt = torch.from_numpy(X).cuda()
+    mlp.init(torch.from_numpy(init).cuda(), xt)
+    magic, npar, mean, inv, w = _model_from_device(mlp)
+    assert magic == gp.MLP_MAGIC and npar == 5057
+    mu, iv = mr.standardisation(X)
+    assert np.allclose(mean, mu, rtol=1e-6, atol=1e-6)
+    assert np.allclose(inv, iv, rtol=1e-6)
+    assert np.array_equal(w, mr.bf16_round(init))
+    assert np.array_equal(mlp.master.cpu().numpy(), init)
+    z = mlp.forward(xt).cpu().numpy().astype(np.float64)
+    zr = mr.forward(w, mean, inv, X)
+    assert np.max(np.abs(z - zr)) <= 1e-4 * max(1.0, np.max(np.abs(zr)))
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 4097])
+def test_mlp_gradient_matches_oracle(n):
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    rng = np.random.default_rng(n)
+    X = (rng.standard_normal((max(n, 2), 12)) * 3).astype(np.float32)[:n]
+    t_sc = (rng.random(n) * 20).astype(np.float32)
+    t_pc = (rng.random(n) * 20).astype(np.float32)
+    mlp = gp.Mlp()
+    xt = torch.from_numpy(X).cuda()
+    Xs = np.vstack([X, X + 1]) if n == 1 else X  # a one-row batch has zero std
+    mlp.init(torch.from_numpy(gg.mlp_init_params(n)).cuda(), torch.from_numpy(np.ascontiguousarray(Xs)).cuda())
+    _, _, mean, inv, w = _model_from_device(mlp)
+    g = mlp.compute_grad(xt, torch.from_numpy(t_sc).cuda(), torch.from_numpy(t_pc).cuda()).cpu().numpy()
+    L, gr = mr.loss_and_grad(w, mean, inv, X, t_sc, t_pc)
+    loss = mlp.loss.cpu().numpy()
+    assert abs(loss[0] - L) <= 1e-4 * max(1.0, abs(L))
+    assert abs(loss[1] - np.abs(t_sc.astype(np.float64) - t_pc).sum()) <= 1e-4 * loss[1]
+    err = np.max(np.abs(g - gr)) / max(np.max(np.abs(gr)), 1e-30)
+    assert err <= 1e-3, err
+
+
+def test_mlp_adam_matches_oracle():
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    init = gg.mlp_init_params(23)
+    mlp = gp.Mlp()
+    X = np.random.default_rng(1).standard_normal((100, 12)).astype(np.float32)
+    mlp.init(torch.from_numpy(init).cuda(), torch.from_numpy(X).cuda())
+    master, m, v = init.astype(np.float64), np.zeros(5057), np.zeros(5057)
+    rng = np.random.default_rng(2)
+    for step in range(1, 5):
+        grad = (rng.standard_normal(5057) * 10.0 ** rng.integers(-6, 1, 5057)).astype(np.float32)
+        mlp.grad.copy_(torch.from_numpy(grad))
+        mlp.adam(lr=1e-2)
+        master, m, v = mr.adam_step(master, m, v, grad.astype(np.float64), step, 1e-2)
+        got = mlp.master.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - master)) <= 1e-5 * max(1.0, np.max(np.abs(master)))
+    _, _, _, _, w = _model_from_device(mlp)
+    assert np.array_equal(w, mr.bf16_round(mlp.master.cpu().numpy()))
+
+
+def test_mlp_training_reduces_loss():
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    rng = np.random.default_rng(5)
+    n = 8192
+    X = rng.standard_normal((n, 12)).astype(np.float32)
+    # PC is faster exactly when feature 11 is negative, by |feature 11|
+    t_sc = (5.0 + np.maximum(-X[:, 11], 0)).astype(np.float32)
+    t_pc = (5.0 + np.maximum(X[:, 11], 0)).astype(np.float32)
+    mlp = gp.Mlp()
+    xt, a, b = (torch.from_numpy(v).cuda() for v in (X, t_sc, t_pc))
+    mlp.init(torch.from_numpy(gg.mlp_init_params(1)).cuda(), xt)
+    mlp.compute_grad(xt, a, b)
+    first = float(mlp.loss[0])
+    for _ in range(300):
+        mlp.train_step(xt, a, b, lr=3e-3)
+    mlp.compute_grad(xt, a, b)
+    last = float(mlp.loss[0])
+    z = mlp.forward(xt).cpu().numpy()
+    acc = np.mean((z >= 0) == (t_pc < t_sc))
+    assert last < 0.5 * first and acc > 0.95, (first, last, acc)
+
+
+def _bfs_with_modes(G, g, root, torch):
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    G.state_init("bfs", st, root=root)
+    G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+    modes = []
+    while G.frontier_size() > 0:
+        G.scatter()
+        modes.append(G.modes())
+        G.gather()
+    return st.cpu().numpy().view(np.uint32), modes
+
+
+def test_learned_modes_follow_the_network_and_results_are_unchanged():
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    g = _graphs()["rmat12_sym"]
+    lp = 8
+    q = 1 << lp
+    G, _ = make_graph(g, lp)
+    root = int(gg.pick_sources(g.offsets, gg.SOURCE_SEED, 1)[0])
+    lv = oracle.bfs_levels(g, root)
+    depth = int(lv[lv != 0xFFFFFFFF].max())
+    # standardise on the features of every BFS frontier, random network
+    F = np.vstack([mr.features(g.offsets, g.cols, q, np.nonzero(lv == t)[0], t) for t in range(depth + 1)])
+    mlp = gp.Mlp()
+    mlp.init(torch.from_numpy(gg.mlp_init_params(99)).cuda(), torch.from_numpy(F.astype(np.float32)).cuda())
+    _, _, mean, inv, w = _model_from_device(mlp)
+    G.set_selector("learned", mlp=mlp.model)
+    state, modes = _bfs_with_modes(G, g, root, torch)
+    assert np.array_equal(state, lv)
+    assert len(modes) == depth + 1
+    png = gpop_ref.build_png(g, q)
+    seen = set()
+    for t, md in enumerate(modes):
+        front = np.nonzero(lv == t)[0]
+        f = mr.features(g.offsets, g.cols, q, front, t)
+        z = mr.forward(w, mean, inv, f)
+        zs = np.abs((f - mean) * inv)
+        for p in range(len(md)):
+            va = int(np.sum(front // q == p))
+            if va == 0:
+                assert md[p] == gp.MODE_NONE
+                continue
+            if np.all(zs[p] <= 6):
+                if abs(z[p]) > 1e-3:
+                    assert md[p] == (gp.MODE_PC if z[p] >= 0 else gp.MODE_SC), (t, p, z[p])
+            else:
+                ea = int(sum(g.offsets[v + 1] - g.offsets[v] for v in front if v // q == p))
+                want = gpop_ref.choose_mode(png.E[p], png.M[p], va, ea, png.k)
+                assert md[p] == (gp.MODE_PC if want == gpop_ref.PC else gp.MODE_SC)
+            seen.add(int(md[p]))
+    assert seen == {gp.MODE_SC, gp.MODE_PC}, "the random network should pick both modes"
+    # PageRank under the learned selector: bitwise equal to the analytical run
+    G.set_selector("analytical")
+    ref, _ = run_program(G, "pagerank", g.n, max_iter=10)
+    G.set_selector("learned", mlp=mlp.model)
+    got, _ = run_program(G, "pagerank", g.n, max_iter=10)
+    assert np.array_equal(ref.view(np.uint32), got.view(np.uint32))
+
+
+def test_set_selector_rejects_bad_models():
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    g = _graphs()["rmat10"]
+    G, _ = make_graph(g, 8)
+    mlp = gp.Mlp()
+    X = np.random.default_rng(0).standard_normal((50, 12)).astype(np.float32)
+    mlp.init(torch.from_numpy(gg.mlp_init_params(3)).cuda(), torch.from_numpy(X).cuda())
+    bad = mlp.model.clone()
+    bad[0] = 0
+    with pytest.raises(gp.GpopError) as e:
+        G.set_selector("learned", mlp=bad)
+    assert e.value.code == gp.EINVAL
+    bad = mlp.model.clone().view(torch.int16)
+    bad[52 + 100] = 0x7FC0  # a NaN weight
+    with pytest.raises(gp.GpopError) as e:
+        G.set_selector("learned", mlp=bad)
+    assert e.value.code == gp.EINVAL
+    G.set_selector("learned", mlp=mlp.model)  # the good one is accepted
+
+
+def test_probe_scatter_times_and_no_side_effects():
+    torch = torch_cuda()
+    g = _graphs()["rmat12_sym"]
+    G, _ = make_graph(g, 8)
+    root = int(gg.pick_sources(g.offsets, gg.SOURCE_SEED, 1)[0])
+    ref, _ = run_program(G, "bfs", g.n, root=root)
+    ref_stats = G.iter_stats()
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    G.state_init("bfs", st, root=root)
+    G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+    n_it = 0
+    while G.frontier_size() > 0:
+        va = np.rint(np.expm1(G.features().cpu().numpy()[:, 0].astype(np.float64)))
+        for kind in ("sc", "pc"):
+            us, tot = G.probe_scatter(kind)
+            assert tot > 0
+            assert np.all(us >= 0) and np.all(us[va == 0] == 0)
+            assert abs(us.sum() - tot) <= 1e-3 * tot + 1e-3
+        G.iterate()
+        n_it += 1
+    G.check()
+    assert np.array_equal(st.cpu().numpy().view(np.uint32), ref)
+    assert G.iter_stats() == ref_stats
+    assert n_it == len(ref_stats)
+
+
+def test_learned_selector_gain_on_held_out_graph():
+    """Trains on probe timings of BFS and PageRank on three RMAT graphs and
+    compares, on a held-out graph, the measured scatter time of the
+    network's choices with Eq. 1's at the paper's ratio."""
+    torch = torch_cuda()
+    from paper_1806_08092_amd import learned
+    train_parts = []
+    for i, (scale, ef, abc) in enumerate([(13, 8, (0.57, 0.19, 0.19)), (13, 16, (0.45, 0.15, 0.15)),
+                                          (12, 16, (0.25, 0.25, 0.25))]):
+        g = gg.rmat_graph(scale, ef, seed=gg.BASE_SEED + 60 + i, abc=abc, symmetric=True)
+        G, _ = make_graph(g, 9)
+        st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for prog in ("bfs", "pagerank"):
+            G.state_init(prog, st, root=int(gg.pick_sources(g.offsets, gg.SOURCE_SEED, 1)[0]))
+            if prog == "pagerank":
+                G.set_frontier_all()
+            else:
+                G.set_frontier(torch.tensor([int(gg.pick_sources(g.offsets, gg.SOURCE_SEED, 1)[0])],
+                                            dtype=torch.int32, device="cuda"))
+            train_parts.append(learned.collect(G, max_iter=10))
+    data = learned.Samples.concat(train_parts)
+    assert len(data) > 100
+    mlp = learned.train(data, gg.mlp_init_params(7), steps=400, batch=2048, lr=3e-3, seed=1)
+    g = gg.rmat_graph(13, 12, seed=gg.BASE_SEED + 70, symmetric=True)
+    G, _ = make_graph(g, 9)
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    root = int(gg.pick_sources(g.offsets, gg.SOURCE_SEED, 1)[0])
+    G.state_init("bfs", st, root=root)
+    G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+    held = learned.collect(G, max_iter=20)
+    z = mlp.forward(torch.from_numpy(held.x).cuda()).cpu().numpy()
+    best = float(np.minimum(held.t_sc, held.t_pc).sum())
+    t_learned = learned.choice_cost(z >= 0, held)
+    t_eq1 = learned.choice_cost(learned.analytical_choice(held, 2.0), held)
+    print("held-out scatter time (us): best %.1f learned %.1f eq1(ratio 2) %.1f" % (best, t_learned, t_eq1))
+    assert best <= t_learned and best <= t_eq1
+    assert t_learned <= 1.10 * t_eq1
