@@ -116,6 +116,13 @@ def load_workload(name):
         g = gg.workload_sssp_er24()
         runs = [("sssp", int(s)) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 8)]
         return g, runs, 14, "SSSP u8 weights [1,255] from 8 sources, Erdos-Renyi 2^24 vertices deg 16"
+    if name == "pagerank_rmat25":
+        g = gg.rmat_graph(25, 16, seed=gg.BASE_SEED + 7)
+        return g, [("pagerank", 0)], 13, "PageRank 10 iterations d=0.85, RMAT scale 25 ef16 directed"
+    if name == "bfs_cc_rmat25":
+        g = gg.rmat_graph(25, 16, seed=gg.BASE_SEED + 7, symmetric=True)
+        runs = [("bfs", int(s)) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 8)] + [("cc", 0)]
+        return g, runs, 14, "BFS levels from 8 sources + min-label CC, RMAT scale 25 ef16 symmetrised"
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -148,6 +155,157 @@ def cpu_baseline(g, runs, budget_s):
     return edges / dt / 1e9, "oracle " + " ".join(done) + " in %.1f s" % dt
 
 
+# ------------------------------------------------------ selector evaluation
+TRAIN_SPECS = [  # (scale, edge factor, (a, b, c)) of the symmetrised RMAT training graphs
+    (18, 32, (0.57, 0.19, 0.19)), (19, 8, (0.45, 0.15, 0.15)), (20, 16, (0.65, 0.10, 0.10)),
+    (21, 32, (0.25, 0.25, 0.25)), (22, 8, (0.57, 0.19, 0.19)), (23, 16, (0.45, 0.15, 0.15)),
+]
+
+
+def _time_runs(G, st, runs, reps, deg, n, m):
+    """Runs the (program, root) list reps times; returns ms per pass, the
+    traversed-edge count of one pass and ms per program family."""
+    import torch
+    roots = {r: torch.tensor([r], dtype=torch.int32, device="cuda") for _, r in runs}
+    max_iter = {"pagerank": 10, "ppr": 20}
+    per = {}
+    edges = 0
+    for rep in range(reps + 1):  # the first pass is the warm-up
+        for prog, root in runs:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            G.state_init(prog, st, root=root)
+            if prog in ("cc", "pagerank"):
+                G.set_frontier_all()
+            else:
+                G.set_frontier(roots[root])
+            G.run(max_iter.get(prog, 1 << 30))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) * 1e3
+            if rep > 0:
+                per[prog] = per.get(prog, 0.0) + dt / reps
+            if rep == 0:
+                for r in G.iter_stats():
+                    per["decisions"] = per.get("decisions", 0) + r["sc_parts"] + r["pc_parts"]
+                    per["pc_decisions"] = per.get("pc_decisions", 0) + r["pc_parts"]
+                    per["fallbacks"] = per.get("fallbacks", 0) + r["learned_fallbacks"]
+                if prog in ("bfs", "sssp"):
+                    edges += int(deg[st != -1].sum().item())
+                elif prog == "pagerank":
+                    edges += 10 * m
+                else:
+                    edges += m
+    G.check()
+    counts = {k: per.pop(k) for k in ("decisions", "pc_decisions", "fallbacks") if k in per}
+    return sum(per.values()), edges, per, counts
+
+
+def selector_eval(args):
+    """Trains the learned selector on probe timings of BFS, CC and PageRank
+    over symmetrised RMAT graphs of scales 18-23 (varied a, b, c and edge
+    factor), then times BFS from 8 sources + CC on the symmetrised RMAT-25
+    graph and PageRank on the directed one under Eq. 1 at the paper's ratio,
+    Eq. 1 at the ratio fitted to the training timings, and the network."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1806_08092_amd as gp
+    from paper_1806_08092_amd import learned
+    # partitions of 2^14 vertices for the min programs, 2^13 for PageRank
+    # (its 64-bit LDS accumulators need twice the bytes per vertex)
+    def lp_of(prog):
+        return args.log2_part or (13 if prog == "pagerank" else 14)
+
+    parts = []
+    for i, (scale, ef, abc) in enumerate(TRAIN_SPECS[:args.train_graphs]):
+        t = time.perf_counter()
+        g = gg.rmat_graph(scale, ef, seed=gg.BASE_SEED + 100 + i, abc=abc, symmetric=True)
+        off, cols, w = gp.upload_csr(g)
+        st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        srcs = [int(x) for x in gg.pick_sources(g.offsets, gg.SOURCE_SEED + i, 2)]
+        for prog, root in [("bfs", srcs[0]), ("bfs", srcs[-1]), ("cc", 0), ("pagerank", 0)]:
+            G = gp.Graph(off, cols, w, log2_part=lp_of(prog))
+            G.state_init(prog, st, root=root)
+            if prog in ("cc", "pagerank"):
+                G.set_frontier_all()
+            else:
+                G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+            parts.append(learned.collect(G, max_iter=10 if prog == "pagerank" else 1 << 20))
+        log("training graph rmat%d ef%d abc=%s: %d rows so far (%.1f s)" % (
+            scale, ef, abc, sum(len(p) for p in parts), time.perf_counter() - t))
+        del G, off, cols, w, st
+        torch.cuda.empty_cache()
+    data = learned.Samples.concat(parts)
+    t = time.perf_counter()
+    mlp = learned.train(data, gg.mlp_init_params(gg.BASE_SEED), steps=args.train_steps, batch=4096,
+                        lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    x = torch.from_numpy(data.x).cuda()
+    mlp.compute_grad(x, torch.from_numpy(data.t_sc).cuda(), torch.from_numpy(data.t_pc).cuda())
+    train_loss = float(mlp.loss[0])
+    z = mlp.forward(x).cpu().numpy()
+    ratio = learned.calibrate_ratio(data)
+    fit = {"rows": len(data), "train_s": train_s, "loss": train_loss,
+           "best_us": float(np.minimum(data.t_sc, data.t_pc).sum()),
+           "learned_us": learned.choice_cost(z >= 0, data),
+           "eq1_ratio2_us": learned.choice_cost(learned.analytical_choice(data, 2.0), data),
+           "eq1_fitted_us": learned.choice_cost(learned.analytical_choice(data, ratio), data),
+           "fitted_ratio": ratio}
+    log("trained on %d rows in %.1f s: %s" % (len(data), train_s, fit))
+
+    scale = args.eval_scale
+    t = time.perf_counter()
+    src, dst = gg.rmat_edges(scale, 16 << scale, gg.BASE_SEED + 7)
+    graphs = [("directed", gg.from_edges(1 << scale, src, dst, name="rmat%d" % scale),
+               [("pagerank", 0)])]
+    ss, sd = gg.symmetrize(src, dst)
+    del src, dst
+    gs = gg.from_edges(1 << scale, ss, sd, name="rmat%d_sym" % scale)
+    del ss, sd
+    graphs.append(("symmetrised", gs, [("bfs", int(r)) for r in gg.pick_sources(gs.offsets, gg.SOURCE_SEED, 8)]
+                   + [("cc", 0)]))
+    log("evaluation graphs generated in %.1f s" % (time.perf_counter() - t))
+    # the learned selector falls back to Eq. 1 at the fitted ratio
+    selectors = [("eq1_ratio2", "analytical", 2.0), ("eq1_fitted", "analytical", ratio),
+                 ("learned", "learned", ratio)]
+    res = {name: {"ms": 0.0, "edges": 0, "per_program_ms": {}, "decisions": 0, "pc_decisions": 0,
+                  "fallbacks": 0} for name, _, _ in selectors}
+    for gname, g, runs in graphs:
+        off, cols, w = gp.upload_csr(g)
+        G = gp.Graph(off, cols, w, log2_part=lp_of(runs[-1][0]))
+        st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        deg = (off[1:] - off[:-1]).to(torch.int64)
+        for name, kind, r in selectors:
+            G.set_selector(kind, r, mlp=mlp.model if kind == "learned" else None)
+            ms, edges, per, counts = _time_runs(G, st, runs, args.steps, deg, g.n, g.m)
+            for kc, vc in counts.items():
+                res[name][kc] += vc
+            res[name]["ms"] += ms
+            res[name]["edges"] += edges
+            res[name]["per_program_ms"].update({"%s_%s" % (gname, k): v for k, v in per.items()})
+            log("%s %s: %.2f ms" % (gname, name, ms))
+        del G, off, cols, w, st, deg
+        torch.cuda.empty_cache()
+    for v in res.values():
+        v["GTEPS"] = v["edges"] / (v["ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "GTEPS under the learned scatter-mode selector vs Eq. 1 (speedup in selector_speedup)",
+        "value": res["learned"]["GTEPS"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": res["learned"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32+f32", "data": "synthetic",
+        "config": {"workload": "BFS 8 sources + CC on symmetrised RMAT-%d ef16, PageRank 10 it on directed "
+                               "RMAT-%d ef16; selector trained on RMAT scales 18-23" % (scale, scale),
+                   "log2_part": {"bfs_cc": lp_of("bfs"), "pagerank": lp_of("pagerank")},
+                   "train_graphs": args.train_graphs, "train_steps": args.train_steps},
+        "selector_speedup": {"learned_vs_eq1_ratio2": res["eq1_ratio2"]["ms"] / res["learned"]["ms"],
+                             "learned_vs_eq1_fitted": res["eq1_fitted"]["ms"] / res["learned"]["ms"]},
+        "selectors": res,
+        "training": fit,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,11 +323,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the device copy used as the practical bandwidth ceiling")
+    ap.add_argument("--train-graphs", type=int, default=len(TRAIN_SPECS),
+                    help="selector_rmat25: training graphs used (from scale 18 up)")
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--eval-scale", type=int, default=25)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "selector_rmat25":
+        if args.steps == 10:
+            args.steps = 2
+        return selector_eval(args)
 
     import numpy as np
     import torch

@@ -139,6 +139,8 @@ typedef struct gpop_iter_stats {
     uint64_t sc_active_edges;    /* E_a summed over SC partitions              */
     uint64_t pc_vertices;        /* vertices of PC partitions                  */
     uint64_t merged_parts;       /* split partitions merged                    */
+    uint32_t learned_fallbacks;  /* partitions the learned selector left to Eq. 1 */
+    uint32_t reserved;
 } gpop_iter_stats;
 
 /* ------------------------------------------------------------------ setup */

@@ -25,8 +25,8 @@
  *   4 r^p = M^p / E^p   5 V_a / q_p         6 E_a / E^p        7 non-empty bins of row p / k
  *   8 log(max out-degree in p / mean out-degree in p)          9 log1p(t)
  *  10 sum over partitions of E_a / |E|
- *  11 log(cost_PC / (ratio * cost_SC)), the two sides of Eq. 1 with the
- *     selector's s_i, s_v and bandwidth ratio
+ *  11 log(cost_PC / cost_SC), the two byte counts of Eq. 1 with the
+ *     selector's s_i and s_v (Eq. 1 picks PC iff this is <= log(ratio))
  * Ratios with a zero denominator are 0.
  *
  * Training: binary cross-entropy on the logit with label [t_PC < t_SC] and

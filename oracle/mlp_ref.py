@@ -6,7 +6,8 @@ checking only:
 * the 12 per-partition features (vertex and edge counts of the partition and
   its active part, the partition's message ratio r^p = M^p / E^p from message
   generation, Sec. 3.1.2, bin fill, degree skew, iteration, the global active
-  edge fraction, and the log ratio of the two sides of Eq. 1, Sec. 3.2);
+  edge fraction, and the log ratio of the two byte counts compared by Eq. 1,
+  Sec. 3.2);
 * the network 12 -> 64 -> 64 -> 1 with ReLU, evaluated in FP64 on weights
   rounded to bf16 (round to nearest even) and on FP32 standardisation
   constants;
@@ -83,8 +84,8 @@ def partition_stats(offsets, cols, q: int):
     return Ep, Mp, [len(r) for r in rows], maxd
 
 
-def features(offsets, cols, q: int, frontier: Iterable[int], it: int, s_i: int = 4, s_v: int = 4,
-             bw_ratio: float = 2.0) -> np.ndarray:
+def features(offsets, cols, q: int, frontier: Iterable[int], it: int, s_i: int = 4,
+             s_v: int = 4) -> np.ndarray:
     """k x 12 FP64 features of the frontier `frontier` at iteration `it`."""
     n = len(offsets) - 1
     m = int(offsets[-1])
@@ -112,7 +113,7 @@ def features(offsets, cols, q: int, frontier: Iterable[int], it: int, s_i: int =
             math.log(maxd[p] / mean_deg) if E else 0.0,
             math.log1p(it),
             frac,
-            math.log(cost_pc / (bw_ratio * cost_sc)) if cost_sc > 0 else 0.0,
+            math.log(cost_pc / cost_sc) if cost_sc > 0 else 0.0,
         ]
     return out
 

@@ -567,6 +567,8 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
             r->sc_active_vertices = t[6];
             r->sc_active_edges = t[7];
             r->pc_vertices = t[8];
+            r->learned_fallbacks = C->mlp_fallback;
+            C->mlp_fallback = 0;
             r->sc_msgs = 0;
             r->sc_ids = 0;
             r->gathered_ids = 0;

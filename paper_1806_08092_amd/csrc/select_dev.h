@@ -56,8 +56,7 @@ __device__ inline void partition_features(const Dev& G, const Params& P, uint32_
     const double cost_pc = ((double)Mp + (double)Ep) * si + 2.0 * (double)Mp * sv + (double)G.k * si;
     const double cost_sc = (Ep ? 2.0 * sv * (double)Mp * (double)Ea / (double)Ep : 0.0) +
                            (3.0 * (double)Ea + (double)Va) * si;
-    const double ratio = (double)P.ratio_num / (double)P.ratio_den;
-    f[11] = cost_sc > 0.0 ? (float)log(cost_pc / (ratio * cost_sc)) : 0.f;
+    f[11] = cost_sc > 0.0 ? (float)log(cost_pc / cost_sc) : 0.f;
 }
 
 // The network's logit for raw features f. Returns false when a standardised

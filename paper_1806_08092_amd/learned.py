@@ -94,8 +94,8 @@ def choice_cost(pick_pc: np.ndarray, data: Samples) -> float:
 
 def analytical_choice(data: Samples, bw_ratio: float = 2.0) -> np.ndarray:
     """Eq. 1's choice for each row from the last feature, which is
-    log(cost_PC / (2 cost_SC)) (PC iff cost_PC <= ratio cost_SC)."""
-    return data.x[:, 11].astype(np.float64) + math.log(2.0) <= math.log(bw_ratio)
+    log(cost_PC / cost_SC) (PC iff cost_PC <= ratio cost_SC)."""
+    return data.x[:, 11].astype(np.float64) <= math.log(bw_ratio)
 
 
 def calibrate_ratio(data: Samples, grid: Optional[np.ndarray] = None) -> float:

@@ -170,8 +170,8 @@ def test_last_feature_agrees_with_eq1(seed):
             continue
         ea = sum(int(g.offsets[v + 1] - g.offsets[v]) for v in front if v // q == p)
         mode = gpop_ref.choose_mode(png.E[p], png.M[p], va, ea, png.k)
-        if abs(f[p, 11]) > 1e-12:
-            assert (f[p, 11] <= 0) == (mode == gpop_ref.PC)
+        if abs(f[p, 11] - math.log(2)) > 1e-12:
+            assert (f[p, 11] <= math.log(2)) == (mode == gpop_ref.PC)
 
 
 def test_features_all_active_invariants():
