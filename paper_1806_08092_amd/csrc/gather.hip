@@ -456,8 +456,16 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
                     if (!__syncthreads_or(pend != 0)) break;
                 }
             } else {
-                // tagged rounds for the exact fixed-point sum
-                for (;;) {
+                // Exact fixed-point sum. Tag rounds: every pending entry
+                // writes its slot number into its destination's tag, the
+                // entry whose tag survived adds. Each round retires one entry
+                // per destination, so a destination hit many times in one
+                // round (a high in-degree vertex) would take as many rounds;
+                // after four rounds the leftovers are first summed per
+                // destination inside each wave, which leaves at most one
+                // entry per destination per wave for the final rounds.
+                bool left = true;
+                for (int tr = 0; tr < 4 && left; ++tr) {
 #pragma unroll
                     for (uint32_t j = 0; j < 4 * PPW; ++j)
                         if ((pend >> j) & 1u) tag[dst[j]] = (uint16_t)(tid * 4u * PPW + j);
@@ -469,7 +477,59 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
                             pend &= ~(1u << j);
                         }
                     }
-                    if (!__syncthreads_or(pend != 0)) break;
+                    left = __syncthreads_or(pend != 0);
+                }
+                if (left) {
+                    uint32_t adst[4 * PPW];
+                    unsigned long long afx[4 * PPW];
+                    uint32_t apend = 0, na = 0;
+                    for (;;) {  // one destination of this wave per pass
+                        const uint64_t bl = ballot(pend != 0);
+                        if (!bl) break;
+                        uint32_t mykey = 0;
+                        bool found = false;
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (!found && ((pend >> j) & 1u)) {
+                                mykey = dst[j];
+                                found = true;
+                            }
+                        }
+                        const uint32_t key = (uint32_t)__shfl((int)mykey, (int)(__ffsll((long long)bl) - 1), 64);
+                        unsigned long long sum = 0;
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (((pend >> j) & 1u) && dst[j] == key) {
+                                sum += fx[j];
+                                pend &= ~(1u << j);
+                            }
+                        }
+                        sum = wave_sum_u64(sum);
+                        const uint32_t tl = na & 63u, ts = na >> 6;
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (lane == tl && j == ts) {
+                                adst[j] = key;
+                                afx[j] = sum;
+                                apend |= 1u << j;
+                            }
+                        }
+                        ++na;
+                    }
+                    for (;;) {  // at most kGW contenders per destination
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j)
+                            if ((apend >> j) & 1u) tag[adst[j]] = (uint16_t)(tid * 4u * PPW + j);
+                        __syncthreads();
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (((apend >> j) & 1u) && tag[adst[j]] == (uint16_t)(tid * 4u * PPW + j)) {
+                                acc[adst[j]] += afx[j];
+                                apend &= ~(1u << j);
+                            }
+                        }
+                        if (!__syncthreads_or(apend != 0)) break;
+                    }
                 }
             }
         }

@@ -283,3 +283,41 @@ def test_split_results_bitwise_equal_unsplit():
     a, _ = run_program(G1, "pagerank", g.n, max_iter=10)
     b, _ = run_program(G2, "pagerank", g.n, max_iter=10)
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def _hub_graph():
+    """Many small messages into a few hubs: every vertex links to hubs 0, 1
+    and 2 (hub 0 twice), plus a ring; 6000 vertices in 2^8-vertex
+    partitions, so each bin holds a few dozen ids and a single combine round
+    sees the same hub many times."""
+    n = 6000
+    edges = []
+    for v in range(3, n):
+        edges += [(v, 0), (v, 0), (v, 1), (v, 2), (v, (v + 1) % n)]
+    edges += [(0, 5), (1, 6), (2, 7)]
+    return edges_graph(n, edges)
+
+
+@pytest.mark.parametrize("sel", SELECTORS)
+@pytest.mark.parametrize("gids", [0, 256])
+def test_sum_programs_with_hub_destinations(sel, gids):
+    g = _hub_graph()
+    G, _ = make_graph(g, 8, gather_task_ids=gids)
+    ref = oracle.pagerank(g, 0.85, 10)
+    got, _ = run_program(G, "pagerank", g.n, selector=sel, max_iter=10)
+    assert pr_ok(got, ref), np.max(np.abs(got.astype(np.float64) - ref))
+    ref = oracle.ppr(g, 7, 0.15, 20)
+    got, _ = run_program(G, "ppr", g.n, root=7, selector=sel, max_iter=20)
+    assert pr_ok(got, ref), np.max(np.abs(got.astype(np.float64) - ref))
+
+
+def test_sum_with_hub_destinations_is_mode_and_split_invariant():
+    g = _hub_graph()
+    outs = []
+    for gids in (0, 256):
+        G, _ = make_graph(g, 8, gather_task_ids=gids)
+        for sel in SELECTORS:
+            got, _ = run_program(G, "pagerank", g.n, selector=sel, max_iter=10)
+            outs.append(got.view(np.uint32))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
