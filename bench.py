@@ -306,6 +306,104 @@ def selector_eval(args):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------ batched runs
+def _batch_specs(name):
+    """(graphs [(Graph, log2_part)], program, roots per run, max_iter, description)."""
+    import graphgen as gg
+    if name == "batch_bfs64_rmat22":
+        g = gg.workload_bfs_cc_rmat22()
+        roots = [int(r) for r in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 64)]
+        return [(g, 14)] * 64, "bfs", roots, 1 << 30, "64-source BFS levels, RMAT-22 ef16 symmetrised"
+    if name == "batch_ppr64_rmat22":
+        g = gg.workload_bfs_cc_rmat22()
+        roots = [int(r) for r in gg.pick_sources(g.offsets, gg.SOURCE_SEED + 7, 64)]
+        return [(g, 13)] * 64, "ppr", roots, 20, "64-seed personalised PageRank (0.15, 20 it), RMAT-22 ef16 sym"
+    if name == "batch_pr32_graphs":
+        gs = []
+        for i in range(32):
+            scale, ef = 12 + (i % 9), 8 * (1 + (i % 4))
+            gs.append((gg.rmat_graph(scale, ef, seed=gg.BASE_SEED + 200 + i), 13))
+        return gs, "pagerank", [0] * 32, 10, "PageRank 10 it on 32 RMAT graphs, scales 12-20, ef 8-32"
+    raise SystemExit("unknown batch workload %s" % name)
+
+
+def batch_eval(args):
+    """Times the runs one after another on the plain path, then as one batch
+    (recorded HIP graph), and reports both."""
+    import numpy as np
+    import torch
+    import paper_1806_08092_amd as gp
+    t = time.perf_counter()
+    items, prog, roots, max_iter, desc = _batch_specs(args.workload)
+    uniq = {}
+    for g, lp in items:
+        if id(g) not in uniq:
+            off, cols, w = gp.upload_csr(g)
+            uniq[id(g)] = (g, gp.Graph(off, cols, w, log2_part=args.log2_part or lp), (off, cols, w))
+    Gs = [uniq[id(g)][1] for g, _ in items]
+    log("%s: %d runs on %d graphs, ready in %.1f s" % (args.workload, len(items), len(uniq), time.perf_counter() - t))
+    states = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g, _ in items]
+    all_front = prog in ("cc", "pagerank")
+    rt = [torch.tensor([r], dtype=torch.int32, device="cuda") for r in roots]
+
+    def sequential():
+        its = []
+        for i, G in enumerate(Gs):
+            G.state_init(prog, states[i], root=roots[i])
+            if all_front:
+                G.set_frontier_all()
+            else:
+                G.set_frontier(rt[i])
+            its.append(G.run(max_iter))
+        return its
+
+    B = gp.Batch(Gs)
+
+    def batched(eager=False):
+        B.state_init(prog, states, roots=roots)
+        for i in range(len(Gs)):
+            if all_front:
+                B.set_frontier_all(i)
+            else:
+                B.set_frontier(i, rt[i])
+        return B.run(max_iter, eager=eager)
+
+    res = {}
+    for mode, fn in (("sequential", sequential), ("batched", batched),
+                     ("batched_eager", lambda: batched(True))):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            its = fn()
+        torch.cuda.synchronize()
+        res[mode] = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.steps, "iterations": its}
+        log("%s: %.2f ms" % (mode, res[mode]["ms_per_step"]))
+    B.check()
+    # traversed edges of one step (same for every mode: results are identical)
+    edges = 0
+    for i, (g, _) in enumerate(items):
+        if prog in ("bfs", "sssp"):
+            deg = np.diff(g.offsets.astype(np.int64))
+            edges += int(deg[states[i].cpu().numpy() != -1].sum())
+        else:
+            edges += res["batched"]["iterations"][i] * g.m
+    for v in res.values():
+        v["GTEPS"] = edges / (v["ms_per_step"] * 1e-3) / 1e9
+    out = {
+        "metric": "GTEPS of the batched launch vs the same runs one after another",
+        "value": res["batched"]["GTEPS"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["batched"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prog in ("pagerank", "ppr") else "u32",
+        "data": "synthetic",
+        "config": {"workload": desc, "runs": len(items), "graphs": len(uniq), "edges_per_step": edges},
+        "batch_speedup": res["sequential"]["ms_per_step"] / res["batched"]["ms_per_step"],
+        "modes": {k: {"ms_per_step": v["ms_per_step"], "GTEPS": v["GTEPS"]} for k, v in res.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +430,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload.startswith("batch_"):
+        if args.steps == 10:
+            args.steps = 3
+        return batch_eval(args)
     if args.workload == "selector_rmat25":
         if args.steps == 10:
             args.steps = 2

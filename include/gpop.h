@@ -259,6 +259,55 @@ int gpop_modes_read(struct gpop_graph* g, uint8_t* h_modes, void* stream);
  * Synchronises `stream`. Returns GPOP_EINVAL if an error was recorded. */
 int gpop_check(struct gpop_graph* g, void* stream);
 
+/* ---------------------------------------------------------------- batches */
+
+/* A batch runs one program many times at once: several seeds on one graph
+ * (graphs[i] may repeat) or independent graphs of any size. Each run has
+ * its own state, frontier and bins; the graphs' preprocessed layouts are
+ * shared. Every kernel of an iteration is launched once for all runs (each
+ * run owns a slice of the grid), and a fixed number of iterations is
+ * recorded once as a HIP graph and replayed until every run has finished, so
+ * the host neither launches per run nor synchronises per iteration. The
+ * graph handles must outlive the batch and must not be iterated while the
+ * batch runs. Each run uses its graph's selector (gpop_set_selector). */
+struct gpop_batch;
+
+#define GPOP_BATCH_EAGER 1u  /* gpop_batch_run flag: launch directly, no HIP graph */
+
+/* Device workspace bytes for a batch of n runs on graphs[0..n-1]. */
+int gpop_batch_plan(struct gpop_graph* const* graphs, uint32_t n, uint64_t* ws_bytes);
+
+/* Creates the batch over a caller-owned, 256-byte aligned workspace of at
+ * least gpop_batch_plan bytes. Synchronises `stream`. Errors: GPOP_EINVAL
+ * (NULL graphs, n = 0, misaligned workspace), GPOP_ENOMEM (workspace too
+ * small). */
+int gpop_batch_create(struct gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t ws_bytes,
+                      void* stream, struct gpop_batch** out);
+
+/* Releases the host-side handle and its recorded graph. NULL ok. */
+int gpop_batch_destroy(struct gpop_batch* b);
+
+/* Binds `prog` to every run: prm[i] and the state array d_states[i] (V_i x
+ * 4 bytes) of run i, and writes the initial values as gpop_state_init does.
+ * Synchronises `stream`. Errors as gpop_state_init, for any run. */
+int gpop_batch_state_init(struct gpop_batch* b, gpop_program prog, const gpop_params* prm,
+                          void* const* d_states, void* stream);
+
+/* Frontier of run `run` (after gpop_batch_state_init, before
+ * gpop_batch_run), as gpop_set_frontier / gpop_set_frontier_all. */
+int gpop_batch_set_frontier(struct gpop_batch* b, uint32_t run, const uint32_t* d_vertices, uint32_t n,
+                            void* stream);
+int gpop_batch_set_frontier_all(struct gpop_batch* b, uint32_t run, void* stream);
+
+/* Runs every run until its frontier is empty or it has done max_iter more
+ * iterations. flags: 0 or GPOP_BATCH_EAGER. Synchronises `stream`; h_iters
+ * (n entries, may be NULL) receives each run's iteration count. */
+int gpop_batch_run(struct gpop_batch* b, uint32_t max_iter, uint32_t flags, uint32_t* h_iters,
+                   void* stream);
+
+/* gpop_check for every run. Synchronises `stream`. */
+int gpop_batch_check(struct gpop_batch* b, void* stream);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Kernel identifiers for gpop_profile_read. */

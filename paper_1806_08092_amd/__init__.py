@@ -133,6 +133,18 @@ _SIGS = {
     "gpop_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_uint32, ctypes.c_uint32,
                                                                    ctypes.c_float]
                             + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "gpop_batch_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
+    "gpop_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "gpop_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "gpop_batch_state_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "gpop_batch_set_frontier": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                               ctypes.c_uint32, ctypes.c_void_p]),
+    "gpop_batch_set_frontier_all": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]),
+    "gpop_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "gpop_batch_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -312,6 +324,64 @@ class Graph:
         n = (ctypes.c_uint64 * nk)()
         _check(lib().gpop_profile_read(self.h, ms, n, _stream(stream)))
         return {KERNELS[i]: (ms[i], int(n[i])) for i in range(nk)}
+
+
+BATCH_EAGER = 1
+
+
+class Batch:
+    """Many runs of one program launched together (include/gpop.h, batches):
+    `graphs` is a list of Graph objects (repeat one for several seeds). The
+    workspace is a torch tensor owned by this object."""
+
+    def __init__(self, graphs, stream=None):
+        import torch
+        self.graphs = list(graphs)
+        self.n = len(self.graphs)
+        self._harr = (ctypes.c_void_p * self.n)(*[g.h.value for g in self.graphs])
+        need = ctypes.c_uint64()
+        _check(lib().gpop_batch_plan(self._harr, self.n, ctypes.byref(need)))
+        self.workspace = torch.empty(need.value + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p()
+        _check(lib().gpop_batch_create(self._harr, self.n, ctypes.c_void_p(aligned), need.value,
+                                       _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.states = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gpop_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state_init(self, prog, states, roots=None, persist: int = 1, damping: float = 0.85,
+                   alpha: float = 0.15, stream=None):
+        prog = PROGRAMS[prog] if isinstance(prog, str) else int(prog)
+        roots = [0] * self.n if roots is None else list(roots)
+        prm = (Params * self.n)(*[Params(int(r), persist, damping, alpha) for r in roots])
+        ptrs = (ctypes.c_void_p * self.n)(*[s.data_ptr() for s in states])
+        _check(lib().gpop_batch_state_init(self.h, prog, prm, ptrs, _stream(stream)))
+        self.states = list(states)
+
+    def set_frontier(self, run: int, vertices, stream=None):
+        _check(lib().gpop_batch_set_frontier(self.h, run, _ptr(vertices), vertices.numel(), _stream(stream)))
+
+    def set_frontier_all(self, run: int, stream=None):
+        _check(lib().gpop_batch_set_frontier_all(self.h, run, _stream(stream)))
+
+    def run(self, max_iter: int = 1 << 30, eager: bool = False, stream=None):
+        iters = (ctypes.c_uint32 * self.n)()
+        _check(lib().gpop_batch_run(self.h, max_iter, BATCH_EAGER if eager else 0, iters, _stream(stream)))
+        return list(iters)
+
+    def check(self, stream=None):
+        _check(lib().gpop_batch_check(self.h, _stream(stream)))
 
 
 class Mlp:

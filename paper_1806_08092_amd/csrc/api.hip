@@ -441,9 +441,10 @@ int gpop_graph_get_info(const gpop_graph* g, gpop_graph_info* out) {
     return GPOP_OK;
 }
 
-int gpop_state_init(gpop_graph* g, gpop_program prog, const gpop_params* prm, void* d_state,
-                    void* stream) {
-    if (!g || !prm || !d_state) return fail(GPOP_EINVAL, "NULL argument");
+namespace {
+
+// Argument checks shared by gpop_state_init and gpop_batch_state_init.
+int check_program(const gpop_graph* g, gpop_program prog, const gpop_params* prm) {
     if ((int)prog < 0 || (int)prog > GPOP_PROG_CARRY_BFS) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
     const bool rooted = prog != GPOP_PROG_CC_MINLABEL && prog != GPOP_PROG_PAGERANK_F32;
     if (rooted && prm->root >= g->G.V) return fail(GPOP_EINVAL, "root %u >= V", prm->root);
@@ -456,14 +457,28 @@ int gpop_state_init(gpop_graph* g, gpop_program prog, const gpop_params* prm, vo
     if (gather_lds_bytes(prog, g->G.q) + 2048 > (size_t)max_lds_per_block())
         return fail(GPOP_ENOTSUP, "program %d needs %zu bytes of LDS at q = %u; use a smaller partition",
                     (int)prog, gather_lds_bytes(prog, g->G.q), g->G.q);
+    return GPOP_OK;
+}
+
+void program_params(const gpop_graph* g, const gpop_params* prm, Params* P) {
+    P->root = prm->root;
+    P->persist = prm->persist;
+    P->damping = prm->damping;
+    P->alpha = prm->alpha;
+    P->inv_n = 1.0 / (double)g->G.V;
+}
+
+}  // namespace
+
+int gpop_state_init(gpop_graph* g, gpop_program prog, const gpop_params* prm, void* d_state,
+                    void* stream) {
+    if (!g || !prm || !d_state) return fail(GPOP_EINVAL, "NULL argument");
+    int rc = check_program(g, prog, prm);
+    if (rc) return rc;
     g->prog = (int)prog;
     g->state = (uint32_t*)d_state;
     g->it = 0;
-    g->P.root = prm->root;
-    g->P.persist = prm->persist;
-    g->P.damping = prm->damping;
-    g->P.alpha = prm->alpha;
-    g->P.inv_n = 1.0 / (double)g->G.V;
+    program_params(g, prm, &g->P);
     hipStream_t st = (hipStream_t)stream;
     HIP_OR_RETURN(launch_state_init(g->G, g->P, g->prog, g->state, st), "state init");
     return GPOP_OK;
@@ -724,3 +739,308 @@ int gpop_profile_read(gpop_graph* g, double* h_ms, uint64_t* h_launches, void* s
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many runs of one program, every kernel launched once per iteration
+// for all runs, the iteration sequence captured as a HIP graph.
+// ---------------------------------------------------------------------------
+struct gpop_batch {
+    std::vector<gpop_graph*> graphs;
+    std::vector<Inst> inst;          // host copy of the run table
+    Inst* d_tab = nullptr;
+    uint32_t* d_status = nullptr;    // {done, iterations} per run
+    std::vector<uint32_t> h_status;
+    BatchGrid grid{};
+    int prog = -1;
+    bool frontier_ok = false;
+    hipStream_t cap = nullptr;       // private stream used only to record the graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_prog = -1;
+    uint32_t chunk = 4;              // iterations per graph replay
+};
+
+namespace {
+
+// Per-run buffers (everything an iteration writes); nullptr base: sizing.
+size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + o : nullptr;
+        o += align256(bytes ? bytes : 1);
+        return p;
+    };
+    const Dev& S = g->G;
+    const uint64_t k = S.k, q = S.q, kk = k * k;
+    const uint64_t E_pad = align256(S.E ? S.E : 1);
+    const uint64_t ngt = S.n_gtask ? S.n_gtask : 1;
+    D->data = (uint32_t*)take((g->M ? g->M : 1) * 4);
+    D->sc_ids = (uint16_t*)take(E_pad * 2);
+    D->sc_w = S.w ? (uint8_t*)take(E_pad) : nullptr;
+    D->sc_chunk = (uint32_t*)take(E_pad / kChunk * 4);
+    D->sc_cnt = (uint2*)take(kk * 8);
+    D->sc_tot = (uint2*)take(k * 8);
+    D->sc_t0 = (uint32_t*)take((k + 1) * 4);
+    D->sc_tc = (uint2*)take((uint64_t)S.max_sctask * k * 8);
+    D->gat_ids = (uint32_t*)take(ngt * 4);
+    D->gat_ran = (uint32_t*)take((ngt + k) * 4);
+    D->mode = (uint8_t*)take(k);
+    D->mode_l = (uint8_t*)take(k);
+    for (int b = 0; b < 2; ++b) {
+        D->flist[b] = (uint16_t*)take(k * q * 2);
+        D->fbits[b] = (uint32_t*)take(k * q / 8);
+        D->fVa[b] = (uint32_t*)take(k * 4);
+        D->fEa[b] = (uint32_t*)take(k * 4);
+        D->fpre[b] = (uint32_t*)take(k * q * 4);
+        D->dpart[b] = (double*)take(k * 8);
+    }
+    D->marks = (uint8_t*)take(k * q);
+    D->ctrl = (Ctrl*)take(sizeof(Ctrl));
+    D->log = (gpop_iter_stats*)take(kLogCap * sizeof(gpop_iter_stats));
+    D->probe = (unsigned long long*)take(3 * k * 8);
+    D->gpart = (uint32_t*)take(ngt * q * 8);
+    D->gflag = (uint32_t*)take(ngt * 4);
+    return o;
+}
+
+size_t batch_header_bytes(uint32_t n) {
+    return align256((size_t)n * sizeof(Inst)) + align256(6 * ((size_t)n + 1) * 4) + align256((size_t)n * 8);
+}
+
+int batch_check_graphs(gpop_graph* const* graphs, uint32_t n) {
+    if (!graphs || n == 0) return fail(GPOP_EINVAL, "a batch needs at least one graph");
+    for (uint32_t i = 0; i < n; ++i)
+        if (!graphs[i]) return fail(GPOP_EINVAL, "graph %u is NULL", i);
+    return GPOP_OK;
+}
+
+void destroy_graph_exec(gpop_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_prog = -1;
+}
+
+int batch_record(gpop_batch* b) {
+    destroy_graph_exec(b);
+    HIP_OR_RETURN(prepare_batch_scatter(b->grid, b->prog), "batch kernel attributes");
+    HIP_OR_RETURN(prepare_batch_gather(b->grid, b->prog), "batch kernel attributes");
+    HIP_OR_RETURN(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture");
+    hipError_t e = hipSuccess;
+    for (uint32_t c = 0; c < b->chunk && e == hipSuccess; ++c) {
+        e = launch_batch_select(b->grid, b->cap);
+        if (e == hipSuccess) e = launch_batch_scatter(b->grid, b->prog, b->cap);
+        if (e == hipSuccess) e = launch_batch_gather(b->grid, b->prog, b->cap);
+    }
+    if (e == hipSuccess) e = launch_batch_status(b->grid, b->d_status, b->cap);
+    hipGraph_t gr = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &gr);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(e != hipSuccess ? e : e2, "record batch iterations");
+    }
+    b->graph = gr;
+    HIP_OR_RETURN(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0), "instantiate batch graph");
+    b->graph_prog = b->prog;
+    return GPOP_OK;
+}
+
+}  // namespace
+
+int gpop_batch_plan(gpop_graph* const* graphs, uint32_t n, uint64_t* ws_bytes) {
+    int rc = batch_check_graphs(graphs, n);
+    if (rc) return rc;
+    if (!ws_bytes) return fail(GPOP_EINVAL, "ws_bytes is NULL");
+    uint64_t t = batch_header_bytes(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        Dev D{};
+        t += carve_run(&D, nullptr, graphs[i]);
+    }
+    *ws_bytes = t;
+    return GPOP_OK;
+}
+
+int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t ws_bytes, void* stream,
+                      gpop_batch** out) {
+    int rc = batch_check_graphs(graphs, n);
+    if (rc) return rc;
+    if (!out) return fail(GPOP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(GPOP_EINVAL, "workspace must be 256-byte aligned");
+    uint64_t need = 0;
+    if ((rc = gpop_batch_plan(graphs, n, &need))) return rc;
+    if (ws_bytes < need) return fail(GPOP_ENOMEM, "batch workspace %zu bytes < %llu needed", ws_bytes,
+                                     (unsigned long long)need);
+    hipStream_t st = (hipStream_t)stream;
+    gpop_batch* b = new (std::nothrow) gpop_batch();
+    if (!b) return fail(GPOP_ENOMEM, "host allocation failed");
+    b->graphs.assign(graphs, graphs + n);
+    b->inst.resize(n);
+    b->h_status.assign(2 * (size_t)n, 0);
+    char* base = (char*)d_ws;
+    b->d_tab = (Inst*)base;
+    uint32_t* boff = (uint32_t*)(base + align256((size_t)n * sizeof(Inst)));
+    b->d_status = (uint32_t*)(base + align256((size_t)n * sizeof(Inst)) + align256(6 * ((size_t)n + 1) * 4));
+    size_t o = batch_header_bytes(n);
+    std::vector<uint32_t> hb(6 * ((size_t)n + 1), 0);
+    const uint32_t sc_cap = std::max<uint32_t>(16u, 2048u / n);
+    uint32_t k_max = 0, q_max = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const gpop_graph* g = graphs[i];
+        Inst& I = b->inst[i];
+        I.G = g->G;  // static arrays shared with the graph
+        o += carve_run(&I.G, base + o, g);
+        I.P = g->P;
+        I.state = nullptr;
+        const Dev& S = g->G;
+        const uint32_t nb[6] = {(S.k + 63) / 64, std::min<uint32_t>((S.max_sctask + kScWaves - 1) / kScWaves, sc_cap),
+                                S.k, S.n_pctask, S.n_gtask, S.n_gsplit};
+        for (int j = 0; j < 6; ++j) hb[(size_t)j * (n + 1) + i + 1] = hb[(size_t)j * (n + 1) + i] + nb[j];
+        k_max = std::max(k_max, S.k);
+        q_max = std::max(q_max, S.q);
+        HIP_OR_RETURN(hipMemsetAsync(I.G.ctrl, 0, sizeof(Ctrl), st), "clear run control");
+    }
+    BatchGrid& B = b->grid;
+    B.tab = b->d_tab;
+    B.n = n;
+    const uint32_t* bo[6];
+    uint32_t tot[6];
+    for (int j = 0; j < 6; ++j) {
+        bo[j] = boff + (size_t)j * (n + 1);
+        tot[j] = hb[(size_t)j * (n + 1) + n];
+    }
+    B.b_select = bo[0];
+    B.b_sc = bo[1];
+    B.b_scan = bo[2];
+    B.b_pc = bo[3];
+    B.b_gather = bo[4];
+    B.b_merge = bo[5];
+    B.nb_select = tot[0];
+    B.nb_sc = tot[1];
+    B.nb_scan = tot[2];
+    B.nb_pc = tot[3];
+    B.nb_gather = tot[4];
+    B.nb_merge = tot[5];
+    B.k_max = k_max;
+    B.q_max = q_max;
+    if (sc_lds_bytes(k_max) > (size_t)max_lds_per_block()) {
+        delete b;
+        return fail(GPOP_ENOTSUP, "k = %u partitions need more LDS than a workgroup has", k_max);
+    }
+    HIP_OR_RETURN(hipMemcpyAsync(boff, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, st), "write batch grid");
+    HIP_OR_RETURN(hipMemcpyAsync(b->d_tab, b->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, st),
+                  "write run table");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return fail(GPOP_EDEVICE, "cannot create the recording stream");
+    }
+    *out = b;
+    return GPOP_OK;
+}
+
+int gpop_batch_destroy(gpop_batch* b) {
+    if (!b) return GPOP_OK;
+    destroy_graph_exec(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return GPOP_OK;
+}
+
+int gpop_batch_state_init(gpop_batch* b, gpop_program prog, const gpop_params* prm, void* const* d_states,
+                          void* stream) {
+    if (!b || !prm || !d_states) return fail(GPOP_EINVAL, "NULL argument");
+    const uint32_t n = (uint32_t)b->inst.size();
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!d_states[i]) return fail(GPOP_EINVAL, "state %u is NULL", i);
+        int rc = check_program(b->graphs[i], prog, &prm[i]);
+        if (rc) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    for (uint32_t i = 0; i < n; ++i) {
+        Inst& I = b->inst[i];
+        I.P = b->graphs[i]->P;  // the graph's selector settings
+        program_params(b->graphs[i], &prm[i], &I.P);
+        I.P.probe = 0;
+        I.state = (uint32_t*)d_states[i];
+        HIP_OR_RETURN(launch_state_init(I.G, I.P, (int)prog, I.state, st), "state init");
+    }
+    HIP_OR_RETURN(hipMemcpyAsync(b->d_tab, b->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, st),
+                  "write run table");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    b->prog = (int)prog;
+    b->frontier_ok = true;
+    return GPOP_OK;
+}
+
+int gpop_batch_set_frontier(gpop_batch* b, uint32_t run, const uint32_t* d_vertices, uint32_t n, void* stream) {
+    if (!b) return fail(GPOP_EINVAL, "NULL batch");
+    if (run >= b->inst.size()) return fail(GPOP_EINVAL, "run %u out of range", run);
+    if (n && !d_vertices) return fail(GPOP_EINVAL, "NULL vertex array");
+    if (!b->frontier_ok) return fail(GPOP_ESTATE, "set the frontier after gpop_batch_state_init, before running");
+    HIP_OR_RETURN(launch_set_frontier(b->inst[run].G, d_vertices, n, 0, 0, (hipStream_t)stream), "set frontier");
+    return GPOP_OK;
+}
+
+int gpop_batch_set_frontier_all(gpop_batch* b, uint32_t run, void* stream) {
+    if (!b) return fail(GPOP_EINVAL, "NULL batch");
+    if (run >= b->inst.size()) return fail(GPOP_EINVAL, "run %u out of range", run);
+    if (!b->frontier_ok) return fail(GPOP_ESTATE, "set the frontier after gpop_batch_state_init, before running");
+    HIP_OR_RETURN(launch_set_frontier(b->inst[run].G, nullptr, 0, 1, 0, (hipStream_t)stream), "set frontier");
+    return GPOP_OK;
+}
+
+int gpop_batch_run(gpop_batch* b, uint32_t max_iter, uint32_t flags, uint32_t* h_iters, void* stream) {
+    if (!b) return fail(GPOP_EINVAL, "NULL batch");
+    if (b->prog < 0) return fail(GPOP_ESTATE, "gpop_batch_state_init not called");
+    if (flags & ~(uint32_t)GPOP_BATCH_EAGER) return fail(GPOP_EINVAL, "unknown flags 0x%x", flags);
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t n = (uint32_t)b->inst.size();
+    b->frontier_ok = false;
+    HIP_OR_RETURN(launch_batch_limits(b->grid, max_iter, st), "iteration limit");
+    const bool eager = flags & GPOP_BATCH_EAGER;
+    if (eager) {
+        HIP_OR_RETURN(prepare_batch_scatter(b->grid, b->prog), "batch kernel attributes");
+        HIP_OR_RETURN(prepare_batch_gather(b->grid, b->prog), "batch kernel attributes");
+    } else if (b->graph_prog != b->prog) {
+        int rc = batch_record(b);
+        if (rc) return rc;
+    }
+    // every run stops at its limit, so max_iter / chunk + 1 passes suffice
+    const uint64_t passes = (uint64_t)max_iter / b->chunk + 2;
+    for (uint64_t r = 0; r < passes; ++r) {
+        if (eager) {
+            for (uint32_t c = 0; c < b->chunk; ++c) {
+                HIP_OR_RETURN(launch_batch_select(b->grid, st), "batch select");
+                HIP_OR_RETURN(launch_batch_scatter(b->grid, b->prog, st), "batch scatter");
+                HIP_OR_RETURN(launch_batch_gather(b->grid, b->prog, st), "batch gather");
+            }
+            HIP_OR_RETURN(launch_batch_status(b->grid, b->d_status, st), "batch status");
+        } else {
+            HIP_OR_RETURN(hipGraphLaunch(b->exec, st), "replay batch iterations");
+        }
+        HIP_OR_RETURN(hipMemcpyAsync(b->h_status.data(), b->d_status, 8 * (size_t)n, hipMemcpyDeviceToHost, st),
+                      "read run status");
+        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+        bool all = true;
+        for (uint32_t i = 0; i < n; ++i) all = all && b->h_status[2 * i];
+        if (all) break;
+    }
+    if (h_iters)
+        for (uint32_t i = 0; i < n; ++i) h_iters[i] = b->h_status[2 * i + 1];
+    return GPOP_OK;
+}
+
+int gpop_batch_check(gpop_batch* b, void* stream) {
+    if (!b) return fail(GPOP_EINVAL, "NULL batch");
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        Ctrl hc;
+        HIP_OR_RETURN(hipMemcpyAsync(&hc, b->inst[i].G.ctrl, sizeof hc, hipMemcpyDeviceToHost, st), "read control");
+        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+        if (hc.bug) return fail(GPOP_EDEVICE, "internal error in run %zu: inconsistent bin", i);
+        if (hc.err) return fail(GPOP_EINVAL, "run %zu: a frontier vertex id was >= V", i);
+    }
+    return GPOP_OK;
+}

@@ -10,20 +10,21 @@ namespace gpop {
 constexpr uint32_t kGT = 512;
 constexpr uint32_t kGW = kGT / 64;
 
-// Programs whose initFunc keeps vertices active need a per-vertex carry flag.
-__host__ __device__ constexpr bool has_carry(int prog) { return prog == P_CARRY || is_sum(prog); }
+// Programs whose initFunc keeps vertices active need a per-vertex carry flag
+// (the PageRank family keeps it in the top bit of its accumulator).
+__host__ __device__ constexpr bool has_carry(int prog) { return prog == P_CARRY; }
+constexpr unsigned long long kCarried = 1ull << 63;  // sum programs: vertex was active before scatter
 
 // LDS layout of the gather workgroup (bytes, all offsets 16-aligned). The
 // bin-list arrays double as scratch for the frontier masks in the filter.
 struct GatherLds {
-    size_t state, tag, carry, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
+    size_t state, carry, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
 };
 
 __host__ __device__ inline GatherLds gather_layout(int prog, uint32_t q) {
     GatherLds L{};
     size_t o = 0;
     L.state = o;  o += (size_t)q * (is_sum(prog) ? 8 : 4);
-    L.tag = o;    o += is_sum(prog) ? ((size_t)q * 2 + 15) / 16 * 16 : 0;
     L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
     L.bl_ioff = o; o += kGT * 4;
     L.bl_icnt = o; o += kGT * 4;
@@ -55,17 +56,17 @@ struct GatherShared {
 
 // reInit frontier: initFunc on the vertices that were active before scatter.
 template <int PROG>
-__device__ void reinit(const Dev& G, const Params& P, uint32_t it, uint32_t cq, const uint32_t* st32,
+__device__ __forceinline__ void reinit(const Dev& G, const Params& P, uint32_t it, uint32_t cq, uint32_t* st32,
                        uint8_t* carry) {
-    if constexpr (has_carry(PROG)) {
+    if constexpr (has_carry(PROG) || is_sum(PROG)) {
         const uint32_t cur = it & 1u;
         const uint32_t vbase = cq << G.s;
-        const uint32_t prevVa = G.fVa[cur][cq];
-        const uint16_t* __restrict__ prev = G.flist[cur] + vbase;
+        const uint32_t prevVa = dbuf(G.fVa, cur)[cq];
+        const uint16_t* __restrict__ prev = dbuf(G.flist, cur) + vbase;
         for (uint32_t i = threadIdx.x; i < prevVa; i += kGT) {
             const uint32_t u = prev[i];
             if constexpr (PROG == P_CARRY) carry[u] = (it + 1u - st32[u]) < P.persist;
-            else carry[u] = 1;  // PageRank family: value restarts at 0, vertex stays active
+            else reinterpret_cast<unsigned long long*>(st32)[u] |= kCarried;  // value restarts at 0, stays active
         }
     }
 }
@@ -80,7 +81,7 @@ __device__ void reinit(const Dev& G, const Params& P, uint32_t it, uint32_t cq, 
 // one scan across waves gives every wave its offsets, pass 2 writes the
 // frontier.
 template <int PROG>
-__device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __restrict__ state,
+__device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, uint32_t* __restrict__ state,
                                  uint32_t it, uint32_t cq, const uint32_t* st32,
                                  const unsigned long long* acc, const uint8_t* carry,
                                  uint64_t* kscratch, GatherShared& sh, uint32_t ids_done,
@@ -108,8 +109,9 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
                 if constexpr (has_carry(PROG)) keep = keep || carry[u];
                 if (hit) state[v] = st32[u];
             } else {
-                if (acc[u] != 0ull || carry[u]) {
-                    const double y = (double)acc[u] * kInvFix;
+                const unsigned long long a = acc[u];
+                if (a != 0ull) {  // received an amount, or was active before scatter
+                    const double y = (double)(a & ~kCarried) * kInvFix;
                     float x;
                     if constexpr (PROG == P_PR) {
                         const double d = (double)P.damping;
@@ -148,9 +150,9 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
         tot += sh.wc[w];
         etot += sh.ws[w];
     }
-    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
-    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
-    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
+    uint16_t* __restrict__ nlist = dbuf(G.flist, nxt) + vbase;
+    uint32_t* __restrict__ npre = dbuf(G.fpre, nxt) + vbase;
+    uint32_t* __restrict__ nbits = dbuf(G.fbits, nxt) + (vbase >> 5);
     for (uint32_t u0 = wb; u0 < wb + per && u0 < Q; u0 += 64) {
         const uint32_t u = u0 + lane;
         const uint64_t km = kscratch[u0 >> 6];
@@ -183,9 +185,9 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
             ni += sh.r64[w];
             d += sh.rd[w];
         }
-        G.fVa[nxt][cq] = tot;
-        G.fEa[nxt][cq] = etot;
-        G.dpart[nxt][cq] = d;
+        dbuf(G.fVa, nxt)[cq] = tot;
+        dbuf(G.fEa, nxt)[cq] = etot;
+        dbuf(G.dpart, nxt)[cq] = d;
         if (task != 0xFFFFFFFFu) G.gat_ids[task] = (uint32_t)ni;
     }
 }
@@ -203,24 +205,22 @@ __device__ void finish_partition(const Dev& G, const Params& P, uint32_t* __rest
 // Each wave decodes a contiguous run of pieces: message index of an id =
 // chunk-table base + number of message-start flags after the piece start.
 //
-// Combining is atomic-free. Min programs: every pending lane reads the state
-// word and writes its value if smaller; after a barrier each lane re-reads,
-// and only lanes whose value is still smaller stay pending. Each round lowers
-// every contested word strictly, so the loop ends with the exact minimum
-// whatever the write order. Sum programs: every pending lane writes its slot
-// number into a per-vertex tag; after a barrier the lane that finds its own
-// number adds its value (one writer per word) and the rest retry. Sums are
-// 64-bit integers in units of 2^-60, so the result is exact and independent
-// of the order of additions.
+// Combining touches only the workgroup's own LDS copy of the partition (no
+// global atomics, no locks). Min programs need no atomics at all: every
+// pending lane reads the state word and writes its value if smaller; after a
+// barrier each lane re-reads, and only lanes whose value is still smaller
+// stay pending. Each round lowers every contested word strictly, so the loop
+// ends with the exact minimum whatever the write order. Sum programs add
+// 64-bit integers in units of 2^-60 with the LDS unit's integer add, one
+// instruction per message and no rounds; integer addition is exact, so the
+// result does not depend on the order in which the adds land.
 template <int PROG>
-__global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __restrict__ state,
-                                                   uint32_t it) {
+__device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
+                                            uint32_t it, uint32_t task) {
     if (G.ctrl->done) return;
     constexpr bool SUM = is_sum(PROG);
     constexpr uint32_t IDENT = is_sum(PROG) ? kIdentSum : kIdentMin;
-    // pieces per wave per combine round (sum tags are 16-bit: kGT * 4 * PPW < 65536)
-    constexpr uint32_t PPW = SUM ? 2 : 4;
-    const uint32_t task = blockIdx.x;
+    constexpr uint32_t PPW = 4;  // pieces per wave per combine round
     const uint4 TA = G.gtask[2 * task], TB = G.gtask[2 * task + 1];
     const uint32_t cq = TA.x, p_lo = TA.y, p_hi = TA.z, nt = TA.w >> 16;
     const uint32_t s0 = TB.x, s1 = TB.y, slot = TB.z;
@@ -237,7 +237,6 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
     const GatherLds L = gather_layout(PROG, Q);
     uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
-    uint16_t* tag = reinterpret_cast<uint16_t*>(smem + L.tag);
     uint8_t* carry = smem + L.carry;   // kept active by initFunc
     uint32_t* bl_ioff = reinterpret_cast<uint32_t*>(smem + L.bl_ioff);
     uint32_t* bl_icnt = reinterpret_cast<uint32_t*>(smem + L.bl_icnt);
@@ -248,7 +247,7 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
     __shared__ GatherShared sh;
 
     // ---- anything to do for this task?
-    int any = (!split && G.fVa[cur][cq] > 0) ? 1 : 0;
+    int any = (!split && dbuf(G.fVa, cur)[cq] > 0) ? 1 : 0;
     for (uint32_t p = p_lo + tid; p <= p_hi && !any; p += kGT) {
         const uint32_t md = G.mode[p];
         const uint32_t ic = md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
@@ -260,9 +259,9 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
             if (split) {
                 G.gflag[slot] = 0;
             } else {
-                G.fVa[nxt][cq] = 0;
-                G.fEa[nxt][cq] = 0;
-                G.dpart[nxt][cq] = 0.0;
+                dbuf(G.fVa, nxt)[cq] = 0;
+                dbuf(G.fEa, nxt)[cq] = 0;
+                dbuf(G.dpart, nxt)[cq] = 0.0;
             }
             G.gat_ids[task] = 0;
             G.gat_ran[task] = 0;
@@ -368,7 +367,6 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
         const uint32_t nrounds = (per_w + PPW - 1) / PPW;
         for (uint32_t r = 0; r < nrounds; ++r) {
             uint32_t dst[4 * PPW], val[4 * PPW];
-            unsigned long long fx[SUM ? 4 * PPW : 1];
             uint32_t pend = 0;
             uint64_t raw[PPW];
             uint32_t wts[PPW], lo_x[PPW], hi_x[PPW], x0[PPW], mb[PPW], bmoff[PPW], bmcnt[PPW];
@@ -424,15 +422,19 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
                 }
                 vmaskall |= vmask << (4 * pi);
             }
-            // phase 3: drop identity messages, apply weights, convert sums
+            // phase 3: drop identity messages, apply weights; sums go straight
+            // into the accumulators
 #pragma unroll
             for (uint32_t j = 0; j < 4 * PPW; ++j) {
                 uint32_t x = val[j];
                 if (((vmaskall >> j) & 1u) && x != IDENT) {
                     if constexpr (is_weighted(PROG)) x = sat_add(x, (wts[j / 4] >> (8 * (j % 4))) & 0xFFu);
                     val[j] = x;
-                    if constexpr (SUM) fx[j] = __double2ull_rn((double)__uint_as_float(x) * kFix);
-                    pend |= 1u << j;
+                    if constexpr (SUM) {
+                        atomicAdd(acc + dst[j], __double2ull_rn((double)__uint_as_float(x) * kFix));
+                    } else {
+                        pend |= 1u << j;
+                    }
                     ++my_ids;
                 }
             }
@@ -454,82 +456,6 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
                     for (uint32_t j = 0; j < 4 * PPW; ++j)
                         if (((pend >> j) & 1u) && !(val[j] < st32[dst[j]])) pend &= ~(1u << j);
                     if (!__syncthreads_or(pend != 0)) break;
-                }
-            } else {
-                // Exact fixed-point sum. Tag rounds: every pending entry
-                // writes its slot number into its destination's tag, the
-                // entry whose tag survived adds. Each round retires one entry
-                // per destination, so a destination hit many times in one
-                // round (a high in-degree vertex) would take as many rounds;
-                // after four rounds the leftovers are first summed per
-                // destination inside each wave, which leaves at most one
-                // entry per destination per wave for the final rounds.
-                bool left = true;
-                for (int tr = 0; tr < 4 && left; ++tr) {
-#pragma unroll
-                    for (uint32_t j = 0; j < 4 * PPW; ++j)
-                        if ((pend >> j) & 1u) tag[dst[j]] = (uint16_t)(tid * 4u * PPW + j);
-                    __syncthreads();
-#pragma unroll
-                    for (uint32_t j = 0; j < 4 * PPW; ++j) {
-                        if (((pend >> j) & 1u) && tag[dst[j]] == (uint16_t)(tid * 4u * PPW + j)) {
-                            acc[dst[j]] += fx[j];
-                            pend &= ~(1u << j);
-                        }
-                    }
-                    left = __syncthreads_or(pend != 0);
-                }
-                if (left) {
-                    uint32_t adst[4 * PPW];
-                    unsigned long long afx[4 * PPW];
-                    uint32_t apend = 0, na = 0;
-                    for (;;) {  // one destination of this wave per pass
-                        const uint64_t bl = ballot(pend != 0);
-                        if (!bl) break;
-                        uint32_t mykey = 0;
-                        bool found = false;
-#pragma unroll
-                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
-                            if (!found && ((pend >> j) & 1u)) {
-                                mykey = dst[j];
-                                found = true;
-                            }
-                        }
-                        const uint32_t key = (uint32_t)__shfl((int)mykey, (int)(__ffsll((long long)bl) - 1), 64);
-                        unsigned long long sum = 0;
-#pragma unroll
-                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
-                            if (((pend >> j) & 1u) && dst[j] == key) {
-                                sum += fx[j];
-                                pend &= ~(1u << j);
-                            }
-                        }
-                        sum = wave_sum_u64(sum);
-                        const uint32_t tl = na & 63u, ts = na >> 6;
-#pragma unroll
-                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
-                            if (lane == tl && j == ts) {
-                                adst[j] = key;
-                                afx[j] = sum;
-                                apend |= 1u << j;
-                            }
-                        }
-                        ++na;
-                    }
-                    for (;;) {  // at most kGW contenders per destination
-#pragma unroll
-                        for (uint32_t j = 0; j < 4 * PPW; ++j)
-                            if ((apend >> j) & 1u) tag[adst[j]] = (uint16_t)(tid * 4u * PPW + j);
-                        __syncthreads();
-#pragma unroll
-                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
-                            if (((apend >> j) & 1u) && tag[adst[j]] == (uint16_t)(tid * 4u * PPW + j)) {
-                                acc[adst[j]] += afx[j];
-                                apend &= ~(1u << j);
-                            }
-                        }
-                        if (!__syncthreads_or(apend != 0)) break;
-                    }
                 }
             }
         }
@@ -560,15 +486,29 @@ __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __
                            reinterpret_cast<uint64_t*>(bl_ioff), sh, my_ids, task);
 }
 
+template <int PROG>
+__global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __restrict__ state,
+                                                   uint32_t it) {
+    gather_body<PROG>(G, P, state, it, blockIdx.x);
+}
+
+template <int PROG>
+__global__ __launch_bounds__(kGT, 2) void kb_gather(const Inst* __restrict__ tab,
+                                                    const uint32_t* __restrict__ boff, uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[i];
+    gather_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+}
+
 // Merge of a partition whose gather was split over several tasks: combines
 // the partial results (min, or exact fixed-point sum) with the state, then
 // runs reInit and the filter like a single-task gather.
 template <int PROG>
-__global__ __launch_bounds__(kGT, 2) void k_merge(Dev G, Params P, uint32_t* __restrict__ state,
-                                                  uint32_t it) {
+__device__ __forceinline__ void merge_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
+                                           uint32_t it, uint32_t sidx) {
     if (G.ctrl->done) return;
     constexpr bool SUM = is_sum(PROG);
-    const uint4 S = G.gsplit[blockIdx.x];
+    const uint4 S = G.gsplit[sidx];
     const uint32_t cq = S.x, nt = S.z, slot0 = S.w;
     const uint32_t Q = G.q;
     const uint32_t vbase = cq << G.s;
@@ -585,17 +525,17 @@ __global__ __launch_bounds__(kGT, 2) void k_merge(Dev G, Params P, uint32_t* __r
     {
         const uint32_t cur = it & 1u, nxt = cur ^ 1u;
         int any = threadIdx.x < 64 && s_flag[threadIdx.x];
-        any = __syncthreads_or(any || G.fVa[cur][cq] > 0);
+        any = __syncthreads_or(any || dbuf(G.fVa, cur)[cq] > 0);
         if (!any) {
             if (threadIdx.x == 0) {
-                G.fVa[nxt][cq] = 0;
-                G.fEa[nxt][cq] = 0;
-                G.dpart[nxt][cq] = 0.0;
-                G.gat_ran[G.n_gtask + blockIdx.x] = 0;
+                dbuf(G.fVa, nxt)[cq] = 0;
+                dbuf(G.fEa, nxt)[cq] = 0;
+                dbuf(G.dpart, nxt)[cq] = 0.0;
+                G.gat_ran[G.n_gtask + sidx] = 0;
             }
             return;
         }
-        if (threadIdx.x == 0) G.gat_ran[G.n_gtask + blockIdx.x] = 3;
+        if (threadIdx.x == 0) G.gat_ran[G.n_gtask + sidx] = 3;
     }
     for (uint32_t u = threadIdx.x; u < Q; u += kGT) {
         if constexpr (has_carry(PROG)) carry[u] = 0;
@@ -628,7 +568,7 @@ __global__ __launch_bounds__(kGT, 2) void k_merge(Dev G, Params P, uint32_t* __r
 #pragma unroll
             for (uint32_t i = 0; i < kMU; ++i) {
                 const uint32_t u = ub + threadIdx.x + kGT * i;
-                if (u < nv) acc[u] = a[i];
+                if (u < nv) acc[u] = a[i] | (acc[u] & kCarried);
             }
         } else {
             uint32_t m[kMU];
@@ -659,6 +599,85 @@ __global__ __launch_bounds__(kGT, 2) void k_merge(Dev G, Params P, uint32_t* __r
     __syncthreads();
     finish_partition<PROG>(G, P, state, it, cq, st32, acc, carry,
                            reinterpret_cast<uint64_t*>(smem + L.bl_ioff), sh, 0, 0xFFFFFFFFu);
+}
+
+template <int PROG>
+__global__ __launch_bounds__(kGT, 2) void k_merge(Dev G, Params P, uint32_t* __restrict__ state,
+                                                  uint32_t it) {
+    merge_body<PROG>(G, P, state, it, blockIdx.x);
+}
+
+template <int PROG>
+__global__ __launch_bounds__(kGT, 2) void kb_merge(const Inst* __restrict__ tab,
+                                                   const uint32_t* __restrict__ boff, uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[i];
+    merge_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+}
+
+// Batched: run status {done, iterations} per run, and the iteration limit of
+// the next batched run (relative to where each run stands).
+__global__ void kb_status(const Inst* __restrict__ tab, uint32_t n, uint32_t* __restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Ctrl* C = tab[i].G.ctrl;
+    out[2 * i] = C->done;
+    out[2 * i + 1] = C->iters;
+}
+
+__global__ void kb_limits(const Inst* __restrict__ tab, uint32_t n, uint32_t max_iter) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Ctrl* C = tab[i].G.ctrl;
+    const uint64_t lim = (uint64_t)C->pos + max_iter;
+    C->max_it = lim > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)lim;
+}
+
+template <int PROG>
+static hipError_t prep_batch_gather_p(const BatchGrid& B) {
+    const int lds = (int)gather_lds_bytes(PROG, B.q_max);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_gather<PROG>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kb_merge<PROG>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+template <int PROG>
+static hipError_t launch_batch_gather_p(const BatchGrid& B, hipStream_t st) {
+    const size_t lds = gather_lds_bytes(PROG, B.q_max);
+    if (B.nb_gather) hipLaunchKernelGGL(kb_gather<PROG>, dim3(B.nb_gather), dim3(kGT), lds, st, B.tab, B.b_gather, B.n);
+    if (B.nb_merge) hipLaunchKernelGGL(kb_merge<PROG>, dim3(B.nb_merge), dim3(kGT), lds, st, B.tab, B.b_merge, B.n);
+    return hipGetLastError();
+}
+
+#define GPOP_PROG_SWITCH(fn, ...)                             \
+    switch (prog) {                                           \
+        case P_BFS: return fn<P_BFS>(__VA_ARGS__);            \
+        case P_CC: return fn<P_CC>(__VA_ARGS__);              \
+        case P_SSSP: return fn<P_SSSP>(__VA_ARGS__);          \
+        case P_PR: return fn<P_PR>(__VA_ARGS__);              \
+        case P_PPR: return fn<P_PPR>(__VA_ARGS__);            \
+        case P_CARRY: return fn<P_CARRY>(__VA_ARGS__);        \
+    }                                                         \
+    return hipErrorInvalidValue;
+
+hipError_t prepare_batch_gather(const BatchGrid& B, int prog) { GPOP_PROG_SWITCH(prep_batch_gather_p, B) }
+
+hipError_t launch_batch_gather(const BatchGrid& B, int prog, hipStream_t st) {
+    GPOP_PROG_SWITCH(launch_batch_gather_p, B, st)
+}
+
+#undef GPOP_PROG_SWITCH
+
+hipError_t launch_batch_limits(const BatchGrid& B, uint32_t max_iter, hipStream_t st) {
+    hipLaunchKernelGGL(kb_limits, dim3((B.n + 63) / 64), dim3(64), 0, st, B.tab, B.n, max_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const BatchGrid& B, uint32_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(kb_status, dim3((B.n + 63) / 64), dim3(64), 0, st, B.tab, B.n, out);
+    return hipGetLastError();
 }
 
 template <int PROG>
@@ -750,6 +769,8 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
         G.ctrl->dangling = 0.0;
         G.ctrl->fin_it = 0;
         G.ctrl->mlp_fallback = 0;
+        G.ctrl->pos = 0;
+        G.ctrl->max_it = 0xFFFFFFFFu;
     }
 }
 
@@ -791,9 +812,9 @@ __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all, uint
     const uint32_t nv = min(G.q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     __shared__ uint32_t s_wc[16], s_ws[16];
-    uint16_t* list = G.flist[buf] + vbase;
-    uint32_t* pre = G.fpre[buf] + vbase;
-    uint32_t* bits = G.fbits[buf] + (vbase >> 5);
+    uint16_t* list = dbuf(G.flist, buf) + vbase;
+    uint32_t* pre = dbuf(G.fpre, buf) + vbase;
+    uint32_t* bits = dbuf(G.fbits, buf) + (vbase >> 5);
     uint32_t running = 0, erun = 0;
     for (uint32_t u0 = 0; u0 < nv; u0 += 1024) {
         const uint32_t u = u0 + tid;
@@ -830,8 +851,8 @@ __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all, uint
         __syncthreads();
     }
     if (tid == 0) {
-        G.fVa[buf][p] = running;
-        G.fEa[buf][p] = erun;
+        dbuf(G.fVa, buf)[p] = running;
+        dbuf(G.fEa, buf)[p] = erun;
     }
     if (p == 0 && tid == 0) {
         G.ctrl->done = 0;

@@ -26,6 +26,7 @@ constexpr uint32_t kLocalMask = 0x7FFFu;  // local destination id bits
 constexpr uint32_t kIdentMin = 0xFFFFFFFFu;  // min-combine identity ("no message")
 constexpr uint32_t kIdentSum = 0x80000000u;  // sum-combine identity: -0.0f bits
 constexpr uint32_t kLogCap = 4096;        // per-iteration stats records
+constexpr uint32_t kScWaves = 4;          // independent source-centric task waves per workgroup
 constexpr double kFix = 1152921504606846976.0;      // 2^60: fixed-point scale of sums
 constexpr double kInvFix = 8.673617379884035e-19;   // 2^-60
 
@@ -52,7 +53,9 @@ struct Ctrl {
     double dangling;      // PageRank-family dangling mass of the current frontier
     uint32_t fin_it;      // records below this iteration are final
     uint32_t mlp_fallback;  // partitions the learned selector left to Eq. 1
-    uint32_t pad[52];
+    uint32_t pos;         // batched runs: iterations planned (the next plan's index)
+    uint32_t max_it;      // batched runs: the plan of this iteration index ends the run
+    uint32_t pad[50];
 };
 
 // Everything the kernels read or write, by value in each launch.
@@ -127,6 +130,31 @@ struct Params {
     uint32_t ratio_num, ratio_den;  // BW_PC / BW_SC as a fraction
     uint32_t probe;           // scatter kernels time their tasks into Dev::probe
 };
+
+// One run of a batch: its graph view (static arrays shared with the graph,
+// per-run arrays of its own), its parameters and its state array.
+struct Inst {
+    Dev G;
+    Params P;
+    uint32_t* state;
+};
+
+// One of the two buffers of a double-buffered array, picked without indexing
+// the view with a run-time value (so a copied view stays in registers).
+template <class T>
+__device__ __forceinline__ T dbuf(T const (&a)[2], uint32_t b) {
+    return b ? a[1] : a[0];
+}
+
+// Batched launches: instance i owns blocks [boff[i], boff[i+1]) of the grid.
+__device__ __forceinline__ uint32_t batch_find(const uint32_t* __restrict__ boff, uint32_t n, uint32_t b) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (boff[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

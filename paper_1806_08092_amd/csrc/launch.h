@@ -48,6 +48,28 @@ hipError_t launch_part_static(const Dev& G, hipStream_t st);
 hipError_t launch_select(const Dev& G, const Params& P, uint32_t it, hipStream_t st);
 hipError_t launch_features(const Dev& G, const Params& P, uint32_t it, float* out, hipStream_t st);
 
+// batched runs: one launch per kernel covers every run of a batch
+struct BatchGrid {
+    const Inst* tab;              // [n] device
+    uint32_t n;
+    // per kernel: device block prefix over the runs (n + 1 entries) and its total
+    const uint32_t* b_select;
+    const uint32_t* b_sc;
+    const uint32_t* b_scan;
+    const uint32_t* b_pc;
+    const uint32_t* b_gather;
+    const uint32_t* b_merge;
+    uint32_t nb_select, nb_sc, nb_scan, nb_pc, nb_gather, nb_merge;
+    uint32_t k_max, q_max;
+};
+hipError_t prepare_batch_scatter(const BatchGrid& B, int prog);
+hipError_t prepare_batch_gather(const BatchGrid& B, int prog);
+hipError_t launch_batch_select(const BatchGrid& B, hipStream_t st);
+hipError_t launch_batch_scatter(const BatchGrid& B, int prog, hipStream_t st);
+hipError_t launch_batch_gather(const BatchGrid& B, int prog, hipStream_t st);
+hipError_t launch_batch_limits(const BatchGrid& B, uint32_t max_iter, hipStream_t st);
+hipError_t launch_batch_status(const BatchGrid& B, uint32_t* out, hipStream_t st);
+
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st);
 hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all,
                                uint32_t buf, hipStream_t st);

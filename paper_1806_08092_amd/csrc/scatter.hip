@@ -48,7 +48,7 @@ __device__ __forceinline__ uint32_t task_owner(const uint32_t* t0, uint32_t k, u
 // WRITE = false: adds per-destination counts to (ci, cm).
 // WRITE = true : (ci, cm) hold the task's bases; writes the bins.
 template <int PROG, bool BUILD, bool WRITE>
-__device__ void sc_wave_task(const Dev& G, const uint32_t* __restrict__ state, uint32_t p,
+__device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __restrict__ state, uint32_t p,
                              uint32_t f0, uint32_t f1, uint32_t nact,
                              const uint16_t* __restrict__ alist, const uint32_t* __restrict__ fpre,
                              uint32_t* ci, uint32_t* cm) {
@@ -149,13 +149,12 @@ __device__ void sc_wave_task(const Dev& G, const uint32_t* __restrict__ state, u
     }
 }
 
-constexpr uint32_t kScWaves = 4;  // independent task waves per workgroup
 
 // Count pass (WRITE = false) and write pass (WRITE = true) of the task waves.
 template <int PROG, bool BUILD, bool WRITE>
-__global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
-                                                           const uint32_t* __restrict__ state,
-                                                           uint32_t it) {
+__device__ __forceinline__ void sc_pass_body(const Dev& G, const Params& P,
+                                             const uint32_t* __restrict__ state, uint32_t it,
+                                             uint32_t bid, uint32_t nblk) {
     if (!BUILD && G.ctrl->done) return;
     const uint32_t cur = it & 1u;
     const uint32_t k = G.k;
@@ -165,7 +164,7 @@ __global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
     extern __shared__ uint32_t lds[];
     uint32_t* ci = lds + wave * 2 * k;
     uint32_t* cm = ci + k;
-    for (uint32_t t = blockIdx.x * kScWaves + wave; t < ntask; t += gridDim.x * kScWaves) {
+    for (uint32_t t = bid * kScWaves + wave; t < ntask; t += nblk * kScWaves) {
         const uint64_t t_beg = (!BUILD && P.probe) ? wall_clock64() : 0;
         uint2* __restrict__ tc = G.sc_tc + (size_t)t * k;
         for (uint32_t j = lane; j < k; j += 64) {
@@ -182,12 +181,12 @@ __global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
         const uint32_t jt = t - t0[p];
         const uint32_t vbase = p << G.s;
         const uint32_t nv = min(G.q, G.V - vbase);
-        const uint32_t Ea = BUILD ? G.part_E[p] : G.fEa[cur][p];
-        const uint32_t nact = BUILD ? nv : G.fVa[cur][p];
+        const uint32_t Ea = BUILD ? G.part_E[p] : dbuf(G.fEa, cur)[p];
+        const uint32_t nact = BUILD ? nv : dbuf(G.fVa, cur)[p];
         const uint32_t f0 = jt << G.sc_shift;
         const uint32_t f1 = min(f0 + (1u << G.sc_shift), Ea);
-        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, G.flist[cur] + vbase,
-                                         G.fpre[cur] + vbase, ci, cm);
+        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, dbuf(G.flist, cur) + vbase,
+                                         dbuf(G.fpre, cur) + vbase, ci, cm);
         if constexpr (!WRITE) {
             for (uint32_t j = lane; j < k; j += 64) tc[j] = make_uint2(cm[j], ci[j]);
         }
@@ -196,14 +195,30 @@ __global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
     }
 }
 
+template <int PROG, bool BUILD, bool WRITE>
+__global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
+                                                           const uint32_t* __restrict__ state,
+                                                           uint32_t it) {
+    sc_pass_body<PROG, BUILD, WRITE>(G, P, state, it, blockIdx.x, gridDim.x);
+}
+
+template <int PROG, bool WRITE>
+__global__ __launch_bounds__(kScWaves * 64) void kb_sc_pass(const Inst* __restrict__ tab,
+                                                            const uint32_t* __restrict__ boff,
+                                                            uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[i];
+    sc_pass_body<PROG, false, WRITE>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i],
+                                     boff[i + 1] - boff[i]);
+}
+
 // Scan pass: per source partition p and destination q, exclusive scan of the
 // task counts over the tasks of p (in place), giving each task its base in
 // bin[p][q]; the totals are the bin's message and id counts this iteration.
 // 16 strips of tasks x 64 destinations per round; strip sums are scanned in
 // LDS, then each strip rewrites its counts as bases.
 template <bool BUILD>
-__global__ __launch_bounds__(1024) void k_sc_scan(Dev G) {
-    const uint32_t p = blockIdx.x;
+__device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p) {
     if constexpr (!BUILD) {
         if (G.ctrl->done) return;
         if (G.mode[p] != GPOP_MODE_SC) return;
@@ -278,6 +293,17 @@ __global__ __launch_bounds__(1024) void k_sc_scan(Dev G) {
     }
 }
 
+template <bool BUILD>
+__global__ __launch_bounds__(1024) void k_sc_scan(Dev G) {
+    sc_scan_body<BUILD>(G, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void kb_sc_scan(const Inst* __restrict__ tab,
+                                                   const uint32_t* __restrict__ boff, uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    sc_scan_body<false>(tab[i].G, blockIdx.x - boff[i]);
+}
+
 size_t sc_lds_bytes(uint32_t k) { return (size_t)kScWaves * 2 * k * 4; }
 
 template <int PROG, bool BUILD, bool WRITE>
@@ -343,10 +369,10 @@ hipError_t launch_scatter_sc(const Dev& G, const Params& P, int prog, const uint
 // at most kPcTask slots so hub partitions spread over many workgroups.
 // ---------------------------------------------------------------------------
 template <int PROG>
-__global__ __launch_bounds__(256) void k_pc(Dev G, Params P, const uint32_t* __restrict__ state,
-                                            uint32_t it) {
+__device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uint32_t* __restrict__ state,
+                                        uint32_t it, uint32_t task) {
     if (G.ctrl->done) return;
-    const uint4 t = G.pctask[blockIdx.x];
+    const uint4 t = G.pctask[task];
     const uint32_t p = t.x;
     if (G.mode[p] != GPOP_MODE_PC) return;
     uint64_t t_beg = 0;
@@ -358,7 +384,7 @@ __global__ __launch_bounds__(256) void k_pc(Dev G, Params P, const uint32_t* __r
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
     extern __shared__ uint32_t mv[];
-    const uint32_t* __restrict__ bits = G.fbits[cur] + (vbase >> 5);
+    const uint32_t* __restrict__ bits = dbuf(G.fbits, cur) + (vbase >> 5);
     for (uint32_t v = threadIdx.x; v < nv; v += 256)
         mv[v] = test_bit(bits, v) ? scatter_value<PROG>(G, state, vbase + v) : ident_of<PROG>();
     __syncthreads();
@@ -384,6 +410,20 @@ __global__ __launch_bounds__(256) void k_pc(Dev G, Params P, const uint32_t* __r
         if (threadIdx.x == 0)
             atomicAdd(G.probe + 2 * G.k + p, 4ull * (unsigned long long)(wall_clock64() - t_beg));
     }
+}
+
+template <int PROG>
+__global__ __launch_bounds__(256) void k_pc(Dev G, Params P, const uint32_t* __restrict__ state,
+                                            uint32_t it) {
+    pc_body<PROG>(G, P, state, it, blockIdx.x);
+}
+
+template <int PROG>
+__global__ __launch_bounds__(256) void kb_pc(const Inst* __restrict__ tab, const uint32_t* __restrict__ boff,
+                                             uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[i];
+    pc_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
 }
 
 template <int PROG>
@@ -415,7 +455,7 @@ hipError_t launch_scatter_pc(const Dev& G, const Params& P, int prog, const uint
 // Fills the stats record of iteration it - 1 (source-centric totals and ids
 // gathered) from per-partition values the previous iteration wrote. Reads
 // mode[], so it must run before the next plan overwrites it.
-__device__ void finalize_prev(const Dev& G, uint32_t it) {
+__device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
     __shared__ uint64_t red[6][16];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     uint64_t v[6] = {0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged
@@ -454,7 +494,7 @@ __device__ void finalize_prev(const Dev& G, uint32_t it) {
 
 // Runs finalize_prev once per iteration: a probe scatter or a stats read may
 // come before the plan of the same iteration, and both rewrite what it reads.
-__device__ void finalize_once(const Dev& G, uint32_t it) {
+__device__ __forceinline__ void finalize_once(const Dev& G, uint32_t it) {
     __shared__ uint32_t s_need;
     if (threadIdx.x == 0) s_need = it > 0 && G.ctrl->fin_it < it;
     __syncthreads();
@@ -466,7 +506,7 @@ __device__ void finalize_once(const Dev& G, uint32_t it) {
 
 __global__ __launch_bounds__(1024) void k_finalize(Dev G, uint32_t it) { finalize_once(G, it); }
 
-__global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
+__device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_t it) {
     Ctrl* C = G.ctrl;
     if (C->done) return;
     const uint32_t cur = it & 1u;
@@ -482,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
         const uint32_t p = p0 + tid;
         uint32_t ntask = 0;
         if (p < G.k) {
-            const uint32_t Va = G.fVa[cur][p], Ea = G.fEa[cur][p];
+            const uint32_t Va = dbuf(G.fVa, cur)[p], Ea = dbuf(G.fEa, cur)[p];
             uint8_t md = GPOP_MODE_NONE;
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
@@ -504,7 +544,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
                 sea += Ea;
                 ntask = (Ea + (1u << G.sc_shift) - 1u) >> G.sc_shift;
             }
-            dang += G.dpart[cur][p];
+            dang += dbuf(G.dpart, cur)[p];
         }
         // exclusive scan of the task counts in partition order
         const uint32_t incl = wave_incl_scan(ntask);
@@ -578,6 +618,70 @@ __global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) {
         }
     }
 }
+
+__global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) { plan_body(G, P, it); }
+
+// Batched plan, one workgroup per run: the iteration index comes from the
+// run's control block; reaching its limit ends the run.
+__global__ __launch_bounds__(1024) void kb_plan(const Inst* __restrict__ tab) {
+    const Dev& G = tab[blockIdx.x].G;
+    const Params& P = tab[blockIdx.x].P;
+    Ctrl* C = G.ctrl;
+    if (C->done) return;
+    const uint32_t it = C->pos;
+    if (it >= C->max_it) {
+        if (threadIdx.x == 0) C->done = 1;
+        return;
+    }
+    plan_body(G, P, it);
+    if (threadIdx.x == 0 && !C->done) C->pos = it + 1;
+}
+
+template <int PROG>
+static hipError_t prep_batch_scatter_p(const BatchGrid& B) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_sc_pass<PROG, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sc_lds_bytes(B.k_max));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_sc_pass<PROG, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sc_lds_bytes(B.k_max));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kb_pc<PROG>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(B.q_max * 4));
+}
+
+template <int PROG>
+static hipError_t launch_batch_scatter_p(const BatchGrid& B, hipStream_t st) {
+    hipLaunchKernelGGL(kb_plan, dim3(B.n), dim3(1024), 0, st, B.tab);
+    if (B.nb_sc) {
+        hipLaunchKernelGGL((kb_sc_pass<PROG, false>), dim3(B.nb_sc), dim3(kScWaves * 64), sc_lds_bytes(B.k_max),
+                           st, B.tab, B.b_sc, B.n);
+        hipLaunchKernelGGL(kb_sc_scan, dim3(B.nb_scan), dim3(1024), 0, st, B.tab, B.b_scan, B.n);
+        hipLaunchKernelGGL((kb_sc_pass<PROG, true>), dim3(B.nb_sc), dim3(kScWaves * 64), sc_lds_bytes(B.k_max),
+                           st, B.tab, B.b_sc, B.n);
+    }
+    if (B.nb_pc)
+        hipLaunchKernelGGL(kb_pc<PROG>, dim3(B.nb_pc), dim3(256), (size_t)B.q_max * 4, st, B.tab, B.b_pc, B.n);
+    return hipGetLastError();
+}
+
+#define GPOP_PROG_SWITCH(fn, ...)                             \
+    switch (prog) {                                           \
+        case P_BFS: return fn<P_BFS>(__VA_ARGS__);            \
+        case P_CC: return fn<P_CC>(__VA_ARGS__);              \
+        case P_SSSP: return fn<P_SSSP>(__VA_ARGS__);          \
+        case P_PR: return fn<P_PR>(__VA_ARGS__);              \
+        case P_PPR: return fn<P_PPR>(__VA_ARGS__);            \
+        case P_CARRY: return fn<P_CARRY>(__VA_ARGS__);        \
+    }                                                         \
+    return hipErrorInvalidValue;
+
+hipError_t prepare_batch_scatter(const BatchGrid& B, int prog) { GPOP_PROG_SWITCH(prep_batch_scatter_p, B) }
+
+hipError_t launch_batch_scatter(const BatchGrid& B, int prog, hipStream_t st) {
+    GPOP_PROG_SWITCH(launch_batch_scatter_p, B, st)
+}
+
+#undef GPOP_PROG_SWITCH
 
 hipError_t launch_plan(const Dev& G, const Params& P, uint32_t it, hipStream_t st) {
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, G, P, it);

@@ -43,24 +43,24 @@ __global__ __launch_bounds__(256) void k_part_static(Dev G) {
 // Sum of E_a over all partitions / |E| (every wave computes it).
 __device__ inline float active_edge_fraction(const Dev& G, uint32_t cur) {
     uint64_t s = 0;
-    for (uint32_t j = lane_id(); j < G.k; j += 64) s += G.fEa[cur][j];
+    for (uint32_t j = lane_id(); j < G.k; j += 64) s += dbuf(G.fEa, cur)[j];
     s = wave_sum_u64(s);
     return G.E ? (float)((double)s / (double)G.E) : 0.f;
 }
 
 // Learned selection for the plan of iteration `it`: one lane per partition.
-__global__ __launch_bounds__(64) void k_select(Dev G, Params P, uint32_t it) {
+__device__ __forceinline__ void select_body(const Dev& G, const Params& P, uint32_t it, uint32_t bid) {
     if (G.ctrl->done) return;
     const uint32_t cur = it & 1u;
     const float ea_frac = active_edge_fraction(G, cur);
-    const uint32_t p = blockIdx.x * 64 + lane_id();
+    const uint32_t p = bid * 64 + lane_id();
     if (p >= G.k) return;
-    const uint32_t Va = G.fVa[cur][p];
+    const uint32_t Va = dbuf(G.fVa, cur)[p];
     if (!Va) {
         G.mode_l[p] = GPOP_MODE_NONE;
         return;
     }
-    const uint32_t Ea = G.fEa[cur][p];
+    const uint32_t Ea = dbuf(G.fEa, cur)[p];
     float f[GPOP_MLP_IN];
     partition_features(G, P, p, Va, Ea, it, ea_frac, f);
     float z;
@@ -74,14 +74,33 @@ __global__ __launch_bounds__(64) void k_select(Dev G, Params P, uint32_t it) {
     G.mode_l[p] = md;
 }
 
+__global__ __launch_bounds__(64) void k_select(Dev G, Params P, uint32_t it) {
+    select_body(G, P, it, blockIdx.x);
+}
+
+// Batched: runs whose selector is not the learned one skip.
+__global__ __launch_bounds__(64) void kb_select(const Inst* __restrict__ tab,
+                                                const uint32_t* __restrict__ boff, uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[i];
+    if (I.P.selector != GPOP_SEL_LEARNED) return;
+    select_body(I.G, I.P, I.G.ctrl->pos, blockIdx.x - boff[i]);
+}
+
 __global__ __launch_bounds__(64) void k_features(Dev G, Params P, uint32_t it, float* __restrict__ out) {
     const uint32_t cur = it & 1u;
     const float ea_frac = active_edge_fraction(G, cur);
     const uint32_t p = blockIdx.x * 64 + lane_id();
     if (p >= G.k) return;
     float f[GPOP_MLP_IN];
-    partition_features(G, P, p, G.fVa[cur][p], G.fEa[cur][p], it, ea_frac, f);
+    partition_features(G, P, p, dbuf(G.fVa, cur)[p], dbuf(G.fEa, cur)[p], it, ea_frac, f);
     for (int i = 0; i < GPOP_MLP_IN; ++i) out[(size_t)p * GPOP_MLP_IN + i] = f[i];
+}
+
+hipError_t launch_batch_select(const BatchGrid& B, hipStream_t st) {
+    if (B.nb_select == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_select, dim3(B.nb_select), dim3(64), 0, st, B.tab, B.b_select, B.n);
+    return hipGetLastError();
 }
 
 hipError_t launch_part_static(const Dev& G, hipStream_t st) {

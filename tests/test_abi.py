@@ -76,3 +76,16 @@ def test_mlp_workspace_size():
     assert L.gpop_mlp_grad_workspace(1) == 5059 * 4
     assert L.gpop_mlp_grad_workspace(64) == 5059 * 4
     assert L.gpop_mlp_grad_workspace(65) == 2 * 5059 * 4
+
+
+def test_batch_entry_points_reject_bad_arguments_on_host():
+    L = gp.lib()
+    n = ctypes.c_uint64()
+    assert L.gpop_batch_plan(None, 0, ctypes.byref(n)) == gp.EINVAL
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.gpop_batch_plan(arr, 2, ctypes.byref(n)) == gp.EINVAL
+    assert L.gpop_batch_destroy(None) == gp.OK
+    assert L.gpop_batch_run(None, 10, 0, None, None) == gp.EINVAL
+    assert L.gpop_batch_state_init(None, 0, None, None, None) == gp.EINVAL
+    assert L.gpop_batch_set_frontier(None, 0, None, 0, None) == gp.EINVAL
+    assert L.gpop_batch_check(None, None) == gp.EINVAL
