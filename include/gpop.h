@@ -308,6 +308,45 @@ int gpop_batch_run(struct gpop_batch* b, uint32_t max_iter, uint32_t flags, uint
 /* gpop_check for every run. Synchronises `stream`. */
 int gpop_batch_check(struct gpop_batch* b, void* stream);
 
+/* -------------------------------------------------------------- autotuner */
+
+/* Tuning space: partition size 2^log2_part (the paper's partition-size
+ * parameter, sized here to the workgroup's on-chip memory) and the "bin tile
+ * shape": ids per gather task (gather_task_ids) and active edges per
+ * source-centric task (2^sc_task_log2). */
+#define GPOP_TUNE_MAX 64
+
+typedef struct gpop_tune_result {
+    gpop_options best;             /* fastest candidate                          */
+    float best_ms;                 /* its run time                               */
+    uint32_t n_tried;              /* candidates that could run                  */
+    float run_ms[GPOP_TUNE_MAX];   /* per candidate (in the order given): fastest of the
+                                      repetitions, or a negative value if it could not
+                                      run (plan, workspace or on-chip memory)     */
+    float prep_ms[GPOP_TUNE_MAX];  /* preprocessing time of each candidate       */
+} gpop_tune_result;
+
+/* Fills out[0..*n) with the default candidates for `prog` on a graph of V
+ * vertices and E edges: every partition size from 2^12 to 2^15 whose gather
+ * fits on chip (one size at least V, at most), crossed with gather tasks of
+ * the default size or 2^16 ids and source-centric tasks of the default size
+ * or 2^12 edges. */
+int gpop_autotune_candidates(gpop_program prog, uint32_t num_vertices, uint64_t num_edges,
+                             gpop_options* out, uint32_t cap, uint32_t* n);
+
+/* Times `prog` on the graph for each candidate: builds the layout in the
+ * caller's workspace (at least the largest gpop_plan size of the
+ * candidates), binds d_state, sets the frontier (d_frontier[0..n_frontier),
+ * or every vertex when d_frontier is NULL), runs at most max_iter
+ * iterations `reps` times, keeps the fastest. The graph layout built last is
+ * released; build the chosen one with gpop_graph_create. Synchronises
+ * `stream`. Errors: GPOP_EINVAL (bad arguments, n_cand = 0 or >
+ * GPOP_TUNE_MAX), GPOP_ENOTSUP if no candidate could run. */
+int gpop_autotune(const gpop_graph_desc* desc, gpop_program prog, const gpop_params* prm,
+                  const uint32_t* d_frontier, uint32_t n_frontier, uint32_t max_iter, uint32_t reps,
+                  const gpop_options* cands, uint32_t n_cand, void* d_ws, size_t ws_bytes,
+                  void* d_state, void* stream, gpop_tune_result* out);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Kernel identifiers for gpop_profile_read. */

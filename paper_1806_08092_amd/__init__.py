@@ -84,6 +84,14 @@ class IterStats(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
 
 
+TUNE_MAX = 64
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", Options), ("best_ms", ctypes.c_float), ("n_tried", ctypes.c_uint32),
+                ("run_ms", ctypes.c_float * TUNE_MAX), ("prep_ms", ctypes.c_float * TUNE_MAX)]
+
+
 _lib = None
 
 _SIGS = {
@@ -145,6 +153,12 @@ _SIGS = {
     "gpop_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                       ctypes.c_void_p]),
     "gpop_batch_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gpop_autotune_candidates": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p,
+                                                ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
+    "gpop_autotune": (ctypes.c_int, [ctypes.POINTER(GraphDesc), ctypes.c_int, ctypes.POINTER(Params),
+                                     ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(TuneResult)]),
 }
 
 
@@ -324,6 +338,48 @@ class Graph:
         n = (ctypes.c_uint64 * nk)()
         _check(lib().gpop_profile_read(self.h, ms, n, _stream(stream)))
         return {KERNELS[i]: (ms[i], int(n[i])) for i in range(nk)}
+
+
+def autotune_candidates(prog, num_vertices: int, num_edges: int):
+    """Default tuning candidates (list of dicts) for a program and graph size."""
+    prog = PROGRAMS[prog] if isinstance(prog, str) else int(prog)
+    buf = (Options * TUNE_MAX)()
+    n = ctypes.c_uint32()
+    _check(lib().gpop_autotune_candidates(prog, num_vertices, num_edges, buf, TUNE_MAX, ctypes.byref(n)))
+    return [{"log2_part": buf[i].log2_part, "sc_task_log2": buf[i].sc_task_log2,
+             "gather_task_ids": buf[i].gather_task_ids} for i in range(n.value)]
+
+
+def autotune(offsets, cols, weights, prog, root: int = 0, persist: int = 1, damping: float = 0.85,
+             alpha: float = 0.15, frontier=None, max_iter: int = 3, reps: int = 2, candidates=None,
+             stream=None):
+    """Times the candidates (default: autotune_candidates) through
+    gpop_autotune and returns (best options dict, per-candidate list of
+    (options, run_ms, prep_ms))."""
+    import torch
+    prog_id = PROGRAMS[prog] if isinstance(prog, str) else int(prog)
+    n, m = offsets.numel() - 1, cols.numel()
+    cands = candidates or autotune_candidates(prog_id, n, m)
+    carr = (Options * len(cands))(*[Options(c["log2_part"], c["sc_task_log2"], c["gather_task_ids"])
+                                    for c in cands])
+    desc = GraphDesc(n, 0, m, offsets.data_ptr(), cols.data_ptr() if m else 0,
+                     None if weights is None else weights.data_ptr())
+    need = 0
+    for i in range(len(cands)):
+        info = PlanInfo()
+        if lib().gpop_plan(ctypes.byref(desc), ctypes.byref(carr[i]), ctypes.byref(info)) == OK:
+            need = max(need, info.workspace_bytes)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=offsets.device)
+    aligned = (ws.data_ptr() + 255) & ~255
+    state = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    p = Params(root, persist, damping, alpha)
+    res = TuneResult()
+    _check(lib().gpop_autotune(ctypes.byref(desc), prog_id, ctypes.byref(p), _ptr(frontier),
+                               0 if frontier is None else frontier.numel(), max_iter, reps, carr, len(cands),
+                               ctypes.c_void_p(aligned), need, _ptr(state), _stream(stream), ctypes.byref(res)))
+    best = {"log2_part": res.best.log2_part, "sc_task_log2": res.best.sc_task_log2,
+            "gather_task_ids": res.best.gather_task_ids}
+    return best, [(cands[i], res.run_ms[i], res.prep_ms[i]) for i in range(len(cands))]
 
 
 BATCH_EAGER = 1

@@ -225,6 +225,8 @@ int collect_profile(gpop_graph* g) {
     return GPOP_OK;
 }
 
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950: on-chip memory a workgroup may use
+
 int max_lds_per_block() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 65536;
@@ -1042,5 +1044,98 @@ int gpop_batch_check(gpop_batch* b, void* stream) {
         if (hc.bug) return fail(GPOP_EDEVICE, "internal error in run %zu: inconsistent bin", i);
         if (hc.err) return fail(GPOP_EINVAL, "run %zu: a frontier vertex id was >= V", i);
     }
+    return GPOP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: partition size and bin tile shape per graph and program.
+// ---------------------------------------------------------------------------
+int gpop_autotune_candidates(gpop_program prog, uint32_t num_vertices, uint64_t num_edges, gpop_options* out,
+                             uint32_t cap, uint32_t* n) {
+    if (!out || !n) return fail(GPOP_EINVAL, "NULL argument");
+    if ((int)prog < 0 || (int)prog > GPOP_PROG_CARRY_BFS) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
+    (void)num_edges;
+    uint32_t c = 0;
+    for (uint32_t lp = 12; lp <= 15; ++lp) {
+        if (gather_lds_bytes((int)prog, 1u << lp) + 2048 > kLdsPerWorkgroup) continue;
+        const uint32_t gids[2] = {0, 1u << 16};
+        const uint32_t scs[2] = {0, 12};
+        for (uint32_t a = 0; a < 2; ++a)
+            for (uint32_t b = 0; b < 2; ++b) {
+                if (c >= cap) return fail(GPOP_EINVAL, "capacity %u too small", cap);
+                gpop_options o{};
+                o.log2_part = lp;
+                o.gather_task_ids = gids[a];
+                o.sc_task_log2 = scs[b];
+                out[c++] = o;
+            }
+        if ((1ull << lp) >= num_vertices) break;  // larger partitions add nothing
+    }
+    *n = c;
+    return GPOP_OK;
+}
+
+int gpop_autotune(const gpop_graph_desc* desc, gpop_program prog, const gpop_params* prm,
+                  const uint32_t* d_frontier, uint32_t n_frontier, uint32_t max_iter, uint32_t reps,
+                  const gpop_options* cands, uint32_t n_cand, void* d_ws, size_t ws_bytes, void* d_state,
+                  void* stream, gpop_tune_result* out) {
+    if (!desc || !prm || !cands || !d_ws || !d_state || !out) return fail(GPOP_EINVAL, "NULL argument");
+    if (n_cand == 0 || n_cand > GPOP_TUNE_MAX) return fail(GPOP_EINVAL, "n_cand must be in [1, %d]", GPOP_TUNE_MAX);
+    if (n_frontier && !d_frontier) return fail(GPOP_EINVAL, "NULL frontier");
+    if (reps == 0) reps = 1;
+    memset(out, 0, sizeof *out);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_OR_RETURN(hipEventCreate(&e0), "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GPOP_EDEVICE, "event");
+    }
+    int best = -1;
+    int rc = GPOP_OK;
+    for (uint32_t c = 0; c < n_cand && rc == GPOP_OK; ++c) {
+        out->run_ms[c] = -1.f;
+        out->prep_ms[c] = -1.f;
+        gpop_plan_info pi;
+        if (gpop_plan(desc, &cands[c], &pi) != GPOP_OK || pi.workspace_bytes > ws_bytes) continue;
+        (void)hipEventRecord(e0, st);
+        gpop_graph* g = nullptr;
+        if (gpop_graph_create(desc, &cands[c], d_ws, ws_bytes, stream, &g) != GPOP_OK) continue;
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float pms = 0.f;
+        (void)hipEventElapsedTime(&pms, e0, e1);
+        out->prep_ms[c] = pms;
+        if (check_program(g, prog, prm) != GPOP_OK) {
+            gpop_graph_destroy(g);
+            continue;
+        }
+        float bestc = -1.f;
+        for (uint32_t r = 0; r < reps && rc == GPOP_OK; ++r) {
+            (void)hipEventRecord(e0, st);
+            rc = gpop_state_init(g, prog, prm, d_state, stream);
+            if (!rc) rc = d_frontier ? gpop_set_frontier(g, d_frontier, n_frontier, stream)
+                                     : gpop_set_frontier_all(g, stream);
+            if (!rc) rc = gpop_run(g, max_iter, nullptr, stream);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (!rc && (bestc < 0.f || ms < bestc)) bestc = ms;
+        }
+        gpop_graph_destroy(g);
+        if (rc) break;
+        out->run_ms[c] = bestc;
+        out->n_tried++;
+        if (best < 0 || bestc < out->best_ms) {
+            best = (int)c;
+            out->best_ms = bestc;
+            out->best = cands[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (best < 0) return fail(GPOP_ENOTSUP, "no candidate could run");
     return GPOP_OK;
 }

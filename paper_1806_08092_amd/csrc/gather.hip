@@ -61,8 +61,8 @@ __device__ __forceinline__ void reinit(const Dev& G, const Params& P, uint32_t i
     if constexpr (has_carry(PROG) || is_sum(PROG)) {
         const uint32_t cur = it & 1u;
         const uint32_t vbase = cq << G.s;
-        const uint32_t prevVa = dbuf(G.fVa, cur)[cq];
-        const uint16_t* __restrict__ prev = dbuf(G.flist, cur) + vbase;
+        const uint32_t prevVa = G.fVa[cur][cq];
+        const uint16_t* __restrict__ prev = G.flist[cur] + vbase;
         for (uint32_t i = threadIdx.x; i < prevVa; i += kGT) {
             const uint32_t u = prev[i];
             if constexpr (PROG == P_CARRY) carry[u] = (it + 1u - st32[u]) < P.persist;
@@ -150,9 +150,9 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
         tot += sh.wc[w];
         etot += sh.ws[w];
     }
-    uint16_t* __restrict__ nlist = dbuf(G.flist, nxt) + vbase;
-    uint32_t* __restrict__ npre = dbuf(G.fpre, nxt) + vbase;
-    uint32_t* __restrict__ nbits = dbuf(G.fbits, nxt) + (vbase >> 5);
+    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
+    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
+    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
     for (uint32_t u0 = wb; u0 < wb + per && u0 < Q; u0 += 64) {
         const uint32_t u = u0 + lane;
         const uint64_t km = kscratch[u0 >> 6];
@@ -185,9 +185,9 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
             ni += sh.r64[w];
             d += sh.rd[w];
         }
-        dbuf(G.fVa, nxt)[cq] = tot;
-        dbuf(G.fEa, nxt)[cq] = etot;
-        dbuf(G.dpart, nxt)[cq] = d;
+        G.fVa[nxt][cq] = tot;
+        G.fEa[nxt][cq] = etot;
+        G.dpart[nxt][cq] = d;
         if (task != 0xFFFFFFFFu) G.gat_ids[task] = (uint32_t)ni;
     }
 }
@@ -223,6 +223,15 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     constexpr uint32_t PPW = 4;  // pieces per wave per combine round
     const uint4 TA = G.gtask[2 * task], TB = G.gtask[2 * task + 1];
     const uint32_t cq = TA.x, p_lo = TA.y, p_hi = TA.z, nt = TA.w >> 16;
+    // the two id / weight / chunk arrays a piece may come from, as uniform
+    // values (a per-lane choice between two fields of the view would
+    // otherwise become a per-lane load of the pointer itself)
+    const uint16_t* __restrict__ ids_sc = uniform_ptr(G.sc_ids);
+    const uint16_t* __restrict__ ids_pc = uniform_ptr(G.png_ids);
+    const uint8_t* __restrict__ w_sc = uniform_ptr(G.sc_w);
+    const uint8_t* __restrict__ w_pc = uniform_ptr(G.png_w);
+    const uint32_t* __restrict__ ch_sc = uniform_ptr(G.sc_chunk);
+    const uint32_t* __restrict__ ch_pc = uniform_ptr(G.png_chunk);
     const uint32_t s0 = TB.x, s1 = TB.y, slot = TB.z;
     const bool split = nt > 1;
     const uint32_t cur = it & 1u, nxt = cur ^ 1u;
@@ -247,7 +256,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     __shared__ GatherShared sh;
 
     // ---- anything to do for this task?
-    int any = (!split && dbuf(G.fVa, cur)[cq] > 0) ? 1 : 0;
+    int any = (!split && G.fVa[cur][cq] > 0) ? 1 : 0;
     for (uint32_t p = p_lo + tid; p <= p_hi && !any; p += kGT) {
         const uint32_t md = G.mode[p];
         const uint32_t ic = md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
@@ -259,9 +268,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
             if (split) {
                 G.gflag[slot] = 0;
             } else {
-                dbuf(G.fVa, nxt)[cq] = 0;
-                dbuf(G.fEa, nxt)[cq] = 0;
-                dbuf(G.dpart, nxt)[cq] = 0.0;
+                G.fVa[nxt][cq] = 0;
+                G.fEa[nxt][cq] = 0;
+                G.dpart[nxt][cq] = 0.0;
             }
             G.gat_ids[task] = 0;
             G.gat_ran[task] = 0;
@@ -387,11 +396,11 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                 hi_x[pi] = live ? min(bioff + bicnt, c * kChunk + kChunk) : 0u;
                 x0[pi] = c * kChunk + lane * 4u;
                 const bool any4 = x0[pi] + 3u >= lo_x[pi] && x0[pi] < hi_x[pi];
-                raw[pi] = any4 ? *reinterpret_cast<const uint64_t*>((sc ? G.sc_ids : G.png_ids) + x0[pi]) : 0ull;
+                raw[pi] = any4 ? *reinterpret_cast<const uint64_t*>((sc ? ids_sc : ids_pc) + x0[pi]) : 0ull;
                 wts[pi] = 0;
                 if constexpr (is_weighted(PROG))
-                    wts[pi] = any4 ? *reinterpret_cast<const uint32_t*>((sc ? G.sc_w : G.png_w) + x0[pi]) : 0u;
-                mb[pi] = (live && lo_x[pi] != bioff) ? (sc ? G.sc_chunk[c] : G.png_chunk[c]) : 0u;
+                    wts[pi] = any4 ? *reinterpret_cast<const uint32_t*>((sc ? w_sc : w_pc) + x0[pi]) : 0u;
+                mb[pi] = (live && lo_x[pi] != bioff) ? (sc ? ch_sc : ch_pc)[c] : 0u;
             }
             // phase 2: message indices and value loads
             uint32_t vmaskall = 0;
@@ -525,12 +534,12 @@ __device__ __forceinline__ void merge_body(const Dev& G, const Params& P, uint32
     {
         const uint32_t cur = it & 1u, nxt = cur ^ 1u;
         int any = threadIdx.x < 64 && s_flag[threadIdx.x];
-        any = __syncthreads_or(any || dbuf(G.fVa, cur)[cq] > 0);
+        any = __syncthreads_or(any || G.fVa[cur][cq] > 0);
         if (!any) {
             if (threadIdx.x == 0) {
-                dbuf(G.fVa, nxt)[cq] = 0;
-                dbuf(G.fEa, nxt)[cq] = 0;
-                dbuf(G.dpart, nxt)[cq] = 0.0;
+                G.fVa[nxt][cq] = 0;
+                G.fEa[nxt][cq] = 0;
+                G.dpart[nxt][cq] = 0.0;
                 G.gat_ran[G.n_gtask + sidx] = 0;
             }
             return;
@@ -812,9 +821,9 @@ __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all, uint
     const uint32_t nv = min(G.q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     __shared__ uint32_t s_wc[16], s_ws[16];
-    uint16_t* list = dbuf(G.flist, buf) + vbase;
-    uint32_t* pre = dbuf(G.fpre, buf) + vbase;
-    uint32_t* bits = dbuf(G.fbits, buf) + (vbase >> 5);
+    uint16_t* list = G.flist[buf] + vbase;
+    uint32_t* pre = G.fpre[buf] + vbase;
+    uint32_t* bits = G.fbits[buf] + (vbase >> 5);
     uint32_t running = 0, erun = 0;
     for (uint32_t u0 = 0; u0 < nv; u0 += 1024) {
         const uint32_t u = u0 + tid;
@@ -851,8 +860,8 @@ __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all, uint
         __syncthreads();
     }
     if (tid == 0) {
-        dbuf(G.fVa, buf)[p] = running;
-        dbuf(G.fEa, buf)[p] = erun;
+        G.fVa[buf][p] = running;
+        G.fEa[buf][p] = erun;
     }
     if (p == 0 && tid == 0) {
         G.ctrl->done = 0;

@@ -139,11 +139,15 @@ struct Inst {
     uint32_t* state;
 };
 
-// One of the two buffers of a double-buffered array, picked without indexing
-// the view with a run-time value (so a copied view stays in registers).
+// A global-memory pointer every lane holds the same value of, made opaque to
+// the compiler (it stays a scalar value and keeps its address space).
 template <class T>
-__device__ __forceinline__ T dbuf(T const (&a)[2], uint32_t b) {
-    return b ? a[1] : a[0];
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    typedef __attribute__((address_space(1))) T GlobalT;
+    return (T*)(GlobalT*)(((uint64_t)hi << 32) | lo);
 }
 
 // Batched launches: instance i owns blocks [boff[i], boff[i+1]) of the grid.

@@ -181,12 +181,12 @@ __device__ __forceinline__ void sc_pass_body(const Dev& G, const Params& P,
         const uint32_t jt = t - t0[p];
         const uint32_t vbase = p << G.s;
         const uint32_t nv = min(G.q, G.V - vbase);
-        const uint32_t Ea = BUILD ? G.part_E[p] : dbuf(G.fEa, cur)[p];
-        const uint32_t nact = BUILD ? nv : dbuf(G.fVa, cur)[p];
+        const uint32_t Ea = BUILD ? G.part_E[p] : G.fEa[cur][p];
+        const uint32_t nact = BUILD ? nv : G.fVa[cur][p];
         const uint32_t f0 = jt << G.sc_shift;
         const uint32_t f1 = min(f0 + (1u << G.sc_shift), Ea);
-        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, dbuf(G.flist, cur) + vbase,
-                                         dbuf(G.fpre, cur) + vbase, ci, cm);
+        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, G.flist[cur] + vbase,
+                                         G.fpre[cur] + vbase, ci, cm);
         if constexpr (!WRITE) {
             for (uint32_t j = lane; j < k; j += 64) tc[j] = make_uint2(cm[j], ci[j]);
         }
@@ -384,7 +384,7 @@ __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uin
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
     extern __shared__ uint32_t mv[];
-    const uint32_t* __restrict__ bits = dbuf(G.fbits, cur) + (vbase >> 5);
+    const uint32_t* __restrict__ bits = G.fbits[cur] + (vbase >> 5);
     for (uint32_t v = threadIdx.x; v < nv; v += 256)
         mv[v] = test_bit(bits, v) ? scatter_value<PROG>(G, state, vbase + v) : ident_of<PROG>();
     __syncthreads();
@@ -522,7 +522,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         const uint32_t p = p0 + tid;
         uint32_t ntask = 0;
         if (p < G.k) {
-            const uint32_t Va = dbuf(G.fVa, cur)[p], Ea = dbuf(G.fEa, cur)[p];
+            const uint32_t Va = G.fVa[cur][p], Ea = G.fEa[cur][p];
             uint8_t md = GPOP_MODE_NONE;
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
@@ -544,7 +544,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 sea += Ea;
                 ntask = (Ea + (1u << G.sc_shift) - 1u) >> G.sc_shift;
             }
-            dang += dbuf(G.dpart, cur)[p];
+            dang += G.dpart[cur][p];
         }
         // exclusive scan of the task counts in partition order
         const uint32_t incl = wave_incl_scan(ntask);

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_part_static(Dev G) {
 // Sum of E_a over all partitions / |E| (every wave computes it).
 __device__ inline float active_edge_fraction(const Dev& G, uint32_t cur) {
     uint64_t s = 0;
-    for (uint32_t j = lane_id(); j < G.k; j += 64) s += dbuf(G.fEa, cur)[j];
+    for (uint32_t j = lane_id(); j < G.k; j += 64) s += G.fEa[cur][j];
     s = wave_sum_u64(s);
     return G.E ? (float)((double)s / (double)G.E) : 0.f;
 }
@@ -55,12 +55,12 @@ __device__ __forceinline__ void select_body(const Dev& G, const Params& P, uint3
     const float ea_frac = active_edge_fraction(G, cur);
     const uint32_t p = bid * 64 + lane_id();
     if (p >= G.k) return;
-    const uint32_t Va = dbuf(G.fVa, cur)[p];
+    const uint32_t Va = G.fVa[cur][p];
     if (!Va) {
         G.mode_l[p] = GPOP_MODE_NONE;
         return;
     }
-    const uint32_t Ea = dbuf(G.fEa, cur)[p];
+    const uint32_t Ea = G.fEa[cur][p];
     float f[GPOP_MLP_IN];
     partition_features(G, P, p, Va, Ea, it, ea_frac, f);
     float z;
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64) void k_features(Dev G, Params P, uint32_t it, f
     const uint32_t p = blockIdx.x * 64 + lane_id();
     if (p >= G.k) return;
     float f[GPOP_MLP_IN];
-    partition_features(G, P, p, dbuf(G.fVa, cur)[p], dbuf(G.fEa, cur)[p], it, ea_frac, f);
+    partition_features(G, P, p, G.fVa[cur][p], G.fEa[cur][p], it, ea_frac, f);
     for (int i = 0; i < GPOP_MLP_IN; ++i) out[(size_t)p * GPOP_MLP_IN + i] = f[i];
 }
 

@@ -89,3 +89,19 @@ def test_batch_entry_points_reject_bad_arguments_on_host():
     assert L.gpop_batch_state_init(None, 0, None, None, None) == gp.EINVAL
     assert L.gpop_batch_set_frontier(None, 0, None, 0, None) == gp.EINVAL
     assert L.gpop_batch_check(None, None) == gp.EINVAL
+
+
+def test_autotune_candidates():
+    # PageRank's 64-bit accumulators rule out 2^15-vertex partitions
+    pr = gp.autotune_candidates("pagerank", 1 << 22, 1 << 27)
+    bfs = gp.autotune_candidates("bfs", 1 << 22, 1 << 27)
+    assert {c["log2_part"] for c in pr} == {12, 13, 14}
+    assert {c["log2_part"] for c in bfs} == {12, 13, 14, 15}
+    assert len(bfs) == 16 and len(pr) == 12
+    # a small graph needs no partition larger than itself
+    small = gp.autotune_candidates("bfs", 3000, 20000)
+    assert {c["log2_part"] for c in small} == {12}
+    L = gp.lib()
+    n = ctypes.c_uint32()
+    assert L.gpop_autotune_candidates(0, 100, 100, None, 0, ctypes.byref(n)) == gp.EINVAL
+    assert L.gpop_autotune(None, 0, None, None, 0, 1, 1, None, 0, None, 0, None, None, None) == gp.EINVAL

@@ -148,3 +148,24 @@ def test_batch_iteration_limit_and_errors():
     with pytest.raises(gp.GpopError) as e:
         B.state_init("bfs", st, roots=[0, g.n])  # root out of range
     assert e.value.code == gp.EINVAL
+
+
+@pytest.mark.parametrize("prog", ["pagerank", "bfs"])
+def test_autotune_choice_is_fastest_tried_and_correct(prog):
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    g = gg.rmat_graph(13, 8, seed=gg.BASE_SEED + 85, symmetric=(prog == "bfs"))
+    off, cols, w = gp.upload_csr(g)
+    root = int(gg.pick_sources(g.offsets, gg.SOURCE_SEED, 1)[0])
+    front = None if prog == "pagerank" else torch.tensor([root], dtype=torch.int32, device="cuda")
+    best, table = gp.autotune(off, cols, w, prog, root=root, frontier=front, max_iter=3, reps=1)
+    ran = [(c, ms) for c, ms, _ in table if ms >= 0]
+    assert ran and best in [c for c, _ in ran]
+    assert min(ms for _, ms in ran) == [ms for c, ms in ran if c == best][0]
+    G = gp.Graph(off, cols, w, **best)
+    if prog == "pagerank":
+        got, _ = run_program(G, "pagerank", g.n, max_iter=10)
+        assert pr_ok(got, oracle.pagerank(g, 0.85, 10))
+    else:
+        got, _ = run_program(G, "bfs", g.n, root=root)
+        assert np.array_equal(got, oracle.bfs_levels(g, root))
