@@ -444,6 +444,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--eval-scale", type=int, default=25)
     ap.add_argument("--no-tune", action="store_true", help="batches of several graphs: skip the autotuner")
+    ap.add_argument("--combine", default="lds", choices=["lds", "rounds"],
+                    help="gather combine: LDS min/add per message, or the atomic-free rounds")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -471,7 +473,7 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter()
     G = gp.Graph(off, cols, w, log2_part=lp, sc_task_log2=args.sc_task_log2,
-                 gather_task_ids=args.gather_task_ids)
+                 gather_task_ids=args.gather_task_ids, combine=args.combine)
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - t) * 1e3
     info = G.info()
@@ -562,7 +564,7 @@ def main():
         "dtype": "u32" if all(p in ("bfs", "cc", "sssp") for p, _ in runs) else "f32",
         "data": "synthetic",
         "config": {"workload": desc, "vertices": g.n, "edges": g.m, "q": info.q, "k": info.k,
-                   "selector": args.selector, "bw_ratio": args.bw_ratio,
+                   "selector": args.selector, "bw_ratio": args.bw_ratio, "combine": args.combine,
                    "gather_task_ids": args.gather_task_ids, "sc_task_log2": args.sc_task_log2,
                    "runs_per_step": len(runs), "iterations_per_run": iters_per_run,
                    "edges_traversed_per_step": edges_per_step, "preprocess_ms": prep_ms},

@@ -89,6 +89,16 @@ typedef struct gpop_graph_desc {
     const uint8_t* weights;
 } gpop_graph_desc;
 
+/* How gather combines a partition's messages in the workgroup's on-chip copy
+ * of its state (neither uses global atomics or locks; both give the same
+ * bits):
+ *   GPOP_COMBINE_LDS    one LDS min / 64-bit integer add per message (default)
+ *   GPOP_COMBINE_ROUNDS atomic-free: write-then-verify rounds (min) and
+ *                       per-destination tag rounds (sum), barriers between
+ *                       rounds */
+#define GPOP_COMBINE_LDS 0u
+#define GPOP_COMBINE_ROUNDS 1u
+
 typedef struct gpop_options {
     uint32_t log2_part;   /* q = 2^log2_part vertices per partition, 8..15;
                              0 picks 14 (16384 vertices)                        */
@@ -98,7 +108,8 @@ typedef struct gpop_options {
                                   max(2^18, E / 512). A partition whose bins
                                   hold more ids is gathered by several tasks
                                   (at most 64) and merged                      */
-    uint32_t reserved[5];      /* must be zero                                  */
+    uint32_t combine;          /* GPOP_COMBINE_LDS (0) or GPOP_COMBINE_ROUNDS   */
+    uint32_t reserved[4];      /* must be zero                                  */
 } gpop_options;
 
 typedef struct gpop_plan_info {

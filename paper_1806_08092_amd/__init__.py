@@ -23,6 +23,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTSUP = range(6)
 BFS_LEVEL, CC_MINLABEL, SSSP_U32, PAGERANK_F32, PPR_F32, CARRY_BFS = range(6)
 PROGRAMS = {"bfs": BFS_LEVEL, "cc": CC_MINLABEL, "sssp": SSSP_U32, "pagerank": PAGERANK_F32,
             "ppr": PPR_F32, "carry_bfs": CARRY_BFS}
+COMBINE_LDS, COMBINE_ROUNDS = 0, 1
+COMBINES = {"lds": COMBINE_LDS, "rounds": COMBINE_ROUNDS}
 # selectors
 SEL_ANALYTICAL, SEL_FORCE_SC, SEL_FORCE_PC, SEL_LEARNED = range(4)
 SELECTORS = {"analytical": SEL_ANALYTICAL, "sc": SEL_FORCE_SC, "pc": SEL_FORCE_PC,
@@ -48,7 +50,8 @@ class GraphDesc(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("log2_part", ctypes.c_uint32), ("sc_task_log2", ctypes.c_uint32),
-                ("gather_task_ids", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+                ("gather_task_ids", ctypes.c_uint32), ("combine", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -214,14 +217,15 @@ class Graph:
     workspace is allocated here as a torch tensor and owned by this object."""
 
     def __init__(self, offsets, cols, weights=None, log2_part: int = 14, stream=None,
-                 sc_task_log2: int = 0, gather_task_ids: int = 0):
+                 sc_task_log2: int = 0, gather_task_ids: int = 0, combine="lds"):
         import torch
         self._keep = (offsets, cols, weights)
         n = offsets.numel() - 1
         m = cols.numel()
         self.desc = GraphDesc(n, 0, m, offsets.data_ptr(), cols.data_ptr() if m else 0,
                               None if weights is None else weights.data_ptr())
-        self.opts = Options(log2_part, sc_task_log2, gather_task_ids)
+        combine = COMBINES[combine] if isinstance(combine, str) else int(combine)
+        self.opts = Options(log2_part, sc_task_log2, gather_task_ids, combine)
         info = PlanInfo()
         _check(lib().gpop_plan(ctypes.byref(self.desc), ctypes.byref(self.opts), ctypes.byref(info)))
         self.q, self.k = info.q, info.k

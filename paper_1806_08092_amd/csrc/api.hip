@@ -166,8 +166,9 @@ int check_desc(const gpop_graph_desc* d, const gpop_options* o, uint32_t* s_out)
     if (d->reserved0) return fail(GPOP_EINVAL, "reserved0 must be zero");
     uint32_t s = 14;
     if (o) {
-        for (int i = 0; i < 5; ++i)
+        for (int i = 0; i < 4; ++i)
             if (o->reserved[i]) return fail(GPOP_EINVAL, "options.reserved must be zero");
+        if (o->combine > GPOP_COMBINE_ROUNDS) return fail(GPOP_EINVAL, "unknown combine %u", o->combine);
         if (o->log2_part) s = o->log2_part;
         if (o->sc_task_log2 && (o->sc_task_log2 < 6 || o->sc_task_log2 > 24))
             return fail(GPOP_EINVAL, "sc_task_log2 must be 0 or in [6, 24]");
@@ -288,7 +289,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     G.sc_shift = z.sc_shift;
     G.max_sctask = (uint32_t)max_sctask_for(G.E, z);
     if (sc_lds_bytes(G.k) > (size_t)max_lds_per_block() ||
-        gather_lds_bytes(P_BFS, G.q) + 2048 > (size_t)max_lds_per_block())
+        gather_lds_bytes(P_BFS, G.q, false) + 2048 > (size_t)max_lds_per_block())
         return fail(GPOP_ENOTSUP, "partition of %u vertices does not fit the LDS", G.q);
 
     HIP_OR_RETURN(hipMemsetAsync(G.ctrl, 0, sizeof(Ctrl), st), "clear control block");
@@ -395,6 +396,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     if (gt.size() / 2 > max_gt) return fail(GPOP_EDEVICE, "internal: gather task bound exceeded");
     G.n_gtask = (uint32_t)(gt.size() / 2);
     G.n_gsplit = (uint32_t)gs.size();
+    G.combine = opts ? opts->combine : GPOP_COMBINE_LDS;
     HIP_OR_RETURN(hipMemcpyAsync(G.gtask, gt.data(), gt.size() * sizeof(uint4), hipMemcpyHostToDevice, st),
                   "write gather tasks");
     if (!gs.empty())
@@ -456,9 +458,10 @@ int check_program(const gpop_graph* g, gpop_program prog, const gpop_params* prm
         return fail(GPOP_EINVAL, "damping must be in [0, 1]");
     if (prog == GPOP_PROG_PPR_F32 && !(prm->alpha >= 0.f && prm->alpha <= 1.f))
         return fail(GPOP_EINVAL, "alpha must be in [0, 1]");
-    if (gather_lds_bytes(prog, g->G.q) + 2048 > (size_t)max_lds_per_block())
+    const bool rounds = g->G.combine == GPOP_COMBINE_ROUNDS;
+    if (gather_lds_bytes(prog, g->G.q, rounds) + 2048 > (size_t)max_lds_per_block())
         return fail(GPOP_ENOTSUP, "program %d needs %zu bytes of LDS at q = %u; use a smaller partition",
-                    (int)prog, gather_lds_bytes(prog, g->G.q), g->G.q);
+                    (int)prog, gather_lds_bytes(prog, g->G.q, rounds), g->G.q);
     return GPOP_OK;
 }
 
@@ -926,6 +929,12 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
     B.nb_merge = tot[5];
     B.k_max = k_max;
     B.q_max = q_max;
+    B.rounds = graphs[0]->G.combine == GPOP_COMBINE_ROUNDS;
+    for (uint32_t i = 1; i < n; ++i)
+        if (graphs[i]->G.combine != graphs[0]->G.combine) {
+            delete b;
+            return fail(GPOP_EINVAL, "every graph of a batch must use the same combine option");
+        }
     if (sc_lds_bytes(k_max) > (size_t)max_lds_per_block()) {
         delete b;
         return fail(GPOP_ENOTSUP, "k = %u partitions need more LDS than a workgroup has", k_max);
@@ -1057,7 +1066,7 @@ int gpop_autotune_candidates(gpop_program prog, uint32_t num_vertices, uint64_t 
     (void)num_edges;
     uint32_t c = 0;
     for (uint32_t lp = 12; lp <= 15; ++lp) {
-        if (gather_lds_bytes((int)prog, 1u << lp) + 2048 > kLdsPerWorkgroup) continue;
+        if (gather_lds_bytes((int)prog, 1u << lp, false) + 2048 > kLdsPerWorkgroup) continue;
         const uint32_t gids[2] = {0, 1u << 16};
         const uint32_t scs[2] = {0, 12};
         for (uint32_t a = 0; a < 2; ++a)

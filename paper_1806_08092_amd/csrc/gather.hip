@@ -18,13 +18,16 @@ constexpr unsigned long long kCarried = 1ull << 63;  // sum programs: vertex was
 // LDS layout of the gather workgroup (bytes, all offsets 16-aligned). The
 // bin-list arrays double as scratch for the frontier masks in the filter.
 struct GatherLds {
-    size_t state, carry, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
+    size_t state, tag, carry, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
 };
 
-__host__ __device__ inline GatherLds gather_layout(int prog, uint32_t q) {
+// `rounds`: the atomic-free combine, whose sum programs need a 16-bit tag per
+// vertex.
+__host__ __device__ inline GatherLds gather_layout(int prog, uint32_t q, bool rounds = false) {
     GatherLds L{};
     size_t o = 0;
     L.state = o;  o += (size_t)q * (is_sum(prog) ? 8 : 4);
+    L.tag = o;    o += (rounds && is_sum(prog)) ? ((size_t)q * 2 + 15) / 16 * 16 : 0;
     L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
     L.bl_ioff = o; o += kGT * 4;
     L.bl_icnt = o; o += kGT * 4;
@@ -36,7 +39,7 @@ __host__ __device__ inline GatherLds gather_layout(int prog, uint32_t q) {
     return L;
 }
 
-size_t gather_lds_bytes(int prog, uint32_t q) { return gather_layout(prog, q).total; }
+size_t gather_lds_bytes(int prog, uint32_t q, bool rounds) { return gather_layout(prog, q, rounds).total; }
 
 // Exclusive prefix of a 0..7 per-lane count across the wave, from bit-plane
 // ballots.
@@ -206,21 +209,29 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
 // chunk-table base + number of message-start flags after the piece start.
 //
 // Combining touches only the workgroup's own LDS copy of the partition (no
-// global atomics, no locks). Min programs need no atomics at all: every
-// pending lane reads the state word and writes its value if smaller; after a
-// barrier each lane re-reads, and only lanes whose value is still smaller
-// stay pending. Each round lowers every contested word strictly, so the loop
-// ends with the exact minimum whatever the write order. Sum programs add
-// 64-bit integers in units of 2^-60 with the LDS unit's integer add, one
-// instruction per message and no rounds; integer addition is exact, so the
-// result does not depend on the order in which the adds land.
-template <int PROG>
+// global atomics, no locks), in one of two ways chosen per graph:
+//  - LDS combine (default): every message is one LDS min (min programs) or
+//    one LDS 64-bit integer add of its value in units of 2^-60 (sum
+//    programs); no rounds and no barriers inside the message loop.
+//  - atomic-free rounds (ROUNDS): min programs: every pending lane reads the
+//    state word and writes its value if smaller; after a barrier each lane
+//    re-reads, and only lanes whose value is still smaller stay pending. Each
+//    round lowers every contested word strictly, so the loop ends with the
+//    exact minimum whatever the write order. Sum programs: every pending lane
+//    writes its slot number into the destination's tag, the lane whose tag
+//    survived adds; after four rounds the leftovers (high in-degree vertices)
+//    are first summed per destination inside each wave, leaving at most one
+//    entry per destination per wave for the last rounds.
+// Both give the same bits: min is order-independent and the sums are exact
+// integer sums.
+template <int PROG, bool ROUNDS>
 __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
                                             uint32_t it, uint32_t task) {
     if (G.ctrl->done) return;
     constexpr bool SUM = is_sum(PROG);
     constexpr uint32_t IDENT = is_sum(PROG) ? kIdentSum : kIdentMin;
-    constexpr uint32_t PPW = 4;  // pieces per wave per combine round
+    // pieces per wave per combine round (the atomic-free sum keeps two, for registers)
+    constexpr uint32_t PPW = (ROUNDS && SUM) ? 2 : 4;
     const uint4 TA = G.gtask[2 * task], TB = G.gtask[2 * task + 1];
     const uint32_t cq = TA.x, p_lo = TA.y, p_hi = TA.z, nt = TA.w >> 16;
     // the two id / weight / chunk arrays a piece may come from, as uniform
@@ -243,9 +254,10 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     const uint2* __restrict__ sccol = G.sc_cnt + (size_t)cq * k;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    const GatherLds L = gather_layout(PROG, Q);
+    const GatherLds L = gather_layout(PROG, Q, ROUNDS);
     uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
+    uint16_t* tag = reinterpret_cast<uint16_t*>(smem + L.tag);
     uint8_t* carry = smem + L.carry;   // kept active by initFunc
     uint32_t* bl_ioff = reinterpret_cast<uint32_t*>(smem + L.bl_ioff);
     uint32_t* bl_icnt = reinterpret_cast<uint32_t*>(smem + L.bl_icnt);
@@ -431,23 +443,25 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                 }
                 vmaskall |= vmask << (4 * pi);
             }
-            // phase 3: drop identity messages, apply weights; sums go straight
-            // into the accumulators
+            // phase 3: drop identity messages, apply weights, combine
+            unsigned long long fx[(SUM && ROUNDS) ? 4 * PPW : 1];
 #pragma unroll
             for (uint32_t j = 0; j < 4 * PPW; ++j) {
                 uint32_t x = val[j];
                 if (((vmaskall >> j) & 1u) && x != IDENT) {
                     if constexpr (is_weighted(PROG)) x = sat_add(x, (wts[j / 4] >> (8 * (j % 4))) & 0xFFu);
                     val[j] = x;
-                    if constexpr (SUM) {
-                        atomicAdd(acc + dst[j], __double2ull_rn((double)__uint_as_float(x) * kFix));
+                    if constexpr (!ROUNDS) {
+                        if constexpr (SUM) atomicAdd(acc + dst[j], __double2ull_rn((double)__uint_as_float(x) * kFix));
+                        else atomicMin(st32 + dst[j], x);
                     } else {
+                        if constexpr (SUM) fx[j] = __double2ull_rn((double)__uint_as_float(x) * kFix);
                         pend |= 1u << j;
                     }
                     ++my_ids;
                 }
             }
-            if constexpr (!SUM) {
+            if constexpr (ROUNDS && !SUM) {
                 // write-verify rounds for the min combine
                 // A lane whose value is not below the word it reads is done
                 // for good (words only decrease); only lanes that wrote must
@@ -465,6 +479,83 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                     for (uint32_t j = 0; j < 4 * PPW; ++j)
                         if (((pend >> j) & 1u) && !(val[j] < st32[dst[j]])) pend &= ~(1u << j);
                     if (!__syncthreads_or(pend != 0)) break;
+                }
+            }
+            if constexpr (ROUNDS && SUM) {
+                // Exact fixed-point sum. Tag rounds: every pending entry
+                // writes its slot number into its destination's tag, the
+                // entry whose tag survived adds. Each round retires one entry
+                // per destination, so a destination hit many times in one
+                // round (a high in-degree vertex) would take as many rounds;
+                // after four rounds the leftovers are first summed per
+                // destination inside each wave, which leaves at most one
+                // entry per destination per wave for the final rounds.
+                bool left = true;
+                for (int tr = 0; tr < 4 && left; ++tr) {
+#pragma unroll
+                    for (uint32_t j = 0; j < 4 * PPW; ++j)
+                        if ((pend >> j) & 1u) tag[dst[j]] = (uint16_t)(tid * 4u * PPW + j);
+                    __syncthreads();
+#pragma unroll
+                    for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                        if (((pend >> j) & 1u) && tag[dst[j]] == (uint16_t)(tid * 4u * PPW + j)) {
+                            acc[dst[j]] += fx[j];
+                            pend &= ~(1u << j);
+                        }
+                    }
+                    left = __syncthreads_or(pend != 0);
+                }
+                if (left) {
+                    uint32_t adst[4 * PPW];
+                    unsigned long long afx[4 * PPW];
+                    uint32_t apend = 0, na = 0;
+                    for (;;) {  // one destination of this wave per pass
+                        const uint64_t bl = ballot(pend != 0);
+                        if (!bl) break;
+                        uint32_t mykey = 0;
+                        bool found = false;
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (!found && ((pend >> j) & 1u)) {
+                                mykey = dst[j];
+                                found = true;
+                            }
+                        }
+                        const uint32_t key = (uint32_t)__shfl((int)mykey, (int)(__ffsll((long long)bl) - 1), 64);
+                        unsigned long long sum = 0;
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (((pend >> j) & 1u) && dst[j] == key) {
+                                sum += fx[j];
+                                pend &= ~(1u << j);
+                            }
+                        }
+                        sum = wave_sum_u64(sum);
+                        const uint32_t tl = na & 63u, ts = na >> 6;
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (lane == tl && j == ts) {
+                                adst[j] = key;
+                                afx[j] = sum;
+                                apend |= 1u << j;
+                            }
+                        }
+                        ++na;
+                    }
+                    for (;;) {  // at most kGW contenders per destination
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j)
+                            if ((apend >> j) & 1u) tag[adst[j]] = (uint16_t)(tid * 4u * PPW + j);
+                        __syncthreads();
+#pragma unroll
+                        for (uint32_t j = 0; j < 4 * PPW; ++j) {
+                            if (((apend >> j) & 1u) && tag[adst[j]] == (uint16_t)(tid * 4u * PPW + j)) {
+                                acc[adst[j]] += afx[j];
+                                apend &= ~(1u << j);
+                            }
+                        }
+                        if (!__syncthreads_or(apend != 0)) break;
+                    }
                 }
             }
         }
@@ -495,18 +586,18 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                            reinterpret_cast<uint64_t*>(bl_ioff), sh, my_ids, task);
 }
 
-template <int PROG>
+template <int PROG, bool ROUNDS>
 __global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __restrict__ state,
                                                    uint32_t it) {
-    gather_body<PROG>(G, P, state, it, blockIdx.x);
+    gather_body<PROG, ROUNDS>(G, P, state, it, blockIdx.x);
 }
 
-template <int PROG>
+template <int PROG, bool ROUNDS>
 __global__ __launch_bounds__(kGT, 2) void kb_gather(const Inst* __restrict__ tab,
                                                     const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    gather_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+    gather_body<PROG, ROUNDS>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
 }
 
 // Merge of a partition whose gather was split over several tasks: combines
@@ -644,19 +735,27 @@ __global__ void kb_limits(const Inst* __restrict__ tab, uint32_t n, uint32_t max
 
 template <int PROG>
 static hipError_t prep_batch_gather_p(const BatchGrid& B) {
-    const int lds = (int)gather_lds_bytes(PROG, B.q_max);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_gather<PROG>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const bool r = B.rounds;
+    hipError_t e = hipFuncSetAttribute(
+        r ? reinterpret_cast<const void*>(kb_gather<PROG, true>) : reinterpret_cast<const void*>(kb_gather<PROG, false>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes(PROG, B.q_max, r));
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kb_merge<PROG>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes(PROG, B.q_max, false));
 }
 
 template <int PROG>
 static hipError_t launch_batch_gather_p(const BatchGrid& B, hipStream_t st) {
-    const size_t lds = gather_lds_bytes(PROG, B.q_max);
-    if (B.nb_gather) hipLaunchKernelGGL(kb_gather<PROG>, dim3(B.nb_gather), dim3(kGT), lds, st, B.tab, B.b_gather, B.n);
-    if (B.nb_merge) hipLaunchKernelGGL(kb_merge<PROG>, dim3(B.nb_merge), dim3(kGT), lds, st, B.tab, B.b_merge, B.n);
+    const size_t lds = gather_lds_bytes(PROG, B.q_max, B.rounds);
+    if (B.nb_gather) {
+        if (B.rounds)
+            hipLaunchKernelGGL((kb_gather<PROG, true>), dim3(B.nb_gather), dim3(kGT), lds, st, B.tab, B.b_gather, B.n);
+        else
+            hipLaunchKernelGGL((kb_gather<PROG, false>), dim3(B.nb_gather), dim3(kGT), lds, st, B.tab, B.b_gather, B.n);
+    }
+    if (B.nb_merge)
+        hipLaunchKernelGGL(kb_merge<PROG>, dim3(B.nb_merge), dim3(kGT), gather_lds_bytes(PROG, B.q_max, false), st,
+                           B.tab, B.b_merge, B.n);
     return hipGetLastError();
 }
 
@@ -692,8 +791,9 @@ hipError_t launch_batch_status(const BatchGrid& B, uint32_t* out, hipStream_t st
 template <int PROG>
 static hipError_t launch_gather_p(const Dev& G, const Params& P, uint32_t* state, uint32_t it,
                                   hipStream_t st) {
-    const size_t lds = gather_lds_bytes(PROG, G.q);
-    auto fn = k_gather<PROG>;
+    const bool r = G.combine == GPOP_COMBINE_ROUNDS;
+    const size_t lds = gather_lds_bytes(PROG, G.q, r);
+    auto fn = r ? k_gather<PROG, true> : k_gather<PROG, false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -705,7 +805,7 @@ template <int PROG>
 static hipError_t launch_merge_p(const Dev& G, const Params& P, uint32_t* state, uint32_t it,
                                  hipStream_t st) {
     if (G.n_gsplit == 0) return hipSuccess;
-    const size_t lds = gather_lds_bytes(PROG, G.q);
+    const size_t lds = gather_lds_bytes(PROG, G.q, false);
     auto fn = k_merge<PROG>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

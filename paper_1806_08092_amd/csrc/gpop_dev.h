@@ -68,6 +68,7 @@ struct Dev {
     uint32_t n_bldtask;       // tasks of the preprocessing build
     uint32_t n_gtask;         // gather tasks (static)
     uint32_t n_gsplit;        // partitions whose gather is split over tasks
+    uint32_t combine;         // GPOP_COMBINE_*
     uint64_t E;
     const uint32_t* off;
     const uint32_t* cols;

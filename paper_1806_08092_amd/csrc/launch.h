@@ -36,7 +36,7 @@ hipError_t launch_scatter_pc(const Dev& G, const Params& P, int prog, const uint
                              uint32_t it, hipStream_t st);
 
 // gather side (gather.hip)
-size_t gather_lds_bytes(int prog, uint32_t q);
+size_t gather_lds_bytes(int prog, uint32_t q, bool rounds);
 hipError_t launch_merge(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
                         hipStream_t st);
 hipError_t launch_gather(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
@@ -61,6 +61,7 @@ struct BatchGrid {
     const uint32_t* b_merge;
     uint32_t nb_select, nb_sc, nb_scan, nb_pc, nb_gather, nb_merge;
     uint32_t k_max, q_max;
+    bool rounds;                  // atomic-free combine (every run of a batch uses the same)
 };
 hipError_t prepare_batch_scatter(const BatchGrid& B, int prog);
 hipError_t prepare_batch_gather(const BatchGrid& B, int prog);

@@ -105,3 +105,11 @@ def test_autotune_candidates():
     n = ctypes.c_uint32()
     assert L.gpop_autotune_candidates(0, 100, 100, None, 0, ctypes.byref(n)) == gp.EINVAL
     assert L.gpop_autotune(None, 0, None, None, 0, 1, 1, None, 0, None, 0, None, None, None) == gp.EINVAL
+
+
+def test_plan_rejects_unknown_combine():
+    d = gp.GraphDesc(1000, 0, 5000, None, None, None)
+    info = gp.PlanInfo()
+    L = gp.lib()
+    assert L.gpop_plan(ctypes.byref(d), ctypes.byref(gp.Options(10, 0, 0, 2)), ctypes.byref(info)) == gp.EINVAL
+    assert L.gpop_plan(ctypes.byref(d), ctypes.byref(gp.Options(10, 0, 0, 1)), ctypes.byref(info)) == gp.OK

@@ -321,3 +321,31 @@ def test_sum_with_hub_destinations_is_mode_and_split_invariant():
             outs.append(got.view(np.uint32))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("zi", [0, 1, 2, 4, 5, 8])
+def test_atomic_free_combine_gives_the_same_bits(zi):
+    """The atomic-free combine (write-verify / tag rounds) and the LDS
+    combine give identical results for every program."""
+    name, g, lp, (G, _) = get_zoo()[zi]
+    R, _ = make_graph(g, lp, combine="rounds")
+    root = roots_of(g, 1)[0]
+    for prog, kw in [("bfs", {}), ("cc", {}), ("sssp", {}), ("pagerank", {"max_iter": 10}),
+                     ("ppr", {"max_iter": 20})]:
+        a, ia = run_program(G, prog, g.n, root=root, **kw)
+        b, ib = run_program(R, prog, g.n, root=root, **kw)
+        assert ia == ib and np.array_equal(a.view(np.uint32), b.view(np.uint32)), (name, prog)
+    ref = oracle.bfs_levels(g, root)
+    got, _ = run_program(R, "bfs", g.n, root=root)
+    assert np.array_equal(got, ref)
+
+
+def test_atomic_free_combine_on_hub_graph_and_splits():
+    g = _hub_graph()
+    for gids in (0, 256):
+        A, _ = make_graph(g, 8, gather_task_ids=gids)
+        R, _ = make_graph(g, 8, gather_task_ids=gids, combine="rounds")
+        for prog, kw in [("pagerank", {"max_iter": 10}), ("ppr", {"root": 7, "max_iter": 20}), ("cc", {})]:
+            a, _ = run_program(A, prog, g.n, **kw)
+            b, _ = run_program(R, prog, g.n, **kw)
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (gids, prog)
