@@ -246,9 +246,13 @@ int gpop_iterate(struct gpop_graph* g, void* stream);
 
 /* Iterates while the frontier is non-empty and fewer than max_iter
  * iterations have run (the driver loop of the applications section).
+ * Iterations are recorded once per program as a HIP graph of four
+ * iterations and replayed; the device stops a run when its frontier is
+ * empty or the limit is reached (later kernels of a replay return at once).
  * Synchronises `stream` before returning and reports the iterations run in
  * *h_iters (may be NULL). Reaching max_iter with a non-empty frontier is not
- * an error: gpop_frontier_size() then reports the remaining frontier. */
+ * an error: gpop_frontier_size() then reports the remaining frontier, and a
+ * later gpop_run or gpop_iterate continues from there. */
 int gpop_run(struct gpop_graph* g, uint32_t max_iter, uint32_t* h_iters, void* stream);
 
 /* G.frontierSize: number of active vertices. Synchronises `stream`. */
@@ -371,7 +375,9 @@ int gpop_autotune(const gpop_graph_desc* desc, gpop_program prog, const gpop_par
 /* When enabled, every kernel launch is bracketed by HIP events on its
  * stream. gpop_profile_read synchronises the stream and returns, per kernel
  * id, the summed milliseconds and the number of launches since profiling
- * was enabled (arrays of GPOP_KERNEL_COUNT entries). */
+ * was enabled (arrays of GPOP_KERNEL_COUNT entries). While profiling,
+ * gpop_run launches its iterations directly instead of replaying the
+ * recorded HIP graph (the kernels are the same). */
 int gpop_profile_enable(struct gpop_graph* g, int enable);
 int gpop_profile_read(struct gpop_graph* g, double* h_ms, uint64_t* h_launches, void* stream);
 

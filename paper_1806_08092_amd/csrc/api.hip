@@ -47,6 +47,32 @@ struct Pending {
     hipEvent_t a, b;
 };
 
+// Records a fixed number of iterations of one or more runs as a HIP graph
+// and replays it until every run has finished or paused. Profiling records
+// an event pair around each kernel group of each iteration.
+struct Runner {
+    hipStream_t cap = nullptr;  // used only to record
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int prog = -1;
+    bool prof = false;
+    uint32_t chunk = 4;
+    std::vector<hipEvent_t> ev;  // 2 * GPOP_KERNEL_COUNT per recorded iteration
+
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        prog = -1;
+    }
+    ~Runner() {
+        drop();
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 }  // namespace
 
 struct gpop_graph {
@@ -54,14 +80,20 @@ struct gpop_graph {
     Params P{};
     int prog = -1;
     uint32_t* state = nullptr;
-    uint32_t it = 0;
     uint64_t M = 0;
     uint64_t nonempty_bins = 0;
     bool prof = false;
+    bool limited = false;  // a finite iteration limit may be set on the device
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     double prof_ms[GPOP_KERNEL_COUNT] = {};
     uint64_t prof_n[GPOP_KERNEL_COUNT] = {};
+    // the graph's own run, launched through the batched kernels as a batch
+    // of one: [0] the run, [1] / [2] source- / partition-centric probes
+    Inst h_tab[3]{};
+    Inst* d_tab = nullptr;
+    BatchGrid grid{}, probe_grid[2]{};
+    Runner run;
 };
 
 namespace {
@@ -96,7 +128,8 @@ uint64_t max_gtask_for(uint64_t E, const Sizes& z) {
     return (E + 512ull * z.k * z.k) / z.T + z.k + 1;
 }
 
-size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z) {
+size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** tab = nullptr,
+             uint32_t** boff = nullptr) {
     size_t o = 0;
     auto take = [&](size_t bytes) -> char* {
         char* p = base ? base + o : nullptr;
@@ -156,6 +189,10 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z) {
     G->mode_l = (uint8_t*)take(k);
     G->mlp = (gpop_mlp_model*)take(sizeof(gpop_mlp_model));
     G->probe = (unsigned long long*)take(3 * k * 8);
+    Inst* t = (Inst*)take(3 * sizeof(Inst));
+    uint32_t* b = (uint32_t*)take(6 * 2 * 4);
+    if (tab) *tab = t;
+    if (boff) *boff = b;
     return o;
 }
 
@@ -226,6 +263,104 @@ int collect_profile(gpop_graph* g) {
     return GPOP_OK;
 }
 
+// One iteration of every run of B; ev (2 * GPOP_KERNEL_COUNT events, or
+// nullptr) brackets plan, SC scatter, PC scatter, gather and merge.
+hipError_t launch_iteration(const BatchGrid& B, int prog, hipStream_t st, const hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    auto mark = [&](int i) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    if (e == hipSuccess) e = launch_batch_select(B, st);
+    if (e == hipSuccess) e = launch_batch_plan(B, st);
+    mark(1);
+    mark(2);
+    if (e == hipSuccess) e = launch_batch_sc(B, prog, st);
+    mark(3);
+    mark(4);
+    if (e == hipSuccess) e = launch_batch_pc(B, prog, st);
+    mark(5);
+    mark(6);
+    if (e == hipSuccess) e = launch_batch_gather(B, prog, st);
+    mark(7);
+    mark(8);
+    if (e == hipSuccess) e = launch_batch_merge(B, prog, st);
+    mark(9);
+    return e;
+}
+
+int runner_record(Runner& R, const BatchGrid& B, int prog, bool prof, uint32_t* d_status) {
+    R.drop();
+    if (!R.cap && hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking) != hipSuccess)
+        return fail(GPOP_EDEVICE, "cannot create the recording stream");
+    const size_t nev = prof ? (size_t)2 * GPOP_KERNEL_COUNT * R.chunk : 0;
+    while (R.ev.size() < nev) {
+        hipEvent_t e = nullptr;
+        HIP_OR_RETURN(hipEventCreate(&e), "event");
+        R.ev.push_back(e);
+    }
+    HIP_OR_RETURN(prepare_batch_scatter(B, prog), "kernel attributes");
+    HIP_OR_RETURN(prepare_batch_gather(B, prog), "kernel attributes");
+    HIP_OR_RETURN(hipStreamBeginCapture(R.cap, hipStreamCaptureModeRelaxed), "begin capture");
+    hipError_t e = hipSuccess;
+    for (uint32_t c = 0; c < R.chunk && e == hipSuccess; ++c)
+        e = launch_iteration(B, prog, R.cap, prof ? &R.ev[(size_t)2 * GPOP_KERNEL_COUNT * c] : nullptr);
+    if (e == hipSuccess && d_status) e = launch_batch_status(B, d_status, R.cap);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(R.cap, &gr);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(e != hipSuccess ? e : e2, "record iterations");
+    }
+    R.graph = gr;
+    HIP_OR_RETURN(hipGraphInstantiate(&R.exec, gr, nullptr, nullptr, 0), "instantiate iterations");
+    R.prog = prog;
+    R.prof = prof;
+    return GPOP_OK;
+}
+
+// Replays the recorded iterations (or launches them directly when `eager`)
+// until `finished()` reports that every run has finished or paused. The
+// limit set on the device bounds the replays: max_iter / chunk + 2 suffice.
+template <class F>
+int runner_run(Runner& R, const BatchGrid& B, int prog, bool prof, bool eager, uint32_t max_iter,
+               uint32_t* d_status, hipStream_t st, double* prof_ms, uint64_t* prof_n, F&& finished) {
+    if (!eager && (R.prog != prog || R.prof != prof || !R.exec)) {
+        int rc = runner_record(R, B, prog, prof, d_status);
+        if (rc) return rc;
+    }
+    if (eager) {
+        HIP_OR_RETURN(prepare_batch_scatter(B, prog), "kernel attributes");
+        HIP_OR_RETURN(prepare_batch_gather(B, prog), "kernel attributes");
+    }
+    const uint64_t passes = (uint64_t)max_iter / R.chunk + 2;
+    for (uint64_t r = 0; r < passes; ++r) {
+        if (eager) {
+            for (uint32_t c = 0; c < R.chunk; ++c)
+                HIP_OR_RETURN(launch_iteration(B, prog, st, nullptr), "iteration");
+            if (d_status) HIP_OR_RETURN(launch_batch_status(B, d_status, st), "run status");
+        } else {
+            HIP_OR_RETURN(hipGraphLaunch(R.exec, st), "replay iterations");
+        }
+        bool done = false;
+        int rc = finished(done);  // synchronises the stream
+        if (rc) return rc;
+        if (prof && !eager) {
+            for (uint32_t c = 0; c < R.chunk; ++c)
+                for (int k = 0; k < GPOP_KERNEL_COUNT; ++k) {
+                    float ms = 0.f;
+                    const size_t i = (size_t)2 * GPOP_KERNEL_COUNT * c + 2 * k;
+                    if (hipEventElapsedTime(&ms, R.ev[i], R.ev[i + 1]) == hipSuccess) {
+                        prof_ms[k] += ms;
+                        prof_n[k] += 1;
+                    }
+                }
+        }
+        if (done) break;
+    }
+    return GPOP_OK;
+}
+
 constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950: on-chip memory a workgroup may use
 
 int max_lds_per_block() {
@@ -273,7 +408,9 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     const size_t need = carve(&G, nullptr, desc->num_vertices, desc->num_edges, z);
     if (ws_bytes < need)
         return fail(GPOP_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
-    carve(&G, (char*)d_ws, desc->num_vertices, desc->num_edges, z);
+    Inst* d_tab = nullptr;
+    uint32_t* d_boff = nullptr;
+    carve(&G, (char*)d_ws, desc->num_vertices, desc->num_edges, z, &d_tab, &d_boff);
     G.V = desc->num_vertices;
     G.E = desc->num_edges;
     G.s = s;
@@ -408,6 +545,17 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
     if (hc2.bug) return fail(GPOP_EDEVICE, "internal error while building the partition layout");
 
+    // the graph's own run as a batch of one: per kernel, blocks [0, n)
+    const uint32_t nb[6] = {(G.k + 63) / 64, std::min<uint32_t>((G.max_sctask + kScWaves - 1) / kScWaves, 2048u),
+                            G.k, G.n_pctask, G.n_gtask, G.n_gsplit};
+    uint32_t hb[12];
+    for (int j = 0; j < 6; ++j) {
+        hb[2 * j] = 0;
+        hb[2 * j + 1] = nb[j];
+    }
+    HIP_OR_RETURN(hipMemcpyAsync(d_boff, hb, sizeof hb, hipMemcpyHostToDevice, st), "write run grid");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+
     gpop_graph* g = new (std::nothrow) gpop_graph();
     if (!g) return fail(GPOP_ENOMEM, "host allocation failed");
     g->G = G;
@@ -418,6 +566,29 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     g->P.s_v = 4;
     g->P.ratio_num = 2048;
     g->P.ratio_den = 1024;
+    g->d_tab = d_tab;
+    BatchGrid& B = g->grid;
+    B.tab = d_tab;
+    B.n = 1;
+    B.b_select = d_boff;
+    B.b_sc = d_boff + 2;
+    B.b_scan = d_boff + 4;
+    B.b_pc = d_boff + 6;
+    B.b_gather = d_boff + 8;
+    B.b_merge = d_boff + 10;
+    B.nb_select = nb[0];
+    B.nb_sc = nb[1];
+    B.nb_scan = nb[2];
+    B.nb_pc = nb[3];
+    B.nb_gather = nb[4];
+    B.nb_merge = nb[5];
+    B.k_max = G.k;
+    B.q_max = G.q;
+    B.rounds = G.combine == GPOP_COMBINE_ROUNDS;
+    for (int i = 0; i < 2; ++i) {
+        g->probe_grid[i] = B;
+        g->probe_grid[i].tab = d_tab + 1 + i;
+    }
     *out = g;
     return GPOP_OK;
 }
@@ -475,6 +646,36 @@ void program_params(const gpop_graph* g, const gpop_params* prm, Params* P) {
 
 }  // namespace
 
+namespace {
+
+// Writes the graph's run table (the run and its two probe variants).
+int upload_tab(gpop_graph* g, hipStream_t st) {
+    for (int i = 0; i < 3; ++i) {
+        g->h_tab[i].G = g->G;
+        g->h_tab[i].P = g->P;
+        g->h_tab[i].state = g->state;
+    }
+    g->h_tab[0].P.probe = 0;
+    g->h_tab[1].P.probe = 1;
+    g->h_tab[1].P.selector = GPOP_SEL_FORCE_SC;
+    g->h_tab[2].P.probe = 1;
+    g->h_tab[2].P.selector = GPOP_SEL_FORCE_PC;
+    HIP_OR_RETURN(hipMemcpyAsync(g->d_tab, g->h_tab, sizeof g->h_tab, hipMemcpyHostToDevice, st), "write run table");
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    return GPOP_OK;
+}
+
+Ctrl read_ctrl(const gpop_graph* g, hipStream_t st, int* rc) {
+    Ctrl hc{};
+    *rc = GPOP_OK;
+    if (hipMemcpyAsync(&hc, g->G.ctrl, sizeof hc, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        *rc = fail(GPOP_EDEVICE, "read control");
+    return hc;
+}
+
+}  // namespace
+
 int gpop_state_init(gpop_graph* g, gpop_program prog, const gpop_params* prm, void* d_state,
                     void* stream) {
     if (!g || !prm || !d_state) return fail(GPOP_EINVAL, "NULL argument");
@@ -482,25 +683,26 @@ int gpop_state_init(gpop_graph* g, gpop_program prog, const gpop_params* prm, vo
     if (rc) return rc;
     g->prog = (int)prog;
     g->state = (uint32_t*)d_state;
-    g->it = 0;
     program_params(g, prm, &g->P);
     hipStream_t st = (hipStream_t)stream;
     HIP_OR_RETURN(launch_state_init(g->G, g->P, g->prog, g->state, st), "state init");
+    g->limited = false;
+    if ((rc = upload_tab(g, st))) return rc;
+    HIP_OR_RETURN(prepare_batch_scatter(g->grid, g->prog), "kernel attributes");
+    HIP_OR_RETURN(prepare_batch_gather(g->grid, g->prog), "kernel attributes");
     return GPOP_OK;
 }
 
 int gpop_set_frontier(gpop_graph* g, const uint32_t* d_vertices, uint32_t n, void* stream) {
     if (!g) return fail(GPOP_EINVAL, "NULL graph");
     if (n && !d_vertices) return fail(GPOP_EINVAL, "NULL vertex array");
-    HIP_OR_RETURN(launch_set_frontier(g->G, d_vertices, n, 0, g->it & 1u, (hipStream_t)stream),
-                  "set frontier");
+    HIP_OR_RETURN(launch_set_frontier(g->G, d_vertices, n, 0, (hipStream_t)stream), "set frontier");
     return GPOP_OK;
 }
 
 int gpop_set_frontier_all(gpop_graph* g, void* stream) {
     if (!g) return fail(GPOP_EINVAL, "NULL graph");
-    HIP_OR_RETURN(launch_set_frontier(g->G, nullptr, 0, 1, g->it & 1u, (hipStream_t)stream),
-                  "set frontier");
+    HIP_OR_RETURN(launch_set_frontier(g->G, nullptr, 0, 1, (hipStream_t)stream), "set frontier");
     return GPOP_OK;
 }
 
@@ -531,12 +733,13 @@ int gpop_set_selector(gpop_graph* g, gpop_selector kind, float bw_ratio, uint32_
     g->P.s_i = s_i;
     g->P.s_v = s_v;
     if (kind == GPOP_SEL_LEARNED && !d_mlp) g->P.selector = GPOP_SEL_ANALYTICAL;
+    if (g->prog >= 0) return upload_tab(g, nullptr);  // the run reads its parameters on the device
     return GPOP_OK;
 }
 
 int gpop_features(gpop_graph* g, float* d_out, void* stream) {
     if (!g || !d_out) return fail(GPOP_EINVAL, "NULL argument");
-    HIP_OR_RETURN(launch_features(g->G, g->P, g->it, d_out, (hipStream_t)stream), "features");
+    HIP_OR_RETURN(launch_features(g->G, g->P, d_out, (hipStream_t)stream), "features");
     return GPOP_OK;
 }
 
@@ -548,34 +751,37 @@ int gpop_probe_scatter(gpop_graph* g, gpop_selector kind, float* h_us, float* h_
     hipStream_t st = (hipStream_t)stream;
     const Dev& G = g->G;
     const uint32_t k = G.k;
-    Params P = g->P;
-    P.selector = (uint32_t)kind;
-    P.probe = 1;
-    hipEvent_t ev[4];
-    for (int i = 0; i < 4; ++i) HIP_OR_RETURN(hipEventCreate(&ev[i]), "event");
+    const BatchGrid& B = g->probe_grid[kind == GPOP_SEL_FORCE_SC ? 0 : 1];
+    hipEvent_t ev[2];
+    HIP_OR_RETURN(hipEventCreate(&ev[0]), "event");
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return fail(GPOP_EDEVICE, "event");
+    }
     struct Guard {
         hipEvent_t* e;
         ~Guard() {
-            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
         }
     } guard{ev};
     HIP_OR_RETURN(launch_fill_u8((uint8_t*)G.probe, 3ull * k * 8, 0, st), "clear probe");
-    HIP_OR_RETURN(launch_plan(G, P, g->it, st), "probe plan");
+    HIP_OR_RETURN(launch_batch_plan(B, st), "probe plan");
     HIP_OR_RETURN(hipEventRecord(ev[0], st), "event");
-    HIP_OR_RETURN(launch_scatter_sc(G, P, g->prog, g->state, g->it, st), "probe scatter SC");
+    if (kind == GPOP_SEL_FORCE_SC) HIP_OR_RETURN(launch_batch_sc(B, g->prog, st), "probe scatter SC");
+    else HIP_OR_RETURN(launch_batch_pc(B, g->prog, st), "probe scatter PC");
     HIP_OR_RETURN(hipEventRecord(ev[1], st), "event");
-    HIP_OR_RETURN(hipEventRecord(ev[2], st), "event");
-    HIP_OR_RETURN(launch_scatter_pc(G, P, g->prog, g->state, g->it, st), "probe scatter PC");
-    HIP_OR_RETURN(hipEventRecord(ev[3], st), "event");
+    int rc;
+    const Ctrl hc = read_ctrl(g, st, &rc);
+    if (rc) return rc;
     std::vector<unsigned long long> acc(3ull * k);
     std::vector<uint32_t> va(k);
     HIP_OR_RETURN(hipMemcpyAsync(acc.data(), G.probe, acc.size() * 8, hipMemcpyDeviceToHost, st), "read probe");
-    HIP_OR_RETURN(hipMemcpyAsync(va.data(), G.fVa[g->it & 1u], k * 4, hipMemcpyDeviceToHost, st),
+    HIP_OR_RETURN(hipMemcpyAsync(va.data(), G.fVa[hc.pos & 1u], k * 4, hipMemcpyDeviceToHost, st),
                   "read frontier sizes");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
     float ms = 0.f;
-    if (kind == GPOP_SEL_FORCE_SC) HIP_OR_RETURN(hipEventElapsedTime(&ms, ev[0], ev[1]), "elapsed");
-    else HIP_OR_RETURN(hipEventElapsedTime(&ms, ev[2], ev[3]), "elapsed");
+    HIP_OR_RETURN(hipEventElapsedTime(&ms, ev[0], ev[1]), "elapsed");
     const double total_us = (double)ms * 1e3;
     double sum = 0.0;
     std::vector<double> wt(k, 0.0);
@@ -594,40 +800,31 @@ int gpop_scatter(gpop_graph* g, void* stream) {
     if (!g) return fail(GPOP_EINVAL, "NULL graph");
     if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
     hipStream_t st = (hipStream_t)stream;
+    const BatchGrid& B = g->grid;
+    if (g->limited) {  // lift a limit an earlier gpop_run left behind
+        HIP_OR_RETURN(launch_batch_limits(B, 0xFFFFFFFFu, st), "iteration limit");
+        g->limited = false;
+    }
     int rc;
     if ((rc = timed(g, GPOP_KERNEL_PLAN, st,
                     [&] {
-                        if (g->P.selector == GPOP_SEL_LEARNED) {
-                            hipError_t e = launch_select(g->G, g->P, g->it, st);
-                            if (e != hipSuccess) return e;
-                        }
-                        return launch_plan(g->G, g->P, g->it, st);
+                        hipError_t e = launch_batch_select(B, st);
+                        return e != hipSuccess ? e : launch_batch_plan(B, st);
                     },
                     "plan")))
         return rc;
-    if ((rc = timed(g, GPOP_KERNEL_SCATTER_SC, st,
-                    [&] { return launch_scatter_sc(g->G, g->P, g->prog, g->state, g->it, st); },
-                    "scatter SC")))
+    if ((rc = timed(g, GPOP_KERNEL_SCATTER_SC, st, [&] { return launch_batch_sc(B, g->prog, st); }, "scatter SC")))
         return rc;
-    if ((rc = timed(g, GPOP_KERNEL_SCATTER_PC, st,
-                    [&] { return launch_scatter_pc(g->G, g->P, g->prog, g->state, g->it, st); },
-                    "scatter PC")))
-        return rc;
-    return GPOP_OK;
+    return timed(g, GPOP_KERNEL_SCATTER_PC, st, [&] { return launch_batch_pc(B, g->prog, st); }, "scatter PC");
 }
 
 int gpop_gather(gpop_graph* g, void* stream) {
     if (!g) return fail(GPOP_EINVAL, "NULL graph");
     if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
     hipStream_t st = (hipStream_t)stream;
-    int rc = timed(g, GPOP_KERNEL_GATHER, st,
-                   [&] { return launch_gather(g->G, g->P, g->prog, g->state, g->it, st); }, "gather");
+    int rc = timed(g, GPOP_KERNEL_GATHER, st, [&] { return launch_batch_gather(g->grid, g->prog, st); }, "gather");
     if (rc) return rc;
-    rc = timed(g, GPOP_KERNEL_MERGE, st,
-               [&] { return launch_merge(g->G, g->P, g->prog, g->state, g->it, st); }, "merge");
-    if (rc) return rc;
-    g->it += 1;
-    return GPOP_OK;
+    return timed(g, GPOP_KERNEL_MERGE, st, [&] { return launch_batch_merge(g->grid, g->prog, st); }, "merge");
 }
 
 int gpop_iterate(gpop_graph* g, void* stream) {
@@ -640,33 +837,53 @@ int gpop_run(gpop_graph* g, uint32_t max_iter, uint32_t* h_iters, void* stream) 
     if (!g) return fail(GPOP_EINVAL, "NULL graph");
     if (g->prog < 0) return fail(GPOP_ESTATE, "gpop_state_init not called");
     hipStream_t st = (hipStream_t)stream;
-    const uint32_t start = g->it;
-    uint32_t batch = 4;
-    while (g->it - start < max_iter) {
-        const uint32_t n = std::min(batch, max_iter - (g->it - start));
-        for (uint32_t i = 0; i < n; ++i) {
-            int rc = gpop_iterate(g, stream);
-            if (rc) return rc;
+    HIP_OR_RETURN(launch_batch_limits(g->grid, max_iter, st), "iteration limit");
+    g->limited = true;
+    Ctrl hc{};
+    auto finished = [&](bool& done) {
+        int r;
+        hc = read_ctrl(g, st, &r);
+        done = hc.done != 0;
+        return r;
+    };
+    int rc = GPOP_OK;
+    if (g->prof) {
+        // profiling brackets every kernel group with events on the stream,
+        // so the iterations are launched directly rather than replayed
+        const uint64_t passes = (uint64_t)max_iter / g->run.chunk + 2;
+        for (uint64_t r = 0; r < passes && !rc; ++r) {
+            for (uint32_t c = 0; c < g->run.chunk && !rc; ++c) {
+                rc = timed(g, GPOP_KERNEL_PLAN, st,
+                           [&] {
+                               hipError_t e = launch_batch_select(g->grid, st);
+                               return e != hipSuccess ? e : launch_batch_plan(g->grid, st);
+                           },
+                           "plan");
+                if (!rc) rc = timed(g, GPOP_KERNEL_SCATTER_SC, st, [&] { return launch_batch_sc(g->grid, g->prog, st); }, "scatter SC");
+                if (!rc) rc = timed(g, GPOP_KERNEL_SCATTER_PC, st, [&] { return launch_batch_pc(g->grid, g->prog, st); }, "scatter PC");
+                if (!rc) rc = timed(g, GPOP_KERNEL_GATHER, st, [&] { return launch_batch_gather(g->grid, g->prog, st); }, "gather");
+                if (!rc) rc = timed(g, GPOP_KERNEL_MERGE, st, [&] { return launch_batch_merge(g->grid, g->prog, st); }, "merge");
+            }
+            bool done = false;
+            if (!rc) rc = finished(done);
+            if (done) break;
         }
-        Ctrl hc;
-        HIP_OR_RETURN(hipMemcpyAsync(&hc, g->G.ctrl, sizeof hc, hipMemcpyDeviceToHost, st), "read control");
-        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
-        if (hc.done) {
-            g->it = hc.iters > start ? hc.iters : start;
-            break;
-        }
-        batch = std::min<uint32_t>(batch * 2, 16);
+    } else {
+        rc = runner_run(g->run, g->grid, g->prog, false, false, max_iter, nullptr, st, nullptr, nullptr, finished);
     }
-    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
-    if (h_iters) *h_iters = g->it - start;
+    if (rc) return rc;
+    if (h_iters) *h_iters = hc.pos - hc.run_start;
     return GPOP_OK;
 }
 
 int gpop_frontier_size(gpop_graph* g, uint64_t* h_out, void* stream) {
     if (!g || !h_out) return fail(GPOP_EINVAL, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
+    int rc;
+    const Ctrl hc = read_ctrl(g, st, &rc);
+    if (rc) return rc;
     std::vector<uint32_t> va(g->G.k);
-    HIP_OR_RETURN(hipMemcpyAsync(va.data(), g->G.fVa[g->it & 1u], g->G.k * 4, hipMemcpyDeviceToHost, st),
+    HIP_OR_RETURN(hipMemcpyAsync(va.data(), g->G.fVa[hc.pos & 1u], g->G.k * 4, hipMemcpyDeviceToHost, st),
                   "read frontier sizes");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
     uint64_t t = 0;
@@ -677,7 +894,10 @@ int gpop_frontier_size(gpop_graph* g, uint64_t* h_out, void* stream) {
 
 int gpop_iterations(const gpop_graph* g, uint32_t* h_out) {
     if (!g || !h_out) return fail(GPOP_EINVAL, "NULL argument");
-    *h_out = g->it;
+    int rc;
+    const Ctrl hc = read_ctrl(g, nullptr, &rc);
+    if (rc) return rc;
+    *h_out = hc.pos;
     return GPOP_OK;
 }
 
@@ -685,10 +905,13 @@ int gpop_iter_stats_read(gpop_graph* g, gpop_iter_stats* h_out, uint32_t max_rec
                          uint32_t* h_count, void* stream) {
     if (!g || !h_count || (max_records && !h_out)) return fail(GPOP_EINVAL, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
-    if (g->it > 0) HIP_OR_RETURN(launch_finalize(g->G, g->it, st), "finalize stats");
-    const uint32_t avail = std::min<uint32_t>(g->it, kLogCap);
+    HIP_OR_RETURN(launch_finalize(g->G, st), "finalize stats");
+    int rc;
+    const Ctrl hc = read_ctrl(g, st, &rc);
+    if (rc) return rc;
+    const uint32_t avail = std::min<uint32_t>(hc.pos, kLogCap);
     const uint32_t n = std::min(avail, max_records);
-    const uint32_t first = g->it - avail;
+    const uint32_t first = hc.pos - avail;
     for (uint32_t i = 0; i < n; ++i) {
         HIP_OR_RETURN(hipMemcpyAsync(h_out + i, g->G.log + ((first + i) % kLogCap), sizeof(gpop_iter_stats),
                                      hipMemcpyDeviceToHost, st), "read stats");
@@ -758,11 +981,7 @@ struct gpop_batch {
     BatchGrid grid{};
     int prog = -1;
     bool frontier_ok = false;
-    hipStream_t cap = nullptr;       // private stream used only to record the graph
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int graph_prog = -1;
-    uint32_t chunk = 4;              // iterations per graph replay
+    Runner run;
 };
 
 namespace {
@@ -816,38 +1035,6 @@ int batch_check_graphs(gpop_graph* const* graphs, uint32_t n) {
     if (!graphs || n == 0) return fail(GPOP_EINVAL, "a batch needs at least one graph");
     for (uint32_t i = 0; i < n; ++i)
         if (!graphs[i]) return fail(GPOP_EINVAL, "graph %u is NULL", i);
-    return GPOP_OK;
-}
-
-void destroy_graph_exec(gpop_batch* b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-    b->graph_prog = -1;
-}
-
-int batch_record(gpop_batch* b) {
-    destroy_graph_exec(b);
-    HIP_OR_RETURN(prepare_batch_scatter(b->grid, b->prog), "batch kernel attributes");
-    HIP_OR_RETURN(prepare_batch_gather(b->grid, b->prog), "batch kernel attributes");
-    HIP_OR_RETURN(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture");
-    hipError_t e = hipSuccess;
-    for (uint32_t c = 0; c < b->chunk && e == hipSuccess; ++c) {
-        e = launch_batch_select(b->grid, b->cap);
-        if (e == hipSuccess) e = launch_batch_scatter(b->grid, b->prog, b->cap);
-        if (e == hipSuccess) e = launch_batch_gather(b->grid, b->prog, b->cap);
-    }
-    if (e == hipSuccess) e = launch_batch_status(b->grid, b->d_status, b->cap);
-    hipGraph_t gr = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->cap, &gr);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (gr) (void)hipGraphDestroy(gr);
-        return hip_fail(e != hipSuccess ? e : e2, "record batch iterations");
-    }
-    b->graph = gr;
-    HIP_OR_RETURN(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0), "instantiate batch graph");
-    b->graph_prog = b->prog;
     return GPOP_OK;
 }
 
@@ -943,18 +1130,11 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
     HIP_OR_RETURN(hipMemcpyAsync(b->d_tab, b->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, st),
                   "write run table");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
-    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
-        delete b;
-        return fail(GPOP_EDEVICE, "cannot create the recording stream");
-    }
     *out = b;
     return GPOP_OK;
 }
 
 int gpop_batch_destroy(gpop_batch* b) {
-    if (!b) return GPOP_OK;
-    destroy_graph_exec(b);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
     return GPOP_OK;
 }
@@ -990,7 +1170,7 @@ int gpop_batch_set_frontier(gpop_batch* b, uint32_t run, const uint32_t* d_verti
     if (run >= b->inst.size()) return fail(GPOP_EINVAL, "run %u out of range", run);
     if (n && !d_vertices) return fail(GPOP_EINVAL, "NULL vertex array");
     if (!b->frontier_ok) return fail(GPOP_ESTATE, "set the frontier after gpop_batch_state_init, before running");
-    HIP_OR_RETURN(launch_set_frontier(b->inst[run].G, d_vertices, n, 0, 0, (hipStream_t)stream), "set frontier");
+    HIP_OR_RETURN(launch_set_frontier(b->inst[run].G, d_vertices, n, 0, (hipStream_t)stream), "set frontier");
     return GPOP_OK;
 }
 
@@ -998,7 +1178,7 @@ int gpop_batch_set_frontier_all(gpop_batch* b, uint32_t run, void* stream) {
     if (!b) return fail(GPOP_EINVAL, "NULL batch");
     if (run >= b->inst.size()) return fail(GPOP_EINVAL, "run %u out of range", run);
     if (!b->frontier_ok) return fail(GPOP_ESTATE, "set the frontier after gpop_batch_state_init, before running");
-    HIP_OR_RETURN(launch_set_frontier(b->inst[run].G, nullptr, 0, 1, 0, (hipStream_t)stream), "set frontier");
+    HIP_OR_RETURN(launch_set_frontier(b->inst[run].G, nullptr, 0, 1, (hipStream_t)stream), "set frontier");
     return GPOP_OK;
 }
 
@@ -1010,34 +1190,17 @@ int gpop_batch_run(gpop_batch* b, uint32_t max_iter, uint32_t flags, uint32_t* h
     const uint32_t n = (uint32_t)b->inst.size();
     b->frontier_ok = false;
     HIP_OR_RETURN(launch_batch_limits(b->grid, max_iter, st), "iteration limit");
-    const bool eager = flags & GPOP_BATCH_EAGER;
-    if (eager) {
-        HIP_OR_RETURN(prepare_batch_scatter(b->grid, b->prog), "batch kernel attributes");
-        HIP_OR_RETURN(prepare_batch_gather(b->grid, b->prog), "batch kernel attributes");
-    } else if (b->graph_prog != b->prog) {
-        int rc = batch_record(b);
-        if (rc) return rc;
-    }
-    // every run stops at its limit, so max_iter / chunk + 1 passes suffice
-    const uint64_t passes = (uint64_t)max_iter / b->chunk + 2;
-    for (uint64_t r = 0; r < passes; ++r) {
-        if (eager) {
-            for (uint32_t c = 0; c < b->chunk; ++c) {
-                HIP_OR_RETURN(launch_batch_select(b->grid, st), "batch select");
-                HIP_OR_RETURN(launch_batch_scatter(b->grid, b->prog, st), "batch scatter");
-                HIP_OR_RETURN(launch_batch_gather(b->grid, b->prog, st), "batch gather");
-            }
-            HIP_OR_RETURN(launch_batch_status(b->grid, b->d_status, st), "batch status");
-        } else {
-            HIP_OR_RETURN(hipGraphLaunch(b->exec, st), "replay batch iterations");
-        }
-        HIP_OR_RETURN(hipMemcpyAsync(b->h_status.data(), b->d_status, 8 * (size_t)n, hipMemcpyDeviceToHost, st),
-                      "read run status");
-        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
-        bool all = true;
-        for (uint32_t i = 0; i < n; ++i) all = all && b->h_status[2 * i];
-        if (all) break;
-    }
+    int rc = runner_run(b->run, b->grid, b->prog, false, (flags & GPOP_BATCH_EAGER) != 0, max_iter, b->d_status, st,
+                        nullptr, nullptr, [&](bool& done) {
+                            if (hipMemcpyAsync(b->h_status.data(), b->d_status, 8 * (size_t)n,
+                                               hipMemcpyDeviceToHost, st) != hipSuccess ||
+                                hipStreamSynchronize(st) != hipSuccess)
+                                return fail(GPOP_EDEVICE, "read run status");
+                            done = true;
+                            for (uint32_t i = 0; i < n; ++i) done = done && b->h_status[2 * i] != 0;
+                            return (int)GPOP_OK;
+                        });
+    if (rc) return rc;
     if (h_iters)
         for (uint32_t i = 0; i < n; ++i) h_iters[i] = b->h_status[2 * i + 1];
     return GPOP_OK;

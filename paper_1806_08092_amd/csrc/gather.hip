@@ -587,12 +587,6 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
 }
 
 template <int PROG, bool ROUNDS>
-__global__ __launch_bounds__(kGT, 2) void k_gather(Dev G, Params P, uint32_t* __restrict__ state,
-                                                   uint32_t it) {
-    gather_body<PROG, ROUNDS>(G, P, state, it, blockIdx.x);
-}
-
-template <int PROG, bool ROUNDS>
 __global__ __launch_bounds__(kGT, 2) void kb_gather(const Inst* __restrict__ tab,
                                                     const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
@@ -702,12 +696,6 @@ __device__ __forceinline__ void merge_body(const Dev& G, const Params& P, uint32
 }
 
 template <int PROG>
-__global__ __launch_bounds__(kGT, 2) void k_merge(Dev G, Params P, uint32_t* __restrict__ state,
-                                                  uint32_t it) {
-    merge_body<PROG>(G, P, state, it, blockIdx.x);
-}
-
-template <int PROG>
 __global__ __launch_bounds__(kGT, 2) void kb_merge(const Inst* __restrict__ tab,
                                                    const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
@@ -722,7 +710,7 @@ __global__ void kb_status(const Inst* __restrict__ tab, uint32_t n, uint32_t* __
     if (i >= n) return;
     const Ctrl* C = tab[i].G.ctrl;
     out[2 * i] = C->done;
-    out[2 * i + 1] = C->iters;
+    out[2 * i + 1] = C->pos - C->run_start;  // iterations of the current run
 }
 
 __global__ void kb_limits(const Inst* __restrict__ tab, uint32_t n, uint32_t max_iter) {
@@ -731,6 +719,8 @@ __global__ void kb_limits(const Inst* __restrict__ tab, uint32_t n, uint32_t max
     Ctrl* C = tab[i].G.ctrl;
     const uint64_t lim = (uint64_t)C->pos + max_iter;
     C->max_it = lim > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)lim;
+    C->run_start = C->pos;
+    C->done &= ~2u;  // resume a paused run
 }
 
 template <int PROG>
@@ -753,6 +743,11 @@ static hipError_t launch_batch_gather_p(const BatchGrid& B, hipStream_t st) {
         else
             hipLaunchKernelGGL((kb_gather<PROG, false>), dim3(B.nb_gather), dim3(kGT), lds, st, B.tab, B.b_gather, B.n);
     }
+    return hipGetLastError();
+}
+
+template <int PROG>
+static hipError_t launch_batch_merge_p(const BatchGrid& B, hipStream_t st) {
     if (B.nb_merge)
         hipLaunchKernelGGL(kb_merge<PROG>, dim3(B.nb_merge), dim3(kGT), gather_lds_bytes(PROG, B.q_max, false), st,
                            B.tab, B.b_merge, B.n);
@@ -776,6 +771,10 @@ hipError_t launch_batch_gather(const BatchGrid& B, int prog, hipStream_t st) {
     GPOP_PROG_SWITCH(launch_batch_gather_p, B, st)
 }
 
+hipError_t launch_batch_merge(const BatchGrid& B, int prog, hipStream_t st) {
+    GPOP_PROG_SWITCH(launch_batch_merge_p, B, st)
+}
+
 #undef GPOP_PROG_SWITCH
 
 hipError_t launch_batch_limits(const BatchGrid& B, uint32_t max_iter, hipStream_t st) {
@@ -788,52 +787,6 @@ hipError_t launch_batch_status(const BatchGrid& B, uint32_t* out, hipStream_t st
     return hipGetLastError();
 }
 
-template <int PROG>
-static hipError_t launch_gather_p(const Dev& G, const Params& P, uint32_t* state, uint32_t it,
-                                  hipStream_t st) {
-    const bool r = G.combine == GPOP_COMBINE_ROUNDS;
-    const size_t lds = gather_lds_bytes(PROG, G.q, r);
-    auto fn = r ? k_gather<PROG, true> : k_gather<PROG, false>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(G.n_gtask), dim3(kGT), lds, st, G, P, state, it);
-    return hipGetLastError();
-}
-
-template <int PROG>
-static hipError_t launch_merge_p(const Dev& G, const Params& P, uint32_t* state, uint32_t it,
-                                 hipStream_t st) {
-    if (G.n_gsplit == 0) return hipSuccess;
-    const size_t lds = gather_lds_bytes(PROG, G.q, false);
-    auto fn = k_merge<PROG>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(G.n_gsplit), dim3(kGT), lds, st, G, P, state, it);
-    return hipGetLastError();
-}
-
-#define GPOP_DISPATCH(fn)                                             \
-    switch (prog) {                                                   \
-        case P_BFS: return fn<P_BFS>(G, P, state, it, st);           \
-        case P_CC: return fn<P_CC>(G, P, state, it, st);             \
-        case P_SSSP: return fn<P_SSSP>(G, P, state, it, st);         \
-        case P_PR: return fn<P_PR>(G, P, state, it, st);             \
-        case P_PPR: return fn<P_PPR>(G, P, state, it, st);           \
-        case P_CARRY: return fn<P_CARRY>(G, P, state, it, st);       \
-    }                                                                 \
-    return hipErrorInvalidValue;
-
-hipError_t launch_gather(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
-                         hipStream_t st) {
-    GPOP_DISPATCH(launch_gather_p)
-}
-
-hipError_t launch_merge(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
-                        hipStream_t st) {
-    GPOP_DISPATCH(launch_merge_p)
-}
 
 // ---------------------------------------------------------------------------
 // Initial vertex values (val[] initialisation of each application) and the
@@ -880,6 +833,7 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
         G.ctrl->mlp_fallback = 0;
         G.ctrl->pos = 0;
         G.ctrl->max_it = 0xFFFFFFFFu;
+        G.ctrl->run_start = 0;
     }
 }
 
@@ -915,8 +869,9 @@ __global__ void k_mark(Dev G, const uint32_t* __restrict__ verts, uint32_t n) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all, uint32_t buf) {
+__global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all) {
     const uint32_t p = blockIdx.x;
+    const uint32_t buf = G.ctrl->pos & 1u;  // the buffer the next plan reads
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
@@ -968,8 +923,7 @@ __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all, uint
     }
 }
 
-hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all,
-                               uint32_t buf, hipStream_t st) {
+hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all, hipStream_t st) {
     if (!all) {
         const uint64_t nm = (uint64_t)G.k * G.q;
         hipLaunchKernelGGL(k_fill_u8, dim3(1024), dim3(256), 0, st, G.marks, nm, (uint8_t)0);
@@ -978,7 +932,7 @@ hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, 
             hipLaunchKernelGGL(k_mark, dim3(blocks), dim3(256), 0, st, G, verts, n);
         }
     }
-    hipLaunchKernelGGL(k_marks_to_frontier, dim3(G.k), dim3(1024), 0, st, G, all, buf);
+    hipLaunchKernelGGL(k_marks_to_frontier, dim3(G.k), dim3(1024), 0, st, G, all);
     return hipGetLastError();
 }
 

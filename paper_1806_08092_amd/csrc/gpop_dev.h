@@ -43,7 +43,7 @@ __host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || pro
 __host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP; }
 
 struct Ctrl {
-    uint32_t done;        // frontier became empty
+    uint32_t done;        // bit 0: frontier became empty; bit 1: paused at max_it
     uint32_t iters;       // iterations whose plan found active vertices
     uint32_t err;         // bad vertex id passed to set_frontier
     uint32_t csr_err;     // CSR validation failure code
@@ -53,9 +53,10 @@ struct Ctrl {
     double dangling;      // PageRank-family dangling mass of the current frontier
     uint32_t fin_it;      // records below this iteration are final
     uint32_t mlp_fallback;  // partitions the learned selector left to Eq. 1
-    uint32_t pos;         // batched runs: iterations planned (the next plan's index)
-    uint32_t max_it;      // batched runs: the plan of this iteration index ends the run
-    uint32_t pad[50];
+    uint32_t pos;         // iterations run so far (index of the next plan)
+    uint32_t max_it;      // a plan at this index pauses the run (done bit 2)
+    uint32_t run_start;   // pos when the current run began
+    uint32_t pad[49];
 };
 
 // Everything the kernels read or write, by value in each launch.

@@ -28,25 +28,15 @@ hipError_t launch_colmajor(const Dev& G, hipStream_t st);
 // scatter side (scatter.hip)
 size_t sc_lds_bytes(uint32_t k);
 hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st);
-hipError_t launch_plan(const Dev& G, const Params& P, uint32_t it, hipStream_t st);
-hipError_t launch_finalize(const Dev& G, uint32_t it, hipStream_t st);
-hipError_t launch_scatter_sc(const Dev& G, const Params& P, int prog, const uint32_t* state,
-                             uint32_t it, hipStream_t st);
-hipError_t launch_scatter_pc(const Dev& G, const Params& P, int prog, const uint32_t* state,
-                             uint32_t it, hipStream_t st);
+hipError_t launch_finalize(const Dev& G, hipStream_t st);
 
 // gather side (gather.hip)
 size_t gather_lds_bytes(int prog, uint32_t q, bool rounds);
-hipError_t launch_merge(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
-                        hipStream_t st);
-hipError_t launch_gather(const Dev& G, const Params& P, int prog, uint32_t* state, uint32_t it,
-                         hipStream_t st);
 hipError_t launch_state_init(const Dev& G, const Params& P, int prog, uint32_t* state,
                              hipStream_t st);
 // learned selector (select.hip)
 hipError_t launch_part_static(const Dev& G, hipStream_t st);
-hipError_t launch_select(const Dev& G, const Params& P, uint32_t it, hipStream_t st);
-hipError_t launch_features(const Dev& G, const Params& P, uint32_t it, float* out, hipStream_t st);
+hipError_t launch_features(const Dev& G, const Params& P, float* out, hipStream_t st);
 
 // batched runs: one launch per kernel covers every run of a batch
 struct BatchGrid {
@@ -66,13 +56,15 @@ struct BatchGrid {
 hipError_t prepare_batch_scatter(const BatchGrid& B, int prog);
 hipError_t prepare_batch_gather(const BatchGrid& B, int prog);
 hipError_t launch_batch_select(const BatchGrid& B, hipStream_t st);
-hipError_t launch_batch_scatter(const BatchGrid& B, int prog, hipStream_t st);
+hipError_t launch_batch_plan(const BatchGrid& B, hipStream_t st);
+hipError_t launch_batch_sc(const BatchGrid& B, int prog, hipStream_t st);
+hipError_t launch_batch_pc(const BatchGrid& B, int prog, hipStream_t st);
 hipError_t launch_batch_gather(const BatchGrid& B, int prog, hipStream_t st);
+hipError_t launch_batch_merge(const BatchGrid& B, int prog, hipStream_t st);
 hipError_t launch_batch_limits(const BatchGrid& B, uint32_t max_iter, hipStream_t st);
 hipError_t launch_batch_status(const BatchGrid& B, uint32_t* out, hipStream_t st);
 
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st);
-hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all,
-                               uint32_t buf, hipStream_t st);
+hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all, hipStream_t st);
 
 }  // namespace gpop

@@ -202,13 +202,16 @@ __global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
     sc_pass_body<PROG, BUILD, WRITE>(G, P, state, it, blockIdx.x, gridDim.x);
 }
 
+// The iteration index: the plan has already advanced pos, except in a probe.
+__device__ __forceinline__ uint32_t scatter_it(const Inst& I) { return I.G.ctrl->pos - (I.P.probe ? 0u : 1u); }
+
 template <int PROG, bool WRITE>
 __global__ __launch_bounds__(kScWaves * 64) void kb_sc_pass(const Inst* __restrict__ tab,
                                                             const uint32_t* __restrict__ boff,
                                                             uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    sc_pass_body<PROG, false, WRITE>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i],
+    sc_pass_body<PROG, false, WRITE>(I.G, I.P, I.state, scatter_it(I), blockIdx.x - boff[i],
                                      boff[i + 1] - boff[i]);
 }
 
@@ -336,28 +339,6 @@ hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st) {
     return launch_pass<P_BFS, true, true>(G, P, nullptr, 0, G.n_bldtask, st);
 }
 
-template <int PROG>
-static hipError_t launch_sc_prog(const Dev& G, const Params& P, const uint32_t* state, uint32_t it,
-                                 hipStream_t st) {
-    hipError_t e = launch_pass<PROG, false, false>(G, P, state, it, G.max_sctask, st);
-    if (e != hipSuccess) return e;
-    e = launch_scan_pass<false>(G, st);
-    if (e != hipSuccess) return e;
-    return launch_pass<PROG, false, true>(G, P, state, it, G.max_sctask, st);
-}
-
-hipError_t launch_scatter_sc(const Dev& G, const Params& P, int prog, const uint32_t* state,
-                             uint32_t it, hipStream_t st) {
-    switch (prog) {
-        case P_BFS: return launch_sc_prog<P_BFS>(G, P, state, it, st);
-        case P_CC: return launch_sc_prog<P_CC>(G, P, state, it, st);
-        case P_SSSP: return launch_sc_prog<P_SSSP>(G, P, state, it, st);
-        case P_PR: return launch_sc_prog<P_PR>(G, P, state, it, st);
-        case P_PPR: return launch_sc_prog<P_PPR>(G, P, state, it, st);
-        case P_CARRY: return launch_sc_prog<P_CARRY>(G, P, state, it, st);
-    }
-    return hipErrorInvalidValue;
-}
 
 // ---------------------------------------------------------------------------
 // Partition-centric scatter (Algorithm 3): for every q and every v in
@@ -413,44 +394,13 @@ __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uin
 }
 
 template <int PROG>
-__global__ __launch_bounds__(256) void k_pc(Dev G, Params P, const uint32_t* __restrict__ state,
-                                            uint32_t it) {
-    pc_body<PROG>(G, P, state, it, blockIdx.x);
-}
-
-template <int PROG>
 __global__ __launch_bounds__(256) void kb_pc(const Inst* __restrict__ tab, const uint32_t* __restrict__ boff,
                                              uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    pc_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+    pc_body<PROG>(I.G, I.P, I.state, scatter_it(I), blockIdx.x - boff[i]);
 }
 
-template <int PROG>
-static hipError_t launch_pc_p(const Dev& G, const Params& P, const uint32_t* state, uint32_t it,
-                              hipStream_t st) {
-    if (G.n_pctask == 0) return hipSuccess;
-    const size_t lds = (size_t)G.q * 4;
-    auto fn = k_pc<PROG>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(G.n_pctask), dim3(256), lds, st, G, P, state, it);
-    return hipGetLastError();
-}
-
-hipError_t launch_scatter_pc(const Dev& G, const Params& P, int prog, const uint32_t* state,
-                             uint32_t it, hipStream_t st) {
-    switch (prog) {
-        case P_BFS: return launch_pc_p<P_BFS>(G, P, state, it, st);
-        case P_CC: return launch_pc_p<P_CC>(G, P, state, it, st);
-        case P_SSSP: return launch_pc_p<P_SSSP>(G, P, state, it, st);
-        case P_PR: return launch_pc_p<P_PR>(G, P, state, it, st);
-        case P_PPR: return launch_pc_p<P_PPR>(G, P, state, it, st);
-        case P_CARRY: return launch_pc_p<P_CARRY>(G, P, state, it, st);
-    }
-    return hipErrorInvalidValue;
-}
 
 // Fills the stats record of iteration it - 1 (source-centric totals and ids
 // gathered) from per-partition values the previous iteration wrote. Reads
@@ -504,11 +454,15 @@ __device__ __forceinline__ void finalize_once(const Dev& G, uint32_t it) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(Dev G, uint32_t it) { finalize_once(G, it); }
+__global__ __launch_bounds__(1024) void k_finalize(Dev G) { finalize_once(G, G.ctrl->pos); }
 
 __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_t it) {
     Ctrl* C = G.ctrl;
     if (C->done) return;
+    if (!P.probe && it >= C->max_it) {  // the run's iteration limit: pause
+        if (threadIdx.x == 0) C->done = 2u;
+        return;
+    }
     const uint32_t cur = it & 1u;
     finalize_once(G, it);
     __shared__ uint64_t red[9][16];
@@ -597,6 +551,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             C->done = 1;
         } else if (!P.probe) {
             C->iters = it + 1;
+            C->pos = it + 1;
             gpop_iter_stats* r = G.log + (it % kLogCap);
             r->active_vertices = t[0];
             r->active_edges = t[1];
@@ -619,22 +574,11 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     }
 }
 
-__global__ __launch_bounds__(1024) void k_plan(Dev G, Params P, uint32_t it) { plan_body(G, P, it); }
-
-// Batched plan, one workgroup per run: the iteration index comes from the
-// run's control block; reaching its limit ends the run.
+// One workgroup per run; the iteration index comes from the run's control
+// block.
 __global__ __launch_bounds__(1024) void kb_plan(const Inst* __restrict__ tab) {
-    const Dev& G = tab[blockIdx.x].G;
-    const Params& P = tab[blockIdx.x].P;
-    Ctrl* C = G.ctrl;
-    if (C->done) return;
-    const uint32_t it = C->pos;
-    if (it >= C->max_it) {
-        if (threadIdx.x == 0) C->done = 1;
-        return;
-    }
-    plan_body(G, P, it);
-    if (threadIdx.x == 0 && !C->done) C->pos = it + 1;
+    const Inst& I = tab[blockIdx.x];
+    plan_body(I.G, I.P, I.G.ctrl->pos);
 }
 
 template <int PROG>
@@ -650,8 +594,7 @@ static hipError_t prep_batch_scatter_p(const BatchGrid& B) {
 }
 
 template <int PROG>
-static hipError_t launch_batch_scatter_p(const BatchGrid& B, hipStream_t st) {
-    hipLaunchKernelGGL(kb_plan, dim3(B.n), dim3(1024), 0, st, B.tab);
+static hipError_t launch_batch_sc_p(const BatchGrid& B, hipStream_t st) {
     if (B.nb_sc) {
         hipLaunchKernelGGL((kb_sc_pass<PROG, false>), dim3(B.nb_sc), dim3(kScWaves * 64), sc_lds_bytes(B.k_max),
                            st, B.tab, B.b_sc, B.n);
@@ -659,6 +602,11 @@ static hipError_t launch_batch_scatter_p(const BatchGrid& B, hipStream_t st) {
         hipLaunchKernelGGL((kb_sc_pass<PROG, true>), dim3(B.nb_sc), dim3(kScWaves * 64), sc_lds_bytes(B.k_max),
                            st, B.tab, B.b_sc, B.n);
     }
+    return hipGetLastError();
+}
+
+template <int PROG>
+static hipError_t launch_batch_pc_p(const BatchGrid& B, hipStream_t st) {
     if (B.nb_pc)
         hipLaunchKernelGGL(kb_pc<PROG>, dim3(B.nb_pc), dim3(256), (size_t)B.q_max * 4, st, B.tab, B.b_pc, B.n);
     return hipGetLastError();
@@ -677,19 +625,20 @@ static hipError_t launch_batch_scatter_p(const BatchGrid& B, hipStream_t st) {
 
 hipError_t prepare_batch_scatter(const BatchGrid& B, int prog) { GPOP_PROG_SWITCH(prep_batch_scatter_p, B) }
 
-hipError_t launch_batch_scatter(const BatchGrid& B, int prog, hipStream_t st) {
-    GPOP_PROG_SWITCH(launch_batch_scatter_p, B, st)
-}
-
-#undef GPOP_PROG_SWITCH
-
-hipError_t launch_plan(const Dev& G, const Params& P, uint32_t it, hipStream_t st) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, G, P, it);
+hipError_t launch_batch_plan(const BatchGrid& B, hipStream_t st) {
+    hipLaunchKernelGGL(kb_plan, dim3(B.n), dim3(1024), 0, st, B.tab);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Dev& G, uint32_t it, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, G, it);
+hipError_t launch_batch_sc(const BatchGrid& B, int prog, hipStream_t st) { GPOP_PROG_SWITCH(launch_batch_sc_p, B, st) }
+
+hipError_t launch_batch_pc(const BatchGrid& B, int prog, hipStream_t st) { GPOP_PROG_SWITCH(launch_batch_pc_p, B, st) }
+
+#undef GPOP_PROG_SWITCH
+
+
+hipError_t launch_finalize(const Dev& G, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, G);
     return hipGetLastError();
 }
 

@@ -74,10 +74,6 @@ __device__ __forceinline__ void select_body(const Dev& G, const Params& P, uint3
     G.mode_l[p] = md;
 }
 
-__global__ __launch_bounds__(64) void k_select(Dev G, Params P, uint32_t it) {
-    select_body(G, P, it, blockIdx.x);
-}
-
 // Batched: runs whose selector is not the learned one skip.
 __global__ __launch_bounds__(64) void kb_select(const Inst* __restrict__ tab,
                                                 const uint32_t* __restrict__ boff, uint32_t n) {
@@ -87,7 +83,8 @@ __global__ __launch_bounds__(64) void kb_select(const Inst* __restrict__ tab,
     select_body(I.G, I.P, I.G.ctrl->pos, blockIdx.x - boff[i]);
 }
 
-__global__ __launch_bounds__(64) void k_features(Dev G, Params P, uint32_t it, float* __restrict__ out) {
+__global__ __launch_bounds__(64) void k_features(Dev G, Params P, float* __restrict__ out) {
+    const uint32_t it = G.ctrl->pos;
     const uint32_t cur = it & 1u;
     const float ea_frac = active_edge_fraction(G, cur);
     const uint32_t p = blockIdx.x * 64 + lane_id();
@@ -108,13 +105,9 @@ hipError_t launch_part_static(const Dev& G, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_select(const Dev& G, const Params& P, uint32_t it, hipStream_t st) {
-    hipLaunchKernelGGL(k_select, dim3((G.k + 63) / 64), dim3(64), 0, st, G, P, it);
-    return hipGetLastError();
-}
 
-hipError_t launch_features(const Dev& G, const Params& P, uint32_t it, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_features, dim3((G.k + 63) / 64), dim3(64), 0, st, G, P, it, out);
+hipError_t launch_features(const Dev& G, const Params& P, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_features, dim3((G.k + 63) / 64), dim3(64), 0, st, G, P, out);
     return hipGetLastError();
 }
 
