@@ -585,6 +585,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     B.k_max = G.k;
     B.q_max = G.q;
     B.rounds = G.combine == GPOP_COMBINE_ROUNDS;
+    B.view = &g->G;
     for (int i = 0; i < 2; ++i) {
         g->probe_grid[i] = B;
         g->probe_grid[i].tab = d_tab + 1 + i;

@@ -581,6 +581,14 @@ __global__ __launch_bounds__(1024) void kb_plan(const Inst* __restrict__ tab) {
     plan_body(I.G, I.P, I.G.ctrl->pos);
 }
 
+// A single run's plan with its view as a kernel argument: the compiler may
+// then re-read view fields instead of keeping them all in registers (read
+// from memory they spill); the parameters still come from the run table.
+__global__ __launch_bounds__(1024) void k_plan1(Dev G, const Params* __restrict__ pp) {
+    const Params P = *pp;
+    plan_body(G, P, G.ctrl->pos);
+}
+
 template <int PROG>
 static hipError_t prep_batch_scatter_p(const BatchGrid& B) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_sc_pass<PROG, false>),
@@ -626,7 +634,8 @@ static hipError_t launch_batch_pc_p(const BatchGrid& B, hipStream_t st) {
 hipError_t prepare_batch_scatter(const BatchGrid& B, int prog) { GPOP_PROG_SWITCH(prep_batch_scatter_p, B) }
 
 hipError_t launch_batch_plan(const BatchGrid& B, hipStream_t st) {
-    hipLaunchKernelGGL(kb_plan, dim3(B.n), dim3(1024), 0, st, B.tab);
+    if (B.view) hipLaunchKernelGGL(k_plan1, dim3(1), dim3(1024), 0, st, *B.view, &B.tab->P);
+    else hipLaunchKernelGGL(kb_plan, dim3(B.n), dim3(1024), 0, st, B.tab);
     return hipGetLastError();
 }
 
