@@ -534,6 +534,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     G.n_gtask = (uint32_t)(gt.size() / 2);
     G.n_gsplit = (uint32_t)gs.size();
     G.combine = opts ? opts->combine : GPOP_COMBINE_LDS;
+    G.whole_ids = (uint32_t)std::min<uint64_t>(z.T / 2, 0x7FFFFFFFull);
     HIP_OR_RETURN(hipMemcpyAsync(G.gtask, gt.data(), gt.size() * sizeof(uint4), hipMemcpyHostToDevice, st),
                   "write gather tasks");
     if (!gs.empty())

@@ -233,7 +233,8 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     // pieces per wave per combine round (the atomic-free sum keeps two, for registers)
     constexpr uint32_t PPW = (ROUNDS && SUM) ? 2 : 4;
     const uint4 TA = G.gtask[2 * task], TB = G.gtask[2 * task + 1];
-    const uint32_t cq = TA.x, p_lo = TA.y, p_hi = TA.z, nt = TA.w >> 16;
+    const uint32_t cq = TA.x, nt = TA.w >> 16, jt = TA.w & 0xFFFFu;
+    uint32_t p_lo = TA.y, p_hi = TA.z;
     // the two id / weight / chunk arrays a piece may come from, as uniform
     // values (a per-lane choice between two fields of the view would
     // otherwise become a per-lane load of the pointer itself)
@@ -243,8 +244,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     const uint8_t* __restrict__ w_pc = uniform_ptr(G.png_w);
     const uint32_t* __restrict__ ch_sc = uniform_ptr(G.sc_chunk);
     const uint32_t* __restrict__ ch_pc = uniform_ptr(G.png_chunk);
-    const uint32_t s0 = TB.x, s1 = TB.y, slot = TB.z;
-    const bool split = nt > 1;
+    uint32_t s0 = TB.x, s1 = TB.y;
+    const uint32_t slot = TB.z;
+    bool split = nt > 1;
     const uint32_t cur = it & 1u, nxt = cur ^ 1u;
     const uint32_t k = G.k, Q = G.q;
     const uint32_t vbase = cq << G.s;
@@ -266,6 +268,38 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     uint32_t* bl_jlo = reinterpret_cast<uint32_t*>(smem + L.bl_jlo);
     uint32_t* bl_scan = reinterpret_cast<uint32_t*>(smem + L.bl_scan);
     __shared__ GatherShared sh;
+
+    // ---- a split partition with few ids this iteration (a sparse frontier)
+    //      is gathered whole by its first task: no partial results, no merge
+    if (split) {
+        uint32_t c = 0;
+        for (uint32_t p = tid; p < k; p += kGT) {
+            const uint32_t md = G.mode[p];
+            c += md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
+        }
+        c = wave_sum_u32(c);
+        if (lane == 0) sh.wc[wave] = c;
+        __syncthreads();
+        uint32_t tot = 0;
+        for (uint32_t w = 0; w < kGW; ++w) tot += sh.wc[w];
+        __syncthreads();
+        if (tot <= G.whole_ids) {
+            if (jt != 0) {
+                if (tid == 0) {
+                    G.gflag[slot] = 0;
+                    G.gat_ids[task] = 0;
+                    G.gat_ran[task] = 0;
+                }
+                return;
+            }
+            if (tid == 0) G.gflag[slot] = 2;  // the merge skips this partition
+            split = false;
+            p_lo = 0;
+            p_hi = k - 1;
+            s0 = 0;
+            s1 = 0xFFFFFFFFu;
+        }
+    }
 
     // ---- anything to do for this task?
     int any = (!split && G.fVa[cur][cq] > 0) ? 1 : 0;
@@ -616,6 +650,10 @@ __device__ __forceinline__ void merge_body(const Dev& G, const Params& P, uint32
     __shared__ uint32_t s_flag[64];
     for (uint32_t j = threadIdx.x; j < 64; j += kGT) s_flag[j] = j < nt ? G.gflag[slot0 + j] : 0u;
     __syncthreads();
+    if (s_flag[0] == 2) {  // gathered whole by its first task
+        if (threadIdx.x == 0) G.gat_ran[G.n_gtask + sidx] = 0;
+        return;
+    }
     {
         const uint32_t cur = it & 1u, nxt = cur ^ 1u;
         int any = threadIdx.x < 64 && s_flag[threadIdx.x];

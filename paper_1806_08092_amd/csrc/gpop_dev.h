@@ -70,6 +70,7 @@ struct Dev {
     uint32_t n_gtask;         // gather tasks (static)
     uint32_t n_gsplit;        // partitions whose gather is split over tasks
     uint32_t combine;         // GPOP_COMBINE_*
+    uint32_t whole_ids;       // a split partition with at most this many ids is gathered by one task
     uint64_t E;
     const uint32_t* off;
     const uint32_t* cols;
