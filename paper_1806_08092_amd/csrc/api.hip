@@ -15,7 +15,7 @@ using namespace gpop;
 
 namespace {
 
-constexpr uint32_t kPcTask = 32768;  // message slots per partition-centric task
+constexpr uint32_t kPcTask = 65536;  // message slots per partition-centric task
 
 thread_local std::string g_err;
 

@@ -681,21 +681,41 @@ __device__ __forceinline__ void merge_body(const Dev& G, const Params& P, uint32
     __syncthreads();
     // every thread owns up to kMU vertices (u = tid + kGT * i); for each
     // written partial it loads all of them at once
-    constexpr uint32_t kMU = 16;
+    // the written partials, compacted; every thread owns kMU vertices
+    // (u = tid + kGT * i) and loads them from kPJ partials at once
+    __shared__ uint32_t s_wl[64];
+    __shared__ uint32_t s_nw;
+    if (threadIdx.x == 0) {
+        uint32_t c = 0;
+        for (uint32_t j = 0; j < nt; ++j)
+            if ((written >> j) & 1u) s_wl[c++] = slot0 + j;
+        s_nw = c;
+    }
+    __syncthreads();
+    const uint32_t nw = s_nw;
+    constexpr uint32_t kMU = 8, kPJ = 4;
     for (uint32_t ub = 0; ub < nv; ub += kGT * kMU) {
         if constexpr (SUM) {
             unsigned long long a[kMU];
 #pragma unroll
             for (uint32_t i = 0; i < kMU; ++i) a[i] = 0ull;
             const unsigned long long* part = reinterpret_cast<const unsigned long long*>(G.gpart);
-            for (uint32_t j = 0; j < nt; ++j) {
-                if (!((written >> j) & 1u)) continue;
-                const unsigned long long* pj = part + (size_t)(slot0 + j) * Q;
+            for (uint32_t w = 0; w < nw; w += kPJ) {
+                unsigned long long x[kPJ][kMU];
 #pragma unroll
-                for (uint32_t i = 0; i < kMU; ++i) {
-                    const uint32_t u = ub + threadIdx.x + kGT * i;
-                    if (u < nv) a[i] += pj[u];
+                for (uint32_t r = 0; r < kPJ; ++r) {
+                    const bool ok = w + r < nw;
+                    const unsigned long long* pj = part + (size_t)s_wl[ok ? w + r : w] * Q;
+#pragma unroll
+                    for (uint32_t i = 0; i < kMU; ++i) {
+                        const uint32_t u = ub + threadIdx.x + kGT * i;
+                        x[r][i] = (ok && u < nv) ? pj[u] : 0ull;
+                    }
                 }
+#pragma unroll
+                for (uint32_t r = 0; r < kPJ; ++r)
+#pragma unroll
+                    for (uint32_t i = 0; i < kMU; ++i) a[i] += x[r][i];
             }
 #pragma unroll
             for (uint32_t i = 0; i < kMU; ++i) {
@@ -709,17 +729,23 @@ __device__ __forceinline__ void merge_body(const Dev& G, const Params& P, uint32
                 const uint32_t u = ub + threadIdx.x + kGT * i;
                 m[i] = u < nv ? st32[u] : 0u;
             }
-            for (uint32_t j = 0; j < nt; ++j) {
-                if (!((written >> j) & 1u)) continue;
-                const uint32_t* pj = G.gpart + (size_t)(slot0 + j) * 2 * Q;
-                uint32_t x[kMU];
+            for (uint32_t w = 0; w < nw; w += kPJ) {
+                uint32_t x[kPJ][kMU];
 #pragma unroll
-                for (uint32_t i = 0; i < kMU; ++i) {
-                    const uint32_t u = ub + threadIdx.x + kGT * i;
-                    x[i] = u < nv ? pj[u] : 0xFFFFFFFFu;
+                for (uint32_t r = 0; r < kPJ; ++r) {
+                    // past the end, re-read the first partial of the group:
+                    // min is idempotent
+                    const uint32_t* pj = G.gpart + (size_t)s_wl[w + r < nw ? w + r : w] * 2 * Q;
+#pragma unroll
+                    for (uint32_t i = 0; i < kMU; ++i) {
+                        const uint32_t u = ub + threadIdx.x + kGT * i;
+                        x[r][i] = u < nv ? pj[u] : 0xFFFFFFFFu;
+                    }
                 }
 #pragma unroll
-                for (uint32_t i = 0; i < kMU; ++i) m[i] = min(m[i], x[i]);
+                for (uint32_t r = 0; r < kPJ; ++r)
+#pragma unroll
+                    for (uint32_t i = 0; i < kMU; ++i) m[i] = min(m[i], x[r][i]);
             }
 #pragma unroll
             for (uint32_t i = 0; i < kMU; ++i) {
