@@ -103,9 +103,9 @@ typedef struct gpop_options {
     uint32_t log2_part;   /* q = 2^log2_part vertices per partition, 8..15;
                              0 picks 14 (16384 vertices)                        */
     uint32_t sc_task_log2;     /* log2 of active edges per source-centric task,
-                                  6..24; 0 picks max(2048, 8k)                  */
+                                  6..24; 0 picks max(1024, 4k)                  */
     uint32_t gather_task_ids;  /* ids per gather task (>= 256); 0 picks
-                                  max(2^18, E / 512). A partition whose bins
+                                  max(2^19, E / 256). A partition whose bins
                                   hold more ids is gathered by several tasks
                                   (at most 64) and merged                      */
     uint32_t combine;          /* GPOP_COMBINE_LDS (0) or GPOP_COMBINE_ROUNDS   */

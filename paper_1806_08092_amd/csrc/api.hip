@@ -101,9 +101,9 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Task sizes of a graph: active out-edges per source-centric task (at least
-// 2048 and at least 8k, so the per-task count row stays small next to the
-// task's edges) and ids per gather task (enough tasks to spread hub
-// partitions over the chip).
+// 1024 and at least 4k, so the per-task count row stays small next to the
+// task's edges) and ids per gather task (about one task per CU for a dense
+// iteration; heavier partitions are split over several).
 struct Sizes {
     uint32_t s, sc_shift;
     uint64_t q, k, T;
@@ -114,10 +114,10 @@ Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
     z.s = s;
     z.q = 1ull << s;
     z.k = (V + z.q - 1) / z.q;
-    z.sc_shift = 11;
-    while ((1ull << z.sc_shift) < 8 * z.k) ++z.sc_shift;
+    z.sc_shift = 10;
+    while ((1ull << z.sc_shift) < 4 * z.k) ++z.sc_shift;
     if (o && o->sc_task_log2) z.sc_shift = o->sc_task_log2;
-    z.T = std::max<uint64_t>(1ull << 18, E / 512);
+    z.T = std::max<uint64_t>(1ull << 19, E / 256);
     if (o && o->gather_task_ids) z.T = o->gather_task_ids;
     return z;
 }
