@@ -159,6 +159,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->gsplit = (uint4*)take(k * 16);
     G->gpart = (uint32_t*)take(ngt * q * 8);
     G->gflag = (uint32_t*)take(ngt * 4);
+    G->mtot = (uint4*)take(k * kMaxMergeChunks * 16);
     G->data = (uint32_t*)take(E_pad * 4);
     G->sc_ids = (uint16_t*)take(E_pad * 2);
     G->sc_w = (uint8_t*)take(E_pad);
@@ -548,7 +549,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
 
     // the graph's own run as a batch of one: per kernel, blocks [0, n)
     const uint32_t nb[6] = {(G.k + 63) / 64, std::min<uint32_t>((G.max_sctask + kScWaves - 1) / kScWaves, 2048u),
-                            G.k, G.n_pctask, G.n_gtask, G.n_gsplit};
+                            G.k, G.n_pctask, G.n_gtask, G.n_gsplit * merge_chunks(G.q)};
     uint32_t hb[12];
     for (int j = 0; j < 6; ++j) {
         hb[2 * j] = 0;
@@ -1026,6 +1027,7 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     D->probe = (unsigned long long*)take(3 * k * 8);
     D->gpart = (uint32_t*)take(ngt * q * 8);
     D->gflag = (uint32_t*)take(ngt * 4);
+    D->mtot = (uint4*)take(k * kMaxMergeChunks * 16);
     return o;
 }
 
@@ -1089,7 +1091,7 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
         I.state = nullptr;
         const Dev& S = g->G;
         const uint32_t nb[6] = {(S.k + 63) / 64, std::min<uint32_t>((S.max_sctask + kScWaves - 1) / kScWaves, sc_cap),
-                                S.k, S.n_pctask, S.n_gtask, S.n_gsplit};
+                                S.k, S.n_pctask, S.n_gtask, S.n_gsplit * merge_chunks(S.q)};
         for (int j = 0; j < 6; ++j) hb[(size_t)j * (n + 1) + i + 1] = hb[(size_t)j * (n + 1) + i] + nb[j];
         k_max = std::max(k_max, S.k);
         q_max = std::max(q_max, S.q);

@@ -628,143 +628,280 @@ __global__ __launch_bounds__(kGT, 2) void kb_gather(const Inst* __restrict__ tab
     gather_body<PROG, ROUNDS>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
 }
 
-// Merge of a partition whose gather was split over several tasks: combines
-// the partial results (min, or exact fixed-point sum) with the state, then
-// runs reInit and the filter like a single-task gather.
+// Merge of a partition whose gather was split over several tasks, in two
+// kernels over chunks of kMergeSpan vertices (several workgroups per
+// partition, so that a few heavy partitions still spread over the chip):
+//  - merge_part: per chunk, the state (min programs) or zero (sum programs),
+//    reInit from the frontier bitmap, the combine of the written partials
+//    (min, or exact fixed-point sum), the filter and the state write-back;
+//    the keep bits go to the next frontier bitmap, the chunk's kept count,
+//    kept out-edges and dangling sum to mtot;
+//  - merge_list: per chunk, the next frontier list and active-edge prefix
+//    from the bitmap, at the offsets the earlier chunks' counts give; chunk 0
+//    writes the partition's V_a, E_a and dangling sum (chunk order, so the
+//    sum is the same on every run).
+constexpr uint32_t kMT = 256;        // merge workgroup
+constexpr uint32_t kMW = kMT / 64;
+constexpr uint32_t kMU = kMergeSpan / kMT;  // vertices per thread
+constexpr uint32_t kPJ = 4;          // partials loaded at once
+constexpr uint32_t kWholeCol = 0xFFFFFFFFu;
+
 template <int PROG>
-__device__ __forceinline__ void merge_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
-                                           uint32_t it, uint32_t sidx) {
+__device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
+                                                uint32_t it, uint32_t local) {
     if (G.ctrl->done) return;
     constexpr bool SUM = is_sum(PROG);
+    const uint32_t Q = G.q, C = merge_chunks(Q), R = Q / C;
+    const uint32_t sidx = local / C, c = local - sidx * C;
     const uint4 S = G.gsplit[sidx];
     const uint32_t cq = S.x, nt = S.z, slot0 = S.w;
-    const uint32_t Q = G.q;
     const uint32_t vbase = cq << G.s;
     const uint32_t nv = min(Q, G.V - vbase);
-    extern __shared__ __align__(16) unsigned char smem[];
-    const GatherLds L = gather_layout(PROG, Q);
-    uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
-    uint8_t* carry = smem + L.carry;
-    __shared__ GatherShared sh;
-    __shared__ uint32_t s_flag[64];
-    for (uint32_t j = threadIdx.x; j < 64; j += kGT) s_flag[j] = j < nt ? G.gflag[slot0 + j] : 0u;
-    __syncthreads();
-    if (s_flag[0] == 2) {  // gathered whole by its first task
-        if (threadIdx.x == 0) G.gat_ran[G.n_gtask + sidx] = 0;
-        return;
-    }
-    {
-        const uint32_t cur = it & 1u, nxt = cur ^ 1u;
-        int any = threadIdx.x < 64 && s_flag[threadIdx.x];
-        any = __syncthreads_or(any || G.fVa[cur][cq] > 0);
-        if (!any) {
-            if (threadIdx.x == 0) {
-                G.fVa[nxt][cq] = 0;
-                G.fEa[nxt][cq] = 0;
-                G.dpart[nxt][cq] = 0.0;
-                G.gat_ran[G.n_gtask + sidx] = 0;
-            }
-            return;
-        }
-        if (threadIdx.x == 0) G.gat_ran[G.n_gtask + sidx] = 3;
-    }
-    for (uint32_t u = threadIdx.x; u < Q; u += kGT) {
-        if constexpr (has_carry(PROG)) carry[u] = 0;
-        if constexpr (SUM) acc[u] = 0ull;
-        else st32[u] = u < nv ? state[vbase + u] : 0xFFFFFFFFu;
-    }
-    __syncthreads();
-    uint64_t written = 0;  // partials that were written (at most 64 tasks per partition)
-    for (uint32_t j = 0; j < nt; ++j) written |= (s_flag[j] ? 1ull : 0ull) << j;
-    reinit<PROG>(G, P, it, cq, st32, carry);  // initFunc sees the values from before gather
-    __syncthreads();
-    // every thread owns up to kMU vertices (u = tid + kGT * i); for each
-    // written partial it loads all of them at once
-    // the written partials, compacted; every thread owns kMU vertices
-    // (u = tid + kGT * i) and loads them from kPJ partials at once
-    __shared__ uint32_t s_wl[64];
+    const uint32_t cur = it & 1u, nxt = cur ^ 1u;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    __shared__ uint32_t s_wl[64];  // written partials, compacted (at most 64 tasks per partition)
     __shared__ uint32_t s_nw;
-    if (threadIdx.x == 0) {
-        uint32_t c = 0;
-        for (uint32_t j = 0; j < nt; ++j)
-            if ((written >> j) & 1u) s_wl[c++] = slot0 + j;
-        s_nw = c;
+    __shared__ uint32_t s_wc[kMW], s_we[kMW];
+    __shared__ double s_wd[kMW];
+    if (wave == 0) {
+        const uint32_t f = lane < nt ? G.gflag[slot0 + lane] : 0u;
+        const uint32_t f0 = (uint32_t)__shfl((int)f, 0, 64);
+        const uint64_t wm = ballot(f != 0u);
+        if (f) s_wl[popc_lt(wm)] = slot0 + lane;
+        if (lane == 0) s_nw = f0 == 2u ? kWholeCol : popc64(wm);
     }
     __syncthreads();
     const uint32_t nw = s_nw;
-    constexpr uint32_t kMU = 8, kPJ = 4;
-    for (uint32_t ub = 0; ub < nv; ub += kGT * kMU) {
+    const bool lead = c == 0 && tid == 0;
+    if (nw == kWholeCol) {  // gathered whole by its first task
+        if (lead) G.gat_ran[G.n_gtask + sidx] = 0;
+        return;
+    }
+    const bool prev = G.fVa[cur][cq] > 0;  // frontier bitmap of cq is current
+    if (nw == 0 && !prev) {
+        if (lead) {
+            G.fVa[nxt][cq] = 0;
+            G.fEa[nxt][cq] = 0;
+            G.dpart[nxt][cq] = 0.0;
+            G.gat_ran[G.n_gtask + sidx] = 0;
+        }
+        return;
+    }
+    if (lead) G.gat_ran[G.n_gtask + sidx] = 3;
+
+    const uint32_t ulo = c * R, nu = R / kMT;
+    const uint32_t* __restrict__ pbits = G.fbits[cur] + (vbase >> 5);
+    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
+    const uint32_t* __restrict__ off = G.off;
+    const double dang = SUM ? G.ctrl->dangling : 0.0;
+    // the thread's vertices u = ulo + kMT * i + tid: state before gather
+    // (min programs), combined value, initFunc's keep-active flag
+    uint32_t m0[kMU], m[kMU];
+    unsigned long long a[kMU];
+    bool was[kMU];
+#pragma unroll
+    for (uint32_t i = 0; i < kMU; ++i) {
+        const uint32_t u = ulo + kMT * i + tid;
+        const bool in = i < nu && u < nv;
+        was[i] = in && prev && test_bit(pbits, u);
+        if constexpr (SUM) a[i] = 0ull;
+        else m0[i] = m[i] = in ? state[vbase + u] : 0xFFFFFFFFu;
+    }
+    for (uint32_t w = 0; w < nw; w += kPJ) {
         if constexpr (SUM) {
-            unsigned long long a[kMU];
-#pragma unroll
-            for (uint32_t i = 0; i < kMU; ++i) a[i] = 0ull;
             const unsigned long long* part = reinterpret_cast<const unsigned long long*>(G.gpart);
-            for (uint32_t w = 0; w < nw; w += kPJ) {
-                unsigned long long x[kPJ][kMU];
+            unsigned long long x[kPJ][kMU];
 #pragma unroll
-                for (uint32_t r = 0; r < kPJ; ++r) {
-                    const bool ok = w + r < nw;
-                    const unsigned long long* pj = part + (size_t)s_wl[ok ? w + r : w] * Q;
+            for (uint32_t r = 0; r < kPJ; ++r) {
+                const bool ok = w + r < nw;
+                const unsigned long long* pj = part + (size_t)s_wl[ok ? w + r : w] * Q;
 #pragma unroll
-                    for (uint32_t i = 0; i < kMU; ++i) {
-                        const uint32_t u = ub + threadIdx.x + kGT * i;
-                        x[r][i] = (ok && u < nv) ? pj[u] : 0ull;
-                    }
+                for (uint32_t i = 0; i < kMU; ++i) {
+                    const uint32_t u = ulo + kMT * i + tid;
+                    x[r][i] = (ok && i < nu && u < nv) ? pj[u] : 0ull;
                 }
-#pragma unroll
-                for (uint32_t r = 0; r < kPJ; ++r)
-#pragma unroll
-                    for (uint32_t i = 0; i < kMU; ++i) a[i] += x[r][i];
             }
 #pragma unroll
-            for (uint32_t i = 0; i < kMU; ++i) {
-                const uint32_t u = ub + threadIdx.x + kGT * i;
-                if (u < nv) acc[u] = a[i] | (acc[u] & kCarried);
-            }
+            for (uint32_t r = 0; r < kPJ; ++r)
+#pragma unroll
+                for (uint32_t i = 0; i < kMU; ++i) a[i] += x[r][i];
         } else {
-            uint32_t m[kMU];
+            uint32_t x[kPJ][kMU];
 #pragma unroll
-            for (uint32_t i = 0; i < kMU; ++i) {
-                const uint32_t u = ub + threadIdx.x + kGT * i;
-                m[i] = u < nv ? st32[u] : 0u;
-            }
-            for (uint32_t w = 0; w < nw; w += kPJ) {
-                uint32_t x[kPJ][kMU];
+            for (uint32_t r = 0; r < kPJ; ++r) {
+                // past the end, re-read the first partial of the group: min
+                // is idempotent
+                const uint32_t* pj = G.gpart + (size_t)s_wl[w + r < nw ? w + r : w] * 2 * Q;
 #pragma unroll
-                for (uint32_t r = 0; r < kPJ; ++r) {
-                    // past the end, re-read the first partial of the group:
-                    // min is idempotent
-                    const uint32_t* pj = G.gpart + (size_t)s_wl[w + r < nw ? w + r : w] * 2 * Q;
-#pragma unroll
-                    for (uint32_t i = 0; i < kMU; ++i) {
-                        const uint32_t u = ub + threadIdx.x + kGT * i;
-                        x[r][i] = u < nv ? pj[u] : 0xFFFFFFFFu;
-                    }
+                for (uint32_t i = 0; i < kMU; ++i) {
+                    const uint32_t u = ulo + kMT * i + tid;
+                    x[r][i] = (i < nu && u < nv) ? pj[u] : 0xFFFFFFFFu;
                 }
-#pragma unroll
-                for (uint32_t r = 0; r < kPJ; ++r)
-#pragma unroll
-                    for (uint32_t i = 0; i < kMU; ++i) m[i] = min(m[i], x[r][i]);
             }
 #pragma unroll
-            for (uint32_t i = 0; i < kMU; ++i) {
-                const uint32_t u = ub + threadIdx.x + kGT * i;
-                if (u < nv) st32[u] = m[i];
-            }
+            for (uint32_t r = 0; r < kPJ; ++r)
+#pragma unroll
+                for (uint32_t i = 0; i < kMU; ++i) m[i] = min(m[i], x[r][i]);
         }
     }
+    // filterFunc and state write-back, as for a single-task partition
+    uint32_t cnt = 0, edges = 0;
+    double my_d = 0.0;
+#pragma unroll
+    for (uint32_t i = 0; i < kMU; ++i) {
+        if (i < nu) {
+            const uint32_t u = ulo + kMT * i + tid;
+            const uint32_t v = vbase + u;
+            bool keep = false;
+            if (u < nv) {
+                if constexpr (!SUM) {
+                    const bool hit = m[i] < m0[i];
+                    keep = hit;
+                    if constexpr (has_carry(PROG)) keep = keep || (was[i] && (it + 1u - m0[i]) < P.persist);
+                    if (hit) state[v] = m[i];
+                } else {
+                    if (a[i] != 0ull || was[i]) {  // received an amount, or was active before scatter
+                        const double y = (double)a[i] * kInvFix;
+                        float x;
+                        if constexpr (PROG == P_PR) {
+                            const double d = (double)P.damping;
+                            x = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
+                            keep = true;
+                        } else {
+                            const double al = (double)P.alpha;
+                            double xd = (1.0 - al) * y;
+                            if (v == P.root) xd += al + (1.0 - al) * dang;
+                            x = (float)xd;
+                            keep = x > 0.0f;
+                        }
+                        state[v] = __float_as_uint(x);
+                        if (off[v + 1] == off[v]) my_d += (double)x;
+                    }
+                }
+                if (keep) edges += off[v + 1] - off[v];
+            }
+            const uint64_t km = ballot(keep);
+            if (lane == 0) {
+                const uint32_t wi = (ulo + kMT * i + wave * 64u) >> 5;
+                nbits[wi] = (uint32_t)km;
+                nbits[wi + 1] = (uint32_t)(km >> 32);
+            }
+            cnt += popc64(km);
+        }
+    }
+    edges = wave_sum_u32(edges);
+    my_d = wave_sum_f64(my_d);
+    if (lane == 0) {
+        s_wc[wave] = cnt;
+        s_we[wave] = edges;
+        s_wd[wave] = my_d;
+    }
     __syncthreads();
-    finish_partition<PROG>(G, P, state, it, cq, st32, acc, carry,
-                           reinterpret_cast<uint64_t*>(smem + L.bl_ioff), sh, 0, 0xFFFFFFFFu);
+    if (tid == 0) {
+        uint32_t tc = 0, te = 0;
+        double td = 0.0;
+        for (uint32_t w = 0; w < kMW; ++w) {
+            tc += s_wc[w];
+            te += s_we[w];
+            td += s_wd[w];
+        }
+        const unsigned long long db = (unsigned long long)__double_as_longlong(td);
+        G.mtot[(size_t)sidx * C + c] = make_uint4(tc, te, (uint32_t)db, (uint32_t)(db >> 32));
+    }
+}
+
+__device__ __forceinline__ void merge_list_body(const Dev& G, uint32_t it, uint32_t local) {
+    if (G.ctrl->done) return;
+    const uint32_t Q = G.q, C = merge_chunks(Q), R = Q / C;
+    const uint32_t sidx = local / C, c = local - sidx * C;
+    if (G.gat_ran[G.n_gtask + sidx] != 3u) return;
+    const uint32_t cq = G.gsplit[sidx].x;
+    const uint32_t vbase = cq << G.s;
+    const uint32_t nxt = (it & 1u) ^ 1u;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    __shared__ uint32_t s_wc[kMW], s_we[kMW], s_base[2];
+    if (wave == 0) {
+        const uint4 t = lane < C ? G.mtot[(size_t)sidx * C + lane] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t before = wave_sum_u32(lane < c ? t.x : 0u);
+        const uint32_t ebefore = wave_sum_u32(lane < c ? t.y : 0u);
+        const double d = __longlong_as_double((long long)(((unsigned long long)t.w << 32) | t.z));
+        if (c == 0) {
+            const uint32_t tot = wave_sum_u32(t.x), etot = wave_sum_u32(t.y);
+            double sd = 0.0;
+            for (uint32_t j = 0; j < C; ++j) sd += __shfl(d, (int)j, 64);
+            if (lane == 0) {
+                G.fVa[nxt][cq] = tot;
+                G.fEa[nxt][cq] = etot;
+                G.dpart[nxt][cq] = sd;
+            }
+        }
+        if (lane == 0) {
+            s_base[0] = before;
+            s_base[1] = ebefore;
+        }
+    }
+    // wave w lists the vertices [ulo + w * per, ulo + (w + 1) * per)
+    const uint32_t per = R / kMW, ng = per / 64;
+    const uint32_t ub = c * R + wave * per;
+    const uint32_t* __restrict__ bits = G.fbits[nxt] + (vbase >> 5);
+    const uint32_t* __restrict__ off = G.off + vbase;
+    uint32_t deg[kMU];
+    uint64_t km[kMU];
+    uint32_t cnt = 0, edges = 0;
+#pragma unroll
+    for (uint32_t g = 0; g < kMU; ++g) {
+        km[g] = 0;
+        deg[g] = 0;
+        if (g < ng) {
+            const uint32_t u0 = ub + 64u * g, u = u0 + lane;
+            km[g] = (uint64_t)bits[u0 >> 5] | ((uint64_t)bits[(u0 >> 5) + 1] << 32);
+            if ((km[g] >> lane) & 1u) deg[g] = off[u + 1] - off[u];
+            cnt += popc64(km[g]);
+            edges += deg[g];
+        }
+    }
+    edges = wave_sum_u32(edges);
+    if (lane == 0) {
+        s_wc[wave] = cnt;
+        s_we[wave] = edges;
+    }
+    __syncthreads();
+    uint32_t pos = s_base[0], epos = s_base[1];
+    for (uint32_t w = 0; w < wave; ++w) {
+        pos += s_wc[w];
+        epos += s_we[w];
+    }
+    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
+    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
+#pragma unroll
+    for (uint32_t g = 0; g < kMU; ++g) {
+        if (g < ng) {
+            const uint32_t u = ub + 64u * g + lane;
+            const uint32_t dincl = wave_incl_scan(deg[g]);
+            if ((km[g] >> lane) & 1u) {
+                const uint32_t at = pos + popc_lt(km[g]);
+                nlist[at] = (uint16_t)u;
+                npre[at] = epos + dincl - deg[g];
+            }
+            pos += popc64(km[g]);
+            epos += __shfl(dincl, 63, 64);
+        }
+    }
 }
 
 template <int PROG>
-__global__ __launch_bounds__(kGT, 2) void kb_merge(const Inst* __restrict__ tab,
-                                                   const uint32_t* __restrict__ boff, uint32_t n) {
+__global__ __launch_bounds__(kMT) void kb_merge_part(const Inst* __restrict__ tab,
+                                                     const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    merge_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+    merge_part_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+}
+
+__global__ __launch_bounds__(kMT) void kb_merge_list(const Inst* __restrict__ tab,
+                                                     const uint32_t* __restrict__ boff, uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[i];
+    merge_list_body(I.G, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
 }
 
 // Batched: run status {done, iterations} per run, and the iteration limit of
@@ -793,9 +930,7 @@ static hipError_t prep_batch_gather_p(const BatchGrid& B) {
     hipError_t e = hipFuncSetAttribute(
         r ? reinterpret_cast<const void*>(kb_gather<PROG, true>) : reinterpret_cast<const void*>(kb_gather<PROG, false>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes(PROG, B.q_max, r));
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kb_merge<PROG>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes(PROG, B.q_max, false));
+    return e;
 }
 
 template <int PROG>
@@ -812,9 +947,10 @@ static hipError_t launch_batch_gather_p(const BatchGrid& B, hipStream_t st) {
 
 template <int PROG>
 static hipError_t launch_batch_merge_p(const BatchGrid& B, hipStream_t st) {
-    if (B.nb_merge)
-        hipLaunchKernelGGL(kb_merge<PROG>, dim3(B.nb_merge), dim3(kGT), gather_lds_bytes(PROG, B.q_max, false), st,
-                           B.tab, B.b_merge, B.n);
+    if (B.nb_merge) {
+        hipLaunchKernelGGL(kb_merge_part<PROG>, dim3(B.nb_merge), dim3(kMT), 0, st, B.tab, B.b_merge, B.n);
+        hipLaunchKernelGGL(kb_merge_list, dim3(B.nb_merge), dim3(kMT), 0, st, B.tab, B.b_merge, B.n);
+    }
     return hipGetLastError();
 }
 

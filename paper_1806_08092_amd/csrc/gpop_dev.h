@@ -27,6 +27,8 @@ constexpr uint32_t kIdentMin = 0xFFFFFFFFu;  // min-combine identity ("no messag
 constexpr uint32_t kIdentSum = 0x80000000u;  // sum-combine identity: -0.0f bits
 constexpr uint32_t kLogCap = 4096;        // per-iteration stats records
 constexpr uint32_t kScWaves = 4;          // independent source-centric task waves per workgroup
+constexpr uint32_t kMergeSpan = 2048;     // vertices per workgroup of a split-partition merge
+constexpr uint32_t kMaxMergeChunks = 16;  // q / kMergeSpan at the largest partition (2^15)
 constexpr double kFix = 1152921504606846976.0;      // 2^60: fixed-point scale of sums
 constexpr double kInvFix = 8.673617379884035e-19;   // 2^-60
 
@@ -41,6 +43,8 @@ enum Prog : int {
 
 __host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || prog == P_PPR; }
 __host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP; }
+// Workgroups that merge one split partition of q vertices.
+__host__ __device__ constexpr uint32_t merge_chunks(uint32_t q) { return q > kMergeSpan ? q / kMergeSpan : 1u; }
 
 struct Ctrl {
     uint32_t done;        // bit 0: frontier became empty; bit 1: paused at max_it
@@ -91,6 +95,7 @@ struct Dev {
     uint4* gsplit;            // [n_gsplit] {q, first task, nt, first slot}
     uint32_t* gpart;          // partial results of split gathers, q (u32) or 2q (u64) words per slot
     uint32_t* gflag;          // [slots] a split task wrote its partial
+    uint4* mtot;              // [k*kMaxMergeChunks] per merge chunk {kept, kept out-edges, dangling sum (f64 bits)}
     // per iteration
     uint32_t* data;           // [M] message values
     uint16_t* sc_ids;         // [E_pad]
