@@ -56,6 +56,7 @@ struct Runner {
     hipGraphExec_t exec = nullptr;
     int prog = -1;
     bool prof = false;
+    bool learned = false;
     uint32_t chunk = 4;
     std::vector<hipEvent_t> ev;  // 2 * GPOP_KERNEL_COUNT per recorded iteration
 
@@ -165,7 +166,8 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->sc_w = (uint8_t*)take(E_pad);
     G->sc_chunk = (uint32_t*)take(nch * 4);
     G->sc_cnt = (uint2*)take(kk * 8);
-    G->sc_tot = (uint2*)take(k * 8);
+    G->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
+    G->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
     G->sc_t0 = (uint32_t*)take((k + 1) * 4);
     G->sc_tc = (uint2*)take(nsct * k * 8);
     G->gat_ids = (uint32_t*)take(ngt * 4);
@@ -317,6 +319,7 @@ int runner_record(Runner& R, const BatchGrid& B, int prog, bool prof, uint32_t* 
     HIP_OR_RETURN(hipGraphInstantiate(&R.exec, gr, nullptr, nullptr, 0), "instantiate iterations");
     R.prog = prog;
     R.prof = prof;
+    R.learned = B.learned;
     return GPOP_OK;
 }
 
@@ -326,7 +329,7 @@ int runner_record(Runner& R, const BatchGrid& B, int prog, bool prof, uint32_t* 
 template <class F>
 int runner_run(Runner& R, const BatchGrid& B, int prog, bool prof, bool eager, uint32_t max_iter,
                uint32_t* d_status, hipStream_t st, double* prof_ms, uint64_t* prof_n, F&& finished) {
-    if (!eager && (R.prog != prog || R.prof != prof || !R.exec)) {
+    if (!eager && (R.prog != prog || R.prof != prof || R.learned != B.learned || !R.exec)) {
         int rc = runner_record(R, B, prog, prof, d_status);
         if (rc) return rc;
     }
@@ -549,7 +552,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
 
     // the graph's own run as a batch of one: per kernel, blocks [0, n)
     const uint32_t nb[6] = {(G.k + 63) / 64, std::min<uint32_t>((G.max_sctask + kScWaves - 1) / kScWaves, 2048u),
-                            G.k, G.n_pctask, G.n_gtask, G.n_gsplit * merge_chunks(G.q)};
+                            scan_grid(G.k), G.n_pctask, G.n_gtask, G.n_gsplit * merge_chunks(G.q)};
     uint32_t hb[12];
     for (int j = 0; j < 6; ++j) {
         hb[2 * j] = 0;
@@ -587,6 +590,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     B.k_max = G.k;
     B.q_max = G.q;
     B.rounds = G.combine == GPOP_COMBINE_ROUNDS;
+    B.learned = false;
     B.view = &g->G;
     for (int i = 0; i < 2; ++i) {
         g->probe_grid[i] = B;
@@ -736,6 +740,7 @@ int gpop_set_selector(gpop_graph* g, gpop_selector kind, float bw_ratio, uint32_
     g->P.s_i = s_i;
     g->P.s_v = s_v;
     if (kind == GPOP_SEL_LEARNED && !d_mlp) g->P.selector = GPOP_SEL_ANALYTICAL;
+    g->grid.learned = g->P.selector == GPOP_SEL_LEARNED;
     if (g->prog >= 0) return upload_tab(g, nullptr);  // the run reads its parameters on the device
     return GPOP_OK;
 }
@@ -1006,7 +1011,8 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     D->sc_w = S.w ? (uint8_t*)take(E_pad) : nullptr;
     D->sc_chunk = (uint32_t*)take(E_pad / kChunk * 4);
     D->sc_cnt = (uint2*)take(kk * 8);
-    D->sc_tot = (uint2*)take(k * 8);
+    D->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
+    D->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
     D->sc_t0 = (uint32_t*)take((k + 1) * 4);
     D->sc_tc = (uint2*)take((uint64_t)S.max_sctask * k * 8);
     D->gat_ids = (uint32_t*)take(ngt * 4);
@@ -1091,7 +1097,7 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
         I.state = nullptr;
         const Dev& S = g->G;
         const uint32_t nb[6] = {(S.k + 63) / 64, std::min<uint32_t>((S.max_sctask + kScWaves - 1) / kScWaves, sc_cap),
-                                S.k, S.n_pctask, S.n_gtask, S.n_gsplit * merge_chunks(S.q)};
+                                scan_grid(S.k), S.n_pctask, S.n_gtask, S.n_gsplit * merge_chunks(S.q)};
         for (int j = 0; j < 6; ++j) hb[(size_t)j * (n + 1) + i + 1] = hb[(size_t)j * (n + 1) + i] + nb[j];
         k_max = std::max(k_max, S.k);
         q_max = std::max(q_max, S.q);
@@ -1121,6 +1127,8 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
     B.k_max = k_max;
     B.q_max = q_max;
     B.rounds = graphs[0]->G.combine == GPOP_COMBINE_ROUNDS;
+    B.learned = false;
+    for (uint32_t i = 0; i < n; ++i) B.learned = B.learned || graphs[i]->P.selector == GPOP_SEL_LEARNED;
     for (uint32_t i = 1; i < n; ++i)
         if (graphs[i]->G.combine != graphs[0]->G.combine) {
             delete b;

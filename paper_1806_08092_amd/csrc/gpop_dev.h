@@ -43,6 +43,15 @@ enum Prog : int {
 
 __host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || prog == P_PPR; }
 __host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP; }
+// A partition with more source-centric tasks than this has its offset scan
+// split into one unit per block of 64 destination partitions.
+constexpr uint32_t kScanRows = 64;
+__host__ __device__ constexpr uint32_t col_blocks(uint32_t k) { return (k + 63u) / 64u; }
+// Workgroups of the source-centric offset scan (they stride over the units).
+__host__ __device__ constexpr uint32_t scan_grid(uint32_t k) {
+    const uint32_t units = k * col_blocks(k), cap = k > 1024u ? k : 1024u;
+    return units < cap ? units : cap;
+}
 // Workgroups that merge one split partition of q vertices.
 __host__ __device__ constexpr uint32_t merge_chunks(uint32_t q) { return q > kMergeSpan ? q / kMergeSpan : 1u; }
 
@@ -60,7 +69,8 @@ struct Ctrl {
     uint32_t pos;         // iterations run so far (index of the next plan)
     uint32_t max_it;      // a plan at this index pauses the run (done bit 2)
     uint32_t run_start;   // pos when the current run began
-    uint32_t pad[49];
+    uint32_t n_scunits;   // source-centric scan units of the current iteration
+    uint32_t pad[48];
 };
 
 // Everything the kernels read or write, by value in each launch.
@@ -102,7 +112,8 @@ struct Dev {
     uint8_t* sc_w;            // [E_pad]
     uint32_t* sc_chunk;       // [E_pad/256]
     uint2* sc_cnt;            // [k*k] column-major {mcnt, icnt} of SC bins
-    uint2* sc_tot;            // [k] SC totals {msgs, ids} per partition
+    uint2* sc_tot;            // [k*col_blocks(k)] SC totals {msgs, ids} per (partition, scan unit)
+    uint32_t* sc_units;       // [k*col_blocks(k)] scan units: p | column block << 16 | bit 31 whole row
     uint32_t* sc_t0;          // [k+1] exclusive prefix of SC tasks per partition
     uint2* sc_tc;             // [max_sctask*k] per-(task, q) counts, then bases
     uint32_t* gat_ids;        // [n_gtask] ids combined per gather task

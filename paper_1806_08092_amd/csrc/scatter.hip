@@ -218,14 +218,13 @@ __global__ __launch_bounds__(kScWaves * 64) void kb_sc_pass(const Inst* __restri
 // Scan pass: per source partition p and destination q, exclusive scan of the
 // task counts over the tasks of p (in place), giving each task its base in
 // bin[p][q]; the totals are the bin's message and id counts this iteration.
-// 16 strips of tasks x 64 destinations per round; strip sums are scanned in
-// LDS, then each strip rewrites its counts as bases.
+// One call scans destinations [qa, qb): 16 strips of tasks x 64 destinations
+// per round; strip sums are scanned in LDS, then each strip rewrites its
+// counts as bases. Loads go in batches of 8 so that a strip of a partition
+// with many tasks keeps several in flight.
 template <bool BUILD>
-__device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p) {
-    if constexpr (!BUILD) {
-        if (G.ctrl->done) return;
-        if (G.mode[p] != GPOP_MODE_SC) return;
-    }
+__device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t qa, uint32_t qb,
+                                             uint32_t tot_slot) {
     const uint32_t k = G.k;
     const uint32_t* __restrict__ t0 = BUILD ? G.bld_t0 : G.sc_t0;
     const uint32_t tb = t0[p], n = t0[p + 1] - tb;
@@ -235,15 +234,29 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p) {
     const uint32_t per = (n + 15u) / 16u;
     const uint32_t a = min(strip * per, n), b = min(a + per, n);
     uint64_t my_tm = 0, my_ti = 0;
-    for (uint32_t q0 = 0; q0 < k; q0 += 64) {
+    for (uint32_t q0 = qa; q0 < qb; q0 += 64) {
         const uint32_t q = q0 + ql;
+        const bool qin = q < qb;
+        uint2* __restrict__ col = G.sc_tc + (size_t)tb * k + q;
         uint32_t sm = 0, si = 0;
-        if (q < k)
-            for (uint32_t t = a; t < b; ++t) {
-                const uint2 c = G.sc_tc[(size_t)(tb + t) * k + q];
+        if (qin) {
+            uint32_t t = a;
+            for (; t + 8u <= b; t += 8u) {
+                uint2 c[8];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) c[j] = col[(size_t)(t + j) * k];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) {
+                    sm += c[j].x;
+                    si += c[j].y;
+                }
+            }
+            for (; t < b; ++t) {
+                const uint2 c = col[(size_t)t * k];
                 sm += c.x;
                 si += c.y;
             }
+        }
         s_m[strip][ql] = sm;
         s_i[strip][ql] = si;
         __syncthreads();
@@ -257,11 +270,22 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p) {
             ti += s_i[w][ql];
         }
         __syncthreads();
-        if (q < k) {
-            for (uint32_t t = a; t < b; ++t) {
-                uint2* c = G.sc_tc + (size_t)(tb + t) * k + q;
-                const uint2 x = *c;
-                *c = make_uint2(rm, ri);
+        if (qin) {
+            uint32_t t = a;
+            for (; t + 8u <= b; t += 8u) {
+                uint2 x[8];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) x[j] = col[(size_t)(t + j) * k];
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) {
+                    col[(size_t)(t + j) * k] = make_uint2(rm, ri);
+                    rm += x[j].x;
+                    ri += x[j].y;
+                }
+            }
+            for (; t < b; ++t) {
+                const uint2 x = col[(size_t)t * k];
+                col[(size_t)t * k] = make_uint2(rm, ri);
                 rm += x.x;
                 ri += x.y;
             }
@@ -291,20 +315,34 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p) {
                 x += s_tot[0][w];
                 y += s_tot[1][w];
             }
-            G.sc_tot[p] = make_uint2((uint32_t)x, (uint32_t)y);
+            G.sc_tot[tot_slot] = make_uint2((uint32_t)x, (uint32_t)y);
         }
+        __syncthreads();  // s_tot and the strip arrays are reused by the next unit
     }
 }
 
 template <bool BUILD>
 __global__ __launch_bounds__(1024) void k_sc_scan(Dev G) {
-    sc_scan_body<BUILD>(G, blockIdx.x);
+    sc_scan_body<BUILD>(G, blockIdx.x, 0, G.k, 0);
 }
 
+// The plan lists the scan units of the iteration (source-centric partitions,
+// those with many tasks once per block of 64 destinations); the workgroups
+// stride over them.
 __global__ __launch_bounds__(1024) void kb_sc_scan(const Inst* __restrict__ tab,
                                                    const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
-    sc_scan_body<false>(tab[i].G, blockIdx.x - boff[i]);
+    const Dev& G = tab[i].G;
+    if (G.ctrl->done) return;
+    const uint32_t nu = G.ctrl->n_scunits, nblk = boff[i + 1] - boff[i];
+    const uint32_t ncb = col_blocks(G.k);
+    for (uint32_t u = blockIdx.x - boff[i]; u < nu; u += nblk) {
+        const uint32_t e = G.sc_units[u];
+        const uint32_t p = e & 0xFFFFu, cb = (e >> 16) & 0x7FFFu;
+        const bool whole = (e >> 31) != 0u;
+        const uint32_t qa = whole ? 0u : cb * 64u, qb = whole ? G.k : min(G.k, qa + 64u);
+        sc_scan_body<false>(G, p, qa, qb, p * ncb + cb);
+    }
 }
 
 size_t sc_lds_bytes(uint32_t k) { return (size_t)kScWaves * 2 * k * 4; }
@@ -409,11 +447,15 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
     __shared__ uint64_t red[6][16];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     uint64_t v[6] = {0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged
+    const uint32_t ncb = col_blocks(G.k);
     for (uint32_t p = tid; p < G.k; p += blockDim.x) {
         if (G.mode[p] == GPOP_MODE_SC) {
-            const uint2 t = G.sc_tot[p];
-            v[0] += t.x;
-            v[1] += t.y;
+            const uint32_t nu = G.sc_t0[p + 1] - G.sc_t0[p] > kScanRows ? ncb : 1u;
+            for (uint32_t j = 0; j < nu; ++j) {
+                const uint2 t = G.sc_tot[(size_t)p * ncb + j];
+                v[0] += t.x;
+                v[1] += t.y;
+            }
         }
     }
     for (uint32_t t = tid; t < G.n_gtask + G.n_gsplit; t += blockDim.x) {
@@ -472,9 +514,13 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0, sva = 0, sea = 0, pcv = 0;
     double dang = 0.0;
     uint32_t tcarry = 0;  // source-centric tasks of the partitions before this block
+    uint32_t ucarry = 0;  // scan units of the partitions before this block
+    __shared__ uint32_t s_u[16];
+    const uint32_t ncb = col_blocks(G.k);
     for (uint32_t p0 = 0; p0 < G.k; p0 += 1024) {
         const uint32_t p = p0 + tid;
         uint32_t ntask = 0;
+        bool in_sc = false;
         if (p < G.k) {
             const uint32_t Va = G.fVa[cur][p], Ea = G.fEa[cur][p];
             uint8_t md = GPOP_MODE_NONE;
@@ -497,20 +543,38 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 sva += Va;
                 sea += Ea;
                 ntask = (Ea + (1u << G.sc_shift) - 1u) >> G.sc_shift;
+                in_sc = true;
             }
             dang += G.dpart[cur][p];
         }
-        // exclusive scan of the task counts in partition order
+        // exclusive scans of the task and scan-unit counts in partition order
+        // (a partition without active out-edges still gets a unit: the scan
+        // writes its zero bin counts)
+        const uint32_t nunit = !in_sc ? 0u : (ntask > kScanRows ? ncb : 1u);
         const uint32_t incl = wave_incl_scan(ntask);
-        if (lane == 63) s_w[wave] = incl;
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
-        for (uint32_t w = 0; w < 16; ++w) {
-            if (w < wave) before += s_w[w];
-            tot += s_w[w];
+        const uint32_t uincl = wave_incl_scan(nunit);
+        if (lane == 63) {
+            s_w[wave] = incl;
+            s_u[wave] = uincl;
         }
-        if (p < G.k) G.sc_t0[p] = tcarry + before + incl - ntask;
+        __syncthreads();
+        uint32_t before = 0, tot = 0, ubefore = 0, utot = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            if (w < wave) {
+                before += s_w[w];
+                ubefore += s_u[w];
+            }
+            tot += s_w[w];
+            utot += s_u[w];
+        }
+        if (p < G.k) {
+            G.sc_t0[p] = tcarry + before + incl - ntask;
+            const uint32_t u0 = ucarry + ubefore + uincl - nunit;
+            for (uint32_t j = 0; j < nunit; ++j)
+                G.sc_units[u0 + j] = p | (j << 16) | (nunit == 1u ? 0x80000000u : 0u);
+        }
         tcarry += tot;
+        ucarry += utot;
         __syncthreads();
     }
     va = wave_sum_u64(va);
@@ -545,6 +609,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         }
         G.sc_t0[G.k] = tcarry;
         C->n_sctask = tcarry;
+        C->n_scunits = ucarry;
         C->frontier = t[0];
         C->dangling = d;
         if (t[0] == 0) {

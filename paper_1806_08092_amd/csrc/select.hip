@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64) void k_features(Dev G, Params P, float* __restr
 }
 
 hipError_t launch_batch_select(const BatchGrid& B, hipStream_t st) {
-    if (B.nb_select == 0) return hipSuccess;
+    if (B.nb_select == 0 || !B.learned) return hipSuccess;
     hipLaunchKernelGGL(kb_select, dim3(B.nb_select), dim3(64), 0, st, B.tab, B.b_select, B.n);
     return hipGetLastError();
 }

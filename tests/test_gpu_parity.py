@@ -285,6 +285,40 @@ def test_split_results_bitwise_equal_unsplit():
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
+@pytest.mark.parametrize("sel", ["analytical", "sc"])
+def test_split_scan_units(sel):
+    """128 partitions (two blocks of 64 destinations) and 64-edge
+    source-centric tasks, so the hub partitions have hundreds of tasks and
+    their offset scans are split into one unit per destination block; results
+    must match the oracle, and PageRank must be bitwise equal to the run with
+    default task sizes."""
+    g = gg.rmat_graph(15, 16, 45, weights_seed=46)
+    sym = gg.rmat_graph(15, 16, 47, symmetric=True)
+    G, _ = make_graph(g, 8, sc_task_log2=6)
+    Gs, _ = make_graph(sym, 8, sc_task_log2=6)
+    assert G.k == 128
+    for root in roots_of(g, 2):
+        got, _ = run_program(G, "bfs", g.n, root=root, selector=sel)
+        assert np.array_equal(got, oracle.bfs_levels(g, root))
+        got, _ = run_program(G, "sssp", g.n, root=root, selector=sel)
+        assert np.array_equal(got, oracle.sssp(g, root))
+        got, _ = run_program(G, "ppr", g.n, root=root, selector=sel, max_iter=20)
+        assert pr_ok(got, oracle.ppr(g, root, 0.15, 20))
+    got, _ = run_program(Gs, "cc", sym.n, selector=sel)
+    assert np.array_equal(got, oracle.cc_minlabel(sym))
+    a, _ = run_program(G, "pagerank", g.n, selector=sel, max_iter=10)
+    assert pr_ok(a, oracle.pagerank(g, 0.85, 10))
+    G1, _ = make_graph(g, 8)
+    b, _ = run_program(G1, "pagerank", g.n, selector=sel, max_iter=10)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    # every active out-edge of a source-centric partition is one id: the
+    # per-unit totals of a split scan must add up to it
+    run_program(G, "bfs", g.n, root=roots_of(g, 1)[0], selector=sel)
+    st = G.iter_stats()
+    assert sum(r["sc_ids"] for r in st) > 0
+    assert all(r["sc_ids"] == r["sc_active_edges"] for r in st)
+
+
 def _hub_graph():
     """Many small messages into a few hubs: every vertex links to hubs 0, 1
     and 2 (hub 0 twice), plus a ring; 6000 vertices in 2^8-vertex
