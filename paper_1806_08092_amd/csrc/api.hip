@@ -101,10 +101,11 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Task sizes of a graph: active out-edges per source-centric task (at least
-// 1024 and at least 4k, so the per-task count row stays small next to the
-// task's edges) and ids per gather task (about one task per CU for a dense
-// iteration; heavier partitions are split over several).
+// Task sizes of a graph: the largest source-centric task in work units (at
+// least 1024 and at least 4k, so the per-task count row stays small next to
+// the task; lighter iterations use smaller tasks) and ids per gather task
+// (about one task per CU for a dense iteration; heavier partitions are split
+// over several).
 struct Sizes {
     uint32_t s, sc_shift;
     uint64_t q, k, T;
@@ -123,7 +124,13 @@ Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
     return z;
 }
 
-uint64_t max_sctask_for(uint64_t E, const Sizes& z) { return (E >> z.sc_shift) + z.k + 1; }
+// Source-centric tasks of one iteration: a task holds at most 2^sc_shift work
+// units (an active vertex is one unit, each of its out-edges one more); the
+// plan takes smaller tasks when the iteration's units are few, never more
+// than 2 x sc_task_target of them (plus one partial task per partition).
+uint64_t max_sctask_for(uint32_t V, uint64_t E, const Sizes& z) {
+    return std::max<uint64_t>((E + V) >> z.sc_shift, 2ull * sc_task_target((uint32_t)z.k)) + z.k + 1;
+}
 
 uint64_t max_gtask_for(uint64_t E, const Sizes& z) {
     return (E + 512ull * z.k * z.k) / z.T + z.k + 1;
@@ -143,7 +150,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     const uint64_t E_pad = align256(E ? E : 1);
     const uint64_t nch = E_pad / kChunk;
     const uint64_t ntask = E / kPcTask + k + 1;
-    const uint64_t nsct = max_sctask_for(E, z);
+    const uint64_t nsct = max_sctask_for(V, E, z);
     const uint64_t ngt = max_gtask_for(E, z);
     G->part_E = (uint32_t*)take(k * 4);
     G->part_M = (uint32_t*)take(k * 4);
@@ -168,6 +175,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->sc_cnt = (uint2*)take(kk * 8);
     G->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
     G->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
+    G->sc_sh = (uint8_t*)take(k);
     G->sc_t0 = (uint32_t*)take((k + 1) * 4);
     G->sc_tc = (uint2*)take(nsct * k * 8);
     G->gat_ids = (uint32_t*)take(ngt * 4);
@@ -428,7 +436,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     hipStream_t st = (hipStream_t)stream;
 
     G.sc_shift = z.sc_shift;
-    G.max_sctask = (uint32_t)max_sctask_for(G.E, z);
+    G.max_sctask = (uint32_t)max_sctask_for(G.V, G.E, z);
     if (sc_lds_bytes(G.k) > (size_t)max_lds_per_block() ||
         gather_lds_bytes(P_BFS, G.q, false) + 2048 > (size_t)max_lds_per_block())
         return fail(GPOP_ENOTSUP, "partition of %u vertices does not fit the LDS", G.q);
@@ -1013,6 +1021,7 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     D->sc_cnt = (uint2*)take(kk * 8);
     D->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
     D->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
+    D->sc_sh = (uint8_t*)take(k);
     D->sc_t0 = (uint32_t*)take((k + 1) * 4);
     D->sc_tc = (uint2*)take((uint64_t)S.max_sctask * k * 8);
     D->gat_ids = (uint32_t*)take(ngt * 4);

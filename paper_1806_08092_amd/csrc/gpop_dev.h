@@ -43,6 +43,22 @@ enum Prog : int {
 
 __host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || prog == P_PPR; }
 __host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP; }
+// Source-centric tasks per iteration the plan aims for (about half the waves
+// the chip holds); bounded so that a count matrix of 2 x target x k words
+// stays at 64 MB at most.
+__host__ __device__ constexpr uint32_t sc_task_target(uint32_t k) {
+    return (1u << 22) / (k ? k : 1u) < 4096u ? (1u << 22) / (k ? k : 1u) : 4096u;
+}
+// Smallest source-centric task (log2 work units): 64, and at least k/4 so the
+// per-task count row of k destinations stays small next to the task.
+__host__ __device__ constexpr uint32_t sc_shift_floor(uint32_t k) {
+    uint32_t l = 0;
+    while ((2u << l) <= k) ++l;  // floor(log2 k)
+    return l > 8u ? l - 2u : 6u;
+}
+// Source-centric tasks of one partition at most (a partition with more work
+// takes larger tasks, so its offset scan stays short).
+constexpr uint32_t kMaxPartTasks = 1024;
 // A partition with more source-centric tasks than this has its offset scan
 // split into one unit per block of 64 destination partitions.
 constexpr uint32_t kScanRows = 64;
@@ -114,6 +130,7 @@ struct Dev {
     uint2* sc_cnt;            // [k*k] column-major {mcnt, icnt} of SC bins
     uint2* sc_tot;            // [k*col_blocks(k)] SC totals {msgs, ids} per (partition, scan unit)
     uint32_t* sc_units;       // [k*col_blocks(k)] scan units: p | column block << 16 | bit 31 whole row
+    uint8_t* sc_sh;           // [k] log2 work units per source-centric task of each partition
     uint32_t* sc_t0;          // [k+1] exclusive prefix of SC tasks per partition
     uint2* sc_tc;             // [max_sctask*k] per-(task, q) counts, then bases
     uint32_t* gat_ids;        // [n_gtask] ids combined per gather task

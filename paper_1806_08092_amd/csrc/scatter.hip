@@ -14,10 +14,14 @@ namespace gpop {
 // messages to q land at consecutive insertion points (Sec. 3.1.2,
 // source-centric mode).
 //
-// GPU form: the active out-edges of partition p, taken in (vertex, edge)
-// order, are cut into tasks of C consecutive edges (a task may start or end
-// inside a vertex's row, so hubs spread over many tasks). One wave owns one
-// task. The insertion points are exclusive prefix sums over that order:
+// GPU form: the active vertices of partition p and their out-edges, taken in
+// (vertex, edge) order with one work unit per vertex and one per edge, are
+// cut into tasks of C consecutive units (a task may start or end inside a
+// vertex's row, so hubs spread over many tasks). C is chosen per iteration:
+// the configured size when the source-centric work is large, smaller (down
+// to 64 units) when it is light, so that there are enough tasks to fill the
+// chip. One wave owns one task. The insertion points are exclusive prefix
+// sums over that order:
 //   count pass  - each task counts ids and message starts per destination q;
 //   scan pass   - per (p, q), an exclusive scan over the tasks of p gives each
 //                 task its base in bin[p][q] (and the bin's totals);
@@ -33,18 +37,34 @@ namespace gpop {
 // partition-centric scatter reuses every iteration (Algorithm 3).
 // ---------------------------------------------------------------------------
 
-// Largest p with t0[p] <= t (t0 is a non-decreasing task prefix over k
-// partitions, t < t0[k]); lands on a partition that owns task t.
-__device__ __forceinline__ uint32_t task_owner(const uint32_t* t0, uint32_t k, uint32_t t) {
-    uint32_t lo = 0, hi = k;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (t0[mid] <= t) lo = mid; else hi = mid;
+// Largest i in [0, n) with key(i) <= x, for a non-decreasing key with
+// key(0) <= x. One wave searches 64 ways at once: a round is one load per
+// lane, and ceil(log64 n) rounds suffice (instead of log2 n dependent loads).
+template <class F>
+__device__ __forceinline__ uint32_t wave_search(uint32_t n, uint32_t x, F key) {
+    const uint32_t lane = lane_id();
+    uint32_t lo = 0;
+    while (n > 1) {
+        const uint32_t stride = (n + 63u) >> 6;
+        const uint32_t o = lane * stride;
+        const bool le = o < n && key(lo + o) <= x;
+        const uint32_t j = popc64(ballot(le)) - 1u;  // lane 0 always holds
+        lo += j * stride;
+        n = min(stride, n - j * stride);
     }
     return lo;
 }
 
-// Processes active-edge range [f0, f1) of partition p with one wave.
+// The partition that owns task t: largest p with t0[p] <= t (t0 is a
+// non-decreasing task prefix over k partitions, t < t0[k]).
+__device__ __forceinline__ uint32_t task_owner(const uint32_t* t0, uint32_t k, uint32_t t) {
+    return wave_search(k, t, [&](uint32_t i) { return t0[i]; });
+}
+
+// Processes the work-unit range [f0, f1) of partition p with one wave. The
+// active vertices of p, in ascending order, are laid end to end as one unit
+// for the vertex followed by one per out-edge (BUILD: edges only), so a task
+// bounds both the edges and the vertices a wave walks.
 // WRITE = false: adds per-destination counts to (ci, cm).
 // WRITE = true : (ci, cm) hold the task's bases; writes the bins.
 template <int PROG, bool BUILD, bool WRITE>
@@ -60,15 +80,12 @@ __device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __res
     const uint32_t* __restrict__ rmoff = G.bin_moff + (size_t)p * k;
     const uint32_t* __restrict__ rioff = G.bin_ioff + (size_t)p * k;
     const uint32_t base_off = off[vbase];
+    constexpr uint32_t hdr = BUILD ? 0u : 1u;  // units of a vertex before its edges
     auto pre = [&](uint32_t i) -> uint32_t {
-        return BUILD ? off[vbase + i] - base_off : fpre[i];
+        return BUILD ? off[vbase + i] - base_off : fpre[i] + i;
     };
-    // first active vertex whose edges reach f0
-    uint32_t lo = 0, hi = nact;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (pre(mid) <= f0) lo = mid; else hi = mid;
-    }
+    // first active vertex whose units reach f0
+    const uint32_t lo = wave_search(nact, f0, pre);
     for (uint32_t i0 = lo; i0 < nact; i0 += 64) {
         const uint32_t ii = i0 + lane;
         const bool vv = ii < nact;
@@ -77,10 +94,10 @@ __device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __res
         const uint32_t rs = vv ? off[v] : 0u;
         const uint32_t deg = vv ? off[v + 1] - rs : 0u;
         const uint32_t pr = vv ? pre(ii) : 0u;
-        const uint32_t clo = max(pr, f0);
-        const uint32_t chi = min(pr + deg, f1);
+        const uint32_t clo = max(pr + hdr, f0);
+        const uint32_t chi = min(pr + hdr + deg, f1);
         const uint32_t cdeg = (vv && chi > clo) ? chi - clo : 0u;
-        const uint32_t cst = rs + (clo - pr);
+        const uint32_t cst = rs + (clo - pr - hdr);
         uint32_t val = vl;
         if constexpr (WRITE && !BUILD) {
             if (cdeg) val = scatter_value<PROG>(G, state, v);
@@ -179,12 +196,14 @@ __device__ __forceinline__ void sc_pass_body(const Dev& G, const Params& P,
         }
         const uint32_t p = task_owner(t0, k, t);
         const uint32_t jt = t - t0[p];
+        const uint32_t sh = BUILD ? G.sc_shift : G.sc_sh[p];
         const uint32_t vbase = p << G.s;
         const uint32_t nv = min(G.q, G.V - vbase);
         const uint32_t Ea = BUILD ? G.part_E[p] : G.fEa[cur][p];
         const uint32_t nact = BUILD ? nv : G.fVa[cur][p];
-        const uint32_t f0 = jt << G.sc_shift;
-        const uint32_t f1 = min(f0 + (1u << G.sc_shift), Ea);
+        // the task's range of work units (BUILD: edges only)
+        const uint32_t f0 = jt << sh;
+        const uint32_t f1 = min(f0 + (1u << sh), BUILD ? Ea : Ea + nact);
         sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, G.flist[cur] + vbase,
                                          G.fpre[cur] + vbase, ci, cm);
         if constexpr (!WRITE) {
@@ -234,7 +253,33 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
     const uint32_t per = (n + 15u) / 16u;
     const uint32_t a = min(strip * per, n), b = min(a + per, n);
     uint64_t my_tm = 0, my_ti = 0;
-    for (uint32_t q0 = qa; q0 < qb; q0 += 64) {
+    // few tasks: one thread per destination walks all of them (no strips)
+    const bool serial = !BUILD && n <= kScanRows;
+    for (uint32_t q = qa + tid; serial && q < qb; q += blockDim.x) {
+        uint2* __restrict__ col = G.sc_tc + (size_t)tb * k + q;
+        uint32_t rm = 0, ri = 0, t = 0;
+        for (; t + 8u <= n; t += 8u) {
+            uint2 x[8];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) x[j] = col[(size_t)(t + j) * k];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) {
+                col[(size_t)(t + j) * k] = make_uint2(rm, ri);
+                rm += x[j].x;
+                ri += x[j].y;
+            }
+        }
+        for (; t < n; ++t) {
+            const uint2 x = col[(size_t)t * k];
+            col[(size_t)t * k] = make_uint2(rm, ri);
+            rm += x.x;
+            ri += x.y;
+        }
+        G.sc_cnt[(size_t)q * k + p] = make_uint2(rm, ri);
+        my_tm += rm;
+        my_ti += ri;
+    }
+    for (uint32_t q0 = qa; !serial && q0 < qb; q0 += 64) {
         const uint32_t q = q0 + ql;
         const bool qin = q < qb;
         uint2* __restrict__ col = G.sc_tc + (size_t)tb * k + q;
@@ -498,6 +543,10 @@ __device__ __forceinline__ void finalize_once(const Dev& G, uint32_t it) {
 
 __global__ __launch_bounds__(1024) void k_finalize(Dev G) { finalize_once(G, G.ctrl->pos); }
 
+// The plan runs as one workgroup of kPlanT threads per run.
+constexpr uint32_t kPlanT = 512;
+constexpr uint32_t kPlanW = kPlanT / 64;
+
 __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_t it) {
     Ctrl* C = G.ctrl;
     if (C->done) return;
@@ -507,20 +556,17 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     }
     const uint32_t cur = it & 1u;
     finalize_once(G, it);
-    __shared__ uint64_t red[9][16];
-    __shared__ double dred[16];
-    __shared__ uint32_t s_w[16];
+    __shared__ uint64_t red[9][kPlanW];
+    __shared__ double dred[kPlanW];
+    __shared__ uint32_t s_w[kPlanW];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0, sva = 0, sea = 0, pcv = 0;
     double dang = 0.0;
-    uint32_t tcarry = 0;  // source-centric tasks of the partitions before this block
-    uint32_t ucarry = 0;  // scan units of the partitions before this block
-    __shared__ uint32_t s_u[16];
-    const uint32_t ncb = col_blocks(G.k);
-    for (uint32_t p0 = 0; p0 < G.k; p0 += 1024) {
+    // pass 1: modes and totals; the source-centric work units (active
+    // vertices + active out-edges) of each partition go to LDS
+    __shared__ uint32_t s_units[4096];  // k <= 4096; 0xFFFFFFFF: not source-centric
+    for (uint32_t p0 = 0; p0 < G.k; p0 += kPlanT) {
         const uint32_t p = p0 + tid;
-        uint32_t ntask = 0;
-        bool in_sc = false;
         if (p < G.k) {
             const uint32_t Va = G.fVa[cur][p], Ea = G.fEa[cur][p];
             uint8_t md = GPOP_MODE_NONE;
@@ -533,6 +579,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             G.mode[p] = md;
             va += Va;
             ea += Ea;
+            uint32_t units = 0xFFFFFFFFu;
             if (md == GPOP_MODE_PC) {
                 ++npc;
                 pcm += G.part_M[p];
@@ -542,12 +589,48 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 ++nsc;
                 sva += Va;
                 sea += Ea;
-                ntask = (Ea + (1u << G.sc_shift) - 1u) >> G.sc_shift;
-                in_sc = true;
+                units = (uint32_t)min<uint64_t>((uint64_t)Va + Ea, 0xFFFFFFFEull);
             }
+            s_units[p] = units;
             dang += G.dpart[cur][p];
         }
-        // exclusive scans of the task and scan-unit counts in partition order
+    }
+    // task size of this iteration: about sc_task_target tasks, between
+    // 2^sc_shift_floor(k) and 2^sc_shift work units (larger for a partition
+    // that would otherwise have more than kMaxPartTasks)
+    __shared__ uint64_t s_sc_units[kPlanW];
+    {
+        const uint64_t w = wave_sum_u64(sva + sea);
+        if (lane == 0) s_sc_units[wave] = w;
+    }
+    __syncthreads();
+    uint32_t sh;
+    {
+        uint64_t tot = 0;
+        for (uint32_t w = 0; w < kPlanW; ++w) tot += s_sc_units[w];
+        const uint32_t hi = G.sc_shift, lo = min(sc_shift_floor(G.k), hi);
+        const uint64_t per = tot / sc_task_target(G.k);
+        uint32_t l = 0;
+        while (l < 40u && (2ull << l) <= per) ++l;  // floor(log2 per) for per >= 1
+        sh = per == 0 ? lo : max(lo, min(hi, l));
+    }
+    // pass 2: tasks and scan units of the source-centric partitions,
+    // exclusive scans in partition order
+    uint32_t tcarry = 0;  // source-centric tasks of the partitions before this block
+    uint32_t ucarry = 0;  // scan units of the partitions before this block
+    __shared__ uint32_t s_u[kPlanW];
+    const uint32_t ncb = col_blocks(G.k);
+    for (uint32_t p0 = 0; p0 < G.k; p0 += kPlanT) {
+        const uint32_t p = p0 + tid;
+        const uint32_t units = p < G.k ? s_units[p] : 0xFFFFFFFFu;
+        const bool in_sc = units != 0xFFFFFFFFu;
+        uint32_t ntask = 0;
+        if (in_sc) {
+            uint32_t shp = sh;  // at most kMaxPartTasks tasks per partition
+            while ((((uint64_t)units + (1ull << shp) - 1ull) >> shp) > kMaxPartTasks) ++shp;
+            ntask = (uint32_t)(((uint64_t)units + (1ull << shp) - 1ull) >> shp);
+            G.sc_sh[p] = (uint8_t)shp;
+        }
         // (a partition without active out-edges still gets a unit: the scan
         // writes its zero bin counts)
         const uint32_t nunit = !in_sc ? 0u : (ntask > kScanRows ? ncb : 1u);
@@ -559,7 +642,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         }
         __syncthreads();
         uint32_t before = 0, tot = 0, ubefore = 0, utot = 0;
-        for (uint32_t w = 0; w < 16; ++w) {
+        for (uint32_t w = 0; w < kPlanW; ++w) {
             if (w < wave) {
                 before += s_w[w];
                 ubefore += s_u[w];
@@ -603,13 +686,17 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     if (tid == 0) {
         uint64_t t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         double d = 0.0;
-        for (int w = 0; w < 16; ++w) {
+        for (uint32_t w = 0; w < kPlanW; ++w) {
             for (int j = 0; j < 9; ++j) t[j] += red[j][w];
             d += dred[w];
         }
         G.sc_t0[G.k] = tcarry;
         C->n_sctask = tcarry;
         C->n_scunits = ucarry;
+        if (tcarry > G.max_sctask) {  // cannot happen (the bound covers every task size): stop
+            C->bug = 1;
+            C->done = 1;
+        }
         C->frontier = t[0];
         C->dangling = d;
         if (t[0] == 0) {
@@ -641,7 +728,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
 
 // One workgroup per run; the iteration index comes from the run's control
 // block.
-__global__ __launch_bounds__(1024) void kb_plan(const Inst* __restrict__ tab) {
+__global__ __launch_bounds__(kPlanT) void kb_plan(const Inst* __restrict__ tab) {
     const Inst& I = tab[blockIdx.x];
     plan_body(I.G, I.P, I.G.ctrl->pos);
 }
@@ -649,7 +736,7 @@ __global__ __launch_bounds__(1024) void kb_plan(const Inst* __restrict__ tab) {
 // A single run's plan with its view as a kernel argument: the compiler may
 // then re-read view fields instead of keeping them all in registers (read
 // from memory they spill); the parameters still come from the run table.
-__global__ __launch_bounds__(1024) void k_plan1(Dev G, const Params* __restrict__ pp) {
+__global__ __launch_bounds__(kPlanT) void k_plan1(Dev G, const Params* __restrict__ pp) {
     const Params P = *pp;
     plan_body(G, P, G.ctrl->pos);
 }
@@ -699,8 +786,8 @@ static hipError_t launch_batch_pc_p(const BatchGrid& B, hipStream_t st) {
 hipError_t prepare_batch_scatter(const BatchGrid& B, int prog) { GPOP_PROG_SWITCH(prep_batch_scatter_p, B) }
 
 hipError_t launch_batch_plan(const BatchGrid& B, hipStream_t st) {
-    if (B.view) hipLaunchKernelGGL(k_plan1, dim3(1), dim3(1024), 0, st, *B.view, &B.tab->P);
-    else hipLaunchKernelGGL(kb_plan, dim3(B.n), dim3(1024), 0, st, B.tab);
+    if (B.view) hipLaunchKernelGGL(k_plan1, dim3(1), dim3(kPlanT), 0, st, *B.view, &B.tab->P);
+    else hipLaunchKernelGGL(kb_plan, dim3(B.n), dim3(kPlanT), 0, st, B.tab);
     return hipGetLastError();
 }
 
