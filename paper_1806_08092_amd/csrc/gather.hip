@@ -57,18 +57,25 @@ struct GatherShared {
     double rd[kGW];
 };
 
+// Programs whose frontier can only come from vertices that received a
+// message: a partition with no incoming message leaves an empty frontier,
+// whatever was active before.
+__host__ __device__ constexpr bool msg_only(int prog) { return !is_sum(prog) && !has_carry(prog); }
+
 // reInit frontier: initFunc on the vertices that were active before scatter.
+// (Min programs start the on-chip copy at the identity, so initFunc reads the
+// stored value.)
 template <int PROG>
-__device__ __forceinline__ void reinit(const Dev& G, const Params& P, uint32_t it, uint32_t cq, uint32_t* st32,
-                       uint8_t* carry) {
+__device__ __forceinline__ void reinit(const Dev& G, const Params& P, const uint32_t* __restrict__ state,
+                                       uint32_t it, uint32_t cq, uint32_t* st32, uint8_t* carry) {
     if constexpr (has_carry(PROG) || is_sum(PROG)) {
         const uint32_t cur = it & 1u;
         const uint32_t vbase = cq << G.s;
-        const uint32_t prevVa = G.fVa[cur][cq];
-        const uint16_t* __restrict__ prev = G.flist[cur] + vbase;
+        const uint32_t prevVa = gptr(G.fVa[cur])[cq];
+        const uint16_t* __restrict__ prev = gptr(G.flist[cur]) + vbase;
         for (uint32_t i = threadIdx.x; i < prevVa; i += kGT) {
             const uint32_t u = prev[i];
-            if constexpr (PROG == P_CARRY) carry[u] = (it + 1u - st32[u]) < P.persist;
+            if constexpr (PROG == P_CARRY) carry[u] = (it + 1u - state[vbase + u]) < P.persist;
             else reinterpret_cast<unsigned long long*>(st32)[u] |= kCarried;  // value restarts at 0, stays active
         }
     }
@@ -94,8 +101,8 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
     const uint32_t vbase = cq << G.s, Q = G.q;
     const uint32_t nv = min(Q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    const double dang = SUM ? G.ctrl->dangling : 0.0;
-    const uint32_t* __restrict__ off = G.off;
+    const double dang = SUM ? gptr(G.ctrl)->dangling : 0.0;
+    const uint32_t* __restrict__ off = gptr(G.off);
     const uint32_t per = ((Q / kGW) + 63u) & ~63u;  // vertices per wave, multiple of 64
     const uint32_t wb = wave * per;
     uint32_t cnt = 0, edges = 0;
@@ -107,10 +114,13 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
         if (u < nv) {
             const uint32_t v = vbase + u;
             if constexpr (!SUM) {
-                const bool hit = st32[u] < state[v];
+                // the on-chip copy holds the least message (identity: none)
+                const uint32_t m = st32[u];
+                bool hit = false;
+                if (m != kIdentMin) hit = m < state[v];
                 keep = hit;
                 if constexpr (has_carry(PROG)) keep = keep || carry[u];
-                if (hit) state[v] = st32[u];
+                if (hit) state[v] = m;
             } else {
                 const unsigned long long a = acc[u];
                 if (a != 0ull) {  // received an amount, or was active before scatter
@@ -153,26 +163,29 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
         tot += sh.wc[w];
         etot += sh.ws[w];
     }
-    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
-    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
-    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
-    for (uint32_t u0 = wb; u0 < wb + per && u0 < Q; u0 += 64) {
+    uint16_t* __restrict__ nlist = gptr(G.flist[nxt]) + vbase;
+    uint32_t* __restrict__ npre = gptr(G.fpre[nxt]) + vbase;
+    uint32_t* __restrict__ nbits = gptr(G.fbits[nxt]) + (vbase >> 5);
+    // the wave's bitmap words, one per lane
+    const uint32_t wend = min(wb + per, Q);
+    for (uint32_t w = (wb >> 5) + lane; w < (wend >> 5); w += 64) {
+        const uint64_t km = kscratch[w >> 1];
+        nbits[w] = (w & 1u) ? (uint32_t)(km >> 32) : (uint32_t)km;
+    }
+    for (uint32_t u0 = wb; u0 < wend; u0 += 64) {
         const uint32_t u = u0 + lane;
         const uint64_t km = kscratch[u0 >> 6];
+        if (km == 0) continue;  // nothing kept in these 64 vertices
         const bool keep = (km >> lane) & 1u;
         const uint32_t deg = keep ? off[vbase + u + 1] - off[vbase + u] : 0u;
         const uint32_t dincl = wave_incl_scan(deg);
-        if (lane == 0) {
-            nbits[u0 >> 5] = (uint32_t)km;
-            nbits[(u0 >> 5) + 1] = (uint32_t)(km >> 32);
-        }
         if (keep) {
             const uint32_t at = pos + popc_lt(km);
             nlist[at] = (uint16_t)u;
             npre[at] = epos + dincl - deg;
         }
         pos += popc64(km);
-        epos += __shfl(dincl, 63, 64);
+        epos += last_lane(dincl);
     }
     my_d = wave_sum_f64(my_d);
     const uint64_t ids64 = wave_sum_u64((uint64_t)ids_done);
@@ -188,10 +201,10 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
             ni += sh.r64[w];
             d += sh.rd[w];
         }
-        G.fVa[nxt][cq] = tot;
-        G.fEa[nxt][cq] = etot;
-        G.dpart[nxt][cq] = d;
-        if (task != 0xFFFFFFFFu) G.gat_ids[task] = (uint32_t)ni;
+        gptr(G.fVa[nxt])[cq] = tot;
+        gptr(G.fEa[nxt])[cq] = etot;
+        gptr(G.dpart[nxt])[cq] = d;
+        if (task != 0xFFFFFFFFu) gptr(G.gat_ids)[task] = (uint32_t)ni;
     }
 }
 
@@ -227,23 +240,23 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
 template <int PROG, bool ROUNDS>
 __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
                                             uint32_t it, uint32_t task) {
-    if (G.ctrl->done) return;
+    if (gptr(G.ctrl)->done) return;
     constexpr bool SUM = is_sum(PROG);
     constexpr uint32_t IDENT = is_sum(PROG) ? kIdentSum : kIdentMin;
     // pieces per wave per combine round (the atomic-free sum keeps two, for registers)
     constexpr uint32_t PPW = (ROUNDS && SUM) ? 2 : 4;
-    const uint4 TA = G.gtask[2 * task], TB = G.gtask[2 * task + 1];
+    const uint4 TA = gptr(G.gtask)[2 * task], TB = gptr(G.gtask)[2 * task + 1];
     const uint32_t cq = TA.x, nt = TA.w >> 16, jt = TA.w & 0xFFFFu;
     uint32_t p_lo = TA.y, p_hi = TA.z;
     // the two id / weight / chunk arrays a piece may come from, as uniform
     // values (a per-lane choice between two fields of the view would
     // otherwise become a per-lane load of the pointer itself)
-    const uint16_t* __restrict__ ids_sc = uniform_ptr(G.sc_ids);
-    const uint16_t* __restrict__ ids_pc = uniform_ptr(G.png_ids);
-    const uint8_t* __restrict__ w_sc = uniform_ptr(G.sc_w);
-    const uint8_t* __restrict__ w_pc = uniform_ptr(G.png_w);
-    const uint32_t* __restrict__ ch_sc = uniform_ptr(G.sc_chunk);
-    const uint32_t* __restrict__ ch_pc = uniform_ptr(G.png_chunk);
+    const uint16_t* __restrict__ ids_sc = uniform_ptr(gptr(G.sc_ids));
+    const uint16_t* __restrict__ ids_pc = uniform_ptr(gptr(G.png_ids));
+    const uint8_t* __restrict__ w_sc = uniform_ptr(gptr(G.sc_w));
+    const uint8_t* __restrict__ w_pc = uniform_ptr(gptr(G.png_w));
+    const uint32_t* __restrict__ ch_sc = uniform_ptr(gptr(G.sc_chunk));
+    const uint32_t* __restrict__ ch_pc = uniform_ptr(gptr(G.png_chunk));
     uint32_t s0 = TB.x, s1 = TB.y;
     const uint32_t slot = TB.z;
     bool split = nt > 1;
@@ -252,8 +265,8 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     const uint32_t vbase = cq << G.s;
     const uint32_t nv = min(Q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    const uint4* __restrict__ cmcol = G.cm + (size_t)cq * k;
-    const uint2* __restrict__ sccol = G.sc_cnt + (size_t)cq * k;
+    const uint4* __restrict__ cmcol = gptr(G.cm) + (size_t)cq * k;
+    const uint2* __restrict__ sccol = gptr(G.sc_cnt) + (size_t)cq * k;
 
     extern __shared__ __align__(16) unsigned char smem[];
     const GatherLds L = gather_layout(PROG, Q, ROUNDS);
@@ -274,7 +287,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     if (split) {
         uint32_t c = 0;
         for (uint32_t p = tid; p < k; p += kGT) {
-            const uint32_t md = G.mode[p];
+            const uint32_t md = gptr(G.mode)[p];
             c += md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
         }
         c = wave_sum_u32(c);
@@ -286,13 +299,13 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         if (tot <= G.whole_ids) {
             if (jt != 0) {
                 if (tid == 0) {
-                    G.gflag[slot] = 0;
-                    G.gat_ids[task] = 0;
-                    G.gat_ran[task] = 0;
+                    gptr(G.gflag)[slot] = 0;
+                    gptr(G.gat_ids)[task] = 0;
+                    gptr(G.gat_ran)[task] = 0;
                 }
                 return;
             }
-            if (tid == 0) G.gflag[slot] = 2;  // the merge skips this partition
+            if (tid == 0) gptr(G.gflag)[slot] = 2;  // the merge skips this partition
             split = false;
             p_lo = 0;
             p_hi = k - 1;
@@ -302,9 +315,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     }
 
     // ---- anything to do for this task?
-    int any = (!split && G.fVa[cur][cq] > 0) ? 1 : 0;
+    int any = (!split && !msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0) ? 1 : 0;
     for (uint32_t p = p_lo + tid; p <= p_hi && !any; p += kGT) {
-        const uint32_t md = G.mode[p];
+        const uint32_t md = gptr(G.mode)[p];
         const uint32_t ic = md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
         any |= ic > 0;
     }
@@ -312,29 +325,29 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     if (!any) {
         if (tid == 0) {
             if (split) {
-                G.gflag[slot] = 0;
+                gptr(G.gflag)[slot] = 0;
             } else {
-                G.fVa[nxt][cq] = 0;
-                G.fEa[nxt][cq] = 0;
-                G.dpart[nxt][cq] = 0.0;
+                gptr(G.fVa[nxt])[cq] = 0;
+                gptr(G.fEa[nxt])[cq] = 0;
+                gptr(G.dpart[nxt])[cq] = 0.0;
             }
-            G.gat_ids[task] = 0;
-            G.gat_ran[task] = 0;
+            gptr(G.gat_ids)[task] = 0;
+            gptr(G.gat_ran)[task] = 0;
         }
         return;
     }
-    if (tid == 0) G.gat_ran[task] = split ? 2u : 1u;
+    if (tid == 0) gptr(G.gat_ran)[task] = split ? 2u : 1u;
 
-    // ---- state into LDS: the partition's values (single task) or the
-    //      combine identity (partial of a split task)
+    // ---- LDS copy of the partition at the combine identity (the filter
+    //      compares it with the stored values)
     for (uint32_t u = tid; u < Q; u += kGT) {
         if constexpr (SUM) acc[u] = 0ull;
-        else st32[u] = (!split && u < nv) ? state[vbase + u] : 0xFFFFFFFFu;
+        else st32[u] = kIdentMin;
         if constexpr (has_carry(PROG)) carry[u] = 0;
     }
     __syncthreads();
     if (!split) {
-        reinit<PROG>(G, P, it, cq, st32, carry);
+        reinit<PROG>(G, P, state, it, cq, st32, carry);
         __syncthreads();
     }
 
@@ -344,7 +357,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     for (uint32_t p0 = p_lo; p0 <= p_hi; p0 += kGT) {
         const uint32_t p = p0 + tid;
         const bool inr = p <= p_hi;
-        const uint32_t md = inr ? G.mode[p] : GPOP_MODE_NONE;
+        const uint32_t md = inr ? gptr(G.mode)[p] : GPOP_MODE_NONE;
         uint32_t sp = 0, ioff = 0, icnt = 0, moff = 0, mcnt = 0;
         if (inr) {
             const uint4 c = cmcol[p];
@@ -470,10 +483,10 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                     midx += (fmask >> j) & 1u;
                     const bool ok = (vmask >> j) & 1u;
                     if (ok && (midx >= bmcnt[pi] || dst[4 * pi + j] >= nv)) {
-                        G.ctrl->bug = 1;  // inconsistent bin: never read or write out of range
+                        gptr(G.ctrl)->bug = 1;  // inconsistent bin: never read or write out of range
                         vmask &= ~(1u << j);
                     }
-                    val[4 * pi + j] = ((vmask >> j) & 1u) ? G.data[bmoff[pi] + midx] : IDENT;
+                    val[4 * pi + j] = ((vmask >> j) & 1u) ? gptr(G.data)[bmoff[pi] + midx] : IDENT;
                 }
                 vmaskall |= vmask << (4 * pi);
             }
@@ -599,10 +612,10 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     if (split) {
         // partial result of this task for the merge
         if constexpr (SUM) {
-            unsigned long long* out = reinterpret_cast<unsigned long long*>(G.gpart) + (size_t)slot * Q;
+            unsigned long long* out = reinterpret_cast<unsigned long long*>(gptr(G.gpart)) + (size_t)slot * Q;
             for (uint32_t u = tid; u < nv; u += kGT) out[u] = acc[u];
         } else {
-            uint32_t* out = G.gpart + (size_t)slot * 2 * Q;
+            uint32_t* out = gptr(G.gpart) + (size_t)slot * 2 * Q;
             for (uint32_t u = tid; u < nv; u += kGT) out[u] = st32[u];
         }
         const uint64_t ids64 = wave_sum_u64((uint64_t)my_ids);
@@ -611,8 +624,8 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         if (tid == 0) {
             uint64_t ni = 0;
             for (uint32_t w = 0; w < kGW; ++w) ni += sh.r64[w];
-            G.gflag[slot] = 1;
-            G.gat_ids[task] = (uint32_t)ni;
+            gptr(G.gflag)[slot] = 1;
+            gptr(G.gat_ids)[task] = (uint32_t)ni;
         }
         return;
     }
@@ -625,7 +638,7 @@ __global__ __launch_bounds__(kGT, 2) void kb_gather(const Inst* __restrict__ tab
                                                     const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    gather_body<PROG, ROUNDS>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+    gather_body<PROG, ROUNDS>(I.G, I.P, gptr(I.state), gptr(I.G.ctrl)->pos - 1u, blockIdx.x - boff[i]);
 }
 
 // Merge of a partition whose gather was split over several tasks, in two
@@ -649,11 +662,11 @@ constexpr uint32_t kWholeCol = 0xFFFFFFFFu;
 template <int PROG>
 __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
                                                 uint32_t it, uint32_t local) {
-    if (G.ctrl->done) return;
+    if (gptr(G.ctrl)->done) return;
     constexpr bool SUM = is_sum(PROG);
     const uint32_t Q = G.q, C = merge_chunks(Q), R = Q / C;
     const uint32_t sidx = local / C, c = local - sidx * C;
-    const uint4 S = G.gsplit[sidx];
+    const uint4 S = gptr(G.gsplit)[sidx];
     const uint32_t cq = S.x, nt = S.z, slot0 = S.w;
     const uint32_t vbase = cq << G.s;
     const uint32_t nv = min(Q, G.V - vbase);
@@ -664,7 +677,7 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
     __shared__ uint32_t s_wc[kMW], s_we[kMW];
     __shared__ double s_wd[kMW];
     if (wave == 0) {
-        const uint32_t f = lane < nt ? G.gflag[slot0 + lane] : 0u;
+        const uint32_t f = lane < nt ? gptr(G.gflag)[slot0 + lane] : 0u;
         const uint32_t f0 = (uint32_t)__shfl((int)f, 0, 64);
         const uint64_t wm = ballot(f != 0u);
         if (f) s_wl[popc_lt(wm)] = slot0 + lane;
@@ -674,29 +687,29 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
     const uint32_t nw = s_nw;
     const bool lead = c == 0 && tid == 0;
     if (nw == kWholeCol) {  // gathered whole by its first task
-        if (lead) G.gat_ran[G.n_gtask + sidx] = 0;
+        if (lead) gptr(G.gat_ran)[G.n_gtask + sidx] = 0;
         return;
     }
-    const bool prev = G.fVa[cur][cq] > 0;  // frontier bitmap of cq is current
+    const bool prev = !msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0;  // frontier bitmap of cq is current
     if (nw == 0 && !prev) {
         if (lead) {
-            G.fVa[nxt][cq] = 0;
-            G.fEa[nxt][cq] = 0;
-            G.dpart[nxt][cq] = 0.0;
-            G.gat_ran[G.n_gtask + sidx] = 0;
+            gptr(G.fVa[nxt])[cq] = 0;
+            gptr(G.fEa[nxt])[cq] = 0;
+            gptr(G.dpart[nxt])[cq] = 0.0;
+            gptr(G.gat_ran)[G.n_gtask + sidx] = 0;
         }
         return;
     }
-    if (lead) G.gat_ran[G.n_gtask + sidx] = 3;
+    if (lead) gptr(G.gat_ran)[G.n_gtask + sidx] = 3;
 
     const uint32_t ulo = c * R, nu = R / kMT;
-    const uint32_t* __restrict__ pbits = G.fbits[cur] + (vbase >> 5);
-    uint32_t* __restrict__ nbits = G.fbits[nxt] + (vbase >> 5);
-    const uint32_t* __restrict__ off = G.off;
-    const double dang = SUM ? G.ctrl->dangling : 0.0;
-    // the thread's vertices u = ulo + kMT * i + tid: state before gather
-    // (min programs), combined value, initFunc's keep-active flag
-    uint32_t m0[kMU], m[kMU];
+    const uint32_t* __restrict__ pbits = gptr(G.fbits[cur]) + (vbase >> 5);
+    uint32_t* __restrict__ nbits = gptr(G.fbits[nxt]) + (vbase >> 5);
+    const uint32_t* __restrict__ off = gptr(G.off);
+    const double dang = SUM ? gptr(G.ctrl)->dangling : 0.0;
+    // the thread's vertices u = ulo + kMT * i + tid: combined value (min
+    // programs: least message, identity if none), initFunc's keep-active flag
+    uint32_t m[kMU];
     unsigned long long a[kMU];
     bool was[kMU];
 #pragma unroll
@@ -705,11 +718,11 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
         const bool in = i < nu && u < nv;
         was[i] = in && prev && test_bit(pbits, u);
         if constexpr (SUM) a[i] = 0ull;
-        else m0[i] = m[i] = in ? state[vbase + u] : 0xFFFFFFFFu;
+        else m[i] = kIdentMin;
     }
     for (uint32_t w = 0; w < nw; w += kPJ) {
         if constexpr (SUM) {
-            const unsigned long long* part = reinterpret_cast<const unsigned long long*>(G.gpart);
+            const unsigned long long* part = reinterpret_cast<const unsigned long long*>(gptr(G.gpart));
             unsigned long long x[kPJ][kMU];
 #pragma unroll
             for (uint32_t r = 0; r < kPJ; ++r) {
@@ -731,7 +744,7 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
             for (uint32_t r = 0; r < kPJ; ++r) {
                 // past the end, re-read the first partial of the group: min
                 // is idempotent
-                const uint32_t* pj = G.gpart + (size_t)s_wl[w + r < nw ? w + r : w] * 2 * Q;
+                const uint32_t* pj = gptr(G.gpart) + (size_t)s_wl[w + r < nw ? w + r : w] * 2 * Q;
 #pragma unroll
                 for (uint32_t i = 0; i < kMU; ++i) {
                     const uint32_t u = ulo + kMT * i + tid;
@@ -755,9 +768,12 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
             bool keep = false;
             if (u < nv) {
                 if constexpr (!SUM) {
-                    const bool hit = m[i] < m0[i];
+                    // the stored value is read only where it is compared
+                    const bool need = m[i] != kIdentMin || (has_carry(PROG) && was[i]);
+                    const uint32_t m0 = need ? state[v] : 0u;
+                    const bool hit = m[i] != kIdentMin && m[i] < m0;
                     keep = hit;
-                    if constexpr (has_carry(PROG)) keep = keep || (was[i] && (it + 1u - m0[i]) < P.persist);
+                    if constexpr (has_carry(PROG)) keep = keep || (was[i] && (it + 1u - m0) < P.persist);
                     if (hit) state[v] = m[i];
                 } else {
                     if (a[i] != 0ull || was[i]) {  // received an amount, or was active before scatter
@@ -806,22 +822,22 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
             td += s_wd[w];
         }
         const unsigned long long db = (unsigned long long)__double_as_longlong(td);
-        G.mtot[(size_t)sidx * C + c] = make_uint4(tc, te, (uint32_t)db, (uint32_t)(db >> 32));
+        gptr(G.mtot)[(size_t)sidx * C + c] = make_uint4(tc, te, (uint32_t)db, (uint32_t)(db >> 32));
     }
 }
 
 __device__ __forceinline__ void merge_list_body(const Dev& G, uint32_t it, uint32_t local) {
-    if (G.ctrl->done) return;
+    if (gptr(G.ctrl)->done) return;
     const uint32_t Q = G.q, C = merge_chunks(Q), R = Q / C;
     const uint32_t sidx = local / C, c = local - sidx * C;
-    if (G.gat_ran[G.n_gtask + sidx] != 3u) return;
-    const uint32_t cq = G.gsplit[sidx].x;
+    if (gptr(G.gat_ran)[G.n_gtask + sidx] != 3u) return;
+    const uint32_t cq = gptr(G.gsplit)[sidx].x;
     const uint32_t vbase = cq << G.s;
     const uint32_t nxt = (it & 1u) ^ 1u;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     __shared__ uint32_t s_wc[kMW], s_we[kMW], s_base[2];
     if (wave == 0) {
-        const uint4 t = lane < C ? G.mtot[(size_t)sidx * C + lane] : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 t = lane < C ? gptr(G.mtot)[(size_t)sidx * C + lane] : make_uint4(0u, 0u, 0u, 0u);
         const uint32_t before = wave_sum_u32(lane < c ? t.x : 0u);
         const uint32_t ebefore = wave_sum_u32(lane < c ? t.y : 0u);
         const double d = __longlong_as_double((long long)(((unsigned long long)t.w << 32) | t.z));
@@ -830,9 +846,9 @@ __device__ __forceinline__ void merge_list_body(const Dev& G, uint32_t it, uint3
             double sd = 0.0;
             for (uint32_t j = 0; j < C; ++j) sd += __shfl(d, (int)j, 64);
             if (lane == 0) {
-                G.fVa[nxt][cq] = tot;
-                G.fEa[nxt][cq] = etot;
-                G.dpart[nxt][cq] = sd;
+                gptr(G.fVa[nxt])[cq] = tot;
+                gptr(G.fEa[nxt])[cq] = etot;
+                gptr(G.dpart[nxt])[cq] = sd;
             }
         }
         if (lane == 0) {
@@ -843,8 +859,8 @@ __device__ __forceinline__ void merge_list_body(const Dev& G, uint32_t it, uint3
     // wave w lists the vertices [ulo + w * per, ulo + (w + 1) * per)
     const uint32_t per = R / kMW, ng = per / 64;
     const uint32_t ub = c * R + wave * per;
-    const uint32_t* __restrict__ bits = G.fbits[nxt] + (vbase >> 5);
-    const uint32_t* __restrict__ off = G.off + vbase;
+    const uint32_t* __restrict__ bits = gptr(G.fbits[nxt]) + (vbase >> 5);
+    const uint32_t* __restrict__ off = gptr(G.off) + vbase;
     uint32_t deg[kMU];
     uint64_t km[kMU];
     uint32_t cnt = 0, edges = 0;
@@ -871,8 +887,8 @@ __device__ __forceinline__ void merge_list_body(const Dev& G, uint32_t it, uint3
         pos += s_wc[w];
         epos += s_we[w];
     }
-    uint16_t* __restrict__ nlist = G.flist[nxt] + vbase;
-    uint32_t* __restrict__ npre = G.fpre[nxt] + vbase;
+    uint16_t* __restrict__ nlist = gptr(G.flist[nxt]) + vbase;
+    uint32_t* __restrict__ npre = gptr(G.fpre[nxt]) + vbase;
 #pragma unroll
     for (uint32_t g = 0; g < kMU; ++g) {
         if (g < ng) {
@@ -884,7 +900,7 @@ __device__ __forceinline__ void merge_list_body(const Dev& G, uint32_t it, uint3
                 npre[at] = epos + dincl - deg[g];
             }
             pos += popc64(km[g]);
-            epos += __shfl(dincl, 63, 64);
+            epos += last_lane(dincl);
         }
     }
 }
@@ -894,14 +910,14 @@ __global__ __launch_bounds__(kMT) void kb_merge_part(const Inst* __restrict__ ta
                                                      const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    merge_part_body<PROG>(I.G, I.P, I.state, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+    merge_part_body<PROG>(I.G, I.P, gptr(I.state), gptr(I.G.ctrl)->pos - 1u, blockIdx.x - boff[i]);
 }
 
 __global__ __launch_bounds__(kMT) void kb_merge_list(const Inst* __restrict__ tab,
                                                      const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    merge_list_body(I.G, I.G.ctrl->pos - 1u, blockIdx.x - boff[i]);
+    merge_list_body(I.G, gptr(I.G.ctrl)->pos - 1u, blockIdx.x - boff[i]);
 }
 
 // Batched: run status {done, iterations} per run, and the iteration limit of
@@ -909,7 +925,7 @@ __global__ __launch_bounds__(kMT) void kb_merge_list(const Inst* __restrict__ ta
 __global__ void kb_status(const Inst* __restrict__ tab, uint32_t n, uint32_t* __restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const Ctrl* C = tab[i].G.ctrl;
+    const Ctrl* C = tab[i].G.ctrl;  // one run per lane: not a uniform pointer
     out[2 * i] = C->done;
     out[2 * i + 1] = C->pos - C->run_start;  // iterations of the current run
 }
@@ -917,7 +933,7 @@ __global__ void kb_status(const Inst* __restrict__ tab, uint32_t n, uint32_t* __
 __global__ void kb_limits(const Inst* __restrict__ tab, uint32_t n, uint32_t max_iter) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    Ctrl* C = tab[i].G.ctrl;
+    Ctrl* C = tab[i].G.ctrl;  // one run per lane: not a uniform pointer
     const uint64_t lim = (uint64_t)C->pos + max_iter;
     C->max_it = lim > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)lim;
     C->run_start = C->pos;
@@ -1009,31 +1025,31 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
             default: x = v == P.root ? 0u : 0xFFFFFFFFu; break;
         }
         state[v] = x;
-        if ((prog == P_PR || prog == P_PPR) && G.off[v + 1] == G.off[v])
+        if ((prog == P_PR || prog == P_PPR) && gptr(G.off)[v + 1] == gptr(G.off)[v])
             my_d += (double)__uint_as_float(x);
     }
     my_d = wave_sum_f64(my_d);
     if ((threadIdx.x & 63u) == 0) s_rd[threadIdx.x >> 6] = my_d;
     __syncthreads();
     if (threadIdx.x == 0) {
-        G.dpart[0][p] = s_rd[0] + s_rd[1] + s_rd[2] + s_rd[3];
-        G.dpart[1][p] = 0.0;
-        G.fVa[0][p] = 0;
-        G.fEa[0][p] = 0;
-        G.fVa[1][p] = 0;
-        G.fEa[1][p] = 0;
-        G.mode[p] = GPOP_MODE_NONE;
+        gptr(G.dpart[0])[p] = s_rd[0] + s_rd[1] + s_rd[2] + s_rd[3];
+        gptr(G.dpart[1])[p] = 0.0;
+        gptr(G.fVa[0])[p] = 0;
+        gptr(G.fEa[0])[p] = 0;
+        gptr(G.fVa[1])[p] = 0;
+        gptr(G.fEa[1])[p] = 0;
+        gptr(G.mode)[p] = GPOP_MODE_NONE;
     }
     if (p == 0 && threadIdx.x == 0) {
-        G.ctrl->done = 0;
-        G.ctrl->iters = 0;
-        G.ctrl->frontier = 0;
-        G.ctrl->dangling = 0.0;
-        G.ctrl->fin_it = 0;
-        G.ctrl->mlp_fallback = 0;
-        G.ctrl->pos = 0;
-        G.ctrl->max_it = 0xFFFFFFFFu;
-        G.ctrl->run_start = 0;
+        gptr(G.ctrl)->done = 0;
+        gptr(G.ctrl)->iters = 0;
+        gptr(G.ctrl)->frontier = 0;
+        gptr(G.ctrl)->dangling = 0.0;
+        gptr(G.ctrl)->fin_it = 0;
+        gptr(G.ctrl)->mlp_fallback = 0;
+        gptr(G.ctrl)->pos = 0;
+        gptr(G.ctrl)->max_it = 0xFFFFFFFFu;
+        gptr(G.ctrl)->run_start = 0;
     }
 }
 
@@ -1064,26 +1080,26 @@ hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st) {
 __global__ void k_mark(Dev G, const uint32_t* __restrict__ verts, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t v = verts[i];
-        if (v < G.V) G.marks[v] = 1;
-        else G.ctrl->err = 1;
+        if (v < G.V) gptr(G.marks)[v] = 1;
+        else gptr(G.ctrl)->err = 1;
     }
 }
 
 __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all) {
     const uint32_t p = blockIdx.x;
-    const uint32_t buf = G.ctrl->pos & 1u;  // the buffer the next plan reads
+    const uint32_t buf = gptr(G.ctrl)->pos & 1u;  // the buffer the next plan reads
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     __shared__ uint32_t s_wc[16], s_ws[16];
-    uint16_t* list = G.flist[buf] + vbase;
-    uint32_t* pre = G.fpre[buf] + vbase;
-    uint32_t* bits = G.fbits[buf] + (vbase >> 5);
+    uint16_t* list = gptr(G.flist[buf]) + vbase;
+    uint32_t* pre = gptr(G.fpre[buf]) + vbase;
+    uint32_t* bits = gptr(G.fbits[buf]) + (vbase >> 5);
     uint32_t running = 0, erun = 0;
     for (uint32_t u0 = 0; u0 < nv; u0 += 1024) {
         const uint32_t u = u0 + tid;
-        const bool keep = u < nv && (all || G.marks[vbase + u]);
-        const uint32_t deg = keep ? G.off[vbase + u + 1] - G.off[vbase + u] : 0u;
+        const bool keep = u < nv && (all || gptr(G.marks)[vbase + u]);
+        const uint32_t deg = keep ? gptr(G.off)[vbase + u + 1] - gptr(G.off)[vbase + u] : 0u;
         const uint64_t bm = ballot(keep);
         const uint32_t dincl = wave_incl_scan(deg);
         if (lane == 0 && u0 + wave * 64u < G.q) {
@@ -1115,11 +1131,11 @@ __global__ __launch_bounds__(1024) void k_marks_to_frontier(Dev G, int all) {
         __syncthreads();
     }
     if (tid == 0) {
-        G.fVa[buf][p] = running;
-        G.fEa[buf][p] = erun;
+        gptr(G.fVa[buf])[p] = running;
+        gptr(G.fEa[buf])[p] = erun;
     }
     if (p == 0 && tid == 0) {
-        G.ctrl->done = 0;
+        gptr(G.ctrl)->done = 0;
     }
 }
 

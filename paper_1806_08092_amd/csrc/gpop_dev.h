@@ -177,6 +177,21 @@ struct Inst {
 
 // A global-memory pointer every lane holds the same value of, made opaque to
 // the compiler (it stays a scalar value and keeps its address space).
+// A pointer into device memory, the same in every lane, marked as global
+// memory. Pointers read from the view in memory are otherwise generic, and
+// accesses through them become flat instructions, which also count against
+// the LDS wait counter (an LDS read then waits for the flat access as well).
+// The value goes through readfirstlane so that the compiler cannot fold the
+// address-space casts away.
+template <class T>
+__device__ __forceinline__ T* gptr(T* p) {
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    typedef __attribute__((address_space(1))) T GlobalT;
+    return (T*)(GlobalT*)(((uint64_t)hi << 32) | lo);
+}
+
 template <class T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
     const uint64_t u = reinterpret_cast<uint64_t>(p);
@@ -210,14 +225,22 @@ __device__ __forceinline__ uint32_t popc_lt(uint64_t m) {
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive prefix sum across the wave with DPP: shifts by 1, 2, 4, 8 lanes
+// inside each row of 16, then the last lane of row 0 is added to row 1 and
+// of row 2 to row 3 (row_bcast:15), then the last lane of row 1 to rows 2
+// and 3 (row_bcast:31). Lanes without a source read 0.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, 64);
-        if (l >= (uint32_t)d) x += y;
-    }
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return x;
+}
+// The value of lane 63 (a scalar read, no LDS traffic).
+__device__ __forceinline__ uint32_t last_lane(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
@@ -257,7 +280,8 @@ __device__ __forceinline__ uint32_t scatter_value(const Dev& G, const uint32_t* 
     } else if constexpr (PROG == P_CC || PROG == P_SSSP) {
         return st[v];
     } else {
-        uint32_t deg = G.off[v + 1] - G.off[v];
+        const uint32_t* __restrict__ off = gptr(G.off);
+        uint32_t deg = off[v + 1] - off[v];
         float x = __uint_as_float(st[v]);
         return __float_as_uint(deg ? x / (float)deg : 0.0f);
     }

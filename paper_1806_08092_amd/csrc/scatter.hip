@@ -75,10 +75,10 @@ __device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __res
     const uint32_t lane = lane_id();
     const uint32_t k = G.k, s = G.s, qmask = G.q - 1u;
     const uint32_t vbase = p << s;
-    const uint32_t* __restrict__ off = G.off;
-    const uint32_t* __restrict__ cols = G.cols;
-    const uint32_t* __restrict__ rmoff = G.bin_moff + (size_t)p * k;
-    const uint32_t* __restrict__ rioff = G.bin_ioff + (size_t)p * k;
+    const uint32_t* __restrict__ off = gptr(G.off);
+    const uint32_t* __restrict__ cols = gptr(G.cols);
+    const uint32_t* __restrict__ rmoff = gptr(G.bin_moff) + (size_t)p * k;
+    const uint32_t* __restrict__ rioff = gptr(G.bin_ioff) + (size_t)p * k;
     const uint32_t base_off = off[vbase];
     constexpr uint32_t hdr = BUILD ? 0u : 1u;  // units of a vertex before its edges
     auto pre = [&](uint32_t i) -> uint32_t {
@@ -103,7 +103,7 @@ __device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __res
             if (cdeg) val = scatter_value<PROG>(G, state, v);
         }
         const uint32_t incl = wave_incl_scan(cdeg);
-        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t total = last_lane(incl);
         for (uint32_t g0 = 0; g0 < total; g0 += 64) {
             const uint32_t f = g0 + lane;
             const bool valid = f < total;
@@ -145,20 +145,20 @@ __device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __res
                 const uint32_t midx = bm + m_le - 1u;
                 // positions must stay inside the static capacity of bin[p][key]
                 if (pos >= rioff[key + 1] || midx >= rmoff[key + 1] - rmoff[key]) {
-                    G.ctrl->bug = 1;
+                    gptr(G.ctrl)->bug = 1;
                     continue;
                 }
                 const uint16_t idw = (uint16_t)((col & qmask) | (flag ? kFlag : 0u));
                 if constexpr (!BUILD) {
-                    if (flag) G.data[rmoff[key] + midx] = o_val;
-                    G.sc_ids[pos] = idw;
-                    if constexpr (is_weighted(PROG)) G.sc_w[pos] = G.w[e];
-                    if ((pos & (kChunk - 1)) == 0) G.sc_chunk[pos / kChunk] = midx;
+                    if (flag) gptr(G.data)[rmoff[key] + midx] = o_val;
+                    gptr(G.sc_ids)[pos] = idw;
+                    if constexpr (is_weighted(PROG)) gptr(G.sc_w)[pos] = gptr(G.w)[e];
+                    if ((pos & (kChunk - 1)) == 0) gptr(G.sc_chunk)[pos / kChunk] = midx;
                 } else {
-                    if (flag) G.png_src[rmoff[key] + midx] = (uint16_t)o_val;
-                    G.png_ids[pos] = idw;
-                    if (G.w) G.png_w[pos] = G.w[e];
-                    if ((pos & (kChunk - 1)) == 0) G.png_chunk[pos / kChunk] = midx;
+                    if (flag) gptr(G.png_src)[rmoff[key] + midx] = (uint16_t)o_val;
+                    gptr(G.png_ids)[pos] = idw;
+                    if (gptr(G.w)) gptr(G.png_w)[pos] = gptr(G.w)[e];
+                    if ((pos & (kChunk - 1)) == 0) gptr(G.png_chunk)[pos / kChunk] = midx;
                 }
             }
         }
@@ -172,18 +172,18 @@ template <int PROG, bool BUILD, bool WRITE>
 __device__ __forceinline__ void sc_pass_body(const Dev& G, const Params& P,
                                              const uint32_t* __restrict__ state, uint32_t it,
                                              uint32_t bid, uint32_t nblk) {
-    if (!BUILD && G.ctrl->done) return;
+    if (!BUILD && gptr(G.ctrl)->done) return;
     const uint32_t cur = it & 1u;
     const uint32_t k = G.k;
-    const uint32_t ntask = BUILD ? G.n_bldtask : G.ctrl->n_sctask;
-    const uint32_t* __restrict__ t0 = BUILD ? G.bld_t0 : G.sc_t0;
+    const uint32_t ntask = BUILD ? G.n_bldtask : gptr(G.ctrl)->n_sctask;
+    const uint32_t* __restrict__ t0 = BUILD ? gptr(G.bld_t0) : gptr(G.sc_t0);
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     extern __shared__ uint32_t lds[];
     uint32_t* ci = lds + wave * 2 * k;
     uint32_t* cm = ci + k;
     for (uint32_t t = bid * kScWaves + wave; t < ntask; t += nblk * kScWaves) {
         const uint64_t t_beg = (!BUILD && P.probe) ? wall_clock64() : 0;
-        uint2* __restrict__ tc = G.sc_tc + (size_t)t * k;
+        uint2* __restrict__ tc = gptr(G.sc_tc) + (size_t)t * k;
         for (uint32_t j = lane; j < k; j += 64) {
             if constexpr (WRITE) {
                 const uint2 b = tc[j];
@@ -196,21 +196,21 @@ __device__ __forceinline__ void sc_pass_body(const Dev& G, const Params& P,
         }
         const uint32_t p = task_owner(t0, k, t);
         const uint32_t jt = t - t0[p];
-        const uint32_t sh = BUILD ? G.sc_shift : G.sc_sh[p];
+        const uint32_t sh = BUILD ? G.sc_shift : gptr(G.sc_sh)[p];
         const uint32_t vbase = p << G.s;
         const uint32_t nv = min(G.q, G.V - vbase);
-        const uint32_t Ea = BUILD ? G.part_E[p] : G.fEa[cur][p];
-        const uint32_t nact = BUILD ? nv : G.fVa[cur][p];
+        const uint32_t Ea = BUILD ? gptr(G.part_E)[p] : gptr(G.fEa[cur])[p];
+        const uint32_t nact = BUILD ? nv : gptr(G.fVa[cur])[p];
         // the task's range of work units (BUILD: edges only)
         const uint32_t f0 = jt << sh;
         const uint32_t f1 = min(f0 + (1u << sh), BUILD ? Ea : Ea + nact);
-        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, G.flist[cur] + vbase,
-                                         G.fpre[cur] + vbase, ci, cm);
+        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, gptr(G.flist[cur]) + vbase,
+                                         gptr(G.fpre[cur]) + vbase, ci, cm);
         if constexpr (!WRITE) {
             for (uint32_t j = lane; j < k; j += 64) tc[j] = make_uint2(cm[j], ci[j]);
         }
         if (!BUILD && P.probe && lane == 0)  // one wave's time, charged to its partition
-            atomicAdd(G.probe + (WRITE ? k : 0) + p, (unsigned long long)(wall_clock64() - t_beg));
+            atomicAdd(gptr(G.probe) + (WRITE ? k : 0) + p, (unsigned long long)(wall_clock64() - t_beg));
     }
 }
 
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
 }
 
 // The iteration index: the plan has already advanced pos, except in a probe.
-__device__ __forceinline__ uint32_t scatter_it(const Inst& I) { return I.G.ctrl->pos - (I.P.probe ? 0u : 1u); }
+__device__ __forceinline__ uint32_t scatter_it(const Inst& I) { return gptr(I.G.ctrl)->pos - (I.P.probe ? 0u : 1u); }
 
 template <int PROG, bool WRITE>
 __global__ __launch_bounds__(kScWaves * 64) void kb_sc_pass(const Inst* __restrict__ tab,
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kScWaves * 64) void kb_sc_pass(const Inst* __restri
                                                             uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    sc_pass_body<PROG, false, WRITE>(I.G, I.P, I.state, scatter_it(I), blockIdx.x - boff[i],
+    sc_pass_body<PROG, false, WRITE>(I.G, I.P, gptr(I.state), scatter_it(I), blockIdx.x - boff[i],
                                      boff[i + 1] - boff[i]);
 }
 
@@ -245,7 +245,7 @@ template <bool BUILD>
 __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t qa, uint32_t qb,
                                              uint32_t tot_slot) {
     const uint32_t k = G.k;
-    const uint32_t* __restrict__ t0 = BUILD ? G.bld_t0 : G.sc_t0;
+    const uint32_t* __restrict__ t0 = BUILD ? gptr(G.bld_t0) : gptr(G.sc_t0);
     const uint32_t tb = t0[p], n = t0[p + 1] - tb;
     const uint32_t tid = threadIdx.x, ql = tid & 63u, strip = tid >> 6;
     __shared__ uint32_t s_m[16][64], s_i[16][64];
@@ -256,7 +256,7 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
     // few tasks: one thread per destination walks all of them (no strips)
     const bool serial = !BUILD && n <= kScanRows;
     for (uint32_t q = qa + tid; serial && q < qb; q += blockDim.x) {
-        uint2* __restrict__ col = G.sc_tc + (size_t)tb * k + q;
+        uint2* __restrict__ col = gptr(G.sc_tc) + (size_t)tb * k + q;
         uint32_t rm = 0, ri = 0, t = 0;
         for (; t + 8u <= n; t += 8u) {
             uint2 x[8];
@@ -275,14 +275,14 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
             rm += x.x;
             ri += x.y;
         }
-        G.sc_cnt[(size_t)q * k + p] = make_uint2(rm, ri);
+        gptr(G.sc_cnt)[(size_t)q * k + p] = make_uint2(rm, ri);
         my_tm += rm;
         my_ti += ri;
     }
     for (uint32_t q0 = qa; !serial && q0 < qb; q0 += 64) {
         const uint32_t q = q0 + ql;
         const bool qin = q < qb;
-        uint2* __restrict__ col = G.sc_tc + (size_t)tb * k + q;
+        uint2* __restrict__ col = gptr(G.sc_tc) + (size_t)tb * k + q;
         uint32_t sm = 0, si = 0;
         if (qin) {
             uint32_t t = a;
@@ -336,10 +336,10 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
             }
             if (strip == 0) {
                 if constexpr (BUILD) {
-                    G.cnt_m[(size_t)p * k + q] = tm;
-                    G.cnt_i[(size_t)p * k + q] = ti;
+                    gptr(G.cnt_m)[(size_t)p * k + q] = tm;
+                    gptr(G.cnt_i)[(size_t)p * k + q] = ti;
                 } else {
-                    G.sc_cnt[(size_t)q * k + p] = make_uint2(tm, ti);
+                    gptr(G.sc_cnt)[(size_t)q * k + p] = make_uint2(tm, ti);
                     my_tm += tm;
                     my_ti += ti;
                 }
@@ -360,7 +360,7 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
                 x += s_tot[0][w];
                 y += s_tot[1][w];
             }
-            G.sc_tot[tot_slot] = make_uint2((uint32_t)x, (uint32_t)y);
+            gptr(G.sc_tot)[tot_slot] = make_uint2((uint32_t)x, (uint32_t)y);
         }
         __syncthreads();  // s_tot and the strip arrays are reused by the next unit
     }
@@ -378,11 +378,11 @@ __global__ __launch_bounds__(1024) void kb_sc_scan(const Inst* __restrict__ tab,
                                                    const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Dev& G = tab[i].G;
-    if (G.ctrl->done) return;
-    const uint32_t nu = G.ctrl->n_scunits, nblk = boff[i + 1] - boff[i];
+    if (gptr(G.ctrl)->done) return;
+    const uint32_t nu = gptr(G.ctrl)->n_scunits, nblk = boff[i + 1] - boff[i];
     const uint32_t ncb = col_blocks(G.k);
     for (uint32_t u = blockIdx.x - boff[i]; u < nu; u += nblk) {
-        const uint32_t e = G.sc_units[u];
+        const uint32_t e = gptr(G.sc_units)[u];
         const uint32_t p = e & 0xFFFFu, cb = (e >> 16) & 0x7FFFu;
         const bool whole = (e >> 31) != 0u;
         const uint32_t qa = whole ? 0u : cb * 64u, qb = whole ? G.k : min(G.k, qa + 64u);
@@ -435,10 +435,10 @@ hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st) {
 template <int PROG>
 __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uint32_t* __restrict__ state,
                                         uint32_t it, uint32_t task) {
-    if (G.ctrl->done) return;
-    const uint4 t = G.pctask[task];
+    if (gptr(G.ctrl)->done) return;
+    const uint4 t = gptr(G.pctask)[task];
     const uint32_t p = t.x;
-    if (G.mode[p] != GPOP_MODE_PC) return;
+    if (gptr(G.mode)[p] != GPOP_MODE_PC) return;
     uint64_t t_beg = 0;
     if (P.probe) {
         __syncthreads();
@@ -448,12 +448,12 @@ __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uin
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
     extern __shared__ uint32_t mv[];
-    const uint32_t* __restrict__ bits = G.fbits[cur] + (vbase >> 5);
+    const uint32_t* __restrict__ bits = gptr(G.fbits[cur]) + (vbase >> 5);
     for (uint32_t v = threadIdx.x; v < nv; v += 256)
         mv[v] = test_bit(bits, v) ? scatter_value<PROG>(G, state, vbase + v) : ident_of<PROG>();
     __syncthreads();
-    const uint16_t* __restrict__ src = G.png_src;
-    uint32_t* __restrict__ data = G.data;
+    const uint16_t* __restrict__ src = gptr(G.png_src);
+    uint32_t* __restrict__ data = gptr(G.data);
     // aligned middle in groups of 4 slots (8-byte source loads, 16-byte stores)
     uint32_t a = t.y, b = t.z;
     uint32_t a4 = min((a + 3u) & ~3u, b);
@@ -472,7 +472,7 @@ __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uin
     if (P.probe) {  // four waves' time, charged to the partition
         __syncthreads();
         if (threadIdx.x == 0)
-            atomicAdd(G.probe + 2 * G.k + p, 4ull * (unsigned long long)(wall_clock64() - t_beg));
+            atomicAdd(gptr(G.probe) + 2 * G.k + p, 4ull * (unsigned long long)(wall_clock64() - t_beg));
     }
 }
 
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void kb_pc(const Inst* __restrict__ tab, const
                                              uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    pc_body<PROG>(I.G, I.P, I.state, scatter_it(I), blockIdx.x - boff[i]);
+    pc_body<PROG>(I.G, I.P, gptr(I.state), scatter_it(I), blockIdx.x - boff[i]);
 }
 
 
@@ -494,18 +494,18 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
     uint64_t v[6] = {0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged
     const uint32_t ncb = col_blocks(G.k);
     for (uint32_t p = tid; p < G.k; p += blockDim.x) {
-        if (G.mode[p] == GPOP_MODE_SC) {
-            const uint32_t nu = G.sc_t0[p + 1] - G.sc_t0[p] > kScanRows ? ncb : 1u;
+        if (gptr(G.mode)[p] == GPOP_MODE_SC) {
+            const uint32_t nu = gptr(G.sc_t0)[p + 1] - gptr(G.sc_t0)[p] > kScanRows ? ncb : 1u;
             for (uint32_t j = 0; j < nu; ++j) {
-                const uint2 t = G.sc_tot[(size_t)p * ncb + j];
+                const uint2 t = gptr(G.sc_tot)[(size_t)p * ncb + j];
                 v[0] += t.x;
                 v[1] += t.y;
             }
         }
     }
     for (uint32_t t = tid; t < G.n_gtask + G.n_gsplit; t += blockDim.x) {
-        if (t < G.n_gtask) v[2] += G.gat_ids[t];
-        const uint32_t r = G.gat_ran[t];
+        if (t < G.n_gtask) v[2] += gptr(G.gat_ids)[t];
+        const uint32_t r = gptr(G.gat_ran)[t];
         v[3] += r == 1;
         v[4] += r == 2;
         v[5] += r == 3;
@@ -518,7 +518,7 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
         uint64_t t[6] = {0, 0, 0, 0, 0, 0};
         for (uint32_t w = 0; w < blockDim.x / 64; ++w)
             for (int j = 0; j < 6; ++j) t[j] += red[j][w];
-        gpop_iter_stats* r = G.log + ((it - 1) % kLogCap);
+        gpop_iter_stats* r = gptr(G.log) + ((it - 1) % kLogCap);
         r->sc_msgs = t[0];
         r->sc_ids = t[1];
         r->gathered_ids = t[2];
@@ -533,22 +533,22 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
 // come before the plan of the same iteration, and both rewrite what it reads.
 __device__ __forceinline__ void finalize_once(const Dev& G, uint32_t it) {
     __shared__ uint32_t s_need;
-    if (threadIdx.x == 0) s_need = it > 0 && G.ctrl->fin_it < it;
+    if (threadIdx.x == 0) s_need = it > 0 && gptr(G.ctrl)->fin_it < it;
     __syncthreads();
     if (s_need) {
         finalize_prev(G, it);
-        if (threadIdx.x == 0) G.ctrl->fin_it = it;
+        if (threadIdx.x == 0) gptr(G.ctrl)->fin_it = it;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(Dev G) { finalize_once(G, G.ctrl->pos); }
+__global__ __launch_bounds__(1024) void k_finalize(Dev G) { finalize_once(G, gptr(G.ctrl)->pos); }
 
 // The plan runs as one workgroup of kPlanT threads per run.
 constexpr uint32_t kPlanT = 512;
 constexpr uint32_t kPlanW = kPlanT / 64;
 
 __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_t it) {
-    Ctrl* C = G.ctrl;
+    Ctrl* C = gptr(G.ctrl);
     if (C->done) return;
     if (!P.probe && it >= C->max_it) {  // the run's iteration limit: pause
         if (threadIdx.x == 0) C->done = 2u;
@@ -568,22 +568,22 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     for (uint32_t p0 = 0; p0 < G.k; p0 += kPlanT) {
         const uint32_t p = p0 + tid;
         if (p < G.k) {
-            const uint32_t Va = G.fVa[cur][p], Ea = G.fEa[cur][p];
+            const uint32_t Va = gptr(G.fVa[cur])[p], Ea = gptr(G.fEa[cur])[p];
             uint8_t md = GPOP_MODE_NONE;
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
                 else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
-                else if (P.selector == GPOP_SEL_LEARNED) md = G.mode_l[p];
+                else if (P.selector == GPOP_SEL_LEARNED) md = gptr(G.mode_l)[p];
                 else md = analytical_mode(G, P, p, Va, Ea);
             }
-            G.mode[p] = md;
+            gptr(G.mode)[p] = md;
             va += Va;
             ea += Ea;
             uint32_t units = 0xFFFFFFFFu;
             if (md == GPOP_MODE_PC) {
                 ++npc;
-                pcm += G.part_M[p];
-                pci += G.part_E[p];
+                pcm += gptr(G.part_M)[p];
+                pci += gptr(G.part_E)[p];
                 pcv += min(G.q, G.V - (p << G.s));
             } else if (md == GPOP_MODE_SC) {
                 ++nsc;
@@ -592,7 +592,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 units = (uint32_t)min<uint64_t>((uint64_t)Va + Ea, 0xFFFFFFFEull);
             }
             s_units[p] = units;
-            dang += G.dpart[cur][p];
+            dang += gptr(G.dpart[cur])[p];
         }
     }
     // task size of this iteration: about sc_task_target tasks, between
@@ -629,7 +629,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             uint32_t shp = sh;  // at most kMaxPartTasks tasks per partition
             while ((((uint64_t)units + (1ull << shp) - 1ull) >> shp) > kMaxPartTasks) ++shp;
             ntask = (uint32_t)(((uint64_t)units + (1ull << shp) - 1ull) >> shp);
-            G.sc_sh[p] = (uint8_t)shp;
+            gptr(G.sc_sh)[p] = (uint8_t)shp;
         }
         // (a partition without active out-edges still gets a unit: the scan
         // writes its zero bin counts)
@@ -651,10 +651,10 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             utot += s_u[w];
         }
         if (p < G.k) {
-            G.sc_t0[p] = tcarry + before + incl - ntask;
+            gptr(G.sc_t0)[p] = tcarry + before + incl - ntask;
             const uint32_t u0 = ucarry + ubefore + uincl - nunit;
             for (uint32_t j = 0; j < nunit; ++j)
-                G.sc_units[u0 + j] = p | (j << 16) | (nunit == 1u ? 0x80000000u : 0u);
+                gptr(G.sc_units)[u0 + j] = p | (j << 16) | (nunit == 1u ? 0x80000000u : 0u);
         }
         tcarry += tot;
         ucarry += utot;
@@ -690,7 +690,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             for (int j = 0; j < 9; ++j) t[j] += red[j][w];
             d += dred[w];
         }
-        G.sc_t0[G.k] = tcarry;
+        gptr(G.sc_t0)[G.k] = tcarry;
         C->n_sctask = tcarry;
         C->n_scunits = ucarry;
         if (tcarry > G.max_sctask) {  // cannot happen (the bound covers every task size): stop
@@ -704,7 +704,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         } else if (!P.probe) {
             C->iters = it + 1;
             C->pos = it + 1;
-            gpop_iter_stats* r = G.log + (it % kLogCap);
+            gpop_iter_stats* r = gptr(G.log) + (it % kLogCap);
             r->active_vertices = t[0];
             r->active_edges = t[1];
             r->sc_parts = (uint32_t)t[2];
@@ -730,7 +730,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
 // block.
 __global__ __launch_bounds__(kPlanT) void kb_plan(const Inst* __restrict__ tab) {
     const Inst& I = tab[blockIdx.x];
-    plan_body(I.G, I.P, I.G.ctrl->pos);
+    plan_body(I.G, I.P, gptr(I.G.ctrl)->pos);
 }
 
 // A single run's plan with its view as a kernel argument: the compiler may
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(kPlanT) void kb_plan(const Inst* __restrict__ tab) 
 // from memory they spill); the parameters still come from the run table.
 __global__ __launch_bounds__(kPlanT) void k_plan1(Dev G, const Params* __restrict__ pp) {
     const Params P = *pp;
-    plan_body(G, P, G.ctrl->pos);
+    plan_body(G, P, gptr(G.ctrl)->pos);
 }
 
 template <int PROG>

@@ -15,8 +15,8 @@ __global__ __launch_bounds__(256) void k_part_static(Dev G) {
     const uint32_t vbase = p << G.s;
     const uint32_t nv = min(G.q, G.V - vbase);
     uint32_t maxd = 0, nz = 0;
-    for (uint32_t v = tid; v < nv; v += 256) maxd = max(maxd, G.off[vbase + v + 1] - G.off[vbase + v]);
-    const uint32_t* row = G.bin_moff + (size_t)p * G.k;
+    for (uint32_t v = tid; v < nv; v += 256) maxd = max(maxd, gptr(G.off)[vbase + v + 1] - gptr(G.off)[vbase + v]);
+    const uint32_t* row = gptr(G.bin_moff) + (size_t)p * G.k;
     for (uint32_t q = tid; q < G.k; q += 256) nz += row[q + 1] > row[q];
     __shared__ uint32_t s_max[4], s_nz[4];
     for (int o = 32; o > 0; o >>= 1) {
@@ -34,44 +34,44 @@ __global__ __launch_bounds__(256) void k_part_static(Dev G) {
             m = max(m, s_max[w]);
             z += s_nz[w];
         }
-        const uint32_t Ep = G.part_E[p];
-        G.pfill[p] = (float)((double)z / (double)G.k);
-        G.pskew[p] = Ep ? (float)log((double)m * (double)nv / (double)Ep) : 0.f;
+        const uint32_t Ep = gptr(G.part_E)[p];
+        gptr(G.pfill)[p] = (float)((double)z / (double)G.k);
+        gptr(G.pskew)[p] = Ep ? (float)log((double)m * (double)nv / (double)Ep) : 0.f;
     }
 }
 
 // Sum of E_a over all partitions / |E| (every wave computes it).
 __device__ inline float active_edge_fraction(const Dev& G, uint32_t cur) {
     uint64_t s = 0;
-    for (uint32_t j = lane_id(); j < G.k; j += 64) s += G.fEa[cur][j];
+    for (uint32_t j = lane_id(); j < G.k; j += 64) s += gptr(G.fEa[cur])[j];
     s = wave_sum_u64(s);
     return G.E ? (float)((double)s / (double)G.E) : 0.f;
 }
 
 // Learned selection for the plan of iteration `it`: one lane per partition.
 __device__ __forceinline__ void select_body(const Dev& G, const Params& P, uint32_t it, uint32_t bid) {
-    if (G.ctrl->done) return;
+    if (gptr(G.ctrl)->done) return;
     const uint32_t cur = it & 1u;
     const float ea_frac = active_edge_fraction(G, cur);
     const uint32_t p = bid * 64 + lane_id();
     if (p >= G.k) return;
-    const uint32_t Va = G.fVa[cur][p];
+    const uint32_t Va = gptr(G.fVa[cur])[p];
     if (!Va) {
-        G.mode_l[p] = GPOP_MODE_NONE;
+        gptr(G.mode_l)[p] = GPOP_MODE_NONE;
         return;
     }
-    const uint32_t Ea = G.fEa[cur][p];
+    const uint32_t Ea = gptr(G.fEa[cur])[p];
     float f[GPOP_MLP_IN];
     partition_features(G, P, p, Va, Ea, it, ea_frac, f);
     float z;
     uint8_t md;
-    if (mlp_logit(G.mlp, f, &z)) {
+    if (mlp_logit(gptr(G.mlp), f, &z)) {
         md = z >= 0.f ? (uint8_t)GPOP_MODE_PC : (uint8_t)GPOP_MODE_SC;
     } else {
         md = analytical_mode(G, P, p, Va, Ea);
-        atomicAdd(&G.ctrl->mlp_fallback, 1u);
+        atomicAdd(&gptr(G.ctrl)->mlp_fallback, 1u);
     }
-    G.mode_l[p] = md;
+    gptr(G.mode_l)[p] = md;
 }
 
 // Batched: runs whose selector is not the learned one skip.
@@ -80,17 +80,17 @@ __global__ __launch_bounds__(64) void kb_select(const Inst* __restrict__ tab,
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
     if (I.P.selector != GPOP_SEL_LEARNED) return;
-    select_body(I.G, I.P, I.G.ctrl->pos, blockIdx.x - boff[i]);
+    select_body(I.G, I.P, gptr(I.G.ctrl)->pos, blockIdx.x - boff[i]);
 }
 
 __global__ __launch_bounds__(64) void k_features(Dev G, Params P, float* __restrict__ out) {
-    const uint32_t it = G.ctrl->pos;
+    const uint32_t it = gptr(G.ctrl)->pos;
     const uint32_t cur = it & 1u;
     const float ea_frac = active_edge_fraction(G, cur);
     const uint32_t p = blockIdx.x * 64 + lane_id();
     if (p >= G.k) return;
     float f[GPOP_MLP_IN];
-    partition_features(G, P, p, G.fVa[cur][p], G.fEa[cur][p], it, ea_frac, f);
+    partition_features(G, P, p, gptr(G.fVa[cur])[p], gptr(G.fEa[cur])[p], it, ea_frac, f);
     for (int i = 0; i < GPOP_MLP_IN; ++i) out[(size_t)p * GPOP_MLP_IN + i] = f[i];
 }
 

@@ -17,7 +17,7 @@ namespace gpop {
 __device__ __forceinline__ uint8_t analytical_mode(const Dev& G, const Params& P, uint32_t p,
                                                    uint32_t Va, uint32_t Ea) {
     typedef unsigned __int128 u128;
-    const uint64_t Ep = G.part_E[p], Mp = G.part_M[p];
+    const uint64_t Ep = gptr(G.part_E)[p], Mp = gptr(G.part_M)[p];
     const uint64_t si = P.s_i, sv = P.s_v;
     const uint64_t cost_pc = (Mp + Ep) * si + 2ull * Mp * sv + (uint64_t)G.k * si;
     const u128 lhs = (u128)cost_pc * Ep * P.ratio_den;
@@ -39,7 +39,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
 // ea_frac is the sum of E_a over all partitions divided by |E|.
 __device__ inline void partition_features(const Dev& G, const Params& P, uint32_t p, uint32_t Va,
                                           uint32_t Ea, uint32_t it, float ea_frac, float* f) {
-    const uint32_t Ep = G.part_E[p], Mp = G.part_M[p];
+    const uint32_t Ep = gptr(G.part_E)[p], Mp = gptr(G.part_M)[p];
     const uint32_t nv = min(G.q, G.V - (p << G.s));
     f[0] = log1pf((float)Va);
     f[1] = log1pf((float)Ea);
@@ -48,8 +48,8 @@ __device__ inline void partition_features(const Dev& G, const Params& P, uint32_
     f[4] = Ep ? (float)((double)Mp / (double)Ep) : 0.f;
     f[5] = (float)((double)Va / (double)nv);
     f[6] = Ep ? (float)((double)Ea / (double)Ep) : 0.f;
-    f[7] = G.pfill[p];
-    f[8] = G.pskew[p];
+    f[7] = gptr(G.pfill)[p];
+    f[8] = gptr(G.pskew)[p];
     f[9] = log1pf((float)it);
     f[10] = ea_frac;
     const double si = P.s_i, sv = P.s_v;
