@@ -102,10 +102,13 @@ typedef struct gpop_graph_desc {
 typedef struct gpop_options {
     uint32_t log2_part;   /* q = 2^log2_part vertices per partition, 8..15;
                              0 picks 14 (16384 vertices)                        */
-    uint32_t sc_task_log2;     /* log2 of active edges per source-centric task,
-                                  6..24; 0 picks max(1024, 4k)                  */
+    uint32_t sc_task_log2;     /* log2 of the largest source-centric task, in
+                                  work units (an active vertex and each of its
+                                  out-edges count one each), 6..24; 0 picks
+                                  max(1024, 4k). Iterations with little
+                                  source-centric work use smaller tasks       */
     uint32_t gather_task_ids;  /* ids per gather task (>= 256); 0 picks
-                                  max(2^19, E / 256). A partition whose bins
+                                  max(2^16, E / 1024). A partition whose bins
                                   hold more ids is gathered by several tasks
                                   (at most 64) and merged                      */
     uint32_t combine;          /* GPOP_COMBINE_LDS (0) or GPOP_COMBINE_ROUNDS   */

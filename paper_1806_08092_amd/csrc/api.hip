@@ -104,7 +104,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Task sizes of a graph: the largest source-centric task in work units (at
 // least 1024 and at least 4k, so the per-task count row stays small next to
 // the task; lighter iterations use smaller tasks) and ids per gather task
-// (about one task per CU for a dense iteration; heavier partitions are split
+// (about 1024 tasks over all bins, so that the workgroups that finish early
+// in a dense iteration pick up further tasks; heavier partitions are split
 // over several).
 struct Sizes {
     uint32_t s, sc_shift;
@@ -119,7 +120,7 @@ Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
     z.sc_shift = 10;
     while ((1ull << z.sc_shift) < 4 * z.k) ++z.sc_shift;
     if (o && o->sc_task_log2) z.sc_shift = o->sc_task_log2;
-    z.T = std::max<uint64_t>(1ull << 19, E / 256);
+    z.T = std::max<uint64_t>(1ull << 16, E / 1024);
     if (o && o->gather_task_ids) z.T = o->gather_task_ids;
     return z;
 }

@@ -432,6 +432,10 @@ hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st) {
 // vertices contribute the combine identity. Work is cut into static tasks of
 // at most kPcTask slots so hub partitions spread over many workgroups.
 // ---------------------------------------------------------------------------
+// Partition-centric workgroup: the partition's values sit in LDS (q words), so
+// two workgroups fit a CU; 16 waves each keep enough loads in flight.
+constexpr uint32_t kPcT = 1024;
+
 template <int PROG>
 __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uint32_t* __restrict__ state,
                                         uint32_t it, uint32_t task) {
@@ -449,17 +453,18 @@ __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uin
     const uint32_t nv = min(G.q, G.V - vbase);
     extern __shared__ uint32_t mv[];
     const uint32_t* __restrict__ bits = gptr(G.fbits[cur]) + (vbase >> 5);
-    for (uint32_t v = threadIdx.x; v < nv; v += 256)
+    for (uint32_t v = threadIdx.x; v < nv; v += kPcT)
         mv[v] = test_bit(bits, v) ? scatter_value<PROG>(G, state, vbase + v) : ident_of<PROG>();
     __syncthreads();
     const uint16_t* __restrict__ src = gptr(G.png_src);
     uint32_t* __restrict__ data = gptr(G.data);
-    // aligned middle in groups of 4 slots (8-byte source loads, 16-byte stores)
-    uint32_t a = t.y, b = t.z;
-    uint32_t a4 = min((a + 3u) & ~3u, b);
-    for (uint32_t i = a + threadIdx.x; i < a4; i += 256) data[i] = mv[src[i]];
-    uint32_t b4 = a4 + ((b - a4) & ~3u);
-    for (uint32_t i = a4 + 4u * threadIdx.x; i < b4; i += 1024) {
+    // aligned middle in groups of 4 slots (8-byte source loads, 16-byte
+    // stores), two groups per thread per step
+    const uint32_t a = t.y, b = t.z;
+    const uint32_t a4 = min((a + 3u) & ~3u, b);
+    for (uint32_t i = a + threadIdx.x; i < a4; i += kPcT) data[i] = mv[src[i]];
+    const uint32_t b4 = a4 + ((b - a4) & ~3u);
+    auto group = [&](uint32_t i) {
         const uint2 sv = *reinterpret_cast<const uint2*>(src + i);
         uint4 o;
         o.x = mv[sv.x & 0xFFFFu];
@@ -467,17 +472,34 @@ __device__ __forceinline__ void pc_body(const Dev& G, const Params& P, const uin
         o.z = mv[sv.y & 0xFFFFu];
         o.w = mv[sv.y >> 16];
         *reinterpret_cast<uint4*>(data + i) = o;
+    };
+    uint32_t i = a4 + 4u * threadIdx.x;
+    for (; i + 4u * kPcT < b4; i += 8u * kPcT) {
+        const uint2 s0 = *reinterpret_cast<const uint2*>(src + i);
+        const uint2 s1 = *reinterpret_cast<const uint2*>(src + i + 4u * kPcT);
+        uint4 o0, o1;
+        o0.x = mv[s0.x & 0xFFFFu];
+        o0.y = mv[s0.x >> 16];
+        o0.z = mv[s0.y & 0xFFFFu];
+        o0.w = mv[s0.y >> 16];
+        o1.x = mv[s1.x & 0xFFFFu];
+        o1.y = mv[s1.x >> 16];
+        o1.z = mv[s1.y & 0xFFFFu];
+        o1.w = mv[s1.y >> 16];
+        *reinterpret_cast<uint4*>(data + i) = o0;
+        *reinterpret_cast<uint4*>(data + i + 4u * kPcT) = o1;
     }
-    for (uint32_t i = b4 + threadIdx.x; i < b; i += 256) data[i] = mv[src[i]];
-    if (P.probe) {  // four waves' time, charged to the partition
+    if (i < b4) group(i);
+    for (uint32_t j = b4 + threadIdx.x; j < b; j += kPcT) data[j] = mv[src[j]];
+    if (P.probe) {  // every wave's time, charged to the partition
         __syncthreads();
         if (threadIdx.x == 0)
-            atomicAdd(gptr(G.probe) + 2 * G.k + p, 4ull * (unsigned long long)(wall_clock64() - t_beg));
+            atomicAdd(gptr(G.probe) + 2 * G.k + p, (unsigned long long)(kPcT / 64) * (wall_clock64() - t_beg));
     }
 }
 
 template <int PROG>
-__global__ __launch_bounds__(256) void kb_pc(const Inst* __restrict__ tab, const uint32_t* __restrict__ boff,
+__global__ __launch_bounds__(kPcT) void kb_pc(const Inst* __restrict__ tab, const uint32_t* __restrict__ boff,
                                              uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
@@ -768,7 +790,7 @@ static hipError_t launch_batch_sc_p(const BatchGrid& B, hipStream_t st) {
 template <int PROG>
 static hipError_t launch_batch_pc_p(const BatchGrid& B, hipStream_t st) {
     if (B.nb_pc)
-        hipLaunchKernelGGL(kb_pc<PROG>, dim3(B.nb_pc), dim3(256), (size_t)B.q_max * 4, st, B.tab, B.b_pc, B.n);
+        hipLaunchKernelGGL(kb_pc<PROG>, dim3(B.nb_pc), dim3(kPcT), (size_t)B.q_max * 4, st, B.tab, B.b_pc, B.n);
     return hipGetLastError();
 }
 
