@@ -37,10 +37,15 @@ def log(*a):
 def kernel_bytes(rec, next_va, q, k, weighted, sum_prog):
     """Algorithmic bytes of each kernel for one iteration record, with the
     element sizes the kernels use: 2-byte ids, 4-byte values and state,
-    1-byte weights, 4-byte CSR entries and offsets."""
+    1-byte weights, 4-byte CSR entries and offsets.
+
+    Gather and merge: a partition's stored values are read where a message
+    arrived (at most q per partition and at most one per id), written where
+    the filter keeps a vertex (min programs) or where an amount arrived (sum
+    programs); the frontier bitmap is written whole, the list, the edge
+    prefix and the degree read for the kept vertices."""
     s_id, s_v, s_w = 2, 4, (1 if weighted else 0)
     s_part = 8 if sum_prog else 4
-    state_in = 0 if sum_prog else 4 * q
     plan = 25 * k
     sc = (rec["sc_active_vertices"] * (2 + 4 + 8 + 4) + rec["sc_active_edges"] * (4 + s_w)
           + rec["sc_ids"] * (s_id + s_w) + rec["sc_msgs"] * s_v + rec["sc_parts"] * 8 * k)
@@ -49,10 +54,17 @@ def kernel_bytes(rec, next_va, q, k, weighted, sum_prog):
     whole = rec["gather_parts"]
     part = rec["split_tasks"]
     merged = rec["merged_parts"]
-    gather = ((rec["sc_ids"] + rec["pc_ids"]) * (s_id + s_w) + (rec["sc_msgs"] + rec["pc_msgs"]) * s_v
-              + whole * (24 * k + state_in + 4 * q + 4 * q + q / 8) + part * s_part * q
-              + next_va * (2 + 4))
-    merge = merged * (state_in + 4 * q + 4 * q + q / 8) + part * s_part * q
+    ids = rec["sc_ids"] + rec["pc_ids"]
+    touched = min(q * (whole + merged), ids)
+    # min programs: read where a message arrived, write the kept vertices;
+    # sum programs: write where an amount arrived, plus two offsets for the
+    # dangling check
+    state_rw = 12 * touched if sum_prog else 4 * touched + 4 * next_va
+    state_share = state_rw * (whole / (whole + merged) if whole + merged else 0.0)
+    gather = (ids * (s_id + s_w) + (rec["sc_msgs"] + rec["pc_msgs"]) * s_v
+              + whole * (24 * k + q / 8) + state_share + part * s_part * q
+              + next_va * (2 + 4 + 8))
+    merge = merged * (q / 8 + q / 8 + 16) + (state_rw - state_share) + part * s_part * q
     return {"plan": plan, "scatter_sc": sc, "scatter_pc": pc, "gather": gather, "merge": merge}
 
 
