@@ -92,11 +92,13 @@ __device__ __forceinline__ void reinit(const Dev& G, const Params& P, const uint
 // frontier.
 template <int PROG>
 __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, uint32_t* __restrict__ state,
-                                 uint32_t it, uint32_t cq, const uint32_t* st32,
-                                 const unsigned long long* acc, const uint8_t* carry,
+                                 uint32_t it, uint32_t cq, uint32_t* st32,
+                                 unsigned long long* acc, const uint8_t* carry,
                                  uint64_t* kscratch, GatherShared& sh, uint32_t ids_done,
                                  uint32_t task) {
     constexpr bool SUM = is_sum(PROG);
+    // 64-vertex groups per step of pass 1: their global loads are issued together
+    constexpr uint32_t U = 8;
     const uint32_t nxt = (it & 1u) ^ 1u;
     const uint32_t vbase = cq << G.s, Q = G.q;
     const uint32_t nv = min(Q, G.V - vbase);
@@ -105,48 +107,87 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
     const uint32_t* __restrict__ off = gptr(G.off);
     const uint32_t per = ((Q / kGW) + 63u) & ~63u;  // vertices per wave, multiple of 64
     const uint32_t wb = wave * per;
+    const uint32_t wend = min(wb + per, Q);
+    // pass 1 leaves the out-degree of each kept vertex in the LDS slot its
+    // value used (sum programs: the upper word of the accumulator)
+    uint32_t* degl = SUM ? reinterpret_cast<uint32_t*>(acc) : st32;
+    const uint32_t dsh = SUM ? 1u : 0u, dadd = SUM ? 1u : 0u;
     uint32_t cnt = 0, edges = 0;
     double my_d = 0.0;
-    for (uint32_t u0 = wb; u0 < wb + per && u0 < Q; u0 += 64) {
-        const uint32_t u = u0 + lane;
-        bool keep = false;
-        uint32_t deg = 0;
-        if (u < nv) {
-            const uint32_t v = vbase + u;
-            if constexpr (!SUM) {
-                // the on-chip copy holds the least message (identity: none)
-                const uint32_t m = st32[u];
-                bool hit = false;
-                if (m != kIdentMin) hit = m < state[v];
-                keep = hit;
-                if constexpr (has_carry(PROG)) keep = keep || carry[u];
-                if (hit) state[v] = m;
-            } else {
-                const unsigned long long a = acc[u];
-                if (a != 0ull) {  // received an amount, or was active before scatter
-                    const double y = (double)(a & ~kCarried) * kInvFix;
-                    float x;
+    for (uint32_t g0 = wb; g0 < wend; g0 += 64u * U) {
+        uint32_t mv[U], sv[U], o0[U], o1[U];
+        unsigned long long av[U];
+        float xv[U];
+        bool keep[U], need[U];
+#pragma unroll
+        for (uint32_t i = 0; i < U; ++i) {
+            const uint32_t u = g0 + 64u * i + lane;
+            const bool in = g0 + 64u * i < wend && u < nv;
+            if constexpr (!SUM) mv[i] = in ? st32[u] : kIdentMin;  // least message (identity: none)
+            else av[i] = in ? acc[u] : 0ull;  // an amount arrived, or active before scatter
+        }
+        if constexpr (!SUM) {
+#pragma unroll
+            for (uint32_t i = 0; i < U; ++i)
+                sv[i] = mv[i] != kIdentMin ? state[vbase + g0 + 64u * i + lane] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < U; ++i) {
+                const uint32_t u = g0 + 64u * i + lane;
+                const bool hit = mv[i] != kIdentMin && mv[i] < sv[i];
+                keep[i] = hit;
+                if constexpr (has_carry(PROG)) {
+                    const bool in = g0 + 64u * i < wend && u < nv;
+                    keep[i] = keep[i] || (in && carry[u]);
+                }
+                if (hit) state[vbase + u] = mv[i];
+                need[i] = keep[i];
+            }
+        } else {
+#pragma unroll
+            for (uint32_t i = 0; i < U; ++i) {
+                const uint32_t v = vbase + g0 + 64u * i + lane;
+                keep[i] = false;
+                need[i] = av[i] != 0ull;
+                xv[i] = 0.f;
+                if (need[i]) {
+                    const double y = (double)(av[i] & ~kCarried) * kInvFix;
                     if constexpr (PROG == P_PR) {
                         const double d = (double)P.damping;
-                        x = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
-                        keep = true;
+                        xv[i] = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
+                        keep[i] = true;
                     } else {
-                        const double a = (double)P.alpha;
-                        double xd = (1.0 - a) * y;
-                        if (v == P.root) xd += a + (1.0 - a) * dang;
-                        x = (float)xd;
-                        keep = x > 0.0f;
+                        const double al = (double)P.alpha;
+                        double xd = (1.0 - al) * y;
+                        if (v == P.root) xd += al + (1.0 - al) * dang;
+                        xv[i] = (float)xd;
+                        keep[i] = xv[i] > 0.0f;
                     }
-                    state[v] = __float_as_uint(x);
-                    if (off[v + 1] == off[v]) my_d += (double)x;
+                    state[v] = __float_as_uint(xv[i]);
                 }
             }
-            if (keep) deg = off[v + 1] - off[v];
         }
-        const uint64_t km = ballot(keep);
-        if (lane == 0) kscratch[u0 >> 6] = km;
-        cnt += popc64(km);
-        edges += deg;
+        // out-degrees: of kept vertices (frontier edges), and for sum programs
+        // of every vertex that got a value (dangling mass)
+#pragma unroll
+        for (uint32_t i = 0; i < U; ++i) {
+            const uint32_t v = vbase + g0 + 64u * i + lane;
+            o0[i] = need[i] ? off[v] : 0u;
+            o1[i] = need[i] ? off[v + 1] : 0u;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < U; ++i) {
+            if (g0 + 64u * i >= wend) break;  // uniform
+            const uint32_t u = g0 + 64u * i + lane;
+            const uint32_t deg = keep[i] ? o1[i] - o0[i] : 0u;
+            if constexpr (SUM) {
+                if (need[i] && o1[i] == o0[i]) my_d += (double)xv[i];
+            }
+            if (u < nv) degl[(u << dsh) + dadd] = deg;
+            const uint64_t km = ballot(keep[i]);
+            if (lane == 0) kscratch[(g0 >> 6) + i] = km;
+            cnt += popc64(km);
+            edges += deg;
+        }
     }
     edges = wave_sum_u32(edges);
     if (lane == 0) {
@@ -167,7 +208,6 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
     uint32_t* __restrict__ npre = gptr(G.fpre[nxt]) + vbase;
     uint32_t* __restrict__ nbits = gptr(G.fbits[nxt]) + (vbase >> 5);
     // the wave's bitmap words, one per lane
-    const uint32_t wend = min(wb + per, Q);
     for (uint32_t w = (wb >> 5) + lane; w < (wend >> 5); w += 64) {
         const uint64_t km = kscratch[w >> 1];
         nbits[w] = (w & 1u) ? (uint32_t)(km >> 32) : (uint32_t)km;
@@ -177,7 +217,7 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
         const uint64_t km = kscratch[u0 >> 6];
         if (km == 0) continue;  // nothing kept in these 64 vertices
         const bool keep = (km >> lane) & 1u;
-        const uint32_t deg = keep ? off[vbase + u + 1] - off[vbase + u] : 0u;
+        const uint32_t deg = keep ? degl[(u << dsh) + dadd] : 0u;
         const uint32_t dincl = wave_incl_scan(deg);
         if (keep) {
             const uint32_t at = pos + popc_lt(km);
@@ -251,12 +291,13 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     // the two id / weight / chunk arrays a piece may come from, as uniform
     // values (a per-lane choice between two fields of the view would
     // otherwise become a per-lane load of the pointer itself)
-    const uint16_t* __restrict__ ids_sc = uniform_ptr(gptr(G.sc_ids));
-    const uint16_t* __restrict__ ids_pc = uniform_ptr(gptr(G.png_ids));
-    const uint8_t* __restrict__ w_sc = uniform_ptr(gptr(G.sc_w));
-    const uint8_t* __restrict__ w_pc = uniform_ptr(gptr(G.png_w));
-    const uint32_t* __restrict__ ch_sc = uniform_ptr(gptr(G.sc_chunk));
-    const uint32_t* __restrict__ ch_pc = uniform_ptr(gptr(G.png_chunk));
+    const uint16_t* __restrict__ ids_sc = gptr(G.sc_ids);
+    const uint16_t* __restrict__ ids_pc = gptr(G.png_ids);
+    const uint8_t* __restrict__ w_sc = gptr(G.sc_w);
+    const uint8_t* __restrict__ w_pc = gptr(G.png_w);
+    const uint32_t* __restrict__ ch_sc = gptr(G.sc_chunk);
+    const uint32_t* __restrict__ ch_pc = gptr(G.png_chunk);
+    const uint32_t* __restrict__ data = gptr(G.data);
     uint32_t s0 = TB.x, s1 = TB.y;
     const uint32_t slot = TB.z;
     bool split = nt > 1;
@@ -463,6 +504,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
             }
             // phase 2: message indices and value loads
             uint32_t vmaskall = 0;
+            bool bad = false;
 #pragma unroll
             for (uint32_t pi = 0; pi < PPW; ++pi) {
                 uint32_t vmask = 0, fmask = 0, fc = 0;
@@ -481,32 +523,46 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     midx += (fmask >> j) & 1u;
+                    // an id outside its bin's messages or partition marks an
+                    // inconsistent bin: it is dropped (never read or written
+                    // out of range) and reported once per round
                     const bool ok = (vmask >> j) & 1u;
-                    if (ok && (midx >= bmcnt[pi] || dst[4 * pi + j] >= nv)) {
-                        gptr(G.ctrl)->bug = 1;  // inconsistent bin: never read or write out of range
-                        vmask &= ~(1u << j);
-                    }
-                    val[4 * pi + j] = ((vmask >> j) & 1u) ? gptr(G.data)[bmoff[pi] + midx] : IDENT;
+                    const bool oob = midx >= bmcnt[pi] || dst[4 * pi + j] >= nv;
+                    bad = bad || (ok && oob);
+                    const bool use = ok && !oob;
+                    vmask &= ~((uint32_t)(ok && oob) << j);
+                    // unused lanes read the bin's first message (in range:
+                    // a bin with ids has messages), so the load is unconditional
+                    val[4 * pi + j] = data[bmoff[pi] + (use ? midx : 0u)];
                 }
                 vmaskall |= vmask << (4 * pi);
             }
-            // phase 3: drop identity messages, apply weights, combine
+            // phase 3: drop identity messages, apply weights, combine. The LDS
+            // combine is unconditional: a lane with nothing to add applies the
+            // identity (min with the identity, add of 0, both no-ops) to LDS
+            // word `lane`, which spreads such lanes over the banks.
             unsigned long long fx[(SUM && ROUNDS) ? 4 * PPW : 1];
 #pragma unroll
             for (uint32_t j = 0; j < 4 * PPW; ++j) {
-                uint32_t x = val[j];
-                if (((vmaskall >> j) & 1u) && x != IDENT) {
-                    if constexpr (is_weighted(PROG)) x = sat_add(x, (wts[j / 4] >> (8 * (j % 4))) & 0xFFu);
-                    val[j] = x;
-                    if constexpr (!ROUNDS) {
-                        if constexpr (SUM) atomicAdd(acc + dst[j], __double2ull_rn((double)__uint_as_float(x) * kFix));
-                        else atomicMin(st32 + dst[j], x);
-                    } else {
-                        if constexpr (SUM) fx[j] = __double2ull_rn((double)__uint_as_float(x) * kFix);
-                        pend |= 1u << j;
-                    }
-                    ++my_ids;
+                uint32_t x = ((vmaskall >> j) & 1u) ? val[j] : IDENT;
+                const bool use = x != IDENT;
+                if constexpr (is_weighted(PROG)) x = use ? sat_add(x, (wts[j / 4] >> (8 * (j % 4))) & 0xFFu) : IDENT;
+                val[j] = x;
+                my_ids += use ? 1u : 0u;
+                if constexpr (!ROUNDS) {
+                    const uint32_t d = use ? dst[j] : lane;
+                    if constexpr (SUM)
+                        atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(x) * kFix) : 0ull);
+                    else
+                        atomicMin(st32 + d, x);
+                } else if (use) {
+                    if constexpr (SUM) fx[j] = __double2ull_rn((double)__uint_as_float(x) * kFix);
+                    pend |= 1u << j;
                 }
+            }
+            if (ballot(bad)) {
+                if (lane == 0) gptr(G.ctrl)->bug = 1;
+                bad = false;
             }
             if constexpr (ROUNDS && !SUM) {
                 // write-verify rounds for the min combine

@@ -192,15 +192,6 @@ __device__ __forceinline__ T* gptr(T* p) {
     return (T*)(GlobalT*)(((uint64_t)hi << 32) | lo);
 }
 
-template <class T>
-__device__ __forceinline__ T* uniform_ptr(T* p) {
-    const uint64_t u = reinterpret_cast<uint64_t>(p);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    typedef __attribute__((address_space(1))) T GlobalT;
-    return (T*)(GlobalT*)(((uint64_t)hi << 32) | lo);
-}
-
 // Batched launches: instance i owns blocks [boff[i], boff[i+1]) of the grid.
 __device__ __forceinline__ uint32_t batch_find(const uint32_t* __restrict__ boff, uint32_t n, uint32_t b) {
     uint32_t lo = 0, hi = n;
