@@ -474,12 +474,12 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
             bcur = lo;
         }
         const uint32_t nrounds = (per_w + PPW - 1) / PPW;
-        for (uint32_t r = 0; r < nrounds; ++r) {
-            uint32_t dst[4 * PPW], val[4 * PPW];
-            uint32_t pend = 0;
-            uint64_t raw[PPW];
-            uint32_t wts[PPW], lo_x[PPW], hi_x[PPW], x0[PPW], mb[PPW], bmoff[PPW], bmcnt[PPW];
-            // phase 1: piece metadata, id / weight / chunk-base loads
+        // Phase 1 of a round (piece metadata, id / weight / chunk-base loads)
+        // is issued one round ahead, so that those loads are in flight while
+        // the wave decodes and combines the current round.
+        uint64_t n_raw[PPW];
+        uint32_t n_wts[PPW], n_lo[PPW], n_hi[PPW], n_x0[PPW], n_mb[PPW], n_moff[PPW], n_mcnt[PPW];
+        auto fetch = [&](uint32_t r) {
 #pragma unroll
             for (uint32_t pi = 0; pi < PPW; ++pi) {
                 const uint32_t pid = pw0 + r * PPW + pi;
@@ -488,20 +488,39 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                     while (pid >= bl_scan[bcur + 1]) ++bcur;
                 const uint32_t b = bcur;
                 const uint32_t bioff = bl_ioff[b], bicnt = bl_icnt[b], bmo = bl_moff[b];
-                bmcnt[pi] = bl_mcnt[b];
+                n_mcnt[pi] = bl_mcnt[b];
                 const bool sc = bmo & 0x80000000u;
-                bmoff[pi] = bmo & 0x7FFFFFFFu;
+                n_moff[pi] = bmo & 0x7FFFFFFFu;
                 const uint32_t c = bioff / kChunk + bl_jlo[b] + (pid - bl_scan[b]);
-                lo_x[pi] = max(bioff, c * kChunk);
-                hi_x[pi] = live ? min(bioff + bicnt, c * kChunk + kChunk) : 0u;
-                x0[pi] = c * kChunk + lane * 4u;
-                const bool any4 = x0[pi] + 3u >= lo_x[pi] && x0[pi] < hi_x[pi];
-                raw[pi] = any4 ? *reinterpret_cast<const uint64_t*>((sc ? ids_sc : ids_pc) + x0[pi]) : 0ull;
-                wts[pi] = 0;
+                n_lo[pi] = max(bioff, c * kChunk);
+                n_hi[pi] = live ? min(bioff + bicnt, c * kChunk + kChunk) : 0u;
+                n_x0[pi] = c * kChunk + lane * 4u;
+                const bool any4 = n_x0[pi] + 3u >= n_lo[pi] && n_x0[pi] < n_hi[pi];
+                n_raw[pi] = any4 ? *reinterpret_cast<const uint64_t*>((sc ? ids_sc : ids_pc) + n_x0[pi]) : 0ull;
+                n_wts[pi] = 0;
                 if constexpr (is_weighted(PROG))
-                    wts[pi] = any4 ? *reinterpret_cast<const uint32_t*>((sc ? w_sc : w_pc) + x0[pi]) : 0u;
-                mb[pi] = (live && lo_x[pi] != bioff) ? (sc ? ch_sc : ch_pc)[c] : 0u;
+                    n_wts[pi] = any4 ? *reinterpret_cast<const uint32_t*>((sc ? w_sc : w_pc) + n_x0[pi]) : 0u;
+                n_mb[pi] = (live && n_lo[pi] != bioff) ? (sc ? ch_sc : ch_pc)[c] : 0u;
             }
+        };
+        if (nrounds) fetch(0);
+        for (uint32_t r = 0; r < nrounds; ++r) {
+            uint32_t dst[4 * PPW], val[4 * PPW];
+            uint32_t pend = 0;
+            uint64_t raw[PPW];
+            uint32_t wts[PPW], lo_x[PPW], hi_x[PPW], x0[PPW], mb[PPW], bmoff[PPW], bmcnt[PPW];
+#pragma unroll
+            for (uint32_t pi = 0; pi < PPW; ++pi) {
+                raw[pi] = n_raw[pi];
+                wts[pi] = n_wts[pi];
+                lo_x[pi] = n_lo[pi];
+                hi_x[pi] = n_hi[pi];
+                x0[pi] = n_x0[pi];
+                mb[pi] = n_mb[pi];
+                bmoff[pi] = n_moff[pi];
+                bmcnt[pi] = n_mcnt[pi];
+            }
+            if (r + 1 < nrounds) fetch(r + 1);
             // phase 2: message indices and value loads
             uint32_t vmaskall = 0;
             bool bad = false;
