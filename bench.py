@@ -265,6 +265,7 @@ def selector_eval(args):
            "best_us": float(np.minimum(data.t_sc, data.t_pc).sum()),
            "learned_us": learned.choice_cost(z >= 0, data),
            "eq1_ratio2_us": learned.choice_cost(learned.analytical_choice(data, 2.0), data),
+           "eq1_default16_us": learned.choice_cost(learned.analytical_choice(data, 16.0), data),
            "eq1_fitted_us": learned.choice_cost(learned.analytical_choice(data, ratio), data),
            "fitted_ratio": ratio}
     log("trained on %d rows in %.1f s: %s" % (len(data), train_s, fit))
@@ -282,8 +283,8 @@ def selector_eval(args):
                    + [("cc", 0)]))
     log("evaluation graphs generated in %.1f s" % (time.perf_counter() - t))
     # the learned selector falls back to Eq. 1 at the fitted ratio
-    selectors = [("eq1_ratio2", "analytical", 2.0), ("eq1_fitted", "analytical", ratio),
-                 ("learned", "learned", ratio)]
+    selectors = [("eq1_ratio2", "analytical", 2.0), ("eq1_default", "analytical", 16.0),
+                 ("eq1_fitted", "analytical", ratio), ("learned", "learned", ratio)]
     res = {name: {"ms": 0.0, "edges": 0, "per_program_ms": {}, "decisions": 0, "pc_decisions": 0,
                   "fallbacks": 0} for name, _, _ in selectors}
     for gname, g, runs in graphs:
@@ -314,6 +315,7 @@ def selector_eval(args):
                    "log2_part": {"bfs_cc": lp_of("bfs"), "pagerank": lp_of("pagerank")},
                    "train_graphs": args.train_graphs, "train_steps": args.train_steps},
         "selector_speedup": {"learned_vs_eq1_ratio2": res["eq1_ratio2"]["ms"] / res["learned"]["ms"],
+                             "learned_vs_eq1_default16": res["eq1_default"]["ms"] / res["learned"]["ms"],
                              "learned_vs_eq1_fitted": res["eq1_fitted"]["ms"] / res["learned"]["ms"]},
         "selectors": res,
         "training": fit,
@@ -444,7 +446,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bfs_cc_rmat22")
     ap.add_argument("--selector", default="analytical")
-    ap.add_argument("--bw-ratio", type=float, default=2.0)
+    ap.add_argument("--bw-ratio", type=float, default=16.0)
     ap.add_argument("--log2-part", type=int, default=0)
     ap.add_argument("--gather-task-ids", type=int, default=0,
                     help="ids per gather task (0: library default)")

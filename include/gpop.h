@@ -201,7 +201,10 @@ int gpop_set_frontier(struct gpop_graph* g, const uint32_t* d_vertices, uint32_t
 int gpop_set_frontier_all(struct gpop_graph* g, void* stream);
 
 /* Mode selection per partition (performance-modelling section). bw_ratio is
- * BW_PC / BW_SC (the paper's default is 2). s_i / s_v are the index and value
+ * BW_PC / BW_SC. The paper's figure for its CPU is 2; a new graph starts with
+ * the analytical model at 16, the ratio that is fastest on MI355X across the
+ * BFS/CC and SSSP workloads (source-centric bins are written in partial cache
+ * lines, partition-centric values in full ones). s_i / s_v are the index and value
  * sizes in bytes used by the model (the paper uses 4 and 4). For
  * GPOP_SEL_LEARNED, d_mlp is a device gpop_mlp_model (gpop_mlp.h); the call
  * copies it into the graph's workspace (synchronously), so the caller may

@@ -270,7 +270,7 @@ class Graph:
     def set_frontier_all(self, stream=None):
         _check(lib().gpop_set_frontier_all(self.h, _stream(stream)))
 
-    def set_selector(self, kind="analytical", bw_ratio: float = 2.0, s_i: int = 4, s_v: int = 4,
+    def set_selector(self, kind="analytical", bw_ratio: float = 16.0, s_i: int = 4, s_v: int = 4,
                      mlp=None):
         kind = SELECTORS[kind] if isinstance(kind, str) else int(kind)
         _check(lib().gpop_set_selector(self.h, kind, bw_ratio, s_i, s_v, _ptr(mlp)))

@@ -578,7 +578,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     g->P.selector = GPOP_SEL_ANALYTICAL;
     g->P.s_i = 4;
     g->P.s_v = 4;
-    g->P.ratio_num = 2048;
+    g->P.ratio_num = 16 * 1024;  // BW_PC / BW_SC = 16 (measured on this GPU; the paper's CPU figure is 2)
     g->P.ratio_den = 1024;
     g->d_tab = d_tab;
     BatchGrid& B = g->grid;

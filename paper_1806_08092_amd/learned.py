@@ -92,7 +92,7 @@ def choice_cost(pick_pc: np.ndarray, data: Samples) -> float:
     return float(np.where(pick_pc, data.t_pc, data.t_sc).sum())
 
 
-def analytical_choice(data: Samples, bw_ratio: float = 2.0) -> np.ndarray:
+def analytical_choice(data: Samples, bw_ratio: float = 16.0) -> np.ndarray:
     """Eq. 1's choice for each row from the last feature, which is
     log(cost_PC / cost_SC) (PC iff cost_PC <= ratio cost_SC)."""
     return data.x[:, 11].astype(np.float64) <= math.log(bw_ratio)

@@ -10,7 +10,7 @@ import graphgen as gg
 import oracle
 from oracle import gpop_ref
 
-from gpu_util import make_graph, pr_ok, run_program
+from gpu_util import make_graph, pr_ok, run_program, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -162,6 +162,34 @@ def test_iteration_stats_match_model():
         for p in np.unique(act // q):
             a = act[act // q == p]
             m = gpop_ref.choose_mode(png.E[p], png.M[p], len(a), int(deg[a].sum()), png.k)
+            nsc += m == "SC"
+            npc += m == "PC"
+        assert (rec["sc_parts"], rec["pc_parts"]) == (nsc, npc), (it, rec)
+
+
+def test_default_selector_uses_ratio_16():
+    """A new graph selects by Eq. 1 with BW_PC / BW_SC = 16 until
+    gpop_set_selector changes it."""
+    from fractions import Fraction
+    torch = torch_cuda()
+    name, g, lp, _ = get_zoo()[8]
+    G, _ = make_graph(g, lp)
+    root = roots_of(g, 1)[0]
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    G.state_init("bfs", st, root=root)
+    G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+    G.run()
+    lv = oracle.bfs_levels(g, root)
+    assert np.array_equal(st.cpu().numpy().view(np.uint32), lv)
+    q = 1 << lp
+    png = gpop_ref.build_png(g, q)
+    deg = g.degrees()
+    for it, rec in enumerate(G.iter_stats()):
+        act = np.flatnonzero(lv == it)
+        nsc = npc = 0
+        for p in np.unique(act // q):
+            a = act[act // q == p]
+            m = gpop_ref.choose_mode(png.E[p], png.M[p], len(a), int(deg[a].sum()), png.k, Fraction(16))
             nsc += m == "SC"
             npc += m == "PC"
         assert (rec["sc_parts"], rec["pc_parts"]) == (nsc, npc), (it, rec)

@@ -180,7 +180,7 @@ def test_learned_modes_follow_the_network_and_results_are_unchanged():
     mlp = gp.Mlp()
     mlp.init(torch.from_numpy(gg.mlp_init_params(99)).cuda(), torch.from_numpy(F.astype(np.float32)).cuda())
     _, _, mean, inv, w = _model_from_device(mlp)
-    G.set_selector("learned", mlp=mlp.model)
+    G.set_selector("learned", 2.0, mlp=mlp.model)  # Eq. 1 fallback at the model's ratio
     state, modes = _bfs_with_modes(G, g, root, torch)
     assert np.array_equal(state, lv)
     assert len(modes) == depth + 1
