@@ -19,7 +19,11 @@ from . import MLP_IN, Mlp
 @dataclass
 class Samples:
     """Per-(iteration, active partition) training rows: raw features and the
-    measured scatter time of the partition in each mode (microseconds)."""
+    cost of the partition's iteration in each mode (microseconds): its
+    measured scatter time plus, when collected with gather costs, the ids the
+    mode sends to gather times that iteration's measured gather time per id
+    (source-centric mode sends one id per active out-edge, partition-centric
+    mode every static id of the partition)."""
     x: np.ndarray        # n x 12 float32
     t_sc: np.ndarray     # n float32
     t_pc: np.ndarray     # n float32
@@ -37,24 +41,43 @@ class Samples:
         return self.x.shape[0]
 
 
-def collect(G, max_iter: int = 1 << 20, stream=None) -> Samples:
+def collect(G, max_iter: int = 1 << 20, stream=None, gather_cost: bool = True) -> Samples:
     """Runs the program bound to G (state and frontier already set) to the
-    end, probing both scatter modes before every iteration."""
+    end, probing both scatter modes before every iteration. With gather_cost
+    the iterations run with profiling on, and each row's mode costs include
+    the modelled gather time of the ids the mode sends."""
     xs, tsc, tpc, its, tot_sc, tot_pc = [], [], [], [], [], []
-    for it in range(max_iter):
-        if G.frontier_size(stream) == 0:
-            break
-        f = G.features(stream).cpu().numpy()
-        a, ta = G.probe_scatter("sc", stream)
-        b, tb = G.probe_scatter("pc", stream)
-        act = f[:, 0] > 0          # log1p(V_a) > 0: the partition scatters
-        xs.append(f[act])
-        tsc.append(a[act])
-        tpc.append(b[act])
-        its.append(np.full(int(act.sum()), it, np.int32))
-        tot_sc.append(ta)
-        tot_pc.append(tb)
-        G.iterate(stream)
+    if gather_cost:
+        G.profile_enable(True)
+    try:
+        for it in range(max_iter):
+            if G.frontier_size(stream) == 0:
+                break
+            f = G.features(stream).cpu().numpy()
+            a, ta = G.probe_scatter("sc", stream)
+            b, tb = G.probe_scatter("pc", stream)
+            act = f[:, 0] > 0          # log1p(V_a) > 0: the partition scatters
+            a = a[act].astype(np.float64)
+            b = b[act].astype(np.float64)
+            before = G.profile_read(stream) if gather_cost else None
+            G.iterate(stream)
+            if gather_cost:
+                after = G.profile_read(stream)
+                g_ms = sum(after[k][0] - before[k][0] for k in ("gather", "merge"))
+                rec = G.iter_stats(stream)[-1]
+                ids = rec["sc_ids"] + rec["pc_ids"]
+                per_id = g_ms * 1e3 / ids if ids else 0.0
+                a = a + per_id * np.expm1(f[act, 1].astype(np.float64))   # E_a ids
+                b = b + per_id * np.expm1(f[act, 2].astype(np.float64))   # E^p ids
+            xs.append(f[act])
+            tsc.append(a.astype(np.float32))
+            tpc.append(b.astype(np.float32))
+            its.append(np.full(int(act.sum()), it, np.int32))
+            tot_sc.append(ta)
+            tot_pc.append(tb)
+    finally:
+        if gather_cost:
+            G.profile_enable(False)
     if not xs:
         return Samples(np.zeros((0, MLP_IN), np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32),
                        np.zeros(0, np.int32), [], [])
