@@ -218,7 +218,8 @@ def _time_runs(G, st, runs, reps, deg, n, m):
 def selector_eval(args):
     """Trains the learned selector on probe timings of BFS, CC and PageRank
     over symmetrised RMAT graphs of scales 18-23 (varied a, b, c and edge
-    factor), then times BFS from 8 sources + CC on the symmetrised RMAT-25
+    factor; BFS and CC on the larger ones also with 2048 partitions), then
+    times BFS from 8 sources + CC on the symmetrised RMAT-25
     graph and PageRank on the directed one under Eq. 1 at the paper's ratio,
     Eq. 1 at the ratio fitted to the training timings, and the network."""
     import numpy as np
@@ -238,8 +239,11 @@ def selector_eval(args):
         off, cols, w = gp.upload_csr(g)
         st = torch.empty(g.n, dtype=torch.int32, device="cuda")
         srcs = [int(x) for x in gg.pick_sources(g.offsets, gg.SOURCE_SEED + i, 2)]
-        for prog, root in [("bfs", srcs[0]), ("bfs", srcs[-1]), ("cc", 0), ("pagerank", 0)]:
-            G = gp.Graph(off, cols, w, log2_part=lp_of(prog))
+        # the larger graphs also run BFS and CC with 2^(scale-11)-vertex
+        # partitions, so that the rows cover k = 2048 partitions as well
+        extra = [("bfs", srcs[0], scale - 11), ("cc", 0, scale - 11)] if scale >= 21 else []
+        for prog, root, lp in [("bfs", srcs[0], 0), ("bfs", srcs[-1], 0), ("cc", 0, 0), ("pagerank", 0, 0)] + extra:
+            G = gp.Graph(off, cols, w, log2_part=lp or lp_of(prog))
             G.state_init(prog, st, root=root)
             if prog in ("cc", "pagerank"):
                 G.set_frontier_all()
