@@ -234,24 +234,47 @@ __device__ __forceinline__ uint32_t last_lane(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
+// Wave sums: the DPP inclusive scan of wave_incl_scan, then lane 63's value
+// read into a scalar register (the same in every lane). 64-bit values move
+// through DPP as two 32-bit halves with the same control. The tree is the
+// same on every call, so floating-point sums are reproducible bit for bit.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROWS, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
 }
-
+__device__ __forceinline__ uint64_t lane63_u64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) { return last_lane(wave_incl_scan(x)); }
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
+    x += dpp_u64<0x111, 0xF>(x);  // row_shr:1
+    x += dpp_u64<0x112, 0xF>(x);  // row_shr:2
+    x += dpp_u64<0x114, 0xF>(x);  // row_shr:4
+    x += dpp_u64<0x118, 0xF>(x);  // row_shr:8
+    x += dpp_u64<0x142, 0xA>(x);  // row_bcast:15
+    x += dpp_u64<0x143, 0xC>(x);  // row_bcast:31
+    return lane63_u64(x);
 }
-
-// Butterfly sum: the same fixed tree on every call, so results are
-// reproducible bit for bit.
+__device__ __forceinline__ double f64_dpp_add(double y, uint64_t b, int step) {
+    uint64_t t = 0;
+    switch (step) {
+        case 0: t = dpp_u64<0x111, 0xF>(b); break;
+        case 1: t = dpp_u64<0x112, 0xF>(b); break;
+        case 2: t = dpp_u64<0x114, 0xF>(b); break;
+        case 3: t = dpp_u64<0x118, 0xF>(b); break;
+        case 4: t = dpp_u64<0x142, 0xA>(b); break;
+        default: t = dpp_u64<0x143, 0xC>(b); break;
+    }
+    return y + __longlong_as_double((long long)t);
+}
 __device__ __forceinline__ double wave_sum_f64(double x) {
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
+    for (int step = 0; step < 6; ++step) x = f64_dpp_add(x, (uint64_t)__double_as_longlong(x), step);
+    return __longlong_as_double((long long)lane63_u64((uint64_t)__double_as_longlong(x)));
 }
 
 __device__ __forceinline__ bool test_bit(const uint32_t* bits, uint32_t i) {
