@@ -9,6 +9,10 @@ namespace gpop {
 // the other streams bins.
 constexpr uint32_t kGT = 512;
 constexpr uint32_t kGW = kGT / 64;
+// Bins of at most this many ids are gathered one per lane (a task covering
+// whole bins only): a sparse frontier spreads few ids over many bins, and a
+// 256-id piece per such bin would leave most of its lanes idle.
+constexpr uint32_t kSmallBin = 8;
 
 // Programs whose initFunc keeps vertices active need a per-vertex carry flag
 // (the PageRank family keeps it in the top bit of its accumulator).
@@ -52,7 +56,7 @@ __device__ __forceinline__ uint32_t pieces_of(uint32_t ioff, uint32_t icnt) {
 }
 
 struct GatherShared {
-    uint32_t wc[kGW], wp[kGW], ws[kGW];
+    uint32_t wc[kGW], wp[kGW], ws[kGW], wsm[kGW];
     uint64_t r64[kGW];
     double rd[kGW];
 };
@@ -415,6 +419,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
             }
         }
         const uint32_t dp = pieces_of(ioff, icnt);
+        // a task that covers whole bins takes a bin of at most kSmallBin ids
+        // with one lane (below) instead of as pieces of 256-id chunks
+        const bool small = !ROUNDS && !split && icnt > 0 && icnt <= kSmallBin;
         // static piece prefix of this bin inside the task's enumeration
         const uint32_t sincl = wave_incl_scan(sp);
         if (lane == 63) sh.ws[wave] = sincl;
@@ -429,24 +436,35 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         // pieces of this bin that fall in [s0, s1)
         const uint32_t jlo = s0 > SP ? s0 - SP : 0u;
         const uint32_t jhi = min(dp, s1 > SP ? s1 - SP : 0u);
-        const uint32_t npieces = jhi > jlo ? jhi - jlo : 0u;
+        const uint32_t npieces = (jhi > jlo && !small) ? jhi - jlo : 0u;
         const bool nz = npieces > 0;
         const uint64_t bm = ballot(nz);
+        const uint64_t sm = ballot(small);
         const uint32_t pincl = wave_incl_scan(npieces);
         if (lane == 63) {
             sh.wc[wave] = popc64(bm);
             sh.wp[wave] = pincl;
+            sh.wsm[wave] = popc64(sm);
         }
         __syncthreads();
-        uint32_t boff = 0, poff = 0, nb = 0, npt = 0;
+        uint32_t boff = 0, poff = 0, nb = 0, npt = 0, soff = 0, ns = 0;
         for (uint32_t w = 0; w < kGW; ++w) {
-            const uint32_t c = sh.wc[w], pc = sh.wp[w];
+            const uint32_t c = sh.wc[w], pc = sh.wp[w], sc = sh.wsm[w];
             if (w < wave) {
                 boff += c;
                 poff += pc;
+                soff += sc;
             }
             nb += c;
             npt += pc;
+            ns += sc;
+        }
+        if (small) {  // small bins from the top of the bin arrays (nb + ns <= kGT)
+            const uint32_t b = kGT - 1u - (soff + popc_lt(sm));
+            bl_ioff[b] = ioff;
+            bl_icnt[b] = icnt;
+            bl_moff[b] = moff | (md == GPOP_MODE_SC ? 0x80000000u : 0u);
+            bl_mcnt[b] = mcnt;
         }
         if (nz) {
             const uint32_t b = boff + popc_lt(bm);
@@ -679,6 +697,51 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                         if (!__syncthreads_or(apend != 0)) break;
                     }
                 }
+            }
+        }
+        // small bins, one per thread: the bin's ids, message indices counted
+        // from its first message (no chunk table), values, combine
+        if constexpr (!ROUNDS) {
+            for (uint32_t sb = tid; sb < ns; sb += kGT) {
+                const uint32_t b = kGT - 1u - sb;
+                const uint32_t bio = bl_ioff[b], bic = bl_icnt[b], bmo = bl_moff[b], bmc = bl_mcnt[b];
+                const bool sc = bmo & 0x80000000u;
+                const uint16_t* __restrict__ sid = (sc ? ids_sc : ids_pc) + bio;
+                const uint8_t* __restrict__ swt = (sc ? w_sc : w_pc) + bio;
+                const uint32_t* __restrict__ sval = data + (bmo & 0x7FFFFFFFu);
+                uint32_t idv[kSmallBin], mi[kSmallBin], vv[kSmallBin], wv[kSmallBin];
+#pragma unroll
+                for (uint32_t i = 0; i < kSmallBin; ++i) idv[i] = i < bic ? sid[i] : 0u;
+#pragma unroll
+                for (uint32_t i = 0; i < kSmallBin; ++i) {
+                    wv[i] = 0u;
+                    if constexpr (is_weighted(PROG)) wv[i] = i < bic ? swt[i] : 0u;
+                }
+                uint32_t m = 0;
+                bool sbad = false;
+#pragma unroll
+                for (uint32_t i = 0; i < kSmallBin; ++i) {
+                    if (i > 0 && (idv[i] & kFlag)) ++m;
+                    const bool ok = i < bic;
+                    const bool oob = m >= bmc || (idv[i] & kLocalMask) >= nv;
+                    sbad = sbad || (ok && oob);
+                    mi[i] = (ok && !oob) ? m : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (uint32_t i = 0; i < kSmallBin; ++i) vv[i] = sval[mi[i] != 0xFFFFFFFFu ? mi[i] : 0u];
+#pragma unroll
+                for (uint32_t i = 0; i < kSmallBin; ++i) {
+                    uint32_t x = mi[i] != 0xFFFFFFFFu ? vv[i] : IDENT;
+                    const bool use = x != IDENT;
+                    if constexpr (is_weighted(PROG)) x = use ? sat_add(x, wv[i]) : IDENT;
+                    my_ids += use ? 1u : 0u;
+                    const uint32_t d = use ? (idv[i] & kLocalMask) : lane;
+                    if constexpr (SUM)
+                        atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(x) * kFix) : 0ull);
+                    else
+                        atomicMin(st32 + d, x);
+                }
+                if (sbad) gptr(G.ctrl)->bug = 1;  // inconsistent bin (never read or written out of range)
             }
         }
         __syncthreads();
