@@ -794,7 +794,8 @@ __global__ __launch_bounds__(kGT, 2) void kb_gather(const Inst* __restrict__ tab
 constexpr uint32_t kMT = 256;        // merge workgroup
 constexpr uint32_t kMW = kMT / 64;
 constexpr uint32_t kMU = kMergeSpan / kMT;  // vertices per thread
-constexpr uint32_t kPJ = 4;          // partials loaded at once
+// partials loaded at once: 8 of 32-bit (min programs), 4 of 64-bit (sums)
+__host__ __device__ constexpr uint32_t merge_pj(int prog) { return is_sum(prog) ? 4u : 8u; }
 constexpr uint32_t kWholeCol = 0xFFFFFFFFu;
 
 template <int PROG>
@@ -858,6 +859,7 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
         if constexpr (SUM) a[i] = 0ull;
         else m[i] = kIdentMin;
     }
+    constexpr uint32_t kPJ = merge_pj(PROG);
     for (uint32_t w = 0; w < nw; w += kPJ) {
         if constexpr (SUM) {
             const unsigned long long* part = reinterpret_cast<const unsigned long long*>(gptr(G.gpart));
@@ -895,46 +897,74 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
                 for (uint32_t i = 0; i < kMU; ++i) m[i] = min(m[i], x[r][i]);
         }
     }
-    // filterFunc and state write-back, as for a single-task partition
+    // filterFunc and state write-back, as for a single-task partition; the
+    // stored values of the thread's vertices, then their offsets, are
+    // loaded together
     uint32_t cnt = 0, edges = 0;
     double my_d = 0.0;
+    bool keep[kMU], need[kMU];
+    float xv[kMU];
+    uint32_t o0[kMU], o1[kMU];
+    if constexpr (!SUM) {
+        uint32_t m0[kMU];
+#pragma unroll
+        for (uint32_t i = 0; i < kMU; ++i) {
+            const uint32_t u = ulo + kMT * i + tid;
+            const bool in = i < nu && u < nv;
+            // the stored value is read only where it is compared
+            m0[i] = (in && (m[i] != kIdentMin || (has_carry(PROG) && was[i]))) ? state[vbase + u] : 0u;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kMU; ++i) {
+            const uint32_t u = ulo + kMT * i + tid;
+            const bool in = i < nu && u < nv;
+            const bool hit = in && m[i] != kIdentMin && m[i] < m0[i];
+            keep[i] = hit;
+            if constexpr (has_carry(PROG)) keep[i] = keep[i] || (in && was[i] && (it + 1u - m0[i]) < P.persist);
+            if (hit) state[vbase + u] = m[i];
+            need[i] = keep[i];
+            xv[i] = 0.f;
+        }
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < kMU; ++i) {
+            const uint32_t u = ulo + kMT * i + tid;
+            const uint32_t v = vbase + u;
+            const bool in = i < nu && u < nv;
+            keep[i] = false;
+            xv[i] = 0.f;
+            need[i] = in && (a[i] != 0ull || was[i]);  // received an amount, or was active before scatter
+            if (need[i]) {
+                const double y = (double)a[i] * kInvFix;
+                if constexpr (PROG == P_PR) {
+                    const double d = (double)P.damping;
+                    xv[i] = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
+                    keep[i] = true;
+                } else {
+                    const double al = (double)P.alpha;
+                    double xd = (1.0 - al) * y;
+                    if (v == P.root) xd += al + (1.0 - al) * dang;
+                    xv[i] = (float)xd;
+                    keep[i] = xv[i] > 0.0f;
+                }
+                state[v] = __float_as_uint(xv[i]);
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kMU; ++i) {
+        const uint32_t v = vbase + ulo + kMT * i + tid;
+        o0[i] = need[i] ? off[v] : 0u;
+        o1[i] = need[i] ? off[v + 1] : 0u;
+    }
 #pragma unroll
     for (uint32_t i = 0; i < kMU; ++i) {
         if (i < nu) {
-            const uint32_t u = ulo + kMT * i + tid;
-            const uint32_t v = vbase + u;
-            bool keep = false;
-            if (u < nv) {
-                if constexpr (!SUM) {
-                    // the stored value is read only where it is compared
-                    const bool need = m[i] != kIdentMin || (has_carry(PROG) && was[i]);
-                    const uint32_t m0 = need ? state[v] : 0u;
-                    const bool hit = m[i] != kIdentMin && m[i] < m0;
-                    keep = hit;
-                    if constexpr (has_carry(PROG)) keep = keep || (was[i] && (it + 1u - m0) < P.persist);
-                    if (hit) state[v] = m[i];
-                } else {
-                    if (a[i] != 0ull || was[i]) {  // received an amount, or was active before scatter
-                        const double y = (double)a[i] * kInvFix;
-                        float x;
-                        if constexpr (PROG == P_PR) {
-                            const double d = (double)P.damping;
-                            x = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
-                            keep = true;
-                        } else {
-                            const double al = (double)P.alpha;
-                            double xd = (1.0 - al) * y;
-                            if (v == P.root) xd += al + (1.0 - al) * dang;
-                            x = (float)xd;
-                            keep = x > 0.0f;
-                        }
-                        state[v] = __float_as_uint(x);
-                        if (off[v + 1] == off[v]) my_d += (double)x;
-                    }
-                }
-                if (keep) edges += off[v + 1] - off[v];
+            if constexpr (SUM) {
+                if (need[i] && o1[i] == o0[i]) my_d += (double)xv[i];
             }
-            const uint64_t km = ballot(keep);
+            if (keep[i]) edges += o1[i] - o0[i];
+            const uint64_t km = ballot(keep[i]);
             if (lane == 0) {
                 const uint32_t wi = (ulo + kMT * i + wave * 64u) >> 5;
                 nbits[wi] = (uint32_t)km;
@@ -1002,17 +1032,26 @@ __device__ __forceinline__ void merge_list_body(const Dev& G, uint32_t it, uint3
     uint32_t deg[kMU];
     uint64_t km[kMU];
     uint32_t cnt = 0, edges = 0;
+    // bitmap words of every group first, then the offsets of the kept
+    // vertices, each batch issued together
 #pragma unroll
     for (uint32_t g = 0; g < kMU; ++g) {
-        km[g] = 0;
-        deg[g] = 0;
-        if (g < ng) {
-            const uint32_t u0 = ub + 64u * g, u = u0 + lane;
-            km[g] = (uint64_t)bits[u0 >> 5] | ((uint64_t)bits[(u0 >> 5) + 1] << 32);
-            if ((km[g] >> lane) & 1u) deg[g] = off[u + 1] - off[u];
-            cnt += popc64(km[g]);
-            edges += deg[g];
-        }
+        const uint32_t u0 = ub + 64u * g;
+        km[g] = g < ng ? ((uint64_t)bits[u0 >> 5] | ((uint64_t)bits[(u0 >> 5) + 1] << 32)) : 0ull;
+    }
+    uint32_t o0[kMU], o1[kMU];
+#pragma unroll
+    for (uint32_t g = 0; g < kMU; ++g) {
+        const uint32_t u = ub + 64u * g + lane;
+        const bool kp = (km[g] >> lane) & 1u;
+        o0[g] = kp ? off[u] : 0u;
+        o1[g] = kp ? off[u + 1] : 0u;
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < kMU; ++g) {
+        deg[g] = o1[g] - o0[g];
+        cnt += popc64(km[g]);
+        edges += deg[g];
     }
     edges = wave_sum_u32(edges);
     if (lane == 0) {
