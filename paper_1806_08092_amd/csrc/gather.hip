@@ -502,23 +502,42 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
             for (uint32_t pi = 0; pi < PPW; ++pi) {
                 const uint32_t pid = pw0 + r * PPW + pi;
                 const bool live = pid < pw1;
-                if (live)
-                    while (pid >= bl_scan[bcur + 1]) ++bcur;
+                // a piece past the run stays in the bin of the run's last
+                // piece (pw1 >= 1 whenever a round runs)
+                const uint32_t pq = min(pid, pw1 - 1u);
+                while (pq >= bl_scan[bcur + 1]) ++bcur;
                 const uint32_t b = bcur;
                 const uint32_t bioff = bl_ioff[b], bicnt = bl_icnt[b], bmo = bl_moff[b];
                 n_mcnt[pi] = bl_mcnt[b];
                 const bool sc = bmo & 0x80000000u;
                 n_moff[pi] = bmo & 0x7FFFFFFFu;
                 const uint32_t c = bioff / kChunk + bl_jlo[b] + (pid - bl_scan[b]);
-                n_lo[pi] = max(bioff, c * kChunk);
-                n_hi[pi] = live ? min(bioff + bicnt, c * kChunk + kChunk) : 0u;
-                n_x0[pi] = c * kChunk + lane * 4u;
-                const bool any4 = n_x0[pi] + 3u >= n_lo[pi] && n_x0[pi] < n_hi[pi];
-                n_raw[pi] = any4 ? *reinterpret_cast<const uint64_t*>((sc ? ids_sc : ids_pc) + n_x0[pi]) : 0ull;
+                const uint32_t lo = max(bioff, c * kChunk);
+                const uint32_t hi = live ? min(bioff + bicnt, c * kChunk + kChunk) : 0u;
+                const uint32_t x0 = c * kChunk + lane * 4u;
+                n_lo[pi] = lo;
+                n_hi[pi] = hi;
+                n_x0[pi] = x0;
+                const bool vm = x0 + 3u >= lo && x0 < hi;
+                // The loads are unconditional: a lane with no id of the piece
+                // (or a piece past the wave's run) reads the 4-id group that
+                // holds the bin's first id, inside the chunk-padded arrays, and
+                // its words are masked off in phase 2. Loads behind a branch
+                // would leave the compiler unable to count the loads in flight,
+                // and the wait for this round's data would then also wait for
+                // the next round's.
+                const uint32_t xa = vm ? x0 : (bioff & ~3u);
+                n_raw[pi] = *reinterpret_cast<const uint64_t*>((sc ? ids_sc : ids_pc) + xa);
                 n_wts[pi] = 0;
                 if constexpr (is_weighted(PROG))
-                    n_wts[pi] = any4 ? *reinterpret_cast<const uint32_t*>((sc ? w_sc : w_pc) + n_x0[pi]) : 0u;
-                n_mb[pi] = (live && n_lo[pi] != bioff) ? (sc ? ch_sc : ch_pc)[c] : 0u;
+                    n_wts[pi] = *reinterpret_cast<const uint32_t*>((sc ? w_sc : w_pc) + xa);
+                // the chunk's first message index; the first piece of a bin
+                // counts from the bin's first message (bit 31 of the message
+                // offset says which, applied where the value is used, so that
+                // nothing here waits on the load)
+                const uint32_t need_mb = (uint32_t)live & (uint32_t)(lo != bioff);
+                n_mb[pi] = (sc ? ch_sc : ch_pc)[need_mb ? c : bioff / kChunk];
+                n_moff[pi] |= need_mb << 31;
             }
         };
         if (nrounds) fetch(0);
@@ -538,7 +557,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                 bmoff[pi] = n_moff[pi];
                 bmcnt[pi] = n_mcnt[pi];
             }
-            if (r + 1 < nrounds) fetch(r + 1);
+            // the fetch past the last round reads only in-bin words of pieces
+            // that are not live; it is not skipped, so that no branch holds loads
+            fetch(r + 1);
             // phase 2: message indices and value loads
             uint32_t vmaskall = 0;
             bool bad = false;
@@ -556,7 +577,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                     fc += f;
                     dst[4 * pi + j] = id & kLocalMask;
                 }
-                uint32_t midx = mb[pi] + wave_excl_small(fc);
+                const bool from_chunk = bmoff[pi] >> 31;
+                bmoff[pi] &= 0x7FFFFFFFu;
+                uint32_t midx = (from_chunk ? mb[pi] : 0u) + wave_excl_small(fc);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     midx += (fmask >> j) & 1u;
@@ -772,7 +795,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
 }
 
 template <int PROG, bool ROUNDS>
-__global__ __launch_bounds__(kGT, 2) void kb_gather(const Inst* __restrict__ tab,
+__global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(4))) void kb_gather(const Inst* __restrict__ tab,
                                                     const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
