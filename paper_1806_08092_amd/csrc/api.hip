@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -522,7 +523,6 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
         }
         uint64_t nt = (tot * kChunk + T - 1) / T;
         nt = std::max<uint64_t>(1, std::min<uint64_t>(nt, 64));
-        const uint32_t first_task = (uint32_t)(gt.size() / 2);
         uint32_t p = 0;
         uint64_t before = 0;  // static pieces of bins p' < p
         for (uint64_t j = 0; j < nt; ++j) {
@@ -541,9 +541,39 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
             gt.push_back(make_uint4(q, plo, phi, (uint32_t)(nt << 16) | (uint32_t)j));
             gt.push_back(make_uint4(s0, s1, sl, 0));
         }
-        if (nt > 1) gs.push_back(make_uint4(q, first_task, (uint32_t)nt, nslot - (uint32_t)nt));
+        if (nt > 1) gs.push_back(make_uint4(q, 0u, (uint32_t)nt, nslot - (uint32_t)nt));
     }
     if (gt.size() / 2 > max_gt) return fail(GPOP_EDEVICE, "internal: gather task bound exceeded");
+    {
+        // Workgroups start in task order: the largest tasks (static pieces)
+        // go first, so that a dense iteration ends on small ones instead of
+        // leaving a partly filled last round of large ones. Each entry is
+        // self-contained (split partials are addressed by slot), so the order
+        // is free.
+        const size_t nt = gt.size() / 2;
+        std::vector<uint32_t> ord(nt);
+        std::vector<uint64_t> wt(nt);
+        for (size_t t = 0; t < nt; ++t) {
+            ord[t] = (uint32_t)t;
+            const uint4 a = gt[2 * t], b = gt[2 * t + 1];
+            if ((a.w >> 16) > 1) wt[t] = b.y - b.x;
+            else {
+                uint64_t tot = 0;
+                for (uint32_t p = 0; p < G.k; ++p) {
+                    const uint64_t r = (uint64_t)p * G.k + a.x, c = cnti[r], o = ioff[r];
+                    tot += c ? (o + c - 1) / kChunk - o / kChunk + 1 : 0;
+                }
+                wt[t] = tot;
+            }
+        }
+        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return wt[x] > wt[y]; });
+        std::vector<uint4> sorted(gt.size());
+        for (size_t t = 0; t < nt; ++t) {
+            sorted[2 * t] = gt[2 * ord[t]];
+            sorted[2 * t + 1] = gt[2 * ord[t] + 1];
+        }
+        gt.swap(sorted);
+    }
     G.n_gtask = (uint32_t)(gt.size() / 2);
     G.n_gsplit = (uint32_t)gs.size();
     G.combine = opts ? opts->combine : GPOP_COMBINE_LDS;

@@ -118,7 +118,7 @@ struct Dev {
     uint4* pctask;            // [n_pctask] {p, slot_begin, slot_end, 0}
     uint32_t* bld_t0;         // [k+1] task prefix of the build (all vertices active)
     uint4* gtask;             // [2*n_gtask] {q, p_lo, p_hi, nt<<16|j}, {s0, s1, slot, 0}
-    uint4* gsplit;            // [n_gsplit] {q, first task, nt, first slot}
+    uint4* gsplit;            // [n_gsplit] {q, 0, nt, first slot}
     uint32_t* gpart;          // partial results of split gathers, q (u32) or 2q (u64) words per slot
     uint32_t* gflag;          // [slots] a split task wrote its partial
     uint4* mtot;              // [k*kMaxMergeChunks] per merge chunk {kept, kept out-edges, dangling sum (f64 bits)}
