@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -16,7 +18,7 @@ using namespace gpop;
 
 namespace {
 
-constexpr uint32_t kPcTask = 65536;  // message slots per partition-centric task
+constexpr uint32_t kPcTaskMin = 32768;  // least message slots per partition-centric task
 
 thread_local std::string g_err;
 
@@ -151,7 +153,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     const uint64_t kk = k * k;
     const uint64_t E_pad = align256(E ? E : 1);
     const uint64_t nch = E_pad / kChunk;
-    const uint64_t ntask = E / kPcTask + k + 1;
+    const uint64_t ntask = E / kPcTaskMin + k + 1;
     const uint64_t nsct = max_sctask_for(V, E, z);
     const uint64_t ngt = max_gtask_for(E, z);
     G->part_E = (uint32_t*)take(k * 4);
@@ -377,6 +379,52 @@ int runner_run(Runner& R, const BatchGrid& B, int prog, bool prof, bool eager, u
 
 constexpr size_t kLdsPerWorkgroup = 160 * 1024;  // gfx950: on-chip memory a workgroup may use
 
+int cu_count() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) return 256;
+    return v;
+}
+
+// Slice length of the partition-centric scatter tasks, from a few sizes, by a
+// model of an iteration where every partition scatters: workgroups (two per
+// CU while the partition's q state words fit twice in LDS) take the slices
+// longest first; a slice costs its slots plus a reload of its partition's
+// state, about q * 4 / 6 slot-equivalents (a slot moves 6 bytes). The least
+// modelled finish time wins, the longer slice on a tie. Long slices reload
+// less state; short ones leave a smaller last round.
+uint64_t pc_task_slots(const std::vector<uint32_t>& partM, uint64_t q) {
+    const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(2, kLdsPerWorkgroup / (q * 4)));
+    const size_t nslot = (size_t)cu_count() * per_cu;
+    const double fix = (double)q * 4.0 / 6.0;
+    const uint64_t cand[] = {kPcTaskMin, 49152, 65536, 98304, 131072, 196608, 262144};
+    uint64_t best_len = 65536;
+    double best = 0.0;
+    bool have = false;
+    std::vector<double> len;
+    for (const uint64_t L : cand) {
+        len.clear();
+        for (const uint32_t m : partM)
+            for (uint64_t a = 0; a < m; a += L) len.push_back((double)std::min<uint64_t>(m - a, L));
+        std::sort(len.begin(), len.end(), [](double x, double y) { return x > y; });
+        std::priority_queue<double, std::vector<double>, std::greater<double>> busy;
+        for (size_t i = 0; i < nslot; ++i) busy.push(0.0);
+        double finish = 0.0;
+        for (const double l : len) {
+            const double t = busy.top() + fix + l;
+            busy.pop();
+            busy.push(t);
+            finish = std::max(finish, t);
+        }
+        if (!have || finish <= best) {
+            best = finish;
+            best_len = L;
+            have = true;
+        }
+    }
+    return best_len;
+}
+
 int max_lds_per_block() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 65536;
@@ -488,15 +536,19 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
                   "read offsets");
     HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
     // partition-centric scatter tasks: slices of each partition's message range
+    const uint64_t pc_len = pc_task_slots(partM, G.q);
     std::vector<uint4> tasks;
     uint64_t slot = 0;
     for (uint32_t p = 0; p < G.k; ++p) {
-        for (uint64_t a = 0; a < partM[p]; a += kPcTask) {
-            const uint64_t b = std::min<uint64_t>(partM[p], a + kPcTask);
+        for (uint64_t a = 0; a < partM[p]; a += pc_len) {
+            const uint64_t b = std::min<uint64_t>(partM[p], a + pc_len);
             tasks.push_back(make_uint4(p, (uint32_t)(slot + a), (uint32_t)(slot + b), 0));
         }
         slot += partM[p];
     }
+    // workgroups start in task order: longest slices first
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [](const uint4& x, const uint4& y) { return x.z - x.y > y.z - y.y; });
     if (slot >= 0x80000000ull)
         return fail(GPOP_ENOTSUP, "graph has %llu messages; at most 2^31 - 1 supported",
                     (unsigned long long)slot);
