@@ -512,25 +512,52 @@ __global__ __launch_bounds__(kPcT) void kb_pc(const Inst* __restrict__ tab, cons
 // mode[], so it must run before the next plan overwrites it.
 __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
     __shared__ uint64_t red[6][16];
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u, B = blockDim.x;
     uint64_t v[6] = {0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged
     const uint32_t ncb = col_blocks(G.k);
-    for (uint32_t p = tid; p < G.k; p += blockDim.x) {
-        if (gptr(G.mode)[p] == GPOP_MODE_SC) {
-            const uint32_t nu = gptr(G.sc_t0)[p + 1] - gptr(G.sc_t0)[p] > kScanRows ? ncb : 1u;
-            for (uint32_t j = 0; j < nu; ++j) {
-                const uint2 t = gptr(G.sc_tot)[(size_t)p * ncb + j];
-                v[0] += t.x;
-                v[1] += t.y;
-            }
+    const uint32_t nt = G.n_gtask + G.n_gsplit;
+    // Loads go out in batches before the sums that use them: the first four
+    // task marks per thread, then every partition's mode and counts (the
+    // second count block only where a partition had more than one).
+    constexpr uint32_t kTB = 4;
+    auto task_batch = [&](uint32_t t0, uint32_t* ids, uint32_t* ran) {
+#pragma unroll
+        for (uint32_t u = 0; u < kTB; ++u) {
+            const uint32_t t = t0 + u * B;
+            ids[u] = t < G.n_gtask ? gptr(G.gat_ids)[t] : 0u;
+            ran[u] = t < nt ? gptr(G.gat_ran)[t] : 0u;
+        }
+    };
+    auto task_sum = [&](const uint32_t* ids, const uint32_t* ran) {
+#pragma unroll
+        for (uint32_t u = 0; u < kTB; ++u) {
+            v[2] += ids[u];
+            v[3] += ran[u] == 1;
+            v[4] += ran[u] == 2;
+            v[5] += ran[u] == 3;
+        }
+    };
+    uint32_t ids0[kTB], ran0[kTB];
+    task_batch(tid, ids0, ran0);
+    for (uint32_t p = tid; p < G.k; p += B) {
+        const uint32_t md = gptr(G.mode)[p], ta = gptr(G.sc_t0)[p], tb = gptr(G.sc_t0)[p + 1];
+        const uint2 t0 = gptr(G.sc_tot)[(size_t)p * ncb];
+        if (md == GPOP_MODE_SC) {
+            v[0] += t0.x;
+            v[1] += t0.y;
+            if (tb - ta > kScanRows)
+                for (uint32_t j = 1; j < ncb; ++j) {
+                    const uint2 t = gptr(G.sc_tot)[(size_t)p * ncb + j];
+                    v[0] += t.x;
+                    v[1] += t.y;
+                }
         }
     }
-    for (uint32_t t = tid; t < G.n_gtask + G.n_gsplit; t += blockDim.x) {
-        if (t < G.n_gtask) v[2] += gptr(G.gat_ids)[t];
-        const uint32_t r = gptr(G.gat_ran)[t];
-        v[3] += r == 1;
-        v[4] += r == 2;
-        v[5] += r == 3;
+    task_sum(ids0, ran0);
+    for (uint32_t t0 = tid + kTB * B; t0 < nt; t0 += kTB * B) {
+        uint32_t ids[kTB], ran[kTB];
+        task_batch(t0, ids, ran);
+        task_sum(ids, ran);
     }
     for (int j = 0; j < 6; ++j) v[j] = wave_sum_u64(v[j]);
     if (lane == 0)
@@ -554,10 +581,9 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
 // Runs finalize_prev once per iteration: a probe scatter or a stats read may
 // come before the plan of the same iteration, and both rewrite what it reads.
 __device__ __forceinline__ void finalize_once(const Dev& G, uint32_t it) {
-    __shared__ uint32_t s_need;
-    if (threadIdx.x == 0) s_need = it > 0 && gptr(G.ctrl)->fin_it < it;
-    __syncthreads();
-    if (s_need) {
+    // Every thread reads the mark; thread 0 rewrites it only after the
+    // barriers inside finalize_prev, which each thread reaches after its read.
+    if (it > 0 && gptr(G.ctrl)->fin_it < it) {
         finalize_prev(G, it);
         if (threadIdx.x == 0) gptr(G.ctrl)->fin_it = it;
     }
@@ -577,11 +603,23 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         return;
     }
     const uint32_t cur = it & 1u;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    // This iteration's inputs of the first kPlanT partitions are loaded before
+    // the previous iteration's statistics are finalised, so that their loads
+    // overlap.
+    uint32_t f_va = 0, f_ea = 0, f_E = 0, f_M = 0;
+    double f_d = 0.0;
+    if (tid < G.k) {
+        f_va = gptr(G.fVa[cur])[tid];
+        f_ea = gptr(G.fEa[cur])[tid];
+        f_E = gptr(G.part_E)[tid];
+        f_M = gptr(G.part_M)[tid];
+        f_d = gptr(G.dpart[cur])[tid];
+    }
     finalize_once(G, it);
     __shared__ uint64_t red[9][kPlanW];
     __shared__ double dred[kPlanW];
     __shared__ uint32_t s_w[kPlanW];
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0, sva = 0, sea = 0, pcv = 0;
     double dang = 0.0;
     // pass 1: modes and totals; the source-centric work units (active
@@ -590,13 +628,15 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     for (uint32_t p0 = 0; p0 < G.k; p0 += kPlanT) {
         const uint32_t p = p0 + tid;
         if (p < G.k) {
-            const uint32_t Va = gptr(G.fVa[cur])[p], Ea = gptr(G.fEa[cur])[p];
+            const bool pre = p0 == 0;
+            const uint32_t Va = pre ? f_va : gptr(G.fVa[cur])[p], Ea = pre ? f_ea : gptr(G.fEa[cur])[p];
+            const uint32_t Ep = pre ? f_E : gptr(G.part_E)[p], Mp = pre ? f_M : gptr(G.part_M)[p];
             uint8_t md = GPOP_MODE_NONE;
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
                 else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
                 else if (P.selector == GPOP_SEL_LEARNED) md = gptr(G.mode_l)[p];
-                else md = analytical_mode(G, P, p, Va, Ea);
+                else md = analytical_mode_of(G, P, Ep, Mp, Va, Ea);
             }
             gptr(G.mode)[p] = md;
             va += Va;
@@ -604,8 +644,8 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             uint32_t units = 0xFFFFFFFFu;
             if (md == GPOP_MODE_PC) {
                 ++npc;
-                pcm += gptr(G.part_M)[p];
-                pci += gptr(G.part_E)[p];
+                pcm += Mp;
+                pci += Ep;
                 pcv += min(G.q, G.V - (p << G.s));
             } else if (md == GPOP_MODE_SC) {
                 ++nsc;
@@ -614,7 +654,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 units = (uint32_t)min<uint64_t>((uint64_t)Va + Ea, 0xFFFFFFFEull);
             }
             s_units[p] = units;
-            dang += gptr(G.dpart[cur])[p];
+            dang += pre ? f_d : gptr(G.dpart[cur])[p];
         }
     }
     // task size of this iteration: about sc_task_target tasks, between

@@ -14,16 +14,20 @@ namespace gpop {
 // PC is chosen iff cost_PC / BW_PC <= cost_SC / BW_SC, evaluated exactly in
 // 128-bit integers with BW_PC / BW_SC = ratio_num / ratio_den; ties pick PC.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint8_t analytical_mode(const Dev& G, const Params& P, uint32_t p,
-                                                   uint32_t Va, uint32_t Ea) {
+__device__ __forceinline__ uint8_t analytical_mode_of(const Dev& G, const Params& P, uint64_t Ep, uint64_t Mp,
+                                                      uint32_t Va, uint32_t Ea) {
     typedef unsigned __int128 u128;
-    const uint64_t Ep = gptr(G.part_E)[p], Mp = gptr(G.part_M)[p];
     const uint64_t si = P.s_i, sv = P.s_v;
     const uint64_t cost_pc = (Mp + Ep) * si + 2ull * Mp * sv + (uint64_t)G.k * si;
     const u128 lhs = (u128)cost_pc * Ep * P.ratio_den;
     const u128 sc_scaled = (u128)(2ull * sv) * Mp * Ea + (u128)((3ull * Ea + Va) * si) * Ep;
     const u128 rhs = sc_scaled * P.ratio_num;
     return lhs <= rhs ? (uint8_t)GPOP_MODE_PC : (uint8_t)GPOP_MODE_SC;
+}
+
+__device__ __forceinline__ uint8_t analytical_mode(const Dev& G, const Params& P, uint32_t p,
+                                                   uint32_t Va, uint32_t Ea) {
+    return analytical_mode_of(G, P, gptr(G.part_E)[p], gptr(G.part_M)[p], Va, Ea);
 }
 
 __device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
