@@ -27,8 +27,8 @@ constexpr uint32_t kIdentMin = 0xFFFFFFFFu;  // min-combine identity ("no messag
 constexpr uint32_t kIdentSum = 0x80000000u;  // sum-combine identity: -0.0f bits
 constexpr uint32_t kLogCap = 4096;        // per-iteration stats records
 constexpr uint32_t kScWaves = 4;          // independent source-centric task waves per workgroup
-constexpr uint32_t kMergeSpan = 2048;     // vertices per workgroup of a split-partition merge
-constexpr uint32_t kMaxMergeChunks = 16;  // q / kMergeSpan at the largest partition (2^15)
+constexpr uint32_t kMergeSpan = 1024;     // vertices per workgroup of a split-partition merge
+constexpr uint32_t kMaxMergeChunks = 32;  // q / kMergeSpan at the largest partition (2^15)
 constexpr double kFix = 1152921504606846976.0;      // 2^60: fixed-point scale of sums
 constexpr double kInvFix = 8.673617379884035e-19;   // 2^-60
 
