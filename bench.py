@@ -233,6 +233,7 @@ def selector_eval(args):
         return args.log2_part or (13 if prog == "pagerank" else 14)
 
     parts = []
+    keep = None  # the largest training graph, kept to calibrate the decision threshold
     for i, (scale, ef, abc) in enumerate(TRAIN_SPECS[:args.train_graphs]):
         t = time.perf_counter()
         g = gg.rmat_graph(scale, ef, seed=gg.BASE_SEED + 100 + i, abc=abc, symmetric=True)
@@ -252,6 +253,8 @@ def selector_eval(args):
             parts.append(learned.collect(G, max_iter=10 if prog == "pagerank" else 1 << 20))
         log("training graph rmat%d ef%d abc=%s: %d rows so far (%.1f s)" % (
             scale, ef, abc, sum(len(p) for p in parts), time.perf_counter() - t))
+        if i == min(args.train_graphs, len(TRAIN_SPECS)) - 1:
+            keep = (g, scale, srcs)
         del G, off, cols, w, st
         torch.cuda.empty_cache()
     data = learned.Samples.concat(parts)
@@ -273,6 +276,28 @@ def selector_eval(args):
            "eq1_fitted_us": learned.choice_cost(learned.analytical_choice(data, ratio), data),
            "fitted_ratio": ratio}
     log("trained on %d rows in %.1f s: %s" % (len(data), train_s, fit))
+    # decision threshold: timed whole runs (BFS from 2 sources + CC) on the
+    # largest training graph, with its partition sizes of the training rows
+    raw_model = mlp.model.clone()
+    kg, kscale, ksrcs = keep
+    koff, kcols, kw = gp.upload_csr(kg)
+    kst = torch.empty(kg.n, dtype=torch.int32, device="cuda")
+    kdeg = (koff[1:] - koff[:-1]).to(torch.int64)
+    kruns = [("bfs", ksrcs[0]), ("bfs", ksrcs[-1]), ("cc", 0)]
+    kGs = [gp.Graph(koff, kcols, kw, log2_part=lp) for lp in sorted({lp_of("bfs"), kscale - 11})]
+    for KG in kGs:
+        KG.set_selector("learned", ratio, mlp=mlp.model)
+
+    def time_train_runs():
+        return sum(_time_runs(KG, kst, kruns, 2, kdeg, kg.n, kg.m)[0] for KG in kGs)
+
+    offset, offset_ms = learned.calibrate_offset(mlp, time_train_runs)
+    fit["logit_offset"] = offset
+    fit["offset_ms_on_training_graph"] = offset_ms
+    fit["learned_us_calibrated"] = learned.choice_cost(mlp.forward(x).cpu().numpy() >= 0, data)
+    log("decision threshold: offset %s (training-graph ms per offset: %s)" % (offset, offset_ms))
+    del kGs, koff, kcols, kw, kst, kdeg, keep, kg
+    torch.cuda.empty_cache()
 
     scale = args.eval_scale
     t = time.perf_counter()
@@ -288,7 +313,8 @@ def selector_eval(args):
     log("evaluation graphs generated in %.1f s" % (time.perf_counter() - t))
     # the learned selector falls back to Eq. 1 at the fitted ratio
     selectors = [("eq1_ratio2", "analytical", 2.0), ("eq1_default", "analytical", 16.0),
-                 ("eq1_fitted", "analytical", ratio), ("learned", "learned", ratio)]
+                 ("eq1_fitted", "analytical", ratio), ("learned_uncalibrated", "learned", ratio),
+                 ("learned", "learned", ratio)]
     res = {name: {"ms": 0.0, "edges": 0, "per_program_ms": {}, "decisions": 0, "pc_decisions": 0,
                   "fallbacks": 0} for name, _, _ in selectors}
     for gname, g, runs in graphs:
@@ -297,7 +323,8 @@ def selector_eval(args):
         st = torch.empty(g.n, dtype=torch.int32, device="cuda")
         deg = (off[1:] - off[:-1]).to(torch.int64)
         for name, kind, r in selectors:
-            G.set_selector(kind, r, mlp=mlp.model if kind == "learned" else None)
+            G.set_selector(kind, r, mlp=(raw_model if name == "learned_uncalibrated" else mlp.model)
+                           if kind == "learned" else None)
             ms, edges, per, counts = _time_runs(G, st, runs, args.steps, deg, g.n, g.m)
             for kc, vc in counts.items():
                 res[name][kc] += vc
@@ -319,6 +346,7 @@ def selector_eval(args):
                    "log2_part": {"bfs_cc": lp_of("bfs"), "pagerank": lp_of("pagerank")},
                    "train_graphs": args.train_graphs, "train_steps": args.train_steps},
         "selector_speedup": {"learned_vs_eq1_ratio2": res["eq1_ratio2"]["ms"] / res["learned"]["ms"],
+                             "learned_vs_uncalibrated": res["learned_uncalibrated"]["ms"] / res["learned"]["ms"],
                              "learned_vs_eq1_default16": res["eq1_default"]["ms"] / res["learned"]["ms"],
                              "learned_vs_eq1_fitted": res["eq1_fitted"]["ms"] / res["learned"]["ms"]},
         "selectors": res,

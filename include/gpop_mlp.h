@@ -110,6 +110,13 @@ int gpop_mlp_train_step(gpop_mlp_model* d_model, float* d_master, float* d_m, fl
                         uint32_t step, float lr, float* d_grad, float* d_loss, void* d_ws,
                         size_t ws_bytes, void* stream);
 
+/* Adds delta to the output bias b3 (the f32 master d_master[GPOP_MLP_B3] and
+ * its bf16 copy in d_model->w), which moves every logit by about delta: a
+ * positive delta makes partition-centric choices more frequent. For
+ * calibrating the decision threshold against whole-run timings after
+ * training. Errors: GPOP_EINVAL on NULL arguments or a non-finite delta. */
+int gpop_mlp_shift_logit(gpop_mlp_model* d_model, float* d_master, float delta, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

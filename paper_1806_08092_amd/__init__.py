@@ -144,6 +144,7 @@ _SIGS = {
     "gpop_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_uint32, ctypes.c_uint32,
                                                                    ctypes.c_float]
                             + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "gpop_mlp_shift_logit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
     "gpop_batch_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
     "gpop_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -490,6 +491,11 @@ class Mlp:
         self.step += 1
         _check(lib().gpop_mlp_adam(_ptr(self.model), _ptr(self.master), _ptr(self.m), _ptr(self.v),
                                    _ptr(self.grad), self.step, lr, _stream(stream)))
+
+    def shift_logit(self, delta, stream=None):
+        """Adds delta to the output bias (gpop_mlp_shift_logit)."""
+        _check(lib().gpop_mlp_shift_logit(_ptr(self.model), _ptr(self.master), ctypes.c_float(delta),
+                                          _stream(stream)))
 
     def train_step(self, x, t_sc, t_pc, lr=1e-3, stream=None):
         ws = self._workspace(x.shape[0])

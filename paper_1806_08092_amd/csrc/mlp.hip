@@ -221,6 +221,15 @@ __global__ __launch_bounds__(256) void k_mlp_adam(gpop_mlp_model* __restrict__ M
     M->w[j] = f32_to_bf16_bits(th);
 }
 
+// Adds delta to the output bias (master and its bf16 copy).
+__global__ __launch_bounds__(64) void k_mlp_shift(gpop_mlp_model* __restrict__ M, float* __restrict__ master,
+                                                 float delta) {
+    if (threadIdx.x != 0) return;
+    const float b = master[GPOP_MLP_B3] + delta;
+    master[GPOP_MLP_B3] = b;
+    M->w[GPOP_MLP_B3] = f32_to_bf16_bits(b);
+}
+
 uint32_t nchunks(uint32_t n) { return (n + 63u) / 64u; }
 
 }  // namespace
@@ -288,6 +297,14 @@ int gpop_mlp_train_step(gpop_mlp_model* d_model, float* d_master, float* d_m, fl
     int rc = gpop_mlp_grad(d_model, d_x, d_t_sc, d_t_pc, n, d_grad, d_loss, d_ws, ws_bytes, stream);
     if (rc) return rc;
     return gpop_mlp_adam(d_model, d_master, d_m, d_v, d_grad, step, lr, stream);
+}
+
+int gpop_mlp_shift_logit(gpop_mlp_model* d_model, float* d_master, float delta, void* stream) {
+    if (!d_model || !d_master) return fail(GPOP_EINVAL, "NULL argument");
+    if (!std::isfinite(delta)) return fail(GPOP_EINVAL, "delta must be finite");
+    hipLaunchKernelGGL(k_mlp_shift, dim3(1), dim3(64), 0, (hipStream_t)stream, d_model, d_master, delta);
+    HIP_OR_RETURN(hipGetLastError(), "mlp shift");
+    return GPOP_OK;
 }
 
 }  // extern "C"

@@ -68,6 +68,10 @@ def test_selector_entry_points_reject_bad_arguments_on_host():
     assert L.gpop_mlp_adam(fake, fake, fake, fake, fake, 0, 1e-3, None) == gp.EINVAL
     assert L.gpop_mlp_adam(fake, fake, fake, fake, fake, 1, -1.0, None) == gp.EINVAL
     assert b"Adam" in L.gpop_last_error() or b"lr" in L.gpop_last_error()
+    assert L.gpop_mlp_shift_logit(None, fake, 1.0, None) == gp.EINVAL
+    assert L.gpop_mlp_shift_logit(fake, None, 1.0, None) == gp.EINVAL
+    assert L.gpop_mlp_shift_logit(fake, fake, float("nan"), None) == gp.EINVAL
+    assert L.gpop_mlp_shift_logit(fake, fake, float("inf"), None) == gp.EINVAL
 
 
 def test_mlp_workspace_size():

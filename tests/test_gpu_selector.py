@@ -88,6 +88,28 @@ def test_mlp_init_and_forward_match_oracle():
     assert np.max(np.abs(z - zr)) <= 1e-4 * max(1.0, np.max(np.abs(zr)))
 
 
+def test_mlp_shift_logit_moves_output_bias():
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    rng = np.random.default_rng(4)
+    X = (rng.standard_normal((300, 12)) * 3).astype(np.float32)
+    init = gg.mlp_init_params(21)
+    mlp = gp.Mlp()
+    xt = torch.from_numpy(X).cuda()
+    mlp.init(torch.from_numpy(init).cuda(), xt)
+    want = init.astype(np.float32).copy()
+    for d in (2.5, -0.75, 0.0):
+        mlp.shift_logit(d)
+        want[5056] = np.float32(want[5056] + np.float32(d))
+        torch.cuda.synchronize()
+        assert np.array_equal(mlp.master.cpu().numpy(), want)
+        magic, npar, mean, inv, w = _model_from_device(mlp)
+        assert np.array_equal(w, mr.bf16_round(want))
+        z = mlp.forward(xt).cpu().numpy().astype(np.float64)
+        zr = mr.forward(w, mean, inv, X)
+        assert np.max(np.abs(z - zr)) <= 1e-4 * max(1.0, np.max(np.abs(zr)))
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 1000, 4097])
 def test_mlp_gradient_matches_oracle(n):
     torch = torch_cuda()
