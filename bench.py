@@ -233,7 +233,7 @@ def selector_eval(args):
         return args.log2_part or (13 if prog == "pagerank" else 14)
 
     parts = []
-    keep = None  # the largest training graph, kept to calibrate the decision threshold
+    keep = []  # the two largest training graphs, kept to calibrate the decision threshold
     for i, (scale, ef, abc) in enumerate(TRAIN_SPECS[:args.train_graphs]):
         t = time.perf_counter()
         g = gg.rmat_graph(scale, ef, seed=gg.BASE_SEED + 100 + i, abc=abc, symmetric=True)
@@ -253,8 +253,8 @@ def selector_eval(args):
             parts.append(learned.collect(G, max_iter=10 if prog == "pagerank" else 1 << 20))
         log("training graph rmat%d ef%d abc=%s: %d rows so far (%.1f s)" % (
             scale, ef, abc, sum(len(p) for p in parts), time.perf_counter() - t))
-        if i == min(args.train_graphs, len(TRAIN_SPECS)) - 1:
-            keep = (g, scale, srcs)
+        if i >= min(args.train_graphs, len(TRAIN_SPECS)) - 2:
+            keep.append((g, scale, srcs))
         del G, off, cols, w, st
         torch.cuda.empty_cache()
     data = learned.Samples.concat(parts)
@@ -277,26 +277,30 @@ def selector_eval(args):
            "fitted_ratio": ratio}
     log("trained on %d rows in %.1f s: %s" % (len(data), train_s, fit))
     # decision threshold: timed whole runs (BFS from 2 sources + CC) on the
-    # largest training graph, with its partition sizes of the training rows
+    # two largest training graphs, with the partition sizes of their rows
     raw_model = mlp.model.clone()
-    kg, kscale, ksrcs = keep
-    koff, kcols, kw = gp.upload_csr(kg)
-    kst = torch.empty(kg.n, dtype=torch.int32, device="cuda")
-    kdeg = (koff[1:] - koff[:-1]).to(torch.int64)
-    kruns = [("bfs", ksrcs[0]), ("bfs", ksrcs[-1]), ("cc", 0)]
-    kGs = [gp.Graph(koff, kcols, kw, log2_part=lp) for lp in sorted({lp_of("bfs"), kscale - 11})]
-    for KG in kGs:
-        KG.set_selector("learned", ratio, mlp=mlp.model)
+    cal = []
+    for kg, kscale, ksrcs in keep:
+        koff, kcols, kw = gp.upload_csr(kg)
+        kst = torch.empty(kg.n, dtype=torch.int32, device="cuda")
+        kdeg = (koff[1:] - koff[:-1]).to(torch.int64)
+        kruns = [("bfs", ksrcs[0]), ("bfs", ksrcs[-1]), ("cc", 0)]
+        lps = sorted({lp_of("bfs")} | ({kscale - 11} if kscale >= 21 else set()))
+        for lp in lps:
+            KG = gp.Graph(koff, kcols, kw, log2_part=lp)
+            KG.set_selector("learned", ratio, mlp=mlp.model)
+            cal.append((KG, kst, kruns, kdeg, kg.n, kg.m))
 
     def time_train_runs():
-        return sum(_time_runs(KG, kst, kruns, 2, kdeg, kg.n, kg.m)[0] for KG in kGs)
+        return sum(_time_runs(*c[:3], 2, *c[3:])[0] for c in cal)
 
-    offset, offset_ms = learned.calibrate_offset(mlp, time_train_runs)
+    offset, offset_ms = learned.calibrate_offset(mlp, time_train_runs,
+                                                 offsets=(-2.0, 0.0, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0))
     fit["logit_offset"] = offset
     fit["offset_ms_on_training_graph"] = offset_ms
     fit["learned_us_calibrated"] = learned.choice_cost(mlp.forward(x).cpu().numpy() >= 0, data)
     log("decision threshold: offset %s (training-graph ms per offset: %s)" % (offset, offset_ms))
-    del kGs, koff, kcols, kw, kst, kdeg, keep, kg
+    del cal, keep
     torch.cuda.empty_cache()
 
     scale = args.eval_scale
