@@ -429,8 +429,9 @@ hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st) {
 // this a pure stream: slot i of the partition's message range gets the value
 // of source png_src[i]. The partition's outgoing values are staged once in
 // LDS (the partition's vertex data is the cached working set), inactive
-// vertices contribute the combine identity. Work is cut into static tasks of
-// at most kPcTask slots so hub partitions spread over many workgroups.
+// vertices contribute the combine identity. Work is cut into static slices of
+// a partition's slots (their length chosen per graph when it is built), so
+// hub partitions spread over many workgroups.
 // ---------------------------------------------------------------------------
 // Partition-centric workgroup: the partition's values sit in LDS (q words), so
 // two workgroups fit a CU; 16 waves each keep enough loads in flight.
