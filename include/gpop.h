@@ -58,9 +58,15 @@ typedef enum gpop_program {
     GPOP_PROG_SSSP_U32 = 2,      /* u32 distance, u8 weights, saturating (SSSP app)   */
     GPOP_PROG_PAGERANK_F32 = 3,  /* f32 PageRank, dangling mass spread uniformly       */
     GPOP_PROG_PPR_F32 = 4,       /* f32 personalised PageRank, restart to one seed     */
-    GPOP_PROG_CARRY_BFS = 5      /* BFS levels where initFunc keeps a reached vertex
+    GPOP_PROG_CARRY_BFS = 5,     /* BFS levels where initFunc keeps a reached vertex
                                     active for `persist` iterations (selective
                                     continuity of the active set)                      */
+    GPOP_PROG_BFS_PARENT = 6     /* u32 parent in the BFS tree of the root (Algorithm 5):
+                                    scatterFunc sends the vertex id, gatherFunc sets
+                                    the parent of an unvisited vertex; of the messages
+                                    one iteration brings, the least source id wins
+                                    (the first in the paper's gather order); the
+                                    root's parent is the root, unreached 0xFFFFFFFF  */
 } gpop_program;
 
 typedef enum gpop_selector {

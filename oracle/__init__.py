@@ -50,6 +50,7 @@ def _L():
         u32, i32, dbl, vp = ctypes.c_uint32, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
         for name, args in [
             ("oracle_bfs_levels", [u32, vp, vp, u32, vp]),
+            ("oracle_bfs_parents", [u32, vp, vp, u32, vp]),
             ("oracle_cc_minlabel", [u32, vp, vp, vp]),
             ("oracle_sssp", [u32, vp, vp, vp, u32, vp]),
             ("oracle_pagerank", [u32, vp, vp, dbl, u32, vp]),
@@ -77,6 +78,16 @@ def bfs_levels(g, root: int) -> np.ndarray:
     off, cols = _csr(g)
     out = np.empty(g.n, np.uint32)
     if _L().oracle_bfs_levels(g.n, _p(off), _p(cols), root, _p(out)) != 0:
+        raise ValueError("bad root or allocation failure")
+    return out
+
+
+def bfs_parents(g, root: int) -> np.ndarray:
+    """Parent of each vertex in the BFS tree of root (least-id in-neighbour one
+    level closer; root: itself; unreached: 0xFFFFFFFF)."""
+    off, cols = _csr(g)
+    out = np.empty(g.n, np.uint32)
+    if _L().oracle_bfs_parents(g.n, _p(off), _p(cols), root, _p(out)) != 0:
         raise ValueError("bad root or allocation failure")
     return out
 

@@ -161,6 +161,28 @@ class BFSLevel(Program):
         return st[v] + 1
 
 
+class BFSParent(Program):
+    """Algorithm 5 as printed: scatterFunc sends the vertex's own id,
+    gatherFunc sets the parent of a vertex that has none, initFunc keeps no
+    vertex, filterFunc keeps every vertex gatherFunc set. The first message a
+    vertex receives wins; this model gathers bins in source-partition order
+    and a bin's messages in source order, so that is the least source id."""
+
+    def start(self, n, params):
+        st = [INF32] * n
+        st[params["root"]] = params["root"]
+        return st, [params["root"]]
+
+    def scatter(self, st, v, ctx):
+        return v
+
+    def gather(self, st, u, val):
+        if st[u] == INF32:
+            st[u] = val
+            return True
+        return False
+
+
 class CCMinLabel(Program):
     def start(self, n, params):
         return list(range(n)), list(range(n))
@@ -232,7 +254,7 @@ class PPR(PageRank):
 
 
 PROGRAMS = {"bfs": BFSLevel, "cc": CCMinLabel, "sssp": SSSP, "pagerank": PageRank,
-            "ppr": PPR, "carry_bfs": CarryBFS}
+            "ppr": PPR, "carry_bfs": CarryBFS, "bfs_parent": BFSParent}
 
 
 # ---------------------------------------------------------------------------

@@ -7,6 +7,10 @@
  *
  *   oracle_bfs_levels   hop distance from one root along out-edges
  *                       (BFS application section; levels, not parents)
+ *   oracle_bfs_parents  parent of each reached vertex in the BFS tree of one
+ *                       root (the BFS application's output, Algorithm 5):
+ *                       the least-id in-neighbour one level closer to the
+ *                       root; the root is its own parent
  *   oracle_cc_minlabel  smallest vertex id of each connected component
  *                       (the fixed point of min-label propagation described
  *                       for connected components in the applications section)
@@ -47,6 +51,30 @@ int oracle_bfs_levels(uint32_t n, const uint32_t* off, const uint32_t* cols,
         }
     }
     free(queue);
+    return 0;
+}
+
+/* Levels by the FIFO search above, then every edge u -> v with
+ * level[u] + 1 == level[v] offers u as the parent of v, and the least offer
+ * stays. */
+int oracle_bfs_parents(uint32_t n, const uint32_t* off, const uint32_t* cols,
+                       uint32_t root, uint32_t* parent) {
+    uint32_t* level = (uint32_t*)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    if (!level) return -1;
+    if (oracle_bfs_levels(n, off, cols, root, level) != 0) {
+        free(level);
+        return -1;
+    }
+    for (uint32_t v = 0; v < n; ++v) parent[v] = INF32;
+    parent[root] = root;
+    for (uint32_t u = 0; u < n; ++u) {
+        if (level[u] == INF32) continue;
+        for (uint32_t e = off[u]; e < off[u + 1]; ++e) {
+            uint32_t v = cols[e];
+            if (v != root && level[v] == level[u] + 1 && u < parent[v]) parent[v] = u;
+        }
+    }
+    free(level);
     return 0;
 }
 

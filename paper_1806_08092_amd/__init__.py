@@ -20,9 +20,9 @@ HEADERS = [os.path.join(INCLUDE, "gpop.h"), os.path.join(INCLUDE, "gpop_mlp.h")]
 # status codes
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTSUP = range(6)
 # programs
-BFS_LEVEL, CC_MINLABEL, SSSP_U32, PAGERANK_F32, PPR_F32, CARRY_BFS = range(6)
+BFS_LEVEL, CC_MINLABEL, SSSP_U32, PAGERANK_F32, PPR_F32, CARRY_BFS, BFS_PARENT = range(7)
 PROGRAMS = {"bfs": BFS_LEVEL, "cc": CC_MINLABEL, "sssp": SSSP_U32, "pagerank": PAGERANK_F32,
-            "ppr": PPR_F32, "carry_bfs": CARRY_BFS}
+            "ppr": PPR_F32, "carry_bfs": CARRY_BFS, "bfs_parent": BFS_PARENT}
 COMBINE_LDS, COMBINE_ROUNDS = 0, 1
 COMBINES = {"lds": COMBINE_LDS, "rounds": COMBINE_ROUNDS}
 # selectors

@@ -718,7 +718,7 @@ namespace {
 
 // Argument checks shared by gpop_state_init and gpop_batch_state_init.
 int check_program(const gpop_graph* g, gpop_program prog, const gpop_params* prm) {
-    if ((int)prog < 0 || (int)prog > GPOP_PROG_CARRY_BFS) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
+    if ((int)prog < 0 || (int)prog > GPOP_PROG_BFS_PARENT) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
     const bool rooted = prog != GPOP_PROG_CC_MINLABEL && prog != GPOP_PROG_PAGERANK_F32;
     if (rooted && prm->root >= g->G.V) return fail(GPOP_EINVAL, "root %u >= V", prm->root);
     if (prog == GPOP_PROG_CARRY_BFS && prm->persist == 0) return fail(GPOP_EINVAL, "persist must be >= 1");
@@ -1329,7 +1329,7 @@ int gpop_batch_check(gpop_batch* b, void* stream) {
 int gpop_autotune_candidates(gpop_program prog, uint32_t num_vertices, uint64_t num_edges, gpop_options* out,
                              uint32_t cap, uint32_t* n) {
     if (!out || !n) return fail(GPOP_EINVAL, "NULL argument");
-    if ((int)prog < 0 || (int)prog > GPOP_PROG_CARRY_BFS) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
+    if ((int)prog < 0 || (int)prog > GPOP_PROG_BFS_PARENT) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
     (void)num_edges;
     uint32_t c = 0;
     for (uint32_t lp = 12; lp <= 15; ++lp) {

@@ -137,7 +137,7 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
 #pragma unroll
             for (uint32_t i = 0; i < U; ++i) {
                 const uint32_t u = g0 + 64u * i + lane;
-                const bool hit = mv[i] != kIdentMin && mv[i] < sv[i];
+                const bool hit = mv[i] != kIdentMin && (first_write(PROG) ? sv[i] == kIdentMin : mv[i] < sv[i]);
                 keep[i] = hit;
                 if constexpr (has_carry(PROG)) {
                     const bool in = g0 + 64u * i < wend && u < nv;
@@ -941,7 +941,7 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
         for (uint32_t i = 0; i < kMU; ++i) {
             const uint32_t u = ulo + kMT * i + tid;
             const bool in = i < nu && u < nv;
-            const bool hit = in && m[i] != kIdentMin && m[i] < m0[i];
+            const bool hit = in && m[i] != kIdentMin && (first_write(PROG) ? m0[i] == kIdentMin : m[i] < m0[i]);
             keep[i] = hit;
             if constexpr (has_carry(PROG)) keep[i] = keep[i] || (in && was[i] && (it + 1u - m0[i]) < P.persist);
             if (hit) state[vbase + u] = m[i];
@@ -1178,6 +1178,7 @@ static hipError_t launch_batch_merge_p(const BatchGrid& B, hipStream_t st) {
         case P_PR: return fn<P_PR>(__VA_ARGS__);              \
         case P_PPR: return fn<P_PPR>(__VA_ARGS__);            \
         case P_CARRY: return fn<P_CARRY>(__VA_ARGS__);        \
+        case P_PARENT: return fn<P_PARENT>(__VA_ARGS__);      \
     }                                                         \
     return hipErrorInvalidValue;
 
@@ -1222,6 +1223,7 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
             case P_CC: x = v; break;
             case P_PR: x = __float_as_uint((float)P.inv_n); break;
             case P_PPR: x = __float_as_uint(v == P.root ? 1.0f : 0.0f); break;
+            case P_PARENT: x = v == P.root ? v : 0xFFFFFFFFu; break;
             default: x = v == P.root ? 0u : 0xFFFFFFFFu; break;
         }
         state[v] = x;

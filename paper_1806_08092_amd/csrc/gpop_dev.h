@@ -39,10 +39,14 @@ enum Prog : int {
     P_PR = GPOP_PROG_PAGERANK_F32,
     P_PPR = GPOP_PROG_PPR_F32,
     P_CARRY = GPOP_PROG_CARRY_BFS,
+    P_PARENT = GPOP_PROG_BFS_PARENT,
 };
 
 __host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || prog == P_PPR; }
 __host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP; }
+// gatherFunc sets an unvisited vertex only (BFS parents); the other min
+// programs keep any smaller value
+__host__ __device__ constexpr bool first_write(int prog) { return prog == P_PARENT; }
 // Source-centric tasks per iteration the plan aims for (about half the waves
 // the chip holds); bounded so that a count matrix of 2 x target x k words
 // stays at 64 MB at most.
@@ -293,6 +297,8 @@ __device__ __forceinline__ uint32_t scatter_value(const Dev& G, const uint32_t* 
         return st[v] + 1u;
     } else if constexpr (PROG == P_CC || PROG == P_SSSP) {
         return st[v];
+    } else if constexpr (PROG == P_PARENT) {
+        return v;
     } else {
         const uint32_t* __restrict__ off = gptr(G.off);
         uint32_t deg = off[v + 1] - off[v];

@@ -77,6 +77,45 @@ def test_bfs_levels(zi, sel):
 
 @pytest.mark.parametrize("zi", range(9))
 @pytest.mark.parametrize("sel", SELECTORS)
+def test_bfs_parents(zi, sel):
+    name, g, lp, (G, _) = get_zoo()[zi]
+    for root in roots_of(g):
+        say("bfs_parent", name, sel, "root", root)
+        got, _ = run_program(G, "bfs_parent", g.n, root=root, selector=sel)
+        ref = oracle.bfs_parents(g, root)
+        assert np.array_equal(got, ref), (name, sel, root, np.flatnonzero(got != ref)[:10])
+
+
+@pytest.mark.parametrize("gids,combine", [(256, "lds"), (1024, "lds"), (0, "rounds"), (256, "rounds")])
+def test_bfs_parents_split_gather_and_combines(gids, combine):
+    """Columns split over many gather tasks (partials and merges) and the
+    atomic-free combine give the same least-id parents."""
+    g = gg.rmat_graph(14, 16, 31, symmetric=True)
+    G, _ = make_graph(g, 10, gather_task_ids=gids, combine=combine)
+    for root in roots_of(g, 2):
+        say("bfs_parent split", gids, combine, "root", root)
+        got, _ = run_program(G, "bfs_parent", g.n, root=root)
+        assert np.array_equal(got, oracle.bfs_parents(g, root)), (gids, combine, root)
+
+
+def test_bfs_parents_tree_at_scale():
+    """RMAT-20 (16.8M directed edges), default sizes: bit-exact against the
+    oracle and a valid BFS tree whose depths are the BFS levels."""
+    g = gg.rmat_graph(20, 16, 32)
+    G, _ = make_graph(g, 14)
+    for root in roots_of(g, 2):
+        say("bfs_parent rmat20 root", root)
+        got, iters = run_program(G, "bfs_parent", g.n, root=root)
+        lv = oracle.bfs_levels(g, root)
+        assert np.array_equal(got, oracle.bfs_parents(g, root)), root
+        v = np.nonzero((got != INF) & (np.arange(g.n) != root))[0]
+        assert np.array_equal(got != INF, lv != INF)
+        assert np.all(lv[got[v]].astype(np.int64) == lv[v].astype(np.int64) - 1)
+        assert iters == int(lv[lv != INF].max()) + 1
+
+
+@pytest.mark.parametrize("zi", range(9))
+@pytest.mark.parametrize("sel", SELECTORS)
 def test_sssp(zi, sel):
     name, g, lp, (G, _) = get_zoo()[zi]
     for root in roots_of(g, 2):

@@ -113,6 +113,71 @@ def dfs_min_label(g):
     return np.array(lab, np.uint32)
 
 
+# ---------------------------------------------------------------- BFS parents
+def brute_parents(g, root):
+    """Levels by repeated relaxation over every edge, then for each reached
+    vertex the least in-neighbour one level closer to the root."""
+    n = g.n
+    lv = [INF] * n
+    lv[root] = 0
+    r, c = edge_list(g)
+    changed = True
+    while changed:
+        changed = False
+        for u, v in zip(r.tolist(), c.tolist()):
+            if lv[u] != INF and lv[u] + 1 < lv[v]:
+                lv[v] = lv[u] + 1
+                changed = True
+    par = [INF] * n
+    par[root] = root
+    for v in range(n):
+        if v != root and lv[v] != INF:
+            par[v] = min(u for u, w in zip(r.tolist(), c.tolist()) if w == v and lv[u] == lv[v] - 1)
+    return np.array(par, np.uint32)
+
+
+@pytest.mark.parametrize("gi", range(15))
+def test_bfs_parents_vs_brute_force(gi):
+    g = small_graphs()[gi]
+    for root in range(min(g.n, 6)):
+        assert np.array_equal(oracle.bfs_parents(g, root), brute_parents(g, root))
+
+
+def test_bfs_parents_hand_example():
+    # 0->1 0->2 1->3 2->3 2->4 3->5 4->5 5->0; vertex 6 has no in-edge.
+    g = graph_from_edges(7, [(0, 1), (0, 2), (1, 3), (2, 3), (2, 4), (3, 5), (4, 5), (5, 0)])
+    # from 0: 1, 2 at level 1 (parent 0); 3 at level 2 is offered 1 and 2 -> 1;
+    # 4 is offered 2; 5 at level 3 is offered 3 and 4 -> 3
+    assert oracle.bfs_parents(g, 0).tolist() == [0, 0, 0, 1, 2, 3, INF]
+    # from 2: 3, 4 at level 1; 5 at level 2 (3 and 4 -> 3); 0 at level 3 (5);
+    # 1 at level 4 (0)
+    assert oracle.bfs_parents(g, 2).tolist() == [5, 0, 2, 2, 2, 3, INF]
+
+
+def test_bfs_parents_tree_validation():
+    """Graph500-style checks of the trees at a size brute force cannot reach:
+    the root is its own parent, exactly the reachable vertices have parents,
+    every tree edge is a graph edge going one level down, and the parent is
+    the least such in-neighbour."""
+    g = gg.rmat_graph(12, 8, 78)
+    r, c = edge_list(g)
+    edges = set(zip(r.tolist(), c.tolist()))
+    for root in gg.pick_sources(g.offsets, 5, 4):
+        root = int(root)
+        par = oracle.bfs_parents(g, root)
+        lv = oracle.bfs_levels(g, root)
+        assert par[root] == root
+        reached = lv != INF
+        assert np.array_equal(par != INF, reached)
+        v = np.nonzero(reached & (np.arange(g.n) != root))[0]
+        assert all((int(par[x]), int(x)) in edges for x in v)
+        assert np.all(lv[par[v]].astype(np.int64) == lv[v].astype(np.int64) - 1)
+        ok = (lv[r] != INF) & (lv[c].astype(np.int64) == lv[r].astype(np.int64) + 1)
+        least = np.full(g.n, INF, np.uint64)
+        np.minimum.at(least, c[ok], r[ok].astype(np.uint64))
+        assert np.array_equal(least[v], par[v].astype(np.uint64))
+
+
 @pytest.mark.parametrize("gi", range(15))
 def test_cc_vs_dfs(gi):
     g = small_graphs()[gi]
@@ -322,6 +387,10 @@ def test_gpop_model_matches_textbook(selector, gi):
         assert np.array_equal(np.array(st, np.uint32), oracle.bfs_levels(g, root))
         st, _ = gpop_ref.run(g, q, "sssp", {"root": root}, 10 * g.n + 5, selector)
         assert np.array_equal(np.array(st, np.uint32), oracle.sssp(g, root))
+        # Algorithm 5 as printed (first message wins, in gather order) against
+        # the textbook least-id parent
+        st, _ = gpop_ref.run(g, q, "bfs_parent", {"root": root}, 10 * g.n + 5, selector)
+        assert np.array_equal(np.array(st, np.uint32), oracle.bfs_parents(g, root))
         st, _ = gpop_ref.run(g, q, "ppr", {"seed": root}, 20, selector)
         assert np.allclose(st, oracle.ppr(g, root), rtol=0, atol=1e-13)
     sym = gg.Graph(g.n, *gg.build_csr(g.n, *gg.symmetrize(*edge_list_u32(g))))
