@@ -120,6 +120,10 @@ def load_workload(name):
         g = gg.workload_bfs_cc_rmat22()
         runs = [("bfs", int(s)) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 8)] + [("cc", 0)]
         return g, runs, 14, "BFS levels from 8 sources + min-label CC, RMAT scale 22 ef16 symmetrised"
+    if name == "bfs_parent_rmat22":
+        g = gg.workload_bfs_cc_rmat22()
+        runs = [("bfs_parent", int(s)) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 8)]
+        return g, runs, 14, "BFS parents (least-id parent) from 8 sources, RMAT scale 22 ef16 symmetrised"
     if name == "pagerank_rmat16":
         g = gg.workload_pagerank_rmat16()
         return g, [("pagerank", 0)], 13, "PageRank 10 iterations d=0.85, RMAT scale 16 ef16 directed"
@@ -154,6 +158,9 @@ def cpu_baseline(g, runs, budget_s):
         if prog == "bfs":
             lv = oracle.bfs_levels(g, root)
             edges += int(deg[lv != 0xFFFFFFFF].sum())
+        elif prog == "bfs_parent":
+            par = oracle.bfs_parents(g, root)
+            edges += int(deg[par != 0xFFFFFFFF].sum())
         elif prog == "cc":
             oracle.cc_minlabel(g)
             edges += g.m
@@ -589,7 +596,7 @@ def main():
         b = run_bytes(stats, info.q, info.k, prog == "sssp", prog in ("pagerank", "ppr"))
         for kname in bytes_step:
             bytes_step[kname] += b[kname]
-        if prog in ("bfs", "sssp"):
+        if prog in ("bfs", "sssp", "bfs_parent"):
             reached = st != -1
             edges_per_step += int(deg[reached].sum().item())
         elif prog == "pagerank":
