@@ -61,12 +61,18 @@ typedef enum gpop_program {
     GPOP_PROG_CARRY_BFS = 5,     /* BFS levels where initFunc keeps a reached vertex
                                     active for `persist` iterations (selective
                                     continuity of the active set)                      */
-    GPOP_PROG_BFS_PARENT = 6     /* u32 parent in the BFS tree of the root (Algorithm 5):
+    GPOP_PROG_BFS_PARENT = 6,    /* u32 parent in the BFS tree of the root (Algorithm 5):
                                     scatterFunc sends the vertex id, gatherFunc sets
                                     the parent of an unvisited vertex; of the messages
                                     one iteration brings, the least source id wins
                                     (the first in the paper's gather order); the
                                     root's parent is the root, unreached 0xFFFFFFFF  */
+    GPOP_PROG_NIBBLE_F32 = 7     /* f32 Parallel Nibble (the paper's Nibble application):
+                                    scatterFunc sends PR/(2 deg), initFunc halves PR
+                                    and keeps the vertex iff PR >= eps * deg,
+                                    gatherFunc adds, filterFunc keeps iff
+                                    PR >= eps * deg; a vertex without out-edges is
+                                    never kept. Seed PR = 1, others 0              */
 } gpop_program;
 
 typedef enum gpop_selector {
@@ -133,7 +139,8 @@ typedef struct gpop_params {
     uint32_t persist;    /* CARRY_BFS: iterations a vertex stays active (>=1) */
     float damping;       /* PAGERANK damping d (0.85 in the paper's runs)    */
     float alpha;         /* PPR restart probability                           */
-    uint32_t reserved[4];
+    float epsilon;       /* NIBBLE threshold eps (> 0, finite)                */
+    uint32_t reserved[3];
 } gpop_params;
 
 /* Static per-graph statistics after preprocessing. */

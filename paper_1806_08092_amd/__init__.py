@@ -20,9 +20,9 @@ HEADERS = [os.path.join(INCLUDE, "gpop.h"), os.path.join(INCLUDE, "gpop_mlp.h")]
 # status codes
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTSUP = range(6)
 # programs
-BFS_LEVEL, CC_MINLABEL, SSSP_U32, PAGERANK_F32, PPR_F32, CARRY_BFS, BFS_PARENT = range(7)
+BFS_LEVEL, CC_MINLABEL, SSSP_U32, PAGERANK_F32, PPR_F32, CARRY_BFS, BFS_PARENT, NIBBLE_F32 = range(8)
 PROGRAMS = {"bfs": BFS_LEVEL, "cc": CC_MINLABEL, "sssp": SSSP_U32, "pagerank": PAGERANK_F32,
-            "ppr": PPR_F32, "carry_bfs": CARRY_BFS, "bfs_parent": BFS_PARENT}
+            "ppr": PPR_F32, "carry_bfs": CARRY_BFS, "bfs_parent": BFS_PARENT, "nibble": NIBBLE_F32}
 COMBINE_LDS, COMBINE_ROUNDS = 0, 1
 COMBINES = {"lds": COMBINE_LDS, "rounds": COMBINE_ROUNDS}
 # selectors
@@ -62,7 +62,7 @@ class PlanInfo(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("root", ctypes.c_uint32), ("persist", ctypes.c_uint32),
                 ("damping", ctypes.c_float), ("alpha", ctypes.c_float),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("epsilon", ctypes.c_float), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -259,9 +259,9 @@ class Graph:
         return out
 
     def state_init(self, prog, state, root: int = 0, persist: int = 1, damping: float = 0.85,
-                   alpha: float = 0.15, stream=None):
+                   alpha: float = 0.15, epsilon: float = 1e-6, stream=None):
         prog = PROGRAMS[prog] if isinstance(prog, str) else int(prog)
-        p = Params(root, persist, damping, alpha)
+        p = Params(root, persist, damping, alpha, epsilon)
         _check(lib().gpop_state_init(self.h, prog, ctypes.byref(p), _ptr(state), _stream(stream)))
         self.prog, self.state = prog, state
 
@@ -357,7 +357,7 @@ def autotune_candidates(prog, num_vertices: int, num_edges: int):
 
 def autotune(offsets, cols, weights, prog, root: int = 0, persist: int = 1, damping: float = 0.85,
              alpha: float = 0.15, frontier=None, max_iter: int = 3, reps: int = 2, candidates=None,
-             stream=None):
+             stream=None, epsilon: float = 1e-6):
     """Times the candidates (default: autotune_candidates) through
     gpop_autotune and returns (best options dict, per-candidate list of
     (options, run_ms, prep_ms))."""
@@ -377,7 +377,7 @@ def autotune(offsets, cols, weights, prog, root: int = 0, persist: int = 1, damp
     ws = torch.empty(need + 256, dtype=torch.uint8, device=offsets.device)
     aligned = (ws.data_ptr() + 255) & ~255
     state = torch.empty(n, dtype=torch.int32, device=offsets.device)
-    p = Params(root, persist, damping, alpha)
+    p = Params(root, persist, damping, alpha, epsilon)
     res = TuneResult()
     _check(lib().gpop_autotune(ctypes.byref(desc), prog_id, ctypes.byref(p), _ptr(frontier),
                                0 if frontier is None else frontier.numel(), max_iter, reps, carr, len(cands),
@@ -422,10 +422,10 @@ class Batch:
             pass
 
     def state_init(self, prog, states, roots=None, persist: int = 1, damping: float = 0.85,
-                   alpha: float = 0.15, stream=None):
+                   alpha: float = 0.15, epsilon: float = 1e-6, stream=None):
         prog = PROGRAMS[prog] if isinstance(prog, str) else int(prog)
         roots = [0] * self.n if roots is None else list(roots)
-        prm = (Params * self.n)(*[Params(int(r), persist, damping, alpha) for r in roots])
+        prm = (Params * self.n)(*[Params(int(r), persist, damping, alpha, epsilon) for r in roots])
         ptrs = (ctypes.c_void_p * self.n)(*[s.data_ptr() for s in states])
         _check(lib().gpop_batch_state_init(self.h, prog, prm, ptrs, _stream(stream)))
         self.states = list(states)

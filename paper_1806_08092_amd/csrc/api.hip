@@ -718,7 +718,7 @@ namespace {
 
 // Argument checks shared by gpop_state_init and gpop_batch_state_init.
 int check_program(const gpop_graph* g, gpop_program prog, const gpop_params* prm) {
-    if ((int)prog < 0 || (int)prog > GPOP_PROG_BFS_PARENT) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
+    if ((int)prog < 0 || (int)prog > GPOP_PROG_NIBBLE_F32) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
     const bool rooted = prog != GPOP_PROG_CC_MINLABEL && prog != GPOP_PROG_PAGERANK_F32;
     if (rooted && prm->root >= g->G.V) return fail(GPOP_EINVAL, "root %u >= V", prm->root);
     if (prog == GPOP_PROG_CARRY_BFS && prm->persist == 0) return fail(GPOP_EINVAL, "persist must be >= 1");
@@ -727,6 +727,8 @@ int check_program(const gpop_graph* g, gpop_program prog, const gpop_params* prm
         return fail(GPOP_EINVAL, "damping must be in [0, 1]");
     if (prog == GPOP_PROG_PPR_F32 && !(prm->alpha >= 0.f && prm->alpha <= 1.f))
         return fail(GPOP_EINVAL, "alpha must be in [0, 1]");
+    if (prog == GPOP_PROG_NIBBLE_F32 && !(prm->epsilon > 0.f && std::isfinite(prm->epsilon)))
+        return fail(GPOP_EINVAL, "epsilon must be finite and > 0");
     const bool rounds = g->G.combine == GPOP_COMBINE_ROUNDS;
     if (gather_lds_bytes(prog, g->G.q, rounds) + 2048 > (size_t)max_lds_per_block())
         return fail(GPOP_ENOTSUP, "program %d needs %zu bytes of LDS at q = %u; use a smaller partition",
@@ -739,6 +741,7 @@ void program_params(const gpop_graph* g, const gpop_params* prm, Params* P) {
     P->persist = prm->persist;
     P->damping = prm->damping;
     P->alpha = prm->alpha;
+    P->eps = prm->epsilon;
     P->inv_n = 1.0 / (double)g->G.V;
 }
 
@@ -1329,7 +1332,7 @@ int gpop_batch_check(gpop_batch* b, void* stream) {
 int gpop_autotune_candidates(gpop_program prog, uint32_t num_vertices, uint64_t num_edges, gpop_options* out,
                              uint32_t cap, uint32_t* n) {
     if (!out || !n) return fail(GPOP_EINVAL, "NULL argument");
-    if ((int)prog < 0 || (int)prog > GPOP_PROG_BFS_PARENT) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
+    if ((int)prog < 0 || (int)prog > GPOP_PROG_NIBBLE_F32) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
     (void)num_edges;
     uint32_t c = 0;
     for (uint32_t lp = 12; lp <= 15; ++lp) {

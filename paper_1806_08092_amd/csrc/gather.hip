@@ -155,7 +155,15 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
                 xv[i] = 0.f;
                 if (need[i]) {
                     const double y = (double)(av[i] & ~kCarried) * kInvFix;
-                    if constexpr (PROG == P_PR) {
+                    if constexpr (PROG == P_NIBBLE) {
+                        // initFunc halved the value of a vertex active before
+                        // scatter; any other vertex keeps its value. Both add
+                        // the arrived amount in the same fixed point.
+                        const float old = __uint_as_float(state[v]);
+                        const float base = (av[i] & kCarried) ? old * 0.5f : old;
+                        const unsigned long long b = __double2ull_rn((double)base * kFix);
+                        xv[i] = (float)((double)((av[i] & ~kCarried) + b) * kInvFix);
+                    } else if constexpr (PROG == P_PR) {
                         const double d = (double)P.damping;
                         xv[i] = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
                         keep[i] = true;
@@ -177,6 +185,13 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
             const uint32_t v = vbase + g0 + 64u * i + lane;
             o0[i] = need[i] ? off[v] : 0u;
             o1[i] = need[i] ? off[v + 1] : 0u;
+        }
+        if constexpr (PROG == P_NIBBLE) {  // filterFunc: PR >= eps * deg (never without out-edges)
+#pragma unroll
+            for (uint32_t i = 0; i < U; ++i) {
+                const uint32_t d = o1[i] - o0[i];
+                keep[i] = need[i] && d > 0u && xv[i] >= P.eps * (float)d;
+            }
         }
 #pragma unroll
         for (uint32_t i = 0; i < U; ++i) {
@@ -959,7 +974,12 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
             need[i] = in && (a[i] != 0ull || was[i]);  // received an amount, or was active before scatter
             if (need[i]) {
                 const double y = (double)a[i] * kInvFix;
-                if constexpr (PROG == P_PR) {
+                if constexpr (PROG == P_NIBBLE) {
+                    const float old = __uint_as_float(state[v]);
+                    const float base = was[i] ? old * 0.5f : old;
+                    const unsigned long long b = __double2ull_rn((double)base * kFix);
+                    xv[i] = (float)((double)(a[i] + b) * kInvFix);
+                } else if constexpr (PROG == P_PR) {
                     const double d = (double)P.damping;
                     xv[i] = (float)((1.0 - d) * P.inv_n + d * (y + dang * P.inv_n));
                     keep[i] = true;
@@ -979,6 +999,13 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
         const uint32_t v = vbase + ulo + kMT * i + tid;
         o0[i] = need[i] ? off[v] : 0u;
         o1[i] = need[i] ? off[v + 1] : 0u;
+    }
+    if constexpr (PROG == P_NIBBLE) {  // filterFunc: PR >= eps * deg (never without out-edges)
+#pragma unroll
+        for (uint32_t i = 0; i < kMU; ++i) {
+            const uint32_t d = o1[i] - o0[i];
+            keep[i] = need[i] && d > 0u && xv[i] >= P.eps * (float)d;
+        }
     }
 #pragma unroll
     for (uint32_t i = 0; i < kMU; ++i) {
@@ -1179,6 +1206,7 @@ static hipError_t launch_batch_merge_p(const BatchGrid& B, hipStream_t st) {
         case P_PPR: return fn<P_PPR>(__VA_ARGS__);            \
         case P_CARRY: return fn<P_CARRY>(__VA_ARGS__);        \
         case P_PARENT: return fn<P_PARENT>(__VA_ARGS__);      \
+        case P_NIBBLE: return fn<P_NIBBLE>(__VA_ARGS__);      \
     }                                                         \
     return hipErrorInvalidValue;
 
@@ -1224,6 +1252,7 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
             case P_PR: x = __float_as_uint((float)P.inv_n); break;
             case P_PPR: x = __float_as_uint(v == P.root ? 1.0f : 0.0f); break;
             case P_PARENT: x = v == P.root ? v : 0xFFFFFFFFu; break;
+            case P_NIBBLE: x = __float_as_uint(v == P.root ? 1.0f : 0.0f); break;
             default: x = v == P.root ? 0u : 0xFFFFFFFFu; break;
         }
         state[v] = x;

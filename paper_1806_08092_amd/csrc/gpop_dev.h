@@ -40,9 +40,10 @@ enum Prog : int {
     P_PPR = GPOP_PROG_PPR_F32,
     P_CARRY = GPOP_PROG_CARRY_BFS,
     P_PARENT = GPOP_PROG_BFS_PARENT,
+    P_NIBBLE = GPOP_PROG_NIBBLE_F32,
 };
 
-__host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || prog == P_PPR; }
+__host__ __device__ constexpr bool is_sum(int prog) { return prog == P_PR || prog == P_PPR || prog == P_NIBBLE; }
 __host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP; }
 // gatherFunc sets an unvisited vertex only (BFS parents); the other min
 // programs keep any smaller value
@@ -164,6 +165,7 @@ struct Dev {
 struct Params {
     uint32_t root, persist;
     float damping, alpha;
+    float eps;                // Nibble threshold
     double inv_n;             // 1 / V
     uint32_t selector;        // gpop_selector
     uint32_t s_i, s_v;        // model element sizes (bytes)
@@ -299,6 +301,11 @@ __device__ __forceinline__ uint32_t scatter_value(const Dev& G, const uint32_t* 
         return st[v];
     } else if constexpr (PROG == P_PARENT) {
         return v;
+    } else if constexpr (PROG == P_NIBBLE) {
+        const uint32_t* __restrict__ off = gptr(G.off);
+        const uint32_t deg = off[v + 1] - off[v];
+        const float x = __uint_as_float(st[v]);
+        return __float_as_uint(deg ? (x * 0.5f) / (float)deg : 0.0f);
     } else {
         const uint32_t* __restrict__ off = gptr(G.off);
         uint32_t deg = off[v + 1] - off[v];

@@ -844,6 +844,7 @@ static hipError_t launch_batch_pc_p(const BatchGrid& B, hipStream_t st) {
         case P_PPR: return fn<P_PPR>(__VA_ARGS__);            \
         case P_CARRY: return fn<P_CARRY>(__VA_ARGS__);        \
         case P_PARENT: return fn<P_PARENT>(__VA_ARGS__);      \
+        case P_NIBBLE: return fn<P_NIBBLE>(__VA_ARGS__);      \
     }                                                         \
     return hipErrorInvalidValue;
 

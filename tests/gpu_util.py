@@ -19,14 +19,14 @@ def make_graph(g, log2_part, sc_task_log2=0, gather_task_ids=0, combine="lds"):
 
 
 def run_program(G, prog, n, root=0, persist=1, selector="analytical", max_iter=1 << 20,
-                damping=0.85, alpha=0.15, bw_ratio=2.0, frontier=None):
+                damping=0.85, alpha=0.15, bw_ratio=2.0, frontier=None, epsilon=1e-6):
     """Runs one program to completion (or max_iter) and returns the state as
     a numpy array (uint32 or float32) plus the iterations run."""
     torch = torch_cuda()
     import paper_1806_08092_amd as gp
     st = torch.empty(n, dtype=torch.int32, device="cuda")
     G.set_selector(selector, bw_ratio)
-    G.state_init(prog, st, root=root, persist=persist, damping=damping, alpha=alpha)
+    G.state_init(prog, st, root=root, persist=persist, damping=damping, alpha=alpha, epsilon=epsilon)
     if frontier is not None:
         G.set_frontier(torch.as_tensor(np.asarray(frontier, np.int32), device="cuda"))
     elif prog in ("cc", "pagerank"):
@@ -37,7 +37,7 @@ def run_program(G, prog, n, root=0, persist=1, selector="analytical", max_iter=1
     G.check()
     torch.cuda.synchronize()
     out = st.cpu().numpy()
-    if prog in ("pagerank", "ppr"):
+    if prog in ("pagerank", "ppr", "nibble"):
         return out.view(np.float32), iters
     return out.view(np.uint32), iters
 

@@ -114,6 +114,47 @@ def test_bfs_parents_tree_at_scale():
         assert iters == int(lv[lv != INF].max()) + 1
 
 
+_NIBBLE_REF = {}
+
+
+def nibble_ref(key, g, q, seed, eps, max_iter):
+    """The oracle's Nibble (kernel precision), cached: the mode never changes
+    the result, so one oracle run serves every selector."""
+    if key not in _NIBBLE_REF:
+        st, tr = gpop_ref.run(g, q, "nibble", {"root": seed, "eps": eps}, max_iter)
+        _NIBBLE_REF[key] = (np.array(st, np.float32), len(tr))
+    return _NIBBLE_REF[key]
+
+
+@pytest.mark.parametrize("zi", [0, 2, 3, 4, 5, 7])
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_nibble(zi, sel):
+    """Parallel Nibble: frontier decisions are threshold tests on FP32 values,
+    so the result is compared bit for bit with the oracle computing in the
+    kernel's precision, iteration count included."""
+    name, g, lp, (G, _) = get_zoo()[zi]
+    for seed in roots_of(g, 2):
+        for eps in (1e-3, 2e-5):
+            say("nibble", name, sel, seed, eps)
+            got, iters = run_program(G, "nibble", g.n, root=seed, selector=sel, epsilon=eps, max_iter=80)
+            ref, n_it = nibble_ref((name, seed, eps), g, 1 << lp, seed, eps, 80)
+            assert iters == n_it, (name, sel, seed, eps, iters, n_it)
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (
+                name, sel, seed, eps, np.flatnonzero(got != ref)[:10])
+
+
+@pytest.mark.parametrize("gids,combine", [(256, "lds"), (0, "rounds")])
+def test_nibble_split_gather_and_combines(gids, combine):
+    g = gg.rmat_graph(12, 8, 33, symmetric=True)
+    G, _ = make_graph(g, 9, gather_task_ids=gids, combine=combine)
+    seed = roots_of(g, 1)[0]
+    say("nibble split", gids, combine, seed)
+    got, iters = run_program(G, "nibble", g.n, root=seed, epsilon=1e-4, max_iter=40)
+    ref, n_it = nibble_ref(("rmat12sym", seed, 1e-4), g, 1 << 9, seed, 1e-4, 40)
+    assert iters == n_it
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
 @pytest.mark.parametrize("zi", range(9))
 @pytest.mark.parametrize("sel", SELECTORS)
 def test_sssp(zi, sel):

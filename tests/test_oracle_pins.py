@@ -178,6 +178,88 @@ def test_bfs_parents_tree_validation():
         assert np.array_equal(least[v], par[v].astype(np.uint64))
 
 
+# ---------------------------------------------------------------- Parallel Nibble
+def nibble_fp64(g, seed, eps, max_iter):
+    """The Nibble iteration in FP64, written out directly on the edge list
+    (no partitions, no fixed point): returns the values, the frontier after
+    every iteration and the least relative distance of any threshold test
+    from its threshold."""
+    n = g.n
+    deg = np.diff(g.offsets.astype(np.int64))
+    r, c = edge_list(g)
+    pr = np.zeros(n)
+    pr[seed] = 1.0
+    active = [seed]
+    fronts, margin = [], np.inf
+
+    def test(x, d):
+        nonlocal margin
+        if d == 0:
+            return False
+        margin = min(margin, abs(x - eps * d) / (eps * d))
+        return x >= eps * d
+
+    for _ in range(max_iter):
+        if not active:
+            break
+        act = np.zeros(n, bool)
+        act[active] = True
+        send = np.where(act & (deg > 0), pr / (2 * np.maximum(deg, 1)), 0.0)
+        m = act[r]
+        inbox = np.zeros(n)
+        np.add.at(inbox, c[m], send[r[m]])
+        got = np.zeros(n, bool)
+        got[c[m]] = True
+        pr[act] *= 0.5
+        carried = [v for v in active if test(pr[v], deg[v])]
+        pr += inbox
+        cand = sorted(set(carried) | set(np.flatnonzero(got).tolist()))
+        active = [v for v in cand if test(pr[v], deg[v])]
+        fronts.append(active)
+    return pr, fronts, margin
+
+
+@pytest.mark.parametrize("gi", [0, 1, 4, 7, 12])
+def test_nibble_model_vs_fp64(gi):
+    """The model in the kernel's precision follows the FP64 iteration: same
+    frontiers wherever no threshold test is closer than 1e-3 to its
+    threshold, values within FP32 rounding, total mass 1 (a seed without
+    out-edges keeps half)."""
+    g = small_graphs()[gi]
+    checked = 0
+    for seed in range(min(3, g.n)):
+        for eps in (1e-2, 3e-3, 1e-3):
+            ref, fronts, margin = nibble_fp64(g, seed, eps, 60)
+            if margin < 1e-3:
+                continue
+            st, tr = gpop_ref.run(g, 8, "nibble", {"root": seed, "eps": eps}, 60)
+            assert [t.frontier_out for t in tr] == fronts
+            x = np.array(st, np.float64)
+            assert np.allclose(x, ref, rtol=1e-5, atol=1e-9)
+            # mass moves along edges; only a seed without out-edges loses
+            # the half initFunc takes from it
+            assert abs(x.sum() - (1.0 if g.degrees()[seed] > 0 else 0.5)) < 1e-5
+            checked += 1
+    assert checked > 0
+
+
+def test_nibble_closed_forms():
+    # a star of 8 leaves around 0, both directions: after the first
+    # iteration the centre holds 1/2 and every leaf 1/16, a fixed point
+    g = graph_from_edges(9, [(0, i) for i in range(1, 9)] + [(i, 0) for i in range(1, 9)])
+    for t in (1, 2, 5):
+        st, tr = gpop_ref.run(g, 4, "nibble", {"root": 0, "eps": 1e-3}, t)
+        assert len(tr) == t
+        assert np.array_equal(np.array(st, np.float32), np.array([0.5] + [1 / 16] * 8, np.float32))
+    # one edge both ways: the seed keeps 1/2 and sends 1/2, then both stay
+    # at 1/2; with eps above 1/2 the seed stops after its first scatter
+    g = graph_from_edges(2, [(0, 1), (1, 0)])
+    st, tr = gpop_ref.run(g, 4, "nibble", {"root": 0, "eps": 0.1}, 3)
+    assert np.array_equal(np.array(st, np.float32), np.array([0.5, 0.5], np.float32)) and len(tr) == 3
+    st, tr = gpop_ref.run(g, 4, "nibble", {"root": 0, "eps": 0.75}, 10)
+    assert np.array_equal(np.array(st, np.float32), np.array([0.5, 0.5], np.float32)) and len(tr) == 1
+
+
 @pytest.mark.parametrize("gi", range(15))
 def test_cc_vs_dfs(gi):
     g = small_graphs()[gi]
