@@ -124,6 +124,11 @@ def load_workload(name):
         g = gg.workload_bfs_cc_rmat22()
         runs = [("bfs_parent", int(s)) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 8)]
         return g, runs, 14, "BFS parents (least-id parent) from 8 sources, RMAT scale 22 ef16 symmetrised"
+    if name == "nibble_rmat22":
+        g = gg.workload_bfs_cc_rmat22()
+        runs = [("nibble", int(s)) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 8)]
+        return g, runs, 13, ("Parallel Nibble eps=1e-9, at most 20 iterations, from 8 seeds, RMAT scale 22 ef16 "
+                             "symmetrised")
     if name == "pagerank_rmat16":
         g = gg.workload_pagerank_rmat16()
         return g, [("pagerank", 0)], 13, "PageRank 10 iterations d=0.85, RMAT scale 16 ef16 directed"
@@ -189,7 +194,7 @@ def _time_runs(G, st, runs, reps, deg, n, m):
     traversed-edge count of one pass and ms per program family."""
     import torch
     roots = {r: torch.tensor([r], dtype=torch.int32, device="cuda") for _, r in runs}
-    max_iter = {"pagerank": 10, "ppr": 20}
+    max_iter = {"pagerank": 10, "ppr": 20, "nibble": 20}
     per = {}
     edges = 0
     for rep in range(reps + 1):  # the first pass is the warm-up
@@ -542,10 +547,10 @@ def main():
     G.set_selector(args.selector, args.bw_ratio)
     st = torch.empty(g.n, dtype=torch.int32, device="cuda")
     roots = {r: torch.tensor([r], dtype=torch.int32, device="cuda") for _, r in runs}
-    max_iter = {"pagerank": 10, "ppr": 20}
+    max_iter = {"pagerank": 10, "ppr": 20, "nibble": 20}
 
     def do_run(prog, root):
-        G.state_init(prog, st, root=root)
+        G.state_init(prog, st, root=root, epsilon=1e-9)
         if prog in ("cc", "pagerank"):
             G.set_frontier_all()
         else:
@@ -593,12 +598,14 @@ def main():
         iters = do_run(prog, root)
         iters_per_run.append(iters)
         stats = G.iter_stats()
-        b = run_bytes(stats, info.q, info.k, prog == "sssp", prog in ("pagerank", "ppr"))
+        b = run_bytes(stats, info.q, info.k, prog == "sssp", prog in ("pagerank", "ppr", "nibble"))
         for kname in bytes_step:
             bytes_step[kname] += b[kname]
         if prog in ("bfs", "sssp", "bfs_parent"):
             reached = st != -1
             edges_per_step += int(deg[reached].sum().item())
+        elif prog == "nibble":  # out-edges of the active vertices, every iteration
+            edges_per_step += sum(r["active_edges"] for r in stats)
         elif prog == "pagerank":
             edges_per_step += 10 * g.m
         else:
