@@ -85,6 +85,33 @@ def test_batch_ppr_seeds_bitwise_equal_single_runs():
         assert np.array_equal(got.view(np.uint32), single.view(np.uint32))
 
 
+@pytest.mark.parametrize("eager", [False, True])
+def test_batch_bfs_parents_and_nibble_equal_single_runs(eager):
+    """The two newest programs batched over seeds: BFS parents against the
+    oracle, and both bitwise against single runs (iteration counts too)."""
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    g = gg.rmat_graph(12, 8, seed=gg.BASE_SEED + 84, symmetric=True)
+    G, _ = make_graph(g, 9)
+    seeds = [int(s) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED + 6, 8)]
+    B = gp.Batch([G] * len(seeds))
+    st = _states(torch, g.n, len(seeds))
+    for prog, kw in (("bfs_parent", {}), ("nibble", {"epsilon": 1e-5})):
+        B.state_init(prog, st, roots=seeds, **kw)
+        for i, s in enumerate(seeds):
+            B.set_frontier(i, torch.tensor([s], dtype=torch.int32, device="cuda"))
+        iters = B.run(max_iter=40, eager=eager)
+        B.check()
+        torch.cuda.synchronize()
+        for i, s in enumerate(seeds):
+            got = st[i].cpu().numpy().view(np.uint32)
+            if prog == "bfs_parent":
+                assert np.array_equal(got, oracle.bfs_parents(g, s)), (prog, i)
+            single, single_iters = run_program(G, prog, g.n, root=s, max_iter=40, **kw)
+            assert np.array_equal(got, single.view(np.uint32)), (prog, i)
+            assert iters[i] == single_iters, (prog, i)
+
+
 def _uneven_graphs(symmetric):
     """Directed graphs for PageRank; min-label CC needs symmetric ones."""
     out = []
