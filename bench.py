@@ -151,35 +151,44 @@ def load_workload(name):
 
 
 def cpu_baseline(g, runs, budget_s):
-    """The oracle (single-threaded C) on the same graph: runs of the step in
-    order until the time budget is spent. Returns GTEPS and the sample."""
-    import numpy as np
+    """The oracle (single-threaded C) on the same graph: whole steps (the runs
+    in order), repeated until about 10 s of work are done or the budget is
+    spent. Returns GTEPS and the sample, or None for a program the C oracle
+    does not cover."""
     import oracle
+    if any(prog not in ("bfs", "bfs_parent", "cc", "sssp", "pagerank") for prog, _ in runs):
+        return None
     deg = g.degrees()
     edges = 0
-    done = []
+    done = 0
     t0 = time.perf_counter()
-    for prog, root in runs:
-        if prog == "bfs":
-            lv = oracle.bfs_levels(g, root)
-            edges += int(deg[lv != 0xFFFFFFFF].sum())
-        elif prog == "bfs_parent":
-            par = oracle.bfs_parents(g, root)
-            edges += int(deg[par != 0xFFFFFFFF].sum())
-        elif prog == "cc":
-            oracle.cc_minlabel(g)
-            edges += g.m
-        elif prog == "sssp":
-            d = oracle.sssp(g, root)
-            edges += int(deg[d != 0xFFFFFFFF].sum())
-        elif prog == "pagerank":
-            oracle.pagerank(g, 0.85, 10)
-            edges += 10 * g.m
-        done.append("%s(%d)" % (prog, root))
-        if time.perf_counter() - t0 > budget_s:
+    while True:
+        for prog, root in runs:
+            if prog == "bfs":
+                lv = oracle.bfs_levels(g, root)
+                edges += int(deg[lv != 0xFFFFFFFF].sum())
+            elif prog == "bfs_parent":
+                par = oracle.bfs_parents(g, root)
+                edges += int(deg[par != 0xFFFFFFFF].sum())
+            elif prog == "cc":
+                oracle.cc_minlabel(g)
+                edges += g.m
+            elif prog == "sssp":
+                d = oracle.sssp(g, root)
+                edges += int(deg[d != 0xFFFFFFFF].sum())
+            else:
+                oracle.pagerank(g, 0.85, 10)
+                edges += 10 * g.m
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        el = time.perf_counter() - t0
+        if el > min(10.0, budget_s):
             break
     dt = time.perf_counter() - t0
-    return edges / dt / 1e9, "oracle " + " ".join(done) + " in %.1f s" % dt
+    step = " ".join("%s(%d)" % r for r in runs)
+    return edges / dt / 1e9, "oracle, %d runs of the step [%s] (%d full steps) in %.1f s" % (
+        done, step, done // len(runs), dt)
 
 
 # ------------------------------------------------------ selector evaluation
@@ -674,9 +683,10 @@ def main():
         del a, b
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        v, sample = cpu_baseline(g, runs, args.cpu_budget)
-        out["cpu_baseline"] = {"value": v, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-                               "sample": sample}
+        cb = cpu_baseline(g, runs, args.cpu_budget)
+        if cb is not None:
+            out["cpu_baseline"] = {"value": cb[0], "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                                   "sample": cb[1]}
     print(json.dumps(out), flush=True)
 
 
