@@ -197,11 +197,13 @@ int gpop_graph_get_info(const struct gpop_graph* g, gpop_graph_info* out);
 /* ---------------------------------------------------------------- program */
 
 /* Binds `prog` and the caller's state array (V x 4 bytes: u32 for the integer
- * programs, f32 for the PageRank family) and writes its initial values
- * (initial val[] of each application in the applications section; PageRank
- * 1/V, PPR e_seed, CC v, BFS/SSSP/CARRY infinity except root = 0). Clears the
+ * programs, f32 for the PageRank family and Nibble) and writes its initial
+ * values (initial val[] of each application in the applications section;
+ * PageRank 1/V, PPR e_seed, Nibble e_seed, CC v, BFS/SSSP/CARRY infinity
+ * except root = 0, BFS_PARENT 0xFFFFFFFF except root = root). Clears the
  * frontier and the iteration counter. Errors: GPOP_EINVAL for a bad program,
- * root >= V, persist = 0 or a weighted program on an unweighted graph. */
+ * root >= V, persist = 0, a weighted program on an unweighted graph, damping
+ * or alpha outside [0, 1], or a Nibble epsilon that is not finite and > 0. */
 int gpop_state_init(struct gpop_graph* g, gpop_program prog, const gpop_params* prm,
                     void* d_state, void* stream);
 
