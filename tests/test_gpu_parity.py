@@ -332,6 +332,22 @@ def test_bad_frontier_vertex_reported():
     G.check()  # cleared
 
 
+def test_program_parameters_rejected():
+    """Bad program parameters fail state_init with EINVAL and change nothing."""
+    import torch
+    import paper_1806_08092_amd as gp
+    name, g, lp, (G, _) = get_zoo()[0]
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for prog, kw in (("nibble", {"epsilon": 0.0}), ("nibble", {"epsilon": float("nan")}),
+                     ("nibble", {"epsilon": -1e-3}), ("bfs_parent", {"root": g.n}),
+                     ("carry_bfs", {"persist": 0}), ("ppr", {"alpha": 1.5}), (99, {})):
+        with pytest.raises(gp.GpopError) as e:
+            G.state_init(prog, st, **kw)
+        assert e.value.code == gp.EINVAL, (prog, kw)
+    got, _ = run_program(G, "nibble", g.n, root=0, epsilon=1e-3)
+    assert np.isfinite(got).all()
+
+
 def test_max_iter_partial_state():
     name, g, lp, (G, _) = get_zoo()[3]  # path: one level per iteration
     got, iters = run_program(G, "bfs", g.n, root=0, max_iter=5)
