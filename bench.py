@@ -279,6 +279,9 @@ def selector_eval(args):
         del G, off, cols, w, st
         torch.cuda.empty_cache()
     data = learned.Samples.concat(parts)
+    # gather cost per id fitted separately for source- and partition-centric ids
+    data, c_sc, c_pc = learned.relabel_by_id_kind(data)
+    log("gather cost per id: %.3g us (SC ids), %.3g us (PC ids)" % (c_sc, c_pc))
     t = time.perf_counter()
     mlp = learned.train(data, gg.mlp_init_params(gg.BASE_SEED), steps=args.train_steps, batch=4096,
                         lr=1e-3, seed=1)
@@ -295,7 +298,7 @@ def selector_eval(args):
            "eq1_ratio2_us": learned.choice_cost(learned.analytical_choice(data, 2.0), data),
            "eq1_default16_us": learned.choice_cost(learned.analytical_choice(data, 16.0), data),
            "eq1_fitted_us": learned.choice_cost(learned.analytical_choice(data, ratio), data),
-           "fitted_ratio": ratio}
+           "fitted_ratio": ratio, "gather_us_per_sc_id": c_sc, "gather_us_per_pc_id": c_pc}
     log("trained on %d rows in %.1f s: %s" % (len(data), train_s, fit))
     # decision threshold: timed whole runs (BFS from 2 sources + CC) on the
     # two largest training graphs, with the partition sizes of their rows

@@ -30,12 +30,26 @@ class Samples:
     it: np.ndarray       # n int32, iteration of the row
     tot_sc: List[float]  # whole SC / PC scatter time of each iteration
     tot_pc: List[float]
+    # with gather costs: the scatter-only times of the rows, and per iteration
+    # the measured gather + merge time (us) with the ids each mode sent
+    s_sc: Optional[np.ndarray] = None
+    s_pc: Optional[np.ndarray] = None
+    g_us: Optional[np.ndarray] = None
+    g_sc_ids: Optional[np.ndarray] = None
+    g_pc_ids: Optional[np.ndarray] = None
 
     @staticmethod
     def concat(parts: List["Samples"]) -> "Samples":
-        return Samples(np.concatenate([p.x for p in parts]), np.concatenate([p.t_sc for p in parts]),
-                       np.concatenate([p.t_pc for p in parts]), np.concatenate([p.it for p in parts]),
-                       sum((p.tot_sc for p in parts), []), sum((p.tot_pc for p in parts), []))
+        out = Samples(np.concatenate([p.x for p in parts]), np.concatenate([p.t_sc for p in parts]),
+                      np.concatenate([p.t_pc for p in parts]), np.concatenate([p.it for p in parts]),
+                      sum((p.tot_sc for p in parts), []), sum((p.tot_pc for p in parts), []))
+        if all(p.g_us is not None for p in parts):
+            # rows point at their iteration in the concatenated per-iteration arrays
+            base = np.cumsum([0] + [len(p.g_us) for p in parts[:-1]])
+            out.it = np.concatenate([p.it + b for p, b in zip(parts, base)]).astype(np.int32)
+            for f in ("s_sc", "s_pc", "g_us", "g_sc_ids", "g_pc_ids"):
+                setattr(out, f, np.concatenate([getattr(p, f) for p in parts]))
+        return out
 
     def __len__(self):
         return self.x.shape[0]
@@ -47,6 +61,7 @@ def collect(G, max_iter: int = 1 << 20, stream=None, gather_cost: bool = True) -
     the iterations run with profiling on, and each row's mode costs include
     the modelled gather time of the ids the mode sends."""
     xs, tsc, tpc, its, tot_sc, tot_pc = [], [], [], [], [], []
+    ssc, spc, gus, gsi, gpi = [], [], [], [], []
     if gather_cost:
         G.profile_enable(True)
     try:
@@ -67,6 +82,11 @@ def collect(G, max_iter: int = 1 << 20, stream=None, gather_cost: bool = True) -
                 rec = G.iter_stats(stream)[-1]
                 ids = rec["sc_ids"] + rec["pc_ids"]
                 per_id = g_ms * 1e3 / ids if ids else 0.0
+                ssc.append(a.astype(np.float32))
+                spc.append(b.astype(np.float32))
+                gus.append(g_ms * 1e3)
+                gsi.append(rec["sc_ids"])
+                gpi.append(rec["pc_ids"])
                 a = a + per_id * np.expm1(f[act, 1].astype(np.float64))   # E_a ids
                 b = b + per_id * np.expm1(f[act, 2].astype(np.float64))   # E^p ids
             xs.append(f[act])
@@ -81,8 +101,32 @@ def collect(G, max_iter: int = 1 << 20, stream=None, gather_cost: bool = True) -
     if not xs:
         return Samples(np.zeros((0, MLP_IN), np.float32), np.zeros(0, np.float32), np.zeros(0, np.float32),
                        np.zeros(0, np.int32), [], [])
-    return Samples(np.concatenate(xs).astype(np.float32), np.concatenate(tsc), np.concatenate(tpc),
-                   np.concatenate(its), tot_sc, tot_pc)
+    out = Samples(np.concatenate(xs).astype(np.float32), np.concatenate(tsc), np.concatenate(tpc),
+                  np.concatenate(its), tot_sc, tot_pc)
+    if gather_cost:
+        out.s_sc, out.s_pc = np.concatenate(ssc), np.concatenate(spc)
+        out.g_us = np.array(gus, np.float64)
+        out.g_sc_ids = np.array(gsi, np.float64)
+        out.g_pc_ids = np.array(gpi, np.float64)
+    return out
+
+
+def relabel_by_id_kind(data: Samples):
+    """Gather cost per id fitted separately for the ids of source-centric
+    bins and of partition-centric bins: the measured gather + merge time of
+    every training iteration against the two id counts, non-negative least
+    squares without intercept. Relabels every row as its scatter time plus
+    the ids its mode sends times that mode's fitted cost. Returns (samples,
+    us per SC id, us per PC id)."""
+    from scipy.optimize import nnls
+    A = np.stack([data.g_sc_ids, data.g_pc_ids], axis=1)
+    (c_sc, c_pc), _ = nnls(A, data.g_us)
+    ea = np.expm1(data.x[:, 1].astype(np.float64))   # E_a ids (source-centric)
+    ep = np.expm1(data.x[:, 2].astype(np.float64))   # E^p ids (partition-centric)
+    out = Samples(data.x, (data.s_sc + c_sc * ea).astype(np.float32), (data.s_pc + c_pc * ep).astype(np.float32),
+                  data.it, data.tot_sc, data.tot_pc, data.s_sc, data.s_pc, data.g_us, data.g_sc_ids,
+                  data.g_pc_ids)
+    return out, float(c_sc), float(c_pc)
 
 
 def train(data: Samples, init_params: np.ndarray, steps: int = 2000, batch: int = 4096, lr: float = 1e-3,
@@ -121,21 +165,30 @@ def analytical_choice(data: Samples, bw_ratio: float = 16.0) -> np.ndarray:
     return data.x[:, 11].astype(np.float64) <= math.log(bw_ratio)
 
 
-def calibrate_offset(mlp, time_runs, offsets=(-1.0, 0.0, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0), stream=None):
+def calibrate_offset(mlp, time_runs, offsets=(-1.0, 0.0, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0), stream=None,
+                     min_gain: float = 0.01):
     """Moves the network's decision threshold to where whole runs are
     fastest. The per-row labels price each mode with every partition
     scattering in it, so they miss how modes interact in one iteration; the
     threshold corrects the resulting bias. Each candidate offset is added to
     the output bias in turn (Mlp.shift_logit), time_runs() times whole runs
     on training graphs (ms), and the fastest offset stays in the model (the
-    one nearer 0 on a tie). Returns (offset, {offset: ms})."""
+    one nearer 0 on a tie). An offset must beat no offset by min_gain (a
+    fraction of its time), or the network stays as trained: smaller
+    differences are timing noise. Returns (offset, {offset: ms})."""
     cur = 0.0
     res = {}
     for d in offsets:
         mlp.shift_logit(float(d) - cur, stream)
         cur = float(d)
         res[float(d)] = float(time_runs())
+    if 0.0 not in res:
+        mlp.shift_logit(0.0 - cur, stream)
+        cur = 0.0
+        res[0.0] = float(time_runs())
     best = min(res, key=lambda d: (res[d], abs(d)))
+    if res[best] > res[0.0] * (1.0 - min_gain):
+        best = 0.0
     mlp.shift_logit(best - cur, stream)
     return best, res
 
