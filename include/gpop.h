@@ -44,7 +44,7 @@ typedef enum gpop_status {
     GPOP_ENOMEM = 2,    /* workspace smaller than gpop_plan() asked for     */
     GPOP_EDEVICE = 3,   /* a HIP runtime call failed                        */
     GPOP_ESTATE = 4,    /* call out of order (e.g. iterate before init)     */
-    GPOP_ENOTSUP = 5    /* valid request this build does not support        */
+    GPOP_ENOTSUP = 5    /* valid request this library does not support      */
 } gpop_status;
 
 /* Programs: the user functions of the programming-interface section

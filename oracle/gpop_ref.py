@@ -13,7 +13,7 @@ Follows the paper's own structure, for tiny graphs only:
   received messages or kept carried vertices, then filterFunc (Algorithm 2);
 * the analytical mode model (performance modelling, Sec. 3.2, Eq. 1).
 
-Readings taken where the paper is silent (each is listed in the design doc):
+Readings taken where the paper is silent:
   - inactive vertices of a partition-centric partition send the combine's
     identity, and gather ignores identity messages (no combine, no
     activation), so the mode never changes results;
