@@ -147,6 +147,20 @@ def load_workload(name):
         g = gg.rmat_graph(25, 16, seed=gg.BASE_SEED + 7, symmetric=True)
         runs = [("bfs", int(s)) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 8)] + [("cc", 0)]
         return g, runs, 14, "BFS levels from 8 sources + min-label CC, RMAT scale 25 ef16 symmetrised"
+    if name == "bfs_cc_rmat22_perm":
+        # the default workload's graph and sources under a random relabelling
+        # of the vertices: same traversal, no id locality
+        g0 = gg.workload_bfs_cc_rmat22()
+        g, perm = gg.permute_vertices(g0, gg.BASE_SEED + 8)
+        runs = [("bfs", int(perm[s])) for s in gg.pick_sources(g0.offsets, gg.SOURCE_SEED, 8)] + [("cc", 0)]
+        return g, runs, 14, ("BFS levels from 8 sources + min-label CC, RMAT scale 22 ef16 symmetrised, vertex ids "
+                             "randomly permuted")
+    if name.startswith("pagerank_rmat22_ef"):
+        ef = int(name[len("pagerank_rmat22_ef"):])
+        if ef < 1 or ef > 128:
+            raise SystemExit("edge factor must be 1..128")
+        g = gg.rmat_graph(22, ef, seed=gg.BASE_SEED + 9)
+        return g, [("pagerank", 0)], 13, "PageRank 10 iterations d=0.85, RMAT scale 22 ef%d directed" % ef
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -554,6 +568,10 @@ def main():
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - t) * 1e3
     info = G.info()
+    inter_frac = None
+    if g.m <= (1 << 28):
+        import graphgen as gg
+        inter_frac = gg.inter_partition_fraction(g, int(info.q).bit_length() - 1)
     log("preprocessed in %.1f ms: q=%d k=%d M=%d bins=%d" % (prep_ms, info.q, info.k, info.num_messages,
                                                              info.nonempty_bins))
     G.set_selector(args.selector, args.bw_ratio)
@@ -658,7 +676,8 @@ def main():
                    "gather_task_ids": args.gather_task_ids, "sc_task_log2": args.sc_task_log2,
                    "runs_per_step": len(runs), "iterations_per_run": iters_per_run,
                    "edges_traversed_per_step": edges_per_step, "preprocess_ms": prep_ms,
-                   "profiled_ms_per_step": prof_ms_per_step},
+                   "profiled_ms_per_step": prof_ms_per_step, "pc_messages": info.num_messages,
+                   "nonempty_bins": info.nonempty_bins, "inter_partition_fraction": inter_frac},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS, "traffic": traffic,
                      "alg_bytes_per_launch": bytes_step[dom] / per_kernel[dom]["launches_per_step"]},

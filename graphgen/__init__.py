@@ -157,6 +157,26 @@ def er_graph(n: int, m: int, seed: int, weights_seed: Optional[int] = None) -> G
     return from_edges(n, src, dst, weights_seed, "er_n%d_m%d" % (n, m))
 
 
+def permute_vertices(g: Graph, seed: int):
+    """The same graph with vertex ids relabelled by a seeded uniform random
+    permutation (vertex v becomes perm[v]); returns (graph, perm). It
+    destroys the locality of RMAT's id order: nearly every edge then joins
+    two different index-range partitions. Unweighted graphs only."""
+    if g.weights is not None:
+        raise ValueError("permute_vertices takes unweighted graphs")
+    perm = np.random.Generator(np.random.PCG64(seed)).permutation(g.n).astype(np.uint32)
+    src = np.repeat(np.arange(g.n, dtype=np.uint32), g.degrees())
+    off, cols = build_csr(g.n, perm[src], perm[g.cols])
+    return Graph(g.n, off, cols, None, g.name + "_perm"), perm
+
+
+def inter_partition_fraction(g: Graph, log2_part: int) -> float:
+    """Fraction of CSR entries whose endpoints lie in different partitions of
+    2^log2_part consecutive ids."""
+    src = np.repeat(np.arange(g.n, dtype=np.uint32), g.degrees())
+    return float(np.count_nonzero((src >> log2_part) != (g.cols >> log2_part))) / max(g.m, 1)
+
+
 # Named workloads (seed offsets fixed so every run sees the same bytes).
 def workload_pagerank_rmat16() -> Graph:
     """PageRank input: directed RMAT scale 16, edge factor 16 (1,048,576 edges)."""

@@ -117,3 +117,36 @@ def test_empty_and_tiny():
     off, cols = gg.build_csr(3, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
     assert off.tolist() == [0, 0, 0, 0] and cols.size == 0
     assert gg.pick_sources(off, 1, 4).size == 0
+
+
+def test_permute_vertices_is_an_isomorphism():
+    g = gg.rmat_graph(10, 8, seed=gg.BASE_SEED + 123, symmetric=True)
+    h, perm = gg.permute_vertices(g, 77)
+    assert sorted(perm.tolist()) == list(range(g.n))
+    assert h.m == g.m and h.n == g.n
+    # degree of v in g equals degree of perm[v] in h
+    assert np.array_equal(h.degrees()[perm], g.degrees())
+    # edge multisets agree under the relabelling
+    src = np.repeat(np.arange(g.n, dtype=np.uint64), g.degrees())
+    a = np.sort(perm[src].astype(np.uint64) << 32 | perm[g.cols].astype(np.uint64))
+    hsrc = np.repeat(np.arange(h.n, dtype=np.uint64), h.degrees())
+    b = np.sort(hsrc << 32 | h.cols.astype(np.uint64))
+    assert np.array_equal(a, b)
+    # rows stay sorted; the same seed gives the same bytes
+    for v in range(0, h.n, 97):
+        row = h.cols[h.offsets[v]:h.offsets[v + 1]]
+        assert np.all(row[1:] >= row[:-1])
+    h2, _ = gg.permute_vertices(g, 77)
+    assert np.array_equal(h2.cols, h.cols)
+
+
+def test_inter_partition_fraction_counts_crossing_entries():
+    # path 0-1-2-3 (both directions), partitions of 2 ids: only 1<->2 crosses
+    g = gg.from_edges(4, [0, 1, 1, 2, 2, 3], [1, 0, 2, 1, 3, 2])
+    assert gg.inter_partition_fraction(g, 1) == 2 / 6
+    assert gg.inter_partition_fraction(g, 2) == 0.0
+    assert gg.inter_partition_fraction(g, 0) == 1.0
+    # a random relabelling of RMAT leaves almost every entry crossing
+    r = gg.rmat_graph(12, 8, seed=gg.BASE_SEED + 5, symmetric=True)
+    rp, _ = gg.permute_vertices(r, 3)
+    assert gg.inter_partition_fraction(rp, 8) > 0.9 > gg.inter_partition_fraction(r, 8)
