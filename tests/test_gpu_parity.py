@@ -507,3 +507,21 @@ def test_atomic_free_combine_on_hub_graph_and_splits():
             a, _ = run_program(A, prog, g.n, **kw)
             b, _ = run_program(R, prog, g.n, **kw)
             assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (gids, prog)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("sel", ["analytical", "sc", "pc"])
+def test_relabelled_rmat(sel):
+    # the locality workload's input form: RMAT with vertex ids randomly
+    # permuted, so hubs land in every partition and every bin fills
+    g0 = gg.rmat_graph(14, 16, gg.BASE_SEED + 41, symmetric=True)
+    g, perm = gg.permute_vertices(g0, gg.BASE_SEED + 42)
+    root0 = roots_of(g0, 1)[0]
+    G, _ = make_graph(g, 11)
+    got, _ = run_program(G, "bfs", g.n, root=int(perm[root0]), selector=sel)
+    ref = oracle.bfs_levels(g, int(perm[root0]))
+    assert np.array_equal(got, ref)
+    # levels are invariant under the relabelling
+    assert np.array_equal(got[perm], oracle.bfs_levels(g0, root0))
+    got, _ = run_program(G, "cc", g.n, selector=sel)
+    assert np.array_equal(got, oracle.cc_minlabel(g))
