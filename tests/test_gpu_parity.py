@@ -525,3 +525,28 @@ def test_relabelled_rmat(sel):
     assert np.array_equal(got[perm], oracle.bfs_levels(g0, root0))
     got, _ = run_program(G, "cc", g.n, selector=sel)
     assert np.array_equal(got, oracle.cc_minlabel(g))
+
+
+@pytest.mark.gpu
+def test_largest_partition_size():
+    # q = 2^15, the largest partition the library takes: min programs fit the
+    # LDS and agree with the oracle; sum programs need 8 bytes per vertex and
+    # are refused; sizes outside [8, 15] are rejected
+    import paper_1806_08092_amd as gp
+    g = gg.rmat_graph(16, 8, gg.BASE_SEED + 43, symmetric=True)
+    G, (off, cols, w) = make_graph(g, 15)
+    assert G.info().q == 1 << 15 and G.info().k == 2
+    root = roots_of(g, 1)[0]
+    for sel in ("analytical", "sc", "pc"):
+        got, _ = run_program(G, "bfs", g.n, root=root, selector=sel)
+        assert np.array_equal(got, oracle.bfs_levels(g, root)), sel
+        got, _ = run_program(G, "cc", g.n, selector=sel)
+        assert np.array_equal(got, oracle.cc_minlabel(g)), sel
+    for prog in ("pagerank", "nibble"):
+        with pytest.raises(gp.GpopError) as e:
+            run_program(G, prog, g.n, root=root, max_iter=2)
+        assert e.value.code == gp.ENOTSUP, prog
+    for lp in (7, 16):
+        with pytest.raises(gp.GpopError) as e:
+            gp.Graph(off, cols, w, log2_part=lp)
+        assert e.value.code == gp.EINVAL, lp
