@@ -99,6 +99,21 @@ int gpop_mlp_grad(const gpop_mlp_model* d_model, const float* d_x, const float* 
                   const float* d_t_pc, uint32_t n, float* d_grad, float* d_loss, void* d_ws,
                   size_t ws_bytes, void* stream);
 
+/* Allocation-free gpop_mlp_grad, for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc). The per-chunk partial sums live in a
+ * fixed array inside the library, one copy per GPU (5.2 MB, held until the
+ * process ends); the call allocates nothing. Results are bit-identical to
+ * gpop_mlp_grad on the same inputs (same kernels, same summation order).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (concurrent streams or threads) race and must be serialised by the
+ * caller. Errors: GPOP_EINVAL on NULL arguments, n = 0 or
+ * n > GPOP_MLP_NOALLOC_MAX_SAMPLES; GPOP_EDEVICE if the array's device
+ * address cannot be obtained. */
+#define GPOP_MLP_NOALLOC_MAX_SAMPLES 16384u
+int gpop_mlp_grad_noalloc(const gpop_mlp_model* d_model, const float* d_x, const float* d_t_sc,
+                          const float* d_t_pc, uint32_t n, float* d_grad, float* d_loss, void* stream);
+
 /* One Adam step (step counts from 1) of the masters with gradient d_grad,
  * learning rate lr; rewrites d_model->w from the new masters. */
 int gpop_mlp_adam(gpop_mlp_model* d_model, float* d_master, float* d_m, float* d_v,

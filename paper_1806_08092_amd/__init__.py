@@ -34,6 +34,7 @@ KERNELS = ["plan", "scatter_sc", "scatter_pc", "gather", "merge"]
 # learned selector (include/gpop_mlp.h)
 MLP_IN, MLP_HIDDEN, MLP_PARAMS, MLP_MODEL_BYTES = 12, 64, 5057, 10240
 MLP_MAGIC = 0x504C4D47
+MLP_NOALLOC_MAX_SAMPLES = 16384
 
 
 class GpopError(RuntimeError):
@@ -139,6 +140,7 @@ _SIGS = {
     "gpop_mlp_grad_workspace": (ctypes.c_size_t, [ctypes.c_uint32]),
     "gpop_mlp_grad": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_uint32] + [ctypes.c_void_p] * 3
                       + [ctypes.c_size_t, ctypes.c_void_p]),
+    "gpop_mlp_grad_noalloc": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_uint32] + [ctypes.c_void_p] * 3),
     "gpop_mlp_adam": (ctypes.c_int, [ctypes.c_void_p] * 5 + [ctypes.c_uint32, ctypes.c_float,
                                                              ctypes.c_void_p]),
     "gpop_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_uint32, ctypes.c_uint32,
@@ -486,6 +488,16 @@ class Mlp:
                                    _ptr(self.grad), _ptr(self.loss), _ptr(ws), ws.numel() * 4,
                                    _stream(stream)))
         return self.grad
+
+    def compute_grad_noalloc(self, x, t_sc, t_pc, grad=None, loss=None, stream=None):
+        """gpop_mlp_grad_noalloc: the gradient without a workspace (the
+        library's fixed per-GPU scratch array); writes `grad` / `loss`
+        (default: this object's buffers)."""
+        grad = self.grad if grad is None else grad
+        loss = self.loss if loss is None else loss
+        _check(lib().gpop_mlp_grad_noalloc(_ptr(self.model), _ptr(x), _ptr(t_sc), _ptr(t_pc), x.shape[0],
+                                           _ptr(grad), _ptr(loss), _stream(stream)))
+        return grad
 
     def adam(self, lr=1e-3, stream=None):
         self.step += 1

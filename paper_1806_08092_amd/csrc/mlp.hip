@@ -6,6 +6,7 @@
 // parameter column per lane for the sums over samples), so every reduction
 // runs in a fixed order and the gradient is reproducible bit for bit.
 #include <cmath>
+#include <mutex>
 
 #include "launch.h"
 #include "select_dev.h"
@@ -232,6 +233,47 @@ __global__ __launch_bounds__(64) void k_mlp_shift(gpop_mlp_model* __restrict__ M
 
 uint32_t nchunks(uint32_t n) { return (n + 63u) / 64u; }
 
+// Chunk partials of gpop_mlp_grad_noalloc: a fixed array in device memory,
+// one copy per GPU, held until the process ends. Host code must not pass
+// `scratch` itself to a kernel (on the host it names a stand-in, not the
+// device copy); it uses the address hipGetSymbolAddress reports for the
+// current device.
+constexpr uint32_t kNoAllocChunks = GPOP_MLP_NOALLOC_MAX_SAMPLES / 64u;
+static __device__ __align__(256) float scratch[(size_t)kNoAllocChunks * kPart];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device with
+// that device current.
+int scratch_of_current_device(float** out) {
+    int dev = 0;
+    HIP_OR_RETURN(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GPOP_ENOTSUP, "device index %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_OR_RETURN(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the gradient scratch");
+        if (!p) return fail(GPOP_EDEVICE, "no device address for the gradient scratch");
+        g_scratch_dev[dev] = (float*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return GPOP_OK;
+}
+
+// The two gradient kernels over a partial buffer of at least nchunks(n) rows.
+int launch_grad(const gpop_mlp_model* d_model, const float* d_x, const float* d_t_sc, const float* d_t_pc,
+                uint32_t n, float* d_grad, float* d_loss, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_grad_chunk, dim3(nchunks(n)), dim3(64), 0, st, d_model, d_x, d_t_sc, d_t_pc, n,
+                       part);
+    HIP_OR_RETURN(hipGetLastError(), "mlp gradient");
+    hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((kP + 1 + 255) / 256), dim3(256), 0, st, part, nchunks(n),
+                       d_grad, d_loss);
+    HIP_OR_RETURN(hipGetLastError(), "mlp gradient reduce");
+    return GPOP_OK;
+}
+
 }  // namespace
 }  // namespace gpop
 
@@ -267,15 +309,20 @@ int gpop_mlp_grad(const gpop_mlp_model* d_model, const float* d_x, const float* 
     if (n == 0) return fail(GPOP_EINVAL, "no samples");
     if (ws_bytes < gpop_mlp_grad_workspace(n))
         return fail(GPOP_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, gpop_mlp_grad_workspace(n));
-    hipStream_t st = (hipStream_t)stream;
-    float* part = (float*)d_ws;
-    hipLaunchKernelGGL(k_mlp_grad_chunk, dim3(nchunks(n)), dim3(64), 0, st, d_model, d_x, d_t_sc, d_t_pc, n,
-                       part);
-    HIP_OR_RETURN(hipGetLastError(), "mlp gradient");
-    hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((kP + 1 + 255) / 256), dim3(256), 0, st, part, nchunks(n),
-                       d_grad, d_loss);
-    HIP_OR_RETURN(hipGetLastError(), "mlp gradient reduce");
-    return GPOP_OK;
+    return launch_grad(d_model, d_x, d_t_sc, d_t_pc, n, d_grad, d_loss, (float*)d_ws, (hipStream_t)stream);
+}
+
+int gpop_mlp_grad_noalloc(const gpop_mlp_model* d_model, const float* d_x, const float* d_t_sc,
+                          const float* d_t_pc, uint32_t n, float* d_grad, float* d_loss, void* stream) {
+    if (!d_model || !d_x || !d_t_sc || !d_t_pc || !d_grad) return fail(GPOP_EINVAL, "NULL argument");
+    if (n == 0) return fail(GPOP_EINVAL, "no samples");
+    if (n > GPOP_MLP_NOALLOC_MAX_SAMPLES)
+        return fail(GPOP_EINVAL, "%u samples > GPOP_MLP_NOALLOC_MAX_SAMPLES (%u): use gpop_mlp_grad with a workspace",
+                    n, (unsigned)GPOP_MLP_NOALLOC_MAX_SAMPLES);
+    float* part = nullptr;
+    const int rc = scratch_of_current_device(&part);
+    if (rc) return rc;
+    return launch_grad(d_model, d_x, d_t_sc, d_t_pc, n, d_grad, d_loss, part, (hipStream_t)stream);
 }
 
 int gpop_mlp_adam(gpop_mlp_model* d_model, float* d_master, float* d_m, float* d_v, const float* d_grad,
