@@ -11,6 +11,8 @@ Contents
   * textbook results (``oracle.c`` via ctypes): BFS levels, min-label
     connected components, integer-weight SSSP, FP64 PageRank and
     personalised PageRank;
+  * ``nibble``: FP64 Parallel Nibble with the distance of every frontier
+    decision from its threshold (``oracle.c``);
   * ``gpop_ref``: the GPOP iteration itself (scatter in source- or
     partition-centric mode, reInit, gather, filter) and the analytical mode
     model, written out in pure Python for tiny graphs;
@@ -55,6 +57,7 @@ def _L():
             ("oracle_sssp", [u32, vp, vp, vp, u32, vp]),
             ("oracle_pagerank", [u32, vp, vp, dbl, u32, vp]),
             ("oracle_ppr", [u32, vp, vp, dbl, u32, u32, vp]),
+            ("oracle_nibble", [u32, vp, vp, u32, dbl, u32, dbl, vp, vp, vp, vp, vp]),
         ]:
             fn = getattr(_lib, name)
             fn.restype = i32
@@ -129,3 +132,26 @@ def ppr(g, seed: int, alpha: float = 0.15, iters: int = 20) -> np.ndarray:
     if _L().oracle_ppr(g.n, _p(off), _p(cols), alpha, iters, seed, _p(out)) != 0:
         raise ValueError("bad seed or allocation failure")
     return out
+
+
+class NibbleResult:
+    """FP64 Parallel Nibble: ``pr`` (float64 [n]), ``fsize`` (frontier size
+    after each iteration), ``iters``, ``min_margin`` (least relative distance
+    of a decisive threshold test from its threshold) and ``near`` (decisive
+    tests closer than the requested delta)."""
+
+    def __init__(self, pr, fsize, iters, min_margin, near):
+        self.pr, self.fsize, self.iters, self.min_margin, self.near = pr, fsize, iters, min_margin, near
+
+
+def nibble(g, seed: int, eps: float, max_iter: int = 20, delta: float = 1e-4) -> NibbleResult:
+    off, cols = _csr(g)
+    pr = np.empty(g.n, np.float64)
+    fs = np.zeros(max(1, max_iter), np.uint64)
+    it = ctypes.c_uint32()
+    mm = ctypes.c_double()
+    near = ctypes.c_uint64()
+    if _L().oracle_nibble(g.n, _p(off), _p(cols), seed, eps, max_iter, delta, _p(pr), _p(fs),
+                          ctypes.addressof(it), ctypes.addressof(mm), ctypes.addressof(near)) != 0:
+        raise ValueError("bad seed or allocation failure")
+    return NibbleResult(pr, fs[:it.value].astype(np.int64), it.value, mm.value, near.value)

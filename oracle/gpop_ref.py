@@ -186,52 +186,36 @@ class BFSParent(Program):
 
 
 class Nibble(Program):
-    """Parallel Nibble as the paper writes it: scatterFunc sends PR/(2 deg),
-    initFunc halves PR and keeps the vertex iff PR >= eps * deg, gatherFunc
-    adds, filterFunc keeps iff PR >= eps * deg. The threshold decides the
-    frontier, so this model computes in the kernel's precision (FP32 values;
-    every amount, including a vertex's own value, enters the sum as an
-    integer multiple of 2^-60 rounded to nearest even, and the sum is rounded
-    back to FP32 once). A vertex without out-edges is never kept."""
+    """Parallel Nibble as the paper writes it, in FP64: scatterFunc sends
+    PR/(2 deg), initFunc halves PR and keeps the vertex iff PR >= eps * deg,
+    gatherFunc adds, filterFunc keeps iff PR >= eps * deg. A vertex without
+    out-edges is never kept (its threshold eps * 0 would keep it forever
+    while it has nothing to send)."""
     combine = "sum"
     identity = 0.0
-    FIX = 2.0 ** 60
 
     def start(self, n, params):
-        self.eps = np.float32(params["eps"])
-        self.acc = {}
-        st = [np.float32(0.0)] * n
-        st[params["root"]] = np.float32(1.0)
+        self.eps = float(params["eps"])
+        st = [0.0] * n
+        st[params["root"]] = 1.0
         return st, [params["root"]]
 
-    def fix(self, x):
-        return int(np.rint(np.float64(x) * self.FIX))
-
-    def unfix(self, a):
-        return np.float32(np.float64(a) / self.FIX)
-
     def keep(self, x, d):
-        return d > 0 and bool(x >= self.eps * np.float32(d))
+        return d > 0 and x >= self.eps * d
 
     def scatter(self, st, v, ctx):
         d = ctx.deg[v]
-        return np.float32(np.float32(st[v] * np.float32(0.5)) / np.float32(d)) if d else np.float32(0.0)
+        return st[v] / (2.0 * d) if d else 0.0
 
     def init(self, st, v, ctx):
-        st[v] = self.unfix(self.fix(np.float32(st[v] * np.float32(0.5))))
+        st[v] = st[v] * 0.5
         return self.keep(st[v], ctx.deg[v])
 
-    def before_gather(self, st, active, ctx):
-        self.acc = {}
-        return None
-
     def gather(self, st, u, val):
-        self.acc[u] = self.acc.get(u, self.fix(st[u])) + self.fix(val)
+        st[u] += val
         return True
 
     def filter(self, st, v, ctx):
-        if v in self.acc:
-            st[v] = self.unfix(self.acc[v])
         return self.keep(st[v], ctx.deg[v])
 
 

@@ -20,6 +20,11 @@
  *   oracle_pagerank     topological PageRank, a fixed number of iterations,
  *                       dangling mass spread uniformly (PageRank application)
  *   oracle_ppr          personalised PageRank with restart to one seed
+ *   oracle_nibble       Parallel Nibble (the Nibble application: a seeded
+ *                       lazy random walk whose frontier keeps a vertex while
+ *                       its mass is at least eps times its out-degree), in
+ *                       FP64, with the distance of every frontier decision
+ *                       from its threshold
  *
  * Unreachable vertices get 0xFFFFFFFF. Arithmetic is exact for the integer
  * results and FP64 for the PageRank family.
@@ -27,6 +32,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 #define INF32 0xFFFFFFFFu
 
@@ -221,5 +227,104 @@ int oracle_ppr(uint32_t n, const uint32_t* off, const uint32_t* cols, double alp
         x[seed] += alpha + (1.0 - alpha) * dang;
     }
     free(y);
+    return 0;
+}
+
+/* Parallel Nibble (the Nibble application with the iteration of Algorithm 2),
+ * FP64. PR = e_seed, frontier A = {seed}. While A is not empty and fewer
+ * than max_iter iterations have run:
+ *   scatter   every v in A with deg(v) > 0 sends PR[v] / (2 deg(v)) along
+ *             each out-edge (duplicate edges send twice); the values are
+ *             taken before initFunc changes PR;
+ *   initFunc  every v in A: PR[v] = PR[v] / 2, and v stays active iff
+ *             PR[v] >= eps deg(v);
+ *   gather    every edge message adds its value to PR of its destination,
+ *             which becomes active;
+ *   filter    every active vertex stays iff PR[v] >= eps deg(v).
+ * A vertex without out-edges never stays active (its threshold eps * 0
+ * would keep it forever while it has nothing to send); an active seed
+ * without out-edges still loses the half initFunc takes.
+ *
+ * Outputs: PR (n doubles), the frontier size after each iteration
+ * (fsize[0 .. *iters)), the iterations run, the least relative distance
+ * |PR - eps deg| / (eps deg) over the decisive threshold tests (the filter
+ * test of each active vertex after gather, and the initFunc test of a vertex
+ * that then receives nothing), and how many of those tests lie closer than
+ * `delta` to their threshold. Returns 0, or -1 on a bad seed or allocation
+ * failure. */
+int oracle_nibble(uint32_t n, const uint32_t* off, const uint32_t* cols, uint32_t seed, double eps,
+                  uint32_t max_iter, double delta, double* pr, uint64_t* fsize, uint32_t* iters,
+                  double* min_margin, uint64_t* near) {
+    *iters = 0;
+    *min_margin = 1.0 / 0.0;
+    *near = 0;
+    if (seed >= n) return -1;
+    double* inbox = (double*)calloc(n, sizeof(double));
+    uint8_t* got = (uint8_t*)calloc(n, 1);    /* received a message this iteration */
+    uint8_t* inA = (uint8_t*)calloc(n, 1);    /* in the next frontier            */
+    uint32_t* A = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t* R = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t* B = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+    if (!inbox || !got || !inA || !A || !R || !B) {
+        free(inbox); free(got); free(inA); free(A); free(R); free(B);
+        return -1;
+    }
+    for (uint32_t v = 0; v < n; ++v) pr[v] = 0.0;
+    pr[seed] = 1.0;
+    size_t na = 1;
+    A[0] = seed;
+#define NIBBLE_TEST(x, d, keep)                                        \
+    do {                                                               \
+        keep = 0;                                                      \
+        if ((d) > 0) {                                                 \
+            const double th = eps * (double)(d);                       \
+            const double m = fabs((x) - th) / th;                      \
+            if (m < *min_margin) *min_margin = m;                      \
+            if (m < delta) ++*near;                                    \
+            keep = (x) >= th;                                          \
+        }                                                              \
+    } while (0)
+    uint32_t t = 0;
+    for (; t < max_iter && na > 0; ++t) {
+        size_t nr = 0, nb = 0;
+        /* scatter, with the values before initFunc */
+        for (size_t i = 0; i < na; ++i) {
+            const uint32_t v = A[i], d = off[v + 1] - off[v];
+            if (d == 0) continue;
+            const double share = pr[v] / (2.0 * (double)d);
+            for (uint32_t e = off[v]; e < off[v + 1]; ++e) {
+                const uint32_t u = cols[e];
+                inbox[u] += share;
+                if (!got[u]) { got[u] = 1; R[nr++] = u; }
+            }
+        }
+        /* initFunc: halve; a vertex that fails and receives nothing leaves
+         * the frontier here (its test is decisive) */
+        for (size_t i = 0; i < na; ++i) {
+            const uint32_t v = A[i], d = off[v + 1] - off[v];
+            pr[v] *= 0.5;
+            if (got[v]) continue;  /* the filter decides after gather */
+            int keep;
+            NIBBLE_TEST(pr[v], d, keep);
+            if (keep && !inA[v]) { inA[v] = 1; B[nb++] = v; }
+        }
+        /* gather, then filter on the received vertices */
+        for (size_t i = 0; i < nr; ++i) {
+            const uint32_t u = R[i], d = off[u + 1] - off[u];
+            pr[u] += inbox[u];
+            inbox[u] = 0.0;
+            got[u] = 0;
+            int keep;
+            NIBBLE_TEST(pr[u], d, keep);
+            if (keep && !inA[u]) { inA[u] = 1; B[nb++] = u; }
+        }
+        for (size_t i = 0; i < nb; ++i) inA[B[i]] = 0;
+        fsize[t] = nb;
+        uint32_t* tmp = A; A = B; B = tmp;
+        na = nb;
+    }
+#undef NIBBLE_TEST
+    *iters = t;
+    free(inbox); free(got); free(inA); free(A); free(R); free(B);
     return 0;
 }

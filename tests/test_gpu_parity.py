@@ -114,45 +114,75 @@ def test_bfs_parents_tree_at_scale():
         assert iters == int(lv[lv != INF].max()) + 1
 
 
-_NIBBLE_REF = {}
+# Parallel Nibble decides its frontier by threshold tests (PR >= eps deg) on
+# FP32 values, the oracle on FP64 ones. The kernel's value of a vertex after
+# an iteration is a halved own value (exact) plus messages (x * 0.5) / deg
+# (one rounding each) summed exactly in 2^-60 fixed point and rounded to
+# FP32 once, so its relative error grows by at most 2 * 2^-24 per iteration.
+# Policy: a case of at most T iterations is compared only when every
+# decisive test of the FP64 run lies more than nibble_delta(T) = 4 T 2^-24
+# (relative, twice that bound) from its threshold; then the iteration count
+# and the frontier size after every iteration must be identical and the
+# values within 1e-6 max-abs and 1e-5 relative L1 of the FP64 oracle. Cases
+# closer to a tie are counted as skipped; each test needs checked cases.
+def nibble_delta(max_iter):
+    return 4.0 * max_iter * 2.0 ** -24
 
 
-def nibble_ref(key, g, q, seed, eps, max_iter):
-    """The oracle's Nibble (kernel precision), cached: the mode never changes
-    the result, so one oracle run serves every selector."""
-    if key not in _NIBBLE_REF:
-        st, tr = gpop_ref.run(g, q, "nibble", {"root": seed, "eps": eps}, max_iter)
-        _NIBBLE_REF[key] = (np.array(st, np.float32), len(tr))
-    return _NIBBLE_REF[key]
+def nibble_check(G, g, seed, eps, max_iter, **kw):
+    """True if checked against the FP64 oracle, False if skipped (near tie)."""
+    delta = nibble_delta(max_iter)
+    ref = oracle.nibble(g, seed, eps, max_iter, delta=delta)
+    if ref.near:
+        say("nibble skipped (%d decisions within %.2g of their threshold)" % (ref.near, delta), seed, eps)
+        return False
+    got, iters = run_program(G, "nibble", g.n, root=seed, epsilon=eps, max_iter=max_iter, **kw)
+    stats = G.iter_stats()
+    fs = [r["active_vertices"] for r in stats[1:iters]] + [G.frontier_size()]
+    assert iters == ref.iters, (seed, eps, iters, ref.iters)
+    assert fs == list(ref.fsize), (seed, eps)
+    assert pr_ok(got, ref.pr), (seed, eps, float(np.max(np.abs(got.astype(np.float64) - ref.pr))))
+    return True
 
 
-@pytest.mark.parametrize("zi", [0, 2, 3, 4, 5, 7])
+@pytest.mark.parametrize("zi", [0, 2, 3, 4, 5, 7, 8])
 @pytest.mark.parametrize("sel", SELECTORS)
 def test_nibble(zi, sel):
-    """Parallel Nibble: frontier decisions are threshold tests on FP32 values,
-    so the result is compared bit for bit with the oracle computing in the
-    kernel's precision, iteration count included."""
+    """Parallel Nibble against the FP64 oracle under the threshold policy."""
     name, g, lp, (G, _) = get_zoo()[zi]
+    checked = 0
     for seed in roots_of(g, 2):
-        for eps in (1e-3, 2e-5):
+        for eps in (1.1e-3, 3.7e-4, 2.3e-5):
             say("nibble", name, sel, seed, eps)
-            got, iters = run_program(G, "nibble", g.n, root=seed, selector=sel, epsilon=eps, max_iter=80)
-            ref, n_it = nibble_ref((name, seed, eps), g, 1 << lp, seed, eps, 80)
-            assert iters == n_it, (name, sel, seed, eps, iters, n_it)
-            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (
-                name, sel, seed, eps, np.flatnonzero(got != ref)[:10])
+            checked += nibble_check(G, g, seed, eps, 80, selector=sel)
+    assert checked >= 2, (name, checked)
 
 
 @pytest.mark.parametrize("gids,combine", [(256, "lds"), (0, "rounds")])
 def test_nibble_split_gather_and_combines(gids, combine):
     g = gg.rmat_graph(12, 8, 33, symmetric=True)
     G, _ = make_graph(g, 9, gather_task_ids=gids, combine=combine)
-    seed = roots_of(g, 1)[0]
-    say("nibble split", gids, combine, seed)
-    got, iters = run_program(G, "nibble", g.n, root=seed, epsilon=1e-4, max_iter=40)
-    ref, n_it = nibble_ref(("rmat12sym", seed, 1e-4), g, 1 << 9, seed, 1e-4, 40)
-    assert iters == n_it
-    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    checked = 0
+    for seed in roots_of(g, 2):
+        for eps in (1.3e-4, 3.1e-5):
+            say("nibble split", gids, combine, seed, eps)
+            checked += nibble_check(G, g, seed, eps, 40)
+    assert checked >= 2
+
+
+def test_nibble_at_scale():
+    """RMAT-18 symmetrised (8.4M CSR entries) at the default partition size
+    for sum programs (2^13) and the default task sizes: the policy above on
+    seeds drawn like the benchmark's."""
+    g = gg.rmat_graph(18, 16, gg.BASE_SEED + 44, symmetric=True)
+    G, _ = make_graph(g, 13)
+    checked = 0
+    for seed in [int(s) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED, 4)]:
+        for eps in (1.1e-6, 3.3e-7):
+            for max_iter in (12, 30):
+                say("nibble rmat18", seed, eps, max_iter)
+                checked += nibble_check(G, g, seed, eps, max_iter)
+    assert checked >= 6
 
 
 @pytest.mark.parametrize("zi", range(9))

@@ -179,85 +179,127 @@ def test_bfs_parents_tree_validation():
 
 
 # ---------------------------------------------------------------- Parallel Nibble
-def nibble_fp64(g, seed, eps, max_iter):
-    """The Nibble iteration in FP64, written out directly on the edge list
-    (no partitions, no fixed point): returns the values, the frontier after
-    every iteration and the least relative distance of any threshold test
-    from its threshold."""
-    n = g.n
-    deg = np.diff(g.offsets.astype(np.int64))
+# oracle.nibble is Parallel Nibble (the Nibble application) in FP64. While
+# every reached vertex stays active it is exactly the lazy random walk
+# x <- (x + A^T D^-1 x) / 2 started at the seed; the thresholds then decide
+# which vertices keep walking.
+
+def test_nibble_cycle_is_binomial():
+    """On a directed cycle every vertex has one out-edge, so with a tiny eps
+    the mass after t < n iterations is the binomial C(t, j) / 2^t at j steps
+    ahead of the seed (a lazy walk), and the frontier is the t + 1 vertices
+    holding mass."""
+    from math import comb
+    n, seed = 50, 7
+    g = graph_from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+    for t in (1, 2, 5, 13):
+        r = oracle.nibble(g, seed, 1e-300, t)
+        want = np.zeros(n)
+        for j in range(t + 1):
+            want[(seed + j) % n] = comb(t, j) / 2.0 ** t
+        assert r.iters == t
+        assert np.array_equal(r.pr, want)
+        assert list(r.fsize) == [i + 2 for i in range(t)]
+
+
+@pytest.mark.parametrize("seed", [0, 3, 11])
+def test_nibble_tiny_eps_is_lazy_walk_matrix_power(seed):
+    """With every reached vertex kept, t iterations equal the t-th power of
+    the lazy walk matrix (I + A^T D^-1) / 2 applied to e_seed (dense numpy;
+    duplicate edges count twice), on a symmetric graph whose vertices all
+    have out-edges."""
+    base = gg.rmat_graph(5, 4, 300, symmetric=True)
+    r0, c0 = edge_list(base)
+    n = base.n
+    ring = [(i, (i + 1) % n) for i in range(n)] + [((i + 1) % n, i) for i in range(n)]
+    g = graph_from_edges(n, list(zip(r0.tolist(), c0.tolist())) + ring)
+    deg = g.degrees().astype(np.float64)
+    assert np.all(deg > 0)
     r, c = edge_list(g)
-    pr = np.zeros(n)
-    pr[seed] = 1.0
-    active = [seed]
-    fronts, margin = [], np.inf
-
-    def test(x, d):
-        nonlocal margin
-        if d == 0:
-            return False
-        margin = min(margin, abs(x - eps * d) / (eps * d))
-        return x >= eps * d
-
-    for _ in range(max_iter):
-        if not active:
-            break
-        act = np.zeros(n, bool)
-        act[active] = True
-        send = np.where(act & (deg > 0), pr / (2 * np.maximum(deg, 1)), 0.0)
-        m = act[r]
-        inbox = np.zeros(n)
-        np.add.at(inbox, c[m], send[r[m]])
-        got = np.zeros(n, bool)
-        got[c[m]] = True
-        pr[act] *= 0.5
-        carried = [v for v in active if test(pr[v], deg[v])]
-        pr += inbox
-        cand = sorted(set(carried) | set(np.flatnonzero(got).tolist()))
-        active = [v for v in cand if test(pr[v], deg[v])]
-        fronts.append(active)
-    return pr, fronts, margin
+    P = np.zeros((n, n))
+    np.add.at(P, (c, r), 1.0 / deg[r])
+    W = 0.5 * (np.eye(n) + P)
+    e = np.zeros(n)
+    e[seed] = 1.0
+    for t in (1, 3, 8):
+        want = np.linalg.matrix_power(W, t) @ e
+        got = oracle.nibble(g, seed, 1e-300, t)
+        assert got.iters == t
+        assert np.max(np.abs(got.pr - want)) <= 1e-14
 
 
-@pytest.mark.parametrize("gi", [0, 1, 4, 7, 12])
-def test_nibble_model_vs_fp64(gi):
-    """The model in the kernel's precision follows the FP64 iteration: same
-    frontiers wherever no threshold test is closer than 1e-3 to its
-    threshold, values within FP32 rounding, total mass 1 (a seed without
-    out-edges keeps half)."""
+@pytest.mark.parametrize("gi", [0, 1, 4, 7, 12, 14])
+def test_nibble_mass_conservation(gi):
+    """Mass only moves along edges: the total stays 1, except that an active
+    seed without out-edges keeps the half initFunc leaves it and sends
+    nothing."""
     g = small_graphs()[gi]
-    checked = 0
-    for seed in range(min(3, g.n)):
-        for eps in (1e-2, 3e-3, 1e-3):
-            ref, fronts, margin = nibble_fp64(g, seed, eps, 60)
-            if margin < 1e-3:
-                continue
-            st, tr = gpop_ref.run(g, 8, "nibble", {"root": seed, "eps": eps}, 60)
-            assert [t.frontier_out for t in tr] == fronts
-            x = np.array(st, np.float64)
-            assert np.allclose(x, ref, rtol=1e-5, atol=1e-9)
-            # mass moves along edges; only a seed without out-edges loses
-            # the half initFunc takes from it
-            assert abs(x.sum() - (1.0 if g.degrees()[seed] > 0 else 0.5)) < 1e-5
-            checked += 1
-    assert checked > 0
+    deg = g.degrees()
+    for seed in range(min(4, g.n)):
+        for eps in (1.3e-2, 2.7e-3, 1e-300):
+            r = oracle.nibble(g, seed, eps, 40)
+            total = 1.0 if deg[seed] > 0 else 0.5
+            assert abs(r.pr.sum() - total) <= 1e-12
+            assert np.all(r.pr >= 0)
 
 
-def test_nibble_closed_forms():
+def test_nibble_threshold_closed_forms():
     # a star of 8 leaves around 0, both directions: after the first
     # iteration the centre holds 1/2 and every leaf 1/16, a fixed point
+    # (every vertex passes its threshold, so all 9 stay active)
     g = graph_from_edges(9, [(0, i) for i in range(1, 9)] + [(i, 0) for i in range(1, 9)])
     for t in (1, 2, 5):
-        st, tr = gpop_ref.run(g, 4, "nibble", {"root": 0, "eps": 1e-3}, t)
-        assert len(tr) == t
-        assert np.array_equal(np.array(st, np.float32), np.array([0.5] + [1 / 16] * 8, np.float32))
+        r = oracle.nibble(g, 0, 1e-3, t)
+        assert r.iters == t and list(r.fsize) == [9] * t
+        assert np.array_equal(r.pr, np.array([0.5] + [1 / 16] * 8))
+    # a leaf's threshold is eps * 1: with eps = 1/10 the leaves (1/16) drop
+    # after the first iteration, the centre (1/2 >= 8/10 fails) too
+    r = oracle.nibble(g, 0, 0.1, 10)
+    assert r.iters == 1 and list(r.fsize) == [0]
     # one edge both ways: the seed keeps 1/2 and sends 1/2, then both stay
     # at 1/2; with eps above 1/2 the seed stops after its first scatter
     g = graph_from_edges(2, [(0, 1), (1, 0)])
-    st, tr = gpop_ref.run(g, 4, "nibble", {"root": 0, "eps": 0.1}, 3)
-    assert np.array_equal(np.array(st, np.float32), np.array([0.5, 0.5], np.float32)) and len(tr) == 3
-    st, tr = gpop_ref.run(g, 4, "nibble", {"root": 0, "eps": 0.75}, 10)
-    assert np.array_equal(np.array(st, np.float32), np.array([0.5, 0.5], np.float32)) and len(tr) == 1
+    r = oracle.nibble(g, 0, 0.1, 3)
+    assert np.array_equal(r.pr, [0.5, 0.5]) and list(r.fsize) == [2, 2, 2]
+    r = oracle.nibble(g, 0, 0.75, 10)
+    assert np.array_equal(r.pr, [0.5, 0.5]) and r.iters == 1 and list(r.fsize) == [0]
+    # a seed without out-edges halves once and stops
+    g = graph_from_edges(3, [(1, 2)])
+    r = oracle.nibble(g, 0, 1e-3, 10)
+    assert r.iters == 1 and list(r.fsize) == [0] and np.array_equal(r.pr, [0.5, 0, 0])
+
+
+def test_nibble_margin_reports_ties():
+    """The reported margin is the least relative distance of a decisive
+    threshold test: on a 4-cycle with eps = 1/4 the second iteration holds
+    [1/4, 1/2, 1/4] from the seed, two exact ties."""
+    g = graph_from_edges(4, [(i, (i + 1) % 4) for i in range(4)])
+    r = oracle.nibble(g, 0, 0.25, 2, delta=1e-6)
+    assert r.min_margin == 0.0 and r.near >= 2
+    # after one iteration the two vertices hold 1/2, twice the threshold
+    r = oracle.nibble(g, 0, 0.25, 1, delta=1e-6)
+    assert r.min_margin == 1.0 and r.near == 0
+
+
+@pytest.mark.parametrize("gi", [0, 1, 4, 7, 12])
+def test_nibble_gpop_model_equals_oracle(gi):
+    """The partitioned GPOP model (bins, both scatter modes, reInit, gather,
+    filter) in FP64 follows the direct edge iteration: the same frontiers and
+    values to rounding, wherever no decision lies within 1e-9 of its
+    threshold."""
+    g = small_graphs()[gi]
+    checked = 0
+    for seed in range(min(3, g.n)):
+        for eps in (1.37e-2, 3.1e-3, 1.1e-3):
+            ref = oracle.nibble(g, seed, eps, 60, delta=1e-9)
+            if ref.near:
+                continue
+            for sel in ("analytical", "sc", "pc"):
+                st, tr = gpop_ref.run(g, 8, "nibble", {"root": seed, "eps": eps}, 60, selector=sel)
+                assert [len(t.frontier_out) for t in tr] == list(ref.fsize)
+                assert np.max(np.abs(np.array(st, np.float64) - ref.pr)) <= 1e-14
+            checked += 1
+    assert checked > 0
 
 
 @pytest.mark.parametrize("gi", range(15))
