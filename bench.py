@@ -1,21 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the partition-centric scatter/gather iteration on one MI355X.
 
-Default workload: BFS (levels) from 8 sources plus min-label connected
-components on the symmetrised RMAT graph of scale 22, edge factor 16
-(4,194,304 vertices, 134,217,728 directed CSR entries). One step = the 8
-BFS runs + 1 CC run, each from a fresh initial state, on inputs already
-resident in HBM. Prints one JSON line.
+Default line (the headline): RMAT scale 25, edge factor 16 -- BFS (levels)
+from 8 sources plus min-label connected components on the symmetrised graph
+(33,554,432 vertices, 1,073,741,824 directed CSR entries) and PageRank, 10
+iterations, on the directed graph (536,870,912 edges). One step = the 8 BFS
+runs + 1 CC run + 1 PageRank run, each from a fresh initial state, on inputs
+already resident in HBM, under Eq. 1 at the library's default bandwidth
+ratio. The same line carries:
+  - `roofline` of the kernel with the largest share of device time, and the
+    fraction of HBM peak of every iteration of one step (`per_iteration`);
+  - `parity`: every GPU output of one step against the oracle (BFS levels and
+    CC labels bit-exact, PageRank within 1e-6 max-abs and 1e-5 relative L1);
+    the script exits non-zero on a mismatch;
+  - `selector`: the learned scatter-mode selector, trained in this run on
+    probe timings of smaller RMAT graphs, against Eq. 1 at ratio 16 and at the
+    paper's ratio 2 on the same step (whole-step times, identical results);
+  - `rmat22`: the scale-22 BFS + CC step (4,194,304 vertices, 134,217,728
+    entries) with its own roofline and parity;
+  - `cpu_baseline`: the single-threaded oracle on a bounded sample.
+Other workloads (`--workload NAME`) print a line of their own.
 
 Throughput is traversed edges per second: each BFS counts the out-degrees of
-the vertices it reaches (directed CSR entries), CC counts every entry once.
-`roofline` reports the kernel with the largest share of device time: its
-algorithmic bytes per launch (the byte model below) over its mean launch
-duration, from HIP events recorded around every launch on the stream the
-kernel runs on, against the 8 TB/s HBM peak. The events come from a second
-timed region of the same steps with profiling on (the library then launches
-each kernel directly instead of replaying its recorded HIP graph; the kernels
-are the same); `value` comes from the first, unprofiled region.
+the vertices it reaches (directed CSR entries), CC counts every entry once,
+PageRank every entry once per iteration. `roofline` reports the kernel with
+the largest share of device time: its algorithmic bytes per launch (the byte
+model below) over its mean launch duration, from HIP events recorded around
+every launch on the stream the kernel runs on, against the 8 TB/s HBM peak.
+The events come from a second timed region of the same steps with profiling
+on (the library then launches each kernel directly instead of replaying its
+recorded HIP graph; the kernels are the same); `value` comes from the first,
+unprofiled region.
 """
 import argparse
 import json
@@ -513,12 +528,433 @@ def batch_eval(args):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------ headline line
+MAX_ITER = {"pagerank": 10, "ppr": 20, "nibble": 20}
+
+
+def parity_of(prog, got, ref):
+    """One GPU output against the oracle's: integers bit-exact, the
+    PageRank family within 1e-6 max-abs and 1e-5 relative L1."""
+    import numpy as np
+    if prog in ("pagerank", "ppr"):
+        x = got.view(np.float32).astype(np.float64)
+        err = float(np.max(np.abs(x - ref))) if ref.size else 0.0
+        rel = float(np.sum(np.abs(x - ref)) / max(np.sum(np.abs(ref)), 1e-300))
+        return {"ok": bool(err <= 1e-6 and rel <= 1e-5), "max_abs": err, "rel_l1": rel}
+    bad = int(np.count_nonzero(got.view(np.uint32) != ref))
+    return {"ok": bad == 0, "mismatches": bad}
+
+
+def oracle_call(g, prog, root):
+    import oracle
+    t = time.perf_counter()
+    if prog == "bfs":
+        out = oracle.bfs_levels(g, root)
+    elif prog == "cc":
+        out = oracle.cc_minlabel(g)
+    elif prog == "sssp":
+        out = oracle.sssp(g, root)
+    elif prog == "pagerank":
+        out = oracle.pagerank(g, 0.85, 10)
+    else:
+        raise ValueError(prog)
+    return out, time.perf_counter() - t
+
+
+class Part:
+    """One graph of a step: its device copy, preprocessed layout and runs."""
+
+    def __init__(self, name, g, runs, lp, args):
+        import torch
+        import paper_1806_08092_amd as gp
+        self.name, self.g, self.runs, self.lp = name, g, runs, lp
+        self.off, self.cols, self.w = gp.upload_csr(g)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        self.G = gp.Graph(self.off, self.cols, self.w, log2_part=lp, sc_task_log2=args.sc_task_log2,
+                          gather_task_ids=args.gather_task_ids, combine=args.combine)
+        torch.cuda.synchronize()
+        self.prep_ms = (time.perf_counter() - t) * 1e3
+        self.info = self.G.info()
+        self.st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        self.roots = {r: torch.tensor([r], dtype=torch.int32, device="cuda") for _, r in runs}
+        self.deg = (self.off[1:] - self.off[:-1]).to(torch.int64)
+
+    def start(self, prog, root):
+        self.G.state_init(prog, self.st, root=root, epsilon=1e-9)
+        if prog in ("cc", "pagerank"):
+            self.G.set_frontier_all()
+        else:
+            self.G.set_frontier(self.roots[root])
+
+    def do_run(self, prog, root):
+        self.start(prog, root)
+        return self.G.run(MAX_ITER.get(prog, 1 << 30))
+
+    def step(self):
+        for prog, root in self.runs:
+            self.do_run(prog, root)
+
+    def traversed(self, prog, stats):
+        if prog in ("bfs", "sssp", "bfs_parent"):
+            return int(self.deg[self.st != -1].sum().item())
+        if prog == "nibble":
+            return sum(r["active_edges"] for r in stats)
+        if prog == "pagerank":
+            return 10 * self.g.m
+        return self.g.m
+
+    def stats_pass(self):
+        """One untimed pass, an iteration at a time with HIP events around
+        every kernel: per-iteration records, algorithmic bytes and kernel
+        time, traversed edges and the outputs (host copies) of every run."""
+        import numpy as np
+        info = self.info
+        bytes_step = {k: 0.0 for k in ("plan", "scatter_sc", "scatter_pc", "gather", "merge")}
+        per_iter, outputs, iters_per_run, edges = [], [], [], 0
+        self.G.profile_enable(True)
+        try:
+            for prog, root in self.runs:
+                self.start(prog, root)
+                lim = MAX_ITER.get(prog, 1 << 30)
+                it, kms, kper = 0, [], []
+                prev = self.G.profile_read()
+                while it < lim and self.G.frontier_size() > 0:
+                    self.G.iterate()
+                    cur = self.G.profile_read()
+                    kper.append({k: cur[k][0] - prev[k][0] for k in cur})
+                    kms.append(sum(kper[-1].values()))
+                    prev = cur
+                    it += 1
+                stats = self.G.iter_stats()
+                assert len(stats) == it, (prog, len(stats), it)
+                weighted, sump = prog == "sssp", prog in ("pagerank", "ppr", "nibble")
+                for i, rec in enumerate(stats):
+                    nva = stats[i + 1]["active_vertices"] if i + 1 < len(stats) else self.G.frontier_size()
+                    kb = kernel_bytes(rec, nva, info.q, info.k, weighted, sump)
+                    for kname in bytes_step:
+                        bytes_step[kname] += kb[kname]
+                    tot = sum(kb.values())
+                    per_iter.append({"run": "%s(%d)" % (prog, root), "it": i,
+                                     "active_vertices": rec["active_vertices"],
+                                     "active_edges": rec["active_edges"], "sc_parts": rec["sc_parts"],
+                                     "pc_parts": rec["pc_parts"], "ms": kms[i],
+                                     "kernel_ms": {k: round(v, 4) for k, v in kper[i].items()}, "alg_MB": tot / 1e6,
+                                     "frac_hbm": tot / (kms[i] * 1e-3) / (HBM_PEAK_GBPS * 1e9) if kms[i] > 0 else 0.0})
+                iters_per_run.append(it)
+                edges += self.traversed(prog, stats)
+                outputs.append((prog, root, self.st.cpu().numpy().copy()))
+        finally:
+            self.G.profile_enable(False)
+        self.G.check()
+        return bytes_step, per_iter, outputs, iters_per_run, edges
+
+
+def time_steps(parts, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        for P in parts:
+            P.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for P in parts:
+            P.step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def profile_steps(parts, steps):
+    """The same steps with HIP events around every kernel: per kernel, ms
+    and launches summed over the graphs."""
+    import torch
+    for P in parts:
+        P.G.profile_enable(True)  # counters start at zero
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for P in parts:
+            P.step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = {}
+    for P in parts:
+        for k, (kms, n) in P.G.profile_read().items():
+            a, b = prof.get(k, (0.0, 0))
+            prof[k] = (a + kms, b + n)
+        P.G.profile_enable(False)
+    return ms, prof
+
+
+def roofline_of(prof, bytes_step, steps):
+    per_kernel = {}
+    for kname, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        per_kernel[kname] = {
+            "ms_per_step": ms / steps, "launches_per_step": n / steps, "mean_launch_us": ms * 1e3 / n,
+            "alg_GB_per_step": bytes_step[kname] / 1e9,
+            "achieved_GBps": bytes_step[kname] * steps / (ms * 1e-3) / 1e9 if ms > 0 else 0.0,
+        }
+    dom = max(per_kernel, key=lambda kn: per_kernel[kn]["ms_per_step"])
+    ach = per_kernel[dom]["achieved_GBps"]
+    return dom, per_kernel, {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBPS,
+                             "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
+                             "alg_bytes_per_launch": bytes_step[dom] / per_kernel[dom]["launches_per_step"]}
+
+
+def iteration_summary(per_iter):
+    import numpy as np
+    fr = np.array([r["frac_hbm"] for r in per_iter])
+    ms = np.array([r["ms"] for r in per_iter])
+    return {"iterations": len(per_iter), "frac_hbm_min": float(fr.min()), "frac_hbm_median": float(np.median(fr)),
+            "frac_hbm_max": float(fr.max()),
+            "frac_hbm_time_weighted": float((fr * ms).sum() / ms.sum()) if ms.sum() > 0 else 0.0}
+
+
+def copy_ceiling(mib):
+    """A plain elementwise kernel of known size (reads and writes 4n bytes):
+    the measured bandwidth ceiling."""
+    import torch
+    n = mib << 18
+    a = torch.empty(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.bitwise_not(a, out=b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        torch.bitwise_not(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    return {"bytes": 2 * 4 * n, "GBps": 2 * 4 * n / (ms * 1e-3) / 1e9}
+
+
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def selector_compare(args, parts, ms_eq1_default):
+    """Trains the learned selector in this run (probe timings of BFS, CC and
+    PageRank on symmetrised RMAT graphs of scales 18 up to args.train_scale,
+    the library's own training kernels), then times the headline step under
+    it and under Eq. 1 at the paper's ratio 2 and the default 16, and checks
+    that its results equal Eq. 1's."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1806_08092_amd as gp
+    from paper_1806_08092_amd import learned
+    t_all = time.perf_counter()
+    data_parts = []
+    for i, (scale, ef, abc) in enumerate(TRAIN_SPECS):
+        if scale > args.train_scale:
+            continue
+        g = gg.rmat_graph(scale, ef, seed=gg.BASE_SEED + 100 + i, abc=abc, symmetric=True)
+        off, cols, w = gp.upload_csr(g)
+        st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        srcs = [int(x) for x in gg.pick_sources(g.offsets, gg.SOURCE_SEED + i, 2)]
+        extra = [("bfs", srcs[0], scale - 11), ("cc", 0, scale - 11)] if scale >= 21 else []
+        for prog, root, lp in [("bfs", srcs[0], 0), ("bfs", srcs[-1], 0), ("cc", 0, 0), ("pagerank", 0, 0)] + extra:
+            G = gp.Graph(off, cols, w, log2_part=lp or (13 if prog == "pagerank" else 14))
+            G.state_init(prog, st, root=root)
+            if prog in ("cc", "pagerank"):
+                G.set_frontier_all()
+            else:
+                G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
+            data_parts.append(learned.collect(G, max_iter=10 if prog == "pagerank" else 1 << 20))
+            del G
+        del off, cols, w, st
+        torch.cuda.empty_cache()
+    data = learned.Samples.concat(data_parts)
+    data, c_sc, c_pc = learned.relabel_by_id_kind(data)
+    mlp = learned.train(data, gg.mlp_init_params(gg.BASE_SEED), steps=args.train_steps, batch=4096, lr=1e-3,
+                        seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t_all
+    log("selector trained on %d rows in %.1f s" % (len(data), train_s))
+    # identical results: one BFS and the CC of the first graph under both
+    P0 = parts[0]
+    same = True
+    for prog, root in P0.runs[:1] + [r for r in P0.runs if r[0] == "cc"]:
+        P0.G.set_selector("analytical", 16.0)
+        P0.do_run(prog, root)
+        a = P0.st.clone()
+        P0.G.set_selector("learned", 16.0, mlp=mlp.model)
+        P0.do_run(prog, root)
+        same = same and bool(torch.equal(a, P0.st))
+    res = {}
+    for name, kind, ratio in (("eq1_default16", "analytical", 16.0), ("eq1_ratio2", "analytical", 2.0),
+                              ("learned", "learned", 16.0), ("eq1_default16_again", "analytical", 16.0)):
+        for P in parts:
+            P.G.set_selector(kind, ratio, mlp=mlp.model if kind == "learned" else None)
+        res[name] = time_steps(parts, args.selector_steps, 1)
+        log("selector %s: %.2f ms per step" % (name, res[name]))
+    for P in parts:
+        P.G.set_selector(args.selector, args.bw_ratio)
+    eq16 = min(res["eq1_default16"], res["eq1_default16_again"])
+    return {"learned_vs_eq1_default": eq16 / res["learned"],
+            "learned_vs_eq1_ratio2": res["eq1_ratio2"] / res["learned"],
+            "ms_per_step": {"eq1_default16": eq16, "eq1_ratio2": res["eq1_ratio2"], "learned": res["learned"]},
+            "identical_results": same, "train_rows": len(data), "train_s": train_s,
+            "train_scales": "18-%d" % args.train_scale, "train_steps": args.train_steps,
+            "gather_us_per_id": {"sc": c_sc, "pc": c_pc}}
+
+
+def headline(args):
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    import graphgen as gg
+
+    scale = args.scale
+    t = time.perf_counter()
+    src, dst = gg.rmat_edges(scale, 16 << scale, gg.BASE_SEED + 7)
+    gd = gg.from_edges(1 << scale, src, dst, name="rmat%d" % scale)
+    ss, sd = gg.symmetrize(src, dst)
+    del src, dst
+    gs = gg.from_edges(1 << scale, ss, sd, name="rmat%d_sym" % scale)
+    del ss, sd
+    gen_s = time.perf_counter() - t
+    log("RMAT-%d generated in %.1f s: directed E=%d, symmetrised E=%d" % (scale, gen_s, gd.m, gs.m))
+    runs_s = [("bfs", int(r)) for r in gg.pick_sources(gs.offsets, gg.SOURCE_SEED, 8)] + [("cc", 0)]
+    runs_d = [("pagerank", 0)]
+    c2 = None if args.no_rmat22 else gg.workload_bfs_cc_rmat22()
+    runs_c2 = None if c2 is None else [("bfs", int(s)) for s in gg.pick_sources(c2.offsets, gg.SOURCE_SEED, 8)] + [("cc", 0)]
+    # the oracle's outputs for the parity check, on host threads (each call
+    # is the single-threaded C oracle; ctypes releases the interpreter lock)
+    pool = futs = None
+    if not args.no_parity:
+        pool = cf.ThreadPoolExecutor(max_workers=min(12, max(2, (os.cpu_count() or 8) - 2)))
+        futs = {("rmat%d_sym" % scale, prog, root): pool.submit(oracle_call, gs, prog, root) for prog, root in runs_s}
+        futs[("rmat%d" % scale, "pagerank", 0)] = pool.submit(oracle_call, gd, "pagerank", 0)
+        if c2 is not None:
+            futs.update({("rmat22_sym", prog, root): pool.submit(oracle_call, c2, prog, root)
+                         for prog, root in runs_c2})
+
+    parts = [Part("rmat%d_sym" % scale, gs, runs_s, args.log2_part or 14, args),
+             Part("rmat%d" % scale, gd, runs_d, args.log2_part or 13, args)]
+    for P in parts:
+        P.G.set_selector(args.selector, args.bw_ratio)
+        log("%s: preprocessed in %.1f ms (q=%d k=%d M=%d)" % (P.name, P.prep_ms, P.info.q, P.info.k,
+                                                            P.info.num_messages))
+    ms_per_step = time_steps(parts, args.steps, args.warmup)
+    log("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step))
+    prof_ms, prof = profile_steps(parts, args.steps)
+    log("profiled %d steps: %.3f ms/step" % (args.steps, prof_ms))
+    bytes_step = {k: 0.0 for k in ("plan", "scatter_sc", "scatter_pc", "gather", "merge")}
+    per_iter, outputs, iters_per_run, edges = [], [], [], 0
+    for P in parts:
+        b, pi, outs, ipr, e = P.stats_pass()
+        for k in bytes_step:
+            bytes_step[k] += b[k]
+        per_iter += [dict(r, graph=P.name) for r in pi]
+        outputs += [(P.name, *o) for o in outs]
+        iters_per_run += ipr
+        edges += e
+    dom, per_kernel, roof = roofline_of(prof, bytes_step, args.steps)
+    gteps = edges / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": "GTEPS (traversed directed CSR edges per second) and % of HBM peak per iteration; "
+                  "learned vs analytical mode-select speedup",
+        "value": gteps, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32+f32", "data": "synthetic",
+        "config": {"workload": "RMAT-%d ef16: BFS levels from 8 sources + min-label CC on the symmetrised graph "
+                               "(%d vertices, %d CSR entries), PageRank 10 it d=0.85 on the directed graph "
+                               "(%d edges)" % (scale, gs.n, gs.m, gd.m),
+                   "graphs": {P.name: {"vertices": P.g.n, "edges": P.g.m, "q": P.info.q, "k": P.info.k,
+                                       "pc_messages": P.info.num_messages, "nonempty_bins": P.info.nonempty_bins,
+                                       "preprocess_ms": P.prep_ms} for P in parts},
+                   "selector": args.selector, "bw_ratio": args.bw_ratio, "combine": args.combine,
+                   "runs_per_step": sum(len(P.runs) for P in parts), "iterations_per_run": iters_per_run,
+                   "edges_traversed_per_step": edges, "profiled_ms_per_step": prof_ms,
+                   "generation_s": gen_s, "seed": gg.BASE_SEED + 7},
+        "roofline": dict(roof, traffic=measured_traffic(dom, "rmat%d" % scale)),
+        "per_kernel": per_kernel,
+        "per_iteration": {"summary": iteration_summary(per_iter), "iterations": per_iter},
+    }
+    if args.copy_mib:
+        out["copy_ceiling"] = copy_ceiling(args.copy_mib)
+        out["roofline"]["frac_of_copy"] = roof["achieved"] / out["copy_ceiling"]["GBps"]
+
+    if not args.no_learned:
+        out["selector"] = selector_compare(args, parts, ms_per_step)
+    del parts
+    torch.cuda.empty_cache()
+
+    if c2 is not None:
+        P2 = Part("rmat22_sym", c2, runs_c2, 14, args)
+        P2.G.set_selector(args.selector, args.bw_ratio)
+        ms2 = time_steps([P2], args.steps, args.warmup)
+        pms2, prof2 = profile_steps([P2], args.steps)
+        b2, pi2, outs2, ipr2, e2 = P2.stats_pass()
+        dom2, pk2, roof2 = roofline_of(prof2, b2, args.steps)
+        outputs += [(P2.name, *o) for o in outs2]
+        out["rmat22"] = {"workload": "BFS levels from 8 sources + min-label CC, RMAT scale 22 ef16 symmetrised",
+                         "GTEPS": e2 / (ms2 * 1e-3) / 1e9, "ms_per_step": ms2, "iterations_per_run": ipr2,
+                         "roofline": dict(roof2, traffic=measured_traffic(dom2, "bfs_cc_rmat22")),
+                         "per_kernel": pk2, "per_iteration_summary": iteration_summary(pi2)}
+        log("rmat22: %.3f ms/step, %.1f GTEPS" % (ms2, out["rmat22"]["GTEPS"]))
+        del P2
+
+    if futs is not None:
+        t = time.perf_counter()
+        cases, ok_all = [], True
+        for gname, prog, root, got in outputs:
+            ref, osec = futs[(gname, prog, root)].result()
+            r = parity_of(prog, got, ref)
+            r.update({"graph": gname, "run": "%s(%d)" % (prog, root), "oracle_s": osec})
+            ok_all = ok_all and r["ok"]
+            cases.append(r)
+        pool.shutdown()
+        out["parity"] = {"ok": ok_all, "cases": len(cases), "rule": "BFS/CC bit-exact; PageRank max-abs <= 1e-6 "
+                         "and relative L1 <= 1e-5 against the FP64 oracle", "checked": cases}
+        log("parity %s over %d outputs (waited %.1f s for the oracle)" % ("ok" if ok_all else "FAILED", len(cases),
+                                                                         time.perf_counter() - t))
+    if not args.no_cpu:
+        # a bounded sample of the step's runs on one host core
+        t0 = time.perf_counter()
+        e, done = 0, []
+        degs = gs.degrees()
+        for prog, root in runs_s:
+            o, _ = oracle_call(gs, prog, root)
+            e += int(degs[o != 0xFFFFFFFF].sum()) if prog == "bfs" else gs.m
+            done.append("%s(%d)" % (prog, root))
+            if time.perf_counter() - t0 > args.cpu_budget / 2:
+                break
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict({"value": e / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                                    "sample": "single-threaded C oracle on the symmetrised RMAT-%d graph: %s in %.1f s"
+                                              % (scale, " ".join(done), dt)}, **host_info())
+    print(json.dumps(out), flush=True)
+    if futs is not None and not out["parity"]["ok"]:
+        sys.exit(3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="bfs_cc_rmat22")
+    ap.add_argument("--workload", default="headline")
+    ap.add_argument("--scale", type=int, default=25, help="headline: RMAT scale")
+    ap.add_argument("--no-parity", action="store_true", help="headline: skip the oracle comparison")
+    ap.add_argument("--no-learned", action="store_true", help="headline: skip the learned-selector comparison")
+    ap.add_argument("--no-rmat22", action="store_true", help="headline: skip the RMAT-22 extra step")
+    ap.add_argument("--train-scale", type=int, default=22, help="headline: largest training graph scale")
+    ap.add_argument("--selector-steps", type=int, default=3, help="headline: steps per selector timing")
     ap.add_argument("--selector", default="analytical")
     ap.add_argument("--bw-ratio", type=float, default=16.0)
     ap.add_argument("--log2-part", type=int, default=0)
@@ -532,7 +968,7 @@ def main():
                     help="size of the device copy used as the practical bandwidth ceiling")
     ap.add_argument("--train-graphs", type=int, default=len(TRAIN_SPECS),
                     help="selector_rmat25: training graphs used (from scale 18 up)")
-    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--eval-scale", type=int, default=25)
     ap.add_argument("--no-tune", action="store_true", help="batches of several graphs: skip the autotuner")
     ap.add_argument("--combine", default="lds", choices=["lds", "rounds"],
@@ -550,6 +986,8 @@ def main():
         if args.steps == 10:
             args.steps = 2
         return selector_eval(args)
+    if args.workload == "headline":
+        return headline(args)
 
     import numpy as np
     import torch
