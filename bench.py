@@ -76,8 +76,15 @@ def kernel_bytes(rec, next_va, q, k, weighted, sum_prog):
     # dangling check
     state_rw = 12 * touched if sum_prog else 4 * touched + 4 * next_va
     state_share = state_rw * (whole / (whole + merged) if whole + merged else 0.0)
+    # the active list: per task that ran, the column stamp and three k-bit
+    # masks (plus the column's k source-centric flags when some partition
+    # scattered source-centric); per listed bin its static entry and piece
+    # prefix, and its counts for a source-centric bin (charged to every bin)
+    kw = (k + 63) // 64
+    tasks = whole + part
+    probe = tasks * (4 + 24 * kw + (k if rec["sc_parts"] else 0)) + rec.get("gathered_bins", 0) * 28
     gather = (ids * (s_id + s_w) + (rec["sc_msgs"] + rec["pc_msgs"]) * s_v
-              + whole * (24 * k + q / 8) + state_share + part * s_part * q
+              + probe + whole * q / 8 + state_share + part * s_part * q
               + next_va * (2 + 4 + 8))
     merge = merged * (q / 8 + q / 8 + 16) + (state_rw - state_share) + part * s_part * q
     return {"plan": plan, "scatter_sc": sc, "scatter_pc": pc, "gather": gather, "merge": merge}

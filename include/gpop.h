@@ -167,7 +167,7 @@ typedef struct gpop_iter_stats {
     uint64_t pc_vertices;        /* vertices of PC partitions                  */
     uint64_t merged_parts;       /* split partitions merged                    */
     uint32_t learned_fallbacks;  /* partitions the learned selector left to Eq. 1 */
-    uint32_t reserved;
+    uint32_t gathered_bins;      /* bins listed by the active list and read by gather */
 } gpop_iter_stats;
 
 /* ------------------------------------------------------------------ setup */

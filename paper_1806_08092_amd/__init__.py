@@ -82,7 +82,7 @@ class IterStats(ctypes.Structure):
                 ("split_tasks", ctypes.c_uint32), ("sc_active_vertices", ctypes.c_uint64),
                 ("sc_active_edges", ctypes.c_uint64), ("pc_vertices", ctypes.c_uint64),
                 ("merged_parts", ctypes.c_uint64), ("learned_fallbacks", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("gathered_bins", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}

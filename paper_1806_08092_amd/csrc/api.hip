@@ -161,6 +161,9 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->bin_moff = (uint32_t*)take((kk + 1) * 4);
     G->bin_ioff = (uint32_t*)take((kk + 1) * 4);
     G->cm = (uint4*)take(kk * 16);
+    const uint64_t kw = (k + 63) / 64;
+    G->colsrc = (uint64_t*)take(k * kw * 8);
+    G->spre = (uint32_t*)take(kk * 4);
     G->png_src = (uint16_t*)take(E_pad * 2);
     G->png_ids = (uint16_t*)take(E_pad * 2);
     G->png_w = (uint8_t*)take(E_pad);
@@ -177,6 +180,10 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->sc_w = (uint8_t*)take(E_pad);
     G->sc_chunk = (uint32_t*)take(nch * 4);
     G->sc_cnt = (uint2*)take(kk * 8);
+    G->nz = (uint8_t*)take(k * kw * 64);
+    G->cact = (uint32_t*)take(k * 4);
+    G->pcmask = (uint64_t*)take(kw * 8);
+    G->scmask = (uint64_t*)take(kw * 8);
     G->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
     G->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
     G->sc_sh = (uint8_t*)take(k);
@@ -478,6 +485,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     G.s = s;
     G.q = 1u << s;
     G.k = (G.V + G.q - 1) / G.q;
+    G.kw = (G.k + 63) / 64;
     G.nbits = 0;
     while ((1u << G.nbits) < G.k) ++G.nbits;
     G.off = desc->offsets;
@@ -527,6 +535,8 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     HIP_OR_RETURN(launch_scan_excl(G.cnt_i, G.bin_ioff, kk, G.scan_tmp, st), "scan ids");
     HIP_OR_RETURN(launch_part_M(G, st), "partition messages");
     HIP_OR_RETURN(launch_colmajor(G, st), "column table");
+    HIP_OR_RETURN(launch_colsrc(G, st), "column source masks");
+    HIP_OR_RETURN(hipMemsetAsync(G.cact, 0, (size_t)G.k * 4, st), "clear column stamps");
     HIP_OR_RETURN(launch_sc_build(G, 1, st), "fill PNG");
 
     std::vector<uint32_t> partM(G.k), cnti(kk), ioff(kk + 1);
@@ -1105,6 +1115,10 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     D->sc_w = S.w ? (uint8_t*)take(E_pad) : nullptr;
     D->sc_chunk = (uint32_t*)take(E_pad / kChunk * 4);
     D->sc_cnt = (uint2*)take(kk * 8);
+    D->nz = (uint8_t*)take(k * ((k + 63) / 64) * 64);
+    D->cact = (uint32_t*)take(k * 4);
+    D->pcmask = (uint64_t*)take((k + 63) / 64 * 8);
+    D->scmask = (uint64_t*)take((k + 63) / 64 * 8);
     D->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
     D->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
     D->sc_sh = (uint8_t*)take(k);
@@ -1197,6 +1211,7 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
         k_max = std::max(k_max, S.k);
         q_max = std::max(q_max, S.q);
         HIP_OR_RETURN(hipMemsetAsync(I.G.ctrl, 0, sizeof(Ctrl), st), "clear run control");
+        HIP_OR_RETURN(hipMemsetAsync(I.G.cact, 0, (size_t)S.k * 4, st), "clear column stamps");
     }
     BatchGrid& B = b->grid;
     B.tab = b->d_tab;

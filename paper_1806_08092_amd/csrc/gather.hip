@@ -14,6 +14,19 @@ constexpr uint32_t kGW = kGT / 64;
 // 256-id piece per such bin would leave most of its lanes idle.
 constexpr uint32_t kSmallBin = 8;
 
+// Words of a partition bitmask (k <= 4096 partitions).
+constexpr uint32_t kMaxMaskWords = 64;
+
+// Bits [lo, hi] of 64-bit word w of a partition mask.
+__device__ __forceinline__ uint64_t range_bits(uint32_t w, uint32_t lo, uint32_t hi) {
+    const uint32_t a = w * 64u, b = a + 63u;
+    if (hi < a || lo > b) return 0ull;
+    uint64_t m = ~0ull;
+    if (lo > a) m &= ~0ull << (lo - a);
+    if (hi < b) m &= ~0ull >> (b - hi);
+    return m;
+}
+
 // Programs whose initFunc keeps vertices active need a per-vertex carry flag
 // (the PageRank family keeps it in the top bit of its accumulator).
 __host__ __device__ constexpr bool has_carry(int prog) { return prog == P_CARRY; }
@@ -22,7 +35,7 @@ constexpr unsigned long long kCarried = 1ull << 63;  // sum programs: vertex was
 // LDS layout of the gather workgroup (bytes, all offsets 16-aligned). The
 // bin-list arrays double as scratch for the frontier masks in the filter.
 struct GatherLds {
-    size_t state, tag, carry, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
+    size_t state, tag, carry, amask, pcm, bl_ioff, bl_icnt, bl_moff, bl_mcnt, bl_jlo, bl_scan, total;
 };
 
 // `rounds`: the atomic-free combine, whose sum programs need a 16-bit tag per
@@ -33,6 +46,8 @@ __host__ __device__ inline GatherLds gather_layout(int prog, uint32_t q, bool ro
     L.state = o;  o += (size_t)q * (is_sum(prog) ? 8 : 4);
     L.tag = o;    o += (rounds && is_sum(prog)) ? ((size_t)q * 2 + 15) / 16 * 16 : 0;
     L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
+    L.amask = o;  o += kMaxMaskWords * 8;
+    L.pcm = o;    o += kMaxMaskWords * 8;
     L.bl_ioff = o; o += kGT * 4;
     L.bl_icnt = o; o += kGT * 4;
     L.bl_moff = o; o += kGT * 4;
@@ -49,10 +64,6 @@ size_t gather_lds_bytes(int prog, uint32_t q, bool rounds) { return gather_layou
 // ballots.
 __device__ __forceinline__ uint32_t wave_excl_small(uint32_t c) {
     return popc_lt(ballot(c & 1u)) + 2u * popc_lt(ballot(c & 2u)) + 4u * popc_lt(ballot(c & 4u));
-}
-
-__device__ __forceinline__ uint32_t pieces_of(uint32_t ioff, uint32_t icnt) {
-    return icnt ? (ioff + icnt - 1u) / kChunk - ioff / kChunk + 1u : 0u;
 }
 
 struct GatherShared {
@@ -275,8 +286,15 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
 // the filter; heavy partitions (RMAT hubs) get several tasks that each leave
 // a partial result for k_merge.
 //
-// Bins are enumerated from the per-partition modes and counts (the two-level
-// active list: only non-empty bins of the scattered partitions are read).
+// Bins are enumerated through the two-level active list (Sec. 3.1.3): the
+// SC offset scan stamps every column that receives source-centric ids
+// (level 1, cact) and flags each non-empty source-centric bin (nz); the plan
+// writes the masks of the partitions scattered in each mode. A task first
+// builds its column's k-bit mask of bins with ids this iteration --
+// partition-centric sources from the static column mask, source-centric ones
+// from the flags, read only when the column is stamped -- and then reads the
+// counts of those bins alone: a column without messages costs two loads, a
+// sparse one a few words per 64 source partitions.
 // Each wave decodes a contiguous run of pieces: message index of an id =
 // chunk-table base + number of message-start flags after the piece start.
 //
@@ -342,13 +360,48 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     uint32_t* bl_scan = reinterpret_cast<uint32_t*>(smem + L.bl_scan);
     __shared__ GatherShared sh;
 
+    // ---- the two-level active list. Level 1: does column cq receive
+    //      anything? (stamped by the source-centric scan; partition-centric
+    //      sources exist only if some partition scattered in that mode).
+    //      Level 2: the k-bit mask of source partitions whose bin to cq holds
+    //      ids, built one byte (8 partitions) per thread with independent
+    //      loads: partition-centric sources from the static column mask,
+    //      source-centric ones from the scan's flags.
+    uint64_t* amask = reinterpret_cast<uint64_t*>(smem + L.amask);
+    uint64_t* pcm = reinterpret_cast<uint64_t*>(smem + L.pcm);
+    {
+        const bool sc_col = gptr(G.cact)[cq] == it + 1u;
+        const bool pc_any = gptr(G.ctrl)->n_pcpart != 0u;
+        uint8_t* ab = reinterpret_cast<uint8_t*>(amask);
+        uint8_t* pb = reinterpret_cast<uint8_t*>(pcm);
+        const uint32_t g = tid;  // byte g covers partitions [8g, 8g + 8); k <= 4096 = 8 * kGT
+        if (g < G.kw * 8u) {
+            uint32_t scb = 0, pcb = 0;
+            if (sc_col) {
+                const uint64_t f = *reinterpret_cast<const uint64_t*>(gptr(G.nz) + (size_t)cq * G.kw * 64u + 8u * g);
+                uint32_t bits = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bits |= (uint32_t)((f >> (8 * j)) & 1u) << j;
+                scb = bits & reinterpret_cast<const uint8_t*>(gptr(G.scmask))[g];
+            }
+            if (pc_any)
+                pcb = reinterpret_cast<const uint8_t*>(gptr(G.colsrc) + (size_t)cq * G.kw)[g] &
+                      reinterpret_cast<const uint8_t*>(gptr(G.pcmask))[g];
+            ab[g] = (uint8_t)(scb | pcb);
+            pb[g] = (uint8_t)pcb;
+        }
+    }
+    __syncthreads();
+    auto abit = [&](uint32_t p) -> bool { return (amask[p >> 6] >> (p & 63u)) & 1ull; };
+    auto pcbit = [&](uint32_t p) -> bool { return (pcm[p >> 6] >> (p & 63u)) & 1ull; };
+
     // ---- a split partition with few ids this iteration (a sparse frontier)
     //      is gathered whole by its first task: no partial results, no merge
     if (split) {
         uint32_t c = 0;
         for (uint32_t p = tid; p < k; p += kGT) {
-            const uint32_t md = gptr(G.mode)[p];
-            c += md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
+            if (!abit(p)) continue;
+            c += pcbit(p) ? cmcol[p].w : sccol[p].y;
         }
         c = wave_sum_u32(c);
         if (lane == 0) sh.wc[wave] = c;
@@ -374,14 +427,20 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         }
     }
 
-    // ---- anything to do for this task?
-    int any = (!split && !msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0) ? 1 : 0;
-    for (uint32_t p = p_lo + tid; p <= p_hi && !any; p += kGT) {
-        const uint32_t md = gptr(G.mode)[p];
-        const uint32_t ic = md == GPOP_MODE_PC ? cmcol[p].w : (md == GPOP_MODE_SC ? sccol[p].y : 0u);
-        any |= ic > 0;
+    // ---- anything to do for this task? (bins with ids in its source range,
+    //      or, for programs that carry vertices, an active set to filter)
+    uint32_t mine = 0;  // listed bins of the thread's byte inside [p_lo, p_hi]
+    if (tid < G.kw * 8u) {
+        const uint32_t byte = reinterpret_cast<const uint8_t*>(amask)[tid];
+        const uint64_t r = range_bits(tid >> 3, p_lo, p_hi) >> (8u * (tid & 7u));
+        mine = (uint32_t)__popc(byte & (uint32_t)(r & 0xFFu));
     }
-    any = __syncthreads_or(any);
+    const uint32_t wbins = wave_sum_u32(mine);
+    if (lane == 0) sh.wsm[wave] = wbins;
+    const bool any = __syncthreads_or(mine > 0u || (tid == 0 && !split && !msg_only(PROG) &&
+                                                    gptr(G.fVa[cur])[cq] > 0));
+    uint32_t nbins = 0;
+    for (uint32_t w = 0; w < kGW; ++w) nbins += sh.wsm[w];
     if (!any) {
         if (tid == 0) {
             if (split) {
@@ -396,7 +455,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         }
         return;
     }
-    if (tid == 0) gptr(G.gat_ran)[task] = split ? 2u : 1u;
+    if (tid == 0) gptr(G.gat_ran)[task] = (split ? 2u : 1u) | (nbins << 2);
 
     // ---- LDS copy of the partition at the combine identity (the filter
     //      compares it with the stored values)
@@ -412,22 +471,30 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     }
 
     // ---- gather the task's pieces, bins in windows of kGT source partitions
+    //      (a window without a listed bin is skipped)
     uint32_t my_ids = 0;
-    uint32_t sp_run = 0;  // static pieces of the bins before the current window
+    // static pieces of the bins before p_lo: the task's piece range [s0, s1)
+    // counts from there
+    const uint32_t sbase = gptr(G.spre)[(size_t)cq * k + p_lo];
     for (uint32_t p0 = p_lo; p0 <= p_hi; p0 += kGT) {
+        const uint32_t pw_hi = min(p0 + kGT - 1u, p_hi);
+        bool wany = false;
+        for (uint32_t w = p0 >> 6; w <= (pw_hi >> 6); ++w) wany |= (amask[w] & range_bits(w, p0, pw_hi)) != 0ull;
+        if (!wany) continue;  // uniform
         const uint32_t p = p0 + tid;
-        const bool inr = p <= p_hi;
-        const uint32_t md = inr ? gptr(G.mode)[p] : GPOP_MODE_NONE;
-        uint32_t sp = 0, ioff = 0, icnt = 0, moff = 0, mcnt = 0;
+        const bool inr = p <= p_hi && abit(p);
+        const bool is_pc = inr && pcbit(p);
+        const uint32_t md = !inr ? GPOP_MODE_NONE : (is_pc ? GPOP_MODE_PC : GPOP_MODE_SC);
+        uint32_t ioff = 0, icnt = 0, moff = 0, mcnt = 0, SP = 0;
         if (inr) {
             const uint4 c = cmcol[p];
-            sp = pieces_of(c.y, c.w);
             ioff = c.y;
             moff = c.x;
-            if (md == GPOP_MODE_PC) {
+            SP = gptr(G.spre)[(size_t)cq * k + p] - sbase;
+            if (is_pc) {
                 icnt = c.w;
                 mcnt = c.z;
-            } else if (md == GPOP_MODE_SC) {
+            } else {
                 const uint2 d = sccol[p];
                 icnt = d.y;
                 mcnt = d.x;
@@ -437,17 +504,6 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         // a task that covers whole bins takes a bin of at most kSmallBin ids
         // with one lane (below) instead of as pieces of 256-id chunks
         const bool small = !ROUNDS && !split && icnt > 0 && icnt <= kSmallBin;
-        // static piece prefix of this bin inside the task's enumeration
-        const uint32_t sincl = wave_incl_scan(sp);
-        if (lane == 63) sh.ws[wave] = sincl;
-        __syncthreads();
-        uint32_t sbefore = 0, stot = 0;
-        for (uint32_t w = 0; w < kGW; ++w) {
-            if (w < wave) sbefore += sh.ws[w];
-            stot += sh.ws[w];
-        }
-        const uint32_t SP = sp_run + sbefore + sincl - sp;
-        sp_run += stot;
         // pieces of this bin that fall in [s0, s1)
         const uint32_t jlo = s0 > SP ? s0 - SP : 0u;
         const uint32_t jhi = min(dp, s1 > SP ? s1 - SP : 0u);

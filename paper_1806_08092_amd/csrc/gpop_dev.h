@@ -91,12 +91,14 @@ struct Ctrl {
     uint32_t max_it;      // a plan at this index pauses the run (done bit 2)
     uint32_t run_start;   // pos when the current run began
     uint32_t n_scunits;   // source-centric scan units of the current iteration
-    uint32_t pad[48];
+    uint32_t n_pcpart;    // partitions scattered partition-centric in the current iteration
+    uint32_t pad[47];
 };
 
 // Everything the kernels read or write, by value in each launch.
 struct Dev {
     uint32_t V, k, s, q;      // vertices, partitions, log2 q, q
+    uint32_t kw;              // 64-bit words of a k-bit partition mask
     uint32_t nbits;           // bits needed for a partition id
     uint32_t n_pctask;        // partition-centric scatter tasks (static)
     uint32_t sc_shift;        // log2 of the active edges per source-centric task
@@ -116,6 +118,8 @@ struct Dev {
     uint32_t* bin_moff;       // [k*k+1] row-major message offsets
     uint32_t* bin_ioff;       // [k*k+1] row-major id offsets
     uint4* cm;                // [k*k] column-major {moff, ioff, mcnt, icnt}, index q*k+p
+    uint64_t* colsrc;         // [k*kw] static: bit p of column q's words set iff bin[p][q] has ids
+    uint32_t* spre;           // [k*k] static: 256-id pieces of bins[0..p)[q], index q*k+p
     uint16_t* png_src;        // [M] local source id of each message
     uint16_t* png_ids;        // [E_pad] static ids
     uint8_t* png_w;           // [E_pad] static weights
@@ -133,6 +137,11 @@ struct Dev {
     uint8_t* sc_w;            // [E_pad]
     uint32_t* sc_chunk;       // [E_pad/256]
     uint2* sc_cnt;            // [k*k] column-major {mcnt, icnt} of SC bins
+    uint8_t* nz;              // [k*kw*64] column-major, column stride kw*64: SC bin[p][q] received ids
+                              // (1 / 0; valid for partitions scattered source-centric)
+    uint32_t* cact;           // [k] column q received SC ids in the iteration with this plan index
+    uint64_t* pcmask;         // [kw] partitions scattered partition-centric this iteration
+    uint64_t* scmask;         // [kw] partitions scattered source-centric this iteration
     uint2* sc_tot;            // [k*col_blocks(k)] SC totals {msgs, ids} per (partition, scan unit)
     uint32_t* sc_units;       // [k*col_blocks(k)] scan units: p | column block << 16 | bit 31 whole row
     uint8_t* sc_sh;           // [k] log2 work units per source-centric task of each partition
@@ -281,6 +290,11 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
 #pragma unroll
     for (int step = 0; step < 6; ++step) x = f64_dpp_add(x, (uint64_t)__double_as_longlong(x), step);
     return __longlong_as_double((long long)lane63_u64((uint64_t)__double_as_longlong(x)));
+}
+
+// 256-id decode pieces touched by the id range [ioff, ioff + icnt).
+__host__ __device__ __forceinline__ uint32_t pieces_of(uint32_t ioff, uint32_t icnt) {
+    return icnt ? (ioff + icnt - 1u) / kChunk - ioff / kChunk + 1u : 0u;
 }
 
 __device__ __forceinline__ bool test_bit(const uint32_t* bits, uint32_t i) {

@@ -175,4 +175,31 @@ hipError_t launch_colmajor(const Dev& G, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Static level-2 tables of the active list, one wave per column q: the
+// source-partition bitmask of q's non-empty bins (colsrc) and the exclusive
+// prefix of the bins' 256-id pieces in source order (spre), which places any
+// bin inside the column's static piece enumeration without a scan.
+__global__ __launch_bounds__(256) void k_colsrc(Dev G) {
+    const uint32_t q = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (q >= G.k) return;
+    const uint4* __restrict__ col = G.cm + (size_t)q * G.k;
+    uint32_t run = 0;
+    for (uint32_t p0 = 0; p0 < G.k; p0 += 64) {
+        const uint32_t p = p0 + lane;
+        const uint4 c = p < G.k ? col[p] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t sp = pieces_of(c.y, c.w);
+        const uint32_t incl = wave_incl_scan(sp);
+        if (p < G.k) G.spre[(size_t)q * G.k + p] = run + incl - sp;
+        const uint64_t m = ballot(c.w > 0u);
+        if (lane == 0) G.colsrc[(size_t)q * G.kw + (p0 >> 6)] = m;
+        run += last_lane(incl);
+    }
+}
+
+hipError_t launch_colsrc(const Dev& G, hipStream_t st) {
+    hipLaunchKernelGGL(k_colsrc, dim3((G.k + 3) / 4), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
 }  // namespace gpop

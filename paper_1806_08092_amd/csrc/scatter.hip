@@ -247,6 +247,10 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
     const uint32_t k = G.k;
     const uint32_t* __restrict__ t0 = BUILD ? gptr(G.bld_t0) : gptr(G.sc_t0);
     const uint32_t tb = t0[p], n = t0[p + 1] - tb;
+    // level 1 of the active list: a column that receives source-centric ids
+    // is stamped with the plan index of this iteration (every writer stores
+    // the same value)
+    const uint32_t stamp = BUILD ? 0u : gptr(G.ctrl)->pos;
     const uint32_t tid = threadIdx.x, ql = tid & 63u, strip = tid >> 6;
     __shared__ uint32_t s_m[16][64], s_i[16][64];
     __shared__ uint64_t s_tot[2][16];
@@ -276,6 +280,8 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
             ri += x.y;
         }
         gptr(G.sc_cnt)[(size_t)q * k + p] = make_uint2(rm, ri);
+        gptr(G.nz)[(size_t)q * G.kw * 64u + p] = ri != 0u;
+        if (ri) gptr(G.cact)[q] = stamp;
         my_tm += rm;
         my_ti += ri;
     }
@@ -340,6 +346,8 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
                     gptr(G.cnt_i)[(size_t)p * k + q] = ti;
                 } else {
                     gptr(G.sc_cnt)[(size_t)q * k + p] = make_uint2(tm, ti);
+                    gptr(G.nz)[(size_t)q * G.kw * 64u + p] = ti != 0u;
+                    if (ti) gptr(G.cact)[q] = stamp;
                     my_tm += tm;
                     my_ti += ti;
                 }
@@ -512,9 +520,9 @@ __global__ __launch_bounds__(kPcT) void kb_pc(const Inst* __restrict__ tab, cons
 // gathered) from per-partition values the previous iteration wrote. Reads
 // mode[], so it must run before the next plan overwrites it.
 __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
-    __shared__ uint64_t red[6][16];
+    __shared__ uint64_t red[7][16];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u, B = blockDim.x;
-    uint64_t v[6] = {0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged
+    uint64_t v[7] = {0, 0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged, bins
     const uint32_t ncb = col_blocks(G.k);
     const uint32_t nt = G.n_gtask + G.n_gsplit;
     // Loads go out in batches before the sums that use them: the first four
@@ -533,9 +541,10 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
 #pragma unroll
         for (uint32_t u = 0; u < kTB; ++u) {
             v[2] += ids[u];
-            v[3] += ran[u] == 1;
-            v[4] += ran[u] == 2;
-            v[5] += ran[u] == 3;
+            v[3] += (ran[u] & 3u) == 1;
+            v[4] += (ran[u] & 3u) == 2;
+            v[5] += (ran[u] & 3u) == 3;
+            v[6] += ran[u] >> 2;
         }
     };
     uint32_t ids0[kTB], ran0[kTB];
@@ -560,14 +569,14 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
         task_batch(t0, ids, ran);
         task_sum(ids, ran);
     }
-    for (int j = 0; j < 6; ++j) v[j] = wave_sum_u64(v[j]);
+    for (int j = 0; j < 7; ++j) v[j] = wave_sum_u64(v[j]);
     if (lane == 0)
-        for (int j = 0; j < 6; ++j) red[j][wave] = v[j];
+        for (int j = 0; j < 7; ++j) red[j][wave] = v[j];
     __syncthreads();
     if (tid == 0) {
-        uint64_t t[6] = {0, 0, 0, 0, 0, 0};
+        uint64_t t[7] = {0, 0, 0, 0, 0, 0, 0};
         for (uint32_t w = 0; w < blockDim.x / 64; ++w)
-            for (int j = 0; j < 6; ++j) t[j] += red[j][w];
+            for (int j = 0; j < 7; ++j) t[j] += red[j][w];
         gpop_iter_stats* r = gptr(G.log) + ((it - 1) % kLogCap);
         r->sc_msgs = t[0];
         r->sc_ids = t[1];
@@ -575,6 +584,7 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
         r->gather_parts = (uint32_t)t[3];
         r->split_tasks = (uint32_t)t[4];
         r->merged_parts = t[5];
+        r->gathered_bins = (uint32_t)t[6];
     }
     __syncthreads();
 }
@@ -656,6 +666,14 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             }
             s_units[p] = units;
             dang += pre ? f_d : gptr(G.dpart[cur])[p];
+        }
+        // level-2 masks of the active list: the partitions scattered in each
+        // mode, one 64-bit word per wave
+        const uint8_t mdp = p < G.k ? gptr(G.mode)[p] : (uint8_t)GPOP_MODE_NONE;
+        const uint64_t pcw = ballot(mdp == GPOP_MODE_PC), scw = ballot(mdp == GPOP_MODE_SC);
+        if (lane == 0 && p0 + 64u * wave < G.k) {
+            gptr(G.pcmask)[(p0 >> 6) + wave] = pcw;
+            gptr(G.scmask)[(p0 >> 6) + wave] = scw;
         }
     }
     // task size of this iteration: about sc_task_target tasks, between
@@ -756,6 +774,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         gptr(G.sc_t0)[G.k] = tcarry;
         C->n_sctask = tcarry;
         C->n_scunits = ucarry;
+        C->n_pcpart = (uint32_t)t[3];
         if (tcarry > G.max_sctask) {  // cannot happen (the bound covers every task size): stop
             C->bug = 1;
             C->done = 1;
@@ -785,6 +804,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             r->gather_parts = 0;
             r->split_tasks = 0;
             r->merged_parts = 0;
+            r->gathered_bins = 0;
         }
     }
 }

@@ -277,6 +277,41 @@ def test_iteration_stats_match_model():
         assert (rec["sc_parts"], rec["pc_parts"]) == (nsc, npc), (it, rec)
 
 
+@pytest.mark.parametrize("sel", SELECTORS)
+def test_active_list_lists_exactly_the_nonempty_bins(sel):
+    """The two-level active list (Sec. 3.1.3): per iteration, gather reads
+    exactly the bins that received ids -- every static bin of a
+    partition-centric partition, and the bins a source-centric partition's
+    active out-edges reach -- counted here from the BFS levels, the mode
+    model and the edge list (no gather task is split at these sizes, so each
+    bin is counted once)."""
+    g, lp = gg.rmat_graph(14, 8, 34, symmetric=True), 8  # k = 64 partitions
+    G, _ = make_graph(g, lp, gather_task_ids=1 << 20)  # one task per column
+    q = 1 << lp
+    png = gpop_ref.build_png(g, q)
+    deg = g.degrees()
+    src = np.repeat(np.arange(g.n), deg)
+    static = {(int(a) // q, int(b) // q) for a, b in zip(src, g.cols)}
+    for root in roots_of(g, 2):
+        say("active list", sel, root)
+        got, iters = run_program(G, "bfs", g.n, root=root, selector=sel)
+        lv = oracle.bfs_levels(g, root)
+        stats = G.iter_stats()
+        assert len(stats) == iters
+        for it, rec in enumerate(stats):
+            act = np.flatnonzero(lv == it)
+            pcs = set()
+            for p in np.unique(act // q).tolist():
+                a = act[act // q == p]
+                m = gpop_ref.choose_mode(png.E[p], png.M[p], len(a), int(deg[a].sum()), png.k)
+                if sel == "pc" or (sel == "analytical" and m == "PC"):
+                    pcs.add(p)
+            e_act = np.isin(src, act)
+            sc_bins = {(int(a) // q, int(b) // q) for a, b in zip(src[e_act], g.cols[e_act]) if int(a) // q not in pcs}
+            pc_bins = {bn for bn in static if bn[0] in pcs}
+            assert rec["gathered_bins"] == len(sc_bins | pc_bins), (sel, root, it, rec)
+
+
 def test_default_selector_uses_ratio_16():
     """A new graph selects by Eq. 1 with BW_PC / BW_SC = 16 until
     gpop_set_selector changes it."""
