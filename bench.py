@@ -978,6 +978,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--eval-scale", type=int, default=25)
     ap.add_argument("--no-tune", action="store_true", help="batches of several graphs: skip the autotuner")
+    ap.add_argument("--isg", type=int, default=0,
+                    help="interleaved scatter-gather colour classes (0: off; BFS, CC and SSSP only)")
     ap.add_argument("--combine", default="lds", choices=["lds", "rounds"],
                     help="gather combine: LDS min/add per message, or the atomic-free rounds")
     args = ap.parse_args()
@@ -1020,6 +1022,8 @@ def main():
     log("preprocessed in %.1f ms: q=%d k=%d M=%d bins=%d" % (prep_ms, info.q, info.k, info.num_messages,
                                                              info.nonempty_bins))
     G.set_selector(args.selector, args.bw_ratio)
+    if args.isg:
+        G.set_isg(args.isg)
     st = torch.empty(g.n, dtype=torch.int32, device="cuda")
     roots = {r: torch.tensor([r], dtype=torch.int32, device="cuda") for _, r in runs}
     max_iter = {"pagerank": 10, "ppr": 20, "nibble": 20}
@@ -1118,6 +1122,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "vertices": g.n, "edges": g.m, "q": info.q, "k": info.k,
                    "selector": args.selector, "bw_ratio": args.bw_ratio, "combine": args.combine,
+                   "isg_classes": args.isg,
                    "gather_task_ids": args.gather_task_ids, "sc_task_log2": args.sc_task_log2,
                    "runs_per_step": len(runs), "iterations_per_run": iters_per_run,
                    "edges_traversed_per_step": edges_per_step, "preprocess_ms": prep_ms,

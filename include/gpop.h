@@ -231,6 +231,24 @@ int gpop_set_frontier_all(struct gpop_graph* g, void* stream);
 int gpop_set_selector(struct gpop_graph* g, gpop_selector kind, float bw_ratio,
                       uint32_t s_i, uint32_t s_v, const void* d_mlp);
 
+/* Interleaved scatter-gather (Sec. 3.3): when a partition is scattered it
+ * should already carry the updates its in-neighbours sent earlier in the same
+ * iteration. Here the partitions are cut into `classes` contiguous index
+ * ranges (colour classes); engine iteration t scatters only the active
+ * partitions of class t mod classes and gathers every column, and the other
+ * active partitions keep their frontier, so they scatter in a later
+ * iteration with values those gathers already improved. Every wait stays at
+ * a kernel boundary. classes = 0 or 1 turns it off (the default); 2..16 turn
+ * it on. Each engine iteration (one class scattered) counts as an iteration
+ * of gpop_run and of the statistics records. Only the programs whose gather
+ * keeps a minimum, whose result is the unique fixed point whatever the order
+ * of updates, take it: BFS_LEVEL, CC_MINLABEL and SSSP_U32 (the paper
+ * enables it for connected components and SSSP). Errors: GPOP_EINVAL for
+ * classes > 16; GPOP_ENOTSUP if the bound program is another one (and
+ * gpop_state_init of another program fails with GPOP_ENOTSUP while it is
+ * on). */
+int gpop_set_isg(struct gpop_graph* g, uint32_t classes);
+
 /* Per-partition features of the learned selector (gpop_mlp.h) for the
  * current frontier and iteration: writes k x GPOP_MLP_IN floats (row p =
  * partition p) to d_out. Partitions without active vertices get their

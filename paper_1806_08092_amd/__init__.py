@@ -115,6 +115,7 @@ _SIGS = {
     "gpop_set_frontier_all": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "gpop_set_selector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]),
+    "gpop_set_isg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "gpop_scatter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "gpop_gather": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "gpop_iterate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -277,6 +278,10 @@ class Graph:
                      mlp=None):
         kind = SELECTORS[kind] if isinstance(kind, str) else int(kind)
         _check(lib().gpop_set_selector(self.h, kind, bw_ratio, s_i, s_v, _ptr(mlp)))
+
+    def set_isg(self, classes: int):
+        """Interleaved scatter-gather in `classes` colour classes (0: off)."""
+        _check(lib().gpop_set_isg(self.h, classes))
 
     def features(self, stream=None):
         """k x 12 float32 CUDA tensor of the learned selector's features."""

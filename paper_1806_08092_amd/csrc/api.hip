@@ -726,6 +726,12 @@ int gpop_graph_get_info(const gpop_graph* g, gpop_graph_info* out) {
 
 namespace {
 
+// Programs whose result does not depend on the order of updates (a minimum
+// fixed point), so that interleaved scatter-gather leaves it unchanged.
+bool isg_program(int prog) {
+    return prog == GPOP_PROG_BFS_LEVEL || prog == GPOP_PROG_CC_MINLABEL || prog == GPOP_PROG_SSSP_U32;
+}
+
 // Argument checks shared by gpop_state_init and gpop_batch_state_init.
 int check_program(const gpop_graph* g, gpop_program prog, const gpop_params* prm) {
     if ((int)prog < 0 || (int)prog > GPOP_PROG_NIBBLE_F32) return fail(GPOP_EINVAL, "unknown program %d", (int)prog);
@@ -739,6 +745,8 @@ int check_program(const gpop_graph* g, gpop_program prog, const gpop_params* prm
         return fail(GPOP_EINVAL, "alpha must be in [0, 1]");
     if (prog == GPOP_PROG_NIBBLE_F32 && !(prm->epsilon > 0.f && std::isfinite(prm->epsilon)))
         return fail(GPOP_EINVAL, "epsilon must be finite and > 0");
+    if (g->P.isg > 1 && !isg_program(prog))
+        return fail(GPOP_ENOTSUP, "interleaved scatter-gather is on; program %d does not take it", (int)prog);
     const bool rounds = g->G.combine == GPOP_COMBINE_ROUNDS;
     if (gather_lds_bytes(prog, g->G.q, rounds) + 2048 > (size_t)max_lds_per_block())
         return fail(GPOP_ENOTSUP, "program %d needs %zu bytes of LDS at q = %u; use a smaller partition",
@@ -845,6 +853,16 @@ int gpop_set_selector(gpop_graph* g, gpop_selector kind, float bw_ratio, uint32_
     g->P.s_v = s_v;
     if (kind == GPOP_SEL_LEARNED && !d_mlp) g->P.selector = GPOP_SEL_ANALYTICAL;
     g->grid.learned = g->P.selector == GPOP_SEL_LEARNED;
+    if (g->prog >= 0) return upload_tab(g, nullptr);  // the run reads its parameters on the device
+    return GPOP_OK;
+}
+
+int gpop_set_isg(gpop_graph* g, uint32_t classes) {
+    if (!g) return fail(GPOP_EINVAL, "NULL graph");
+    if (classes > 16) return fail(GPOP_EINVAL, "at most 16 colour classes (got %u)", classes);
+    if (classes > 1 && g->prog >= 0 && !isg_program(g->prog))
+        return fail(GPOP_ENOTSUP, "program %d does not take interleaved scatter-gather", g->prog);
+    g->P.isg = classes > 1 ? classes : 0;
     if (g->prog >= 0) return upload_tab(g, nullptr);  // the run reads its parameters on the device
     return GPOP_OK;
 }

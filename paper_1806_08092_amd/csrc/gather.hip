@@ -110,7 +110,7 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
                                  uint32_t it, uint32_t cq, uint32_t* st32,
                                  unsigned long long* acc, const uint8_t* carry,
                                  uint64_t* kscratch, GatherShared& sh, uint32_t ids_done,
-                                 uint32_t task) {
+                                 uint32_t task, bool carry_col) {
     constexpr bool SUM = is_sum(PROG);
     // 64-vertex groups per step of pass 1: their global loads are issued together
     constexpr uint32_t U = 8;
@@ -142,6 +142,15 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
             else av[i] = in ? acc[u] : 0ull;  // an amount arrived, or active before scatter
         }
         if constexpr (!SUM) {
+            // a column held back by interleaved scatter-gather keeps its
+            // active vertices (the current frontier bitmap), one word per 32
+            uint32_t hw[U];
+#pragma unroll
+            for (uint32_t i = 0; i < U; ++i) {
+                const uint32_t u = g0 + 64u * i + lane;
+                hw[i] = (carry_col && g0 + 64u * i < wend && u < nv)
+                            ? gptr(G.fbits[it & 1u])[(vbase + u) >> 5] : 0u;
+            }
 #pragma unroll
             for (uint32_t i = 0; i < U; ++i)
                 sv[i] = mv[i] != kIdentMin ? state[vbase + g0 + 64u * i + lane] : 0u;
@@ -149,7 +158,7 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
             for (uint32_t i = 0; i < U; ++i) {
                 const uint32_t u = g0 + 64u * i + lane;
                 const bool hit = mv[i] != kIdentMin && (first_write(PROG) ? sv[i] == kIdentMin : mv[i] < sv[i]);
-                keep[i] = hit;
+                keep[i] = hit || ((hw[i] >> (u & 31u)) & 1u);
                 if constexpr (has_carry(PROG)) {
                     const bool in = g0 + 64u * i < wend && u < nv;
                     keep[i] = keep[i] || (in && carry[u]);
@@ -437,8 +446,10 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     }
     const uint32_t wbins = wave_sum_u32(mine);
     if (lane == 0) sh.wsm[wave] = wbins;
-    const bool any = __syncthreads_or(mine > 0u || (tid == 0 && !split && !msg_only(PROG) &&
-                                                    gptr(G.fVa[cur])[cq] > 0));
+    // a column held back by interleaved scatter-gather keeps its frontier
+    const bool carry_col = !SUM && isg_holds(P, cq, k, it) && gptr(G.fVa[cur])[cq] > 0;
+    const bool any = __syncthreads_or(mine > 0u || (tid == 0 && !split && (carry_col || (!msg_only(PROG) &&
+                                                    gptr(G.fVa[cur])[cq] > 0))));
     uint32_t nbins = 0;
     for (uint32_t w = 0; w < kGW; ++w) nbins += sh.wsm[w];
     if (!any) {
@@ -862,7 +873,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         return;
     }
     finish_partition<PROG>(G, P, state, it, cq, st32, acc, carry,
-                           reinterpret_cast<uint64_t*>(bl_ioff), sh, my_ids, task);
+                           reinterpret_cast<uint64_t*>(bl_ioff), sh, my_ids, task, carry_col);
 }
 
 template <int PROG, bool ROUNDS>
@@ -923,7 +934,9 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
         if (lead) gptr(G.gat_ran)[G.n_gtask + sidx] = 0;
         return;
     }
-    const bool prev = !msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0;  // frontier bitmap of cq is current
+    // interleaved scatter-gather: a held-back column keeps its frontier
+    const bool carry_col = !SUM && isg_holds(P, cq, G.k, it);
+    const bool prev = (!msg_only(PROG) || carry_col) && gptr(G.fVa[cur])[cq] > 0;  // frontier bitmap of cq is current
     if (nw == 0 && !prev) {
         if (lead) {
             gptr(G.fVa[nxt])[cq] = 0;
@@ -1013,7 +1026,7 @@ __device__ __forceinline__ void merge_part_body(const Dev& G, const Params& P, u
             const uint32_t u = ulo + kMT * i + tid;
             const bool in = i < nu && u < nv;
             const bool hit = in && m[i] != kIdentMin && (first_write(PROG) ? m0[i] == kIdentMin : m[i] < m0[i]);
-            keep[i] = hit;
+            keep[i] = hit || (carry_col && was[i]);
             if constexpr (has_carry(PROG)) keep[i] = keep[i] || (in && was[i] && (it + 1u - m0[i]) < P.persist);
             if (hit) state[vbase + u] = m[i];
             need[i] = keep[i];

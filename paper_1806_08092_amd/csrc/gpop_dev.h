@@ -180,7 +180,20 @@ struct Params {
     uint32_t s_i, s_v;        // model element sizes (bytes)
     uint32_t ratio_num, ratio_den;  // BW_PC / BW_SC as a fraction
     uint32_t probe;           // scatter kernels time their tasks into Dev::probe
+    uint32_t isg;             // interleaved scatter-gather: colour classes (0 or 1: off)
 };
+
+// Interleaved scatter-gather (Sec. 3.3) in colour classes: partitions are
+// cut into isg contiguous index ranges; iteration it scatters only the
+// active partitions of class it mod isg, and every other active partition
+// keeps its frontier, so it scatters later with the values the gathers in
+// between have already improved.
+__host__ __device__ __forceinline__ uint32_t isg_class(uint32_t p, uint32_t k, uint32_t classes) {
+    return (uint32_t)(((uint64_t)p * classes) / k);
+}
+__host__ __device__ __forceinline__ bool isg_holds(const Params& P, uint32_t p, uint32_t k, uint32_t it) {
+    return P.isg > 1u && isg_class(p, k, P.isg) != it % P.isg;
+}
 
 // One run of a batch: its graph view (static arrays shared with the graph,
 // per-run arrays of its own), its parameters and its state array.

@@ -648,6 +648,9 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
                 else if (P.selector == GPOP_SEL_LEARNED) md = gptr(G.mode_l)[p];
                 else md = analytical_mode_of(G, P, Ep, Mp, Va, Ea);
+                // interleaved scatter-gather: a partition of another colour
+                // class stays active without scattering this iteration
+                if (isg_holds(P, p, G.k, it)) md = GPOP_MODE_NONE;
             }
             gptr(G.mode)[p] = md;
             va += Va;

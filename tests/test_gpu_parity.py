@@ -213,6 +213,88 @@ def edge_arrays(g):
     return rows, g.cols.copy()
 
 
+# Interleaved scatter-gather (Sec. 3.3) in colour classes: BFS levels, SSSP
+# distances and CC labels are the unique minimum fixed points, so the results
+# must equal the oracle's bit for bit whatever the class count.
+@pytest.mark.parametrize("zi", range(9))
+@pytest.mark.parametrize("classes", [2, 3, 16])
+def test_isg_min_programs(zi, classes):
+    name, g, lp, (G, _) = get_zoo()[zi]
+    sym = gg.from_edges(g.n, *gg.symmetrize(*edge_arrays(g)))
+    GS, keep = make_graph(sym, lp)
+    try:
+        G.set_isg(classes)
+        GS.set_isg(classes)
+        for sel in SELECTORS:
+            for root in roots_of(g, 2):
+                say("isg", classes, name, sel, root)
+                got, _ = run_program(G, "bfs", g.n, root=root, selector=sel)
+                assert np.array_equal(got, oracle.bfs_levels(g, root)), ("bfs", name, sel, root)
+                got, _ = run_program(G, "sssp", g.n, root=root, selector=sel)
+                assert np.array_equal(got, oracle.sssp(g, root)), ("sssp", name, sel, root)
+            got, _ = run_program(GS, "cc", sym.n, selector=sel)
+            assert np.array_equal(got, oracle.cc_minlabel(sym)), ("cc", name, sel)
+    finally:
+        G.set_isg(0)
+
+
+@pytest.mark.parametrize("gids,combine", [(256, "lds"), (2048, "lds"), (0, "rounds"), (256, "rounds")])
+def test_isg_split_gather_and_combines(gids, combine):
+    """Columns split over several gather tasks (held-back columns pass
+    through the merge) and the atomic-free combine."""
+    g = gg.rmat_graph(14, 16, 35, symmetric=True, weights_seed=36)
+    G, _ = make_graph(g, 10, gather_task_ids=gids, combine=combine)
+    G.set_isg(4)
+    for root in roots_of(g, 2):
+        say("isg split", gids, combine, root)
+        got, _ = run_program(G, "sssp", g.n, root=root)
+        assert np.array_equal(got, oracle.sssp(g, root)), (gids, combine, root)
+        got, _ = run_program(G, "bfs", g.n, root=root)
+        assert np.array_equal(got, oracle.bfs_levels(g, root)), (gids, combine, root)
+    got, _ = run_program(G, "cc", g.n)
+    assert np.array_equal(got, oracle.cc_minlabel(g)), (gids, combine)
+
+
+def test_isg_at_scale_and_fewer_sweeps():
+    """RMAT-20 symmetrised, default sizes: CC and SSSP bit-exact with two
+    classes; CC needs fewer sweeps (pairs of half-steps) than iterations
+    without interleaving."""
+    g = gg.rmat_graph(20, 16, 37, symmetric=True, weights_seed=38)
+    G, _ = make_graph(g, 14)
+    _, it_plain = run_program(G, "cc", g.n)
+    G.set_isg(2)
+    got, it_isg = run_program(G, "cc", g.n)
+    assert np.array_equal(got, oracle.cc_minlabel(g))
+    say("cc iterations plain %d, isg half-steps %d" % (it_plain, it_isg))
+    assert it_isg <= 2 * it_plain
+    root = roots_of(g, 1)[0]
+    got, _ = run_program(G, "sssp", g.n, root=root)
+    assert np.array_equal(got, oracle.sssp(g, root))
+
+
+def test_isg_rejects_other_programs():
+    import torch
+    import paper_1806_08092_amd as gp
+    name, g, lp, (G, _) = get_zoo()[0]
+    st = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    with pytest.raises(gp.GpopError) as e:
+        G.set_isg(17)
+    assert e.value.code == gp.EINVAL
+    G.set_isg(2)
+    try:
+        for prog in ("pagerank", "ppr", "nibble", "bfs_parent", "carry_bfs"):
+            with pytest.raises(gp.GpopError) as e:
+                G.state_init(prog, st, root=0)
+            assert e.value.code == gp.ENOTSUP, prog
+        G.set_isg(0)
+        G.state_init("pagerank", st)
+        with pytest.raises(gp.GpopError) as e:
+            G.set_isg(2)
+        assert e.value.code == gp.ENOTSUP
+    finally:
+        G.set_isg(0)
+
+
 @pytest.mark.parametrize("zi", [0, 1, 2, 4, 5, 7, 8])
 @pytest.mark.parametrize("sel", SELECTORS)
 def test_pagerank(zi, sel):
