@@ -1346,7 +1346,6 @@ __global__ __launch_bounds__(256) void k_state_init(Dev G, Params P, int prog,
         gptr(G.ctrl)->frontier = 0;
         gptr(G.ctrl)->dangling = 0.0;
         gptr(G.ctrl)->fin_it = 0;
-        gptr(G.ctrl)->mlp_fallback = 0;
         gptr(G.ctrl)->pos = 0;
         gptr(G.ctrl)->max_it = 0xFFFFFFFFu;
         gptr(G.ctrl)->run_start = 0;

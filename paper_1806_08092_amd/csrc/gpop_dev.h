@@ -26,6 +26,7 @@ constexpr uint32_t kLocalMask = 0x7FFFu;  // local destination id bits
 constexpr uint32_t kIdentMin = 0xFFFFFFFFu;  // min-combine identity ("no message")
 constexpr uint32_t kIdentSum = 0x80000000u;  // sum-combine identity: -0.0f bits
 constexpr uint32_t kLogCap = 4096;        // per-iteration stats records
+constexpr uint8_t kFallbackMark = 0x80u;  // a learned mode the network left to Eq. 1
 constexpr uint32_t kScWaves = 4;          // independent source-centric task waves per workgroup
 constexpr uint32_t kMergeSpan = 1024;     // vertices per workgroup of a split-partition merge
 constexpr uint32_t kMaxMergeChunks = 32;  // q / kMergeSpan at the largest partition (2^15)
@@ -86,7 +87,7 @@ struct Ctrl {
     uint64_t frontier;    // sum of V_a at the last plan
     double dangling;      // PageRank-family dangling mass of the current frontier
     uint32_t fin_it;      // records below this iteration are final
-    uint32_t mlp_fallback;  // partitions the learned selector left to Eq. 1
+    uint32_t reserved0;   // keeps the layout of the fields below
     uint32_t pos;         // iterations run so far (index of the next plan)
     uint32_t max_it;      // a plan at this index pauses the run (done bit 2)
     uint32_t run_start;   // pos when the current run began

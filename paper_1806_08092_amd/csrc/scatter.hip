@@ -628,10 +628,10 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         f_d = gptr(G.dpart[cur])[tid];
     }
     finalize_once(G, it);
-    __shared__ uint64_t red[9][kPlanW];
+    __shared__ uint64_t red[10][kPlanW];
     __shared__ double dred[kPlanW];
     __shared__ uint32_t s_w[kPlanW];
-    uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0, sva = 0, sea = 0, pcv = 0;
+    uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0, sva = 0, sea = 0, pcv = 0, nfb = 0;
     double dang = 0.0;
     // pass 1: modes and totals; the source-centric work units (active
     // vertices + active out-edges) of each partition go to LDS
@@ -646,7 +646,11 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
                 else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
-                else if (P.selector == GPOP_SEL_LEARNED) md = gptr(G.mode_l)[p];
+                else if (P.selector == GPOP_SEL_LEARNED) {
+                    const uint8_t ml = gptr(G.mode_l)[p];
+                    md = ml & (uint8_t)~kFallbackMark;
+                    nfb += ml >> 7;
+                }
                 else md = analytical_mode_of(G, P, Ep, Mp, Va, Ea);
                 // interleaved scatter-gather: a partition of another colour
                 // class stays active without scattering this iteration
@@ -753,6 +757,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     sva = wave_sum_u64(sva);
     sea = wave_sum_u64(sea);
     pcv = wave_sum_u64(pcv);
+    nfb = wave_sum_u64(nfb);
     dang = wave_sum_f64(dang);
     if (lane == 0) {
         red[0][wave] = va;
@@ -764,14 +769,15 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         red[6][wave] = sva;
         red[7][wave] = sea;
         red[8][wave] = pcv;
+        red[9][wave] = nfb;
         dred[wave] = dang;
     }
     __syncthreads();
     if (tid == 0) {
-        uint64_t t[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        uint64_t t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         double d = 0.0;
         for (uint32_t w = 0; w < kPlanW; ++w) {
-            for (int j = 0; j < 9; ++j) t[j] += red[j][w];
+            for (int j = 0; j < 10; ++j) t[j] += red[j][w];
             d += dred[w];
         }
         gptr(G.sc_t0)[G.k] = tcarry;
@@ -799,8 +805,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             r->sc_active_vertices = t[6];
             r->sc_active_edges = t[7];
             r->pc_vertices = t[8];
-            r->learned_fallbacks = C->mlp_fallback;
-            C->mlp_fallback = 0;
+            r->learned_fallbacks = (uint32_t)t[9];
             r->sc_msgs = 0;
             r->sc_ids = 0;
             r->gathered_ids = 0;

@@ -68,8 +68,8 @@ __device__ __forceinline__ void select_body(const Dev& G, const Params& P, uint3
     if (mlp_logit(gptr(G.mlp), f, &z)) {
         md = z >= 0.f ? (uint8_t)GPOP_MODE_PC : (uint8_t)GPOP_MODE_SC;
     } else {
-        md = analytical_mode(G, P, p, Va, Ea);
-        atomicAdd(&gptr(G.ctrl)->mlp_fallback, 1u);
+        // left to Eq. 1: bit 7 marks the fallback, which the plan counts
+        md = (uint8_t)(analytical_mode(G, P, p, Va, Ea) | kFallbackMark);
     }
     gptr(G.mode_l)[p] = md;
 }

@@ -3,6 +3,8 @@ import numpy as np
 
 import graphgen as gg
 
+INF = 0xFFFFFFFF
+
 
 def torch_cuda():
     import torch
@@ -46,3 +48,26 @@ def pr_ok(x32, ref64, max_abs=1e-6, rel_l1=1e-5):
     x = x32.astype(np.float64)
     return (np.max(np.abs(x - ref64)) <= max_abs and
             np.sum(np.abs(x - ref64)) <= rel_l1 * np.sum(np.abs(ref64)))
+
+
+def sssp_certificate(g, root, dist):
+    """Shortest-path certificate for positive weights: dist[root] = 0; every
+    edge u -> v with dist[u] finite has dist[v] <= dist[u] + w; every reached
+    v != root has an in-edge with equality; the reached set is the set
+    reachable from root (BFS levels). Together these force dist to equal the
+    shortest-path distances."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.offsets.astype(np.int64)))
+    dst = g.cols.astype(np.int64)
+    w = g.weights.astype(np.int64)
+    d = dist.astype(np.int64)
+    fin = d[src] != INF
+    assert d[root] == 0
+    import oracle
+    reach = oracle.bfs_levels(g, root) != INF
+    assert np.array_equal(dist != INF, reach)
+    cand = d[src[fin]] + w[fin]
+    assert np.all(d[dst[fin]] <= cand)
+    tight = np.zeros(g.n, bool)
+    tight[dst[fin][d[dst[fin]] == cand]] = True
+    tight[root] = True
+    assert np.all(tight[reach])
