@@ -111,6 +111,23 @@ typedef struct gpop_graph_desc {
 #define GPOP_COMBINE_LDS 0u
 #define GPOP_COMBINE_ROUNDS 1u
 
+/* Where gather reads the static ids of partition-centric bins (Sec. 3.1.2;
+ * the results are the same bits either way):
+ *   GPOP_PCSTREAM_AUTO  column streams in iterations where partition-centric
+ *                       partitions hold at least half of the graph's edges,
+ *                       the per-bin layout otherwise (default)
+ *   GPOP_PCSTREAM_OFF   always the per-bin layout; the column streams are
+ *                       not built (smaller workspace, faster preprocessing)
+ *   GPOP_PCSTREAM_ON    column streams whenever a partition is scattered
+ *                       partition-centric
+ * A column stream holds every static id of one destination partition, bins
+ * in source order, cut into 256-id chunks; per chunk a bitmap of bin starts
+ * and a short table ({message offset, source partition}) of the bins that
+ * start in it let a wave decode a whole chunk that spans several bins. */
+#define GPOP_PCSTREAM_AUTO 0u
+#define GPOP_PCSTREAM_OFF 1u
+#define GPOP_PCSTREAM_ON 2u
+
 typedef struct gpop_options {
     uint32_t log2_part;   /* q = 2^log2_part vertices per partition, 8..15;
                              0 picks 14 (16384 vertices)                        */
@@ -124,7 +141,9 @@ typedef struct gpop_options {
                                   hold more ids is gathered by several tasks
                                   (at most 64) and merged                      */
     uint32_t combine;          /* GPOP_COMBINE_LDS (0) or GPOP_COMBINE_ROUNDS   */
-    uint32_t reserved[4];      /* must be zero                                  */
+    uint32_t pc_stream;        /* GPOP_PCSTREAM_AUTO (0), _OFF or _ON: how
+                                  gather reads partition-centric bins       */
+    uint32_t reserved[3];      /* must be zero                                  */
 } gpop_options;
 
 typedef struct gpop_plan_info {

@@ -25,6 +25,8 @@ PROGRAMS = {"bfs": BFS_LEVEL, "cc": CC_MINLABEL, "sssp": SSSP_U32, "pagerank": P
             "ppr": PPR_F32, "carry_bfs": CARRY_BFS, "bfs_parent": BFS_PARENT, "nibble": NIBBLE_F32}
 COMBINE_LDS, COMBINE_ROUNDS = 0, 1
 COMBINES = {"lds": COMBINE_LDS, "rounds": COMBINE_ROUNDS}
+PCSTREAM_AUTO, PCSTREAM_OFF, PCSTREAM_ON = 0, 1, 2
+PCSTREAMS = {"auto": PCSTREAM_AUTO, "off": PCSTREAM_OFF, "on": PCSTREAM_ON}
 # selectors
 SEL_ANALYTICAL, SEL_FORCE_SC, SEL_FORCE_PC, SEL_LEARNED = range(4)
 SELECTORS = {"analytical": SEL_ANALYTICAL, "sc": SEL_FORCE_SC, "pc": SEL_FORCE_PC,
@@ -52,7 +54,7 @@ class GraphDesc(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("log2_part", ctypes.c_uint32), ("sc_task_log2", ctypes.c_uint32),
                 ("gather_task_ids", ctypes.c_uint32), ("combine", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("pc_stream", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -207,9 +209,10 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def plan(num_vertices: int, num_edges: int, log2_part: int = 14, sc_task_log2: int = 0,
-         gather_task_ids: int = 0) -> PlanInfo:
+         gather_task_ids: int = 0, pc_stream="auto") -> PlanInfo:
     d = GraphDesc(num_vertices, 0, num_edges, None, None, None)
-    o = Options(log2_part, sc_task_log2, gather_task_ids)
+    pc_stream = PCSTREAMS[pc_stream] if isinstance(pc_stream, str) else int(pc_stream)
+    o = Options(log2_part, sc_task_log2, gather_task_ids, 0, pc_stream)
     out = PlanInfo()
     _check(lib().gpop_plan(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)))
     return out
@@ -221,7 +224,7 @@ class Graph:
     workspace is allocated here as a torch tensor and owned by this object."""
 
     def __init__(self, offsets, cols, weights=None, log2_part: int = 14, stream=None,
-                 sc_task_log2: int = 0, gather_task_ids: int = 0, combine="lds"):
+                 sc_task_log2: int = 0, gather_task_ids: int = 0, combine="lds", pc_stream="auto"):
         import torch
         self._keep = (offsets, cols, weights)
         n = offsets.numel() - 1
@@ -229,7 +232,8 @@ class Graph:
         self.desc = GraphDesc(n, 0, m, offsets.data_ptr(), cols.data_ptr() if m else 0,
                               None if weights is None else weights.data_ptr())
         combine = COMBINES[combine] if isinstance(combine, str) else int(combine)
-        self.opts = Options(log2_part, sc_task_log2, gather_task_ids, combine)
+        pc_stream = PCSTREAMS[pc_stream] if isinstance(pc_stream, str) else int(pc_stream)
+        self.opts = Options(log2_part, sc_task_log2, gather_task_ids, combine, pc_stream)
         info = PlanInfo()
         _check(lib().gpop_plan(ctypes.byref(self.desc), ctypes.byref(self.opts), ctypes.byref(info)))
         self.q, self.k = info.q, info.k

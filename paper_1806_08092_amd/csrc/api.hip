@@ -113,6 +113,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Sizes {
     uint32_t s, sc_shift;
     uint64_t q, k, T;
+    uint32_t pc_stream;  // GPOP_PCSTREAM_*
 };
 
 Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
@@ -125,6 +126,7 @@ Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
     if (o && o->sc_task_log2) z.sc_shift = o->sc_task_log2;
     z.T = std::max<uint64_t>(1ull << 16, E / 1024);
     if (o && o->gather_task_ids) z.T = o->gather_task_ids;
+    z.pc_stream = o ? o->pc_stream : GPOP_PCSTREAM_AUTO;
     return z;
 }
 
@@ -134,6 +136,20 @@ Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
 // than 2 x sc_task_target of them (plus one partial task per partition).
 uint64_t max_sctask_for(uint32_t V, uint64_t E, const Sizes& z) {
     return std::max<uint64_t>((E + V) >> z.sc_shift, 2ull * sc_task_target((uint32_t)z.k)) + z.k + 1;
+}
+
+// Bounds of the column streams (chunks, entries). A chunk takes at most 62
+// inner bin starts before a padding run moves the next bin to a chunk
+// boundary, so padding adds at most one chunk per 62 non-empty bins, plus
+// one partial chunk per column.
+uint64_t cs_bins_max(uint64_t E, const Sizes& z) { return std::min<uint64_t>(E, z.k * z.k); }
+uint64_t cs_chunks_max(uint64_t E, const Sizes& z) {
+    if (z.pc_stream == GPOP_PCSTREAM_OFF) return 0;
+    return (E + kChunk - 1) / kChunk + z.k + cs_bins_max(E, z) / 62 + 1;
+}
+uint64_t cs_entries_max(uint64_t E, const Sizes& z) {
+    if (z.pc_stream == GPOP_PCSTREAM_OFF) return 0;
+    return cs_chunks_max(E, z) + cs_bins_max(E, z) + cs_bins_max(E, z) / 62 + z.k + 1;
 }
 
 uint64_t max_gtask_for(uint64_t E, const Sizes& z) {
@@ -169,13 +185,22 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->png_w = (uint8_t*)take(E_pad);
     G->png_chunk = (uint32_t*)take(nch * 4);
     G->pctask = (uint4*)take(ntask * 16);
+    {
+        const uint64_t nc = cs_chunks_max(E, z), ne = cs_entries_max(E, z);
+        G->cs_c0 = (uint32_t*)take((k + 1) * 4);
+        G->cs_ids = (uint16_t*)take(nc * kChunk * 2);
+        G->cs_w = (uint8_t*)take(nc * kChunk);
+        G->cs_bm = (uint32_t*)take(nc * 32);
+        G->cs_tabo = (uint32_t*)take((nc + 1) * 4);
+        G->cs_ent = (uint2*)take((ne + 64) * 8);
+    }
     G->bld_t0 = (uint32_t*)take((k + 1) * 4);
     G->gtask = (uint4*)take(ngt * 32);
     G->gsplit = (uint4*)take(k * 16);
     G->gpart = (uint32_t*)take(ngt * q * 8);
     G->gflag = (uint32_t*)take(ngt * 4);
     G->mtot = (uint4*)take(k * kMaxMergeChunks * 16);
-    G->data = (uint32_t*)take(E_pad * 4);
+    G->data = (uint32_t*)take((E_pad + 256) * 4);  // messages (M <= E), then the identity words
     G->sc_ids = (uint16_t*)take(E_pad * 2);
     G->sc_w = (uint8_t*)take(E_pad);
     G->sc_chunk = (uint32_t*)take(nch * 4);
@@ -218,6 +243,115 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     return o;
 }
 
+// Column streams of the partition-centric ids (the layout is described with
+// the cs_* fields of Dev). Each destination partition's non-empty bins are
+// laid out in source order; a bin that would be the 63rd bin to start inside
+// one chunk is moved to the next chunk boundary behind a padding run, so
+// that a chunk's table never exceeds 64 entries. The walk over bins is done
+// here on the host, from the per-bin id counts (row-major, bin[p][q] at
+// p*k+q), in row order with per-column state; the per-id work (copying ids
+// and weights, counting message starts) is done by launch_cs_fill.
+struct ColWalk {
+    uint64_t pos = 0;      // stream position inside the column
+    uint32_t inner = 0;    // inner starts in the chunk of pos
+    uint64_t chunks = 0, entries = 0;
+};
+
+int build_streams(Dev& G, const Sizes& z, const std::vector<uint32_t>& cnti, hipStream_t st) {
+    const uint32_t k = G.k;
+    if (z.pc_stream == GPOP_PCSTREAM_OFF) {
+        G.n_chunks = 0;
+        return GPOP_OK;
+    }
+    std::vector<ColWalk> w(k);
+    std::vector<uint64_t> cbase(k + 1, 0), ebase(k + 1, 0);
+    std::vector<uint32_t> bm, tabo;
+    std::vector<uint2> ent;
+    // pass 0 counts chunks and entries per column; pass 1 writes them
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t q = 0; q < k; ++q) w[q] = ColWalk{};
+        auto chunk_begin = [&](uint32_t q, uint32_t p, uint64_t x0) {  // entry 0 of a new chunk
+            ColWalk& c = w[q];
+            if (pass) {
+                const uint64_t ch = cbase[q] + c.chunks;
+                tabo[ch] = (uint32_t)(ebase[q] + c.entries);
+                ent[ebase[q] + c.entries] = make_uint2((uint32_t)x0, p | (q << 16));
+            }
+            ++c.chunks;
+            ++c.entries;
+        };
+        auto inner_start = [&](uint32_t q, uint32_t p) {  // a bin (or padding, p = 0xFFFF) inside a chunk
+            ColWalk& c = w[q];
+            const uint32_t t = (uint32_t)(c.pos % kChunk);
+            if (pass) {
+                const uint64_t ch = cbase[q] + c.chunks - 1;
+                bm[ch * 8 + t / 32] |= 1u << (t % 32);
+                ent[ebase[q] + c.entries] = make_uint2(t, p | (q << 16));
+            }
+            ++c.entries;
+            ++c.inner;
+        };
+        for (uint32_t p = 0; p < k; ++p) {
+            const uint32_t* row = cnti.data() + (size_t)p * k;
+            for (uint32_t q = 0; q < k; ++q) {
+                const uint32_t ic = row[q];
+                if (!ic) continue;
+                ColWalk& c = w[q];
+                if (c.pos % kChunk) {
+                    if (c.inner >= 62) {  // padding to the chunk boundary
+                        inner_start(q, 0xFFFFu);
+                        c.pos = (c.pos / kChunk + 1) * kChunk;
+                    } else {
+                        inner_start(q, p);
+                    }
+                }
+                // chunks that begin inside [pos, pos + ic), entry 0 = this bin
+                const uint64_t first = (c.pos + kChunk - 1) / kChunk, last = (c.pos + ic - 1) / kChunk;
+                for (uint64_t ch = first; ch <= last; ++ch) {
+                    chunk_begin(q, p, ch * kChunk - c.pos);
+                    c.inner = 0;
+                }
+                c.pos += ic;
+            }
+        }
+        for (uint32_t q = 0; q < k; ++q) {
+            ColWalk& c = w[q];
+            if (c.pos % kChunk) inner_start(q, 0xFFFFu);  // padding to the end of the last chunk
+        }
+        if (pass == 0) {
+            for (uint32_t q = 0; q < k; ++q) {
+                cbase[q + 1] = cbase[q] + w[q].chunks;
+                ebase[q + 1] = ebase[q] + w[q].entries;
+            }
+            if (cbase[k] > cs_chunks_max(G.E, z) || ebase[k] > cs_entries_max(G.E, z))
+                return fail(GPOP_EDEVICE, "internal: column stream bound exceeded");
+            if (cbase[k] * kChunk >= 0xFFFFFFFFull)
+                return fail(GPOP_ENOTSUP, "column streams of %llu positions exceed 2^32",
+                            (unsigned long long)(cbase[k] * kChunk));
+            bm.assign(cbase[k] * 8, 0u);
+            tabo.assign(cbase[k] + 1, 0u);
+            ent.assign(ebase[k] + 64, make_uint2(0u, 0xFFFFu));
+            tabo[cbase[k]] = (uint32_t)ebase[k];
+        }
+    }
+    G.n_chunks = (uint32_t)cbase[k];
+    std::vector<uint32_t> c0(k + 1);
+    for (uint32_t q = 0; q <= k; ++q) c0[q] = (uint32_t)cbase[q];
+    HIP_OR_RETURN(hipMemcpyAsync(G.cs_c0, c0.data(), c0.size() * 4, hipMemcpyHostToDevice, st), "write stream bases");
+    if (G.n_chunks) {
+        HIP_OR_RETURN(hipMemcpyAsync(G.cs_bm, bm.data(), bm.size() * 4, hipMemcpyHostToDevice, st),
+                      "write stream bin starts");
+        HIP_OR_RETURN(hipMemcpyAsync(G.cs_tabo, tabo.data(), tabo.size() * 4, hipMemcpyHostToDevice, st),
+                      "write stream tables");
+        HIP_OR_RETURN(hipMemcpyAsync(G.cs_ent, ent.data(), ent.size() * 8, hipMemcpyHostToDevice, st),
+                      "write stream entries");
+        HIP_OR_RETURN(launch_cs_fill(G, st), "fill column streams");
+    }
+    // the host vectors must outlive the copies
+    HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+    return GPOP_OK;
+}
+
 int check_desc(const gpop_graph_desc* d, const gpop_options* o, uint32_t* s_out) {
     if (!d) return fail(GPOP_EINVAL, "desc is NULL");
     if (d->num_vertices == 0) return fail(GPOP_EINVAL, "graph has no vertex");
@@ -225,9 +359,10 @@ int check_desc(const gpop_graph_desc* d, const gpop_options* o, uint32_t* s_out)
     if (d->reserved0) return fail(GPOP_EINVAL, "reserved0 must be zero");
     uint32_t s = 14;
     if (o) {
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 3; ++i)
             if (o->reserved[i]) return fail(GPOP_EINVAL, "options.reserved must be zero");
         if (o->combine > GPOP_COMBINE_ROUNDS) return fail(GPOP_EINVAL, "unknown combine %u", o->combine);
+        if (o->pc_stream > GPOP_PCSTREAM_ON) return fail(GPOP_EINVAL, "unknown pc_stream mode %u", o->pc_stream);
         if (o->log2_part) s = o->log2_part;
         if (o->sc_task_log2 && (o->sc_task_log2 < 6 || o->sc_task_log2 > 24))
             return fail(GPOP_EINVAL, "sc_task_log2 must be 0 or in [6, 24]");
@@ -645,6 +780,10 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     if (!gs.empty())
         HIP_OR_RETURN(hipMemcpyAsync(G.gsplit, gs.data(), gs.size() * sizeof(uint4), hipMemcpyHostToDevice,
                                      st), "write split list");
+    G.idb = (uint32_t)slot;
+    G.pcs_mode = z.pc_stream;
+    HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(G.data + G.idb), 0xFFFFFFFF, 256, st), "write identity words");
+    if ((rc = build_streams(G, z, cnti, st))) return rc;
     HIP_OR_RETURN(launch_part_static(G, st), "partition features");
     Ctrl hc2;
     HIP_OR_RETURN(hipMemcpyAsync(&hc2, G.ctrl, sizeof hc2, hipMemcpyDeviceToHost, st), "read control");
@@ -1128,7 +1267,7 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     const uint64_t k = S.k, q = S.q, kk = k * k;
     const uint64_t E_pad = align256(S.E ? S.E : 1);
     const uint64_t ngt = S.n_gtask ? S.n_gtask : 1;
-    D->data = (uint32_t*)take((g->M ? g->M : 1) * 4);
+    D->data = (uint32_t*)take((g->M + 256) * 4);  // messages, then the identity words
     D->sc_ids = (uint16_t*)take(E_pad * 2);
     D->sc_w = S.w ? (uint8_t*)take(E_pad) : nullptr;
     D->sc_chunk = (uint32_t*)take(E_pad / kChunk * 4);
@@ -1230,6 +1369,8 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
         q_max = std::max(q_max, S.q);
         HIP_OR_RETURN(hipMemsetAsync(I.G.ctrl, 0, sizeof(Ctrl), st), "clear run control");
         HIP_OR_RETURN(hipMemsetAsync(I.G.cact, 0, (size_t)S.k * 4, st), "clear column stamps");
+        HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(I.G.data + S.idb), 0xFFFFFFFF, 256, st),
+                      "write identity words");
     }
     BatchGrid& B = b->grid;
     B.tab = b->d_tab;

@@ -287,6 +287,158 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
     }
 }
 
+// Partition-centric ids of one column read from its stream, chunks
+// [c_lo, c_hi): wave w takes chunks c_lo + w, c_lo + w + kGW, ..., SPW per
+// round. Lane l decodes chunk positions 4l..4l+3. The entry b of a position
+// is the number of inner bin starts at positions 1..i (bitmap prefix) and its
+// message index the number of message starts at positions 1..i (flag
+// prefix); both come from one packed wave scan. The entry's adj value is
+// taken from lane b with ds_bpermute (a chunk has at most 64 entries), and
+// data[adj + message index] is the position's message value. A bin whose
+// source partition did not scatter partition-centric this iteration (or a
+// padding run) reads the identity words instead, so no id is masked.
+// The next round's ids, bitmaps, weights and entries are loaded before the
+// current round is decoded; the table offsets one round earlier still.
+template <int PROG, bool WIDE>
+__device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, uint32_t c_hi, bool dense,
+                                                  const uint64_t* pcm, uint32_t* st32,
+                                                  unsigned long long* acc) {
+    constexpr bool SUM = is_sum(PROG);
+    constexpr uint32_t SPW = 4;  // chunks per wave per round
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t n = c_hi - c_lo;
+    const uint32_t nrounds = (n + kGW * SPW - 1) / (kGW * SPW);
+    const uint2* __restrict__ ids = reinterpret_cast<const uint2*>(gptr(G.cs_ids));
+    const uint32_t* __restrict__ wts = reinterpret_cast<const uint32_t*>(gptr(G.cs_w));
+    const uint32_t* __restrict__ bmp = gptr(G.cs_bm);
+    const uint32_t* __restrict__ tabo = gptr(G.cs_tabo);
+    const uint2* __restrict__ ent = gptr(G.cs_ent);
+    const uint32_t* __restrict__ data = gptr(G.data);
+    const uint32_t k = G.k, idb = G.idb;
+    const uint32_t bsh = 4u * (lane & 7u);
+    // message-start flags of the lane's positions after the byte gather
+    // below (bit 8j + 7 = position 4l + j); position 0 of the chunk is not
+    // counted
+    const uint32_t mm = lane == 0 ? 0x80808000u : 0x80808080u;
+    // a message value: data words are addressed with 32-bit byte offsets
+    // from the array's base unless the array reaches 4 GiB
+    auto msg = [&](uint32_t d) -> uint32_t {
+        if constexpr (WIDE) return data[d];
+        else return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(data) + (d << 2));
+    };
+    auto piece = [&](uint32_t r, uint32_t pi) -> uint32_t { return (r * SPW + pi) * kGW + wave; };
+    auto chunk = [&](uint32_t r, uint32_t pi) -> uint32_t {
+        const uint32_t i = piece(r, pi);
+        return i < n ? c_lo + i : c_lo;  // past the range: re-read the first chunk, not combined
+    };
+    // table offsets (start, end) of a round's chunks, loaded one round before
+    // they are used (the same value in every lane)
+    uint32_t tb_n[SPW], te_n[SPW];
+    uint2 raw_n[SPW], ent_n[SPW];
+    uint32_t bm_n[SPW], w_n[SPW];
+    auto fetch_tb = [&](uint32_t r, uint32_t* tb, uint32_t* te) {
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) {
+            const uint32_t c = chunk(r, pi);
+            tb[pi] = tabo[c];
+            te[pi] = tabo[c + 1];
+        }
+    };
+    auto fetch = [&](uint32_t r, const uint32_t* tb, const uint32_t* te) {
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) {
+            const uint32_t c = chunk(r, pi);
+            raw_n[pi] = gptr(ids + (size_t)c * 64)[lane];
+            bm_n[pi] = gptr(bmp + (size_t)c * 8)[lane >> 3];
+            // lanes past the chunk's table read its last entry (one fetch)
+            const uint32_t t0 = __builtin_amdgcn_readfirstlane(tb[pi]);
+            const uint32_t ne = __builtin_amdgcn_readfirstlane(te[pi]) - t0;
+            ent_n[pi] = gptr(ent + t0)[min(lane, ne - 1u)];
+            w_n[pi] = 0u;
+            if constexpr (is_weighted(PROG)) w_n[pi] = gptr(wts + (size_t)c * 64)[lane];
+        }
+    };
+    uint32_t my_ids = 0;
+    if (nrounds == 0) return 0;
+    uint32_t tb_a[SPW], te_a[SPW];
+    fetch_tb(0, tb_a, te_a);
+    fetch(0, tb_a, te_a);
+    fetch_tb(1, tb_n, te_n);
+    for (uint32_t r = 0; r < nrounds; ++r) {
+        uint2 raw[SPW], ev[SPW];
+        uint32_t bmw[SPW], wv[SPW], tb_b[SPW], te_b[SPW];
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) {
+            raw[pi] = raw_n[pi];
+            ev[pi] = ent_n[pi];
+            bmw[pi] = bm_n[pi];
+            wv[pi] = w_n[pi];
+            tb_b[pi] = tb_n[pi];
+            te_b[pi] = te_n[pi];
+        }
+        // loads of the next round (chunks past the range re-read the first)
+        fetch_tb(r + 2, tb_n, te_n);
+        fetch(r + 1, tb_b, te_b);
+        // the round's four chunks go through each step together, so that
+        // their scans, ds_bpermutes and loads overlap one another's latency
+        uint32_t val[4 * SPW], dst[4 * SPW], mi[4 * SPW], adjv[SPW], hb[SPW], b4[SPW], ex[SPW];
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) {
+            adjv[pi] = ev[pi].x;
+            if (!dense) {
+                const uint32_t src = ev[pi].y & 0xFFFFu;
+                if (src < k && !((pcm[src >> 6] >> (src & 63u)) & 1ull)) adjv[pi] = idb - (ev[pi].y >> 16);
+            }
+            // a chunk past the task's range (a re-read of its first chunk)
+            // reads the identity words: its combines change nothing
+            if (piece(r, pi) >= n) adjv[pi] = idb;
+            hb[pi] = __builtin_amdgcn_perm(raw[pi].y, raw[pi].x, 0x07050301u) & mm;
+            b4[pi] = (bmw[pi] >> bsh) & 0xFu;
+            ex[pi] = ((uint32_t)__popc(b4[pi]) << 16) | (uint32_t)__popc(hb[pi]);
+        }
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) ex[pi] = wave_incl_scan(ex[pi]) - ex[pi];
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) {
+            const uint32_t mex = ex[pi] & 0xFFFFu, bex = ex[pi] >> 16;
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                mi[4 * pi + j] = mex + (uint32_t)__popc(hb[pi] & ((0x100u << (8u * j)) - 1u));
+                const uint32_t bj = bex + (uint32_t)__popc(b4[pi] & ((2u << j) - 1u));
+                val[4 * pi + j] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(bj << 2), (int)adjv[pi]);
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < 4 * SPW; ++j) val[j] = msg(val[j] + mi[j]);
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) {
+            dst[4 * pi + 0] = raw[pi].x & kLocalMask;
+            dst[4 * pi + 1] = (raw[pi].x >> 16) & kLocalMask;
+            dst[4 * pi + 2] = raw[pi].y & kLocalMask;
+            dst[4 * pi + 3] = (raw[pi].y >> 16) & kLocalMask;
+        }
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) {
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                uint32_t x = val[4 * pi + j];
+                if constexpr (is_weighted(PROG)) x = sat_add(x, (wv[pi] >> (8u * j)) & 0xFFu);
+                const uint32_t d = dst[4 * pi + j];
+                if constexpr (SUM) {
+                    const bool use = (int32_t)x >= 0;  // identities and padding read negative words
+                    my_ids += use ? 1u : 0u;
+                    atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(x) * kFix) : 0ull);
+                } else {
+                    my_ids += x != kIdentMin ? 1u : 0u;
+                    atomicMin(st32 + d, x);
+                }
+            }
+        }
+    }
+    return my_ids;
+}
+
 // Gather task: a contiguous range [s0, s1) of the static 256-id pieces of the
 // bins bin[p][cq], p in [p_lo, p_hi], taken in p order. The destination
 // partition's state lives in LDS (the cached vertex data of Sec. 3): every
@@ -378,6 +530,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     //      source-centric ones from the scan's flags.
     uint64_t* amask = reinterpret_cast<uint64_t*>(smem + L.amask);
     uint64_t* pcm = reinterpret_cast<uint64_t*>(smem + L.pcm);
+    bool col_pc = false;  // some partition-centric source has a bin in this column
     {
         const bool sc_col = gptr(G.cact)[cq] == it + 1u;
         const bool pc_any = gptr(G.ctrl)->n_pcpart != 0u;
@@ -398,11 +551,16 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                       reinterpret_cast<const uint8_t*>(gptr(G.pcmask))[g];
             ab[g] = (uint8_t)(scb | pcb);
             pb[g] = (uint8_t)pcb;
+            col_pc = pcb != 0u;
         }
     }
-    __syncthreads();
+    col_pc = __syncthreads_or(col_pc);
     auto abit = [&](uint32_t p) -> bool { return (amask[p >> 6] >> (p & 63u)) & 1ull; };
     auto pcbit = [&](uint32_t p) -> bool { return (pcm[p >> 6] >> (p & 63u)) & 1ull; };
+    // partition-centric bins from the column stream this iteration (the bin
+    // list below then takes only the source-centric ones)
+    const bool use_stream = !ROUNDS && col_pc && gptr(G.ctrl)->pc_stream != 0u;
+    auto lbit = [&](uint32_t p) -> bool { return abit(p) && !(use_stream && pcbit(p)); };
 
     // ---- a split partition with few ids this iteration (a sparse frontier)
     //      is gathered whole by its first task: no partial results, no merge
@@ -438,18 +596,33 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
 
     // ---- anything to do for this task? (bins with ids in its source range,
     //      or, for programs that carry vertices, an active set to filter)
-    uint32_t mine = 0;  // listed bins of the thread's byte inside [p_lo, p_hi]
+    uint32_t mine = 0, mine_l = 0;  // listed bins of the thread's byte inside [p_lo, p_hi] (all; bin-list path)
     if (tid < G.kw * 8u) {
         const uint32_t byte = reinterpret_cast<const uint8_t*>(amask)[tid];
+        const uint32_t lbyte = use_stream ? byte & ~(uint32_t)reinterpret_cast<const uint8_t*>(pcm)[tid] : byte;
         const uint64_t r = range_bits(tid >> 3, p_lo, p_hi) >> (8u * (tid & 7u));
         mine = (uint32_t)__popc(byte & (uint32_t)(r & 0xFFu));
+        mine_l = (uint32_t)__popc(lbyte & (uint32_t)(r & 0xFFu));
     }
     const uint32_t wbins = wave_sum_u32(mine);
     if (lane == 0) sh.wsm[wave] = wbins;
+    // this task's share of the column stream
+    uint32_t cs_lo = 0, cs_hi = 0;
+    if (use_stream) {
+        const uint32_t c0 = gptr(G.cs_c0)[cq], c1 = gptr(G.cs_c0)[cq + 1];
+        if (split) {
+            const uint64_t C = c1 - c0;
+            cs_lo = c0 + (uint32_t)(C * jt / nt);
+            cs_hi = c0 + (uint32_t)(C * (jt + 1u) / nt);
+        } else {
+            cs_lo = c0;
+            cs_hi = c1;
+        }
+    }
     // a column held back by interleaved scatter-gather keeps its frontier
     const bool carry_col = !SUM && isg_holds(P, cq, k, it) && gptr(G.fVa[cur])[cq] > 0;
-    const bool any = __syncthreads_or(mine > 0u || (tid == 0 && !split && (carry_col || (!msg_only(PROG) &&
-                                                    gptr(G.fVa[cur])[cq] > 0))));
+    const bool any = __syncthreads_or(mine_l > 0u || (tid == 0 && (cs_hi > cs_lo || (!split && (carry_col ||
+                                      (!msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0))))));
     uint32_t nbins = 0;
     for (uint32_t w = 0; w < kGW; ++w) nbins += sh.wsm[w];
     if (!any) {
@@ -462,7 +635,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                 gptr(G.dpart[nxt])[cq] = 0.0;
             }
             gptr(G.gat_ids)[task] = 0;
-            gptr(G.gat_ran)[task] = 0;
+            // listed bins in this task's source range whose ids another task
+            // of the column reads from the stream still count as gathered
+            gptr(G.gat_ran)[task] = nbins << 2;
         }
         return;
     }
@@ -484,16 +659,24 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     // ---- gather the task's pieces, bins in windows of kGT source partitions
     //      (a window without a listed bin is skipped)
     uint32_t my_ids = 0;
+    if constexpr (!ROUNDS) {
+        if (use_stream) {
+            const bool dense = gptr(G.ctrl)->n_pcpart == k;
+            if (G.idb < (1u << 30) - 256u) my_ids += stream_gather<PROG, false>(G, cs_lo, cs_hi, dense, pcm, st32, acc);
+            else my_ids += stream_gather<PROG, true>(G, cs_lo, cs_hi, dense, pcm, st32, acc);
+        }
+    }
     // static pieces of the bins before p_lo: the task's piece range [s0, s1)
     // counts from there
     const uint32_t sbase = gptr(G.spre)[(size_t)cq * k + p_lo];
     for (uint32_t p0 = p_lo; p0 <= p_hi; p0 += kGT) {
         const uint32_t pw_hi = min(p0 + kGT - 1u, p_hi);
         bool wany = false;
-        for (uint32_t w = p0 >> 6; w <= (pw_hi >> 6); ++w) wany |= (amask[w] & range_bits(w, p0, pw_hi)) != 0ull;
+        for (uint32_t w = p0 >> 6; w <= (pw_hi >> 6); ++w)
+            wany |= ((amask[w] & ~(use_stream ? pcm[w] : 0ull)) & range_bits(w, p0, pw_hi)) != 0ull;
         if (!wany) continue;  // uniform
         const uint32_t p = p0 + tid;
-        const bool inr = p <= p_hi && abit(p);
+        const bool inr = p <= p_hi && lbit(p);
         const bool is_pc = inr && pcbit(p);
         const uint32_t md = !inr ? GPOP_MODE_NONE : (is_pc ? GPOP_MODE_PC : GPOP_MODE_SC);
         uint32_t ioff = 0, icnt = 0, moff = 0, mcnt = 0, SP = 0;
@@ -851,6 +1034,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         }
         __syncthreads();
     }
+    __syncthreads();  // the stream's combines are complete before the state is read
 
     if (split) {
         // partial result of this task for the merge

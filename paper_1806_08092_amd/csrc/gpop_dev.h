@@ -87,7 +87,7 @@ struct Ctrl {
     uint64_t frontier;    // sum of V_a at the last plan
     double dangling;      // PageRank-family dangling mass of the current frontier
     uint32_t fin_it;      // records below this iteration are final
-    uint32_t reserved0;   // keeps the layout of the fields below
+    uint32_t pc_stream;   // gather reads partition-centric ids from the column streams
     uint32_t pos;         // iterations run so far (index of the next plan)
     uint32_t max_it;      // a plan at this index pauses the run (done bit 2)
     uint32_t run_start;   // pos when the current run began
@@ -109,6 +109,9 @@ struct Dev {
     uint32_t n_gsplit;        // partitions whose gather is split over tasks
     uint32_t combine;         // GPOP_COMBINE_*
     uint32_t whole_ids;       // a split partition with at most this many ids is gathered by one task
+    uint32_t pcs_mode;        // GPOP_PCSTREAM_*
+    uint32_t idb;             // data[idb, idb + 256): combine identities (min and sum), never written
+    uint32_t n_chunks;        // chunks of all column streams
     uint64_t E;
     const uint32_t* off;
     const uint32_t* cols;
@@ -126,6 +129,22 @@ struct Dev {
     uint8_t* png_w;           // [E_pad] static weights
     uint32_t* png_chunk;      // [E_pad/256]
     uint4* pctask;            // [n_pctask] {p, slot_begin, slot_end, 0}
+    // column streams of the partition-centric ids (static): column q's
+    // chunks are [cs_c0[q], cs_c0[q+1]); chunk c holds stream positions
+    // [256c, 256c + 256). A bin starts at chunk position 0 or at a position
+    // flagged in cs_bm (at most 63 such inner starts per chunk, a padding
+    // run included). Chunk c's entries [cs_tabo[c], cs_tabo[c+1]) are, for
+    // the bin at position 0 and then each inner start in position order,
+    // {adj, src | mt << 16}: the data index of a position i is
+    // adj[b] + (message starts at positions 1..i), b = inner starts at 1..i;
+    // src is the source partition (0xFFFF: padding, whose adj points into the
+    // identity words) and mt the message starts at positions 1..start.
+    uint32_t* cs_c0;          // [k+1]
+    uint16_t* cs_ids;         // [n_chunks*256] ids (local id | message-start flag)
+    uint8_t* cs_w;            // [n_chunks*256] weights
+    uint32_t* cs_bm;          // [n_chunks*8] inner bin starts, bit i of the chunk = position i
+    uint32_t* cs_tabo;        // [n_chunks+1]
+    uint2* cs_ent;            // [entries + 64]
     uint32_t* bld_t0;         // [k+1] task prefix of the build (all vertices active)
     uint4* gtask;             // [2*n_gtask] {q, p_lo, p_hi, nt<<16|j}, {s0, s1, slot, 0}
     uint4* gsplit;            // [n_gsplit] {q, 0, nt, first slot}

@@ -25,6 +25,7 @@ size_t scan_tmp_words(uint64_t n);
 hipError_t launch_part_M(const Dev& G, hipStream_t st);
 hipError_t launch_colmajor(const Dev& G, hipStream_t st);
 hipError_t launch_colsrc(const Dev& G, hipStream_t st);
+hipError_t launch_cs_fill(const Dev& G, hipStream_t st);
 
 // scatter side (scatter.hip)
 size_t sc_lds_bytes(uint32_t k);

@@ -784,6 +784,11 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         C->n_sctask = tcarry;
         C->n_scunits = ucarry;
         C->n_pcpart = (uint32_t)t[3];
+        // gather reads the partition-centric ids from the column streams
+        // when their partitions hold at least half of the edges (a stream
+        // chunk is read whole, whatever the mode of its bins' sources)
+        C->pc_stream = (G.n_chunks != 0u && t[3] != 0u &&
+                        (G.pcs_mode == GPOP_PCSTREAM_ON || 2ull * t[5] >= G.E)) ? 1u : 0u;
         if (tcarry > G.max_sctask) {  // cannot happen (the bound covers every task size): stop
             C->bug = 1;
             C->done = 1;

@@ -117,3 +117,17 @@ def test_plan_rejects_unknown_combine():
     L = gp.lib()
     assert L.gpop_plan(ctypes.byref(d), ctypes.byref(gp.Options(10, 0, 0, 2)), ctypes.byref(info)) == gp.EINVAL
     assert L.gpop_plan(ctypes.byref(d), ctypes.byref(gp.Options(10, 0, 0, 1)), ctypes.byref(info)) == gp.OK
+
+
+def test_plan_pc_stream_modes():
+    """pc_stream selects where gather reads partition-centric ids: unknown
+    modes are rejected, and without column streams the workspace is smaller
+    (the streams hold a copy of every static id, its weight, and per 256-id
+    chunk a bin-start bitmap and table)."""
+    d = gp.GraphDesc(1 << 20, 0, 1 << 24, None, None, None)
+    L = gp.lib()
+    info = gp.PlanInfo()
+    assert L.gpop_plan(ctypes.byref(d), ctypes.byref(gp.Options(14, 0, 0, 0, 3)), ctypes.byref(info)) == gp.EINVAL
+    ws = {m: gp.plan(1 << 20, 1 << 24, 14, pc_stream=m).workspace_bytes for m in ("auto", "off", "on")}
+    assert ws["auto"] == ws["on"]
+    assert ws["auto"] - ws["off"] >= (1 << 24) * 3  # 2-byte ids + 1-byte weights of every edge
