@@ -831,6 +831,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     B.q_max = G.q;
     B.rounds = G.combine == GPOP_COMBINE_ROUNDS;
     B.learned = false;
+    B.streams = G.n_chunks != 0;
     B.view = &g->G;
     for (int i = 0; i < 2; ++i) {
         g->probe_grid[i] = B;
@@ -1397,7 +1398,11 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
     B.q_max = q_max;
     B.rounds = graphs[0]->G.combine == GPOP_COMBINE_ROUNDS;
     B.learned = false;
-    for (uint32_t i = 0; i < n; ++i) B.learned = B.learned || graphs[i]->P.selector == GPOP_SEL_LEARNED;
+    B.streams = false;
+    for (uint32_t i = 0; i < n; ++i) {
+        B.learned = B.learned || graphs[i]->P.selector == GPOP_SEL_LEARNED;
+        B.streams = B.streams || graphs[i]->G.n_chunks != 0;
+    }
     for (uint32_t i = 1; i < n; ++i)
         if (graphs[i]->G.combine != graphs[0]->G.combine) {
             delete b;

@@ -66,11 +66,13 @@ __device__ __forceinline__ uint32_t wave_excl_small(uint32_t c) {
     return popc_lt(ballot(c & 1u)) + 2u * popc_lt(ballot(c & 2u)) + 4u * popc_lt(ballot(c & 4u));
 }
 
-struct GatherShared {
-    uint32_t wc[kGW], wp[kGW], ws[kGW], wsm[kGW];
-    uint64_t r64[kGW];
-    double rd[kGW];
+template <uint32_t NW>
+struct GatherSharedT {
+    uint32_t wc[NW], wp[NW], ws[NW], wsm[NW];
+    uint64_t r64[NW];
+    double rd[NW];
 };
+using GatherShared = GatherSharedT<kGW>;
 
 // Programs whose frontier can only come from vertices that received a
 // message: a partition with no incoming message leaves an empty frontier,
@@ -80,7 +82,7 @@ __host__ __device__ constexpr bool msg_only(int prog) { return !is_sum(prog) && 
 // reInit frontier: initFunc on the vertices that were active before scatter.
 // (Min programs start the on-chip copy at the identity, so initFunc reads the
 // stored value.)
-template <int PROG>
+template <int PROG, uint32_t NT = kGT>
 __device__ __forceinline__ void reinit(const Dev& G, const Params& P, const uint32_t* __restrict__ state,
                                        uint32_t it, uint32_t cq, uint32_t* st32, uint8_t* carry) {
     if constexpr (has_carry(PROG) || is_sum(PROG)) {
@@ -88,7 +90,7 @@ __device__ __forceinline__ void reinit(const Dev& G, const Params& P, const uint
         const uint32_t vbase = cq << G.s;
         const uint32_t prevVa = gptr(G.fVa[cur])[cq];
         const uint16_t* __restrict__ prev = gptr(G.flist[cur]) + vbase;
-        for (uint32_t i = threadIdx.x; i < prevVa; i += kGT) {
+        for (uint32_t i = threadIdx.x; i < prevVa; i += NT) {
             const uint32_t u = prev[i];
             if constexpr (PROG == P_CARRY) carry[u] = (it + 1u - state[vbase + u]) < P.persist;
             else reinterpret_cast<unsigned long long*>(st32)[u] |= kCarried;  // value restarts at 0, stays active
@@ -105,11 +107,11 @@ __device__ __forceinline__ void reinit(const Dev& G, const Params& P, const uint
 // counts kept vertices and their out-edges (keep masks go to LDS scratch),
 // one scan across waves gives every wave its offsets, pass 2 writes the
 // frontier.
-template <int PROG>
+template <int PROG, uint32_t NW = kGW>
 __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, uint32_t* __restrict__ state,
                                  uint32_t it, uint32_t cq, uint32_t* st32,
                                  unsigned long long* acc, const uint8_t* carry,
-                                 uint64_t* kscratch, GatherShared& sh, uint32_t ids_done,
+                                 uint64_t* kscratch, GatherSharedT<NW>& sh, uint32_t ids_done,
                                  uint32_t task, bool carry_col) {
     constexpr bool SUM = is_sum(PROG);
     // 64-vertex groups per step of pass 1: their global loads are issued together
@@ -120,7 +122,7 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     const double dang = SUM ? gptr(G.ctrl)->dangling : 0.0;
     const uint32_t* __restrict__ off = gptr(G.off);
-    const uint32_t per = ((Q / kGW) + 63u) & ~63u;  // vertices per wave, multiple of 64
+    const uint32_t per = ((Q / NW) + 63u) & ~63u;  // vertices per wave, multiple of 64
     const uint32_t wb = wave * per;
     const uint32_t wend = min(wb + per, Q);
     // pass 1 leaves the out-degree of each kept vertex in the LDS slot its
@@ -235,7 +237,7 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
     }
     __syncthreads();
     uint32_t pos = 0, epos = 0, tot = 0, etot = 0;
-    for (uint32_t w = 0; w < kGW; ++w) {
+    for (uint32_t w = 0; w < NW; ++w) {
         if (w < wave) {
             pos += sh.wc[w];
             epos += sh.ws[w];
@@ -276,7 +278,7 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
     if (tid == 0) {
         uint64_t ni = 0;
         double d = 0.0;
-        for (uint32_t w = 0; w < kGW; ++w) {
+        for (uint32_t w = 0; w < NW; ++w) {
             ni += sh.r64[w];
             d += sh.rd[w];
         }
@@ -299,16 +301,18 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
 // padding run) reads the identity words instead, so no id is masked.
 // The next round's ids, bitmaps, weights and entries are loaded before the
 // current round is decoded; the table offsets one round earlier still.
-template <int PROG, bool WIDE>
+template <int PROG, bool WIDE, uint32_t NW = kGW, uint32_t SPW = 4>
 __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, uint32_t c_hi, bool dense,
                                                   const uint64_t* pcm, uint32_t* st32,
                                                   unsigned long long* acc) {
     constexpr bool SUM = is_sum(PROG);
-    constexpr uint32_t SPW = 4;  // chunks per wave per round
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the range is the same in every lane: keep its arithmetic scalar
+    c_lo = __builtin_amdgcn_readfirstlane(c_lo);
+    c_hi = __builtin_amdgcn_readfirstlane(c_hi);
     const uint32_t n = c_hi - c_lo;
-    const uint32_t nrounds = (n + kGW * SPW - 1) / (kGW * SPW);
+    const uint32_t nrounds = (n + NW * SPW - 1) / (NW * SPW);
     const uint2* __restrict__ ids = reinterpret_cast<const uint2*>(gptr(G.cs_ids));
     const uint32_t* __restrict__ wts = reinterpret_cast<const uint32_t*>(gptr(G.cs_w));
     const uint32_t* __restrict__ bmp = gptr(G.cs_bm);
@@ -321,13 +325,15 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
     // below (bit 8j + 7 = position 4l + j); position 0 of the chunk is not
     // counted
     const uint32_t mm = lane == 0 ? 0x80808000u : 0x80808080u;
-    // a message value: data words are addressed with 32-bit byte offsets
-    // from the array's base unless the array reaches 4 GiB
+    // a message value: below 4 GiB of data, a buffer load with a 32-bit
+    // byte offset (no 64-bit address arithmetic per id)
+    const __amdgpu_buffer_rsrc_t drsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(data), (short)0, (int)0xFFFFFFFF, (int)0x00020000);
     auto msg = [&](uint32_t d) -> uint32_t {
         if constexpr (WIDE) return data[d];
-        else return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(data) + (d << 2));
+        else return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(drsrc, (int)(d << 2), 0, 0);
     };
-    auto piece = [&](uint32_t r, uint32_t pi) -> uint32_t { return (r * SPW + pi) * kGW + wave; };
+    auto piece = [&](uint32_t r, uint32_t pi) -> uint32_t { return (r * SPW + pi) * NW + wave; };
     auto chunk = [&](uint32_t r, uint32_t pi) -> uint32_t {
         const uint32_t i = piece(r, pi);
         return i < n ? c_lo + i : c_lo;  // past the range: re-read the first chunk, not combined
@@ -359,7 +365,7 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
             if constexpr (is_weighted(PROG)) w_n[pi] = gptr(wts + (size_t)c * 64)[lane];
         }
     };
-    uint32_t my_ids = 0;
+    uint32_t my_ids = 0;  // non-identity ids combined by the wave (the same in every lane)
     if (nrounds == 0) return 0;
     uint32_t tb_a[SPW], te_a[SPW];
     fetch_tb(0, tb_a, te_a);
@@ -382,7 +388,7 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
         fetch(r + 1, tb_b, te_b);
         // the round's four chunks go through each step together, so that
         // their scans, ds_bpermutes and loads overlap one another's latency
-        uint32_t val[4 * SPW], dst[4 * SPW], mi[4 * SPW], adjv[SPW], hb[SPW], b4[SPW], ex[SPW];
+        uint32_t val[4 * SPW], adjv[SPW], hb[SPW], b4[SPW], ex[SPW];
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
             adjv[pi] = ev[pi].x;
@@ -399,44 +405,184 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
         }
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) ex[pi] = wave_incl_scan(ex[pi]) - ex[pi];
+        // data index of each position: its entry's adj (from the lane that
+        // holds the entry) plus the message starts at positions 1..i
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
             const uint32_t mex = ex[pi] & 0xFFFFu, bex = ex[pi] >> 16;
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
-                mi[4 * pi + j] = mex + (uint32_t)__popc(hb[pi] & ((0x100u << (8u * j)) - 1u));
                 const uint32_t bj = bex + (uint32_t)__popc(b4[pi] & ((2u << j) - 1u));
-                val[4 * pi + j] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(bj << 2), (int)adjv[pi]);
+                val[4 * pi + j] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(bj << 2), (int)adjv[pi]) +
+                                  mex + (uint32_t)__popc(hb[pi] & ((0x100u << (8u * j)) - 1u));
             }
         }
 #pragma unroll
-        for (uint32_t j = 0; j < 4 * SPW; ++j) val[j] = msg(val[j] + mi[j]);
-#pragma unroll
-        for (uint32_t pi = 0; pi < SPW; ++pi) {
-            dst[4 * pi + 0] = raw[pi].x & kLocalMask;
-            dst[4 * pi + 1] = (raw[pi].x >> 16) & kLocalMask;
-            dst[4 * pi + 2] = raw[pi].y & kLocalMask;
-            dst[4 * pi + 3] = (raw[pi].y >> 16) & kLocalMask;
-        }
+        for (uint32_t j = 0; j < 4 * SPW; ++j) val[j] = msg(val[j]);
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 uint32_t x = val[4 * pi + j];
                 if constexpr (is_weighted(PROG)) x = sat_add(x, (wv[pi] >> (8u * j)) & 0xFFu);
-                const uint32_t d = dst[4 * pi + j];
+                const uint32_t d = ((j < 2 ? raw[pi].x : raw[pi].y) >> (16u * (j & 1u))) & kLocalMask;
                 if constexpr (SUM) {
                     const bool use = (int32_t)x >= 0;  // identities and padding read negative words
-                    my_ids += use ? 1u : 0u;
+                    my_ids += popc64(ballot(use));
                     atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(x) * kFix) : 0ull);
                 } else {
-                    my_ids += x != kIdentMin ? 1u : 0u;
+                    my_ids += popc64(ballot(x != kIdentMin));
                     atomicMin(st32 + d, x);
                 }
             }
         }
     }
-    return my_ids;
+    return lane == 0 ? my_ids : 0u;  // the wave's count, once
+}
+
+// An iteration in which every partition scattered partition-centric and
+// gather reads the column streams: no source-centric bin exists anywhere, so
+// kb_gather_dense runs it with wider workgroups and kb_gather returns.
+__device__ __forceinline__ bool dense_stream_iteration(const Dev& G) {
+    const Ctrl* C = gptr(G.ctrl);
+    return C->pc_stream != 0u && C->n_pcpart == G.k;
+}
+
+// Workgroup of the dense gather: 16 waves. Without the bin-list arrays its LDS
+// is the partition's state plus the filter's keep masks, so two workgroups
+// share a CU (32 waves, at most 64 registers per lane), twice the waves the
+// general gather can keep in flight on the column streams.
+constexpr uint32_t kDT = 1024;
+constexpr uint32_t kDW = kDT / 64;
+
+struct DenseLds {
+    size_t state, carry, keep, total;
+};
+__host__ __device__ inline DenseLds dense_layout(int prog, uint32_t q) {
+    DenseLds L{};
+    size_t o = 0;
+    L.state = o;  o += (size_t)q * (is_sum(prog) ? 8 : 4);
+    L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
+    L.keep = o;   o += ((size_t)q / 64 + 1) * 8;
+    L.total = o;
+    return L;
+}
+
+// The gather task of a dense iteration: the task table, the split of heavy
+// columns and the partial results are those of gather_body; the task's share
+// of the column stream is all it reads.
+template <int PROG>
+__device__ __forceinline__ void dense_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
+                                           uint32_t it, uint32_t task) {
+    if (gptr(G.ctrl)->done || !dense_stream_iteration(G)) return;
+    constexpr bool SUM = is_sum(PROG);
+    const uint4 TA = gptr(G.gtask)[2 * task], TB = gptr(G.gtask)[2 * task + 1];
+    const uint32_t cq = TA.x, nt = TA.w >> 16, jt = TA.w & 0xFFFFu;
+    uint32_t p_lo = TA.y, p_hi = TA.z;
+    const uint32_t slot = TB.z;
+    bool split = nt > 1;
+    const uint32_t cur = it & 1u, nxt = cur ^ 1u;
+    const uint32_t k = G.k, Q = G.q;
+    const uint32_t vbase = cq << G.s;
+    const uint32_t nv = min(Q, G.V - vbase);
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DenseLds L = dense_layout(PROG, Q);
+    uint32_t* st32 = reinterpret_cast<uint32_t*>(smem + L.state);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem + L.state);
+    uint8_t* carry = smem + L.carry;
+    __shared__ GatherSharedT<kDW> sh;
+
+    // a split column whose ids fit one task is gathered whole by its first
+    // task (every source's bin holds its static ids in a dense iteration)
+    if (split) {
+        const uint4* __restrict__ cmcol = gptr(G.cm) + (size_t)cq * k;
+        uint32_t c = 0;
+        for (uint32_t p = tid; p < k; p += kDT) c += cmcol[p].w;
+        c = wave_sum_u32(c);
+        if (lane == 0) sh.wc[wave] = c;
+        __syncthreads();
+        uint32_t tot = 0;
+        for (uint32_t w = 0; w < kDW; ++w) tot += sh.wc[w];
+        __syncthreads();
+        if (tot <= G.whole_ids) {
+            if (jt != 0) {
+                if (tid == 0) {
+                    gptr(G.gflag)[slot] = 0;
+                    gptr(G.gat_ids)[task] = 0;
+                    gptr(G.gat_ran)[task] = 0;
+                }
+                return;
+            }
+            if (tid == 0) gptr(G.gflag)[slot] = 2;  // the merge skips this partition
+            split = false;
+            p_lo = 0;
+            p_hi = k - 1;
+        }
+    }
+    // bins of the task's source range (statistics: every non-empty bin of
+    // the column is read in a dense iteration)
+    uint32_t mine = 0;
+    if (tid < G.kw) mine = (uint32_t)__popcll(gptr(G.colsrc)[(size_t)cq * G.kw + tid] & range_bits(tid, p_lo, p_hi));
+    mine = wave_sum_u32(mine);
+    const uint32_t c0 = gptr(G.cs_c0)[cq], c1 = gptr(G.cs_c0)[cq + 1];
+    uint32_t cs_lo = c0, cs_hi = c1;
+    if (split) {
+        const uint64_t C = c1 - c0;
+        cs_lo = c0 + (uint32_t)(C * jt / nt);
+        cs_hi = c0 + (uint32_t)(C * (jt + 1u) / nt);
+    }
+    const bool any = cs_hi > cs_lo || (!split && !msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0);
+    if (!any) {
+        if (tid == 0) {
+            if (split) {
+                gptr(G.gflag)[slot] = 0;
+            } else {
+                gptr(G.fVa[nxt])[cq] = 0;
+                gptr(G.fEa[nxt])[cq] = 0;
+                gptr(G.dpart[nxt])[cq] = 0.0;
+            }
+            gptr(G.gat_ids)[task] = 0;
+            gptr(G.gat_ran)[task] = mine << 2;
+        }
+        return;
+    }
+    if (tid == 0) gptr(G.gat_ran)[task] = (split ? 2u : 1u) | (mine << 2);
+    for (uint32_t u = tid; u < Q; u += kDT) {
+        if constexpr (SUM) acc[u] = 0ull;
+        else st32[u] = kIdentMin;
+        if constexpr (has_carry(PROG)) carry[u] = 0;
+    }
+    __syncthreads();
+    if (!split) {
+        reinit<PROG, kDT>(G, P, state, it, cq, st32, carry);
+        __syncthreads();
+    }
+    uint32_t my_ids;
+    if (G.idb < (1u << 30) - 256u) my_ids = stream_gather<PROG, false, kDW, 2>(G, cs_lo, cs_hi, true, nullptr, st32, acc);
+    else my_ids = stream_gather<PROG, true, kDW, 2>(G, cs_lo, cs_hi, true, nullptr, st32, acc);
+    __syncthreads();
+    if (split) {
+        if constexpr (SUM) {
+            unsigned long long* out = reinterpret_cast<unsigned long long*>(gptr(G.gpart)) + (size_t)slot * Q;
+            for (uint32_t u = tid; u < nv; u += kDT) out[u] = acc[u];
+        } else {
+            uint32_t* out = gptr(G.gpart) + (size_t)slot * 2 * Q;
+            for (uint32_t u = tid; u < nv; u += kDT) out[u] = st32[u];
+        }
+        const uint64_t ids64 = wave_sum_u64((uint64_t)my_ids);
+        if (lane == 0) sh.r64[wave] = ids64;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t ni = 0;
+            for (uint32_t w = 0; w < kDW; ++w) ni += sh.r64[w];
+            gptr(G.gflag)[slot] = 1;
+            gptr(G.gat_ids)[task] = (uint32_t)ni;
+        }
+        return;
+    }
+    finish_partition<PROG, kDW>(G, P, state, it, cq, st32, acc, carry,
+                                reinterpret_cast<uint64_t*>(smem + L.keep), sh, my_ids, task, false);
 }
 
 // Gather task: a contiguous range [s0, s1) of the static 256-id pieces of the
@@ -479,6 +625,9 @@ template <int PROG, bool ROUNDS>
 __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint32_t* __restrict__ state,
                                             uint32_t it, uint32_t task) {
     if (gptr(G.ctrl)->done) return;
+    if constexpr (!ROUNDS) {
+        if (dense_stream_iteration(G)) return;  // kb_gather_dense gathers every column
+    }
     constexpr bool SUM = is_sum(PROG);
     constexpr uint32_t IDENT = is_sum(PROG) ? kIdentSum : kIdentMin;
     // pieces per wave per combine round (the atomic-free sum keeps two, for registers)
@@ -1068,6 +1217,14 @@ __global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(4))) void k
     gather_body<PROG, ROUNDS>(I.G, I.P, gptr(I.state), gptr(I.G.ctrl)->pos - 1u, blockIdx.x - boff[i]);
 }
 
+template <int PROG>
+__global__ __launch_bounds__(kDT) __attribute__((amdgpu_waves_per_eu(8))) void kb_gather_dense(
+    const Inst* __restrict__ tab, const uint32_t* __restrict__ boff, uint32_t n) {
+    const uint32_t i = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[i];
+    dense_body<PROG>(I.G, I.P, gptr(I.state), gptr(I.G.ctrl)->pos - 1u, blockIdx.x - boff[i]);
+}
+
 // Merge of a partition whose gather was split over several tasks, in two
 // kernels over chunks of kMergeSpan vertices (several workgroups per
 // partition, so that a few heavy partitions still spread over the chip):
@@ -1426,6 +1583,9 @@ static hipError_t prep_batch_gather_p(const BatchGrid& B) {
     hipError_t e = hipFuncSetAttribute(
         r ? reinterpret_cast<const void*>(kb_gather<PROG, true>) : reinterpret_cast<const void*>(kb_gather<PROG, false>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes(PROG, B.q_max, r));
+    if (e == hipSuccess && !r && B.streams)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_gather_dense<PROG>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dense_layout(PROG, B.q_max).total);
     return e;
 }
 
@@ -1437,6 +1597,11 @@ static hipError_t launch_batch_gather_p(const BatchGrid& B, hipStream_t st) {
             hipLaunchKernelGGL((kb_gather<PROG, true>), dim3(B.nb_gather), dim3(kGT), lds, st, B.tab, B.b_gather, B.n);
         else
             hipLaunchKernelGGL((kb_gather<PROG, false>), dim3(B.nb_gather), dim3(kGT), lds, st, B.tab, B.b_gather, B.n);
+        // dense iterations of graphs with column streams (the kernel returns
+        // at once in any other iteration)
+        if (!B.rounds && B.streams)
+            hipLaunchKernelGGL(kb_gather_dense<PROG>, dim3(B.nb_gather), dim3(kDT), dense_layout(PROG, B.q_max).total, st,
+                               B.tab, B.b_gather, B.n);
     }
     return hipGetLastError();
 }

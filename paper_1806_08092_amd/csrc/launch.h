@@ -55,6 +55,7 @@ struct BatchGrid {
     uint32_t k_max, q_max;
     bool rounds;                  // atomic-free combine (every run of a batch uses the same)
     bool learned = true;          // some run uses the learned selector (else its kernel is not launched)
+    bool streams = false;         // some run's graph has column streams (the dense gather kernel is launched)
     const Dev* view = nullptr;    // a single run's view on the host, passed by value where it helps
 };
 hipError_t prepare_batch_scatter(const BatchGrid& B, int prog);
