@@ -138,18 +138,19 @@ uint64_t max_sctask_for(uint32_t V, uint64_t E, const Sizes& z) {
     return std::max<uint64_t>((E + V) >> z.sc_shift, 2ull * sc_task_target((uint32_t)z.k)) + z.k + 1;
 }
 
-// Bounds of the column streams (chunks, entries). A chunk takes at most 62
-// inner bin starts before a padding run moves the next bin to a chunk
-// boundary, so padding adds at most one chunk per 62 non-empty bins, plus
-// one partial chunk per column.
+// Bounds of the column streams (chunks, entries): every non-empty bin is
+// padded by at most 3 null ids to a multiple of 4 positions, and every
+// column by less than one chunk. Streams are built for partitions of at most
+// 2^14 vertices (the null id is q, which needs the local-id field's 15th bit).
+bool cs_enabled(const Sizes& z) { return z.pc_stream != GPOP_PCSTREAM_OFF && z.s <= 14; }
 uint64_t cs_bins_max(uint64_t E, const Sizes& z) { return std::min<uint64_t>(E, z.k * z.k); }
 uint64_t cs_chunks_max(uint64_t E, const Sizes& z) {
-    if (z.pc_stream == GPOP_PCSTREAM_OFF) return 0;
-    return (E + kChunk - 1) / kChunk + z.k + cs_bins_max(E, z) / 62 + 1;
+    if (!cs_enabled(z)) return 0;
+    return (E + 3 * cs_bins_max(E, z) + kChunk - 1) / kChunk + z.k + 1;
 }
 uint64_t cs_entries_max(uint64_t E, const Sizes& z) {
-    if (z.pc_stream == GPOP_PCSTREAM_OFF) return 0;
-    return cs_chunks_max(E, z) + cs_bins_max(E, z) + cs_bins_max(E, z) / 62 + z.k + 1;
+    if (!cs_enabled(z)) return 0;
+    return cs_chunks_max(E, z) + cs_bins_max(E, z) + z.k + 1;
 }
 
 uint64_t max_gtask_for(uint64_t E, const Sizes& z) {
@@ -190,7 +191,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
         G->cs_c0 = (uint32_t*)take((k + 1) * 4);
         G->cs_ids = (uint16_t*)take(nc * kChunk * 2);
         G->cs_w = (uint8_t*)take(nc * kChunk);
-        G->cs_bm = (uint32_t*)take(nc * 32);
+        G->cs_lm = (uint64_t*)take(nc * 8);
         G->cs_tabo = (uint32_t*)take((nc + 1) * 4);
         G->cs_ent = (uint2*)take((ne + 64) * 8);
     }
@@ -200,7 +201,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->gpart = (uint32_t*)take(ngt * q * 8);
     G->gflag = (uint32_t*)take(ngt * 4);
     G->mtot = (uint4*)take(k * kMaxMergeChunks * 16);
-    G->data = (uint32_t*)take((E_pad + 256) * 4);  // messages (M <= E), then the identity words
+    G->data = (uint32_t*)take((E_pad + kIdWords) * 4);  // messages (M <= E), then the identity words
     G->sc_ids = (uint16_t*)take(E_pad * 2);
     G->sc_w = (uint8_t*)take(E_pad);
     G->sc_chunk = (uint32_t*)take(nch * 4);
@@ -245,27 +246,26 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
 
 // Column streams of the partition-centric ids (the layout is described with
 // the cs_* fields of Dev). Each destination partition's non-empty bins are
-// laid out in source order; a bin that would be the 63rd bin to start inside
-// one chunk is moved to the next chunk boundary behind a padding run, so
-// that a chunk's table never exceeds 64 entries. The walk over bins is done
-// here on the host, from the per-bin id counts (row-major, bin[p][q] at
+// laid out in source order, each from a multiple of 4 positions, so that a
+// decoding lane's four positions never span two bins. The walk over bins is
+// done here on the host from the per-bin id counts (row-major, bin[p][q] at
 // p*k+q), in row order with per-column state; the per-id work (copying ids
 // and weights, counting message starts) is done by launch_cs_fill.
 struct ColWalk {
-    uint64_t pos = 0;      // stream position inside the column
-    uint32_t inner = 0;    // inner starts in the chunk of pos
+    uint64_t pos = 0;      // stream position inside the column (a multiple of 4 between bins)
     uint64_t chunks = 0, entries = 0;
 };
 
 int build_streams(Dev& G, const Sizes& z, const std::vector<uint32_t>& cnti, hipStream_t st) {
     const uint32_t k = G.k;
-    if (z.pc_stream == GPOP_PCSTREAM_OFF) {
+    if (!cs_enabled(z)) {
         G.n_chunks = 0;
         return GPOP_OK;
     }
     std::vector<ColWalk> w(k);
     std::vector<uint64_t> cbase(k + 1, 0), ebase(k + 1, 0);
-    std::vector<uint32_t> bm, tabo;
+    std::vector<uint64_t> lm;
+    std::vector<uint32_t> tabo;
     std::vector<uint2> ent;
     // pass 0 counts chunks and entries per column; pass 1 writes them
     for (int pass = 0; pass < 2; ++pass) {
@@ -280,16 +280,14 @@ int build_streams(Dev& G, const Sizes& z, const std::vector<uint32_t>& cnti, hip
             ++c.chunks;
             ++c.entries;
         };
-        auto inner_start = [&](uint32_t q, uint32_t p) {  // a bin (or padding, p = 0xFFFF) inside a chunk
+        auto lane_start = [&](uint32_t q, uint32_t p) {  // a bin (or padding, p = 0xFFFF) at lane pos/4 > 0
             ColWalk& c = w[q];
             const uint32_t t = (uint32_t)(c.pos % kChunk);
             if (pass) {
-                const uint64_t ch = cbase[q] + c.chunks - 1;
-                bm[ch * 8 + t / 32] |= 1u << (t % 32);
+                lm[cbase[q] + c.chunks - 1] |= 1ull << (t / 4);
                 ent[ebase[q] + c.entries] = make_uint2(t, p | (q << 16));
             }
             ++c.entries;
-            ++c.inner;
         };
         for (uint32_t p = 0; p < k; ++p) {
             const uint32_t* row = cnti.data() + (size_t)p * k;
@@ -297,26 +295,16 @@ int build_streams(Dev& G, const Sizes& z, const std::vector<uint32_t>& cnti, hip
                 const uint32_t ic = row[q];
                 if (!ic) continue;
                 ColWalk& c = w[q];
-                if (c.pos % kChunk) {
-                    if (c.inner >= 62) {  // padding to the chunk boundary
-                        inner_start(q, 0xFFFFu);
-                        c.pos = (c.pos / kChunk + 1) * kChunk;
-                    } else {
-                        inner_start(q, p);
-                    }
-                }
+                if (c.pos % kChunk) lane_start(q, p);
                 // chunks that begin inside [pos, pos + ic), entry 0 = this bin
                 const uint64_t first = (c.pos + kChunk - 1) / kChunk, last = (c.pos + ic - 1) / kChunk;
-                for (uint64_t ch = first; ch <= last; ++ch) {
-                    chunk_begin(q, p, ch * kChunk - c.pos);
-                    c.inner = 0;
-                }
-                c.pos += ic;
+                for (uint64_t ch = first; ch <= last; ++ch) chunk_begin(q, p, ch * kChunk - c.pos);
+                c.pos += (ic + 3u) & ~3u;  // null ids fill the bin's last lane
             }
         }
         for (uint32_t q = 0; q < k; ++q) {
             ColWalk& c = w[q];
-            if (c.pos % kChunk) inner_start(q, 0xFFFFu);  // padding to the end of the last chunk
+            if (c.pos % kChunk) lane_start(q, 0xFFFFu);  // padding to the end of the last chunk
         }
         if (pass == 0) {
             for (uint32_t q = 0; q < k; ++q) {
@@ -328,7 +316,7 @@ int build_streams(Dev& G, const Sizes& z, const std::vector<uint32_t>& cnti, hip
             if (cbase[k] * kChunk >= 0xFFFFFFFFull)
                 return fail(GPOP_ENOTSUP, "column streams of %llu positions exceed 2^32",
                             (unsigned long long)(cbase[k] * kChunk));
-            bm.assign(cbase[k] * 8, 0u);
+            lm.assign(cbase[k], 0ull);
             tabo.assign(cbase[k] + 1, 0u);
             ent.assign(ebase[k] + 64, make_uint2(0u, 0xFFFFu));
             tabo[cbase[k]] = (uint32_t)ebase[k];
@@ -339,8 +327,8 @@ int build_streams(Dev& G, const Sizes& z, const std::vector<uint32_t>& cnti, hip
     for (uint32_t q = 0; q <= k; ++q) c0[q] = (uint32_t)cbase[q];
     HIP_OR_RETURN(hipMemcpyAsync(G.cs_c0, c0.data(), c0.size() * 4, hipMemcpyHostToDevice, st), "write stream bases");
     if (G.n_chunks) {
-        HIP_OR_RETURN(hipMemcpyAsync(G.cs_bm, bm.data(), bm.size() * 4, hipMemcpyHostToDevice, st),
-                      "write stream bin starts");
+        HIP_OR_RETURN(hipMemcpyAsync(G.cs_lm, lm.data(), lm.size() * 8, hipMemcpyHostToDevice, st),
+                      "write stream lane starts");
         HIP_OR_RETURN(hipMemcpyAsync(G.cs_tabo, tabo.data(), tabo.size() * 4, hipMemcpyHostToDevice, st),
                       "write stream tables");
         HIP_OR_RETURN(hipMemcpyAsync(G.cs_ent, ent.data(), ent.size() * 8, hipMemcpyHostToDevice, st),
@@ -782,7 +770,8 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
                                      st), "write split list");
     G.idb = (uint32_t)slot;
     G.pcs_mode = z.pc_stream;
-    HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(G.data + G.idb), 0xFFFFFFFF, 256, st), "write identity words");
+    HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(G.data + G.idb), 0xFFFFFFFF, kIdWords, st),
+                  "write identity words");
     if ((rc = build_streams(G, z, cnti, st))) return rc;
     HIP_OR_RETURN(launch_part_static(G, st), "partition features");
     Ctrl hc2;
@@ -1268,7 +1257,7 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     const uint64_t k = S.k, q = S.q, kk = k * k;
     const uint64_t E_pad = align256(S.E ? S.E : 1);
     const uint64_t ngt = S.n_gtask ? S.n_gtask : 1;
-    D->data = (uint32_t*)take((g->M + 256) * 4);  // messages, then the identity words
+    D->data = (uint32_t*)take((g->M + kIdWords) * 4);  // messages, then the identity words
     D->sc_ids = (uint16_t*)take(E_pad * 2);
     D->sc_w = S.w ? (uint8_t*)take(E_pad) : nullptr;
     D->sc_chunk = (uint32_t*)take(E_pad / kChunk * 4);
@@ -1370,7 +1359,7 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
         q_max = std::max(q_max, S.q);
         HIP_OR_RETURN(hipMemsetAsync(I.G.ctrl, 0, sizeof(Ctrl), st), "clear run control");
         HIP_OR_RETURN(hipMemsetAsync(I.G.cact, 0, (size_t)S.k * 4, st), "clear column stamps");
-        HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(I.G.data + S.idb), 0xFFFFFFFF, 256, st),
+        HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(I.G.data + S.idb), 0xFFFFFFFF, kIdWords, st),
                       "write identity words");
     }
     BatchGrid& B = b->grid;

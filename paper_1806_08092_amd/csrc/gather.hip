@@ -43,7 +43,8 @@ struct GatherLds {
 __host__ __device__ inline GatherLds gather_layout(int prog, uint32_t q, bool rounds = false) {
     GatherLds L{};
     size_t o = 0;
-    L.state = o;  o += (size_t)q * (is_sum(prog) ? 8 : 4);
+    // the state, plus one spare word (index q) that null stream ids combine into
+    L.state = o;  o += ((size_t)(q + 1) * (is_sum(prog) ? 8 : 4) + 15) / 16 * 16;
     L.tag = o;    o += (rounds && is_sum(prog)) ? ((size_t)q * 2 + 15) / 16 * 16 : 0;
     L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
     L.amask = o;  o += kMaxMaskWords * 8;
@@ -290,22 +291,28 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
 }
 
 // Partition-centric ids of one column read from its stream, chunks
-// [c_lo, c_hi): wave w takes chunks c_lo + w, c_lo + w + kGW, ..., SPW per
-// round. Lane l decodes chunk positions 4l..4l+3. The entry b of a position
-// is the number of inner bin starts at positions 1..i (bitmap prefix) and its
-// message index the number of message starts at positions 1..i (flag
-// prefix); both come from one packed wave scan. The entry's adj value is
-// taken from lane b with ds_bpermute (a chunk has at most 64 entries), and
-// data[adj + message index] is the position's message value. A bin whose
-// source partition did not scatter partition-centric this iteration (or a
-// padding run) reads the identity words instead, so no id is masked.
-// The next round's ids, bitmaps, weights and entries are loaded before the
-// current round is decoded; the table offsets one round earlier still.
+// [c_lo, c_hi): wave w takes chunks c_lo + w, c_lo + w + NW, ..., SPW per
+// round. Lane l decodes chunk positions 4l..4l+3, which belong to one bin
+// (bins start at multiples of 4). Its entry is the number of lane starts at
+// lanes 1..l (a popcount of the chunk's lane-start mask); the entry's adj
+// value comes from the lane that holds the entry (ds_bpermute; a chunk has at
+// most 64 entries) and the message index from one wave scan of the
+// message-start flags. One 16-byte load at data[adj + message starts before
+// 4l] then holds the values of all four positions (a bin's messages are
+// contiguous). A bin whose source did not scatter partition-centric this
+// iteration (or a padding run) reads the identity words instead, so no id is
+// masked; null ids (local id q) combine into a spare LDS word past the
+// partition's state and are not counted.
+// The next round's ids, weights and entries are loaded before the current
+// round is decoded; the chunks' table offsets and lane-start masks one round
+// earlier still, with scalar loads.
 template <int PROG, bool WIDE, uint32_t NW = kGW, uint32_t SPW = 4>
 __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, uint32_t c_hi, bool dense,
                                                   const uint64_t* pcm, uint32_t* st32,
                                                   unsigned long long* acc) {
     constexpr bool SUM = is_sum(PROG);
+    typedef __attribute__((address_space(4))) const uint32_t CU32;  // read with scalar loads
+    typedef __attribute__((address_space(4))) const uint64_t CU64;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // the range is the same in every lane: keep its arithmetic scalar
@@ -315,40 +322,43 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
     const uint32_t nrounds = (n + NW * SPW - 1) / (NW * SPW);
     const uint2* __restrict__ ids = reinterpret_cast<const uint2*>(gptr(G.cs_ids));
     const uint32_t* __restrict__ wts = reinterpret_cast<const uint32_t*>(gptr(G.cs_w));
-    const uint32_t* __restrict__ bmp = gptr(G.cs_bm);
-    const uint32_t* __restrict__ tabo = gptr(G.cs_tabo);
+    CU64* lmp = (CU64*)reinterpret_cast<uint64_t>(gptr(G.cs_lm));
+    CU32* tabo = (CU32*)reinterpret_cast<uint64_t>(gptr(G.cs_tabo));
     const uint2* __restrict__ ent = gptr(G.cs_ent);
     const uint32_t* __restrict__ data = gptr(G.data);
-    const uint32_t k = G.k, idb = G.idb;
-    const uint32_t bsh = 4u * (lane & 7u);
+    const uint32_t k = G.k, idb = G.idb, nulld = G.q;
     // message-start flags of the lane's positions after the byte gather
     // below (bit 8j + 7 = position 4l + j); position 0 of the chunk is not
     // counted
     const uint32_t mm = lane == 0 ? 0x80808000u : 0x80808080u;
-    // a message value: below 4 GiB of data, a buffer load with a 32-bit
-    // byte offset (no 64-bit address arithmetic per id)
+    // four message values: below 4 GiB of data, one 16-byte buffer load with
+    // a 32-bit byte offset
     const __amdgpu_buffer_rsrc_t drsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint32_t*>(data), (short)0, (int)0xFFFFFFFF, (int)0x00020000);
-    auto msg = [&](uint32_t d) -> uint32_t {
-        if constexpr (WIDE) return data[d];
-        else return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(drsrc, (int)(d << 2), 0, 0);
+    auto msg4 = [&](uint32_t d) -> uint4 {
+        if constexpr (WIDE) return make_uint4(data[d], data[d + 1], data[d + 2], data[d + 3]);
+        else {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(drsrc, (int)(d << 2), 0, 0);
+            return make_uint4((uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]);
+        }
     };
     auto piece = [&](uint32_t r, uint32_t pi) -> uint32_t { return (r * SPW + pi) * NW + wave; };
     auto chunk = [&](uint32_t r, uint32_t pi) -> uint32_t {
         const uint32_t i = piece(r, pi);
         return i < n ? c_lo + i : c_lo;  // past the range: re-read the first chunk, not combined
     };
-    // table offsets (start, end) of a round's chunks, loaded one round before
-    // they are used (the same value in every lane)
+    // per chunk of the next round: table offsets and lane-start mask (scalar)
     uint32_t tb_n[SPW], te_n[SPW];
+    uint64_t lm_n[SPW];
     uint2 raw_n[SPW], ent_n[SPW];
-    uint32_t bm_n[SPW], w_n[SPW];
-    auto fetch_tb = [&](uint32_t r, uint32_t* tb, uint32_t* te) {
+    uint32_t w_n[SPW];
+    auto fetch_meta = [&](uint32_t r, uint32_t* tb, uint32_t* te, uint64_t* lm) {
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
             const uint32_t c = chunk(r, pi);
             tb[pi] = tabo[c];
             te[pi] = tabo[c + 1];
+            lm[pi] = lmp[c];
         }
     };
     auto fetch = [&](uint32_t r, const uint32_t* tb, const uint32_t* te) {
@@ -356,39 +366,42 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
         for (uint32_t pi = 0; pi < SPW; ++pi) {
             const uint32_t c = chunk(r, pi);
             raw_n[pi] = gptr(ids + (size_t)c * 64)[lane];
-            bm_n[pi] = gptr(bmp + (size_t)c * 8)[lane >> 3];
             // lanes past the chunk's table read its last entry (one fetch)
-            const uint32_t t0 = __builtin_amdgcn_readfirstlane(tb[pi]);
-            const uint32_t ne = __builtin_amdgcn_readfirstlane(te[pi]) - t0;
-            ent_n[pi] = gptr(ent + t0)[min(lane, ne - 1u)];
+            ent_n[pi] = gptr(ent + tb[pi])[min(lane, te[pi] - tb[pi] - 1u)];
             w_n[pi] = 0u;
             if constexpr (is_weighted(PROG)) w_n[pi] = gptr(wts + (size_t)c * 64)[lane];
         }
     };
-    uint32_t my_ids = 0;  // non-identity ids combined by the wave (the same in every lane)
+    uint32_t my_ids = 0;  // non-identity ids the lane combined
     if (nrounds == 0) return 0;
     uint32_t tb_a[SPW], te_a[SPW];
-    fetch_tb(0, tb_a, te_a);
+    uint64_t lm_a[SPW];
+    fetch_meta(0, tb_a, te_a, lm_a);
     fetch(0, tb_a, te_a);
-    fetch_tb(1, tb_n, te_n);
+    fetch_meta(1, tb_n, te_n, lm_n);
     for (uint32_t r = 0; r < nrounds; ++r) {
         uint2 raw[SPW], ev[SPW];
-        uint32_t bmw[SPW], wv[SPW], tb_b[SPW], te_b[SPW];
+        uint32_t wv[SPW], tb_b[SPW], te_b[SPW];
+        uint64_t lmc[SPW], lm_b[SPW];
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
             raw[pi] = raw_n[pi];
             ev[pi] = ent_n[pi];
-            bmw[pi] = bm_n[pi];
             wv[pi] = w_n[pi];
+            lmc[pi] = lm_a[pi];
             tb_b[pi] = tb_n[pi];
             te_b[pi] = te_n[pi];
+            lm_b[pi] = lm_n[pi];
         }
         // loads of the next round (chunks past the range re-read the first)
-        fetch_tb(r + 2, tb_n, te_n);
+        fetch_meta(r + 2, tb_n, te_n, lm_n);
         fetch(r + 1, tb_b, te_b);
-        // the round's four chunks go through each step together, so that
-        // their scans, ds_bpermutes and loads overlap one another's latency
-        uint32_t val[4 * SPW], adjv[SPW], hb[SPW], b4[SPW], ex[SPW];
+#pragma unroll
+        for (uint32_t pi = 0; pi < SPW; ++pi) lm_a[pi] = lm_b[pi];
+        // the round's chunks go through each step together, so that their
+        // scans, ds_bpermutes and loads overlap one another's latency
+        uint32_t adjv[SPW], hb[SPW], mex[SPW];
+        uint4 v4[SPW];
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
             adjv[pi] = ev[pi].x;
@@ -400,44 +413,52 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
             // reads the identity words: its combines change nothing
             if (piece(r, pi) >= n) adjv[pi] = idb;
             hb[pi] = __builtin_amdgcn_perm(raw[pi].y, raw[pi].x, 0x07050301u) & mm;
-            b4[pi] = (bmw[pi] >> bsh) & 0xFu;
-            ex[pi] = ((uint32_t)__popc(b4[pi]) << 16) | (uint32_t)__popc(hb[pi]);
+            mex[pi] = (uint32_t)__popc(hb[pi]);
         }
 #pragma unroll
-        for (uint32_t pi = 0; pi < SPW; ++pi) ex[pi] = wave_incl_scan(ex[pi]) - ex[pi];
-        // data index of each position: its entry's adj (from the lane that
-        // holds the entry) plus the message starts at positions 1..i
+        for (uint32_t pi = 0; pi < SPW; ++pi) mex[pi] = wave_incl_scan(mex[pi]) - mex[pi];
 #pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
-            const uint32_t mex = ex[pi] & 0xFFFFu, bex = ex[pi] >> 16;
-#pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) {
-                const uint32_t bj = bex + (uint32_t)__popc(b4[pi] & ((2u << j) - 1u));
-                val[4 * pi + j] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(bj << 2), (int)adjv[pi]) +
-                                  mex + (uint32_t)__popc(hb[pi] & ((0x100u << (8u * j)) - 1u));
-            }
+            // entry of the lane: lane starts at lanes 1..lane
+            const uint32_t b = popc_lt(lmc[pi]) + (uint32_t)((lmc[pi] >> lane) & 1ull);
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(b << 2), (int)adjv[pi]) + mex[pi] +
+                                ((hb[pi] >> 7) & 1u);
+            v4[pi] = msg4(d0);
         }
 #pragma unroll
-        for (uint32_t j = 0; j < 4 * SPW; ++j) val[j] = msg(val[j]);
-#pragma unroll
         for (uint32_t pi = 0; pi < SPW; ++pi) {
+            // message of position 4l + j relative to that of 4l: the starts at 4l+1..4l+j
+            // word r of the four loaded, r = the message starts at
+            // positions 4l+1..4l+j, by bit selects (m* = 0 or all ones)
+            const uint32_t m1 = (uint32_t)__builtin_amdgcn_sbfe((int)hb[pi], 15, 1);
+            const uint32_t m2 = (uint32_t)__builtin_amdgcn_sbfe((int)hb[pi], 23, 1);
+            const uint32_t m3 = (uint32_t)__builtin_amdgcn_sbfe((int)hb[pi], 31, 1);
+            const uint32_t a = v4[pi].x, bb = v4[pi].y, cc = v4[pi].z, dd = v4[pi].w;
+            auto bfi = [](uint32_t m, uint32_t y, uint32_t x) { return (m & y) | (~m & x); };
+            const uint32_t t1 = bfi(m1, cc, bb), t2 = bfi(m1, dd, cc);
+            uint32_t xv[4];
+            xv[0] = a;
+            xv[1] = bfi(m1, bb, a);
+            xv[2] = bfi(m2, t1, xv[1]);
+            xv[3] = bfi(m3, bfi(m2, t2, t1), xv[2]);
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
-                uint32_t x = val[4 * pi + j];
+                uint32_t x = xv[j];
                 if constexpr (is_weighted(PROG)) x = sat_add(x, (wv[pi] >> (8u * j)) & 0xFFu);
                 const uint32_t d = ((j < 2 ? raw[pi].x : raw[pi].y) >> (16u * (j & 1u))) & kLocalMask;
+                const bool real = d != nulld;
                 if constexpr (SUM) {
-                    const bool use = (int32_t)x >= 0;  // identities and padding read negative words
-                    my_ids += popc64(ballot(use));
+                    const bool use = (int32_t)x >= 0 && real;  // identities and padding read negative words
+                    my_ids += use ? 1u : 0u;
                     atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(x) * kFix) : 0ull);
                 } else {
-                    my_ids += popc64(ballot(x != kIdentMin));
+                    my_ids += (x != kIdentMin && real) ? 1u : 0u;
                     atomicMin(st32 + d, x);
                 }
             }
         }
     }
-    return lane == 0 ? my_ids : 0u;  // the wave's count, once
+    return my_ids;
 }
 
 // An iteration in which every partition scattered partition-centric and
@@ -461,7 +482,7 @@ struct DenseLds {
 __host__ __device__ inline DenseLds dense_layout(int prog, uint32_t q) {
     DenseLds L{};
     size_t o = 0;
-    L.state = o;  o += (size_t)q * (is_sum(prog) ? 8 : 4);
+    L.state = o;  o += ((size_t)(q + 1) * (is_sum(prog) ? 8 : 4) + 15) / 16 * 16;  // plus the spare word
     L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
     L.keep = o;   o += ((size_t)q / 64 + 1) * 8;
     L.total = o;
@@ -559,7 +580,7 @@ __device__ __forceinline__ void dense_body(const Dev& G, const Params& P, uint32
         __syncthreads();
     }
     uint32_t my_ids;
-    if (G.idb < (1u << 30) - 256u) my_ids = stream_gather<PROG, false, kDW, 2>(G, cs_lo, cs_hi, true, nullptr, st32, acc);
+    if (G.idb < (1u << 30) - kIdWords) my_ids = stream_gather<PROG, false, kDW, 2>(G, cs_lo, cs_hi, true, nullptr, st32, acc);
     else my_ids = stream_gather<PROG, true, kDW, 2>(G, cs_lo, cs_hi, true, nullptr, st32, acc);
     __syncthreads();
     if (split) {
@@ -811,7 +832,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     if constexpr (!ROUNDS) {
         if (use_stream) {
             const bool dense = gptr(G.ctrl)->n_pcpart == k;
-            if (G.idb < (1u << 30) - 256u) my_ids += stream_gather<PROG, false>(G, cs_lo, cs_hi, dense, pcm, st32, acc);
+            if (G.idb < (1u << 30) - kIdWords) my_ids += stream_gather<PROG, false>(G, cs_lo, cs_hi, dense, pcm, st32, acc);
             else my_ids += stream_gather<PROG, true>(G, cs_lo, cs_hi, dense, pcm, st32, acc);
         }
     }

@@ -27,6 +27,7 @@ constexpr uint32_t kIdentMin = 0xFFFFFFFFu;  // min-combine identity ("no messag
 constexpr uint32_t kIdentSum = 0x80000000u;  // sum-combine identity: -0.0f bits
 constexpr uint32_t kLogCap = 4096;        // per-iteration stats records
 constexpr uint8_t kFallbackMark = 0x80u;  // a learned mode the network left to Eq. 1
+constexpr uint32_t kIdWords = 320;        // identity words after the messages (a 256-position chunk plus a lane's 4)
 constexpr uint32_t kScWaves = 4;          // independent source-centric task waves per workgroup
 constexpr uint32_t kMergeSpan = 1024;     // vertices per workgroup of a split-partition merge
 constexpr uint32_t kMaxMergeChunks = 32;  // q / kMergeSpan at the largest partition (2^15)
@@ -110,7 +111,7 @@ struct Dev {
     uint32_t combine;         // GPOP_COMBINE_*
     uint32_t whole_ids;       // a split partition with at most this many ids is gathered by one task
     uint32_t pcs_mode;        // GPOP_PCSTREAM_*
-    uint32_t idb;             // data[idb, idb + 256): combine identities (min and sum), never written
+    uint32_t idb;             // data[idb, idb + kIdWords): combine identities (min and sum), never written
     uint32_t n_chunks;        // chunks of all column streams
     uint64_t E;
     const uint32_t* off;
@@ -129,20 +130,24 @@ struct Dev {
     uint8_t* png_w;           // [E_pad] static weights
     uint32_t* png_chunk;      // [E_pad/256]
     uint4* pctask;            // [n_pctask] {p, slot_begin, slot_end, 0}
-    // column streams of the partition-centric ids (static): column q's
-    // chunks are [cs_c0[q], cs_c0[q+1]); chunk c holds stream positions
-    // [256c, 256c + 256). A bin starts at chunk position 0 or at a position
-    // flagged in cs_bm (at most 63 such inner starts per chunk, a padding
-    // run included). Chunk c's entries [cs_tabo[c], cs_tabo[c+1]) are, for
-    // the bin at position 0 and then each inner start in position order,
+    // column streams of the partition-centric ids (static; built for
+    // partitions of at most 2^14 vertices): column q's chunks are
+    // [cs_c0[q], cs_c0[q+1]); chunk c holds stream positions [256c, 256c+256),
+    // four per lane of the wave that decodes it. Every bin starts at a
+    // multiple of 4 (its last lane is filled with null ids: local id q, no
+    // message start), so a lane's four positions always belong to one bin.
+    // Bit l of cs_lm[c] marks a bin (or the padding run at a column's end)
+    // starting at lane l > 0. Chunk c's entries [cs_tabo[c], cs_tabo[c+1])
+    // are, for the bin at position 0 and then each lane start in order,
     // {adj, src | mt << 16}: the data index of a position i is
-    // adj[b] + (message starts at positions 1..i), b = inner starts at 1..i;
-    // src is the source partition (0xFFFF: padding, whose adj points into the
-    // identity words) and mt the message starts at positions 1..start.
+    // adj[b] + (message starts at positions 1..i), b = lane starts at lanes
+    // 1..i/4; src is the source partition (0xFFFF: padding, whose adj points
+    // into the identity words) and mt the message starts at positions
+    // 1..start.
     uint32_t* cs_c0;          // [k+1]
     uint16_t* cs_ids;         // [n_chunks*256] ids (local id | message-start flag)
     uint8_t* cs_w;            // [n_chunks*256] weights
-    uint32_t* cs_bm;          // [n_chunks*8] inner bin starts, bit i of the chunk = position i
+    uint64_t* cs_lm;          // [n_chunks] lanes that start a bin
     uint32_t* cs_tabo;        // [n_chunks+1]
     uint2* cs_ent;            // [entries + 64]
     uint32_t* bld_t0;         // [k+1] task prefix of the build (all vertices active)

@@ -203,14 +203,15 @@ hipError_t launch_colsrc(const Dev& G, hipStream_t st) {
 }
 
 // Column streams, per-id part (one wave per chunk, after the host walk has
-// written each chunk's bin-start bitmap, table offset and raw entries:
-// entry 0 {offset of the chunk start inside its bin, src | q << 16}, inner
-// entries {start position, src | q << 16}, src = 0xFFFF for padding).
-// Lane l covers chunk positions 4l..4l+3: it finds the bin of each position
-// from the bitmap, copies the id and weight from the bin's per-bin layout
-// (padding: a message-start id of vertex 0 with weight 0), and counts
-// message starts. The entries are then rewritten in their final form
-// {adj, src | mt << 16} (see Dev::cs_ent).
+// written each chunk's lane-start mask, table offset and raw entries:
+// entry 0 {offset of the chunk start inside its bin, src | q << 16}, lane
+// starts {start position, src | q << 16}, src = 0xFFFF for padding).
+// Lane l covers chunk positions 4l..4l+3, all in one bin: it copies their ids
+// and weights from the bin's per-bin layout, fills the bin's last lane past
+// its ids with null ids (local id q, not a message start, weight 0) and the
+// padding run with one-id messages to vertices 0..63 (identity values then
+// spread over the LDS banks), and counts message starts. The entries are
+// then rewritten in their final form {adj, src | mt << 16} (see Dev::cs_ent).
 __device__ __forceinline__ uint32_t bperm(uint32_t lane_src, uint32_t v) {
     return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(lane_src << 2), (int)v);
 }
@@ -221,7 +222,8 @@ __global__ __launch_bounds__(256) void k_cs_fill(Dev G) {
     if (c >= G.n_chunks) return;
     const uint32_t k = G.k;
     const uint32_t tb = G.cs_tabo[c], ne = G.cs_tabo[c + 1] - tb;
-    if (ne == 0 || ne > 64) {
+    const uint64_t lm = G.cs_lm[c];
+    if (ne == 0 || ne > 64 || ne != 1u + (uint32_t)__popcll(lm) || (lm & 1ull)) {
         if (lane == 0) G.ctrl->bug = 1;
         return;
     }
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(256) void k_cs_fill(Dev G) {
     // hold a copy of its last entry, which they never use)
     const uint32_t t = (lane == 0 || lane >= ne) ? 0u : e.x;
     const uint32_t x0 = lane == 0 ? e.x : 0u;  // entry 0: offset of the chunk start inside its bin
-    const bool sane = q < k && (pad || src < k) && t < kChunk;
+    const bool sane = q < k && (pad || src < k) && t < kChunk && (t & 3u) == 0u;
     if (__builtin_amdgcn_read_exec() != ballot(sane)) {  // an inconsistent table (internal error)
         if (lane == 0) G.ctrl->bug = 1;
         return;
@@ -246,28 +248,27 @@ __global__ __launch_bounds__(256) void k_cs_fill(Dev G) {
     // per-bin position of chunk position i for this entry: ioff + x0 + i - t
     const uint32_t rbase = cb.y + x0 - t;
     const uint32_t rend = cb.y + cb.w;          // end of the bin in the per-bin layout
-    const uint32_t bmw = G.cs_bm[(size_t)c * 8 + (lane >> 3)];
-    const uint32_t b4 = (bmw >> (4u * (lane & 7u))) & 0xFu;
-    const uint32_t bc = __popc(b4);
-    const uint32_t bex = wave_incl_scan(bc) - bc;
+    // the lane's entry: lane starts at lanes 1..lane
+    const uint32_t bl = popc_lt(lm) + (uint32_t)((lm >> lane) & 1ull);
+    const uint32_t rb = bperm(bl, rbase), re = bperm(bl, rend), pj = bperm(bl, pad ? 1u : 0u);
     uint32_t ids[4], wv[4], mflag = 0;
     bool bad = false;
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) {
-        const uint32_t bj = bex + __popc(b4 & ((2u << j) - 1u));  // entry of position 4l + j
-        const uint32_t rb = bperm(bj, rbase), re = bperm(bj, rend), pj = bperm(bj, pad ? 1u : 0u);
         const uint32_t i = 4u * lane + j;
-        // padding: one-id messages to vertices 0..63 of the partition, which
-        // spreads their (identity) combines over the LDS banks
         if (pj) {
             ids[j] = kFlag | (i & 63u);
             wv[j] = 0u;
         } else {
             const uint32_t r = rb + i;
-            const bool ok = bj < ne && r < re;
-            bad = bad || !ok;
-            ids[j] = ok ? G.png_ids[r] : kFlag;
-            wv[j] = ok && G.w ? G.png_w[r] : 0u;
+            if (r < re) {
+                ids[j] = G.png_ids[r];
+                wv[j] = G.w ? G.png_w[r] : 0u;
+            } else {
+                ids[j] = G.q;  // null id after the bin's last id
+                wv[j] = 0u;
+                bad = bad || j == 0;  // a lane starts with an id of its bin
+            }
         }
         if (i > 0 && (ids[j] & kFlag)) mflag |= 1u << j;
     }
@@ -277,17 +278,11 @@ __global__ __launch_bounds__(256) void k_cs_fill(Dev G) {
     iw.y = ids[2] | (ids[3] << 16);
     reinterpret_cast<uint2*>(G.cs_ids)[(size_t)c * 64 + lane] = iw;
     reinterpret_cast<uint32_t*>(G.cs_w)[(size_t)c * 64 + lane] = wv[0] | (wv[1] << 8) | (wv[2] << 16) | (wv[3] << 24);
-    // message starts at positions 1..i, inclusive, for each of the lane's positions
+    // message starts at positions 1..4l, inclusive
     const uint32_t mc = __popc(mflag);
-    const uint32_t mex = wave_incl_scan(mc) - mc;
-    uint32_t mi[4];
-#pragma unroll
-    for (uint32_t j = 0; j < 4; ++j) mi[j] = mex + __popc(mflag & ((2u << j) - 1u));
+    const uint32_t m0 = wave_incl_scan(mc) - mc + (mflag & 1u);
     // message starts at positions 1..t of each entry's start t (entry 0: 0)
-    const uint32_t m0 = bperm(t >> 2, mi[0]), m1 = bperm(t >> 2, mi[1]);
-    const uint32_t m2 = bperm(t >> 2, mi[2]), m3 = bperm(t >> 2, mi[3]);
-    const uint32_t tj = t & 3u;
-    const uint32_t mt = lane == 0 ? 0u : (tj == 0 ? m0 : tj == 1 ? m1 : tj == 2 ? m2 : m3);
+    const uint32_t mt = lane == 0 ? 0u : bperm(t >> 2, m0);
     // entry 0: message index (inside bin 0) of the message holding the chunk
     // start, counted from the per-bin chunk table and up to 255 flags
     uint32_t midx0 = 0;
