@@ -766,6 +766,7 @@ def selector_compare(args, parts, ms_eq1_default):
     from paper_1806_08092_amd import learned
     t_all = time.perf_counter()
     data_parts = []
+    keep = None  # the largest training graph: whole runs that calibrate the confidence margin
     for i, (scale, ef, abc) in enumerate(TRAIN_SPECS):
         if scale > args.train_scale:
             continue
@@ -783,6 +784,8 @@ def selector_compare(args, parts, ms_eq1_default):
                 G.set_frontier(torch.tensor([root], dtype=torch.int32, device="cuda"))
             data_parts.append(learned.collect(G, max_iter=10 if prog == "pagerank" else 1 << 20))
             del G
+        if keep is None or scale > keep[1]:
+            keep = (g, scale, srcs)
         del off, cols, w, st
         torch.cuda.empty_cache()
     data = learned.Samples.concat(data_parts)
@@ -790,8 +793,25 @@ def selector_compare(args, parts, ms_eq1_default):
     mlp = learned.train(data, gg.mlp_init_params(gg.BASE_SEED), steps=args.train_steps, batch=4096, lr=1e-3,
                         seed=1)
     torch.cuda.synchronize()
+    # confidence margin: whole BFS and CC runs on the largest training graph
+    kg, kscale, ksrcs = keep
+    koff, kcols, kw = gp.upload_csr(kg)
+    kst = torch.empty(kg.n, dtype=torch.int32, device="cuda")
+    kdeg = (koff[1:] - koff[:-1]).to(torch.int64)
+    KG = gp.Graph(koff, kcols, kw, log2_part=14)
+    KG.set_selector("learned", 16.0, mlp=mlp.model)
+    kruns = [("bfs", ksrcs[0]), ("bfs", ksrcs[-1]), ("cc", 0)]
+
+    def time_train_runs():
+        KG.set_selector("learned", 16.0, mlp=mlp.model)  # the selector's copy takes the new margin
+        return _time_runs(KG, kst, kruns, 3, kdeg, kg.n, kg.m)[0]
+
+    margin, margin_ms = learned.calibrate_margin(mlp, time_train_runs)
+    del KG, koff, kcols, kw, kst, kdeg, keep
+    torch.cuda.empty_cache()
     train_s = time.perf_counter() - t_all
-    log("selector trained on %d rows in %.1f s" % (len(data), train_s))
+    log("selector trained on %d rows in %.1f s; confidence margin %s (training-graph ms: %s)" % (
+        len(data), train_s, margin, {str(k): round(v, 3) for k, v in margin_ms.items()}))
     # identical results: one BFS and the CC of the first graph under both
     P0 = parts[0]
     same = True
@@ -802,6 +822,15 @@ def selector_compare(args, parts, ms_eq1_default):
         P0.G.set_selector("learned", 16.0, mlp=mlp.model)
         P0.do_run(prog, root)
         same = same and bool(torch.equal(a, P0.st))
+    # share of the learned run's decisions the network made (the rest fell
+    # back to Eq. 1: inside the confidence margin or an untrained input)
+    P0.G.set_selector("learned", 16.0, mlp=mlp.model)
+    nfb = ndec = 0
+    for prog, root in P0.runs:
+        P0.do_run(prog, root)
+        for rec in P0.G.iter_stats():
+            nfb += rec["learned_fallbacks"]
+            ndec += rec["sc_parts"] + rec["pc_parts"]
     res = {}
     for name, kind, ratio in (("eq1_default16", "analytical", 16.0), ("eq1_ratio2", "analytical", 2.0),
                               ("learned", "learned", 16.0), ("eq1_default16_again", "analytical", 16.0)):
@@ -817,7 +846,10 @@ def selector_compare(args, parts, ms_eq1_default):
             "ms_per_step": {"eq1_default16": eq16, "eq1_ratio2": res["eq1_ratio2"], "learned": res["learned"]},
             "identical_results": same, "train_rows": len(data), "train_s": train_s,
             "train_scales": "18-%d" % args.train_scale, "train_steps": args.train_steps,
-            "gather_us_per_id": {"sc": c_sc, "pc": c_pc}}
+            "gather_us_per_id": {"sc": c_sc, "pc": c_pc},
+            "confidence_margin": None if margin == float("inf") else margin,
+            "margin_ms_on_training_graph": {str(k): v for k, v in margin_ms.items()},
+            "network_decided_fraction": (1.0 - nfb / ndec) if ndec else 0.0}
 
 
 def headline(args):

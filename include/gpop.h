@@ -137,9 +137,10 @@ typedef struct gpop_options {
                                   max(1024, 4k). Iterations with little
                                   source-centric work use smaller tasks       */
     uint32_t gather_task_ids;  /* ids per gather task (>= 256); 0 picks
-                                  max(2^16, E / 1024). A partition whose bins
-                                  hold more ids is gathered by several tasks
-                                  (at most 64) and merged                      */
+                                  max(2^16, E / n), n = 2^20 / k clamped to
+                                  [256, 512]. A partition whose bins hold more
+                                  ids is gathered by several tasks (at most
+                                  64) and merged                               */
     uint32_t combine;          /* GPOP_COMBINE_LDS (0) or GPOP_COMBINE_ROUNDS   */
     uint32_t pc_stream;        /* GPOP_PCSTREAM_AUTO (0), _OFF or _ON: how
                                   gather reads partition-centric bins       */

@@ -69,7 +69,11 @@ typedef struct gpop_mlp_model {
     float mean[GPOP_MLP_IN];       /* feature standardisation                 */
     float inv_std[GPOP_MLP_IN];
     uint16_t w[GPOP_MLP_PARAMS];   /* bf16 bit patterns                       */
-    uint16_t pad[11];
+    uint16_t pad0;
+    float margin;                  /* confidence gate: a partition whose |logit|
+                                      is below it keeps Eq. 1's mode (0: the
+                                      network decides alone, +inf: Eq. 1 alone) */
+    uint16_t pad[8];
 } gpop_mlp_model;
 
 /* Starts a model: writes the header, sets mean / inv_std from the n x 12
@@ -131,6 +135,14 @@ int gpop_mlp_train_step(gpop_mlp_model* d_model, float* d_master, float* d_m, fl
  * calibrating the decision threshold against whole-run timings after
  * training. Errors: GPOP_EINVAL on NULL arguments or a non-finite delta. */
 int gpop_mlp_shift_logit(gpop_mlp_model* d_model, float* d_master, float delta, void* stream);
+
+/* Sets the model's confidence margin: the learned selector takes the
+ * network's mode for a partition only where |logit| >= margin, and Eq. 1's
+ * mode (at the graph's bandwidth ratio) elsewhere, counted as a fallback in
+ * the iteration records. gpop_mlp_init sets 0. For calibrating, after
+ * training, how far the network is trusted against whole-run timings.
+ * Errors: GPOP_EINVAL on NULL, a negative or NaN margin (+inf is allowed). */
+int gpop_mlp_set_margin(gpop_mlp_model* d_model, float margin, void* stream);
 
 #ifdef __cplusplus
 }

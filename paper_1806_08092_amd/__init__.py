@@ -150,6 +150,7 @@ _SIGS = {
                                                                    ctypes.c_float]
                             + [ctypes.c_void_p] * 3 + [ctypes.c_size_t, ctypes.c_void_p]),
     "gpop_mlp_shift_logit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+    "gpop_mlp_set_margin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
     "gpop_batch_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]),
     "gpop_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -512,6 +513,11 @@ class Mlp:
         self.step += 1
         _check(lib().gpop_mlp_adam(_ptr(self.model), _ptr(self.master), _ptr(self.m), _ptr(self.v),
                                    _ptr(self.grad), self.step, lr, _stream(stream)))
+
+    def set_margin(self, margin, stream=None):
+        """Confidence margin of the learned selector (gpop_mlp_set_margin):
+        partitions with |logit| below it keep Eq. 1's mode."""
+        _check(lib().gpop_mlp_set_margin(_ptr(self.model), ctypes.c_float(margin), _stream(stream)))
 
     def shift_logit(self, delta, stream=None):
         """Adds delta to the output bias (gpop_mlp_shift_logit)."""

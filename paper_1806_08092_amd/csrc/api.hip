@@ -107,7 +107,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Task sizes of a graph: the largest source-centric task in work units (at
 // least 1024 and at least 4k, so the per-task count row stays small next to
 // the task; lighter iterations use smaller tasks) and ids per gather task
-// (about 1024 tasks over all bins, so that the workgroups that finish early
+// (about 256-512 tasks over all bins, so that the workgroups that finish early
 // in a dense iteration pick up further tasks; heavier partitions are split
 // over several).
 struct Sizes {
@@ -124,7 +124,10 @@ Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
     z.sc_shift = 10;
     while ((1ull << z.sc_shift) < 4 * z.k) ++z.sc_shift;
     if (o && o->sc_task_log2) z.sc_shift = o->sc_task_log2;
-    z.T = std::max<uint64_t>(1ull << 16, E / 1024);
+    // about 512 tasks, or 256 when there are 4096 destination partitions
+    // (enough columns to fill the chip without splitting as many)
+    const uint64_t ntask = std::min<uint64_t>(512, std::max<uint64_t>(256, (1ull << 20) / z.k));
+    z.T = std::max<uint64_t>(1ull << 16, E / ntask);
     if (o && o->gather_task_ids) z.T = o->gather_task_ids;
     z.pc_stream = o ? o->pc_stream : GPOP_PCSTREAM_AUTO;
     return z;
@@ -972,7 +975,10 @@ int gpop_set_selector(gpop_graph* g, gpop_selector kind, float bw_ratio, uint32_
                 return fail(GPOP_EINVAL, "model standardisation %d is not finite and positive", i);
         for (int j = 0; j < GPOP_MLP_PARAMS; ++j)
             if ((h.w[j] & 0x7F80u) == 0x7F80u) return fail(GPOP_EINVAL, "model weight %d is not finite", j);
+        if (!(h.margin >= 0.f)) return fail(GPOP_EINVAL, "model margin must be >= 0");
         HIP_OR_RETURN(hipMemcpy(g->G.mlp, &h, sizeof h, hipMemcpyHostToDevice), "write model");
+        // an infinite margin: the plan applies Eq. 1 and no selection kernel runs
+        g->P.learned_eq1 = std::isinf(h.margin) ? 1u : 0u;
     }
     g->P.selector = (uint32_t)kind;
     g->P.ratio_num = (uint32_t)std::lround((double)bw_ratio * 1024.0);
@@ -981,7 +987,7 @@ int gpop_set_selector(gpop_graph* g, gpop_selector kind, float bw_ratio, uint32_
     g->P.s_i = s_i;
     g->P.s_v = s_v;
     if (kind == GPOP_SEL_LEARNED && !d_mlp) g->P.selector = GPOP_SEL_ANALYTICAL;
-    g->grid.learned = g->P.selector == GPOP_SEL_LEARNED;
+    g->grid.learned = g->P.selector == GPOP_SEL_LEARNED && !g->P.learned_eq1;
     if (g->prog >= 0) return upload_tab(g, nullptr);  // the run reads its parameters on the device
     return GPOP_OK;
 }
@@ -1389,7 +1395,7 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
     B.learned = false;
     B.streams = false;
     for (uint32_t i = 0; i < n; ++i) {
-        B.learned = B.learned || graphs[i]->P.selector == GPOP_SEL_LEARNED;
+        B.learned = B.learned || (graphs[i]->P.selector == GPOP_SEL_LEARNED && !graphs[i]->P.learned_eq1);
         B.streams = B.streams || graphs[i]->G.n_chunks != 0;
     }
     for (uint32_t i = 1; i < n; ++i)

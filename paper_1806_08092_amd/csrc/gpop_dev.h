@@ -206,6 +206,7 @@ struct Params {
     uint32_t ratio_num, ratio_den;  // BW_PC / BW_SC as a fraction
     uint32_t probe;           // scatter kernels time their tasks into Dev::probe
     uint32_t isg;             // interleaved scatter-gather: colour classes (0 or 1: off)
+    uint32_t learned_eq1;     // learned selector whose margin is infinite: Eq. 1 decides every partition
 };
 
 // Interleaved scatter-gather (Sec. 3.3) in colour classes: partitions are

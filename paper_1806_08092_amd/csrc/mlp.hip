@@ -6,6 +6,7 @@
 // parameter column per lane for the sums over samples), so every reduction
 // runs in a fixed order and the gradient is reproducible bit for bit.
 #include <cmath>
+#include <cstddef>
 #include <mutex>
 
 #include "launch.h"
@@ -61,10 +62,12 @@ __global__ __launch_bounds__(256) void k_mlp_init(gpop_mlp_model* __restrict__ M
         mom2[j] = 0.f;
         M->w[j] = f32_to_bf16_bits(init[j]);
     }
-    for (uint32_t j = tid; j < 11; j += 256) M->pad[j] = 0;
+    for (uint32_t j = tid; j < 8; j += 256) M->pad[j] = 0;
     if (tid == 0) {
         M->magic = GPOP_MLP_MAGIC;
         M->n_params = kP;
+        M->pad0 = 0;
+        M->margin = 0.f;
     }
 }
 
@@ -351,6 +354,19 @@ int gpop_mlp_shift_logit(gpop_mlp_model* d_model, float* d_master, float delta, 
     if (!std::isfinite(delta)) return fail(GPOP_EINVAL, "delta must be finite");
     hipLaunchKernelGGL(k_mlp_shift, dim3(1), dim3(64), 0, (hipStream_t)stream, d_model, d_master, delta);
     HIP_OR_RETURN(hipGetLastError(), "mlp shift");
+    return GPOP_OK;
+}
+
+int gpop_mlp_set_margin(gpop_mlp_model* d_model, float margin, void* stream) {
+    if (!d_model) return fail(GPOP_EINVAL, "NULL argument");
+    if (!(margin >= 0.f)) return fail(GPOP_EINVAL, "margin must be >= 0 (or +inf)");
+    static_assert(offsetof(gpop_mlp_model, margin) % 4 == 0, "margin is 4-byte aligned");
+    static_assert(sizeof(gpop_mlp_model) == 10240, "model layout");
+    // the value is on this function's stack: wait for the copy before returning
+    HIP_OR_RETURN(hipMemcpyAsync(reinterpret_cast<char*>(d_model) + offsetof(gpop_mlp_model, margin), &margin,
+                                 sizeof margin, hipMemcpyHostToDevice, (hipStream_t)stream),
+                  "write margin");
+    HIP_OR_RETURN(hipStreamSynchronize((hipStream_t)stream), "sync");
     return GPOP_OK;
 }
 

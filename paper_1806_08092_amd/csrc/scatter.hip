@@ -646,7 +646,10 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
                 else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
-                else if (P.selector == GPOP_SEL_LEARNED) {
+                else if (P.selector == GPOP_SEL_LEARNED && P.learned_eq1) {
+                    md = analytical_mode_of(G, P, Ep, Mp, Va, Ea);  // the network decides nothing
+                    nfb += 1;
+                } else if (P.selector == GPOP_SEL_LEARNED) {
                     const uint8_t ml = gptr(G.mode_l)[p];
                     md = ml & (uint8_t)~kFallbackMark;
                     nfb += ml >> 7;

@@ -65,9 +65,13 @@ __device__ __forceinline__ void select_body(const Dev& G, const Params& P, uint3
     partition_features(G, P, p, Va, Ea, it, ea_frac, f);
     float z;
     uint8_t md;
-    if (mlp_logit(gptr(G.mlp), f, &z)) {
+    // an infinite margin leaves every partition to Eq. 1 (no network pass)
+    const float margin = gptr(G.mlp)->margin;
+    if (margin != INFINITY && mlp_logit(gptr(G.mlp), f, &z) && fabsf(z) >= margin) {
         md = z >= 0.f ? (uint8_t)GPOP_MODE_PC : (uint8_t)GPOP_MODE_SC;
     } else {
+        // an input the network was not trained on, or a logit inside the
+        // confidence margin: Eq. 1 decides
         // left to Eq. 1: bit 7 marks the fallback, which the plan counts
         md = (uint8_t)(analytical_mode(G, P, p, Va, Ea) | kFallbackMark);
     }
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(64) void kb_select(const Inst* __restrict__ tab,
                                                 const uint32_t* __restrict__ boff, uint32_t n) {
     const uint32_t i = batch_find(boff, n, blockIdx.x);
     const Inst& I = tab[i];
-    if (I.P.selector != GPOP_SEL_LEARNED) return;
+    if (I.P.selector != GPOP_SEL_LEARNED || I.P.learned_eq1) return;
     select_body(I.G, I.P, gptr(I.G.ctrl)->pos, blockIdx.x - boff[i]);
 }
 

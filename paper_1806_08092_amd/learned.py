@@ -193,6 +193,28 @@ def calibrate_offset(mlp, time_runs, offsets=(-1.0, 0.0, 0.5, 1.0, 2.0, 4.0, 8.0
     return best, res
 
 
+def calibrate_margin(mlp, time_runs, margins=(math.inf, 8.0, 4.0, 2.0, 1.0, 0.5, 0.0), stream=None,
+                     min_gain: float = 0.01):
+    """Chooses how far the network is trusted: with margin m the selector
+    takes the network's mode only where |logit| >= m and Eq. 1's elsewhere
+    (m = inf: Eq. 1 alone; m = 0: the network alone). time_runs() times whole
+    runs on training graphs (ms) under each candidate; a finite margin must
+    beat Eq. 1 alone by min_gain (a fraction of its time), else the margin
+    stays inf. Returns (margin, {margin: ms}); the model keeps the margin."""
+    res = {}
+    for m in margins:
+        mlp.set_margin(float(m), stream)
+        res[float(m)] = float(time_runs())
+    if math.inf not in res:
+        mlp.set_margin(math.inf, stream)
+        res[math.inf] = float(time_runs())
+    best = min(res, key=lambda m: (res[m], -m))
+    if res[best] > res[math.inf] * (1.0 - min_gain):
+        best = math.inf
+    mlp.set_margin(best, stream)
+    return best, res
+
+
 def calibrate_ratio(data: Samples, grid: Optional[np.ndarray] = None) -> float:
     """The bandwidth ratio whose Eq. 1 choices cost least on `data`."""
     if grid is None:
