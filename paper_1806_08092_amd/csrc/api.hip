@@ -85,6 +85,7 @@ struct gpop_graph {
     int prog = -1;
     uint32_t* state = nullptr;
     uint64_t M = 0;
+    uint64_t M_sc = 0;  // source-centric message slots (after the identity words)
     uint64_t nonempty_bins = 0;
     bool prof = false;
     bool limited = false;  // a finite iteration limit may be set on the device
@@ -136,9 +137,9 @@ Sizes sizes_for(uint32_t V, uint64_t E, uint32_t s, const gpop_options* o) {
 // Source-centric tasks of one iteration: a task holds at most 2^sc_shift work
 // units (an active vertex is one unit, each of its out-edges one more); the
 // plan takes smaller tasks when the iteration's units are few, never more
-// than 2 x sc_task_target of them (plus one partial task per partition).
+// than 2 x kScTaskTarget of them (plus one partial task per partition).
 uint64_t max_sctask_for(uint32_t V, uint64_t E, const Sizes& z) {
-    return std::max<uint64_t>((E + V) >> z.sc_shift, 2ull * sc_task_target((uint32_t)z.k)) + z.k + 1;
+    return std::max<uint64_t>((E + V) >> z.sc_shift, 2ull * kScTaskTarget) + z.k + 1;
 }
 
 // Bounds of the column streams (chunks, entries): every non-empty bin is
@@ -181,6 +182,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->bin_moff = (uint32_t*)take((kk + 1) * 4);
     G->bin_ioff = (uint32_t*)take((kk + 1) * 4);
     G->cm = (uint4*)take(kk * 16);
+    G->sc_mo = (uint32_t*)take(kk * 4);
     const uint64_t kw = (k + 63) / 64;
     G->colsrc = (uint64_t*)take(k * kw * 8);
     G->spre = (uint32_t*)take(kk * 4);
@@ -204,7 +206,9 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->gpart = (uint32_t*)take(ngt * q * 8);
     G->gflag = (uint32_t*)take(ngt * 4);
     G->mtot = (uint4*)take(k * kMaxMergeChunks * 16);
-    G->data = (uint32_t*)take((E_pad + kIdWords) * 4);  // messages (M <= E), then the identity words
+    // partition-centric messages (M <= E), the identity words, then the
+    // source-centric message slots (at most M + E / kPiece)
+    G->data = (uint32_t*)take((2 * E_pad + E_pad / kPiece + kIdWords) * 4);
     G->sc_ids = (uint16_t*)take(E_pad * 2);
     G->sc_w = (uint8_t*)take(E_pad);
     G->sc_chunk = (uint32_t*)take(nch * 4);
@@ -213,11 +217,10 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->cact = (uint32_t*)take(k * 4);
     G->pcmask = (uint64_t*)take(kw * 8);
     G->scmask = (uint64_t*)take(kw * 8);
-    G->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
-    G->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
+    G->sc_tt = (uint2*)take(nsct * 8);
     G->sc_sh = (uint8_t*)take(k);
     G->sc_t0 = (uint32_t*)take((k + 1) * 4);
-    G->sc_tc = (uint2*)take(nsct * k * 8);
+    G->sc_tc = (uint2*)take(((E >> z.sc_shift) + k + 1) * k * 8);  // build tasks x k
     G->gat_ids = (uint32_t*)take(ngt * 4);
     G->gat_ran = (uint32_t*)take((ngt + k) * 4);
     G->mode = (uint8_t*)take(k);
@@ -662,7 +665,28 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     HIP_OR_RETURN(launch_part_M(G, st), "partition messages");
     HIP_OR_RETURN(launch_colmajor(G, st), "column table");
     HIP_OR_RETURN(launch_colsrc(G, st), "column source masks");
+    // source-centric message slots: per bin its capacity (cnt_m becomes it),
+    // scanned into the counter array, which is cleared below
+    uint64_t m_sc = 0;
+    {
+        uint32_t* sx = reinterpret_cast<uint32_t*>(G.sc_cnt);  // kk * 8 bytes >= (kk + 1) words
+        HIP_OR_RETURN(launch_sc_cap(G, st), "source-centric capacities");
+        HIP_OR_RETURN(launch_scan_excl(G.cnt_m, sx, kk, G.scan_tmp, st), "scan source-centric capacities");
+        uint32_t tot[2];
+        HIP_OR_RETURN(hipMemcpyAsync(&tot[0], G.bin_moff + kk, 4, hipMemcpyDeviceToHost, st), "read M");
+        HIP_OR_RETURN(hipMemcpyAsync(&tot[1], sx + kk, 4, hipMemcpyDeviceToHost, st), "read SC slots");
+        HIP_OR_RETURN(hipStreamSynchronize(st), "sync");
+        m_sc = tot[1];
+        if ((uint64_t)tot[0] + kIdWords + m_sc >= 0x80000000ull)
+            return fail(GPOP_ENOTSUP, "graph has %llu + %llu message slots; at most 2^31 - 1 supported",
+                        (unsigned long long)tot[0], (unsigned long long)m_sc);
+        HIP_OR_RETURN(launch_sc_mo(G, sx, tot[0] + kIdWords, st), "source-centric message offsets");
+    }
+    // source-centric counters and marks start clear (each scatter clears what
+    // the one before it stamped)
     HIP_OR_RETURN(hipMemsetAsync(G.cact, 0, (size_t)G.k * 4, st), "clear column stamps");
+    HIP_OR_RETURN(hipMemsetAsync(G.sc_cnt, 0, kk * 8, st), "clear bin counters");
+    HIP_OR_RETURN(hipMemsetAsync(G.nz, 0, (size_t)G.k * G.kw * 64, st), "clear bin marks");
     HIP_OR_RETURN(launch_sc_build(G, 1, st), "fill PNG");
 
     std::vector<uint32_t> partM(G.k), cnti(kk), ioff(kk + 1);
@@ -784,7 +808,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
 
     // the graph's own run as a batch of one: per kernel, blocks [0, n)
     const uint32_t nb[6] = {(G.k + 63) / 64, std::min<uint32_t>((G.max_sctask + kScWaves - 1) / kScWaves, 2048u),
-                            scan_grid(G.k), G.n_pctask, G.n_gtask, G.n_gsplit * merge_chunks(G.q)};
+                            (G.k + 3) / 4, G.n_pctask, G.n_gtask, G.n_gsplit * merge_chunks(G.q)};
     uint32_t hb[12];
     for (int j = 0; j < 6; ++j) {
         hb[2 * j] = 0;
@@ -797,6 +821,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     if (!g) return fail(GPOP_ENOMEM, "host allocation failed");
     g->G = G;
     g->M = slot;
+    g->M_sc = m_sc;
     g->nonempty_bins = nz;
     g->P.selector = GPOP_SEL_ANALYTICAL;
     g->P.s_i = 4;
@@ -809,13 +834,13 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     B.n = 1;
     B.b_select = d_boff;
     B.b_sc = d_boff + 2;
-    B.b_scan = d_boff + 4;
+    B.b_clr = d_boff + 4;
     B.b_pc = d_boff + 6;
     B.b_gather = d_boff + 8;
     B.b_merge = d_boff + 10;
     B.nb_select = nb[0];
     B.nb_sc = nb[1];
-    B.nb_scan = nb[2];
+    B.nb_clr = nb[2];
     B.nb_pc = nb[3];
     B.nb_gather = nb[4];
     B.nb_merge = nb[5];
@@ -1263,7 +1288,8 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     const uint64_t k = S.k, q = S.q, kk = k * k;
     const uint64_t E_pad = align256(S.E ? S.E : 1);
     const uint64_t ngt = S.n_gtask ? S.n_gtask : 1;
-    D->data = (uint32_t*)take((g->M + kIdWords) * 4);  // messages, then the identity words
+    // partition-centric messages, the identity words, source-centric message slots
+    D->data = (uint32_t*)take((g->M + kIdWords + g->M_sc) * 4);
     D->sc_ids = (uint16_t*)take(E_pad * 2);
     D->sc_w = S.w ? (uint8_t*)take(E_pad) : nullptr;
     D->sc_chunk = (uint32_t*)take(E_pad / kChunk * 4);
@@ -1272,11 +1298,9 @@ size_t carve_run(Dev* D, char* base, const gpop_graph* g) {
     D->cact = (uint32_t*)take(k * 4);
     D->pcmask = (uint64_t*)take((k + 63) / 64 * 8);
     D->scmask = (uint64_t*)take((k + 63) / 64 * 8);
-    D->sc_tot = (uint2*)take(k * col_blocks(k) * 8);
-    D->sc_units = (uint32_t*)take(k * col_blocks(k) * 4);
+    D->sc_tt = (uint2*)take((uint64_t)S.max_sctask * 8);
     D->sc_sh = (uint8_t*)take(k);
     D->sc_t0 = (uint32_t*)take((k + 1) * 4);
-    D->sc_tc = (uint2*)take((uint64_t)S.max_sctask * k * 8);
     D->gat_ids = (uint32_t*)take(ngt * 4);
     D->gat_ran = (uint32_t*)take((ngt + k) * 4);
     D->mode = (uint8_t*)take(k);
@@ -1359,12 +1383,16 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
         I.state = nullptr;
         const Dev& S = g->G;
         const uint32_t nb[6] = {(S.k + 63) / 64, std::min<uint32_t>((S.max_sctask + kScWaves - 1) / kScWaves, sc_cap),
-                                scan_grid(S.k), S.n_pctask, S.n_gtask, S.n_gsplit * merge_chunks(S.q)};
+                                (S.k + 3) / 4, S.n_pctask, S.n_gtask, S.n_gsplit * merge_chunks(S.q)};
         for (int j = 0; j < 6; ++j) hb[(size_t)j * (n + 1) + i + 1] = hb[(size_t)j * (n + 1) + i] + nb[j];
         k_max = std::max(k_max, S.k);
         q_max = std::max(q_max, S.q);
         HIP_OR_RETURN(hipMemsetAsync(I.G.ctrl, 0, sizeof(Ctrl), st), "clear run control");
+        // source-centric counters and marks start clear (each scatter clears
+        // what the one before it stamped)
         HIP_OR_RETURN(hipMemsetAsync(I.G.cact, 0, (size_t)S.k * 4, st), "clear column stamps");
+        HIP_OR_RETURN(hipMemsetAsync(I.G.sc_cnt, 0, (size_t)S.k * S.k * 8, st), "clear bin counters");
+        HIP_OR_RETURN(hipMemsetAsync(I.G.nz, 0, (size_t)S.k * S.kw * 64, st), "clear bin marks");
         HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(I.G.data + S.idb), 0xFFFFFFFF, kIdWords, st),
                       "write identity words");
     }
@@ -1379,13 +1407,13 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
     }
     B.b_select = bo[0];
     B.b_sc = bo[1];
-    B.b_scan = bo[2];
+    B.b_clr = bo[2];
     B.b_pc = bo[3];
     B.b_gather = bo[4];
     B.b_merge = bo[5];
     B.nb_select = tot[0];
     B.nb_sc = tot[1];
-    B.nb_scan = tot[2];
+    B.nb_clr = tot[2];
     B.nb_pc = tot[3];
     B.nb_gather = tot[4];
     B.nb_merge = tot[5];
@@ -1403,10 +1431,6 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
             delete b;
             return fail(GPOP_EINVAL, "every graph of a batch must use the same combine option");
         }
-    if (sc_lds_bytes(k_max) > (size_t)max_lds_per_block()) {
-        delete b;
-        return fail(GPOP_ENOTSUP, "k = %u partitions need more LDS than a workgroup has", k_max);
-    }
     HIP_OR_RETURN(hipMemcpyAsync(boff, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, st), "write batch grid");
     HIP_OR_RETURN(hipMemcpyAsync(b->d_tab, b->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, st),
                   "write run table");

@@ -862,6 +862,7 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
                 const uint2 d = sccol[p];
                 icnt = d.y;
                 mcnt = d.x;
+                moff = gptr(G.sc_mo)[(size_t)cq * k + p];  // source-centric message slots
             }
         }
         const uint32_t dp = pieces_of(ioff, icnt);

@@ -50,31 +50,14 @@ __host__ __device__ constexpr bool is_weighted(int prog) { return prog == P_SSSP
 // gatherFunc sets an unvisited vertex only (BFS parents); the other min
 // programs keep any smaller value
 __host__ __device__ constexpr bool first_write(int prog) { return prog == P_PARENT; }
-// Source-centric tasks per iteration the plan aims for (about half the waves
-// the chip holds); bounded so that a count matrix of 2 x target x k words
-// stays at 64 MB at most.
-__host__ __device__ constexpr uint32_t sc_task_target(uint32_t k) {
-    return (1u << 22) / (k ? k : 1u) < 4096u ? (1u << 22) / (k ? k : 1u) : 4096u;
-}
-// Smallest source-centric task (log2 work units): 64, and at least k/4 so the
-// per-task count row of k destinations stays small next to the task.
-__host__ __device__ constexpr uint32_t sc_shift_floor(uint32_t k) {
-    uint32_t l = 0;
-    while ((2u << l) <= k) ++l;  // floor(log2 k)
-    return l > 8u ? l - 2u : 6u;
-}
-// Source-centric tasks of one partition at most (a partition with more work
-// takes larger tasks, so its offset scan stays short).
-constexpr uint32_t kMaxPartTasks = 1024;
-// A partition with more source-centric tasks than this has its offset scan
-// split into one unit per block of 64 destination partitions.
-constexpr uint32_t kScanRows = 64;
-__host__ __device__ constexpr uint32_t col_blocks(uint32_t k) { return (k + 63u) / 64u; }
-// Workgroups of the source-centric offset scan (they stride over the units).
-__host__ __device__ constexpr uint32_t scan_grid(uint32_t k) {
-    const uint32_t units = k * col_blocks(k), cap = k > 1024u ? k : 1024u;
-    return units < cap ? units : cap;
-}
+// Source-centric tasks per iteration the plan aims for: one per wave of the
+// largest scatter grid (2048 workgroups of kScWaves waves).
+constexpr uint32_t kScTaskTarget = 8192;
+// Smallest source-centric task, log2 of its work units.
+constexpr uint32_t kScShiftFloor = 6;
+// Source-centric scatter cuts a message into pieces of at most this many
+// edges (each with its own flag and value), so no task holds a long one.
+constexpr uint32_t kPiece = 256;
 // Workgroups that merge one split partition of q vertices.
 __host__ __device__ constexpr uint32_t merge_chunks(uint32_t q) { return q > kMergeSpan ? q / kMergeSpan : 1u; }
 
@@ -92,9 +75,8 @@ struct Ctrl {
     uint32_t pos;         // iterations run so far (index of the next plan)
     uint32_t max_it;      // a plan at this index pauses the run (done bit 2)
     uint32_t run_start;   // pos when the current run began
-    uint32_t n_scunits;   // source-centric scan units of the current iteration
     uint32_t n_pcpart;    // partitions scattered partition-centric in the current iteration
-    uint32_t pad[47];
+    uint32_t pad[48];
 };
 
 // Everything the kernels read or write, by value in each launch.
@@ -161,17 +143,19 @@ struct Dev {
     uint16_t* sc_ids;         // [E_pad]
     uint8_t* sc_w;            // [E_pad]
     uint32_t* sc_chunk;       // [E_pad/256]
-    uint2* sc_cnt;            // [k*k] column-major {mcnt, icnt} of SC bins
+    uint2* sc_cnt;            // [k*k] column-major {mcnt, icnt} of SC bins: reservation counters,
+                              // zero outside the stamped columns
     uint8_t* nz;              // [k*kw*64] column-major, column stride kw*64: SC bin[p][q] received ids
                               // (1 / 0; valid for partitions scattered source-centric)
     uint32_t* cact;           // [k] column q received SC ids in the iteration with this plan index
+                              // (0: its counters and marks are clear)
     uint64_t* pcmask;         // [kw] partitions scattered partition-centric this iteration
     uint64_t* scmask;         // [kw] partitions scattered source-centric this iteration
-    uint2* sc_tot;            // [k*col_blocks(k)] SC totals {msgs, ids} per (partition, scan unit)
-    uint32_t* sc_units;       // [k*col_blocks(k)] scan units: p | column block << 16 | bit 31 whole row
+    uint2* sc_tt;             // [max_sctask] {messages, ids} written by each SC task
+    uint32_t* sc_mo;          // [k*k] column-major: data index of SC bin[p][q]'s first message slot
     uint8_t* sc_sh;           // [k] log2 work units per source-centric task of each partition
     uint32_t* sc_t0;          // [k+1] exclusive prefix of SC tasks per partition
-    uint2* sc_tc;             // [max_sctask*k] per-(task, q) counts, then bases
+    uint2* sc_tc;             // [n_bldtask*k] build: per-(task, q) counts, then bases
     uint32_t* gat_ids;        // [n_gtask] ids combined per gather task
     uint32_t* gat_ran;        // [n_gtask + n_gsplit] 1 whole partition, 2 partial, 3 merge, 0 idle
     uint8_t* mode;            // [k]

@@ -24,6 +24,8 @@ hipError_t launch_scan_excl(const uint32_t* in, uint32_t* out, uint64_t n, uint3
 size_t scan_tmp_words(uint64_t n);
 hipError_t launch_part_M(const Dev& G, hipStream_t st);
 hipError_t launch_colmajor(const Dev& G, hipStream_t st);
+hipError_t launch_sc_cap(const Dev& G, hipStream_t st);
+hipError_t launch_sc_mo(const Dev& G, const uint32_t* sx, uint32_t base, hipStream_t st);
 hipError_t launch_colsrc(const Dev& G, hipStream_t st);
 hipError_t launch_cs_fill(const Dev& G, hipStream_t st);
 
@@ -47,11 +49,11 @@ struct BatchGrid {
     // per kernel: device block prefix over the runs (n + 1 entries) and its total
     const uint32_t* b_select;
     const uint32_t* b_sc;
-    const uint32_t* b_scan;
+    const uint32_t* b_clr;
     const uint32_t* b_pc;
     const uint32_t* b_gather;
     const uint32_t* b_merge;
-    uint32_t nb_select, nb_sc, nb_scan, nb_pc, nb_gather, nb_merge;
+    uint32_t nb_select, nb_sc, nb_clr, nb_pc, nb_gather, nb_merge;
     uint32_t k_max, q_max;
     bool rounds;                  // atomic-free combine (every run of a batch uses the same)
     bool learned = true;          // some run uses the learned selector (else its kernel is not launched)

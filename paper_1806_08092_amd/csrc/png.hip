@@ -175,6 +175,44 @@ hipError_t launch_colmajor(const Dev& G, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Source-centric message capacity of each bin. Source-centric scatter cuts
+// every message (a maximal run of one vertex's edges into q) into pieces of at
+// most kPiece edges, each with its own start flag and value, so a bin holds at
+// most runs + ids / kPiece of them. Overwrites cnt_m, whose last reader is the
+// column-major table.
+__global__ void k_sc_cap(Dev G) {
+    const uint64_t kk = (uint64_t)G.k * G.k;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < kk;
+         o += (uint64_t)gridDim.x * blockDim.x)
+        G.cnt_m[o] += G.cnt_i[o] / kPiece;
+}
+
+// Column-major data index of each source-centric bin's first message slot:
+// base plus the row-major exclusive prefix sx of the capacities.
+__global__ void k_sc_mo(Dev G, const uint32_t* __restrict__ sx, uint32_t base) {
+    const uint64_t kk = (uint64_t)G.k * G.k;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < kk;
+         o += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = o / G.k, p = o % G.k;
+        G.sc_mo[o] = base + sx[p * G.k + q];
+    }
+}
+
+static uint32_t kk_blocks(const Dev& G) {
+    const uint64_t want = ((uint64_t)G.k * G.k + 255) / 256;
+    return (uint32_t)(want < 4096 ? want : 4096);
+}
+
+hipError_t launch_sc_cap(const Dev& G, hipStream_t st) {
+    hipLaunchKernelGGL(k_sc_cap, dim3(kk_blocks(G)), dim3(256), 0, st, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_sc_mo(const Dev& G, const uint32_t* sx, uint32_t base, hipStream_t st) {
+    hipLaunchKernelGGL(k_sc_mo, dim3(kk_blocks(G)), dim3(256), 0, st, G, sx, base);
+    return hipGetLastError();
+}
+
 // Static level-2 tables of the active list, one wave per column q: the
 // source-partition bitmask of q's non-empty bins (colsrc) and the exclusive
 // prefix of the bins' 256-id pieces in source order (spre), which places any

@@ -10,31 +10,41 @@ namespace gpop {
 // ---------------------------------------------------------------------------
 // Source-centric scatter (Algorithm 2, scatter loop): for active v in
 // ascending order, for each neighbouring partition q in ascending order,
-// insert {val[v], ids of v's out-neighbours in q} into bin[p][q]; successive
-// messages to q land at consecutive insertion points (Sec. 3.1.2,
-// source-centric mode).
+// insert {val[v], ids of v's out-neighbours in q} into bin[p][q] (Sec. 3.1.2,
+// source-centric mode). A message is a maximal run of one vertex's edges into
+// one q (rows are sorted, so it is v's whole neighbourhood in q); its first id
+// carries the message-start flag and its value is written once.
 //
-// GPU form: the active vertices of partition p and their out-edges, taken in
-// (vertex, edge) order with one work unit per vertex and one per edge, are
-// cut into tasks of C consecutive units (a task may start or end inside a
-// vertex's row, so hubs spread over many tasks). C is chosen per iteration:
-// the configured size when the source-centric work is large, smaller (down
-// to 64 units) when it is light, so that there are enough tasks to fill the
-// chip. One wave owns one task. The insertion points are exclusive prefix
-// sums over that order:
+// GPU form, per iteration: the active vertices of partition p and their
+// out-edges, taken in (vertex, edge) order with one work unit per vertex and
+// one per edge, are cut into tasks of about C consecutive units (C chosen per
+// iteration so that the tasks fill the chip; a hub's row spreads over many
+// tasks). One wave owns one task. The task moves both ends of its range
+// forward to the next message boundary, so it owns exactly the messages that
+// start inside its range and no message is split between tasks. For each
+// message the wave reserves its slots with one 64-bit atomic add of
+// {1, length} on the bin's {message, id} counter: the old value gives the
+// message index and the first id slot at once, so every message is a
+// contiguous run of its bin and message indices follow id order, which is
+// what the gather's decoding needs. The order of messages inside a bin is the
+// order of the reservations; no combine depends on it (minima, and sums in
+// exact fixed point). The first reservation in a bin marks it nonempty and
+// stamps its column (the two levels of the active list); before the next
+// source-centric scatter one pass clears exactly the stamped columns' counters
+// and marks. There is no per-task count table and no offset scan, so the
+// metadata a task moves is proportional to the messages it writes.
+//
+// The static partition-node layout (N_i^p(q) in png_src and the static ids
+// that partition-centric scatter reuses every iteration, Algorithm 3) is
+// built once at preprocessing with every vertex active and a deterministic
+// order, in three passes over edge tasks:
 //   count pass  - each task counts ids and message starts per destination q;
 //   scan pass   - per (p, q), an exclusive scan over the tasks of p gives each
 //                 task its base in bin[p][q] (and the bin's totals);
 //   write pass  - each task replays its edges and writes at base + rank.
 // Inside a task, lanes that hold edges to the same q are grouped with a
 // ballot match on the bits of q; only the lowest lane of a group updates the
-// wave's LDS counter row, so no two lanes touch the same word and no atomics
-// are used. A message is a maximal run of a vertex's edges into one q; its
-// first edge carries the message-start flag and writes the value.
-//
-// The same kernels build the static partition-node layout once, with every
-// vertex active (BUILD): N_i^p(q) (png_src) and the static ids that
-// partition-centric scatter reuses every iteration (Algorithm 3).
+// wave's LDS counter row, so no two lanes touch the same word.
 // ---------------------------------------------------------------------------
 
 // Largest i in [0, n) with key(i) <= x, for a non-decreasing key with
@@ -61,63 +71,65 @@ __device__ __forceinline__ uint32_t task_owner(const uint32_t* t0, uint32_t k, u
     return wave_search(k, t, [&](uint32_t i) { return t0[i]; });
 }
 
-// Processes the work-unit range [f0, f1) of partition p with one wave. The
-// active vertices of p, in ascending order, are laid end to end as one unit
-// for the vertex followed by one per out-edge (BUILD: edges only), so a task
-// bounds both the edges and the vertices a wave walks.
-// WRITE = false: adds per-destination counts to (ci, cm).
-// WRITE = true : (ci, cm) hold the task's bases; writes the bins.
-template <int PROG, bool BUILD, bool WRITE>
-__device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __restrict__ state, uint32_t p,
-                             uint32_t f0, uint32_t f1, uint32_t nact,
-                             const uint16_t* __restrict__ alist, const uint32_t* __restrict__ fpre,
-                             uint32_t* ci, uint32_t* cm) {
+// Lane of the edge with flat index f among 64 vertices whose edge counts have
+// the inclusive prefix incl (the largest o with incl[o - 1] <= f).
+__device__ __forceinline__ uint32_t owner_lane(uint32_t incl, uint32_t f) {
+    uint32_t o = 0;
+#pragma unroll
+    for (uint32_t step = 32; step >= 1; step >>= 1) {
+        const uint32_t c = __shfl(incl, (int)(o + step - 1), 64);
+        if (c <= f) o += step;
+    }
+    return o;
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t x, uint32_t l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+}
+
+// ---------------------------------------------------------------- build
+
+// Build pass over the edge range [f0, f1) of partition p (every vertex of p,
+// edges in CSR order) with one wave.
+// WRITE = false: adds per-destination id and message counts to (ci, cm).
+// WRITE = true : (ci, cm) hold the task's bases; writes the static layout.
+template <bool WRITE>
+__device__ __forceinline__ void bld_wave_task(const Dev& G, uint32_t p, uint32_t f0, uint32_t f1,
+                                              uint32_t* ci, uint32_t* cm) {
     const uint32_t lane = lane_id();
     const uint32_t k = G.k, s = G.s, qmask = G.q - 1u;
     const uint32_t vbase = p << s;
+    const uint32_t nv = min(G.q, G.V - vbase);
     const uint32_t* __restrict__ off = gptr(G.off);
     const uint32_t* __restrict__ cols = gptr(G.cols);
     const uint32_t* __restrict__ rmoff = gptr(G.bin_moff) + (size_t)p * k;
     const uint32_t* __restrict__ rioff = gptr(G.bin_ioff) + (size_t)p * k;
     const uint32_t base_off = off[vbase];
-    constexpr uint32_t hdr = BUILD ? 0u : 1u;  // units of a vertex before its edges
-    auto pre = [&](uint32_t i) -> uint32_t {
-        return BUILD ? off[vbase + i] - base_off : fpre[i] + i;
-    };
-    // first active vertex whose units reach f0
-    const uint32_t lo = wave_search(nact, f0, pre);
-    for (uint32_t i0 = lo; i0 < nact; i0 += 64) {
-        const uint32_t ii = i0 + lane;
-        const bool vv = ii < nact;
-        const uint32_t vl = vv ? (BUILD ? ii : (uint32_t)alist[ii]) : 0u;
+    auto pre = [&](uint32_t i) -> uint32_t { return off[vbase + i] - base_off; };
+    // first vertex whose edges reach f0
+    const uint32_t lo = wave_search(nv, f0, pre);
+    for (uint32_t i0 = lo; i0 < nv; i0 += 64) {
+        const uint32_t vl = i0 + lane;
+        const bool vv = vl < nv;
         const uint32_t v = vbase + vl;
         const uint32_t rs = vv ? off[v] : 0u;
         const uint32_t deg = vv ? off[v + 1] - rs : 0u;
-        const uint32_t pr = vv ? pre(ii) : 0u;
-        const uint32_t clo = max(pr + hdr, f0);
-        const uint32_t chi = min(pr + hdr + deg, f1);
+        const uint32_t pr = vv ? rs - base_off : 0u;
+        const uint32_t clo = max(pr, f0);
+        const uint32_t chi = min(pr + deg, f1);
         const uint32_t cdeg = (vv && chi > clo) ? chi - clo : 0u;
-        const uint32_t cst = rs + (clo - pr - hdr);
-        uint32_t val = vl;
-        if constexpr (WRITE && !BUILD) {
-            if (cdeg) val = scatter_value<PROG>(G, state, v);
-        }
+        const uint32_t cst = rs + (clo - pr);
         const uint32_t incl = wave_incl_scan(cdeg);
         const uint32_t total = last_lane(incl);
         for (uint32_t g0 = 0; g0 < total; g0 += 64) {
             const uint32_t f = g0 + lane;
             const bool valid = f < total;
-            uint32_t o = 0;
-#pragma unroll
-            for (uint32_t step = 32; step >= 1; step >>= 1) {
-                const uint32_t c = __shfl(incl, (int)(o + step - 1), 64);
-                if (c <= f) o += step;
-            }
+            const uint32_t o = owner_lane(incl, f);
             const uint32_t o_rs = __shfl(rs, (int)o, 64);
             const uint32_t o_cst = __shfl(cst, (int)o, 64);
             const uint32_t o_incl = __shfl(incl, (int)o, 64);
             const uint32_t o_cdeg = __shfl(cdeg, (int)o, 64);
-            const uint32_t o_val = __shfl(val, (int)o, 64);
+            const uint32_t o_vl = __shfl(vl, (int)o, 64);
             const uint32_t e = o_cst + (f - (o_incl - o_cdeg));
             const uint32_t col = valid ? cols[e] : 0u;
             const uint32_t key = col >> s;
@@ -143,46 +155,31 @@ __device__ __forceinline__ void sc_wave_task(const Dev& G, const uint32_t* __res
             if (WRITE && valid) {
                 const uint32_t pos = rioff[key] + bi + rank_i;
                 const uint32_t midx = bm + m_le - 1u;
-                // positions must stay inside the static capacity of bin[p][key]
+                // positions must stay inside the capacity the count pass gave bin[p][key]
                 if (pos >= rioff[key + 1] || midx >= rmoff[key + 1] - rmoff[key]) {
                     gptr(G.ctrl)->bug = 1;
-                    continue;
-                }
-                const uint16_t idw = (uint16_t)((col & qmask) | (flag ? kFlag : 0u));
-                if constexpr (!BUILD) {
-                    if (flag) gptr(G.data)[rmoff[key] + midx] = o_val;
-                    gptr(G.sc_ids)[pos] = idw;
-                    if constexpr (is_weighted(PROG)) gptr(G.sc_w)[pos] = gptr(G.w)[e];
-                    if ((pos & (kChunk - 1)) == 0) gptr(G.sc_chunk)[pos / kChunk] = midx;
                 } else {
-                    if (flag) gptr(G.png_src)[rmoff[key] + midx] = (uint16_t)o_val;
-                    gptr(G.png_ids)[pos] = idw;
+                    if (flag) gptr(G.png_src)[rmoff[key] + midx] = (uint16_t)o_vl;
+                    gptr(G.png_ids)[pos] = (uint16_t)((col & qmask) | (flag ? kFlag : 0u));
                     if (gptr(G.w)) gptr(G.png_w)[pos] = gptr(G.w)[e];
                     if ((pos & (kChunk - 1)) == 0) gptr(G.png_chunk)[pos / kChunk] = midx;
                 }
             }
         }
-        if (i0 + 64 >= nact || pre(i0 + 64) >= f1) break;
+        if (i0 + 64 >= nv || pre(i0 + 64) >= f1) break;
     }
 }
 
-
-// Count pass (WRITE = false) and write pass (WRITE = true) of the task waves.
-template <int PROG, bool BUILD, bool WRITE>
-__device__ __forceinline__ void sc_pass_body(const Dev& G, const Params& P,
-                                             const uint32_t* __restrict__ state, uint32_t it,
-                                             uint32_t bid, uint32_t nblk) {
-    if (!BUILD && gptr(G.ctrl)->done) return;
-    const uint32_t cur = it & 1u;
+// Count pass (WRITE = false) and write pass (WRITE = true) of the build tasks.
+template <bool WRITE>
+__global__ __launch_bounds__(kScWaves * 64) void k_bld_pass(Dev G) {
     const uint32_t k = G.k;
-    const uint32_t ntask = BUILD ? G.n_bldtask : gptr(G.ctrl)->n_sctask;
-    const uint32_t* __restrict__ t0 = BUILD ? gptr(G.bld_t0) : gptr(G.sc_t0);
+    const uint32_t* __restrict__ t0 = gptr(G.bld_t0);
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     extern __shared__ uint32_t lds[];
     uint32_t* ci = lds + wave * 2 * k;
     uint32_t* cm = ci + k;
-    for (uint32_t t = bid * kScWaves + wave; t < ntask; t += nblk * kScWaves) {
-        const uint64_t t_beg = (!BUILD && P.probe) ? wall_clock64() : 0;
+    for (uint32_t t = blockIdx.x * kScWaves + wave; t < G.n_bldtask; t += gridDim.x * kScWaves) {
         uint2* __restrict__ tc = gptr(G.sc_tc) + (size_t)t * k;
         for (uint32_t j = lane; j < k; j += 64) {
             if constexpr (WRITE) {
@@ -195,99 +192,32 @@ __device__ __forceinline__ void sc_pass_body(const Dev& G, const Params& P,
             }
         }
         const uint32_t p = task_owner(t0, k, t);
-        const uint32_t jt = t - t0[p];
-        const uint32_t sh = BUILD ? G.sc_shift : gptr(G.sc_sh)[p];
-        const uint32_t vbase = p << G.s;
-        const uint32_t nv = min(G.q, G.V - vbase);
-        const uint32_t Ea = BUILD ? gptr(G.part_E)[p] : gptr(G.fEa[cur])[p];
-        const uint32_t nact = BUILD ? nv : gptr(G.fVa[cur])[p];
-        // the task's range of work units (BUILD: edges only)
-        const uint32_t f0 = jt << sh;
-        const uint32_t f1 = min(f0 + (1u << sh), BUILD ? Ea : Ea + nact);
-        sc_wave_task<PROG, BUILD, WRITE>(G, state, p, f0, f1, nact, gptr(G.flist[cur]) + vbase,
-                                         gptr(G.fpre[cur]) + vbase, ci, cm);
+        const uint32_t f0 = (t - t0[p]) << G.sc_shift;
+        const uint32_t f1 = min(f0 + (1u << G.sc_shift), gptr(G.part_E)[p]);
+        bld_wave_task<WRITE>(G, p, f0, f1, ci, cm);
         if constexpr (!WRITE) {
             for (uint32_t j = lane; j < k; j += 64) tc[j] = make_uint2(cm[j], ci[j]);
         }
-        if (!BUILD && P.probe && lane == 0)  // one wave's time, charged to its partition
-            atomicAdd(gptr(G.probe) + (WRITE ? k : 0) + p, (unsigned long long)(wall_clock64() - t_beg));
     }
 }
 
-template <int PROG, bool BUILD, bool WRITE>
-__global__ __launch_bounds__(kScWaves * 64) void k_sc_pass(Dev G, Params P,
-                                                           const uint32_t* __restrict__ state,
-                                                           uint32_t it) {
-    sc_pass_body<PROG, BUILD, WRITE>(G, P, state, it, blockIdx.x, gridDim.x);
-}
-
-// The iteration index: the plan has already advanced pos, except in a probe.
-__device__ __forceinline__ uint32_t scatter_it(const Inst& I) { return gptr(I.G.ctrl)->pos - (I.P.probe ? 0u : 1u); }
-
-template <int PROG, bool WRITE>
-__global__ __launch_bounds__(kScWaves * 64) void kb_sc_pass(const Inst* __restrict__ tab,
-                                                            const uint32_t* __restrict__ boff,
-                                                            uint32_t n) {
-    const uint32_t i = batch_find(boff, n, blockIdx.x);
-    const Inst& I = tab[i];
-    sc_pass_body<PROG, false, WRITE>(I.G, I.P, gptr(I.state), scatter_it(I), blockIdx.x - boff[i],
-                                     boff[i + 1] - boff[i]);
-}
-
-// Scan pass: per source partition p and destination q, exclusive scan of the
-// task counts over the tasks of p (in place), giving each task its base in
-// bin[p][q]; the totals are the bin's message and id counts this iteration.
-// One call scans destinations [qa, qb): 16 strips of tasks x 64 destinations
-// per round; strip sums are scanned in LDS, then each strip rewrites its
-// counts as bases. Loads go in batches of 8 so that a strip of a partition
-// with many tasks keeps several in flight.
-template <bool BUILD>
-__device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t qa, uint32_t qb,
-                                             uint32_t tot_slot) {
-    const uint32_t k = G.k;
-    const uint32_t* __restrict__ t0 = BUILD ? gptr(G.bld_t0) : gptr(G.sc_t0);
+// Scan pass of the build: per source partition p (one workgroup) and each
+// destination q, exclusive scan of the task counts over the tasks of p (in
+// place), giving each task its base in bin[p][q]; the totals are the bin's
+// message and id counts. 16 strips of tasks x 64 destinations per round:
+// strip sums are scanned in LDS, then each strip rewrites its counts as
+// bases. Loads go in batches of 8 so that a strip keeps several in flight.
+__global__ __launch_bounds__(1024) void k_bld_scan(Dev G) {
+    const uint32_t p = blockIdx.x, k = G.k;
+    const uint32_t* __restrict__ t0 = gptr(G.bld_t0);
     const uint32_t tb = t0[p], n = t0[p + 1] - tb;
-    // level 1 of the active list: a column that receives source-centric ids
-    // is stamped with the plan index of this iteration (every writer stores
-    // the same value)
-    const uint32_t stamp = BUILD ? 0u : gptr(G.ctrl)->pos;
     const uint32_t tid = threadIdx.x, ql = tid & 63u, strip = tid >> 6;
     __shared__ uint32_t s_m[16][64], s_i[16][64];
-    __shared__ uint64_t s_tot[2][16];
     const uint32_t per = (n + 15u) / 16u;
     const uint32_t a = min(strip * per, n), b = min(a + per, n);
-    uint64_t my_tm = 0, my_ti = 0;
-    // few tasks: one thread per destination walks all of them (no strips)
-    const bool serial = !BUILD && n <= kScanRows;
-    for (uint32_t q = qa + tid; serial && q < qb; q += blockDim.x) {
-        uint2* __restrict__ col = gptr(G.sc_tc) + (size_t)tb * k + q;
-        uint32_t rm = 0, ri = 0, t = 0;
-        for (; t + 8u <= n; t += 8u) {
-            uint2 x[8];
-#pragma unroll
-            for (uint32_t j = 0; j < 8; ++j) x[j] = col[(size_t)(t + j) * k];
-#pragma unroll
-            for (uint32_t j = 0; j < 8; ++j) {
-                col[(size_t)(t + j) * k] = make_uint2(rm, ri);
-                rm += x[j].x;
-                ri += x[j].y;
-            }
-        }
-        for (; t < n; ++t) {
-            const uint2 x = col[(size_t)t * k];
-            col[(size_t)t * k] = make_uint2(rm, ri);
-            rm += x.x;
-            ri += x.y;
-        }
-        gptr(G.sc_cnt)[(size_t)q * k + p] = make_uint2(rm, ri);
-        gptr(G.nz)[(size_t)q * G.kw * 64u + p] = ri != 0u;
-        if (ri) gptr(G.cact)[q] = stamp;
-        my_tm += rm;
-        my_ti += ri;
-    }
-    for (uint32_t q0 = qa; !serial && q0 < qb; q0 += 64) {
+    for (uint32_t q0 = 0; q0 < k; q0 += 64) {
         const uint32_t q = q0 + ql;
-        const bool qin = q < qb;
+        const bool qin = q < k;
         uint2* __restrict__ col = gptr(G.sc_tc) + (size_t)tb * k + q;
         uint32_t sm = 0, si = 0;
         if (qin) {
@@ -341,93 +271,284 @@ __device__ __forceinline__ void sc_scan_body(const Dev& G, uint32_t p, uint32_t 
                 ri += x.y;
             }
             if (strip == 0) {
-                if constexpr (BUILD) {
-                    gptr(G.cnt_m)[(size_t)p * k + q] = tm;
-                    gptr(G.cnt_i)[(size_t)p * k + q] = ti;
-                } else {
-                    gptr(G.sc_cnt)[(size_t)q * k + p] = make_uint2(tm, ti);
-                    gptr(G.nz)[(size_t)q * G.kw * 64u + p] = ti != 0u;
-                    if (ti) gptr(G.cact)[q] = stamp;
-                    my_tm += tm;
-                    my_ti += ti;
-                }
+                gptr(G.cnt_m)[(size_t)p * k + q] = tm;
+                gptr(G.cnt_i)[(size_t)p * k + q] = ti;
             }
         }
-    }
-    if constexpr (!BUILD) {
-        my_tm = wave_sum_u64(my_tm);
-        my_ti = wave_sum_u64(my_ti);
-        if (ql == 0) {
-            s_tot[0][strip] = my_tm;
-            s_tot[1][strip] = my_ti;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint64_t x = 0, y = 0;
-            for (int w = 0; w < 16; ++w) {
-                x += s_tot[0][w];
-                y += s_tot[1][w];
-            }
-            gptr(G.sc_tot)[tot_slot] = make_uint2((uint32_t)x, (uint32_t)y);
-        }
-        __syncthreads();  // s_tot and the strip arrays are reused by the next unit
-    }
-}
-
-template <bool BUILD>
-__global__ __launch_bounds__(1024) void k_sc_scan(Dev G) {
-    sc_scan_body<BUILD>(G, blockIdx.x, 0, G.k, 0);
-}
-
-// The plan lists the scan units of the iteration (source-centric partitions,
-// those with many tasks once per block of 64 destinations); the workgroups
-// stride over them.
-__global__ __launch_bounds__(1024) void kb_sc_scan(const Inst* __restrict__ tab,
-                                                   const uint32_t* __restrict__ boff, uint32_t n) {
-    const uint32_t i = batch_find(boff, n, blockIdx.x);
-    const Dev& G = tab[i].G;
-    if (gptr(G.ctrl)->done) return;
-    const uint32_t nu = gptr(G.ctrl)->n_scunits, nblk = boff[i + 1] - boff[i];
-    const uint32_t ncb = col_blocks(G.k);
-    for (uint32_t u = blockIdx.x - boff[i]; u < nu; u += nblk) {
-        const uint32_t e = gptr(G.sc_units)[u];
-        const uint32_t p = e & 0xFFFFu, cb = (e >> 16) & 0x7FFFu;
-        const bool whole = (e >> 31) != 0u;
-        const uint32_t qa = whole ? 0u : cb * 64u, qb = whole ? G.k : min(G.k, qa + 64u);
-        sc_scan_body<false>(G, p, qa, qb, p * ncb + cb);
     }
 }
 
 size_t sc_lds_bytes(uint32_t k) { return (size_t)kScWaves * 2 * k * 4; }
 
-template <int PROG, bool BUILD, bool WRITE>
-static hipError_t launch_pass(const Dev& G, const Params& P, const uint32_t* state, uint32_t it,
-                              uint32_t max_tasks, hipStream_t st) {
-    if (max_tasks == 0) return hipSuccess;
-    const size_t lds = sc_lds_bytes(G.k);
-    auto fn = k_sc_pass<PROG, BUILD, WRITE>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    const uint32_t blocks = std::min<uint32_t>((max_tasks + kScWaves - 1) / kScWaves, 2048u);
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kScWaves * 64), lds, st, G, P, state, it);
-    return hipGetLastError();
-}
-
-template <bool BUILD>
-static hipError_t launch_scan_pass(const Dev& G, hipStream_t st) {
-    hipLaunchKernelGGL(k_sc_scan<BUILD>, dim3(G.k), dim3(1024), 0, st, G);
-    return hipGetLastError();
-}
-
 hipError_t launch_sc_build(const Dev& G, int fill, hipStream_t st) {
-    Params P{};
-    if (!fill) {
-        hipError_t e = launch_pass<P_BFS, true, false>(G, P, nullptr, 0, G.n_bldtask, st);
+    const size_t lds = sc_lds_bytes(G.k);
+    const uint32_t blocks = std::min<uint32_t>((G.n_bldtask + kScWaves - 1) / kScWaves, 2048u);
+    hipError_t e = hipSuccess;
+    if (fill) {
+        if (blocks == 0) return hipSuccess;
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bld_pass<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        return launch_scan_pass<true>(G, st);
+        hipLaunchKernelGGL(k_bld_pass<true>, dim3(blocks), dim3(kScWaves * 64), lds, st, G);
+        return hipGetLastError();
     }
-    return launch_pass<P_BFS, true, true>(G, P, nullptr, 0, G.n_bldtask, st);
+    if (blocks) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bld_pass<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bld_pass<false>, dim3(blocks), dim3(kScWaves * 64), lds, st, G);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // the scan also writes the zero counts of bins without edges
+    hipLaunchKernelGGL(k_bld_scan, dim3(G.k), dim3(1024), 0, st, G);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ iterations
+
+// First edge of the run (the stretch of a sorted row into one partition) that
+// edge e of the row starting at rs belongs to; key = cols[e] >> s.
+// Wave-uniform.
+__device__ __forceinline__ uint32_t run_start(const uint32_t* __restrict__ cols, uint32_t rs, uint32_t e,
+                                              uint32_t key, uint32_t s) {
+    if ((cols[rs] >> s) == key) return rs;
+    // the last edge before the run: largest j with cols[rs + j] >> s <= key - 1
+    const uint32_t j = wave_search(e - rs + 1u, key - 1u, [&](uint32_t i) { return cols[rs + i] >> s; });
+    return rs + j + 1u;
+}
+
+// First piece boundary at or after unit x of a partition's source-centric
+// units (end: their number). A piece is at most kPiece edges of one run,
+// starting at the run's start or kPiece, 2 kPiece, ... edges after it. The
+// boundary is x itself if x is a vertex's unit or a piece's first edge, else
+// the end of the piece x falls in. r_out: the run start of the boundary's edge
+// (when the boundary is an edge). Wave-uniform.
+__device__ __forceinline__ uint32_t sc_cut(uint32_t x, uint32_t end, uint32_t nact, uint32_t vbase,
+                                           uint32_t s, const uint32_t* __restrict__ off,
+                                           const uint32_t* __restrict__ cols,
+                                           const uint16_t* __restrict__ alist,
+                                           const uint32_t* __restrict__ fpre, uint32_t& r_out) {
+    r_out = 0;
+    if (x >= end) return end;
+    const uint32_t i = wave_search(nact, x, [&](uint32_t j) { return fpre[j] + j; });
+    const uint32_t u = fpre[i] + i;  // the vertex's own unit; its edges follow
+    if (x == u) return x;
+    const uint32_t v = vbase + alist[i];
+    const uint32_t rs = off[v], re = off[v + 1];
+    const uint32_t e = rs + (x - u - 1u);
+    const uint32_t key = cols[e] >> s;
+    const uint32_t r0 = e == rs ? rs : run_start(cols, rs, e, key, s);
+    r_out = r0;
+    if (((e - r0) & (kPiece - 1u)) == 0) return x;
+    // the piece ends at the next multiple of kPiece after its run start, or
+    // earlier where the run ends
+    const uint32_t lim = min(r0 + ((e - r0) | (kPiece - 1u)) + 1u, re);
+    uint32_t y = e + 1u;
+    for (; y < lim; y += 64u) {
+        const uint32_t yy = y + lane_id();
+        const uint64_t stop = ballot(yy >= lim || (cols[yy] >> s) != key);
+        if (stop) {
+            y += (uint32_t)__builtin_ctzll(stop);
+            break;
+        }
+    }
+    y = min(y, lim);
+    if (y < re) r_out = (cols[y] >> s) == key ? r0 : y;
+    return x + (y - e);
+}
+
+// One source-centric task: the units [f0, f1) of partition p moved to piece
+// boundaries (see above). n_msg / n_ids count the messages (runs) started and
+// the ids written.
+template <int PROG>
+__device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict__ state, uint32_t p,
+                                        uint32_t f0, uint32_t f1, uint32_t end, uint32_t nact,
+                                        uint32_t stamp, const uint16_t* __restrict__ alist,
+                                        const uint32_t* __restrict__ fpre, uint32_t& n_msg,
+                                        uint32_t& n_ids) {
+    const uint32_t lane = lane_id();
+    const uint32_t k = G.k, s = G.s, qmask = G.q - 1u;
+    const uint32_t vbase = p << s;
+    const uint32_t* __restrict__ off = gptr(G.off);
+    const uint32_t* __restrict__ cols = gptr(G.cols);
+    const uint32_t* __restrict__ rmoff = gptr(G.bin_moff) + (size_t)p * k;
+    const uint32_t* __restrict__ rioff = gptr(G.bin_ioff) + (size_t)p * k;
+    const uint32_t* __restrict__ smo = gptr(G.sc_mo);
+    unsigned long long* __restrict__ cnt = reinterpret_cast<unsigned long long*>(gptr(G.sc_cnt));
+    uint32_t r_first, r_unused;
+    const uint32_t b0 = sc_cut(f0, end, nact, vbase, s, off, cols, alist, fpre, r_first);
+    const uint32_t b1 = sc_cut(f1, end, nact, vbase, s, off, cols, alist, fpre, r_unused);
+    if (b0 >= b1) return;
+    auto pre = [&](uint32_t i) -> uint32_t { return fpre[i] + i; };
+    const uint64_t below_eq = lane == 63u ? ~0ull : (2ull << lane) - 1ull;  // lanes <= this one
+    // first active vertex whose units reach b0
+    const uint32_t lo = wave_search(nact, b0, pre);
+    for (uint32_t i0 = lo; i0 < nact; i0 += 64) {
+        const uint32_t ii = i0 + lane;
+        const bool vv = ii < nact;
+        const uint32_t v = vbase + (vv ? (uint32_t)alist[ii] : 0u);
+        const uint32_t rs = vv ? off[v] : 0u;
+        const uint32_t deg = vv ? off[v + 1] - rs : 0u;
+        const uint32_t pr = vv ? pre(ii) : 0u;
+        const uint32_t clo = max(pr + 1u, b0);
+        const uint32_t chi = min(pr + 1u + deg, b1);
+        const uint32_t cdeg = (vv && chi > clo) ? chi - clo : 0u;
+        const uint32_t cst = rs + (clo - pr - 1u);
+        const uint32_t val = cdeg ? scatter_value<PROG>(G, state, v) : 0u;
+        const uint32_t incl = wave_incl_scan(cdeg);
+        const uint32_t total = last_lane(incl);
+        // carried from the previous 64 edges: the open piece (first id slot,
+        // flat index of its first edge, message index) and the open run's
+        // first edge (the task's first edge may lie inside a run)
+        uint32_t c_slot = 0, c_f = 0, c_m = 0, c_rs = i0 == lo ? r_first : 0u;
+        for (uint32_t g0 = 0; g0 < total; g0 += 64) {
+            const uint32_t f = g0 + lane;
+            const bool valid = f < total;
+            const uint32_t o = owner_lane(incl, f);
+            const uint32_t o_rs = __shfl(rs, (int)o, 64);
+            const uint32_t o_cst = __shfl(cst, (int)o, 64);
+            const uint32_t o_incl = __shfl(incl, (int)o, 64);
+            const uint32_t o_cdeg = __shfl(cdeg, (int)o, 64);
+            const uint32_t o_val = __shfl(val, (int)o, 64);
+            const uint32_t e = o_cst + (f - (o_incl - o_cdeg));
+            const uint32_t col = valid ? cols[e] : 0u;
+            const uint32_t key = col >> s;
+            // run starts, then piece starts: kPiece-aligned offsets from the run start
+            const bool rflag = valid && (e == o_rs || (cols[e - 1] >> s) != key);
+            const uint64_t rfm = ballot(rflag);
+            const uint64_t rmine = rfm & below_eq;
+            const uint32_t r_e = __shfl(e, (int)(rmine ? 63u - (uint32_t)__builtin_clzll(rmine) : 0u), 64);
+            const uint32_t r0 = rmine ? r_e : c_rs;
+            const bool flag = valid && ((e - r0) & (kPiece - 1u)) == 0;
+            const uint64_t fm = ballot(flag);
+            n_msg += popc64(rfm);
+            n_ids += popc64(ballot(valid));
+            if (rfm) c_rs = readlane_u32(e, 63u - (uint32_t)__builtin_clzll(rfm));
+            // A piece that starts here ends at the next start in these 64
+            // edges; the last one may run on, to the end of its vertex's edges
+            // in the task, the end of its run or kPiece edges.
+            const uint32_t lf = fm ? 63u - (uint32_t)__builtin_clzll(fm) : 0u;
+            uint32_t len_last = 0;
+            if (fm) {
+                const uint32_t fl = g0 + lf;
+                const uint32_t el = readlane_u32(e, lf), kl = readlane_u32(key, lf);
+                const uint32_t lim = min(el + kPiece, el + (readlane_u32(o_incl, lf) - fl));
+                uint32_t y = el + (g0 + 64u - fl);  // its first edge after these 64
+                for (; y < lim; y += 64u) {
+                    const uint32_t yy = y + lane;
+                    const uint64_t stop = ballot(yy >= lim || (cols[yy] >> s) != kl);
+                    if (stop) {
+                        y += (uint32_t)__builtin_ctzll(stop);
+                        break;
+                    }
+                }
+                len_last = min(y, lim) - el;
+            }
+            const uint64_t after = fm & ~below_eq;
+            unsigned long long old = 0;
+            if (flag) {
+                const uint32_t len = after ? (uint32_t)__builtin_ctzll(after) - lane : len_last;
+                old = atomicAdd(cnt + (size_t)key * k + p, 1ull | ((unsigned long long)len << 32));
+                if (old == 0ull) {  // first piece of the bin this iteration
+                    gptr(G.nz)[(size_t)key * G.kw * 64u + p] = 1;
+                    gptr(G.cact)[key] = stamp;
+                }
+            }
+            const uint32_t o_slot = (uint32_t)(old >> 32), o_m = (uint32_t)old;
+            // each edge belongs to the latest piece start at or below its lane
+            const uint64_t mine = fm & below_eq;
+            const uint32_t own = mine ? 63u - (uint32_t)__builtin_clzll(mine) : 0u;
+            const uint32_t s_slot = __shfl(o_slot, (int)own, 64), s_m = __shfl(o_m, (int)own, 64);
+            const uint32_t slot = mine ? s_slot + (lane - own) : c_slot + (f - c_f);
+            const uint32_t midx = mine ? s_m : c_m;
+            if (fm) {
+                c_slot = readlane_u32(o_slot, lf);
+                c_m = readlane_u32(o_m, lf);
+                c_f = g0 + lf;
+            }
+            if (valid) {
+                const uint32_t ib = rioff[key], icap = rioff[key + 1] - ib;
+                const uint32_t mcap = rmoff[key + 1] - rmoff[key] + icap / kPiece;
+                // the reservation must stay inside the capacity of bin[p][key]
+                if (slot >= icap || midx >= mcap) {
+                    gptr(G.ctrl)->bug = 1;
+                } else {
+                    const uint32_t pos = ib + slot;
+                    if (flag) gptr(G.data)[smo[(size_t)key * k + p] + midx] = o_val;
+                    gptr(G.sc_ids)[pos] = (uint16_t)((col & qmask) | (flag ? kFlag : 0u));
+                    if constexpr (is_weighted(PROG)) gptr(G.sc_w)[pos] = gptr(G.w)[e];
+                    if ((pos & (kChunk - 1)) == 0) gptr(G.sc_chunk)[pos / kChunk] = midx;
+                }
+            }
+        }
+        if (i0 + 64 >= nact || pre(i0 + 64) >= b1) break;
+    }
+}
+
+// The iteration index: the plan has already advanced pos, except in a probe.
+__device__ __forceinline__ uint32_t scatter_it(const Inst& I) { return gptr(I.G.ctrl)->pos - (I.P.probe ? 0u : 1u); }
+
+template <int PROG>
+__global__ __launch_bounds__(kScWaves * 64) void kb_sc_scatter(const Inst* __restrict__ tab,
+                                                               const uint32_t* __restrict__ boff,
+                                                               uint32_t n) {
+    const uint32_t bi = batch_find(boff, n, blockIdx.x);
+    const Inst& I = tab[bi];
+    const Dev& G = I.G;
+    const Ctrl* C = gptr(G.ctrl);
+    if (C->done) return;
+    const uint32_t it = scatter_it(I), cur = it & 1u;
+    // the gather of this iteration looks for the stamp; a probe's (never
+    // gathered) must still be nonzero, so that the next clear finds it
+    const uint32_t stamp = I.P.probe ? C->pos | 0x80000000u : C->pos;
+    const uint32_t ntask = C->n_sctask, nblk = boff[bi + 1] - boff[bi];
+    const uint32_t* __restrict__ t0 = gptr(G.sc_t0);
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    for (uint32_t t = (blockIdx.x - boff[bi]) * kScWaves + wave; t < ntask; t += nblk * kScWaves) {
+        const uint64_t t_beg = I.P.probe ? wall_clock64() : 0;
+        const uint32_t p = task_owner(t0, G.k, t);
+        const uint32_t sh = gptr(G.sc_sh)[p];
+        const uint32_t nact = gptr(G.fVa[cur])[p];
+        const uint32_t end = gptr(G.fEa[cur])[p] + nact;
+        const uint32_t f0 = (t - t0[p]) << sh;
+        const uint32_t f1 = min(f0 + (1u << sh), end);
+        const uint32_t vbase = p << G.s;
+        uint32_t n_msg = 0, n_ids = 0;
+        sc_task<PROG>(G, gptr(I.state), p, f0, f1, end, nact, stamp, gptr(G.flist[cur]) + vbase,
+                      gptr(G.fpre[cur]) + vbase, n_msg, n_ids);
+        if (lane == 0) {
+            gptr(G.sc_tt)[t] = make_uint2(n_msg, n_ids);
+            if (I.P.probe)  // one wave's time, charged to its partition
+                atomicAdd(gptr(G.probe) + G.k + p, (unsigned long long)(wall_clock64() - t_beg));
+        }
+    }
+}
+
+// Before a source-centric scatter: the counters and nonempty marks of every
+// column an earlier one stamped go back to zero, then the stamps. One wave
+// per column; an unstamped column costs one load.
+__global__ __launch_bounds__(256) void kb_sc_clear(const Inst* __restrict__ tab,
+                                                   const uint32_t* __restrict__ boff, uint32_t n) {
+    const uint32_t bi = batch_find(boff, n, blockIdx.x);
+    const Dev& G = tab[bi].G;
+    if (gptr(G.ctrl)->done) return;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t nblk = boff[bi + 1] - boff[bi];
+    const uint32_t nw = G.kw * 8u;  // 8-partition words of a column's marks
+    for (uint32_t q = (blockIdx.x - boff[bi]) * 4u + wave; q < G.k; q += nblk * 4u) {
+        if (gptr(G.cact)[q] == 0u) continue;
+        uint64_t* __restrict__ mw = reinterpret_cast<uint64_t*>(gptr(G.nz) + (size_t)q * G.kw * 64u);
+        uint2* __restrict__ c = gptr(G.sc_cnt) + (size_t)q * G.k;
+        for (uint32_t j = lane; j < nw; j += 64u) {
+            const uint64_t m = mw[j];
+            if (!m) continue;
+            mw[j] = 0;
+            for (uint32_t b = 0; b < 8u; ++b)
+                if ((m >> (8u * b)) & 1u) c[8u * j + b] = make_uint2(0u, 0u);
+        }
+        if (lane == 0) gptr(G.cact)[q] = 0u;
+    }
 }
 
 
@@ -523,11 +644,9 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
     __shared__ uint64_t red[7][16];
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u, B = blockDim.x;
     uint64_t v[7] = {0, 0, 0, 0, 0, 0, 0};  // sc msgs, sc ids, ids, whole, partial, merged, bins
-    const uint32_t ncb = col_blocks(G.k);
     const uint32_t nt = G.n_gtask + G.n_gsplit;
     // Loads go out in batches before the sums that use them: the first four
-    // task marks per thread, then every partition's mode and counts (the
-    // second count block only where a partition had more than one).
+    // task marks per thread, then the source-centric task records.
     constexpr uint32_t kTB = 4;
     auto task_batch = [&](uint32_t t0, uint32_t* ids, uint32_t* ran) {
 #pragma unroll
@@ -549,19 +668,12 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
     };
     uint32_t ids0[kTB], ran0[kTB];
     task_batch(tid, ids0, ran0);
-    for (uint32_t p = tid; p < G.k; p += B) {
-        const uint32_t md = gptr(G.mode)[p], ta = gptr(G.sc_t0)[p], tb = gptr(G.sc_t0)[p + 1];
-        const uint2 t0 = gptr(G.sc_tot)[(size_t)p * ncb];
-        if (md == GPOP_MODE_SC) {
-            v[0] += t0.x;
-            v[1] += t0.y;
-            if (tb - ta > kScanRows)
-                for (uint32_t j = 1; j < ncb; ++j) {
-                    const uint2 t = gptr(G.sc_tot)[(size_t)p * ncb + j];
-                    v[0] += t.x;
-                    v[1] += t.y;
-                }
-        }
+    // source-centric messages and ids: one record per task of that iteration
+    const uint32_t nsct = gptr(G.ctrl)->n_sctask;
+    for (uint32_t t = tid; t < nsct; t += B) {
+        const uint2 c = gptr(G.sc_tt)[t];
+        v[0] += c.x;
+        v[1] += c.y;
     }
     task_sum(ids0, ran0);
     for (uint32_t t0 = tid + kTB * B; t0 < nt; t0 += kTB * B) {
@@ -686,9 +798,8 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
             gptr(G.scmask)[(p0 >> 6) + wave] = scw;
         }
     }
-    // task size of this iteration: about sc_task_target tasks, between
-    // 2^sc_shift_floor(k) and 2^sc_shift work units (larger for a partition
-    // that would otherwise have more than kMaxPartTasks)
+    // task size of this iteration: about kScTaskTarget tasks, between
+    // 2^kScShiftFloor and 2^sc_shift work units
     __shared__ uint64_t s_sc_units[kPlanW];
     {
         const uint64_t w = wave_sum_u64(sva + sea);
@@ -699,56 +810,33 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     {
         uint64_t tot = 0;
         for (uint32_t w = 0; w < kPlanW; ++w) tot += s_sc_units[w];
-        const uint32_t hi = G.sc_shift, lo = min(sc_shift_floor(G.k), hi);
-        const uint64_t per = tot / sc_task_target(G.k);
+        const uint32_t hi = G.sc_shift, lo = min(kScShiftFloor, hi);
+        const uint64_t per = tot / kScTaskTarget;
         uint32_t l = 0;
         while (l < 40u && (2ull << l) <= per) ++l;  // floor(log2 per) for per >= 1
         sh = per == 0 ? lo : max(lo, min(hi, l));
     }
-    // pass 2: tasks and scan units of the source-centric partitions,
-    // exclusive scans in partition order
+    // pass 2: tasks of the source-centric partitions, an exclusive scan in
+    // partition order
     uint32_t tcarry = 0;  // source-centric tasks of the partitions before this block
-    uint32_t ucarry = 0;  // scan units of the partitions before this block
-    __shared__ uint32_t s_u[kPlanW];
-    const uint32_t ncb = col_blocks(G.k);
     for (uint32_t p0 = 0; p0 < G.k; p0 += kPlanT) {
         const uint32_t p = p0 + tid;
         const uint32_t units = p < G.k ? s_units[p] : 0xFFFFFFFFu;
-        const bool in_sc = units != 0xFFFFFFFFu;
         uint32_t ntask = 0;
-        if (in_sc) {
-            uint32_t shp = sh;  // at most kMaxPartTasks tasks per partition
-            while ((((uint64_t)units + (1ull << shp) - 1ull) >> shp) > kMaxPartTasks) ++shp;
-            ntask = (uint32_t)(((uint64_t)units + (1ull << shp) - 1ull) >> shp);
-            gptr(G.sc_sh)[p] = (uint8_t)shp;
+        if (units != 0xFFFFFFFFu) {
+            ntask = (uint32_t)(((uint64_t)units + (1ull << sh) - 1ull) >> sh);
+            gptr(G.sc_sh)[p] = (uint8_t)sh;
         }
-        // (a partition without active out-edges still gets a unit: the scan
-        // writes its zero bin counts)
-        const uint32_t nunit = !in_sc ? 0u : (ntask > kScanRows ? ncb : 1u);
         const uint32_t incl = wave_incl_scan(ntask);
-        const uint32_t uincl = wave_incl_scan(nunit);
-        if (lane == 63) {
-            s_w[wave] = incl;
-            s_u[wave] = uincl;
-        }
+        if (lane == 63) s_w[wave] = incl;
         __syncthreads();
-        uint32_t before = 0, tot = 0, ubefore = 0, utot = 0;
+        uint32_t before = 0, tot = 0;
         for (uint32_t w = 0; w < kPlanW; ++w) {
-            if (w < wave) {
-                before += s_w[w];
-                ubefore += s_u[w];
-            }
+            if (w < wave) before += s_w[w];
             tot += s_w[w];
-            utot += s_u[w];
         }
-        if (p < G.k) {
-            gptr(G.sc_t0)[p] = tcarry + before + incl - ntask;
-            const uint32_t u0 = ucarry + ubefore + uincl - nunit;
-            for (uint32_t j = 0; j < nunit; ++j)
-                gptr(G.sc_units)[u0 + j] = p | (j << 16) | (nunit == 1u ? 0x80000000u : 0u);
-        }
+        if (p < G.k) gptr(G.sc_t0)[p] = tcarry + before + incl - ntask;
         tcarry += tot;
-        ucarry += utot;
         __syncthreads();
     }
     va = wave_sum_u64(va);
@@ -785,7 +873,6 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         }
         gptr(G.sc_t0)[G.k] = tcarry;
         C->n_sctask = tcarry;
-        C->n_scunits = ucarry;
         C->n_pcpart = (uint32_t)t[3];
         // gather reads the partition-centric ids from the column streams
         // when their partitions hold at least half of the edges (a stream
@@ -842,12 +929,6 @@ __global__ __launch_bounds__(kPlanT) void k_plan1(Dev G, const Params* __restric
 
 template <int PROG>
 static hipError_t prep_batch_scatter_p(const BatchGrid& B) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_sc_pass<PROG, false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sc_lds_bytes(B.k_max));
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_sc_pass<PROG, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sc_lds_bytes(B.k_max));
-    if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kb_pc<PROG>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(B.q_max * 4));
 }
@@ -855,11 +936,8 @@ static hipError_t prep_batch_scatter_p(const BatchGrid& B) {
 template <int PROG>
 static hipError_t launch_batch_sc_p(const BatchGrid& B, hipStream_t st) {
     if (B.nb_sc) {
-        hipLaunchKernelGGL((kb_sc_pass<PROG, false>), dim3(B.nb_sc), dim3(kScWaves * 64), sc_lds_bytes(B.k_max),
-                           st, B.tab, B.b_sc, B.n);
-        hipLaunchKernelGGL(kb_sc_scan, dim3(B.nb_scan), dim3(1024), 0, st, B.tab, B.b_scan, B.n);
-        hipLaunchKernelGGL((kb_sc_pass<PROG, true>), dim3(B.nb_sc), dim3(kScWaves * 64), sc_lds_bytes(B.k_max),
-                           st, B.tab, B.b_sc, B.n);
+        hipLaunchKernelGGL(kb_sc_clear, dim3(B.nb_clr), dim3(256), 0, st, B.tab, B.b_clr, B.n);
+        hipLaunchKernelGGL(kb_sc_scatter<PROG>, dim3(B.nb_sc), dim3(kScWaves * 64), 0, st, B.tab, B.b_sc, B.n);
     }
     return hipGetLastError();
 }
