@@ -15,8 +15,12 @@
  * Network: x (12 features, f32) -> standardise ((x - mean) * inv_std)
  *   -> h1 = relu(W1 x + b1) (64) -> h2 = relu(W2 h1 + b2) (64)
  *   -> z = w3 . h2 + b3; PC iff z >= 0.
- * Weights are bf16 (round to nearest even from f32 masters); all arithmetic
- * is f32. Parameters are stored in this order (row-major, output-major):
+ * Weights are bf16 (round to nearest even from f32 masters). Training and
+ * gpop_mlp_forward compute in f32; the per-iteration mode selection evaluates
+ * the two hidden layers on the matrix cores, with the input of each (the
+ * standardised features, then the first hidden layer after its ReLU) rounded
+ * to bf16 (nearest even) and f32 accumulation. Parameters are stored in this
+ * order (row-major, output-major):
  *   W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3   (5057 values).
  *
  * Features of partition p (vertices q_p, out-edges E^p, all-active messages

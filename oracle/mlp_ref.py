@@ -10,7 +10,10 @@ checking only:
   Sec. 3.2);
 * the network 12 -> 64 -> 64 -> 1 with ReLU, evaluated in FP64 on weights
   rounded to bf16 (round to nearest even) and on FP32 standardisation
-  constants;
+  constants; and as the per-iteration selection evaluates it, with the input
+  of each hidden layer rounded to bf16 (forward_infer), and which samples
+  hold a value so close to a bf16 rounding midpoint that an FP32 difference
+  could round it the other way (infer_ambiguous);
 * the regret-weighted binary cross-entropy (label: partition-centric was
   faster; weight: |t_SC - t_PC|) and its exact gradient with respect to the
   bf16 weights, by hand-written backpropagation;
@@ -143,6 +146,48 @@ def _layers(theta_bf16, mean, inv_std, X):
 def forward(theta_bf16, mean, inv_std, X) -> np.ndarray:
     """Logits of the samples X (n x 12 raw features)."""
     return _layers(theta_bf16, mean, inv_std, X)[-1]
+
+
+def forward_infer(theta_bf16, mean, inv_std, X) -> np.ndarray:
+    """Logits as the per-iteration mode selection evaluates the network: the
+    input of each hidden layer is rounded to bf16 (ties to even) -- the
+    standardised features (taken to FP32 first, as the device computes them;
+    b1 multiplies an exact 1) and the first hidden layer after its ReLU.
+    Products and sums in FP64."""
+    P = unpack(theta_bf16)
+    xs = (np.asarray(X, dtype=np.float64) - np.asarray(mean, np.float64)) * np.asarray(inv_std, np.float64)
+    Xh = bf16_round(xs.astype(np.float32))
+    H1 = bf16_round(np.maximum(Xh @ P["W1"].T + P["b1"], 0.0).astype(np.float32))
+    H2 = np.maximum(H1 @ P["W2"].T + P["b2"], 0.0)
+    return H2 @ P["w3"] + P["b3"]
+
+
+def infer_ambiguous(theta_bf16, mean, inv_std, X, rel_x: float = 1e-5, rel_h: float = 1e-6) -> np.ndarray:
+    """Per sample: True if one of the values forward_infer rounds to bf16 lies
+    so close to a rounding midpoint that another evaluation could round it
+    the other way: a standardised feature within rel_x of the magnitudes it
+    is made of (plus rel_x absolute on the raw feature: features computed in
+    FP32 agree to a few 1e-6), a first-layer sum within rel_h of the sum of
+    its terms' magnitudes (13 FP32 additions err by at most 13 * 2^-24 of
+    that). Elsewhere every rounding is the same on both sides and the logits
+    differ by FP32 summation only."""
+    P = unpack(theta_bf16)
+    Xr = np.asarray(X, dtype=np.float64)
+    mu, iv = np.asarray(mean, np.float64), np.asarray(inv_std, np.float64)
+    xs = (Xr - mu) * iv
+    e0 = rel_x * (np.abs(Xr) + np.abs(mu) + 1.0) * np.abs(iv)
+
+    def flips(v, e):
+        lo = bf16_round((v - e).astype(np.float32))
+        hi = bf16_round((v + e).astype(np.float32))
+        return lo != hi
+
+    amb = np.any(flips(xs, e0), axis=1)
+    Xh = bf16_round(xs.astype(np.float32))
+    pre = Xh @ P["W1"].T + P["b1"]
+    e1 = rel_h * (np.abs(Xh) @ np.abs(P["W1"]).T + np.abs(P["b1"]))
+    amb |= np.any(flips(np.maximum(pre, 0.0), e1) & (pre + e1 > 0), axis=1)
+    return amb
 
 
 def loss_and_grad(theta_bf16, mean, inv_std, X, t_sc, t_pc):

@@ -807,7 +807,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
     if (hc2.bug) return fail(GPOP_EDEVICE, "internal error while building the partition layout");
 
     // the graph's own run as a batch of one: per kernel, blocks [0, n)
-    const uint32_t nb[6] = {(G.k + 63) / 64, std::min<uint32_t>((G.max_sctask + kScWaves - 1) / kScWaves, 2048u),
+    const uint32_t nb[6] = {(G.k + 31) / 32, std::min<uint32_t>((G.max_sctask + kScWaves - 1) / kScWaves, 2048u),
                             (G.k + 3) / 4, G.n_pctask, G.n_gtask, G.n_gsplit * merge_chunks(G.q)};
     uint32_t hb[12];
     for (int j = 0; j < 6; ++j) {
@@ -1382,7 +1382,7 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
         I.P = g->P;
         I.state = nullptr;
         const Dev& S = g->G;
-        const uint32_t nb[6] = {(S.k + 63) / 64, std::min<uint32_t>((S.max_sctask + kScWaves - 1) / kScWaves, sc_cap),
+        const uint32_t nb[6] = {(S.k + 31) / 32, std::min<uint32_t>((S.max_sctask + kScWaves - 1) / kScWaves, sc_cap),
                                 (S.k + 3) / 4, S.n_pctask, S.n_gtask, S.n_gsplit * merge_chunks(S.q)};
         for (int j = 0; j < 6; ++j) hb[(size_t)j * (n + 1) + i + 1] = hb[(size_t)j * (n + 1) + i] + nb[j];
         k_max = std::max(k_max, S.k);

@@ -211,7 +211,11 @@ def test_learned_modes_follow_the_network_and_results_are_unchanged():
     for t, md in enumerate(modes):
         front = np.nonzero(lv == t)[0]
         f = mr.features(g.offsets, g.cols, q, front, t)
-        z = mr.forward(w, mean, inv, f)
+        # the selection's arithmetic: bf16 layer inputs; where an FP32
+        # feature difference could round one of them the other way, skip
+        z = mr.forward_infer(w, mean, inv, f)
+        amb = mr.infer_ambiguous(w, mean, inv, f)
+        tol = np.where(amb, np.inf, 1e-4 * np.maximum(1.0, np.abs(z)))
         zs = np.abs((f - mean) * inv)
         for p in range(len(md)):
             va = int(np.sum(front // q == p))
@@ -219,7 +223,7 @@ def test_learned_modes_follow_the_network_and_results_are_unchanged():
                 assert md[p] == gp.MODE_NONE
                 continue
             if np.all(zs[p] <= 6):
-                if abs(z[p]) > 1e-3:
+                if abs(z[p]) > tol[p]:
                     assert md[p] == (gp.MODE_PC if z[p] >= 0 else gp.MODE_SC), (t, p, z[p])
             else:
                 ea = int(sum(g.offsets[v + 1] - g.offsets[v] for v in front if v // q == p))
@@ -351,8 +355,9 @@ def test_learned_selector_held_out_whole_runs():
 
 
 def test_confidence_margin_gates_the_network():
-    """gpop_mlp_set_margin: a partition whose logit (oracle forward pass)
-    lies inside the margin keeps Eq. 1's mode, one outside takes the
+    """gpop_mlp_set_margin: a partition whose logit (the oracle's forward
+    pass in the selection's arithmetic) lies inside the margin keeps Eq. 1's
+    mode, one outside takes the
     network's; margin inf reproduces Eq. 1 exactly, and the iteration records
     count the gated partitions as fallbacks. Results never change."""
     torch = torch_cuda()
@@ -370,7 +375,7 @@ def test_confidence_margin_gates_the_network():
     mlp.init(torch.from_numpy(gg.mlp_init_params(99)).cuda(), torch.from_numpy(F.astype(np.float32)).cuda())
     _, _, mean, inv, w = _model_from_device(mlp)
     png = gpop_ref.build_png(g, q)
-    zall = np.concatenate([mr.forward(w, mean, inv, mr.features(g.offsets, g.cols, q, np.nonzero(lv == t)[0], t))
+    zall = np.concatenate([mr.forward_infer(w, mean, inv, mr.features(g.offsets, g.cols, q, np.nonzero(lv == t)[0], t))
                            for t in range(depth + 1)])
     med = float(np.median(np.abs(zall[np.isfinite(zall)])))
     for margin in (math.inf, med, 0.0):
@@ -382,7 +387,9 @@ def test_confidence_margin_gates_the_network():
         for t, md in enumerate(modes):
             front = np.nonzero(lv == t)[0]
             f = mr.features(g.offsets, g.cols, q, front, t)
-            z = mr.forward(w, mean, inv, f)
+            z = mr.forward_infer(w, mean, inv, f)
+            amb = mr.infer_ambiguous(w, mean, inv, f)
+            tol = np.where(amb, np.inf, 1e-4 * np.maximum(1.0, np.abs(z)))
             zs = np.abs((f - mean) * inv)
             for p in range(len(md)):
                 va = int(np.sum(front // q == p))
@@ -392,10 +399,10 @@ def test_confidence_margin_gates_the_network():
                 eq1 = gp.MODE_PC if gpop_ref.choose_mode(png.E[p], png.M[p], va, ea, png.k) == gpop_ref.PC \
                     else gp.MODE_SC
                 net_ok = bool(np.all(zs[p] <= 6))
-                if net_ok and abs(abs(z[p]) - margin) < 1e-3:
-                    continue  # on the margin: FP32 rounding may go either way
+                if net_ok and abs(abs(z[p]) - margin) < tol[p]:
+                    continue  # on the margin: a bf16 rounding may go either way
                 if net_ok and abs(z[p]) >= margin:
-                    if abs(z[p]) > 1e-3:
+                    if abs(z[p]) > tol[p]:
                         assert md[p] == (gp.MODE_PC if z[p] >= 0 else gp.MODE_SC), (margin, t, p, z[p])
                     decided += 1
                 else:

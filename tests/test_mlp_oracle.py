@@ -82,6 +82,64 @@ def test_forward_and_loss_match_torch():
     assert math.isclose(L, L_ref, rel_tol=1e-12)
 
 
+def test_inference_forward_matches_torch_bf16_layers():
+    """forward_infer against torch: the layer inputs cast to bfloat16 by
+    torch (its own round-to-nearest-even conversion), the layers in float64."""
+    theta, mean, inv_std = _random_model(6)
+    X, _, _ = _random_batch(6, n=211)
+    X = X * 3
+    W1 = torch.tensor(theta[mr.OFF_W1:mr.OFF_B1], dtype=torch.float64).view(64, 12)
+    b1 = torch.tensor(theta[mr.OFF_B1:mr.OFF_W2], dtype=torch.float64)
+    W2 = torch.tensor(theta[mr.OFF_W2:mr.OFF_B2], dtype=torch.float64).view(64, 64)
+    b2 = torch.tensor(theta[mr.OFF_B2:mr.OFF_W3], dtype=torch.float64)
+    w3 = torch.tensor(theta[mr.OFF_W3:mr.OFF_B3], dtype=torch.float64)
+    b3 = float(theta[mr.OFF_B3])
+    xs = (torch.tensor(X, dtype=torch.float64) - torch.tensor(mean, dtype=torch.float64)) * \
+        torch.tensor(inv_std, dtype=torch.float64)
+    xb = xs.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    h1 = torch.relu(xb @ W1.T + b1).to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    z_ref = (torch.relu(h1 @ W2.T + b2) @ w3 + b3).numpy()
+    z = mr.forward_infer(theta, mean, inv_std, X)
+    assert np.allclose(z, z_ref, rtol=1e-12, atol=1e-12)
+    # and it differs from the exact forward pass by rounding only
+    assert 0 < np.max(np.abs(z - mr.forward(theta, mean, inv_std, X))) < 0.05 * np.max(np.abs(z))
+
+
+def test_inference_forward_is_exact_on_bf16_values():
+    """Inputs whose standardised values and first hidden layer are already
+    bf16 values (small integers, weights in {-1, 0, 1}): no rounding happens
+    and forward_infer equals the exact forward pass."""
+    rng = np.random.default_rng(8)
+    theta = rng.integers(-1, 2, mr.N_PARAMS).astype(np.float64)
+    mean = np.zeros(12, np.float32)
+    inv_std = np.ones(12, np.float32)
+    X = rng.integers(-3, 4, (50, 12)).astype(np.float32)
+    assert np.array_equal(mr.forward_infer(theta, mean, inv_std, X), mr.forward(theta, mean, inv_std, X))
+
+
+def test_inference_ambiguity_flags_every_rounding_that_moves():
+    """Inputs moved by a relative 1e-6 (below the 1e-5 the flag allows for)
+    leave forward_infer's roundings, hence its logit, unchanged on every
+    sample not flagged ambiguous; the flag marks a minority of samples."""
+    theta, mean, inv_std = _random_model(9)
+    X, _, _ = _random_batch(9, n=400)
+    X = X * 2
+    z = mr.forward_infer(theta, mean, inv_std, X)
+    amb = mr.infer_ambiguous(theta, mean, inv_std, X)
+    assert 0 < np.mean(amb) < 0.5
+    rng = np.random.default_rng(10)
+    moved = 0
+    for _ in range(20):
+        Xp = (X * (1 + 1e-6 * rng.standard_normal(X.shape))).astype(np.float64)
+        zp = mr.forward_infer(theta, mean, inv_std, Xp)
+        d = np.abs(zp - z)
+        # unflagged samples: the same bf16 inputs, so the same logit up to the
+        # first layer's FP64 sums of slightly different features
+        assert np.all(d[~amb] == 0.0)
+        moved += int(np.sum(d[amb] > 0))
+    assert moved > 0  # some flagged roundings did flip
+
+
 def test_gradient_matches_torch_autograd():
     theta, mean, inv_std = _random_model(3)
     X, t_sc, t_pc = _random_batch(3, n=53)
