@@ -984,6 +984,38 @@ def headline(args):
         sys.exit(3)
 
 
+def modes_eval(args):
+    """Scatter modes compared on one workload (the paper's SC-only / PC-only /
+    dual comparison): for each selector configuration, ms per step timed over
+    whole steps, then per-kernel ms from the library's HIP events. One JSON
+    line; the table goes to stderr."""
+    import torch
+    g, runs, lp, desc = load_workload(args.workload)
+    if args.log2_part:
+        lp = args.log2_part
+    P = Part(args.workload, g, runs, lp, args)
+    P.G.set_selector("analytical", 16.0)
+    _, _, _, _, edges = P.stats_pass()
+    rows = []
+    log("%-16s %-14s %8s %7s %6s %10s %10s %7s %6s" % ("workload", "selector", "ms/step", "GTEPS", "plan",
+                                                       "scatter_sc", "scatter_pc", "gather", "merge"))
+    for spec in args.modes.split(","):
+        sel, _, r = spec.partition(":")
+        ratio = float(r) if r else 16.0
+        P.G.set_selector({"eq1": "analytical"}.get(sel, sel), ratio)
+        ms = time_steps([P], args.steps, args.warmup)
+        _, prof = profile_steps([P], 2)
+        km = {k: v[0] / 2 for k, v in prof.items()}
+        name = "eq1 ratio %g" % ratio if sel == "eq1" else sel + " only"
+        rows.append({"selector": name, "ms_per_step": ms, "GTEPS": edges / (ms * 1e-3) / 1e9,
+                     "kernel_ms": {k: round(v, 3) for k, v in km.items()}})
+        log("%-16s %-14s %8.2f %7.2f %6.2f %10.2f %10.2f %7.2f %6.2f" % (
+            args.workload, name, ms, rows[-1]["GTEPS"], km.get("plan", 0), km.get("scatter_sc", 0),
+            km.get("scatter_pc", 0), km.get("gather", 0), km.get("merge", 0)))
+    print(json.dumps({"workload": args.workload, "description": desc, "edges_per_step": edges,
+                      "steps": args.steps, "warmup": args.warmup, "modes": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1018,6 +1050,8 @@ def main():
                     help="gather combine: LDS min/add per message, or the atomic-free rounds")
     ap.add_argument("--pc-stream", default="auto", choices=["auto", "on", "off"],
                     help="gather reads partition-centric ids from column streams (auto/on) or per bin (off)")
+    ap.add_argument("--modes", default="",
+                    help="compare scatter modes on --workload: comma-separated eq1:RATIO, sc, pc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -1031,6 +1065,8 @@ def main():
         if args.steps == 10:
             args.steps = 2
         return selector_eval(args)
+    if args.modes:
+        return modes_eval(args)
     if args.workload == "headline":
         return headline(args)
 

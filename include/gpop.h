@@ -128,6 +128,19 @@ typedef struct gpop_graph_desc {
 #define GPOP_PCSTREAM_OFF 1u
 #define GPOP_PCSTREAM_ON 2u
 
+/* How a source-centric task reserves the slots of its messages in the bins
+ * (gpop_options.sc_reserve):
+ *   GPOP_SCRES_AUTO   per bin when the iteration's tasks hold at least 2k
+ *                     work units, else per message piece
+ *   GPOP_SCRES_PIECE  one device-wide atomic per message piece (one pass)
+ *   GPOP_SCRES_BIN    two passes: the wave counts its pieces per bin in LDS,
+ *                     reserves each bin's share with one atomic, then writes
+ * The result is the same in every mode; only the order of messages inside a
+ * bin differs, and no combine depends on it. */
+#define GPOP_SCRES_AUTO 0u
+#define GPOP_SCRES_PIECE 1u
+#define GPOP_SCRES_BIN 2u
+
 typedef struct gpop_options {
     uint32_t log2_part;   /* q = 2^log2_part vertices per partition, 8..15;
                              0 picks 14 (16384 vertices)                        */
@@ -144,7 +157,8 @@ typedef struct gpop_options {
     uint32_t combine;          /* GPOP_COMBINE_LDS (0) or GPOP_COMBINE_ROUNDS   */
     uint32_t pc_stream;        /* GPOP_PCSTREAM_AUTO (0), _OFF or _ON: how
                                   gather reads partition-centric bins       */
-    uint32_t reserved[3];      /* must be zero                                  */
+    uint32_t sc_reserve;       /* GPOP_SCRES_AUTO (0), _PIECE or _BIN        */
+    uint32_t reserved[2];      /* must be zero                                  */
 } gpop_options;
 
 typedef struct gpop_plan_info {

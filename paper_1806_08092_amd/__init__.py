@@ -27,6 +27,8 @@ COMBINE_LDS, COMBINE_ROUNDS = 0, 1
 COMBINES = {"lds": COMBINE_LDS, "rounds": COMBINE_ROUNDS}
 PCSTREAM_AUTO, PCSTREAM_OFF, PCSTREAM_ON = 0, 1, 2
 PCSTREAMS = {"auto": PCSTREAM_AUTO, "off": PCSTREAM_OFF, "on": PCSTREAM_ON}
+SCRES_AUTO, SCRES_PIECE, SCRES_BIN = 0, 1, 2
+SCRESERVES = {"auto": SCRES_AUTO, "piece": SCRES_PIECE, "bin": SCRES_BIN}
 # selectors
 SEL_ANALYTICAL, SEL_FORCE_SC, SEL_FORCE_PC, SEL_LEARNED = range(4)
 SELECTORS = {"analytical": SEL_ANALYTICAL, "sc": SEL_FORCE_SC, "pc": SEL_FORCE_PC,
@@ -54,7 +56,8 @@ class GraphDesc(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("log2_part", ctypes.c_uint32), ("sc_task_log2", ctypes.c_uint32),
                 ("gather_task_ids", ctypes.c_uint32), ("combine", ctypes.c_uint32),
-                ("pc_stream", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("pc_stream", ctypes.c_uint32), ("sc_reserve", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -225,7 +228,8 @@ class Graph:
     workspace is allocated here as a torch tensor and owned by this object."""
 
     def __init__(self, offsets, cols, weights=None, log2_part: int = 14, stream=None,
-                 sc_task_log2: int = 0, gather_task_ids: int = 0, combine="lds", pc_stream="auto"):
+                 sc_task_log2: int = 0, gather_task_ids: int = 0, combine="lds", pc_stream="auto",
+                 sc_reserve="auto"):
         import torch
         self._keep = (offsets, cols, weights)
         n = offsets.numel() - 1
@@ -234,7 +238,8 @@ class Graph:
                               None if weights is None else weights.data_ptr())
         combine = COMBINES[combine] if isinstance(combine, str) else int(combine)
         pc_stream = PCSTREAMS[pc_stream] if isinstance(pc_stream, str) else int(pc_stream)
-        self.opts = Options(log2_part, sc_task_log2, gather_task_ids, combine, pc_stream)
+        sc_reserve = SCRESERVES[sc_reserve] if isinstance(sc_reserve, str) else int(sc_reserve)
+        self.opts = Options(log2_part, sc_task_log2, gather_task_ids, combine, pc_stream, sc_reserve)
         info = PlanInfo()
         _check(lib().gpop_plan(ctypes.byref(self.desc), ctypes.byref(self.opts), ctypes.byref(info)))
         self.q, self.k = info.q, info.k

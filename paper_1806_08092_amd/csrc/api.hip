@@ -353,8 +353,9 @@ int check_desc(const gpop_graph_desc* d, const gpop_options* o, uint32_t* s_out)
     if (d->reserved0) return fail(GPOP_EINVAL, "reserved0 must be zero");
     uint32_t s = 14;
     if (o) {
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 2; ++i)
             if (o->reserved[i]) return fail(GPOP_EINVAL, "options.reserved must be zero");
+        if (o->sc_reserve > GPOP_SCRES_BIN) return fail(GPOP_EINVAL, "unknown sc_reserve mode %u", o->sc_reserve);
         if (o->combine > GPOP_COMBINE_ROUNDS) return fail(GPOP_EINVAL, "unknown combine %u", o->combine);
         if (o->pc_stream > GPOP_PCSTREAM_ON) return fail(GPOP_EINVAL, "unknown pc_stream mode %u", o->pc_stream);
         if (o->log2_part) s = o->log2_part;
@@ -797,6 +798,7 @@ int gpop_graph_create(const gpop_graph_desc* desc, const gpop_options* opts, voi
                                      st), "write split list");
     G.idb = (uint32_t)slot;
     G.pcs_mode = z.pc_stream;
+    G.scres_mode = opts ? opts->sc_reserve : GPOP_SCRES_AUTO;
     HIP_OR_RETURN(hipMemsetD32Async((hipDeviceptr_t)(G.data + G.idb), 0xFFFFFFFF, kIdWords, st),
                   "write identity words");
     if ((rc = build_streams(G, z, cnti, st))) return rc;
@@ -1431,6 +1433,10 @@ int gpop_batch_create(gpop_graph* const* graphs, uint32_t n, void* d_ws, size_t 
             delete b;
             return fail(GPOP_EINVAL, "every graph of a batch must use the same combine option");
         }
+    if (sc_lds_bytes(k_max) > (size_t)max_lds_per_block()) {
+        delete b;
+        return fail(GPOP_ENOTSUP, "k = %u partitions need more LDS than a workgroup has", k_max);
+    }
     HIP_OR_RETURN(hipMemcpyAsync(boff, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, st), "write batch grid");
     HIP_OR_RETURN(hipMemcpyAsync(b->d_tab, b->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice, st),
                   "write run table");

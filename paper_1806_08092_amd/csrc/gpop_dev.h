@@ -76,7 +76,8 @@ struct Ctrl {
     uint32_t max_it;      // a plan at this index pauses the run (done bit 2)
     uint32_t run_start;   // pos when the current run began
     uint32_t n_pcpart;    // partitions scattered partition-centric in the current iteration
-    uint32_t pad[48];
+    uint32_t sc_agg;      // source-centric tasks reserve per bin (1) or per piece (0)
+    uint32_t pad[47];
 };
 
 // Everything the kernels read or write, by value in each launch.
@@ -93,6 +94,7 @@ struct Dev {
     uint32_t combine;         // GPOP_COMBINE_*
     uint32_t whole_ids;       // a split partition with at most this many ids is gathered by one task
     uint32_t pcs_mode;        // GPOP_PCSTREAM_*
+    uint32_t scres_mode;      // GPOP_SCRES_*
     uint32_t idb;             // data[idb, idb + kIdWords): combine identities (min and sum), never written
     uint32_t n_chunks;        // chunks of all column streams
     uint64_t E;

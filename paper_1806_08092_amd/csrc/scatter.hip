@@ -358,15 +358,23 @@ __device__ __forceinline__ uint32_t sc_cut(uint32_t x, uint32_t end, uint32_t na
     return x + (y - e);
 }
 
+// How a task reserves its pieces' slots.
+enum ScKind : int {
+    SC_DIRECT = 0,  // one global atomic per piece
+    SC_COUNT = 1,   // pass 1 of a large task: per-bin totals in the wave's LDS row
+    SC_WRITE = 2,   // pass 2: slots from the row, which holds the task's bases
+};
+
 // One source-centric task: the units [f0, f1) of partition p moved to piece
 // boundaries (see above). n_msg / n_ids count the messages (runs) started and
-// the ids written.
-template <int PROG>
+// the ids written. row: the wave's LDS row of k {message, id} words
+// (SC_COUNT, SC_WRITE).
+template <int PROG, int KIND>
 __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict__ state, uint32_t p,
                                         uint32_t f0, uint32_t f1, uint32_t end, uint32_t nact,
                                         uint32_t stamp, const uint16_t* __restrict__ alist,
                                         const uint32_t* __restrict__ fpre, uint32_t& n_msg,
-                                        uint32_t& n_ids) {
+                                        uint32_t& n_ids, unsigned long long* row) {
     const uint32_t lane = lane_id();
     const uint32_t k = G.k, s = G.s, qmask = G.q - 1u;
     const uint32_t vbase = p << s;
@@ -395,7 +403,7 @@ __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict
         const uint32_t chi = min(pr + 1u + deg, b1);
         const uint32_t cdeg = (vv && chi > clo) ? chi - clo : 0u;
         const uint32_t cst = rs + (clo - pr - 1u);
-        const uint32_t val = cdeg ? scatter_value<PROG>(G, state, v) : 0u;
+        const uint32_t val = (KIND != SC_COUNT && cdeg) ? scatter_value<PROG>(G, state, v) : 0u;
         const uint32_t incl = wave_incl_scan(cdeg);
         const uint32_t total = last_lane(incl);
         // carried from the previous 64 edges: the open piece (first id slot,
@@ -449,12 +457,18 @@ __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict
             unsigned long long old = 0;
             if (flag) {
                 const uint32_t len = after ? (uint32_t)__builtin_ctzll(after) - lane : len_last;
-                old = atomicAdd(cnt + (size_t)key * k + p, 1ull | ((unsigned long long)len << 32));
-                if (old == 0ull) {  // first piece of the bin this iteration
-                    gptr(G.nz)[(size_t)key * G.kw * 64u + p] = 1;
-                    gptr(G.cact)[key] = stamp;
+                const unsigned long long add = 1ull | ((unsigned long long)len << 32);
+                if constexpr (KIND == SC_DIRECT) {
+                    old = atomicAdd(cnt + (size_t)key * k + p, add);
+                    if (old == 0ull) {  // first piece of the bin this iteration
+                        gptr(G.nz)[(size_t)key * G.kw * 64u + p] = 1;
+                        gptr(G.cact)[key] = stamp;
+                    }
+                } else {
+                    old = atomicAdd(row + key, add);  // LDS
                 }
             }
+            if constexpr (KIND == SC_COUNT) continue;
             const uint32_t o_slot = (uint32_t)(old >> 32), o_m = (uint32_t)old;
             // each edge belongs to the latest piece start at or below its lane
             const uint64_t mine = fm & below_eq;
@@ -489,7 +503,13 @@ __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict
 // The iteration index: the plan has already advanced pos, except in a probe.
 __device__ __forceinline__ uint32_t scatter_it(const Inst& I) { return gptr(I.G.ctrl)->pos - (I.P.probe ? 0u : 1u); }
 
-template <int PROG>
+// The source-centric tasks of an iteration. AGG = false: one global atomic per
+// piece. AGG = true (iterations whose tasks are large next to k, where a task
+// holds many pieces per bin): the wave counts its pieces per bin in its LDS
+// row, reserves each bin's share with one global atomic, then walks the task
+// again and takes slots from the row. The plan picks one of the two per
+// iteration; the other kernel returns at once.
+template <int PROG, bool AGG>
 __global__ __launch_bounds__(kScWaves * 64) void kb_sc_scatter(const Inst* __restrict__ tab,
                                                                const uint32_t* __restrict__ boff,
                                                                uint32_t n) {
@@ -497,7 +517,7 @@ __global__ __launch_bounds__(kScWaves * 64) void kb_sc_scatter(const Inst* __res
     const Inst& I = tab[bi];
     const Dev& G = I.G;
     const Ctrl* C = gptr(G.ctrl);
-    if (C->done) return;
+    if (C->done || (C->sc_agg != 0u) != AGG) return;
     const uint32_t it = scatter_it(I), cur = it & 1u;
     // the gather of this iteration looks for the stamp; a probe's (never
     // gathered) must still be nonzero, so that the next clear finds it
@@ -505,22 +525,50 @@ __global__ __launch_bounds__(kScWaves * 64) void kb_sc_scatter(const Inst* __res
     const uint32_t ntask = C->n_sctask, nblk = boff[bi + 1] - boff[bi];
     const uint32_t* __restrict__ t0 = gptr(G.sc_t0);
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t k = G.k;
+    extern __shared__ unsigned long long sc_rows[];
+    unsigned long long* row = AGG ? sc_rows + (size_t)wave * k : nullptr;
+    if constexpr (AGG)
+        for (uint32_t j = lane; j < k; j += 64u) row[j] = 0ull;
     for (uint32_t t = (blockIdx.x - boff[bi]) * kScWaves + wave; t < ntask; t += nblk * kScWaves) {
         const uint64_t t_beg = I.P.probe ? wall_clock64() : 0;
-        const uint32_t p = task_owner(t0, G.k, t);
+        const uint32_t p = task_owner(t0, k, t);
         const uint32_t sh = gptr(G.sc_sh)[p];
         const uint32_t nact = gptr(G.fVa[cur])[p];
         const uint32_t end = gptr(G.fEa[cur])[p] + nact;
         const uint32_t f0 = (t - t0[p]) << sh;
         const uint32_t f1 = min(f0 + (1u << sh), end);
         const uint32_t vbase = p << G.s;
+        const uint16_t* __restrict__ alist = gptr(G.flist[cur]) + vbase;
+        const uint32_t* __restrict__ fpre = gptr(G.fpre[cur]) + vbase;
         uint32_t n_msg = 0, n_ids = 0;
-        sc_task<PROG>(G, gptr(I.state), p, f0, f1, end, nact, stamp, gptr(G.flist[cur]) + vbase,
-                      gptr(G.fpre[cur]) + vbase, n_msg, n_ids);
+        if constexpr (!AGG) {
+            sc_task<PROG, SC_DIRECT>(G, gptr(I.state), p, f0, f1, end, nact, stamp, alist, fpre, n_msg, n_ids,
+                                     nullptr);
+        } else {
+            uint32_t u0 = 0, u1 = 0;
+            sc_task<PROG, SC_COUNT>(G, gptr(I.state), p, f0, f1, end, nact, stamp, alist, fpre, u0, u1, row);
+            // the task's share of each bin it writes: one reservation per bin;
+            // the row then holds the task's bases
+            unsigned long long* __restrict__ cnt = reinterpret_cast<unsigned long long*>(gptr(G.sc_cnt));
+            for (uint32_t j = lane; j < k; j += 64u) {
+                const unsigned long long c = row[j];
+                if (c == 0ull) continue;
+                const unsigned long long old = atomicAdd(cnt + (size_t)j * k + p, c);
+                if (old == 0ull) {  // first pieces of the bin this iteration
+                    gptr(G.nz)[(size_t)j * G.kw * 64u + p] = 1;
+                    gptr(G.cact)[j] = stamp;
+                }
+                row[j] = old;
+            }
+            sc_task<PROG, SC_WRITE>(G, gptr(I.state), p, f0, f1, end, nact, stamp, alist, fpre, n_msg, n_ids,
+                                    row);
+            for (uint32_t j = lane; j < k; j += 64u) row[j] = 0ull;
+        }
         if (lane == 0) {
             gptr(G.sc_tt)[t] = make_uint2(n_msg, n_ids);
             if (I.P.probe)  // one wave's time, charged to its partition
-                atomicAdd(gptr(G.probe) + G.k + p, (unsigned long long)(wall_clock64() - t_beg));
+                atomicAdd(gptr(G.probe) + k + p, (unsigned long long)(wall_clock64() - t_beg));
         }
     }
 }
@@ -873,6 +921,9 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         }
         gptr(G.sc_t0)[G.k] = tcarry;
         C->n_sctask = tcarry;
+        // tasks of at least 2k units hold many pieces per bin: reserve per bin
+        C->sc_agg = G.scres_mode == GPOP_SCRES_BIN ||
+                    (G.scres_mode == GPOP_SCRES_AUTO && (1u << sh) >= 2u * G.k) ? 1u : 0u;
         C->n_pcpart = (uint32_t)t[3];
         // gather reads the partition-centric ids from the column streams
         // when their partitions hold at least half of the edges (a stream
@@ -929,6 +980,9 @@ __global__ __launch_bounds__(kPlanT) void k_plan1(Dev G, const Params* __restric
 
 template <int PROG>
 static hipError_t prep_batch_scatter_p(const BatchGrid& B) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kb_sc_scatter<PROG, true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sc_lds_bytes(B.k_max));
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kb_pc<PROG>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(B.q_max * 4));
 }
@@ -937,7 +991,10 @@ template <int PROG>
 static hipError_t launch_batch_sc_p(const BatchGrid& B, hipStream_t st) {
     if (B.nb_sc) {
         hipLaunchKernelGGL(kb_sc_clear, dim3(B.nb_clr), dim3(256), 0, st, B.tab, B.b_clr, B.n);
-        hipLaunchKernelGGL(kb_sc_scatter<PROG>, dim3(B.nb_sc), dim3(kScWaves * 64), 0, st, B.tab, B.b_sc, B.n);
+        hipLaunchKernelGGL((kb_sc_scatter<PROG, false>), dim3(B.nb_sc), dim3(kScWaves * 64), 0, st, B.tab,
+                           B.b_sc, B.n);
+        hipLaunchKernelGGL((kb_sc_scatter<PROG, true>), dim3(B.nb_sc), dim3(kScWaves * 64),
+                           sc_lds_bytes(B.k_max), st, B.tab, B.b_sc, B.n);
     }
     return hipGetLastError();
 }

@@ -12,11 +12,13 @@ def torch_cuda():
     return torch
 
 
-def make_graph(g, log2_part, sc_task_log2=0, gather_task_ids=0, combine="lds", pc_stream="auto"):
+def make_graph(g, log2_part, sc_task_log2=0, gather_task_ids=0, combine="lds", pc_stream="auto",
+               sc_reserve="auto"):
     import paper_1806_08092_amd as gp
     off, cols, w = gp.upload_csr(g)
     G = gp.Graph(off, cols, w, log2_part=log2_part, sc_task_log2=sc_task_log2,
-                 gather_task_ids=gather_task_ids, combine=combine, pc_stream=pc_stream)
+                 gather_task_ids=gather_task_ids, combine=combine, pc_stream=pc_stream,
+                 sc_reserve=sc_reserve)
     return G, (off, cols, w)
 
 

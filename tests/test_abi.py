@@ -133,3 +133,17 @@ def test_plan_pc_stream_modes():
     ws = {m: gp.plan(1 << 20, 1 << 24, 14, pc_stream=m).workspace_bytes for m in ("auto", "off", "on")}
     assert ws["auto"] == ws["on"]
     assert ws["auto"] - ws["off"] >= (1 << 24) * 3  # 2-byte ids + 1-byte weights of every edge
+
+
+def test_plan_sc_reserve_modes():
+    """sc_reserve picks how source-centric tasks reserve bin slots; unknown
+    modes and nonzero reserved words are rejected, known ones plan."""
+    d = gp.GraphDesc(1 << 20, 0, 1 << 24, None, None, None)
+    L = gp.lib()
+    info = gp.PlanInfo()
+    for m in (gp.SCRES_AUTO, gp.SCRES_PIECE, gp.SCRES_BIN):
+        assert L.gpop_plan(ctypes.byref(d), ctypes.byref(gp.Options(14, 0, 0, 0, 0, m)), ctypes.byref(info)) == gp.OK
+    assert L.gpop_plan(ctypes.byref(d), ctypes.byref(gp.Options(14, 0, 0, 0, 0, 3)), ctypes.byref(info)) == gp.EINVAL
+    o = gp.Options(14, 0, 0, 0, 0, 0)
+    o.reserved[1] = 1
+    assert L.gpop_plan(ctypes.byref(d), ctypes.byref(o), ctypes.byref(info)) == gp.EINVAL
