@@ -984,6 +984,100 @@ def headline(args):
         sys.exit(3)
 
 
+# kernel families: (name, kernels (name fragments), the kernel launched once per iteration)
+FAMILIES = [
+    ("plan", ["k_plan1(", "kb_plan("], None),
+    ("scatter_sc", ["kb_sc_clear(", "kb_sc_scatter<"], "kb_sc_clear("),
+    ("scatter_pc", ["kb_pc<"], "kb_pc<"),
+    ("gather", ["kb_gather<", "kb_gather_dense<"], "kb_gather<"),
+    ("merge", ["kb_merge_part<", "kb_merge_list("], "kb_merge_part<"),
+]
+
+
+def traffic_summary(args):
+    """Writes profiles/traffic_<family>_<tag>.txt from two rocprofv3 runs of
+    the same bench command, one with --pmc FETCH_SIZE and one with --pmc
+    WRITE_SIZE (csv output), and the JSON line of a plain run of that
+    command (algorithmic bytes). Counters are scaled by what they read for
+    the bench's copy kernel (torch bitwise_not over --copy-mib MiB of int32:
+    reads and writes 4 bytes per element)."""
+    import collections
+    import csv
+    import glob
+    fdir, wdir = args.traffic_summary.split(",")
+    bench_line = json.loads(open(args.traffic_bench).read().strip().splitlines()[-1])
+    per_kernel = bench_line["per_kernel"]
+
+    def load(d, counter):
+        per = collections.defaultdict(float)  # (kernel, dispatch) -> value
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        per[(r["Kernel_Name"], fn, r["Dispatch_Id"])] += float(r["Counter_Value"])
+        out = collections.defaultdict(list)
+        for (kn, _, _), v in per.items():
+            out[kn].append(v)
+        return out
+
+    fv, wv = load(fdir, "FETCH_SIZE"), load(wdir, "WRITE_SIZE")
+    expected = (args.copy_mib << 18) * 4
+
+    def factor(vals):
+        c = [v for kn, vs in vals.items() if "bitwise_not" in kn for v in vs]
+        return expected / (sum(c) / len(c) * 1024.0), sum(c) / len(c)
+
+    ff, fk = factor(fv)
+    wf, wk = factor(wv)
+    cmd = bench_line.get("config", {}).get("command", "")
+    for fam, frags, anchor in FAMILIES:
+        if fam not in per_kernel:
+            continue
+
+        def fam_total(vals, fac):
+            tot, groups = 0.0, 0
+            for kn, vs in vals.items():
+                if any(fr in kn for fr in frags):
+                    tot += sum(vs) * 1024.0 * fac
+                    if anchor is None or anchor in kn:
+                        groups += len(vs)
+            return tot, groups
+
+        ft, fg = fam_total(fv, ff)
+        wt, wg = fam_total(wv, wf)
+        if fg == 0 or wg == 0:
+            continue
+        alg = per_kernel[fam]["alg_GB_per_step"] * 1e9 / per_kernel[fam]["launches_per_step"]
+        path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (fam, args.traffic_tag))
+        with open(path, "w") as fh:
+            fh.write("# HBM traffic per launch group of the %s kernels (%s), averaged over every group of the run\n"
+                     % (fam, ", ".join(fr.rstrip("(<") for fr in frags)))
+            fh.write("# workload: %s\n" % bench_line.get("config", {}).get("workload", args.traffic_tag))
+            fh.write("# commands (from /tmp with TMPDIR=/tmp, one MI355X; R = the repository root):\n")
+            fh.write("#   timeout -s KILL 900 rocprofv3 --pmc FETCH_SIZE --output-format csv -d R/gpurun_out/pmc_fetch -o run -- "
+                     "python3 R/bench.py %s\n" % args.traffic_args)
+            fh.write("#   timeout -s KILL 900 rocprofv3 --pmc WRITE_SIZE --output-format csv -d R/gpurun_out/pmc_write -o run -- "
+                     "python3 R/bench.py %s\n" % args.traffic_args)
+            fh.write("#   python3 R/bench.py %s > R/gpurun_out/traffic_bench.json   (algorithmic bytes)\n" % args.traffic_args)
+            fh.write("#   python3 R/bench.py --traffic-summary R/gpurun_out/pmc_fetch,R/gpurun_out/pmc_write "
+                     "--traffic-bench R/gpurun_out/traffic_bench.json --traffic-tag %s --copy-mib %d\n"
+                     % (args.traffic_tag, args.copy_mib))
+            fh.write("# calibration: the copy kernel reads and writes %d bytes per dispatch; FETCH_SIZE reads %.0f KiB, "
+                     "WRITE_SIZE %.0f KiB -> factors %.4f %.4f\n" % (expected, fk, wk, ff, wf))
+            fh.write("# FETCH_SIZE and WRITE_SIZE are KiB per dispatch; bytes = KiB x 1024 x factor, summed over the "
+                     "family's dispatches, / launch groups (one per iteration)\n")
+            fh.write("kernel: %s\n" % fam)
+            fh.write("source_files: %s\n" % " ".join(KERNEL_SOURCES[fam]))
+            fh.write("source_sha256: %s\n" % kernel_source_hash(fam))
+            fh.write("launch_groups: %d/%d\n" % (fg, wg))
+            fh.write("algorithmic_bytes_per_launch: %.0f\n" % alg)
+            fh.write("fetch_bytes_per_launch: %.0f\n" % (ft / fg))
+            fh.write("write_bytes_per_launch: %.0f\n" % (wt / wg))
+            fh.write("traffic_bytes_per_launch: %.0f\n" % (ft / fg + wt / wg))
+            fh.write("traffic_over_algorithmic: %.3f\n" % ((ft / fg + wt / wg) / alg if alg else 0.0))
+        log("wrote %s" % path)
+
+
 def modes_eval(args):
     """Scatter modes compared on one workload (the paper's SC-only / PC-only /
     dual comparison): for each selector configuration, ms per step timed over
@@ -1050,6 +1144,13 @@ def main():
                     help="gather combine: LDS min/add per message, or the atomic-free rounds")
     ap.add_argument("--pc-stream", default="auto", choices=["auto", "on", "off"],
                     help="gather reads partition-centric ids from column streams (auto/on) or per bin (off)")
+    ap.add_argument("--traffic-summary", default="",
+                    help="FETCH_DIR,WRITE_DIR: rocprofv3 --pmc csv output of the same bench command; writes "
+                         "profiles/traffic_<kernel>_<tag>.txt")
+    ap.add_argument("--traffic-bench", default="", help="with --traffic-summary: that command's JSON line")
+    ap.add_argument("--traffic-tag", default="rmat25", help="with --traffic-summary: workload tag of the files")
+    ap.add_argument("--traffic-args", default="--steps 2 --warmup 1 --no-cpu --no-learned --no-rmat22 --no-parity",
+                    help="with --traffic-summary: the bench arguments of the profiled command (recorded)")
     ap.add_argument("--modes", default="",
                     help="compare scatter modes on --workload: comma-separated eq1:RATIO, sc, pc")
     args = ap.parse_args()
@@ -1065,6 +1166,8 @@ def main():
         if args.steps == 10:
             args.steps = 2
         return selector_eval(args)
+    if args.traffic_summary:
+        return traffic_summary(args)
     if args.modes:
         return modes_eval(args)
     if args.workload == "headline":

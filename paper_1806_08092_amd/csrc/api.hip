@@ -183,6 +183,7 @@ size_t carve(Dev* G, char* base, uint32_t V, uint64_t E, const Sizes& z, Inst** 
     G->bin_ioff = (uint32_t*)take((kk + 1) * 4);
     G->cm = (uint4*)take(kk * 16);
     G->sc_mo = (uint32_t*)take(kk * 4);
+    G->sc_mor = (uint32_t*)take((kk + 1) * 4);
     const uint64_t kw = (k + 63) / 64;
     G->colsrc = (uint64_t*)take(k * kw * 8);
     G->spre = (uint32_t*)take(kk * 4);

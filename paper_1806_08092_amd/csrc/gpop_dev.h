@@ -155,6 +155,7 @@ struct Dev {
     uint64_t* scmask;         // [kw] partitions scattered source-centric this iteration
     uint2* sc_tt;             // [max_sctask] {messages, ids} written by each SC task
     uint32_t* sc_mo;          // [k*k] column-major: data index of SC bin[p][q]'s first message slot
+    uint32_t* sc_mor;         // [k*k+1] the same, row-major (scatter), then the end of the last bin
     uint8_t* sc_sh;           // [k] log2 work units per source-centric task of each partition
     uint32_t* sc_t0;          // [k+1] exclusive prefix of SC tasks per partition
     uint2* sc_tc;             // [n_bldtask*k] build: per-(task, q) counts, then bases

@@ -187,12 +187,15 @@ __global__ void k_sc_cap(Dev G) {
         G.cnt_m[o] += G.cnt_i[o] / kPiece;
 }
 
-// Column-major data index of each source-centric bin's first message slot:
-// base plus the row-major exclusive prefix sx of the capacities.
+// Data index of each source-centric bin's first message slot, base plus the
+// row-major exclusive prefix sx of the capacities: row-major (with the end of
+// the last bin) for the scatter, column-major for the gather.
 __global__ void k_sc_mo(Dev G, const uint32_t* __restrict__ sx, uint32_t base) {
     const uint64_t kk = (uint64_t)G.k * G.k;
-    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < kk;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o <= kk;
          o += (uint64_t)gridDim.x * blockDim.x) {
+        G.sc_mor[o] = base + sx[o];
+        if (o == kk) continue;
         const uint64_t q = o / G.k, p = o % G.k;
         G.sc_mo[o] = base + sx[p * G.k + q];
     }

@@ -380,9 +380,8 @@ __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict
     const uint32_t vbase = p << s;
     const uint32_t* __restrict__ off = gptr(G.off);
     const uint32_t* __restrict__ cols = gptr(G.cols);
-    const uint32_t* __restrict__ rmoff = gptr(G.bin_moff) + (size_t)p * k;
     const uint32_t* __restrict__ rioff = gptr(G.bin_ioff) + (size_t)p * k;
-    const uint32_t* __restrict__ smo = gptr(G.sc_mo);
+    const uint32_t* __restrict__ smor = gptr(G.sc_mor) + (size_t)p * k;  // row p: cached
     unsigned long long* __restrict__ cnt = reinterpret_cast<unsigned long long*>(gptr(G.sc_cnt));
     uint32_t r_first, r_unused;
     const uint32_t b0 = sc_cut(f0, end, nact, vbase, s, off, cols, alist, fpre, r_first);
@@ -483,13 +482,13 @@ __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict
             }
             if (valid) {
                 const uint32_t ib = rioff[key], icap = rioff[key + 1] - ib;
-                const uint32_t mcap = rmoff[key + 1] - rmoff[key] + icap / kPiece;
+                const uint32_t mb = smor[key], mcap = smor[key + 1] - mb;
                 // the reservation must stay inside the capacity of bin[p][key]
                 if (slot >= icap || midx >= mcap) {
                     gptr(G.ctrl)->bug = 1;
                 } else {
                     const uint32_t pos = ib + slot;
-                    if (flag) gptr(G.data)[smo[(size_t)key * k + p] + midx] = o_val;
+                    if (flag) gptr(G.data)[mb + midx] = o_val;
                     gptr(G.sc_ids)[pos] = (uint16_t)((col & qmask) | (flag ? kFlag : 0u));
                     if constexpr (is_weighted(PROG)) gptr(G.sc_w)[pos] = gptr(G.w)[e];
                     if ((pos & (kChunk - 1)) == 0) gptr(G.sc_chunk)[pos / kChunk] = midx;
