@@ -63,7 +63,7 @@ def kernel_bytes(rec, next_va, q, k, weighted, sum_prog):
     s_part = 8 if sum_prog else 4
     plan = 25 * k
     sc = (rec["sc_active_vertices"] * (2 + 4 + 8 + 4) + rec["sc_active_edges"] * (4 + s_w)
-          + rec["sc_ids"] * (s_id + s_w) + rec["sc_msgs"] * s_v + rec["sc_parts"] * 8 * k)
+          + rec["sc_ids"] * (s_id + s_w) + rec["sc_msgs"] * s_v)
     pc = (rec["pc_vertices"] * (4 + 0.125 + (8 if sum_prog else 0))
           + rec["pc_msgs"] * (2 + s_v))
     whole = rec["gather_parts"]
