@@ -1078,6 +1078,69 @@ def traffic_summary(args):
         log("wrote %s" % path)
 
 
+def counter_summary(args):
+    """Writes profiles/counters_<tag>.txt from rocprofv3 --pmc runs (csv
+    output) of the same bench command, one directory per counter pass: per
+    kernel of the scatter/gather families, dispatches split into heavy (at
+    least 60 us) and light ones, each counter summed over them, and derived
+    ratios."""
+    import collections
+    import csv
+    import glob
+    dirs = args.counter_summary.split(",")
+    sums = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    frags = [fr for _, frs, _ in FAMILIES for fr in frs]
+    for d in dirs:
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(fn) as fh:
+                for r in csv.DictReader(fh):
+                    kn = r["Kernel_Name"]
+                    if not any(fr in kn for fr in frags):
+                        continue
+                    us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                    key = (kn.split("(")[0].replace("void ", "").replace("gpop::", ""), "heavy" if us >= 60 else "light")
+                    sums[key][r["Counter_Name"]] += float(r["Counter_Value"])
+                    disp[(key, fn)].add(r["Dispatch_Id"])
+    lines = ["# rocprofv3 counters of the scatter/gather kernels: %s" % args.counter_tag,
+             "# commands (from /tmp with TMPDIR=/tmp, one MI355X; R = the repository root), one per counter pass:"]
+    for i, c in enumerate(args.counter_sets.split(";")):
+        lines.append("#   timeout -s KILL 900 rocprofv3 --pmc %s --output-format csv -d R/gpurun_out/pmc_c%d -o run -- "
+                     "python3 R/bench.py %s" % (c.strip(), i, args.traffic_args))
+    lines.append("#   python3 R/bench.py --counter-summary %s --counter-tag %s" %
+                 (",".join("R/gpurun_out/pmc_c%d" % i for i in range(len(dirs))), args.counter_tag))
+    lines.append("# heavy: dispatches of at least 60 us; counters summed over every dispatch of the kind (all XCDs).")
+    lines.append("# derived: per wave = instructions / SQ_WAVES; waiting = SQ_WAIT_ANY / SQ_WAVE_CYCLES (share of the")
+    lines.append("#   waves' lifetime spent stalled); LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS (bank-conflict")
+    lines.append("#   cycles per LDS instruction); TA busy = TA_TA_BUSY / (GRBM_GUI_ACTIVE / 8 XCDs x 256 CUs) (share of")
+    lines.append("#   the kernel's cycles each CU's texture addresser, the vector-memory address unit, is busy); L2 hit =")
+    lines.append("#   TCC_HIT / (TCC_HIT + TCC_MISS); L2 read latency = TCP_TCC_READ_REQ_LATENCY / TCP_TCC_READ_REQ cycles")
+    for key in sorted(sums):
+        a = sums[key]
+        nd = max(len(v) for (k, _), v in disp.items() if k == key)
+
+        def ratio(x, y, scale=1.0):
+            return "%.3g" % (scale * a[x] / a[y]) if a.get(x) is not None and a.get(y) else "-"
+
+        lines.append("")
+        lines.append("kernel: %s (%s), dispatches %d" % (key[0], key[1], nd))
+        lines.append("  per wave: VALU %s, VMEM read %s, VMEM write %s, LDS %s, SALU %s" % (
+            ratio("SQ_INSTS_VALU", "SQ_WAVES"), ratio("SQ_INSTS_VMEM_RD", "SQ_WAVES"),
+            ratio("SQ_INSTS_VMEM_WR", "SQ_WAVES"), ratio("SQ_INSTS_LDS", "SQ_WAVES"), ratio("SQ_INSTS_SALU", "SQ_WAVES")))
+        ta = "%.3g" % (a["TA_TA_BUSY"] / (a["GRBM_GUI_ACTIVE"] / 8 * 256)) if a.get("GRBM_GUI_ACTIVE") else "-"
+        lines.append("  waiting %s, LDS conflict %s, TA busy %s, L2 hit %s, L2 read latency %s" % (
+                         ratio("SQ_WAIT_ANY", "SQ_WAVE_CYCLES"), ratio("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS"),
+                         ta, "%.3g" % (a["TCC_HIT"] / (a["TCC_HIT"] + a["TCC_MISS"]))
+                         if a.get("TCC_HIT") is not None and a.get("TCC_MISS") else "-",
+                         ratio("TCP_TCC_READ_REQ_LATENCY", "TCP_TCC_READ_REQ")))
+        for c in sorted(a):
+            lines.append("  %-28s %.6g" % (c, a[c]))
+    path = os.path.join(ROOT, "profiles", "counters_%s.txt" % args.counter_tag)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    log("wrote %s" % path)
+
+
 def modes_eval(args):
     """Scatter modes compared on one workload (the paper's SC-only / PC-only /
     dual comparison): for each selector configuration, ms per step timed over
@@ -1151,6 +1214,12 @@ def main():
     ap.add_argument("--traffic-tag", default="rmat25", help="with --traffic-summary: workload tag of the files")
     ap.add_argument("--traffic-args", default="--steps 2 --warmup 1 --no-cpu --no-learned --no-rmat22 --no-parity",
                     help="with --traffic-summary: the bench arguments of the profiled command (recorded)")
+    ap.add_argument("--counter-summary", default="",
+                    help="DIR,DIR,...: rocprofv3 --pmc csv output of counter passes of the same bench command; "
+                         "writes profiles/counters_<tag>.txt")
+    ap.add_argument("--counter-tag", default="rmat25", help="with --counter-summary: workload tag")
+    ap.add_argument("--counter-sets", default="", help="with --counter-summary: the passes' counters (recorded), "
+                    "';' between passes")
     ap.add_argument("--modes", default="",
                     help="compare scatter modes on --workload: comma-separated eq1:RATIO, sc, pc")
     args = ap.parse_args()
@@ -1168,6 +1237,8 @@ def main():
         return selector_eval(args)
     if args.traffic_summary:
         return traffic_summary(args)
+    if args.counter_summary:
+        return counter_summary(args)
     if args.modes:
         return modes_eval(args)
     if args.workload == "headline":
