@@ -461,12 +461,11 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
     return my_ids;
 }
 
-// An iteration in which every partition scattered partition-centric and
-// gather reads the column streams: no source-centric bin exists anywhere, so
-// kb_gather_dense runs it with wider workgroups and kb_gather returns.
+// An iteration in which gather reads the column streams and source-centric
+// bins hold few ids (the plan decides): kb_gather_dense runs it with wider
+// workgroups and kb_gather returns.
 __device__ __forceinline__ bool dense_stream_iteration(const Dev& G) {
-    const Ctrl* C = gptr(G.ctrl);
-    return C->pc_stream != 0u && C->n_pcpart == G.k;
+    return gptr(G.ctrl)->dense_gather != 0u;
 }
 
 // Workgroup of the dense gather: 16 waves. Without the bin-list arrays its LDS
@@ -477,7 +476,7 @@ constexpr uint32_t kDT = 1024;
 constexpr uint32_t kDW = kDT / 64;
 
 struct DenseLds {
-    size_t state, carry, keep, total;
+    size_t state, carry, keep, pcm, scm, total;
 };
 __host__ __device__ inline DenseLds dense_layout(int prog, uint32_t q) {
     DenseLds L{};
@@ -485,8 +484,72 @@ __host__ __device__ inline DenseLds dense_layout(int prog, uint32_t q) {
     L.state = o;  o += ((size_t)(q + 1) * (is_sum(prog) ? 8 : 4) + 15) / 16 * 16;  // plus the spare word
     L.carry = o;  o += has_carry(prog) ? ((size_t)q + 15) / 16 * 16 : 0;
     L.keep = o;   o += ((size_t)q / 64 + 1) * 8;
+    L.pcm = o;    o += 64 * 8;  // k-bit source masks (k <= 4096)
+    L.scm = o;    o += 64 * 8;
     L.total = o;
     return L;
+}
+
+// The source-centric bins of source partitions [p_lo, p_hi] marked in scm,
+// one wave per bin, 64 ids a step; the message of an id is the bin's first
+// plus the message starts before it. A task of a split column takes the bins
+// whose first static piece lies in its piece range [s0, s1) (counted from the
+// first piece of bin p_lo), so every bin has one owner. Returns the ids with a
+// value the lane combined.
+template <int PROG>
+__device__ __forceinline__ uint32_t dense_sc_bins(const Dev& G, uint32_t cq, uint32_t p_lo, uint32_t p_hi,
+                                                  bool split, uint32_t s0, uint32_t s1, const uint64_t* scm,
+                                                  uint32_t* st32, unsigned long long* acc) {
+    constexpr bool SUM = is_sum(PROG);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t k = G.k;
+    const uint64_t below_eq = lane == 63u ? ~0ull : (2ull << lane) - 1ull;
+    const uint16_t* __restrict__ ids = gptr(G.sc_ids);
+    const uint8_t* __restrict__ wts = gptr(G.sc_w);
+    const uint32_t* __restrict__ data = gptr(G.data);
+    const uint2* __restrict__ cnt = gptr(G.sc_cnt) + (size_t)cq * k;
+    const uint4* __restrict__ cmc = gptr(G.cm) + (size_t)cq * k;
+    const uint32_t* __restrict__ smo = gptr(G.sc_mo) + (size_t)cq * k;
+    const uint32_t* __restrict__ spre = gptr(G.spre) + (size_t)cq * k;
+    const uint32_t sbase = spre[p_lo];
+    uint32_t my_ids = 0, rank = 0;
+    for (uint32_t w = p_lo >> 6; w <= (p_hi >> 6); ++w) {
+        uint64_t m = scm[w] & range_bits(w, p_lo, p_hi);
+        while (m) {
+            const uint32_t b = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            const uint32_t p = 64u * w + b;
+            if (split) {
+                const uint32_t sp = spre[p] - sbase;
+                if (sp < s0 || sp >= s1) continue;  // another task of the column owns the bin
+            }
+            if ((rank++ % kDW) != wave) continue;
+            const uint32_t icnt = cnt[p].y, ioff = cmc[p].y, moff = smo[p];
+            uint32_t before = 0;  // message starts before this step
+            for (uint32_t x = 0; x < icnt; x += 64u) {
+                const uint32_t i = x + lane;
+                const bool valid = i < icnt;
+                const uint32_t id = valid ? (uint32_t)ids[ioff + i] : 0u;
+                const uint64_t fm = ballot(valid && (id & kFlag));
+                uint32_t v = SUM ? kIdentSum : kIdentMin;
+                if (valid) {
+                    v = data[moff + before + popc64(fm & below_eq) - 1u];
+                    if constexpr (is_weighted(PROG)) v = sat_add(v, wts[ioff + i]);
+                }
+                const uint32_t d = id & kLocalMask;
+                if constexpr (SUM) {
+                    const bool use = valid && (int32_t)v >= 0;
+                    my_ids += use ? 1u : 0u;
+                    atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(v) * kFix) : 0ull);
+                } else {
+                    my_ids += (valid && v != kIdentMin) ? 1u : 0u;
+                    atomicMin(st32 + d, v);
+                }
+                before += popc64(fm);
+            }
+        }
+    }
+    return my_ids;
 }
 
 // The gather task of a dense iteration: the task table, the split of heavy
@@ -514,12 +577,44 @@ __device__ __forceinline__ void dense_body(const Dev& G, const Params& P, uint32
     uint8_t* carry = smem + L.carry;
     __shared__ GatherSharedT<kDW> sh;
 
+    // Source masks of the column when some partition did not scatter
+    // partition-centric: pcm, bins whose source did (read from the stream);
+    // scm, source-centric bins with ids (the column's stamp says whether any).
+    const bool mixed = gptr(G.ctrl)->n_pcpart != k;
+    uint64_t* pcm = reinterpret_cast<uint64_t*>(smem + L.pcm);
+    uint64_t* scm = reinterpret_cast<uint64_t*>(smem + L.scm);
+    if (mixed) {
+        const bool sc_col = gptr(G.cact)[cq] == it + 1u;
+        const uint32_t g = tid;  // byte g covers partitions [8g, 8g + 8); k <= 4096 = 8 * 512
+        if (g < G.kw * 8u) {
+            uint32_t scb = 0;
+            if (sc_col) {
+                const uint64_t f = *reinterpret_cast<const uint64_t*>(gptr(G.nz) + (size_t)cq * G.kw * 64u + 8u * g);
+                uint32_t bits = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bits |= (uint32_t)((f >> (8 * j)) & 1u) << j;
+                scb = bits & reinterpret_cast<const uint8_t*>(gptr(G.scmask))[g];
+            }
+            reinterpret_cast<uint8_t*>(pcm)[g] = (uint8_t)(reinterpret_cast<const uint8_t*>(
+                gptr(G.colsrc) + (size_t)cq * G.kw)[g] & reinterpret_cast<const uint8_t*>(gptr(G.pcmask))[g]);
+            reinterpret_cast<uint8_t*>(scm)[g] = (uint8_t)scb;
+        }
+        __syncthreads();
+    }
+    auto bit = [&](const uint64_t* m, uint32_t p) -> bool { return (m[p >> 6] >> (p & 63u)) & 1ull; };
+
     // a split column whose ids fit one task is gathered whole by its first
-    // task (every source's bin holds its static ids in a dense iteration)
+    // task (the ids of its listed bins: every static id of a partition-centric
+    // source, the reserved ids of a source-centric one)
     if (split) {
         const uint4* __restrict__ cmcol = gptr(G.cm) + (size_t)cq * k;
+        const uint2* __restrict__ sccol = gptr(G.sc_cnt) + (size_t)cq * k;
         uint32_t c = 0;
-        for (uint32_t p = tid; p < k; p += kDT) c += cmcol[p].w;
+        for (uint32_t p = tid; p < k; p += kDT) {
+            if (!mixed) c += cmcol[p].w;
+            else if (bit(pcm, p)) c += cmcol[p].w;
+            else if (bit(scm, p)) c += sccol[p].y;
+        }
         c = wave_sum_u32(c);
         if (lane == 0) sh.wc[wave] = c;
         __syncthreads();
@@ -541,11 +636,20 @@ __device__ __forceinline__ void dense_body(const Dev& G, const Params& P, uint32
             p_hi = k - 1;
         }
     }
-    // bins of the task's source range (statistics: every non-empty bin of
-    // the column is read in a dense iteration)
-    uint32_t mine = 0;
-    if (tid < G.kw) mine = (uint32_t)__popcll(gptr(G.colsrc)[(size_t)cq * G.kw + tid] & range_bits(tid, p_lo, p_hi));
-    mine = wave_sum_u32(mine);
+    // statistics: the listed bins of the task's source range, as kb_gather
+    // counts them (in a dense iteration every non-empty static bin)
+    uint32_t mine = 0, sc_mine = 0;
+    if (tid < G.kw) {
+        const uint64_t r = range_bits(tid, p_lo, p_hi);
+        if (mixed) {
+            mine = (uint32_t)__popcll((pcm[tid] | scm[tid]) & r);
+            sc_mine = (uint32_t)__popcll(scm[tid] & r);
+        } else {
+            mine = (uint32_t)__popcll(gptr(G.colsrc)[(size_t)cq * G.kw + tid] & r);
+        }
+    }
+    mine = wave_sum_u32(mine);  // kw <= 64: wave 0 holds the sum
+    sc_mine = __syncthreads_or(sc_mine != 0u) ? 1u : 0u;  // some source-centric bin in the range
     const uint32_t c0 = gptr(G.cs_c0)[cq], c1 = gptr(G.cs_c0)[cq + 1];
     uint32_t cs_lo = c0, cs_hi = c1;
     if (split) {
@@ -553,7 +657,7 @@ __device__ __forceinline__ void dense_body(const Dev& G, const Params& P, uint32
         cs_lo = c0 + (uint32_t)(C * jt / nt);
         cs_hi = c0 + (uint32_t)(C * (jt + 1u) / nt);
     }
-    const bool any = cs_hi > cs_lo || (!split && !msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0);
+    const bool any = cs_hi > cs_lo || sc_mine != 0u || (!split && !msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0);
     if (!any) {
         if (tid == 0) {
             if (split) {
@@ -580,8 +684,9 @@ __device__ __forceinline__ void dense_body(const Dev& G, const Params& P, uint32
         __syncthreads();
     }
     uint32_t my_ids;
-    if (G.idb < (1u << 30) - kIdWords) my_ids = stream_gather<PROG, false, kDW, 2>(G, cs_lo, cs_hi, true, nullptr, st32, acc);
-    else my_ids = stream_gather<PROG, true, kDW, 2>(G, cs_lo, cs_hi, true, nullptr, st32, acc);
+    if (G.idb < (1u << 30) - kIdWords) my_ids = stream_gather<PROG, false, kDW, 2>(G, cs_lo, cs_hi, !mixed, pcm, st32, acc);
+    else my_ids = stream_gather<PROG, true, kDW, 2>(G, cs_lo, cs_hi, !mixed, pcm, st32, acc);
+    if (sc_mine) my_ids += dense_sc_bins<PROG>(G, cq, p_lo, p_hi, split, TB.x, TB.y, scm, st32, acc);
     __syncthreads();
     if (split) {
         if constexpr (SUM) {
@@ -615,7 +720,7 @@ __device__ __forceinline__ void dense_body(const Dev& G, const Params& P, uint32
 // a partial result for k_merge.
 //
 // Bins are enumerated through the two-level active list (Sec. 3.1.3): the
-// SC offset scan stamps every column that receives source-centric ids
+// source-centric scatter stamps every column that receives source-centric ids
 // (level 1, cact) and flags each non-empty source-centric bin (nz); the plan
 // writes the masks of the partitions scattered in each mode. A task first
 // builds its column's k-bit mask of bins with ids this iteration --
@@ -692,12 +797,12 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     __shared__ GatherShared sh;
 
     // ---- the two-level active list. Level 1: does column cq receive
-    //      anything? (stamped by the source-centric scan; partition-centric
+    //      anything? (stamped by the source-centric scatter; partition-centric
     //      sources exist only if some partition scattered in that mode).
     //      Level 2: the k-bit mask of source partitions whose bin to cq holds
     //      ids, built one byte (8 partitions) per thread with independent
     //      loads: partition-centric sources from the static column mask,
-    //      source-centric ones from the scan's flags.
+    //      source-centric ones from the scatter's marks.
     uint64_t* amask = reinterpret_cast<uint64_t*>(smem + L.amask);
     uint64_t* pcm = reinterpret_cast<uint64_t*>(smem + L.pcm);
     bool col_pc = false;  // some partition-centric source has a bin in this column

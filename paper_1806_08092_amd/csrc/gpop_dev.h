@@ -77,7 +77,8 @@ struct Ctrl {
     uint32_t run_start;   // pos when the current run began
     uint32_t n_pcpart;    // partitions scattered partition-centric in the current iteration
     uint32_t sc_agg;      // source-centric tasks reserve per bin (1) or per piece (0)
-    uint32_t pad[47];
+    uint32_t dense_gather;  // the wide gather kernel takes this iteration (column streams, few SC ids)
+    uint32_t pad[46];
 };
 
 // Everything the kernels read or write, by value in each launch.
