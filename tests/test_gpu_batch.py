@@ -196,3 +196,33 @@ def test_autotune_choice_is_fastest_tried_and_correct(prog):
     else:
         got, _ = run_program(G, "bfs", g.n, root=root)
         assert np.array_equal(got, oracle.bfs_levels(g, root))
+
+
+@pytest.mark.parametrize("sel", ["analytical", "sc"])
+def test_batch_at_scale_rmat18(sel):
+    """A batch of 16 BFS and then 8 SSSP runs on RMAT-18 symmetrised at the
+    default partition size (k = 16), under Eq. 1 at the default ratio and
+    with every partition source-centric: every run equals the oracle, and
+    per-run iteration counts equal single runs'."""
+    torch = torch_cuda()
+    import paper_1806_08092_amd as gp
+    g = gg.rmat_graph(18, 16, seed=gg.BASE_SEED + 86, symmetric=True, weights_seed=gg.BASE_SEED + 87)
+    G, _ = make_graph(g, 14)
+    G.set_selector(sel, 16.0)
+    for prog, count in (("bfs", 16), ("sssp", 8)):
+        seeds = [int(s) for s in gg.pick_sources(g.offsets, gg.SOURCE_SEED + 7, count)]
+        B = gp.Batch([G] * count)
+        st = _states(torch, g.n, count)
+        B.state_init(prog, st, roots=seeds)
+        for i, s in enumerate(seeds):
+            B.set_frontier(i, torch.tensor([s], dtype=torch.int32, device="cuda"))
+        iters = B.run()
+        B.check()
+        torch.cuda.synchronize()
+        for i, s in enumerate(seeds):
+            want = oracle.bfs_levels(g, s) if prog == "bfs" else oracle.sssp(g, s)
+            assert np.array_equal(st[i].cpu().numpy().view(np.uint32), want), (prog, sel, i)
+        for i in (0, count - 1):
+            _, single_iters = run_program(G, prog, g.n, root=seeds[i], selector=sel, bw_ratio=16.0)
+            assert iters[i] == single_iters, (prog, sel, i)
+        B.close()
