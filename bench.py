@@ -49,6 +49,12 @@ def log(*a):
 
 
 # ---------------------------------------------------------------- byte model
+# the iteration-record fields the byte model reads
+RECORD_FIELDS = ("active_vertices", "active_edges", "sc_parts", "pc_parts", "sc_msgs", "sc_ids", "pc_msgs", "pc_ids",
+                 "gathered_ids", "gather_parts", "split_tasks", "sc_active_vertices", "sc_active_edges",
+                 "pc_vertices", "merged_parts", "gathered_bins")
+
+
 def kernel_bytes(rec, next_va, q, k, weighted, sum_prog):
     """Algorithmic bytes of each kernel for one iteration record, with the
     element sizes the kernels use: 2-byte ids, 4-byte values and state,
@@ -644,6 +650,8 @@ class Part:
                         bytes_step[kname] += kb[kname]
                     tot = sum(kb.values())
                     per_iter.append({"run": "%s(%d)" % (prog, root), "it": i,
+                                     "record": {f: int(rec[f]) for f in RECORD_FIELDS}, "next_va": int(nva),
+                                     "q": int(info.q), "k": int(info.k), "weighted": weighted, "sum_prog": sump,
                                      "active_vertices": rec["active_vertices"],
                                      "active_edges": rec["active_edges"], "sc_parts": rec["sc_parts"],
                                      "pc_parts": rec["pc_parts"], "ms": kms[i],
@@ -1078,6 +1086,35 @@ def traffic_summary(args):
         log("wrote %s" % path)
 
 
+def iterations_summary(args):
+    """Writes profiles/iterations_<tag>.txt from a bench JSON line: the
+    iteration records of its per-iteration pass (one step) and the byte model
+    recomputed from them, which reproduces the line's alg_GB_per_step."""
+    line = json.loads(open(args.iterations_summary).read().strip().splitlines()[-1])
+    its = line["per_iteration"]["iterations"]
+    cols = ["run", "it"] + list(RECORD_FIELDS) + ["next_va"]
+    tot = {k: 0.0 for k in ("plan", "scatter_sc", "scatter_pc", "gather", "merge")}
+    rows = []
+    for r in its:
+        kb = kernel_bytes(r["record"], r["next_va"], r["q"], r["k"], r["weighted"], r["sum_prog"])
+        for kname in tot:
+            tot[kname] += kb[kname]
+        rows.append(" ".join(str(r[c]) if c in ("run", "it", "next_va") else str(r["record"][c]) for c in cols))
+    out = ["# iteration records of one step of: python3 bench.py %s" % args.traffic_args,
+           "# (the bench line's per-iteration pass; %s)" % line["config"]["workload"],
+           "# written by: python3 bench.py --iterations-summary <that line's JSON> --iterations-tag %s" %
+           args.iterations_tag,
+           "# byte model (bench.py kernel_bytes) over these records, GB per step: " +
+           ", ".join("%s %.6f" % (k, v / 1e9) for k, v in tot.items()),
+           "# the same line's per_kernel alg_GB_per_step: " +
+           ", ".join("%s %.6f" % (k, v["alg_GB_per_step"]) for k, v in line["per_kernel"].items()),
+           " ".join(cols)] + rows
+    path = os.path.join(ROOT, "profiles", "iterations_%s.txt" % args.iterations_tag)
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    log("wrote %s" % path)
+
+
 def counter_summary(args):
     """Writes profiles/counters_<tag>.txt from rocprofv3 --pmc runs (csv
     output) of the same bench command, one directory per counter pass: per
@@ -1220,6 +1257,9 @@ def main():
     ap.add_argument("--counter-tag", default="rmat25", help="with --counter-summary: workload tag")
     ap.add_argument("--counter-sets", default="", help="with --counter-summary: the passes' counters (recorded), "
                     "';' between passes")
+    ap.add_argument("--iterations-summary", default="",
+                    help="a bench JSON line: writes profiles/iterations_<tag>.txt (records and byte model)")
+    ap.add_argument("--iterations-tag", default="rmat25", help="with --iterations-summary: workload tag")
     ap.add_argument("--modes", default="",
                     help="compare scatter modes on --workload: comma-separated eq1:RATIO, sc, pc")
     args = ap.parse_args()
@@ -1239,6 +1279,8 @@ def main():
         return traffic_summary(args)
     if args.counter_summary:
         return counter_summary(args)
+    if args.iterations_summary:
+        return iterations_summary(args)
     if args.modes:
         return modes_eval(args)
     if args.workload == "headline":
