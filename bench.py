@@ -586,7 +586,7 @@ class Part:
         t = time.perf_counter()
         self.G = gp.Graph(self.off, self.cols, self.w, log2_part=lp, sc_task_log2=args.sc_task_log2,
                           gather_task_ids=args.gather_task_ids, combine=args.combine,
-                          pc_stream=args.pc_stream)
+                          pc_stream=args.pc_stream, sc_reserve=args.sc_reserve)
         torch.cuda.synchronize()
         self.prep_ms = (time.perf_counter() - t) * 1e3
         self.info = self.G.info()
@@ -926,7 +926,7 @@ def headline(args):
                                        "pc_messages": P.info.num_messages, "nonempty_bins": P.info.nonempty_bins,
                                        "preprocess_ms": P.prep_ms} for P in parts},
                    "selector": args.selector, "bw_ratio": args.bw_ratio, "combine": args.combine,
-                   "pc_stream": args.pc_stream,
+                   "pc_stream": args.pc_stream, "sc_reserve": args.sc_reserve,
                    "runs_per_step": sum(len(P.runs) for P in parts), "iterations_per_run": iters_per_run,
                    "edges_traversed_per_step": edges, "profiled_ms_per_step": prof_ms,
                    "generation_s": gen_s, "seed": gg.BASE_SEED + 7},
@@ -1242,6 +1242,8 @@ def main():
                     help="interleaved scatter-gather colour classes (0: off; BFS, CC and SSSP only)")
     ap.add_argument("--combine", default="lds", choices=["lds", "rounds"],
                     help="gather combine: LDS min/add per message, or the atomic-free rounds")
+    ap.add_argument("--sc-reserve", default="auto", choices=["auto", "piece", "bin"],
+                    help="source-centric slot reservation: per piece, per bin and task, or chosen per iteration")
     ap.add_argument("--pc-stream", default="auto", choices=["auto", "on", "off"],
                     help="gather reads partition-centric ids from column streams (auto/on) or per bin (off)")
     ap.add_argument("--traffic-summary", default="",
@@ -1299,7 +1301,8 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter()
     G = gp.Graph(off, cols, w, log2_part=lp, sc_task_log2=args.sc_task_log2,
-                 gather_task_ids=args.gather_task_ids, combine=args.combine, pc_stream=args.pc_stream)
+                 gather_task_ids=args.gather_task_ids, combine=args.combine, pc_stream=args.pc_stream,
+                 sc_reserve=args.sc_reserve)
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - t) * 1e3
     info = G.info()
@@ -1410,7 +1413,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "vertices": g.n, "edges": g.m, "q": info.q, "k": info.k,
                    "selector": args.selector, "bw_ratio": args.bw_ratio, "combine": args.combine,
-                   "pc_stream": args.pc_stream,
+                   "pc_stream": args.pc_stream, "sc_reserve": args.sc_reserve,
                    "isg_classes": args.isg,
                    "gather_task_ids": args.gather_task_ids, "sc_task_log2": args.sc_task_log2,
                    "runs_per_step": len(runs), "iterations_per_run": iters_per_run,
