@@ -490,12 +490,14 @@ __host__ __device__ inline DenseLds dense_layout(int prog, uint32_t q) {
     return L;
 }
 
-// The source-centric bins of source partitions [p_lo, p_hi] marked in scm,
-// one wave per bin, 64 ids a step; the message of an id is the bin's first
-// plus the message starts before it. A task of a split column takes the bins
-// whose first static piece lies in its piece range [s0, s1) (counted from the
-// first piece of bin p_lo), so every bin has one owner. Returns the ids with a
-// value the lane combined.
+// The source-centric bins of source partitions [p_lo, p_hi] marked in scm.
+// A task of a split column takes the bins whose first static piece lies in
+// its piece range [s0, s1) (counted from the first piece of bin p_lo), so
+// every bin has one owner. The waves take the task's bins in turn, 64 at a
+// time, one per lane: a lane walks a bin of at most 8 ids by itself (message
+// index: the starts seen so far), a larger bin is taken by the whole wave, 64
+// ids a step (message index: the bin's first plus the starts before the id).
+// Returns the ids with a value the lane combined.
 template <int PROG>
 __device__ __forceinline__ uint32_t dense_sc_bins(const Dev& G, uint32_t cq, uint32_t p_lo, uint32_t p_hi,
                                                   bool split, uint32_t s0, uint32_t s1, const uint64_t* scm,
@@ -512,7 +514,60 @@ __device__ __forceinline__ uint32_t dense_sc_bins(const Dev& G, uint32_t cq, uin
     const uint32_t* __restrict__ smo = gptr(G.sc_mo) + (size_t)cq * k;
     const uint32_t* __restrict__ spre = gptr(G.spre) + (size_t)cq * k;
     const uint32_t sbase = spre[p_lo];
-    uint32_t my_ids = 0, rank = 0;
+    uint32_t my_ids = 0;
+    auto combine = [&](uint32_t d, uint32_t v, bool use) {
+        if constexpr (SUM) {
+            use = use && (int32_t)v >= 0;
+            my_ids += use ? 1u : 0u;
+            atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(v) * kFix) : 0ull);
+        } else {
+            if (!use) v = kIdentMin;
+            my_ids += v != kIdentMin ? 1u : 0u;
+            atomicMin(st32 + d, v);
+        }
+    };
+    // one group: lane j < n holds bin gp
+    auto group = [&](uint32_t n, uint32_t gp) {
+        const bool valid = lane < n;
+        uint32_t icnt = 0, ioff = 0, moff = 0;
+        if (valid) {
+            icnt = cnt[gp].y;
+            ioff = cmc[gp].y;
+            moff = smo[gp];
+        }
+        const bool small = valid && icnt <= 8u;
+        if (small) {
+            uint32_t m = 0xFFFFFFFFu;  // message index of the id
+            for (uint32_t i = 0; i < icnt; ++i) {
+                const uint32_t id = ids[ioff + i];
+                m += (id & kFlag) ? 1u : 0u;
+                uint32_t v = data[moff + m];
+                if constexpr (is_weighted(PROG)) v = sat_add(v, wts[ioff + i]);
+                combine(id & kLocalMask, v, true);
+            }
+        }
+        uint64_t big = ballot(valid && !small);
+        while (big) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(big);
+            big &= big - 1ull;
+            const uint32_t bn = readlane_u32(icnt, j), bo = readlane_u32(ioff, j), bm = readlane_u32(moff, j);
+            uint32_t before = 0;  // message starts before this step
+            for (uint32_t x = 0; x < bn; x += 64u) {
+                const uint32_t i = x + lane;
+                const bool ok = i < bn;
+                const uint32_t id = ok ? (uint32_t)ids[bo + i] : 0u;
+                const uint64_t fm = ballot(ok && (id & kFlag));
+                uint32_t v = SUM ? kIdentSum : kIdentMin;
+                if (ok) {
+                    v = data[bm + before + popc64(fm & below_eq) - 1u];
+                    if constexpr (is_weighted(PROG)) v = sat_add(v, wts[bo + i]);
+                }
+                combine(id & kLocalMask, v, ok);
+                before += popc64(fm);
+            }
+        }
+    };
+    uint32_t rank = 0, n = 0, gp = 0;
     for (uint32_t w = p_lo >> 6; w <= (p_hi >> 6); ++w) {
         uint64_t m = scm[w] & range_bits(w, p_lo, p_hi);
         while (m) {
@@ -524,31 +579,14 @@ __device__ __forceinline__ uint32_t dense_sc_bins(const Dev& G, uint32_t cq, uin
                 if (sp < s0 || sp >= s1) continue;  // another task of the column owns the bin
             }
             if ((rank++ % kDW) != wave) continue;
-            const uint32_t icnt = cnt[p].y, ioff = cmc[p].y, moff = smo[p];
-            uint32_t before = 0;  // message starts before this step
-            for (uint32_t x = 0; x < icnt; x += 64u) {
-                const uint32_t i = x + lane;
-                const bool valid = i < icnt;
-                const uint32_t id = valid ? (uint32_t)ids[ioff + i] : 0u;
-                const uint64_t fm = ballot(valid && (id & kFlag));
-                uint32_t v = SUM ? kIdentSum : kIdentMin;
-                if (valid) {
-                    v = data[moff + before + popc64(fm & below_eq) - 1u];
-                    if constexpr (is_weighted(PROG)) v = sat_add(v, wts[ioff + i]);
-                }
-                const uint32_t d = id & kLocalMask;
-                if constexpr (SUM) {
-                    const bool use = valid && (int32_t)v >= 0;
-                    my_ids += use ? 1u : 0u;
-                    atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(v) * kFix) : 0ull);
-                } else {
-                    my_ids += (valid && v != kIdentMin) ? 1u : 0u;
-                    atomicMin(st32 + d, v);
-                }
-                before += popc64(fm);
+            if (lane == n) gp = p;
+            if (++n == 64u) {
+                group(64u, gp);
+                n = 0;
             }
         }
     }
+    if (n) group(n, gp);
     return my_ids;
 }
 

@@ -257,6 +257,11 @@ __device__ __forceinline__ uint32_t popc_lt(uint64_t m) {
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
+// The value of lane l (l the same in every lane).
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t x, uint32_t l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave.
 // Inclusive prefix sum across the wave with DPP: shifts by 1, 2, 4, 8 lanes
 // inside each row of 16, then the last lane of row 0 is added to row 1 and

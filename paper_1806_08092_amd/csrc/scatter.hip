@@ -83,9 +83,6 @@ __device__ __forceinline__ uint32_t owner_lane(uint32_t incl, uint32_t f) {
     return o;
 }
 
-__device__ __forceinline__ uint32_t readlane_u32(uint32_t x, uint32_t l) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
-}
 
 // ---------------------------------------------------------------- build
 
@@ -929,14 +926,11 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         // chunk is read whole, whatever the mode of its bins' sources)
         C->pc_stream = (G.n_chunks != 0u && t[3] != 0u &&
                         (G.pcs_mode == GPOP_PCSTREAM_ON || 2ull * t[5] >= G.E)) ? 1u : 0u;
-        // the wide gather kernel reads the streams and, one wave per bin, the
-        // source-centric bins: taken when at most half the partitions scattered
-        // source-centric and their bins hold at most an eighth of the
-        // partition-centric ids (many small bins are faster one per lane in
-        // kb_gather); not with interleaved scatter-gather, whose held-back
-        // columns kb_gather keeps
-        C->dense_gather = (C->pc_stream != 0u && P.isg <= 1u &&
-                           (t[3] == G.k || (8ull * t[7] <= t[5] && 2ull * t[2] <= G.k))) ? 1u : 0u;
+        // the wide gather kernel reads the streams and the source-centric bins
+        // (small ones one per lane): taken when those hold at most an eighth
+        // of the partition-centric ids; not with interleaved scatter-gather,
+        // whose held-back columns kb_gather keeps
+        C->dense_gather = (C->pc_stream != 0u && P.isg <= 1u && (t[3] == G.k || 8ull * t[7] <= t[5])) ? 1u : 0u;
         if (tcarry > G.max_sctask) {  // cannot happen (the bound covers every task size): stop
             C->bug = 1;
             C->done = 1;
