@@ -873,7 +873,6 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     // partition-centric bins from the column stream this iteration (the bin
     // list below then takes only the source-centric ones)
     const bool use_stream = !ROUNDS && col_pc && gptr(G.ctrl)->pc_stream != 0u;
-    auto lbit = [&](uint32_t p) -> bool { return abit(p) && !(use_stream && pcbit(p)); };
 
     // ---- a split partition with few ids this iteration (a sparse frontier)
     //      is gathered whole by its first task: no partial results, no merge
@@ -910,15 +909,21 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     // ---- anything to do for this task? (bins with ids in its source range,
     //      or, for programs that carry vertices, an active set to filter)
     uint32_t mine = 0, mine_l = 0;  // listed bins of the thread's byte inside [p_lo, p_hi] (all; bin-list path)
+    uint32_t lbits = 0;               // those of the bin-list path, as bits of the byte
     if (tid < G.kw * 8u) {
         const uint32_t byte = reinterpret_cast<const uint8_t*>(amask)[tid];
         const uint32_t lbyte = use_stream ? byte & ~(uint32_t)reinterpret_cast<const uint8_t*>(pcm)[tid] : byte;
         const uint64_t r = range_bits(tid >> 3, p_lo, p_hi) >> (8u * (tid & 7u));
         mine = (uint32_t)__popc(byte & (uint32_t)(r & 0xFFu));
-        mine_l = (uint32_t)__popc(lbyte & (uint32_t)(r & 0xFFu));
+        lbits = lbyte & (uint32_t)(r & 0xFFu);
+        mine_l = (uint32_t)__popc(lbits);
     }
     const uint32_t wbins = wave_sum_u32(mine);
     if (lane == 0) sh.wsm[wave] = wbins;
+    // rank of the thread's first bin-list bin among those of the task (bytes
+    // are in source-partition order)
+    const uint32_t lincl = wave_incl_scan(mine_l);
+    if (lane == 63) sh.wp[wave] = lincl;
     // this task's share of the column stream
     uint32_t cs_lo = 0, cs_hi = 0;
     if (use_stream) {
@@ -936,8 +941,12 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     const bool carry_col = !SUM && isg_holds(P, cq, k, it) && gptr(G.fVa[cur])[cq] > 0;
     const bool any = __syncthreads_or(mine_l > 0u || (tid == 0 && (cs_hi > cs_lo || (!split && (carry_col ||
                                       (!msg_only(PROG) && gptr(G.fVa[cur])[cq] > 0))))));
-    uint32_t nbins = 0;
-    for (uint32_t w = 0; w < kGW; ++w) nbins += sh.wsm[w];
+    uint32_t nbins = 0, lrank = lincl - mine_l, nlisted = 0;
+    for (uint32_t w = 0; w < kGW; ++w) {
+        nbins += sh.wsm[w];
+        if (w < wave) lrank += sh.wp[w];
+        nlisted += sh.wp[w];
+    }
     if (!any) {
         if (tid == 0) {
             if (split) {
@@ -969,8 +978,9 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
         __syncthreads();
     }
 
-    // ---- gather the task's pieces, bins in windows of kGT source partitions
-    //      (a window without a listed bin is skipped)
+    // ---- gather the task's pieces, bins in windows of kGT bin-list bins
+    //      (ascending source partition), so that a column with few listed
+    //      bins takes one window whatever their partitions
     uint32_t my_ids = 0;
     if constexpr (!ROUNDS) {
         if (use_stream) {
@@ -982,14 +992,14 @@ __device__ __forceinline__ void gather_body(const Dev& G, const Params& P, uint3
     // static pieces of the bins before p_lo: the task's piece range [s0, s1)
     // counts from there
     const uint32_t sbase = gptr(G.spre)[(size_t)cq * k + p_lo];
-    for (uint32_t p0 = p_lo; p0 <= p_hi; p0 += kGT) {
-        const uint32_t pw_hi = min(p0 + kGT - 1u, p_hi);
-        bool wany = false;
-        for (uint32_t w = p0 >> 6; w <= (pw_hi >> 6); ++w)
-            wany |= ((amask[w] & ~(use_stream ? pcm[w] : 0ull)) & range_bits(w, p0, pw_hi)) != 0ull;
-        if (!wany) continue;  // uniform
-        const uint32_t p = p0 + tid;
-        const bool inr = p <= p_hi && lbit(p);
+    for (uint32_t j0 = 0; j0 < nlisted; j0 += kGT) {
+        // the window's partitions, listed in bl_jlo (rewritten with the
+        // window's bins only after the barrier that follows the reads)
+        for (uint32_t m = lbits, r = lrank; m; m &= m - 1u, ++r)
+            if (r >= j0 && r < j0 + kGT) bl_jlo[r - j0] = 8u * tid + (uint32_t)__builtin_ctz(m);
+        __syncthreads();
+        const bool inr = j0 + tid < nlisted;
+        const uint32_t p = inr ? bl_jlo[tid] : 0u;
         const bool is_pc = inr && pcbit(p);
         const uint32_t md = !inr ? GPOP_MODE_NONE : (is_pc ? GPOP_MODE_PC : GPOP_MODE_SC);
         uint32_t ioff = 0, icnt = 0, moff = 0, mcnt = 0, SP = 0;
