@@ -714,10 +714,19 @@ __device__ __forceinline__ void finalize_prev(const Dev& G, uint32_t it) {
     task_batch(tid, ids0, ran0);
     // source-centric messages and ids: one record per task of that iteration
     const uint32_t nsct = gptr(G.ctrl)->n_sctask;
-    for (uint32_t t = tid; t < nsct; t += B) {
-        const uint2 c = gptr(G.sc_tt)[t];
-        v[0] += c.x;
-        v[1] += c.y;
+    constexpr uint32_t kSB = 8;  // task records loaded at once
+    for (uint32_t t0 = tid; t0 < nsct; t0 += kSB * B) {
+        uint2 c[kSB];
+#pragma unroll
+        for (uint32_t u = 0; u < kSB; ++u) {
+            const uint32_t t = t0 + u * B;
+            c[u] = t < nsct ? gptr(G.sc_tt)[t] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kSB; ++u) {
+            v[0] += c[u].x;
+            v[1] += c[u].y;
+        }
     }
     task_sum(ids0, ran0);
     for (uint32_t t0 = tid + kTB * B; t0 < nt; t0 += kTB * B) {
@@ -771,17 +780,21 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     }
     const uint32_t cur = it & 1u;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    // This iteration's inputs of the first kPlanT partitions are loaded before
-    // the previous iteration's statistics are finalised, so that their loads
-    // overlap.
-    uint32_t f_va = 0, f_ea = 0, f_E = 0, f_M = 0;
-    double f_d = 0.0;
-    if (tid < G.k) {
-        f_va = gptr(G.fVa[cur])[tid];
-        f_ea = gptr(G.fEa[cur])[tid];
-        f_E = gptr(G.part_E)[tid];
-        f_M = gptr(G.part_M)[tid];
-        f_d = gptr(G.dpart[cur])[tid];
+    // This iteration's inputs of every partition (thread tid holds partitions
+    // tid, tid + kPlanT, ...) are loaded before the previous iteration's
+    // statistics are finalised, so that all their loads overlap.
+    constexpr uint32_t kPJ = 4096 / kPlanT;  // k <= 4096
+    uint32_t f_va[kPJ], f_ea[kPJ], f_E[kPJ], f_M[kPJ];
+    double f_d[kPJ];
+#pragma unroll
+    for (uint32_t j = 0; j < kPJ; ++j) {
+        const uint32_t p = j * kPlanT + tid;
+        const bool in = p < G.k;
+        f_va[j] = in ? gptr(G.fVa[cur])[p] : 0u;
+        f_ea[j] = in ? gptr(G.fEa[cur])[p] : 0u;
+        f_E[j] = in ? gptr(G.part_E)[p] : 0u;
+        f_M[j] = in ? gptr(G.part_M)[p] : 0u;
+        f_d[j] = in ? gptr(G.dpart[cur])[p] : 0.0;
     }
     finalize_once(G, it);
     __shared__ uint64_t red[10][kPlanW];
@@ -792,13 +805,14 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     // pass 1: modes and totals; the source-centric work units (active
     // vertices + active out-edges) of each partition go to LDS
     __shared__ uint32_t s_units[4096];  // k <= 4096; 0xFFFFFFFF: not source-centric
-    for (uint32_t p0 = 0; p0 < G.k; p0 += kPlanT) {
+#pragma unroll
+    for (uint32_t j = 0; j < kPJ; ++j) {
+        const uint32_t p0 = j * kPlanT;
+        if (p0 >= G.k) break;  // uniform
         const uint32_t p = p0 + tid;
+        uint8_t md = GPOP_MODE_NONE;
         if (p < G.k) {
-            const bool pre = p0 == 0;
-            const uint32_t Va = pre ? f_va : gptr(G.fVa[cur])[p], Ea = pre ? f_ea : gptr(G.fEa[cur])[p];
-            const uint32_t Ep = pre ? f_E : gptr(G.part_E)[p], Mp = pre ? f_M : gptr(G.part_M)[p];
-            uint8_t md = GPOP_MODE_NONE;
+            const uint32_t Va = f_va[j], Ea = f_ea[j], Ep = f_E[j], Mp = f_M[j];
             if (Va) {
                 if (P.selector == GPOP_SEL_FORCE_SC) md = GPOP_MODE_SC;
                 else if (P.selector == GPOP_SEL_FORCE_PC) md = GPOP_MODE_PC;
@@ -831,12 +845,11 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 units = (uint32_t)min<uint64_t>((uint64_t)Va + Ea, 0xFFFFFFFEull);
             }
             s_units[p] = units;
-            dang += pre ? f_d : gptr(G.dpart[cur])[p];
+            dang += f_d[j];
         }
         // level-2 masks of the active list: the partitions scattered in each
         // mode, one 64-bit word per wave
-        const uint8_t mdp = p < G.k ? gptr(G.mode)[p] : (uint8_t)GPOP_MODE_NONE;
-        const uint64_t pcw = ballot(mdp == GPOP_MODE_PC), scw = ballot(mdp == GPOP_MODE_SC);
+        const uint64_t pcw = ballot(md == GPOP_MODE_PC), scw = ballot(md == GPOP_MODE_SC);
         if (lane == 0 && p0 + 64u * wave < G.k) {
             gptr(G.pcmask)[(p0 >> 6) + wave] = pcw;
             gptr(G.scmask)[(p0 >> 6) + wave] = scw;
