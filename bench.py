@@ -748,6 +748,49 @@ def copy_ceiling(mib):
     return {"bytes": 2 * 4 * n, "GBps": 2 * 4 * n / (ms * 1e-3) / 1e9}
 
 
+def stream_ceilings(mib):
+    """The library's reference streams (gpop_stream_ceiling) over mib MiB
+    of source: reads only (the gather's mix, which is almost all reads),
+    copy, and 16-bit reads widened to 32-bit writes (the mix of the
+    partition-centric scatter's stream). Bytes moved per launch / time."""
+    import torch
+    import paper_1806_08092_amd as gp
+    nb = mib << 20
+    src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty(nb // 2, dtype=torch.int32, device="cuda")  # room for the widened words
+    out = {}
+    for name, mix, moved in (("read", gp.STREAM_READ, nb), ("copy", gp.STREAM_COPY, 2 * nb),
+                             ("read2_write4", gp.STREAM_WIDEN, 3 * nb)):
+        gp.stream_ceiling(mix, src, dst, nb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            gp.stream_ceiling(mix, src, dst, nb)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out[name] = {"bytes": moved, "GBps": moved / (ms * 1e-3) / 1e9}
+    del src, dst
+    return out
+
+
+def add_ceilings(out, per_kernel, mib):
+    """The copy ceiling (a torch elementwise kernel, also the reference that
+    scales rocprofv3 FETCH_SIZE / WRITE_SIZE), the library's reference
+    streams, and each kernel's fraction of the stream of its mix (gather:
+    reads; partition-centric scatter: 2-byte reads and 4-byte writes)."""
+    out["copy_ceiling"] = copy_ceiling(mib)
+    out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy_ceiling"]["GBps"]
+    sc = stream_ceilings(mib)
+    out["stream_ceilings"] = sc
+    for kname, mix in (("gather", "read"), ("scatter_pc", "read2_write4")):
+        if kname in per_kernel:
+            per_kernel[kname]["frac_of_%s_stream" % mix] = per_kernel[kname]["achieved_GBps"] / sc[mix]["GBps"]
+    out["roofline"]["frac_of_mix_stream"] = per_kernel[out["roofline"]["kernel"]].get(
+        "frac_of_read_stream" if out["roofline"]["kernel"] == "gather" else "frac_of_read2_write4_stream")
+
+
 def host_info():
     model = None
     try:
@@ -935,8 +978,7 @@ def headline(args):
         "per_iteration": {"summary": iteration_summary(per_iter), "iterations": per_iter},
     }
     if args.copy_mib:
-        out["copy_ceiling"] = copy_ceiling(args.copy_mib)
-        out["roofline"]["frac_of_copy"] = roof["achieved"] / out["copy_ceiling"]["GBps"]
+        add_ceilings(out, per_kernel, args.copy_mib)
 
     if not args.no_learned:
         out["selector"] = selector_compare(args, parts, ms_per_step)
@@ -1426,25 +1468,7 @@ def main():
         "per_kernel": per_kernel,
     }
     if args.copy_mib:
-        # a plain elementwise copy kernel of known size (reads and writes
-        # 4n bytes): the measured ceiling, and the reference that scales
-        # rocprofv3 FETCH_SIZE / WRITE_SIZE
-        n = args.copy_mib << 18
-        a = torch.empty(n, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1)
-        torch.bitwise_not(a, out=b)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            torch.bitwise_not(a, out=b)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 5
-        out["copy_ceiling"] = {"bytes": 2 * 4 * n, "GBps": 2 * 4 * n / (ms * 1e-3) / 1e9}
-        out["roofline"]["frac_of_copy"] = ach / out["copy_ceiling"]["GBps"]
-        del a, b
+        add_ceilings(out, out["per_kernel"], args.copy_mib)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(g, runs, args.cpu_budget)

@@ -454,6 +454,26 @@ int gpop_autotune(const gpop_graph_desc* desc, gpop_program prog, const gpop_par
 int gpop_profile_enable(struct gpop_graph* g, int enable);
 int gpop_profile_read(struct gpop_graph* g, double* h_ms, uint64_t* h_launches, void* stream);
 
+/* Reference streams for the roofline of the kernels above: one launch on
+ * `stream` of a plain kernel that moves `bytes` bytes of device memory in
+ * the access mix `mix`, so that a caller timing it gets the bandwidth that
+ * mix reaches on this GPU. GPOP_STREAM_READ reads `bytes` bytes of d_src
+ * (d_dst: at least 4 bytes, written at most once); GPOP_STREAM_COPY copies
+ * `bytes` bytes of d_src to d_dst (the reads and writes of the merge, and
+ * the copy ceiling); GPOP_STREAM_WIDEN reads `bytes` bytes of 16-bit words
+ * from d_src and writes them widened to 32 bits, 2 * bytes bytes, to d_dst
+ * (the mix of the partition-centric scatter's stream: a 2-byte source index
+ * read and a 4-byte value written per message slot). The gather reads far
+ * more than it writes: its reference is GPOP_STREAM_READ. Both pointers
+ * are 16-byte aligned, `bytes` is a nonzero multiple of 16 (of 8 for
+ * GPOP_STREAM_WIDEN) and below 2^40; d_src and d_dst are the caller's and
+ * do not overlap. Errors: GPOP_EINVAL for another mix, a NULL or misaligned
+ * pointer or a bad size; GPOP_EDEVICE if the launch fails. */
+#define GPOP_STREAM_READ 0
+#define GPOP_STREAM_COPY 1
+#define GPOP_STREAM_WIDEN 2
+int gpop_stream_ceiling(int mix, const void* d_src, void* d_dst, uint64_t bytes, void* stream);
+
 /* --------------------------------------------------------------- errors */
 
 const char* gpop_last_error(void);

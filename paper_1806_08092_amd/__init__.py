@@ -137,6 +137,8 @@ _SIGS = {
     "gpop_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "gpop_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
+    "gpop_stream_ceiling": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                           ctypes.c_void_p]),
     "gpop_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gpop_probe_scatter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
@@ -536,6 +538,15 @@ class Mlp:
                                          _ptr(x), _ptr(t_sc), _ptr(t_pc), x.shape[0], self.step, lr,
                                          _ptr(self.grad), _ptr(self.loss), _ptr(ws), ws.numel() * 4,
                                          _stream(stream)))
+
+
+STREAM_READ, STREAM_COPY, STREAM_WIDEN = 0, 1, 2
+
+
+def stream_ceiling(mix: int, src, dst, nbytes: int, stream=None):
+    """One launch of the library's reference stream for access mix `mix`
+    over `nbytes` bytes of the device tensor `src` (gpop_stream_ceiling)."""
+    _check(lib().gpop_stream_ceiling(int(mix), _ptr(src), _ptr(dst), int(nbytes), _stream(stream)))
 
 
 def upload_csr(g, device="cuda"):

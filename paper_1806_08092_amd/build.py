@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgpop.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["png.hip", "scatter.hip", "gather.hip", "select.hip", "mlp.hip", "api.hip"]
+SOURCES = ["png.hip", "scatter.hip", "gather.hip", "select.hip", "mlp.hip", "ceiling.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1259,6 +1259,19 @@ int gpop_profile_read(gpop_graph* g, double* h_ms, uint64_t* h_launches, void* s
     return GPOP_OK;
 }
 
+int gpop_stream_ceiling(int mix, const void* d_src, void* d_dst, uint64_t bytes, void* stream) {
+    if (mix != GPOP_STREAM_READ && mix != GPOP_STREAM_COPY && mix != GPOP_STREAM_WIDEN)
+        return fail(GPOP_EINVAL, "unknown stream mix %d", mix);
+    if (!d_src || !d_dst) return fail(GPOP_EINVAL, "NULL pointer");
+    if ((reinterpret_cast<uintptr_t>(d_src) | reinterpret_cast<uintptr_t>(d_dst)) & 15u)
+        return fail(GPOP_EINVAL, "pointers must be 16-byte aligned");
+    const uint64_t unit = mix == GPOP_STREAM_WIDEN ? 8u : 16u;
+    if (bytes == 0 || bytes % unit || bytes >= (1ull << 40))
+        return fail(GPOP_EINVAL, "bytes must be a nonzero multiple of %llu below 2^40", (unsigned long long)unit);
+    HIP_OR_RETURN(launch_stream_ceiling(mix, d_src, d_dst, bytes / unit, (hipStream_t)stream), "stream ceiling");
+    return GPOP_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -147,3 +147,19 @@ def test_plan_sc_reserve_modes():
     o = gp.Options(14, 0, 0, 0, 0, 0)
     o.reserved[1] = 1
     assert L.gpop_plan(ctypes.byref(d), ctypes.byref(o), ctypes.byref(info)) == gp.EINVAL
+
+
+def test_stream_ceiling_rejects_bad_arguments_on_host():
+    # every one of these is refused before anything is launched
+    L = gp.lib()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)  # never dereferenced
+    assert L.gpop_stream_ceiling(3, a, b, 1 << 20, None) == gp.EINVAL  # unknown mix
+    assert L.gpop_stream_ceiling(-1, a, b, 1 << 20, None) == gp.EINVAL
+    assert L.gpop_stream_ceiling(gp.STREAM_READ, None, b, 1 << 20, None) == gp.EINVAL
+    assert L.gpop_stream_ceiling(gp.STREAM_COPY, a, None, 1 << 20, None) == gp.EINVAL
+    assert L.gpop_stream_ceiling(gp.STREAM_COPY, ctypes.c_void_p((1 << 20) + 8), b, 1 << 20, None) == gp.EINVAL
+    assert L.gpop_stream_ceiling(gp.STREAM_COPY, a, ctypes.c_void_p((2 << 20) + 4), 1 << 20, None) == gp.EINVAL
+    assert L.gpop_stream_ceiling(gp.STREAM_COPY, a, b, 0, None) == gp.EINVAL
+    assert L.gpop_stream_ceiling(gp.STREAM_COPY, a, b, 24, None) == gp.EINVAL  # not a multiple of 16
+    assert L.gpop_stream_ceiling(gp.STREAM_WIDEN, a, b, 20, None) == gp.EINVAL  # not a multiple of 8
+    assert L.gpop_stream_ceiling(gp.STREAM_READ, a, b, 1 << 40, None) == gp.EINVAL
