@@ -417,9 +417,20 @@ __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict
             const uint32_t o_val = __shfl(val, (int)o, 64);
             const uint32_t e = o_cst + (f - (o_incl - o_cdeg));
             const uint32_t col = valid ? cols[e] : 0u;
+            // the edge before (same row) for the run-start test, loaded together with it
+            const uint32_t prevc = (valid && e != o_rs) ? cols[e - 1] : 0u;
             const uint32_t key = col >> s;
+            // bounds of bin[p][key] (ids and message slots), loaded before the
+            // reservation below so that they are in flight together with it
+            uint32_t ib = 0, iend = 0, mb = 0, mend = 0;
+            if (KIND != SC_COUNT && valid) {
+                ib = rioff[key];
+                iend = rioff[key + 1];
+                mb = smor[key];
+                mend = smor[key + 1];
+            }
             // run starts, then piece starts: kPiece-aligned offsets from the run start
-            const bool rflag = valid && (e == o_rs || (cols[e - 1] >> s) != key);
+            const bool rflag = valid && (e == o_rs || (prevc >> s) != key);
             const uint64_t rfm = ballot(rflag);
             const uint64_t rmine = rfm & below_eq;
             const uint32_t r_e = __shfl(e, (int)(rmine ? 63u - (uint32_t)__builtin_clzll(rmine) : 0u), 64);
@@ -478,8 +489,7 @@ __device__ __forceinline__ void sc_task(const Dev& G, const uint32_t* __restrict
                 c_f = g0 + lf;
             }
             if (valid) {
-                const uint32_t ib = rioff[key], icap = rioff[key + 1] - ib;
-                const uint32_t mb = smor[key], mcap = smor[key + 1] - mb;
+                const uint32_t icap = iend - ib, mcap = mend - mb;
                 // the reservation must stay inside the capacity of bin[p][key]
                 if (slot >= icap || midx >= mcap) {
                     gptr(G.ctrl)->bug = 1;
