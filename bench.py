@@ -751,8 +751,10 @@ def copy_ceiling(mib):
 def stream_ceilings(mib):
     """The library's reference streams (gpop_stream_ceiling) over mib MiB
     of source: reads only (the gather's mix, which is almost all reads),
-    copy, and 16-bit reads widened to 32-bit writes (the mix of the
-    partition-centric scatter's stream). Bytes moved per launch / time."""
+    copy, 16-bit reads widened to 32-bit writes (the mix of the
+    partition-centric scatter's stream), and reads of 512-byte segments in a
+    scattered order (the pattern of the gather's message values; mib must be
+    a power of two). Bytes moved per launch / time."""
     import torch
     import paper_1806_08092_amd as gp
     nb = mib << 20
@@ -760,7 +762,10 @@ def stream_ceilings(mib):
     dst = torch.empty(nb // 2, dtype=torch.int32, device="cuda")  # room for the widened words
     out = {}
     for name, mix, moved in (("read", gp.STREAM_READ, nb), ("copy", gp.STREAM_COPY, 2 * nb),
-                             ("read2_write4", gp.STREAM_WIDEN, 3 * nb)):
+                             ("read2_write4", gp.STREAM_WIDEN, 3 * nb),
+                             ("read_512B_scattered", gp.STREAM_SEGMENTS, nb)):
+        if mix == gp.STREAM_SEGMENTS and (nb // 512) & (nb // 512 - 1):
+            continue  # needs a power-of-two number of segments
         gp.stream_ceiling(mix, src, dst, nb)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -784,8 +789,8 @@ def add_ceilings(out, per_kernel, mib):
     out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / out["copy_ceiling"]["GBps"]
     sc = stream_ceilings(mib)
     out["stream_ceilings"] = sc
-    for kname, mix in (("gather", "read"), ("scatter_pc", "read2_write4")):
-        if kname in per_kernel:
+    for kname, mix in (("gather", "read"), ("gather", "read_512B_scattered"), ("scatter_pc", "read2_write4")):
+        if kname in per_kernel and mix in sc:
             per_kernel[kname]["frac_of_%s_stream" % mix] = per_kernel[kname]["achieved_GBps"] / sc[mix]["GBps"]
     out["roofline"]["frac_of_mix_stream"] = per_kernel[out["roofline"]["kernel"]].get(
         "frac_of_read_stream" if out["roofline"]["kernel"] == "gather" else "frac_of_read2_write4_stream")

@@ -464,7 +464,12 @@ int gpop_profile_read(struct gpop_graph* g, double* h_ms, uint64_t* h_launches, 
  * from d_src and writes them widened to 32 bits, 2 * bytes bytes, to d_dst
  * (the mix of the partition-centric scatter's stream: a 2-byte source index
  * read and a 4-byte value written per message slot). The gather reads far
- * more than it writes: its reference is GPOP_STREAM_READ. Both pointers
+ * more than it writes: its reference is GPOP_STREAM_READ.
+ * GPOP_STREAM_SEGMENTS reads `bytes` bytes of d_src as 512-byte segments in a
+ * scattered order (segment j at j times an odd constant, modulo their
+ * count; d_dst as for GPOP_STREAM_READ): the pattern of the gather's message
+ * values, short runs spread over the message array; `bytes` / 512 must be
+ * a power of two. Both pointers
  * are 16-byte aligned, `bytes` is a nonzero multiple of 16 (of 8 for
  * GPOP_STREAM_WIDEN) and below 2^40; d_src and d_dst are the caller's and
  * do not overlap. Errors: GPOP_EINVAL for another mix, a NULL or misaligned
@@ -472,6 +477,7 @@ int gpop_profile_read(struct gpop_graph* g, double* h_ms, uint64_t* h_launches, 
 #define GPOP_STREAM_READ 0
 #define GPOP_STREAM_COPY 1
 #define GPOP_STREAM_WIDEN 2
+#define GPOP_STREAM_SEGMENTS 3
 int gpop_stream_ceiling(int mix, const void* d_src, void* d_dst, uint64_t bytes, void* stream);
 
 /* --------------------------------------------------------------- errors */

@@ -540,7 +540,7 @@ class Mlp:
                                          _stream(stream)))
 
 
-STREAM_READ, STREAM_COPY, STREAM_WIDEN = 0, 1, 2
+STREAM_READ, STREAM_COPY, STREAM_WIDEN, STREAM_SEGMENTS = 0, 1, 2, 3
 
 
 def stream_ceiling(mix: int, src, dst, nbytes: int, stream=None):

@@ -1260,7 +1260,8 @@ int gpop_profile_read(gpop_graph* g, double* h_ms, uint64_t* h_launches, void* s
 }
 
 int gpop_stream_ceiling(int mix, const void* d_src, void* d_dst, uint64_t bytes, void* stream) {
-    if (mix != GPOP_STREAM_READ && mix != GPOP_STREAM_COPY && mix != GPOP_STREAM_WIDEN)
+    if (mix != GPOP_STREAM_READ && mix != GPOP_STREAM_COPY && mix != GPOP_STREAM_WIDEN &&
+        mix != GPOP_STREAM_SEGMENTS)
         return fail(GPOP_EINVAL, "unknown stream mix %d", mix);
     if (!d_src || !d_dst) return fail(GPOP_EINVAL, "NULL pointer");
     if ((reinterpret_cast<uintptr_t>(d_src) | reinterpret_cast<uintptr_t>(d_dst)) & 15u)
@@ -1268,6 +1269,8 @@ int gpop_stream_ceiling(int mix, const void* d_src, void* d_dst, uint64_t bytes,
     const uint64_t unit = mix == GPOP_STREAM_WIDEN ? 8u : 16u;
     if (bytes == 0 || bytes % unit || bytes >= (1ull << 40))
         return fail(GPOP_EINVAL, "bytes must be a nonzero multiple of %llu below 2^40", (unsigned long long)unit);
+    if (mix == GPOP_STREAM_SEGMENTS && (bytes % 512u || ((bytes / 512u) & (bytes / 512u - 1u))))
+        return fail(GPOP_EINVAL, "bytes / 512 must be a power of two");
     HIP_OR_RETURN(launch_stream_ceiling(mix, d_src, d_dst, bytes / unit, (hipStream_t)stream), "stream ceiling");
     return GPOP_OK;
 }

@@ -1,6 +1,7 @@
 // Reference streams for the roofline of the scatter and gather kernels: plain
 // kernels of known size with the access mixes those kernels have (reads
-// only; reads and writes of equal size; 2-byte reads with 4-byte writes).
+// only; reads and writes of equal size; 2-byte reads with 4-byte writes;
+// reads of short runs in a scattered order).
 // Each thread moves four 16-byte vectors, the loads of all four issued before
 // any is used, and the grid covers the array once, so that every wave has
 // the same bytes in flight and neighbouring waves touch neighbouring memory.
@@ -63,6 +64,29 @@ __global__ __launch_bounds__(kCeilT) void k_ceil_widen(const uint2* __restrict__
     }
 }
 
+// 512-byte segments (32 vectors) read in a scattered order: segment j of a
+// power-of-two count n is read at (j * an odd constant) mod n, a bijection,
+// half a wave per segment and four segments per half-wave in flight. This is
+// the pattern of the gather's message values, which it reads as many short
+// runs (one per bin) spread over the message array.
+constexpr uint32_t kSegVecs = 32;
+__global__ __launch_bounds__(kCeilT) void k_ceil_segments(const uint4* __restrict__ a, uint64_t nseg,
+                                                          uint32_t* __restrict__ sink) {
+    const uint64_t half = ((uint64_t)blockIdx.x * kCeilT + threadIdx.x) / kSegVecs;
+    const uint32_t l = threadIdx.x & (kSegVecs - 1u);
+    uint4 v[kCeilU];
+#pragma unroll
+    for (uint32_t u = 0; u < kCeilU; ++u) {
+        const uint64_t j = half * kCeilU + u;
+        const uint64_t sj = (j * 0x9E3779B97F4A7C15ull) & (nseg - 1u);
+        v[u] = j < nseg ? a[sj * kSegVecs + l] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    uint32_t x = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kCeilU; ++u) x ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    if (x == 0x9E3779B9u) sink[0] = x;
+}
+
 }  // namespace
 
 hipError_t launch_stream_ceiling(int mix, const void* src, void* dst, uint64_t vecs, hipStream_t st) {
@@ -74,9 +98,12 @@ hipError_t launch_stream_ceiling(int mix, const void* src, void* dst, uint64_t v
     else if (mix == 1)
         hipLaunchKernelGGL(k_ceil_copy, grid, dim3(kCeilT), 0, st, static_cast<const uint4*>(src),
                            static_cast<uint4*>(dst), vecs);
-    else
+    else if (mix == 2)
         hipLaunchKernelGGL(k_ceil_widen, grid, dim3(kCeilT), 0, st, static_cast<const uint2*>(src),
                            static_cast<uint4*>(dst), vecs);
+    else
+        hipLaunchKernelGGL(k_ceil_segments, grid, dim3(kCeilT), 0, st, static_cast<const uint4*>(src),
+                           vecs / kSegVecs, static_cast<uint32_t*>(dst));
     return hipGetLastError();
 }
 

@@ -74,7 +74,8 @@ hipError_t launch_batch_status(const BatchGrid& B, uint32_t* out, hipStream_t st
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st);
 // mix 0: read vecs 16-byte vectors of src (dst: one word, written at most
 // once); 1: copy them to dst; 2: widen vecs groups of four 16-bit words of
-// src to four 32-bit words of dst.
+// src to four 32-bit words of dst; 3: read vecs 16-byte vectors of src as
+// 512-byte segments in a scattered order (vecs / 32 a power of two).
 hipError_t launch_stream_ceiling(int mix, const void* src, void* dst, uint64_t vecs, hipStream_t st);
 hipError_t launch_set_frontier(const Dev& G, const uint32_t* verts, uint32_t n, int all, hipStream_t st);
 

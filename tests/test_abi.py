@@ -153,7 +153,7 @@ def test_stream_ceiling_rejects_bad_arguments_on_host():
     # every one of these is refused before anything is launched
     L = gp.lib()
     a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)  # never dereferenced
-    assert L.gpop_stream_ceiling(3, a, b, 1 << 20, None) == gp.EINVAL  # unknown mix
+    assert L.gpop_stream_ceiling(5, a, b, 1 << 20, None) == gp.EINVAL  # unknown mix
     assert L.gpop_stream_ceiling(-1, a, b, 1 << 20, None) == gp.EINVAL
     assert L.gpop_stream_ceiling(gp.STREAM_READ, None, b, 1 << 20, None) == gp.EINVAL
     assert L.gpop_stream_ceiling(gp.STREAM_COPY, a, None, 1 << 20, None) == gp.EINVAL
@@ -163,3 +163,6 @@ def test_stream_ceiling_rejects_bad_arguments_on_host():
     assert L.gpop_stream_ceiling(gp.STREAM_COPY, a, b, 24, None) == gp.EINVAL  # not a multiple of 16
     assert L.gpop_stream_ceiling(gp.STREAM_WIDEN, a, b, 20, None) == gp.EINVAL  # not a multiple of 8
     assert L.gpop_stream_ceiling(gp.STREAM_READ, a, b, 1 << 40, None) == gp.EINVAL
+    assert L.gpop_stream_ceiling(gp.STREAM_SEGMENTS, a, b, 3 * 512, None) == gp.EINVAL  # 3 segments
+    assert L.gpop_stream_ceiling(gp.STREAM_SEGMENTS, a, b, 256, None) == gp.EINVAL  # half a segment
+    assert L.gpop_stream_ceiling(4, a, b, 1 << 20, None) == gp.EINVAL

@@ -1,6 +1,7 @@
 """The library's reference streams (gpop_stream_ceiling): the copy and the
 widening copy write exactly what they read, over sizes that end inside a
-workgroup's span and span several workgroups; the read writes nothing."""
+workgroup's span and span several workgroups; the reads (whole array, and
+scattered 512-byte segments) write nothing."""
 import pytest
 import torch
 
@@ -41,5 +42,14 @@ def test_read_writes_nothing():
     src = torch.ones((1 << 20) // 4, dtype=torch.int32, device="cuda")  # XOR of ones: 0
     sink = torch.full((16,), 5, dtype=torch.int32, device="cuda")
     gp.stream_ceiling(gp.STREAM_READ, src, sink, 1 << 20)
+    torch.cuda.synchronize()
+    assert bool((sink == 5).all())
+
+
+@pytest.mark.parametrize("nbytes", [512, 1 << 20])
+def test_scattered_segments_write_nothing(nbytes):
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")  # XOR of ones: 0
+    sink = torch.full((16,), 5, dtype=torch.int32, device="cuda")
+    gp.stream_ceiling(gp.STREAM_SEGMENTS, src, sink, nbytes)
     torch.cuda.synchronize()
     assert bool((sink == 5).all())
