@@ -3,7 +3,8 @@ workgroup lists at once (512): symmetrised RMAT-18 with q = 256 gives
 k = 1024 partitions, and its busiest columns receive bins from more than
 512 of them, so their gather takes the bins in several windows. BFS levels,
 CC and SSSP stay bit-exact against the oracle under the analytical, the
-all source-centric and the all partition-centric selection."""
+all source-centric and the all partition-centric selection, and with both
+source-centric reservation modes."""
 import numpy as np
 import pytest
 
@@ -13,16 +14,15 @@ from gpu_util import make_graph, run_program
 
 pytestmark = pytest.mark.gpu
 
-_G = None
+_G = {}
 
 
-def graph():
-    global _G
-    if _G is None:
+def graph(sc_reserve="auto"):
+    if sc_reserve not in _G:
         g = gg.rmat_graph(18, 8, 31, symmetric=True, weights_seed=32)
-        G, _ = make_graph(g, 8)
-        _G = (g, G)
-    return _G
+        G, _ = make_graph(g, 8, sc_reserve=sc_reserve)
+        _G[sc_reserve] = (g, G)
+    return _G[sc_reserve]
 
 
 def test_columns_span_several_windows():
@@ -37,9 +37,12 @@ def test_columns_span_several_windows():
     assert per_col.max() > 512, per_col.max()
 
 
-@pytest.mark.parametrize("sel", ["analytical", "sc", "pc"])
-def test_bfs_cc_sssp(sel):
-    g, G = graph()
+@pytest.mark.parametrize("sel,reserve", [("analytical", "auto"), ("sc", "auto"), ("pc", "auto"),
+                                         ("sc", "bin"), ("analytical", "piece")])
+def test_bfs_cc_sssp(sel, reserve):
+    # reserve: how source-centric tasks reserve bin slots (per bin: a k-word
+    # LDS row per wave, 1024 words here)
+    g, G = graph(reserve)
     for root in gg.pick_sources(g.offsets, 33, 2).tolist():
         got, _ = run_program(G, "bfs", g.n, root=root, selector=sel)
         ref = oracle.bfs_levels(g, root)
