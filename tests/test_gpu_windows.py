@@ -17,12 +17,13 @@ pytestmark = pytest.mark.gpu
 _G = {}
 
 
-def graph(sc_reserve="auto"):
-    if sc_reserve not in _G:
+def graph(sc_reserve="auto", task_ids=0):
+    key = (sc_reserve, task_ids)
+    if key not in _G:
         g = gg.rmat_graph(18, 8, 31, symmetric=True, weights_seed=32)
-        G, _ = make_graph(g, 8, sc_reserve=sc_reserve)
-        _G[sc_reserve] = (g, G)
-    return _G[sc_reserve]
+        G, _ = make_graph(g, 8, sc_reserve=sc_reserve, gather_task_ids=task_ids)
+        _G[key] = (g, G)
+    return _G[key]
 
 
 def test_columns_span_several_windows():
@@ -53,3 +54,16 @@ def test_bfs_cc_sssp(sel, reserve):
     got, _ = run_program(G, "cc", g.n, selector=sel)
     ref = oracle.cc_minlabel(g)
     assert np.array_equal(got, ref), ("cc", sel, np.flatnonzero(got != ref)[:10])
+
+
+def test_split_tasks_take_their_source_ranges():
+    # gather tasks of about 2^14 ids: the heavy columns split into tasks that
+    # each list only the bins of their own source-partition range
+    g, G = graph("auto", 1 << 14)
+    got, _ = run_program(G, "cc", g.n, selector="sc")
+    assert np.array_equal(got, oracle.cc_minlabel(g))
+    assert max(r["split_tasks"] for r in G.iter_stats()) > 0
+    for root in gg.pick_sources(g.offsets, 34, 2).tolist():
+        got, _ = run_program(G, "bfs", g.n, root=root, selector="analytical")
+        ref = oracle.bfs_levels(g, root)
+        assert np.array_equal(got, ref), ("bfs", root, np.flatnonzero(got != ref)[:10])
