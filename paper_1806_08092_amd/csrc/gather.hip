@@ -300,9 +300,10 @@ __device__ __forceinline__ void finish_partition(const Dev& G, const Params& P, 
 // message-start flags. One 16-byte load at data[adj + message starts before
 // 4l] then holds the values of all four positions (a bin's messages are
 // contiguous). A bin whose source did not scatter partition-centric this
-// iteration (or a padding run) reads the identity words instead, so no id is
-// masked; null ids (local id q) combine into a spare LDS word past the
-// partition's state and are not counted.
+// iteration (or a padding run) reads the identity words instead, so no id
+// needs a mask of its own; values equal to the identity (inactive sources
+// included) skip the LDS combine, and null ids (local id q) combine into a
+// spare LDS word past the partition's state and are not counted.
 // The next round's ids, weights and entries are loaded before the current
 // round is decoded; the chunks' table offsets and lane-start masks one round
 // earlier still, with scalar loads.
@@ -447,13 +448,16 @@ __device__ __forceinline__ uint32_t stream_gather(const Dev& G, uint32_t c_lo, u
                 if constexpr (is_weighted(PROG)) x = sat_add(x, (wv[pi] >> (8u * j)) & 0xFFu);
                 const uint32_t d = ((j < 2 ? raw[pi].x : raw[pi].y) >> (16u * (j & 1u))) & kLocalMask;
                 const bool real = d != nulld;
+                // an identity (a source that did not scatter, padding) changes
+                // nothing and is not combined: its LDS operation would only add
+                // bank conflicts at a random word
                 if constexpr (SUM) {
                     const bool use = (int32_t)x >= 0 && real;  // identities and padding read negative words
                     my_ids += use ? 1u : 0u;
-                    atomicAdd(acc + d, use ? __double2ull_rn((double)__uint_as_float(x) * kFix) : 0ull);
+                    if (use) atomicAdd(acc + d, __double2ull_rn((double)__uint_as_float(x) * kFix));
                 } else {
                     my_ids += (x != kIdentMin && real) ? 1u : 0u;
-                    atomicMin(st32 + d, x);
+                    if (x != kIdentMin) atomicMin(st32 + d, x);
                 }
             }
         }
