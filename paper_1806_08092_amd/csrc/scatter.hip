@@ -812,6 +812,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     __shared__ uint32_t s_w[kPlanW];
     uint64_t va = 0, ea = 0, nsc = 0, npc = 0, pcm = 0, pci = 0, sva = 0, sea = 0, pcv = 0, nfb = 0;
     double dang = 0.0;
+    uint32_t msc = 0;  // most active edges of one source-centric partition (the thread's)
     // pass 1: modes and totals; the source-centric work units (active
     // vertices + active out-edges) of each partition go to LDS
     __shared__ uint32_t s_units[4096];  // k <= 4096; 0xFFFFFFFF: not source-centric
@@ -852,6 +853,7 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
                 ++nsc;
                 sva += Va;
                 sea += Ea;
+                msc = max(msc, Ea);
                 units = (uint32_t)min<uint64_t>((uint64_t)Va + Ea, 0xFFFFFFFEull);
             }
             s_units[p] = units;
@@ -868,9 +870,12 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
     // task size of this iteration: about kScTaskTarget tasks, between
     // 2^kScShiftFloor and 2^sc_shift work units
     __shared__ uint64_t s_sc_units[kPlanW];
+    __shared__ uint32_t s_msc[kPlanW];  // the wave's largest source-centric partition (active edges)
     {
         const uint64_t w = wave_sum_u64(sva + sea);
         if (lane == 0) s_sc_units[wave] = w;
+        for (int o = 32; o > 0; o >>= 1) msc = max(msc, (uint32_t)__shfl_xor((int)msc, o, 64));
+        if (lane == 0) s_msc[wave] = msc;
     }
     __syncthreads();
     uint32_t sh;
@@ -950,10 +955,16 @@ __device__ __forceinline__ void plan_body(const Dev& G, const Params& P, uint32_
         C->pc_stream = (G.n_chunks != 0u && t[3] != 0u &&
                         (G.pcs_mode == GPOP_PCSTREAM_ON || 2ull * t[5] >= G.E)) ? 1u : 0u;
         // the wide gather kernel reads the streams and the source-centric bins
-        // (small ones one per lane): taken when those hold at most an eighth
-        // of the partition-centric ids; not with interleaved scatter-gather,
-        // whose held-back columns kb_gather keeps
-        C->dense_gather = (C->pc_stream != 0u && P.isg <= 1u && (t[3] == G.k || 8ull * t[7] <= t[5])) ? 1u : 0u;
+        // (small ones one per lane, larger ones one wave each): taken when
+        // those hold at most an eighth of the partition-centric ids and no
+        // source-centric partition has more than 64 active edges per
+        // destination partition on average (a hub partition's bins would each
+        // keep one wave busy while its workgroup waits); not with interleaved
+        // scatter-gather, whose held-back columns kb_gather keeps
+        uint32_t msc_all = 0;
+        for (uint32_t w = 0; w < kPlanW; ++w) msc_all = max(msc_all, s_msc[w]);
+        C->dense_gather = (C->pc_stream != 0u && P.isg <= 1u &&
+                           (t[3] == G.k || (8ull * t[7] <= t[5] && (uint64_t)msc_all <= 64ull * G.k))) ? 1u : 0u;
         if (tcarry > G.max_sctask) {  // cannot happen (the bound covers every task size): stop
             C->bug = 1;
             C->done = 1;
